@@ -1,0 +1,203 @@
+/*
+ * saa.h -- C ABI of the MI355X SAA smoothed-CVaR engine.
+ *
+ * The library evaluates, for a fixed set of N random-field samples m_i and a
+ * control z, the sample-average smoothed-CVaR objective
+ *
+ *   J(z) = min_t  t + 1/(N (1-beta)) sum_i s_eps(q_i(z) - t) + alpha/2 |z|^2
+ *
+ * (paper Sec. 2.2, eq. (CVaR_saa_ouu), with the C^2 smoothed plus function of
+ * Sec. 2.1) and its gradient grad J = sum_i w_i dq_i/dz + alpha z, where
+ * w_i = s_eps'(q_i - t*) / (N (1-beta)) (chain rule of eq.
+ * (ouu_risk_gradient)).  q_i = int (u_i - u_target)^2 dx is the tracking QoI of
+ * the state u_i of the semilinear elliptic equation of Sec. 4.2,
+ *
+ *   -div(exp(m_i) grad u) + r u^3 = sum_k z_k f_k,   u = 0 on the boundary,
+ *
+ * discretised by P1 finite elements on a uniform n x n triangulated grid.
+ * dq_i/dz comes from one adjoint solve per sample (Sec. 2.3,
+ * eq. (ouu_qoi_gradient)).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an int status (SAA_OK = 0, > 0 success with warning,
+ *    < 0 error).  No C++ exception crosses this boundary.
+ *  - Arguments are validated before any device work; invalid arguments return
+ *    SAA_E_INVALID and leave outputs untouched.
+ *  - "device" pointers are HIP device allocations owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  The library never
+ *    keeps a caller pointer past the call, except that saa_set_samples copies
+ *    the samples into the context.
+ *  - All device work is enqueued on the HIP stream given at context creation;
+ *    calls that return host values synchronise that stream before returning.
+ *  - A context is not thread-safe: calls on one context must be serialised.
+ *
+ * Grid conventions (2D): nodes x_p = (i h, j h), 0 <= i, j <= n, h = 1/n, flat
+ * node index p = j (n+1) + i.  The d_U = (n-1)^2 unknowns are the interior
+ * nodes, listed in increasing flat index ("interior order").
+ */
+#ifndef SAA_H
+#define SAA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SAA_ABI_VERSION 1
+
+/* Status codes. */
+enum {
+  SAA_OK = 0,
+  SAA_W_FALLBACK = 1,  /* success; the surrogate was replaced by the PDE form */
+  SAA_E_INVALID = -1,  /* bad argument (null pointer, out-of-range value, NaN) */
+  SAA_E_NOCONV = -2,   /* a Newton or CG iteration did not converge; outputs
+                          are written, report->n_unconverged says how many */
+  SAA_E_DEVICE = -3,   /* a HIP runtime call failed */
+  SAA_E_OOM = -4,      /* device allocation failed */
+  SAA_E_MODEL = -5,    /* model does not match the context's problem */
+  SAA_E_IO = -6        /* file could not be read or written, or is corrupt */
+};
+
+/* Forms of the objective. */
+enum { SAA_FORM_PDE = 0, SAA_FORM_MRDINO = 1 };
+
+/* Arithmetic precision of the PDE form.
+ *  SAA_FP64      : FP64 everywhere (FP64 multigrid-preconditioned CG).
+ *  SAA_FP32      : FP32 everywhere except the final CVaR reduction (FP64).
+ *  SAA_FP32_DC64 : FP32 multigrid-preconditioned CG inside FP64 Newton /
+ *                  defect correction: residuals, state, adjoint, QoI and
+ *                  gradient in FP64. */
+enum { SAA_FP64 = 0, SAA_FP32 = 1, SAA_FP32_DC64 = 2, SAA_BF16 = 3, SAA_FP8 = 4 };
+
+/* Problem definition (Sec. 4.2).  Sources f_k(x) = (sigma sqrt(2 pi))^-1
+ * exp(-|x - x_k|^2 / (2 sigma^2)) sit on the interior lattice
+ * x_k = ((a+1)/(s+1), (b+1)/(s+1)), k = s b + a, s = n_src_per_dim.
+ * The log-coefficient is m(x) = sum_{j,k=1..K1} a_jk xi_jk sin(j pi x) sin(k pi y)
+ * with a_jk = kl_amp (pi^2 (j^2 + k^2) + kl_shift)^(-kl_exp). */
+typedef struct saa_problem {
+  int dim;             /* 2 */
+  int n;               /* cells per side; a power of two >= 4 */
+  int n_src_per_dim;   /* s: d_Z = s^2 controls (1..8) */
+  double src_sigma;    /* source width sigma > 0 */
+  int kl_per_dim;      /* K1 in 1..64 */
+  double kl_shift;     /* >= 0 */
+  double kl_exp;       /* > 0 */
+  double kl_amp;       /* any finite value */
+  double reaction;     /* r >= 0 */
+  double u_target;     /* target state (constant) */
+} saa_problem;
+
+/* Options of one objective evaluation.  Fill with saa_options_default() and
+ * override fields as needed. */
+typedef struct saa_options {
+  double beta;         /* CVaR level, 0 <= beta < 1 */
+  double eps;          /* smoothing width of s_eps, > 0 */
+  double alpha;        /* control cost weight, >= 0 */
+  int t_mode;          /* 0: t minimised out (J(z) = min_t J_hat(z,t));
+                          1: J_hat(z, t_in) and dJ_hat/dt are returned */
+  double t_in;
+  int prec;            /* SAA_FP64 | SAA_FP32 | SAA_FP32_DC64 (PDE form) */
+  double newton_tol;   /* stop Newton / defect correction when the update is
+                          <= newton_tol * |iterate| (2-norms); <= 0: default
+                          (1e-13 with FP64 state, 1e-5 with FP32 state); an
+                          iteration also stops once its updates stop
+                          contracting below 1e-4 relative (rounding floor) */
+  double lin_rtol;     /* relative residual of each inner PCG solve; <= 0:
+                          default 1e-6 (1e-5 with FP32 state) */
+  int max_newton;      /* <= 0: default 30 */
+  int max_lin;         /* max PCG iterations per inner solve; <= 0: 200 */
+  int max_dc;          /* max adjoint defect-correction passes; <= 0: 10 */
+  int all_adjoints;    /* 0: solve adjoints only for samples whose CVaR weight
+                          w_i is non-zero (the others contribute exactly 0 to
+                          grad J); 1: solve all */
+  double fallback_tol; /* MR-DINO form: relative error above which the PDE form
+                          is used instead; < 0 disables */
+} saa_options;
+
+typedef struct saa_report {
+  double t_star;       /* the t used (minimiser, or t_in) */
+  double dJ_dt;        /* 1 - sum_i w_i */
+  double err_estimate; /* surrogate error estimate, or 0 */
+  double seconds;      /* wall time of the call (device-synchronised) */
+  int newton_max;      /* max Newton iterations over samples */
+  int n_unconverged;   /* samples whose Newton or adjoint did not converge */
+  int n_adjoints;      /* adjoint solves performed */
+  int fallback_used;   /* 1 if the PDE form replaced the surrogate */
+  int64_t lin_total;   /* total inner PCG iterations over all samples */
+} saa_report;
+
+typedef struct saa_ctx saa_ctx;
+
+/* Library ABI version (SAA_ABI_VERSION). */
+int saa_abi_version(void);
+
+/* Text for a status code; never NULL. */
+const char* saa_status_str(int status);
+
+/* Defaults: beta 0.95, eps 1e-4, alpha 1e-3, t_mode 0, prec SAA_FP32_DC64,
+ * tolerances <= 0 (i.e. per-precision defaults), all_adjoints 0,
+ * fallback_tol 1e-2.  Returns SAA_E_INVALID for NULL. */
+int saa_options_default(saa_options* opt);
+
+/* Create a context for `prob` that can hold up to N_max samples.  The
+ * context owns all workspaces (sized for N_max) and the shared operators
+ * (source matrix, sine tables).  `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  On success *out receives the context; the caller frees it
+ * with saa_ctx_destroy. */
+int saa_ctx_create(const saa_problem* prob, int64_t N_max, void* hip_stream, saa_ctx** out);
+
+/* Free a context and everything it owns (NULL is ignored). */
+void saa_ctx_destroy(saa_ctx* ctx);
+
+/* Number of unknowns d_U, controls d_Z and KL coefficients per sample of the
+ * context's problem; any pointer may be NULL. */
+int saa_ctx_dims(const saa_ctx* ctx, int64_t* d_u, int* d_z, int* n_kl);
+
+/* Install the fixed sample set (Sec. 2.2: fixed samples make the SAA problem
+ * deterministic).  xi_dev: device, N x K1^2 float64, row-major, sample-major,
+ * within a sample j (x-frequency) slow and k fast.  Builds on the device the
+ * nodal fields exp(m_i) and the multigrid operator hierarchy of every sample.
+ * 1 <= N <= N_max.  Not part of an objective evaluation's timing. */
+int saa_set_samples(saa_ctx* ctx, int64_t N, const double* xi_dev);
+
+/* SAA objective and gradient at control z (host, d_Z float64).  form selects
+ * the PDE form (model must be NULL) or the MR-DINO surrogate.  J (host, 1) and
+ * grad_z (host, d_Z) receive the results; report may be NULL.  Returns
+ * SAA_E_NOCONV if some sample did not converge (results still written). */
+int saa_objective_grad(saa_ctx* ctx, const double* z, int form, const void* model,
+                       const saa_options* opt, double* J, double* grad_z,
+                       saa_report* report);
+
+/* Per-sample QoI and gradient at control z (host, d_Z): q_dev (device, N
+ * float64) and g_dev (device, N x d_Z float64, row-major) receive q_i and
+ * dq_i/dz for every sample (all adjoints are solved).  report may be NULL. */
+int saa_per_sample(saa_ctx* ctx, const double* z, int form, const void* model,
+                   const saa_options* opt, double* q_dev, double* g_dev,
+                   saa_report* report);
+
+/* PDE states at per-sample controls (training data, Sec. 3.4).
+ * Z_dev: device, N x d_Z float64 (control of sample i in row i).
+ * u_dev (device, N x d_U float64, interior order) receives the states; q_dev
+ * (device, N, may be NULL) the QoIs; dudz_dev (device, N x d_Z x d_U float64,
+ * may be NULL) the control Jacobians du_i/dz = A(u_i)^{-1} F by d_Z
+ * linearised solves with the state's operator (eq. (projected_sensitivity),
+ * d_Z < r_U case).  Uses opt->prec, tolerances and iteration limits. */
+int saa_solve_states(saa_ctx* ctx, const double* Z_dev, const saa_options* opt,
+                     double* u_dev, double* q_dev, double* dudz_dev, saa_report* report);
+
+/* Per-sample solver status of the last saa_objective_grad, saa_per_sample or
+ * saa_solve_states call on this context.  Host arrays of N entries each (any
+ * may be NULL): flags (bit 1: Newton not converged, 2: an inner PCG hit
+ * max_lin or broke down, 4: adjoint / linearised defect correction not
+ * converged, 8: non-finite update), Newton iterations, PCG iterations of the
+ * state solve, PCG iterations of the adjoint / linearised solves.  N is the
+ * number of installed samples.  Synchronises the context's stream. */
+int saa_sample_status(saa_ctx* ctx, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAA_H */

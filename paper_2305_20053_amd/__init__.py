@@ -1,0 +1,262 @@
+"""Python binding of the MI355X SAA smoothed-CVaR engine (libsaa.so).
+
+Argument marshalling only: every numerical step runs in the HIP kernels
+behind the C ABI declared in include/saa.h.  PyTorch provides device memory
+and the stream.  If the shared library is missing, importing still works
+(so that the host-side tests can run) but every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsaa.so")
+
+SAA_OK, SAA_W_FALLBACK = 0, 1
+SAA_E_INVALID, SAA_E_NOCONV, SAA_E_DEVICE, SAA_E_OOM, SAA_E_MODEL, SAA_E_IO = -1, -2, -3, -4, -5, -6
+FORM_PDE, FORM_MRDINO = 0, 1
+FP64, FP32, FP32_DC64, BF16, FP8 = 0, 1, 2, 3, 4
+
+
+class SaaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("n_src_per_dim", ctypes.c_int),
+                ("src_sigma", ctypes.c_double), ("kl_per_dim", ctypes.c_int),
+                ("kl_shift", ctypes.c_double), ("kl_exp", ctypes.c_double), ("kl_amp", ctypes.c_double),
+                ("reaction", ctypes.c_double), ("u_target", ctypes.c_double)]
+
+
+class COptions(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("eps", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("t_mode", ctypes.c_int), ("t_in", ctypes.c_double), ("prec", ctypes.c_int),
+                ("newton_tol", ctypes.c_double), ("lin_rtol", ctypes.c_double),
+                ("max_newton", ctypes.c_int), ("max_lin", ctypes.c_int), ("max_dc", ctypes.c_int),
+                ("all_adjoints", ctypes.c_int), ("fallback_tol", ctypes.c_double)]
+
+
+class CReport(ctypes.Structure):
+    _fields_ = [("t_star", ctypes.c_double), ("dJ_dt", ctypes.c_double), ("err_estimate", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("newton_max", ctypes.c_int), ("n_unconverged", ctypes.c_int),
+                ("n_adjoints", ctypes.c_int), ("fallback_used", ctypes.c_int), ("lin_total", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "saa_abi_version": (ctypes.c_int, []),
+    "saa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "saa_options_default": (ctypes.c_int, [ctypes.POINTER(COptions)]),
+    "saa_ctx_create": (ctypes.c_int, [ctypes.POINTER(CProblem), ctypes.c_int64, _P, ctypes.POINTER(_P)]),
+    "saa_ctx_destroy": (None, [_P]),
+    "saa_ctx_dims": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]),
+    "saa_set_samples": (ctypes.c_int, [_P, ctypes.c_int64, _P]),
+    "saa_objective_grad": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.POINTER(COptions), _P, _P,
+                                          ctypes.POINTER(CReport)]),
+    "saa_per_sample": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.POINTER(COptions), _P, _P,
+                                      ctypes.POINTER(CReport)]),
+    "saa_solve_states": (ctypes.c_int, [_P, _P, ctypes.POINTER(COptions), _P, _P, _P, ctypes.POINTER(CReport)]),
+    "saa_sample_status": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+}
+
+_lib = None
+_lib_error = None
+
+
+def _load():
+    global _lib, _lib_error
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        _lib_error = f"{LIB_PATH} is not built; run __graft_entry__.build() or paper_2305_20053_amd/build.py"
+        raise SaaError(SAA_E_DEVICE, _lib_error)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def lib():
+    """The loaded ctypes library (raises SaaError if it is not built)."""
+    return _load()
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGS)
+
+
+def status_str(status: int) -> str:
+    return _load().saa_status_str(status).decode()
+
+
+def _check(status: int, allow=(SAA_OK,)):
+    if status not in allow:
+        raise SaaError(status, status_str(status))
+    return status
+
+
+def require_gpu():
+    """Raise unless the HIP library is built and a GPU is visible."""
+    _load()
+    import torch
+    if not torch.cuda.is_available():
+        raise SaaError(SAA_E_DEVICE, "no HIP device is visible")
+
+
+@dataclass
+class Problem:
+    """Semilinear elliptic source-control problem (paper Sec. 4.2)."""
+    n: int = 32
+    n_src_per_dim: int = 5
+    src_sigma: float = 0.05
+    kl_per_dim: int = 8
+    kl_shift: float = 25.0
+    kl_exp: float = 1.25
+    kl_amp: float = 1.0
+    reaction: float = 1.0
+    u_target: float = 0.5
+    dim: int = 2
+
+    def c_struct(self) -> CProblem:
+        return CProblem(self.dim, self.n, self.n_src_per_dim, self.src_sigma, self.kl_per_dim,
+                        self.kl_shift, self.kl_exp, self.kl_amp, self.reaction, self.u_target)
+
+    @property
+    def d_z(self) -> int:
+        return self.n_src_per_dim ** self.dim
+
+    @property
+    def d_u(self) -> int:
+        return (self.n - 1) ** self.dim
+
+
+def problem_small() -> Problem:
+    """n = 32 (1089 nodes), 8 x 8 KL modes: the N = 64 correctness workload."""
+    return Problem(n=32, kl_per_dim=8)
+
+
+def problem_medium() -> Problem:
+    """n = 128 (16641 nodes), 16 x 16 KL modes: the N = 1024 PDE workload."""
+    return Problem(n=128, kl_per_dim=16)
+
+
+def options(**kw) -> COptions:
+    o = COptions()
+    _check(_load().saa_options_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """A sample set of one problem with its device workspaces."""
+
+    def __init__(self, problem: Problem, n_max: int, stream=None):
+        self._lib = _load()
+        self.problem = problem
+        self._stream = _stream_handle() if stream is None else stream
+        h = _P()
+        _check(self._lib.saa_ctx_create(ctypes.byref(problem.c_struct()), n_max, _P(self._stream),
+                                        ctypes.byref(h)))
+        self._h = h
+        du, dz, nk = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.saa_ctx_dims(h, ctypes.byref(du), ctypes.byref(dz), ctypes.byref(nk)))
+        self.d_u, self.d_z, self.n_kl = du.value, dz.value, nk.value
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.saa_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_samples(self, xi):
+        """xi: float64 CUDA tensor (N, K1, K1) of KL coefficients."""
+        xi = xi.contiguous()
+        _check(self._lib.saa_set_samples(self._h, xi.shape[0], _P(_ptr(xi))))
+        self.n = xi.shape[0]
+
+    def objective_grad(self, z, form=FORM_PDE, model=None, opt=None, allow_noconv=False):
+        """Returns (J, grad (numpy d_Z), report dict)."""
+        import numpy as np
+        opt = opt if opt is not None else options()
+        zz = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        J = ctypes.c_double()
+        grad = np.zeros(self.d_z)
+        rep = CReport()
+        st = self._lib.saa_objective_grad(self._h, zz.ctypes.data, form, _P(model.handle if model else None),
+                                          ctypes.byref(opt), ctypes.byref(J), grad.ctypes.data, ctypes.byref(rep))
+        _check(st, (SAA_OK, SAA_W_FALLBACK) + ((SAA_E_NOCONV,) if allow_noconv else ()))
+        out = rep.as_dict()
+        out["status"] = st
+        return J.value, grad, out
+
+    def per_sample(self, z, form=FORM_PDE, model=None, opt=None, allow_noconv=False):
+        """Returns (q (N,), g (N, d_Z)) float64 CUDA tensors and the report."""
+        import numpy as np
+        import torch
+        opt = opt if opt is not None else options()
+        zz = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        q = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.n, self.d_z, dtype=torch.float64, device="cuda")
+        rep = CReport()
+        st = self._lib.saa_per_sample(self._h, zz.ctypes.data, form, _P(model.handle if model else None),
+                                      ctypes.byref(opt), _P(_ptr(q)), _P(_ptr(g)), ctypes.byref(rep))
+        _check(st, (SAA_OK, SAA_W_FALLBACK) + ((SAA_E_NOCONV,) if allow_noconv else ()))
+        out = rep.as_dict()
+        out["status"] = st
+        return q, g, out
+
+    def sample_status(self):
+        """Per-sample (flags, newton_iters, lin_iters, adj_lin_iters) of the last call (numpy int32)."""
+        import numpy as np
+        arrs = [np.zeros(self.n, dtype=np.int32) for _ in range(4)]
+        _check(self._lib.saa_sample_status(self._h, *[a.ctypes.data for a in arrs]))
+        return tuple(arrs)
+
+    def solve_states(self, Z, want_dudz=False, opt=None):
+        """Z: float64 CUDA tensor (N, d_Z).  Returns (u (N, d_U), q (N,),
+        dudz (N, d_Z, d_U) or None, report)."""
+        import torch
+        opt = opt if opt is not None else options()
+        Z = Z.contiguous()
+        u = torch.empty(self.n, self.d_u, dtype=torch.float64, device="cuda")
+        q = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        dudz = (torch.empty(self.n, self.d_z, self.d_u, dtype=torch.float64, device="cuda")
+                if want_dudz else None)
+        rep = CReport()
+        _check(self._lib.saa_solve_states(self._h, _P(_ptr(Z)), ctypes.byref(opt), _P(_ptr(u)), _P(_ptr(q)),
+                                          _P(_ptr(dudz)) if want_dudz else None, ctypes.byref(rep)))
+        return u, q, dudz, rep.as_dict()

@@ -1,0 +1,526 @@
+// C ABI of the SAA engine: argument validation, context and workspace
+// management, and the launch sequence of each entry point.  All numerical
+// work runs in the HIP kernels of pde.hip / cvar.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/saa.h"
+#include "pde.h"
+#include "runtime.h"
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+namespace saa_launch {
+void sine_table(double* S, int K1, int n, hipStream_t st);
+void source_matrix(double* FT, int n, int s, double sigma, hipStream_t st);
+void field(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
+           hipStream_t st);
+template <typename TS>
+void hierarchy(const PdeGeo& g, const double* em, double* kap, int64_t kstride, int64_t chunk,
+               const MgBufs<TS>& b, int64_t N, hipStream_t st);
+template <typename TW, typename TS>
+void state(const PdeGeo& g, const double* FT, const double* Z, int64_t z_stride, const double* em, TW* u, TW* f,
+           const MgBufs<TS>& b, const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N,
+           hipStream_t st);
+template <typename TW, typename TS>
+void adjoint(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* lam,
+             const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int all_samples,
+             double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st);
+template <typename TW, typename TS>
+void linearized(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* x,
+                const MgBufs<TS>& b, const SolveParams& sp, double* dudz, int* lin, int* flag, int64_t N,
+                hipStream_t st);
+template <typename TW>
+void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st);
+void cvar(const double* q, const double* g, int64_t N, int dz, double beta, double eps, double alpha,
+          const double* z, int t_mode, double t_in, int phase, double* tstar, double* out, const int* newton,
+          const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, hipStream_t st);
+}  // namespace saa_launch
+
+using saa_rt::DevBuf;
+
+namespace {
+
+struct CvarStatsHost {
+  int newton_max;
+  int n_unconverged;
+  int n_adjoints;
+  int pad;
+  long long lin_total;
+};
+
+template <typename TS>
+struct MgStore {
+  DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;
+  bool allocated = false;
+  bool built = false;
+  MgBufs<TS> view() const {
+    MgBufs<TS> m;
+    m.WE = (TS*)WE.p;
+    m.WN = (TS*)WN.p;
+    m.KD = (TS*)KD.p;
+    m.D = (TS*)D.p;
+    m.X = (TS*)X.p;
+    m.B = (TS*)B.p;
+    m.T = (TS*)T.p;
+    m.cx = (TS*)cx.p;
+    m.cr = (TS*)cr.p;
+    m.cp = (TS*)cp.p;
+    m.cq = (TS*)cq.p;
+    return m;
+  }
+};
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+struct saa_ctx {
+  saa_problem prob{};
+  int64_t N_max = 0;
+  int64_t N = 0;
+  hipStream_t st = nullptr;
+  PdeGeo geo{};
+  int K1 = 0, dz = 0;
+  int64_t nodes = 0, d_u = 0;
+  DevBuf FT, S, amp, em, xi, kap;
+  int64_t kstride = 0, kchunk = 0;
+  MgStore<double> mg64;
+  MgStore<float> mg32;
+  DevBuf u, f, lam;          // TW node vectors (sized for float64)
+  DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
+};
+
+namespace {
+
+int check_hip(hipError_t e) { return e == hipSuccess ? SAA_OK : SAA_E_DEVICE; }
+
+template <typename TS>
+int alloc_mg(saa_ctx* c, MgStore<TS>& m) {
+  if (m.allocated) return SAA_OK;
+  const size_t ls = (size_t)c->N_max * c->geo.lstride * sizeof(TS);
+  const size_t ns = (size_t)c->N_max * c->nodes * sizeof(TS);
+  DevBuf* lv[] = {&m.WE, &m.WN, &m.KD, &m.D, &m.X, &m.B, &m.T};
+  for (DevBuf* b : lv) {
+    int rc = b->alloc_zero(ls, c->st);
+    if (rc) return rc;
+  }
+  DevBuf* fv[] = {&m.cx, &m.cr, &m.cp, &m.cq};
+  for (DevBuf* b : fv) {
+    int rc = b->alloc_zero(ns, c->st);
+    if (rc) return rc;
+  }
+  m.allocated = true;
+  return SAA_OK;
+}
+
+template <typename TS>
+int build_mg(saa_ctx* c, MgStore<TS>& m) {
+  int rc = alloc_mg(c, m);
+  if (rc) return rc;
+  if (c->N == 0) return SAA_OK;
+  if (!c->kap.p) {
+    rc = c->kap.alloc((size_t)c->kchunk * c->kstride * sizeof(double));
+    if (rc) return rc;
+  }
+  saa_launch::hierarchy<TS>(c->geo, (const double*)c->em.p, (double*)c->kap.p, c->kstride, c->kchunk, m.view(),
+                            c->N, c->st);
+  m.built = true;
+  return check_hip(hipGetLastError());
+}
+
+SolveParams solve_params(const saa_options* o, bool fp32_state) {
+  SolveParams sp;
+  sp.newton_tol = o->newton_tol > 0 ? o->newton_tol : (fp32_state ? 1e-5 : 1e-13);
+  sp.lin_rtol = o->lin_rtol > 0 ? o->lin_rtol : (fp32_state ? 1e-5 : 1e-6);
+  sp.max_newton = o->max_newton > 0 ? o->max_newton : 30;
+  sp.max_lin = o->max_lin > 0 ? o->max_lin : 200;
+  sp.max_dc = o->max_dc > 0 ? o->max_dc : 10;
+  sp.nu = 1;
+  return sp;
+}
+
+int validate_options(const saa_options* o) {
+  if (!o) return SAA_E_INVALID;
+  if (!is_fin(o->beta) || o->beta < 0.0 || o->beta >= 1.0) return SAA_E_INVALID;
+  if (!is_fin(o->eps) || o->eps <= 0.0) return SAA_E_INVALID;
+  if (!is_fin(o->alpha) || o->alpha < 0.0) return SAA_E_INVALID;
+  if (o->t_mode != 0 && o->t_mode != 1) return SAA_E_INVALID;
+  if (o->t_mode == 1 && !is_fin(o->t_in)) return SAA_E_INVALID;
+  if (o->prec < SAA_FP64 || o->prec > SAA_FP8) return SAA_E_INVALID;
+  if (!is_fin(o->newton_tol) || !is_fin(o->lin_rtol)) return SAA_E_INVALID;
+  return SAA_OK;
+}
+
+// Launch the state solve for the requested PDE precision.
+int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const SolveParams& sp) {
+  int rc;
+  switch (prec) {
+    case SAA_FP64:
+      if (!c->mg64.built && (rc = build_mg(c, c->mg64))) return rc;
+      saa_launch::state<double, double>(c->geo, (double*)c->FT.p, Z, z_stride, (double*)c->em.p, (double*)c->u.p,
+                                        (double*)c->f.p, c->mg64.view(), sp, (double*)c->q.p, (int*)c->newton.p,
+                                        (int*)c->lin.p, (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32_DC64:
+      if (!c->mg32.built && (rc = build_mg(c, c->mg32))) return rc;
+      saa_launch::state<double, float>(c->geo, (double*)c->FT.p, Z, z_stride, (double*)c->em.p, (double*)c->u.p,
+                                       (double*)c->f.p, c->mg32.view(), sp, (double*)c->q.p, (int*)c->newton.p,
+                                       (int*)c->lin.p, (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32:
+      if (!c->mg32.built && (rc = build_mg(c, c->mg32))) return rc;
+      saa_launch::state<float, float>(c->geo, (double*)c->FT.p, Z, z_stride, (double*)c->em.p, (float*)c->u.p,
+                                      (float*)c->f.p, c->mg32.view(), sp, (double*)c->q.p, (int*)c->newton.p,
+                                      (int*)c->lin.p, (int*)c->flag.p, c->N, c->st);
+      break;
+    default:
+      return SAA_E_INVALID;
+  }
+  return check_hip(hipGetLastError());
+}
+
+int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int all, double* gout) {
+  switch (prec) {
+    case SAA_FP64:
+      saa_launch::adjoint<double, double>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
+                                          (double*)c->f.p, (double*)c->lam.p, c->mg64.view(), sp, (double*)c->q.p,
+                                          (double*)c->tstar.p, all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                          (int*)c->did.p, c->N, c->st);
+      break;
+    case SAA_FP32_DC64:
+      saa_launch::adjoint<double, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
+                                         (double*)c->f.p, (double*)c->lam.p, c->mg32.view(), sp, (double*)c->q.p,
+                                         (double*)c->tstar.p, all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                         (int*)c->did.p, c->N, c->st);
+      break;
+    case SAA_FP32:
+      saa_launch::adjoint<float, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (float*)c->u.p,
+                                        (float*)c->f.p, (float*)c->lam.p, c->mg32.view(), sp, (double*)c->q.p,
+                                        (double*)c->tstar.p, all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                        (int*)c->did.p, c->N, c->st);
+      break;
+    default:
+      return SAA_E_INVALID;
+  }
+  return check_hip(hipGetLastError());
+}
+
+int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJdt) {
+  CvarStatsHost s{};
+  int rc = check_hip(hipMemcpyAsync(&s, c->stats.p, sizeof(s), hipMemcpyDeviceToHost, c->st));
+  if (rc) return rc;
+  rc = check_hip(hipStreamSynchronize(c->st));
+  if (rc) return rc;
+  if (rep) {
+    rep->t_star = t;
+    rep->dJ_dt = dJdt;
+    rep->err_estimate = 0.0;
+    rep->seconds = seconds;
+    rep->newton_max = s.newton_max;
+    rep->n_unconverged = s.n_unconverged;
+    rep->n_adjoints = s.n_adjoints;
+    rep->fallback_used = 0;
+    rep->lin_total = s.lin_total;
+  }
+  return s.n_unconverged > 0 ? SAA_E_NOCONV : SAA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int saa_abi_version(void) { return SAA_ABI_VERSION; }
+
+const char* saa_status_str(int status) {
+  switch (status) {
+    case SAA_OK: return "ok";
+    case SAA_W_FALLBACK: return "ok (surrogate replaced by the PDE form)";
+    case SAA_E_INVALID: return "invalid argument";
+    case SAA_E_NOCONV: return "a Newton or CG iteration did not converge";
+    case SAA_E_DEVICE: return "HIP runtime error";
+    case SAA_E_OOM: return "device memory allocation failed";
+    case SAA_E_MODEL: return "model does not match the problem";
+    case SAA_E_IO: return "file could not be read or written, or is corrupt";
+    default: return "unknown status";
+  }
+}
+
+int saa_options_default(saa_options* o) {
+  if (!o) return SAA_E_INVALID;
+  std::memset(o, 0, sizeof(*o));
+  o->beta = 0.95;
+  o->eps = 1e-4;
+  o->alpha = 1e-3;
+  o->t_mode = 0;
+  o->t_in = 0.0;
+  o->prec = SAA_FP32_DC64;
+  o->newton_tol = 0.0;
+  o->lin_rtol = 0.0;
+  o->max_newton = 0;
+  o->max_lin = 0;
+  o->max_dc = 0;
+  o->all_adjoints = 0;
+  o->fallback_tol = 1e-2;
+  return SAA_OK;
+}
+
+int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx** out) {
+  if (!p || !out) return SAA_E_INVALID;
+  *out = nullptr;
+  if (p->dim != 2) return SAA_E_INVALID;
+  if (p->n < 4 || p->n > 4096 || (p->n & (p->n - 1))) return SAA_E_INVALID;
+  if (p->n_src_per_dim < 1 || p->n_src_per_dim > 8) return SAA_E_INVALID;
+  if (!is_fin(p->src_sigma) || p->src_sigma <= 0) return SAA_E_INVALID;
+  if (p->kl_per_dim < 1 || p->kl_per_dim > 64) return SAA_E_INVALID;
+  if (!is_fin(p->kl_shift) || p->kl_shift < 0 || !is_fin(p->kl_exp) || p->kl_exp <= 0) return SAA_E_INVALID;
+  if (!is_fin(p->kl_amp) || !is_fin(p->reaction) || p->reaction < 0 || !is_fin(p->u_target))
+    return SAA_E_INVALID;
+  if (N_max < 1 || N_max > (int64_t)1 << 24) return SAA_E_INVALID;
+  // the field synthesis keeps a K1 x (n+1) table and the K1 x K1 coefficients in 64 KB of LDS
+  if ((int64_t)p->kl_per_dim * (p->n + 1) + (int64_t)p->kl_per_dim * p->kl_per_dim > 8192) return SAA_E_INVALID;
+
+  saa_ctx* c = new (std::nothrow) saa_ctx();
+  if (!c) return SAA_E_OOM;
+  c->prob = *p;
+  c->N_max = N_max;
+  c->st = (hipStream_t)hip_stream;
+  c->K1 = p->kl_per_dim;
+  c->dz = p->n_src_per_dim * p->n_src_per_dim;
+  c->nodes = (int64_t)(p->n + 1) * (p->n + 1);
+  c->d_u = (int64_t)(p->n - 1) * (p->n - 1);
+  PdeGeo& g = c->geo;
+  g.L = 0;
+  int64_t off = 0;
+  for (int n = p->n; n >= 2; n >>= 1) {
+    g.n[g.L] = n;
+    g.off[g.L] = off;
+    off += (int64_t)(n + 1) * (n + 1);
+    ++g.L;
+  }
+  g.lstride = off;
+  g.nodes = c->nodes;
+  g.dz = c->dz;
+  g.h2 = 1.0 / ((double)p->n * p->n);
+  g.r = p->reaction;
+  g.ut = p->u_target;
+  int64_t ks = 0;
+  for (int l = 0; l < g.L; ++l) ks += 2 * (int64_t)g.n[l] * g.n[l];
+  c->kstride = ks;
+  c->kchunk = N_max < 256 ? N_max : 256;
+
+  int rc = SAA_OK;
+  const size_t tw = (size_t)N_max * c->nodes * sizeof(double);
+  if (!rc) rc = c->FT.alloc((size_t)c->dz * c->nodes * sizeof(double));
+  if (!rc) rc = c->S.alloc((size_t)c->K1 * (p->n + 1) * sizeof(double));
+  if (!rc) rc = c->amp.alloc((size_t)c->K1 * c->K1 * sizeof(double));
+  if (!rc) rc = c->em.alloc(tw);
+  if (!rc) rc = c->xi.alloc((size_t)N_max * c->K1 * c->K1 * sizeof(double));
+  if (!rc) rc = c->u.alloc_zero(tw, c->st);
+  if (!rc) rc = c->f.alloc_zero(tw, c->st);
+  if (!rc) rc = c->lam.alloc_zero(tw, c->st);
+  if (!rc) rc = c->q.alloc((size_t)N_max * sizeof(double));
+  if (!rc) rc = c->g.alloc((size_t)N_max * c->dz * sizeof(double));
+  if (!rc) rc = c->newton.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->lin.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->lin_adj.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->flag.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->did.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->tstar.alloc(sizeof(double));
+  if (!rc) rc = c->zdev.alloc(SAA_MAX_DZ * sizeof(double));
+  if (!rc) rc = c->out.alloc((2 + SAA_MAX_DZ) * sizeof(double));
+  if (!rc) rc = c->stats.alloc(sizeof(CvarStatsHost));
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  // shared operators: sine table, KL amplitudes, lumped source matrix
+  {
+    double* a = new double[(size_t)c->K1 * c->K1];
+    for (int j = 1; j <= c->K1; ++j)
+      for (int k = 1; k <= c->K1; ++k)
+        a[(j - 1) * c->K1 + (k - 1)] =
+            p->kl_amp * std::pow(M_PI * M_PI * (double)(j * j + k * k) + p->kl_shift, -p->kl_exp);
+    rc = check_hip(hipMemcpyAsync(c->amp.p, a, sizeof(double) * c->K1 * c->K1, hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+    delete[] a;
+  }
+  if (!rc) {
+    saa_launch::sine_table((double*)c->S.p, c->K1, p->n, c->st);
+    saa_launch::source_matrix((double*)c->FT.p, p->n, p->n_src_per_dim, p->src_sigma, c->st);
+    rc = check_hip(hipGetLastError());
+  }
+  if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return SAA_OK;
+}
+
+void saa_ctx_destroy(saa_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  delete c;
+}
+
+int saa_ctx_dims(const saa_ctx* c, int64_t* d_u, int* d_z, int* n_kl) {
+  if (!c) return SAA_E_INVALID;
+  if (d_u) *d_u = c->d_u;
+  if (d_z) *d_z = c->dz;
+  if (n_kl) *n_kl = c->K1 * c->K1;
+  return SAA_OK;
+}
+
+int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
+  if (!c || !xi_dev || N < 1 || N > c->N_max) return SAA_E_INVALID;
+  int rc = check_hip(hipMemcpyAsync(c->xi.p, xi_dev, sizeof(double) * N * c->K1 * c->K1,
+                                    hipMemcpyDeviceToDevice, c->st));
+  if (rc) return rc;
+  c->N = N;
+  saa_launch::field((const double*)c->xi.p, (const double*)c->S.p, (const double*)c->amp.p, (double*)c->em.p,
+                    c->K1, c->prob.n, N, c->st);
+  rc = check_hip(hipGetLastError());
+  if (rc) return rc;
+  c->mg64.built = false;
+  c->mg32.built = false;
+  if (c->mg64.allocated && (rc = build_mg(c, c->mg64))) return rc;
+  if (c->mg32.allocated && (rc = build_mg(c, c->mg32))) return rc;
+  return check_hip(hipStreamSynchronize(c->st));
+}
+
+int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
+                       double* J, double* grad_z, saa_report* rep) {
+  if (!c || !z || !J || !grad_z) return SAA_E_INVALID;
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  if (c->N < 1) return SAA_E_INVALID;
+  for (int k = 0; k < c->dz; ++k)
+    if (!is_fin(z[k])) return SAA_E_INVALID;
+  if (form != SAA_FORM_PDE || model != nullptr) return SAA_E_INVALID;
+  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
+
+  const auto t0 = std::chrono::steady_clock::now();
+  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+  if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
+    return rc;
+  if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
+  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
+                   (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, (double*)c->tstar.p, (double*)c->out.p, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, nullptr, c->st);
+  if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
+  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
+                   (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, (double*)c->tstar.p, (double*)c->out.p,
+                   (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
+                   c->stats.p, c->st);
+  if ((rc = check_hip(hipGetLastError()))) return rc;
+  double host[2 + SAA_MAX_DZ];
+  double t = 0;
+  if ((rc = check_hip(hipMemcpyAsync(host, c->out.p, sizeof(double) * (2 + c->dz), hipMemcpyDeviceToHost, c->st))))
+    return rc;
+  if ((rc = check_hip(hipMemcpyAsync(&t, c->tstar.p, sizeof(double), hipMemcpyDeviceToHost, c->st)))) return rc;
+  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *J = host[0];
+  for (int k = 0; k < c->dz; ++k) grad_z[k] = host[2 + k];
+  return fill_report(c, rep, secs, t, host[1]);
+}
+
+int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
+                   double* q_dev, double* g_dev, saa_report* rep) {
+  if (!c || !z || !q_dev || !g_dev) return SAA_E_INVALID;
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  if (c->N < 1) return SAA_E_INVALID;
+  for (int k = 0; k < c->dz; ++k)
+    if (!is_fin(z[k])) return SAA_E_INVALID;
+  if (form != SAA_FORM_PDE || model != nullptr) return SAA_E_INVALID;
+  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+  if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
+    return rc;
+  if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
+  if ((rc = run_adjoint(c, opt->prec, sp, 1, g_dev))) return rc;
+  if ((rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
+    return rc;
+  saa_launch::cvar((double*)c->q.p, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p,
+                   opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p,
+                   (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats.p, c->st);
+  if ((rc = check_hip(hipGetLastError()))) return rc;
+  double t = 0, host[2];
+  if ((rc = check_hip(hipMemcpyAsync(host, c->out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, c->st)))) return rc;
+  if ((rc = check_hip(hipMemcpyAsync(&t, c->tstar.p, sizeof(double), hipMemcpyDeviceToHost, c->st)))) return rc;
+  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return fill_report(c, rep, secs, t, host[1]);
+}
+
+int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
+                     double* dudz_dev, saa_report* rep) {
+  if (!c || !Z_dev || !u_dev) return SAA_E_INVALID;
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  if (c->N < 1) return SAA_E_INVALID;
+  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+  if ((rc = run_state(c, opt->prec, Z_dev, c->dz, sp))) return rc;
+  const int n = c->prob.n;
+  if (opt->prec == SAA_FP32) saa_launch::interior_copy<float>((float*)c->u.p, u_dev, n, c->N, c->st);
+  else saa_launch::interior_copy<double>((double*)c->u.p, u_dev, n, c->N, c->st);
+  if (q_dev &&
+      (rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
+    return rc;
+  if ((rc = check_hip(hipMemsetAsync(c->lin_adj.p, 0, sizeof(int) * c->N, c->st)))) return rc;
+  if (dudz_dev) {
+    switch (opt->prec) {
+      case SAA_FP64:
+        saa_launch::linearized<double, double>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
+                                               (double*)c->f.p, (double*)c->lam.p, c->mg64.view(), sp, dudz_dev,
+                                               (int*)c->lin_adj.p, (int*)c->flag.p, c->N, c->st);
+        break;
+      case SAA_FP32_DC64:
+        saa_launch::linearized<double, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
+                                              (double*)c->f.p, (double*)c->lam.p, c->mg32.view(), sp, dudz_dev,
+                                              (int*)c->lin_adj.p, (int*)c->flag.p, c->N, c->st);
+        break;
+      default:
+        saa_launch::linearized<float, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (float*)c->u.p,
+                                             (float*)c->f.p, (float*)c->lam.p, c->mg32.view(), sp, dudz_dev,
+                                             (int*)c->lin_adj.p, (int*)c->flag.p, c->N, c->st);
+    }
+  }
+  // stats only (phase 0)
+  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, 0.0, 1.0, 0.0, (double*)c->zdev.p, 1, 0.0, 0,
+                   (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
+                   (int*)c->lin_adj.p, nullptr, c->stats.p, c->st);
+  if ((rc = check_hip(hipGetLastError()))) return rc;
+  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return fill_report(c, rep, secs, 0.0, 0.0);
+}
+
+int saa_sample_status(saa_ctx* c, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters) {
+  if (!c || c->N < 1) return SAA_E_INVALID;
+  const size_t b = sizeof(int) * (size_t)c->N;
+  int rc = SAA_OK;
+  if (flags && !rc) rc = check_hip(hipMemcpyAsync(flags, c->flag.p, b, hipMemcpyDeviceToHost, c->st));
+  if (newton_iters && !rc) rc = check_hip(hipMemcpyAsync(newton_iters, c->newton.p, b, hipMemcpyDeviceToHost, c->st));
+  if (lin_iters && !rc) rc = check_hip(hipMemcpyAsync(lin_iters, c->lin.p, b, hipMemcpyDeviceToHost, c->st));
+  if (adj_lin_iters && !rc) rc = check_hip(hipMemcpyAsync(adj_lin_iters, c->lin_adj.p, b, hipMemcpyDeviceToHost, c->st));
+  if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+  return rc;
+}
+
+}  // extern "C"

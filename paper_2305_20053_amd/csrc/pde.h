@@ -1,0 +1,52 @@
+// PDE-form data structures shared by the HIP kernels and the host runtime.
+#pragma once
+#include <stdint.h>
+
+#define SAA_MAX_LEVELS 12
+#define SAA_MAX_DZ 64
+
+// Multigrid level geometry of one sample.  Level 0 is the fine grid with n
+// cells per side; level l has n >> l cells.  Every per-level array stores the
+// full (n_l+1)^2 node grid (boundary entries stay zero), and the levels of
+// one sample are stacked at offsets off[l] inside a block of `lstride`
+// elements.
+struct PdeGeo {
+  int L;                        // number of levels (coarsest has 1 unknown)
+  int n[SAA_MAX_LEVELS];        // cells per side
+  int64_t off[SAA_MAX_LEVELS];  // element offset of level l inside a sample block
+  int64_t lstride;              // elements per sample of level-stacked arrays
+  int64_t nodes;                // (n_0 + 1)^2
+  int dz;                       // number of controls
+  double h2;                    // h^2 = lumped P1 weight of an interior node
+  double r;                     // reaction coefficient
+  double ut;                    // target state
+};
+
+// Per-sample multigrid / CG workspaces in the solver precision TS.
+template <typename TS>
+struct MgBufs {
+  TS* WE;  // edge weight of (i,j)-(i+1,j), level-stacked
+  TS* WN;  // edge weight of (i,j)-(i,j+1), level-stacked
+  TS* KD;  // stiffness diagonal (sum of the four incident edge weights)
+  TS* D;   // operator diagonal: KD + lumped reaction 3 r h^2 u^2 (restricted)
+  TS* X;   // V-cycle iterate per level (level 0 = preconditioned residual z)
+  TS* B;   // V-cycle right-hand side per level (level 0 unused)
+  TS* T;   // V-cycle residual / reaction scratch per level
+  TS* cx;  // CG solution (fine grid)
+  TS* cr;  // CG residual
+  TS* cp;  // CG search direction
+  TS* cq;  // A p
+};
+
+// Solver controls passed to the persistent kernels.
+struct SolveParams {
+  double newton_tol;  // stop when |update| <= newton_tol |iterate|
+  double lin_rtol;    // inner PCG relative residual
+  int max_newton;
+  int max_lin;
+  int max_dc;
+  int nu;             // red-black smoothing sweeps before and after each coarse correction
+};
+
+// Per-sample status flags.
+enum { SAA_FLAG_NEWTON = 1, SAA_FLAG_CG = 2, SAA_FLAG_DC = 4, SAA_FLAG_NAN = 8 };

@@ -1,0 +1,808 @@
+// PDE form of the SAA objective: batched P1 finite-element Newton solves of
+//   -div(exp(m) grad u) + r u^3 = sum_k z_k f_k,  u = 0 on the boundary
+// (paper Sec. 4.2, eq. (elliptic_pde)), the tracking QoI, and the adjoint
+// gradient dq/dz = F^T lambda, A(u) lambda = dq/du (Sec. 2.3,
+// eq. (ouu_qoi_gradient)).
+//
+// Design: one workgroup owns one sample for its whole solve.  Samples are
+// independent, so every Newton step, every preconditioned-CG iteration and
+// every multigrid V-cycle of a sample runs inside one persistent workgroup
+// with only workgroup barriers; per-sample convergence decisions are taken on
+// the device and no grid-wide synchronisation or host round trip is needed.
+//
+// Discretisation facts used here (all follow from the P1 element matrices on
+// the mesh whose cells are split along the (i,j)-(i+1,j+1) diagonal):
+//  * the stiffness matrix is a 5-point stencil: the edge (i,j)-(i+1,j) has
+//    weight (kappa_lo(i,j) + kappa_up(i,j-1))/2, the edge (i,j)-(i,j+1) has
+//    weight (kappa_up(i,j) + kappa_lo(i-1,j))/2, with kappa_T the mean of
+//    exp(m) over the vertices of T; diagonal-edge couplings vanish;
+//  * the lumped reaction / source weight of an interior node is h^2;
+//  * the consistent mass matrix couples a node to its E, W, N, S, NE and SW
+//    neighbours with h^2/12 and to itself with h^2/2;
+//  * the P1 spaces of the grids n and n/2 are nested, so prolongation is
+//    linear interpolation (midpoints of horizontal, vertical and diagonal
+//    coarse edges take the mean of the two end values) and the Galerkin
+//    coarse stiffness is again the P1 stencil with each coarse triangle's
+//    kappa equal to the mean over its four child triangles.
+#include "common.h"
+#include "pde.h"
+
+#ifndef SAA_PDE_BLOCK
+#define SAA_PDE_BLOCK 512
+#endif
+
+namespace {
+
+constexpr int BS = SAA_PDE_BLOCK;
+
+// ---------------------------------------------------------------------------
+// Node iteration: the calling thread visits nodes p = tid, tid + BS, ... of an
+// (n+1)^2 grid, tracking (i, j) incrementally.
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void for_nodes(int n, F&& f) {
+  const int np = n + 1;
+  const int total = np * np;
+  int p = threadIdx.x;
+  if (p >= total) return;
+  int j = p / np;
+  int i = p - j * np;
+  const int sj = BS / np;
+  const int si = BS - sj * np;
+  for (; p < total; p += BS) {
+    f(p, i, j);
+    i += si;
+    j += sj;
+    if (i >= np) {
+      i -= np;
+      ++j;
+    }
+  }
+}
+
+__device__ __forceinline__ bool interior(int i, int j, int n) {
+  return i > 0 && j > 0 && i < n && j < n;
+}
+
+// FP64 edge weights of the fine stiffness computed from nodal exp(m):
+// WE(i,j) = [2e(i,j) + 2e(i+1,j) + e(i+1,j+1) + e(i,j-1)] / 6
+// WN(i,j) = [2e(i,j) + 2e(i,j+1) + e(i+1,j+1) + e(i-1,j)] / 6
+template <typename TW>
+__device__ __forceinline__ TW weight_e(const double* e, int p, int np) {
+  return (TW)((2.0 * e[p] + 2.0 * e[p + 1] + e[p + np + 1] + e[p - np]) * (1.0 / 6.0));
+}
+template <typename TW>
+__device__ __forceinline__ TW weight_n(const double* e, int p, int np) {
+  return (TW)((2.0 * e[p] + 2.0 * e[p + np] + e[p + np + 1] + e[p - 1]) * (1.0 / 6.0));
+}
+
+// (K u)_p with the fine stiffness from exp(m), in precision TW.
+template <typename TW>
+__device__ __forceinline__ TW stiff_apply_em(const double* e, const TW* u, int p, int np) {
+  const TW we = weight_e<TW>(e, p, np);
+  const TW ww = weight_e<TW>(e, p - 1, np);
+  const TW wn = weight_n<TW>(e, p, np);
+  const TW ws = weight_n<TW>(e, p - np, np);
+  return (we + ww + wn + ws) * u[p] - we * u[p + 1] - ww * u[p - 1] - wn * u[p + np] - ws * u[p - np];
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid building blocks (precision TS), all for one sample.
+// ---------------------------------------------------------------------------
+template <typename TS>
+struct Level {
+  int n, np;
+  const TS* WE;
+  const TS* WN;
+  const TS* D;
+};
+
+template <typename TS>
+__device__ __forceinline__ Level<TS> level(const PdeGeo& g, const MgBufs<TS>& m, int l) {
+  Level<TS> L;
+  L.n = g.n[l];
+  L.np = g.n[l] + 1;
+  L.WE = m.WE + g.off[l];
+  L.WN = m.WN + g.off[l];
+  L.D = m.D + g.off[l];
+  return L;
+}
+
+template <typename TS>
+__device__ __forceinline__ TS offdiag_sum(const Level<TS>& L, const TS* x, int p) {
+  return L.WE[p] * x[p + 1] + L.WE[p - 1] * x[p - 1] + L.WN[p] * x[p + L.np] + L.WN[p - L.np] * x[p - L.np];
+}
+
+// One red-black Gauss-Seidel half sweep on colour c: x_p = (b_p + sum w x_q) / D_p.
+// If `first`, the other colour is known to be zero and x_p = b_p / D_p.
+template <typename TS>
+__device__ void gs_half(const Level<TS>& L, const TS* b, TS* x, int c, bool first) {
+  for_nodes(L.n, [&](int p, int i, int j) {
+    if (interior(i, j, L.n) && ((i + j) & 1) == c) {
+      TS s = b[p];
+      if (!first) s += offdiag_sum(L, x, p);
+      x[p] = s / L.D[p];
+    }
+  });
+  __syncthreads();
+}
+
+// t = b - A x on level L.
+template <typename TS>
+__device__ void residual_level(const Level<TS>& L, const TS* b, const TS* x, TS* t) {
+  for_nodes(L.n, [&](int p, int i, int j) {
+    if (interior(i, j, L.n)) t[p] = b[p] - (L.D[p] * x[p] - offdiag_sum(L, x, p));
+  });
+  __syncthreads();
+}
+
+// Restriction R = P^T from the fine level (n) to the coarse level (n/2).
+template <typename TS>
+__device__ void restrict_level(int nf, const TS* t, int nc, TS* bc) {
+  const int npf = nf + 1;
+  for_nodes(nc, [&](int pc, int I, int J) {
+    if (interior(I, J, nc)) {
+      const int p = (2 * J) * npf + 2 * I;
+      bc[pc] = t[p] + (TS)0.5 * (t[p + 1] + t[p - 1] + t[p + npf] + t[p - npf] + t[p + npf + 1] + t[p - npf - 1]);
+    }
+  });
+  __syncthreads();
+}
+
+// x_f += P x_c (linear interpolation on the nested P1 mesh).
+template <typename TS>
+__device__ void prolong_add(int nf, TS* xf, int nc, const TS* xc) {
+  const int npc = nc + 1;
+  for_nodes(nf, [&](int p, int i, int j) {
+    if (interior(i, j, nf)) {
+      const int I = i >> 1, J = j >> 1;
+      const int q = J * npc + I;
+      TS v;
+      if (!(i & 1) && !(j & 1)) v = xc[q];
+      else if ((i & 1) && !(j & 1)) v = (TS)0.5 * (xc[q] + xc[q + 1]);
+      else if (!(i & 1) && (j & 1)) v = (TS)0.5 * (xc[q] + xc[q + npc]);
+      else v = (TS)0.5 * (xc[q] + xc[q + npc + 1]);
+      xf[p] += v;
+    }
+  });
+  __syncthreads();
+}
+
+// Symmetric V-cycle: X_0 = V(b0).  Pre-smoothing nu x (red, black), post
+// smoothing nu x (black, red), so that the preconditioner is symmetric.
+template <typename TS>
+__device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int nu) {
+  const int L = g.L;
+  for (int l = 0; l < L - 1; ++l) {
+    const Level<TS> lv = level(g, m, l);
+    const TS* b = (l == 0) ? b0 : m.B + g.off[l];
+    TS* x = m.X + g.off[l];
+    TS* t = m.T + g.off[l];
+    for (int s = 0; s < nu; ++s) {
+      gs_half(lv, b, x, 0, s == 0);
+      gs_half(lv, b, x, 1, false);
+    }
+    residual_level(lv, b, x, t);
+    restrict_level(g.n[l], t, g.n[l + 1], m.B + g.off[l + 1]);
+  }
+  {  // coarsest level: a single unknown at node (1,1) of the n = 2 grid
+    const int l = L - 1;
+    if (threadIdx.x == 0) {
+      const int p = 1 * (g.n[l] + 1) + 1;
+      m.X[g.off[l] + p] = m.B[g.off[l] + p] / m.D[g.off[l] + p];
+    }
+    __syncthreads();
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const Level<TS> lv = level(g, m, l);
+    const TS* b = (l == 0) ? b0 : m.B + g.off[l];
+    TS* x = m.X + g.off[l];
+    prolong_add(g.n[l], x, g.n[l + 1], m.X + g.off[l + 1]);
+    for (int s = 0; s < nu; ++s) {
+      gs_half(lv, b, x, 1, false);
+      gs_half(lv, b, x, 0, false);
+    }
+  }
+}
+
+// Lumped reaction 3 r h^2 u^2 on the fine level and its restrictions; sets
+// D_l = KD_l + reaction_l on every level.  Uses T as scratch.
+template <typename TW, typename TS>
+__device__ void build_diagonals(const PdeGeo& g, const MgBufs<TS>& m, const TW* u) {
+  const double c = 3.0 * g.r * g.h2;
+  for_nodes(g.n[0], [&](int p, int i, int j) {
+    if (interior(i, j, g.n[0])) {
+      const double uu = (double)u[p];
+      const TS d = (TS)(c * uu * uu);
+      m.T[p] = d;
+      m.D[p] = m.KD[p] + d;
+    }
+  });
+  __syncthreads();
+  for (int l = 0; l < g.L - 1; ++l) {
+    restrict_level(g.n[l], m.T + g.off[l], g.n[l + 1], m.T + g.off[l + 1]);
+    const int64_t o = g.off[l + 1];
+    for_nodes(g.n[l + 1], [&](int p, int i, int j) {
+      if (interior(i, j, g.n[l + 1])) m.D[o + p] = m.KD[o + p] + m.T[o + p];
+    });
+    __syncthreads();
+  }
+}
+
+// Preconditioned CG on A x = b with b in m.cr (overwritten by the residual),
+// x in m.cx.  Returns iterations; sets *ok = false if not converged.
+template <typename TS>
+__device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it, int nu,
+                   double* red, bool* ok) {
+  const Level<TS> L0 = level(g, m, 0);
+  const int n = g.n[0];
+  double rr0 = 0.0;
+  for_nodes(n, [&](int p, int i, int j) {
+    if (interior(i, j, n)) {
+      const double r = (double)m.cr[p];
+      rr0 += r * r;
+      m.cx[p] = (TS)0;
+    }
+  });
+  rr0 = block_sum1(rr0, red);
+  if (!(rr0 > 0.0)) {
+    *ok = (rr0 == 0.0);
+    return 0;
+  }
+  TS* z = m.X;  // level-0 V-cycle output
+  vcycle(g, m, m.cr, nu);
+  double rz = 0.0;
+  for_nodes(n, [&](int p, int i, int j) {
+    if (interior(i, j, n)) {
+      rz += (double)m.cr[p] * (double)z[p];
+      m.cp[p] = z[p];
+    }
+  });
+  rz = block_sum1(rz, red);
+  const double tol2 = rtol * rtol * rr0;
+  for (int it = 1; it <= max_it; ++it) {
+    double pq = 0.0;
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        const TS q = L0.D[p] * m.cp[p] - offdiag_sum(L0, m.cp, p);
+        m.cq[p] = q;
+        pq += (double)m.cp[p] * (double)q;
+      }
+    });
+    pq = block_sum1(pq, red);
+    if (!(pq > 0.0)) {
+      *ok = false;
+      return it;
+    }
+    const double alpha = rz / pq;
+    const TS a = (TS)alpha;
+    double rr = 0.0;
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        m.cx[p] += a * m.cp[p];
+        const TS r = m.cr[p] - a * m.cq[p];
+        m.cr[p] = r;
+        rr += (double)r * (double)r;
+      }
+    });
+    rr = block_sum1(rr, red);
+    if (rr <= tol2) return it;
+    vcycle(g, m, m.cr, nu);
+    double rzn = 0.0;
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) rzn += (double)m.cr[p] * (double)z[p];
+    });
+    rzn = block_sum1(rzn, red);
+    const TS beta = (TS)(rzn / rz);
+    rz = rzn;
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) m.cp[p] = z[p] + beta * m.cp[p];
+    });
+    __syncthreads();
+  }
+  *ok = false;
+  return max_it;
+}
+
+// Per-sample views of the batched buffers.
+template <typename TS>
+__device__ __forceinline__ MgBufs<TS> sample_bufs(const MgBufs<TS>& all, const PdeGeo& g, int64_t s) {
+  MgBufs<TS> m;
+  const int64_t ls = s * g.lstride, ns = s * g.nodes;
+  m.WE = all.WE + ls;
+  m.WN = all.WN + ls;
+  m.KD = all.KD + ls;
+  m.D = all.D + ls;
+  m.X = all.X + ls;
+  m.B = all.B + ls;
+  m.T = all.T + ls;
+  m.cx = all.cx + ns;
+  m.cr = all.cr + ns;
+  m.cp = all.cp + ns;
+  m.cq = all.cq + ns;
+  return m;
+}
+
+// Defect correction for A(u) x = b with A in precision TW (exact fine
+// stiffness from exp(m) plus 3 r h^2 u^2) and inner PCG in precision TS.
+// b and x are TW node vectors.  The multigrid diagonals must already be built
+// for u.  Returns the number of inner CG iterations; clears *ok on failure.
+template <typename TW, typename TS>
+__device__ int dc_solve(const PdeGeo& g, const MgBufs<TS>& m, const SolveParams& sp,
+                        const double* em, const TW* u, const TW* b, TW* x, double* red,
+                        bool* ok, int* passes) {
+  const int n = g.n[0], np = n + 1;
+  const double c = 3.0 * g.r * g.h2;
+  int lin = 0;
+  for_nodes(n, [&](int p, int i, int j) {
+    x[p] = (TW)0;
+    if (interior(i, j, n)) m.cr[p] = (TS)b[p];
+  });
+  __syncthreads();
+  int pass = 0;
+  double prev_step = INFINITY;
+  for (pass = 0; pass < sp.max_dc; ++pass) {
+    bool cg_ok = true;
+    lin += pcg(g, m, sp.lin_rtol, sp.max_lin, sp.nu, red, &cg_ok);
+    double v[2] = {0.0, 0.0};
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        const TW d = (TW)m.cx[p];
+        const TW xn = x[p] + d;
+        x[p] = xn;
+        v[0] += (double)d * (double)d;
+        v[1] += (double)xn * (double)xn;
+      }
+    });
+    block_sum<2>(v, red);
+    if (!(v[0] == v[0]) || !(v[1] == v[1])) {
+      *ok = false;
+      break;
+    }
+    if (v[0] <= sp.newton_tol * sp.newton_tol * v[1] || (v[0] <= 1e-8 * v[1] && v[0] > 0.0625 * prev_step))
+      break;
+    prev_step = v[0];
+    // new defect b - A x in precision TW
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        const TW uu = u[p];
+        const TW ax = stiff_apply_em<TW>(em, x, p, np) + (TW)c * uu * uu * x[p];
+        m.cr[p] = (TS)(b[p] - ax);
+      }
+    });
+    __syncthreads();
+  }
+  if (pass == sp.max_dc) *ok = false;
+  *passes = pass + 1;
+  return lin;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Setup kernels (run once per sample set; not part of an objective evaluation)
+// ---------------------------------------------------------------------------
+
+// S[j][i] = sin((j+1) pi i / n), j < K1, 0 <= i <= n.
+__global__ void saa_k_sine_table(double* S, int K1, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K1 * (n + 1)) return;
+  const int j = t / (n + 1), i = t - j * (n + 1);
+  S[t] = sin(M_PI * (double)((j + 1) * i) / (double)n);
+}
+
+// FT[k][p] = h^2 f_k(x_p) on interior nodes (lumped P1 load), 0 on the boundary.
+__global__ void saa_k_source_matrix(double* FT, int n, int s, double sigma) {
+  const int np = n + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nodes = (int64_t)np * np;
+  if (t >= nodes * s * s) return;
+  const int k = (int)(t / nodes);
+  const int p = (int)(t - (int64_t)k * nodes);
+  const int j = p / np, i = p - j * np;
+  double v = 0.0;
+  if (i > 0 && j > 0 && i < n && j < n) {
+    const int a = k % s, b = k / s;
+    const double h = 1.0 / n;
+    const double cx = (a + 1.0) / (s + 1.0), cy = (b + 1.0) / (s + 1.0);
+    const double dx = i * h - cx, dy = j * h - cy;
+    v = h * h * exp(-(dx * dx + dy * dy) / (2.0 * sigma * sigma)) / (sigma * sqrt(2.0 * M_PI));
+  }
+  FT[t] = v;
+}
+
+// Nodal exp(m) of each sample: m = sum_jk a_jk xi_jk sin(j pi x) sin(k pi y),
+// evaluated separably (a K1 x (n+1) intermediate in LDS).  One block per sample.
+__global__ void __launch_bounds__(256) saa_k_field(const double* xi, const double* S, const double* amp,
+                                                   double* em, int K1, int n, int64_t N) {
+  extern __shared__ double sh[];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  const int np = n + 1;
+  double* Tjy = sh;                 // K1 x np : sum_k a_jk xi_jk sin(k pi y)
+  double* axi = sh + K1 * np;       // K1 x K1
+  const double* x = xi + s * K1 * K1;
+  for (int t = threadIdx.x; t < K1 * K1; t += blockDim.x) axi[t] = amp[t] * x[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < K1 * np; t += blockDim.x) {
+    const int j = t / np, y = t - j * np;
+    double acc = 0.0;
+    for (int k = 0; k < K1; ++k) acc += axi[j * K1 + k] * S[k * np + y];
+    Tjy[t] = acc;
+  }
+  __syncthreads();
+  double* e = em + s * (int64_t)np * np;
+  for (int p = threadIdx.x; p < np * np; p += blockDim.x) {
+    const int y = p / np, xx = p - y * np;
+    double acc = 0.0;
+    for (int j = 0; j < K1; ++j) acc += Tjy[j * np + y] * S[j * np + xx];
+    e[p] = exp(acc);
+  }
+}
+
+// Multigrid hierarchy of each sample: per-triangle kappa on every level
+// (fine: vertex means of exp(m); coarse: mean of the four child triangles),
+// then edge weights and stiffness diagonals.  kap: per-sample scratch of
+// 2 * sum_l n_l^2 doubles.  One block per sample.
+template <typename TS>
+__global__ void __launch_bounds__(BS) saa_k_hierarchy(PdeGeo g, const double* em_all, double* kap_all,
+                                                      int64_t kstride, MgBufs<TS> all, int64_t s0,
+                                                      int64_t N) {
+  const int64_t s = s0 + blockIdx.x;
+  if (s >= N) return;
+  const double* e = em_all + s * g.nodes;
+  double* kap = kap_all + (int64_t)blockIdx.x * kstride;
+  MgBufs<TS> m = sample_bufs(all, g, s);
+  // kappa offsets per level: lo at ko, up at ko + n^2
+  int64_t ko = 0;
+  for (int l = 0; l < g.L; ++l) {
+    const int n = g.n[l];
+    double* klo = kap + ko;
+    double* kup = klo + (int64_t)n * n;
+    if (l == 0) {
+      const int np = n + 1;
+      for (int c = threadIdx.x; c < n * n; c += BS) {
+        const int j = c / n, i = c - j * n;
+        const int p = j * np + i;
+        klo[c] = (e[p] + e[p + 1] + e[p + np + 1]) / 3.0;
+        kup[c] = (e[p] + e[p + np + 1] + e[p + np]) / 3.0;
+      }
+    } else {
+      const int nf = 2 * n;
+      const double* flo = kap + ko - 2 * (int64_t)nf * nf;
+      const double* fup = flo + (int64_t)nf * nf;
+      for (int c = threadIdx.x; c < n * n; c += BS) {
+        const int J = c / n, I = c - J * n;
+        const int f00 = (2 * J) * nf + 2 * I, f10 = f00 + 1, f01 = f00 + nf, f11 = f00 + nf + 1;
+        klo[c] = 0.25 * (flo[f00] + flo[f10] + flo[f11] + fup[f10]);
+        kup[c] = 0.25 * (fup[f00] + fup[f11] + fup[f01] + flo[f01]);
+      }
+    }
+    __syncthreads();
+    // edge weights and diagonal on the node grid of this level
+    const int np = n + 1;
+    TS* WE = m.WE + g.off[l];
+    TS* WN = m.WN + g.off[l];
+    TS* KD = m.KD + g.off[l];
+    for (int p = threadIdx.x; p < np * np; p += BS) {
+      const int j = p / np, i = p - j * np;
+      double we = 0.0, wn = 0.0;
+      if (i < n && j >= 1 && j <= n - 1) we = 0.5 * (klo[j * n + i] + kup[(j - 1) * n + i]);
+      if (j < n && i >= 1 && i <= n - 1) wn = 0.5 * (kup[j * n + i] + klo[j * n + i - 1]);
+      WE[p] = (TS)we;
+      WN[p] = (TS)wn;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < np * np; p += BS) {
+      const int j = p / np, i = p - j * np;
+      TS d = (TS)0;
+      if (i > 0 && j > 0 && i < n && j < n) d = WE[p] + WE[p - 1] + WN[p] + WN[p - np];
+      KD[p] = d;
+      m.D[g.off[l] + p] = d;
+    }
+    __syncthreads();
+    ko += 2 * (int64_t)n * n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// State solve: Newton (precision TW) with inner MG-PCG (precision TS), then
+// the QoI q = (u - ut)^T M (u - ut) over all nodes.  One block per sample.
+// Z: controls, sample s uses Z + s * z_stride (z_stride = 0: shared control).
+// ---------------------------------------------------------------------------
+template <typename TW, typename TS>
+__global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, const double* Z,
+                                                  int64_t z_stride, const double* em_all, TW* u_all,
+                                                  TW* f_all, MgBufs<TS> all, SolveParams sp, double* q_out,
+                                                  int* newton_out, int* lin_out, int* flag_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  __shared__ double zs[SAA_MAX_DZ];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  const int n = g.n[0], np = n + 1;
+  const double* em = em_all + s * g.nodes;
+  TW* u = u_all + s * g.nodes;
+  TW* f = f_all + s * g.nodes;
+  const MgBufs<TS> m = sample_bufs(all, g, s);
+  if (threadIdx.x < g.dz) zs[threadIdx.x] = Z[s * z_stride + threadIdx.x];
+  __syncthreads();
+  const double c = g.r * g.h2;
+  // Initialising passes write every node (boundary zeros included): the TW
+  // buffers are shared by the FP32 and FP64 state precisions.
+  for_nodes(n, [&](int p, int i, int j) {
+    double acc = 0.0;
+    if (interior(i, j, n))
+      for (int k = 0; k < g.dz; ++k) acc += FT[(int64_t)k * g.nodes + p] * zs[k];
+    f[p] = (TW)acc;
+    u[p] = (TW)0;
+  });
+  __syncthreads();
+  int flags = 0, lin = 0, it = 0;
+  bool conv = false;
+  double prev_step = INFINITY;
+  for (it = 0; it < sp.max_newton; ++it) {
+    // residual R = K u + r h^2 u^3 - f; CG right-hand side -R
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        const TW uu = u[p];
+        const TW R = stiff_apply_em<TW>(em, u, p, np) + (TW)c * uu * uu * uu - f[p];
+        m.cr[p] = (TS)(-R);
+      }
+    });
+    __syncthreads();
+    build_diagonals<TW, TS>(g, m, u);
+    bool ok = true;
+    lin += pcg(g, m, sp.lin_rtol, sp.max_lin, sp.nu, red, &ok);
+    if (!ok) flags |= SAA_FLAG_CG;
+    double v[2] = {0.0, 0.0};
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        const TW d = (TW)m.cx[p];
+        const TW un = u[p] + d;
+        u[p] = un;
+        v[0] += (double)d * (double)d;
+        v[1] += (double)un * (double)un;
+      }
+    });
+    block_sum<2>(v, red);
+    if (!(v[0] == v[0]) || !(v[1] == v[1])) {
+      flags |= SAA_FLAG_NAN;
+      break;
+    }
+    // converged: the update is below tolerance, or the iteration has reached
+    // the rounding floor of the state precision (updates in the asymptotic
+    // regime stopped contracting)
+    if (v[0] <= sp.newton_tol * sp.newton_tol * v[1] ||
+        (v[0] <= 1e-8 * v[1] && v[0] > 0.0625 * prev_step)) {
+      conv = true;
+      ++it;
+      break;
+    }
+    prev_step = v[0];
+  }
+  if (!conv) flags |= SAA_FLAG_NEWTON;
+  // QoI: q = u^T M_II u - 2 ut h^2 sum u + ut^2 (the full mass has row sum h^2
+  // at interior nodes and total mass 1).
+  const double h2 = g.h2;
+  double qa = 0.0;
+  for_nodes(n, [&](int p, int i, int j) {
+    if (interior(i, j, n)) {
+      const double up = (double)u[p];
+      const double mu = (h2 / 12.0) * (6.0 * up + (double)u[p + 1] + (double)u[p - 1] + (double)u[p + np] +
+                                       (double)u[p - np] + (double)u[p + np + 1] + (double)u[p - np - 1]);
+      qa += up * mu - 2.0 * g.ut * h2 * up;
+    }
+  });
+  qa = block_sum1(qa, red);
+  if (threadIdx.x == 0) {
+    q_out[s] = qa + g.ut * g.ut;
+    newton_out[s] = it;
+    lin_out[s] = lin;
+    flag_out[s] = flags;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint: A(u) lambda = 2 (M (u - ut))_I, g = F^T lambda (Sec. 2.3).  One
+// block per sample.  Samples with q_i <= t (zero CVaR weight: s_eps'(q - t) = 0)
+// are skipped unless `all`; their g row is written as 0.
+// ---------------------------------------------------------------------------
+template <typename TW, typename TS>
+__global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, const double* em_all,
+                                                    const TW* u_all, TW* b_all, TW* lam_all, MgBufs<TS> all,
+                                                    SolveParams sp, const double* q, const double* tstar,
+                                                    int all_samples, double* g_out, int* lin_out, int* flag_out,
+                                                    int* did_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  const int n = g.n[0], np = n + 1;
+  const bool active = all_samples || (q[s] - tstar[0] > 0.0);
+  if (!active) {
+    if (threadIdx.x < g.dz) g_out[s * g.dz + threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) {
+      lin_out[s] = 0;
+      did_out[s] = 0;
+    }
+    return;
+  }
+  const double* em = em_all + s * g.nodes;
+  const TW* u = u_all + s * g.nodes;
+  TW* b = b_all + s * g.nodes;
+  TW* lam = lam_all + s * g.nodes;
+  const MgBufs<TS> m = sample_bufs(all, g, s);
+  const double h2 = g.h2;
+  for_nodes(n, [&](int p, int i, int j) {
+    double v = 0.0;
+    if (interior(i, j, n)) {
+      const double up = (double)u[p];
+      const double mu = (h2 / 12.0) * (6.0 * up + (double)u[p + 1] + (double)u[p - 1] + (double)u[p + np] +
+                                       (double)u[p - np] + (double)u[p + np + 1] + (double)u[p - np - 1]);
+      v = 2.0 * mu - 2.0 * g.ut * h2;
+    }
+    b[p] = (TW)v;
+  });
+  __syncthreads();
+  build_diagonals<TW, TS>(g, m, u);
+  bool ok = true;
+  int passes = 0;
+  const int lin = dc_solve<TW, TS>(g, m, sp, em, u, b, lam, red, &ok, &passes);
+  // g = F^T lambda, eight controls per pass over the grid (register-resident sums)
+  for (int k0 = 0; k0 < g.dz; k0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = 0.0;
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) {
+        const double l = (double)lam[p];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (k0 + t < g.dz) v[t] += FT[(int64_t)(k0 + t) * g.nodes + p] * l;
+      }
+    });
+    block_sum<8>(v, red);
+    if (threadIdx.x == 0) {
+      for (int t = 0; t < 8 && k0 + t < g.dz; ++t) g_out[s * g.dz + k0 + t] = v[t];
+    }
+  }
+  if (threadIdx.x == 0) {
+    lin_out[s] = lin;
+    did_out[s] = 1;
+    if (!ok) flag_out[s] |= SAA_FLAG_DC;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Control Jacobian du/dz = A(u)^{-1} F by d_Z linearised solves sharing the
+// state's multigrid hierarchy (Sec. 3.4, eq. (projected_sensitivity)).
+// Output dudz[s][k][interior index] in float64.  One block per sample.
+// ---------------------------------------------------------------------------
+template <typename TW, typename TS>
+__global__ void __launch_bounds__(BS) saa_k_linearized(PdeGeo g, const double* FT, const double* em_all,
+                                                       const TW* u_all, TW* b_all, TW* x_all, MgBufs<TS> all,
+                                                       SolveParams sp, double* dudz, int* lin_out, int* flag_out,
+                                                       int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  const int n = g.n[0];
+  const int64_t du = (int64_t)(n - 1) * (n - 1);
+  const double* em = em_all + s * g.nodes;
+  const TW* u = u_all + s * g.nodes;
+  TW* b = b_all + s * g.nodes;
+  TW* x = x_all + s * g.nodes;
+  const MgBufs<TS> m = sample_bufs(all, g, s);
+  build_diagonals<TW, TS>(g, m, u);
+  int lin = 0;
+  bool ok_all = true;
+  for (int k = 0; k < g.dz; ++k) {
+    for_nodes(n, [&](int p, int i, int j) { b[p] = (TW)FT[(int64_t)k * g.nodes + p]; });
+    __syncthreads();
+    bool ok = true;
+    int passes = 0;
+    lin += dc_solve<TW, TS>(g, m, sp, em, u, b, x, red, &ok, &passes);
+    ok_all = ok_all && ok;
+    double* out = dudz + (s * g.dz + k) * du;
+    for_nodes(n, [&](int p, int i, int j) {
+      if (interior(i, j, n)) out[(int64_t)(j - 1) * (n - 1) + (i - 1)] = (double)x[p];
+    });
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    lin_out[s] = lin;
+    if (!ok_all) flag_out[s] |= SAA_FLAG_DC;
+  }
+}
+
+// Copy interior node values to the dense interior-order layout (float64).
+template <typename TW>
+__global__ void saa_k_interior(const TW* u_all, double* out, int n, int64_t N) {
+  const int64_t du = (int64_t)(n - 1) * (n - 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * du) return;
+  const int64_t s = t / du;
+  const int64_t r = t - s * du;
+  const int j = (int)(r / (n - 1)) + 1, i = (int)(r % (n - 1)) + 1;
+  out[t] = (double)u_all[s * (int64_t)(n + 1) * (n + 1) + (int64_t)j * (n + 1) + i];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+namespace saa_launch {
+
+void sine_table(double* S, int K1, int n, hipStream_t st) {
+  const int total = K1 * (n + 1);
+  saa_k_sine_table<<<(total + 255) / 256, 256, 0, st>>>(S, K1, n);
+}
+
+void source_matrix(double* FT, int n, int s, double sigma, hipStream_t st) {
+  const int64_t total = (int64_t)(n + 1) * (n + 1) * s * s;
+  saa_k_source_matrix<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(FT, n, s, sigma);
+}
+
+void field(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
+           hipStream_t st) {
+  const size_t lds = sizeof(double) * ((size_t)K1 * (n + 1) + (size_t)K1 * K1);
+  saa_k_field<<<(unsigned)N, 256, lds, st>>>(xi, S, amp, em, K1, n, N);
+}
+
+template <typename TS>
+void hierarchy(const PdeGeo& g, const double* em, double* kap, int64_t kstride, int64_t chunk,
+               const MgBufs<TS>& b, int64_t N, hipStream_t st) {
+  for (int64_t s0 = 0; s0 < N; s0 += chunk) {
+    const int64_t nb = (N - s0 < chunk) ? (N - s0) : chunk;
+    saa_k_hierarchy<TS><<<(unsigned)nb, BS, 0, st>>>(g, em, kap, kstride, b, s0, N);
+  }
+}
+template void hierarchy<float>(const PdeGeo&, const double*, double*, int64_t, int64_t, const MgBufs<float>&,
+                               int64_t, hipStream_t);
+template void hierarchy<double>(const PdeGeo&, const double*, double*, int64_t, int64_t,
+                                const MgBufs<double>&, int64_t, hipStream_t);
+
+template <typename TW, typename TS>
+void state(const PdeGeo& g, const double* FT, const double* Z, int64_t z_stride, const double* em, TW* u, TW* f,
+           const MgBufs<TS>& b, const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N,
+           hipStream_t st) {
+  saa_k_state<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, FT, Z, z_stride, em, u, f, b, sp, q, newton, lin, flag, N);
+}
+
+template <typename TW, typename TS>
+void adjoint(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* lam,
+             const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int all_samples,
+             double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st) {
+  saa_k_adjoint<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, all_samples, gout,
+                                                    lin, flag, did, N);
+}
+
+template <typename TW, typename TS>
+void linearized(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* x,
+                const MgBufs<TS>& b, const SolveParams& sp, double* dudz, int* lin, int* flag, int64_t N,
+                hipStream_t st) {
+  saa_k_linearized<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, x, b, sp, dudz, lin, flag, N);
+}
+
+template <typename TW>
+void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st) {
+  const int64_t total = N * (int64_t)(n - 1) * (n - 1);
+  saa_k_interior<TW><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(u, out, n, N);
+}
+
+#define SAA_INST(TW, TS)                                                                                         \
+  template void state<TW, TS>(const PdeGeo&, const double*, const double*, int64_t, const double*, TW*, TW*,     \
+                              const MgBufs<TS>&, const SolveParams&, double*, int*, int*, int*, int64_t,         \
+                              hipStream_t);                                                                      \
+  template void adjoint<TW, TS>(const PdeGeo&, const double*, const double*, const TW*, TW*, TW*,                \
+                                const MgBufs<TS>&, const SolveParams&, const double*, const double*, int,        \
+                                double*, int*, int*, int*, int64_t, hipStream_t);                                \
+  template void linearized<TW, TS>(const PdeGeo&, const double*, const double*, const TW*, TW*, TW*,             \
+                                   const MgBufs<TS>&, const SolveParams&, double*, int*, int*, int64_t,          \
+                                   hipStream_t);
+SAA_INST(double, double)
+SAA_INST(double, float)
+SAA_INST(float, float)
+#undef SAA_INST
+template void interior_copy<double>(const double*, double*, int, int64_t, hipStream_t);
+template void interior_copy<float>(const float*, double*, int, int64_t, hipStream_t);
+
+}  // namespace saa_launch

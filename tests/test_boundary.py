@@ -1,0 +1,84 @@
+"""Host-side checks of the C-ABI boundary (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2305_20053_amd as saa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, re.M):
+            name = m.group(1)
+            if name.startswith(("saa_", "mrdino_")):
+                names.add(name)
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = saa.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 9
+    out = subprocess.run(["nm", "-D", "--defined-only", saa.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = declared - exported
+    assert not missing, missing
+    for name in declared:
+        getattr(lib, name)
+    assert set(saa.exported_symbols()) <= exported
+
+
+def test_status_strings_and_version():
+    lib = saa.lib()
+    assert lib.saa_abi_version() == 1
+    for st in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert saa.status_str(st) and saa.status_str(st) != "unknown status"
+    assert saa.status_str(12345) == "unknown status"
+
+
+def test_options_default():
+    o = saa.options()
+    assert o.beta == 0.95 and o.eps == 1e-4 and o.alpha == 1e-3 and o.prec == saa.FP32_DC64
+    assert saa.lib().saa_options_default(None) == saa.SAA_E_INVALID
+
+
+@pytest.mark.parametrize("field,value", [("n", 3), ("n", 48), ("n", 0), ("dim", 3), ("n_src_per_dim", 0),
+                                         ("src_sigma", 0.0), ("src_sigma", float("nan")), ("kl_per_dim", 0),
+                                         ("kl_exp", -1.0), ("reaction", -1.0), ("u_target", float("inf")),
+                                         ("kl_per_dim", 64)])
+def test_ctx_create_rejects_bad_problem_before_device_work(field, value):
+    p = saa.problem_small()
+    if field == "kl_per_dim" and value == 64:
+        p.n = 256      # LDS table K1 (n+1) + K1^2 too large
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    st = saa.lib().saa_ctx_create(ctypes.byref(p.c_struct()), 16, None, ctypes.byref(h))
+    assert st == saa.SAA_E_INVALID and not h.value
+
+
+def test_null_arguments_rejected():
+    lib = saa.lib()
+    p = saa.problem_small().c_struct()
+    assert lib.saa_ctx_create(None, 4, None, ctypes.byref(ctypes.c_void_p())) == saa.SAA_E_INVALID
+    assert lib.saa_ctx_create(ctypes.byref(p), 4, None, None) == saa.SAA_E_INVALID
+    assert lib.saa_ctx_create(ctypes.byref(p), 0, None, ctypes.byref(ctypes.c_void_p())) == saa.SAA_E_INVALID
+    assert lib.saa_set_samples(None, 4, None) == saa.SAA_E_INVALID
+    o = saa.options()
+    J = ctypes.c_double()
+    assert lib.saa_objective_grad(None, None, 0, None, ctypes.byref(o), ctypes.byref(J), None,
+                                  None) == saa.SAA_E_INVALID
+    assert lib.saa_per_sample(None, None, 0, None, ctypes.byref(o), None, None, None) == saa.SAA_E_INVALID
+    assert lib.saa_solve_states(None, None, ctypes.byref(o), None, None, None, None) == saa.SAA_E_INVALID
+    assert lib.saa_sample_status(None, None, None, None, None) == saa.SAA_E_INVALID
+    lib.saa_ctx_destroy(None)

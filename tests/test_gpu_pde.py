@@ -1,0 +1,179 @@
+"""GPU parity of the PDE form against the CPU FP64 oracle (through the C ABI).
+
+Tolerances (relative, 2-norm): FP64 and FP32-in-FP64-defect-correction paths
+1e-9 on J and grad J; pure FP32 1e-4.  t* to 1e-14 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2305_20053_amd as saa
+import saa_inputs as si
+from oracle import cvar, fem2d, saa as osaa
+
+pytestmark = pytest.mark.gpu
+
+TOL = {saa.FP64: 1e-9, saa.FP32_DC64: 1e-9, saa.FP32: 1e-4}
+
+
+def _oprob(p: saa.Problem) -> fem2d.Problem2D:
+    return fem2d.Problem2D(n=p.n, n_src_per_dim=p.n_src_per_dim, src_sigma=p.src_sigma,
+                           kl_per_dim=p.kl_per_dim, kl_shift=p.kl_shift, kl_exp=p.kl_exp,
+                           kl_amp=p.kl_amp, reaction=p.reaction, u_target=p.u_target)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def small(gpu_lib):
+    prob = saa.problem_small()
+    xi = si.kl_coefficients(si.SEED_XI_SMALL, 64, prob.kl_per_dim)
+    z = si.control(si.SEED_Z_SMALL)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 64)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    return prob, xi, z, ref, ctx
+
+
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64, saa.FP32])
+def test_small_per_sample(small, prec):
+    prob, xi, z, ref, ctx = small
+    print(f"case small per_sample prec={prec}", flush=True)
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=prec))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    tol = TOL[prec]
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= (1e-12 if prec != saa.FP32 else 1e-5)
+    for i in range(len(q)):
+        assert _rel(g[i], ref["g"][i]) <= tol, (i, _rel(g[i], ref["g"][i]))
+    assert rep["n_unconverged"] == 0 and rep["n_adjoints"] == 64
+
+
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64, saa.FP32])
+def test_small_objective(small, prec):
+    prob, xi, z, ref, ctx = small
+    print(f"case small objective prec={prec}", flush=True)
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=prec))
+    tol = TOL[prec]
+    assert abs(J - ref["J"]) / abs(ref["J"]) <= tol
+    assert _rel(grad, ref["grad"]) <= tol
+    if prec != saa.FP32:
+        assert abs(rep["t_star"] - ref["t"]) <= 1e-14 * abs(ref["t"]) + 1e-12 * 0
+    assert rep["n_unconverged"] == 0
+    assert 2 <= rep["newton_max"] <= 8
+
+
+def test_adjoint_skipping_is_exact(small):
+    prob, xi, z, ref, ctx = small
+    a = ctx.objective_grad(z, opt=saa.options(all_adjoints=0))
+    b = ctx.objective_grad(z, opt=saa.options(all_adjoints=1))
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+    assert a[2]["n_adjoints"] < b[2]["n_adjoints"] == 64
+    # exactly the samples with q_i > t* carry weight
+    assert a[2]["n_adjoints"] == int(np.sum(ref["q"] > ref["t"]))
+
+
+def test_bitwise_determinism(small):
+    prob, xi, z, ref, ctx = small
+    a = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32_DC64))
+    b = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32_DC64))
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and a[2]["t_star"] == b[2]["t_star"]
+
+
+def test_joint_t_mode_and_beta_zero(small):
+    prob, xi, z, ref, ctx = small
+    t_in = ref["t"] + 2e-5
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(t_mode=1, t_in=t_in))
+    r = cvar.objective(ref["q"], ref["g"], z, 0.95, 1e-4, 1e-3, t_mode=1, t_in=t_in)
+    assert abs(J - r["J"]) <= 1e-9 * abs(r["J"])
+    assert _rel(grad, r["grad"]) <= 1e-9
+    assert abs(rep["dJ_dt"] - r["dJdt"]) <= 1e-9
+    J0, g0, _ = ctx.objective_grad(z, opt=saa.options(beta=0.0))
+    r0 = cvar.objective(ref["q"], ref["g"], z, 0.0, 1e-4, 1e-3)
+    assert abs(J0 - (ref["q"].mean() - 0.5e-4 + 0.5e-3 * z @ z)) <= 1e-9 * abs(J0)
+    assert _rel(g0, r0["grad"]) <= 1e-9
+
+
+def test_heavy_tail_ragged_batch(gpu_lib):
+    """Larger field variance (amplitude 20), beta = 0.9, N = 37 (ragged)."""
+    prob = saa.Problem(n=32, kl_per_dim=8, kl_amp=20.0)
+    xi = si.kl_coefficients(77, 37, 8)
+    z = si.control(78)
+    ref = osaa.objective_grad(_oprob(prob), xi, z, beta=0.9)
+    ctx = saa.Context(prob, 40)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(beta=0.9))
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"])
+    assert _rel(grad, ref["grad"]) <= 1e-9
+    assert abs(rep["t_star"] - ref["t"]) <= 1e-14 * abs(ref["t"])
+
+
+def test_single_sample(gpu_lib):
+    prob = saa.Problem(n=16, kl_per_dim=4)
+    xi = si.kl_coefficients(5, 1, 4)
+    z = si.control(6)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 1)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    J, grad, rep = ctx.objective_grad(z)
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"])
+    assert _rel(grad, ref["grad"]) <= 1e-9
+
+
+def test_states_and_control_jacobian(gpu_lib):
+    prob = saa.Problem(n=32, kl_per_dim=8, kl_amp=10.0)
+    xi = si.kl_coefficients(90, 6, 8)
+    Z = si.controls(91, 6)
+    ctx = saa.Context(prob, 6)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    u, q, dudz, rep = ctx.solve_states(torch.from_numpy(Z).cuda(), want_dudz=True)
+    u, q, dudz = u.cpu().numpy(), q.cpu().numpy(), dudz.cpu().numpy()
+    ops = fem2d.operators(_oprob(prob))
+    for i in range(6):
+        s = fem2d.solve_sample(ops, xi[i], Z[i])
+        assert _rel(u[i], s["u"]) <= 1e-11
+        assert abs(q[i] - s["q"]) <= 1e-12 * abs(s["q"])
+        Jac = fem2d.control_jacobian(ops, s)          # d_U x d_Z
+        assert _rel(dudz[i].T, Jac) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def medium(gpu_lib):
+    prob = saa.problem_medium()
+    N = 1024
+    xi = si.kl_coefficients(si.SEED_XI_MEDIUM, N, prob.kl_per_dim)
+    z = si.control(si.SEED_Z_EVAL[0])
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    return prob, xi, z, ctx
+
+
+@pytest.mark.parametrize("prec", [saa.FP32_DC64, saa.FP64])
+def test_medium_sampled_parity(medium, prec):
+    """n = 128, N = 1024 as timed: sampled per-sample outputs vs the oracle,
+    and the reduction checked on the GPU's own q, g."""
+    prob, xi, z, ctx = medium
+    print(f"case medium prec={prec}", flush=True)
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=prec))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert rep["n_unconverged"] == 0
+    ops = fem2d.operators(_oprob(prob))
+    for i in (0, 511, 1023):
+        s = fem2d.solve_sample(ops, xi[i], z)
+        assert abs(q[i] - s["q"]) <= 1e-12 * abs(s["q"])
+        assert _rel(g[i], s["g"]) <= 1e-9
+    J, grad, rep2 = ctx.objective_grad(z, opt=saa.options(prec=prec))
+    r = cvar.objective(q, g, z, 0.95, 1e-4, 1e-3)
+    assert abs(J - r["J"]) <= 1e-12 * abs(r["J"])
+    assert _rel(grad, r["grad"]) <= 1e-10
+    assert abs(rep2["t_star"] - r["t"]) <= 1e-14 * abs(r["t"])
+
+
+def test_medium_fp32_vs_fp64(medium):
+    prob, xi, z, ctx = medium
+    J64, g64, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64))
+    J32, g32, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32))
+    Jdc, gdc, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32_DC64))
+    assert abs(J32 - J64) <= 1e-4 * abs(J64) and _rel(g32, g64) <= 1e-4
+    assert abs(Jdc - J64) <= 1e-10 * abs(J64) and _rel(gdc, g64) <= 1e-9
