@@ -1,0 +1,184 @@
+"""Benchmark: SAA smoothed-CVaR objective + gradient throughput on one GPU.
+
+One step = one saa_objective_grad call over the whole sample set (state
+solves, t*, adjoint solves of the weighted samples, reductions) at a control z
+drawn from the evaluation seeds.  Default workload: the PDE form on the
+128 x 128 P1 grid (16641 nodes), N = 1024 samples, 16 x 16 KL modes, FP32
+multigrid-preconditioned CG inside FP64 Newton / defect correction.
+
+Prints one JSON line (see the keys below).  Samples are installed before the
+timed region (fixed samples, paper Sec. 2.2); inputs are resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SAA CVaR obj+grad samples/s, MR-DINO vs PDE form, 1 GPU, at stated error"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unknown of the state-solve kernel (FP32 solver
+# arrays, FP64 state): each pass reads / writes each array it needs once.
+#   PCG iteration: A p (5 x 4 B) + x, r update (6 x 4 B) + V-cycle (fine
+#   level 21 x 4 B, coarse levels a third of that) + r.z (2 x 4 B) +
+#   p update (3 x 4 B)                                          = 176 B
+#   PCG start (r.r, x = 0, first V-cycle, r.z and p = z)        = 132 B
+#   Newton step: residual 28 B + diagonals 25 B + update 20 B   =  73 B
+#   per sample: f = F z and u = 0 (16 B) + QoI (8 B)            =  24 B
+BYTES_PCG_ITER_F32 = 176
+BYTES_PCG_START_F32 = 132
+BYTES_NEWTON_F64 = 73
+BYTES_SAMPLE = 24
+
+
+def _source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_key, src_hash):
+    """HBM bytes per launch from the committed counter summary, or None if
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(kernel_key)
+    if not ent or ent.get("source_hash") != src_hash:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, xi, z, seconds_target=15.0):
+    """Time the CPU oracle (state + adjoint per sample, one process per usable
+    core, at most 16) on a bounded slice of the same workload.  A pilot with
+    one sample per worker sizes the slice to about `seconds_target`."""
+    from oracle import fem2d, saa as osaa
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(16, usable))
+    oprob = fem2d.Problem2D(n=prob.n, kl_per_dim=prob.kl_per_dim)
+    t = time.perf_counter()
+    osaa.per_sample_parallel(oprob, xi[:workers], z, workers=workers)
+    pilot = time.perf_counter() - t
+    n_s = int(min(len(xi), max(workers, workers * round(seconds_target / max(pilot, 1e-3)))))
+    t = time.perf_counter()
+    osaa.per_sample_parallel(oprob, xi[:n_s], z, workers=workers)
+    wall = time.perf_counter() - t
+    return {"value": n_s / wall, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {n_s} of the {len(xi)} samples at n={prob.n}: Newton with sparse LU, "
+                      f"QoI and adjoint per sample (float64 scipy), {workers} worker processes, {wall:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="fp32_dc64", choices=["fp64", "fp32", "fp32_dc64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2305_20053_amd as saa
+    import saa_inputs as si
+
+    saa.require_gpu()
+    prec = {"fp64": saa.FP64, "fp32": saa.FP32, "fp32_dc64": saa.FP32_DC64}[args.prec]
+    prob = saa.problem_medium()
+    N = 1024
+    xi = si.kl_coefficients(si.SEED_XI_MEDIUM, N, prob.kl_per_dim)
+    zs = [si.control(s) for s in si.SEED_Z_EVAL]
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    opt = saa.options(prec=prec, timing=1)
+
+    for k in range(args.warmup):
+        ctx.objective_grad(zs[k % len(zs)], opt=opt)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        J, g, rep = ctx.objective_grad(zs[k % len(zs)], opt=opt)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    value = N * args.steps / wall
+
+    # roofline of the dominant kernel (state solve), timed by HIP events on its stream
+    d_u = prob.d_u
+    s_bytes = 4 if prec in (saa.FP32, saa.FP32_DC64) else 8
+    per_iter = BYTES_PCG_ITER_F32 * s_bytes // 4
+    per_start = BYTES_PCG_START_F32 * s_bytes // 4
+    ms_state = float(np.mean([r["ms_state"] for r in reps]))
+    ms_adj = float(np.mean([r["ms_adjoint"] for r in reps]))
+    ms_red = float(np.mean([r["ms_reduce"] for r in reps]))
+    st = ctx.sample_status()
+    lin_state = int(st[2].sum())
+    newton_total = int(st[1].sum())
+    bytes_launch = d_u * (per_iter * lin_state + (BYTES_NEWTON_F64 + per_start) * newton_total
+                          + BYTES_SAMPLE * N)
+    achieved = bytes_launch / (ms_state * 1e-3) / 1e9
+    src_hash = _source_hash(["paper_2305_20053_amd/csrc/pde.hip", "paper_2305_20053_amd/csrc/pde.h"])
+    traffic = _traffic(f"saa_k_state/{args.prec}/n128_N1024", src_hash)
+
+    # error of this precision against the FP64 GPU path at the first z
+    J64, g64, _ = ctx.objective_grad(zs[0], opt=saa.options(prec=saa.FP64))
+    Jp, gp, _ = ctx.objective_grad(zs[0], opt=saa.options(prec=prec))
+    err = {"J_rel_vs_gpu_fp64": abs(Jp - J64) / abs(J64),
+           "grad_rel_vs_gpu_fp64": float(np.linalg.norm(gp - g64) / np.linalg.norm(g64)),
+           "oracle_parity": "tests/test_gpu_pde.py (<= 1e-9 FP64 / FP32-DC64, <= 1e-4 FP32)"}
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "fp32_dc64": "f32+f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "PDE form: 128x128 P1 semilinear elliptic (16641 nodes, 16129 unknowns), "
+                               "N=1024 KL samples (16x16 modes), 25 sources, smoothed CVaR_0.95, "
+                               f"precision {args.prec}",
+                   "n": prob.n, "N": N, "form": "pde", "prec": args.prec},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "saa_k_state", "alg_bytes_per_launch": bytes_launch,
+                     "kernel_ms": ms_state},
+        "phases_ms": {"state": ms_state, "adjoint": ms_adj, "reduce": ms_red},
+        "solver": {"newton_total": newton_total, "pcg_state_iters": lin_state,
+                   "pcg_adjoint_iters": int(st[3].sum()), "adjoints": reps[-1]["n_adjoints"],
+                   "newton_max": reps[-1]["newton_max"]},
+        "error": err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, xi, zs[0])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -99,11 +99,14 @@ typedef struct saa_options {
                           1: J_hat(z, t_in) and dJ_hat/dt are returned */
   double t_in;
   int prec;            /* SAA_FP64 | SAA_FP32 | SAA_FP32_DC64 (PDE form) */
-  double newton_tol;   /* stop Newton / defect correction when the update is
-                          <= newton_tol * |iterate| (2-norms); <= 0: default
-                          (1e-13 with FP64 state, 1e-5 with FP32 state); an
-                          iteration also stops once its updates stop
-                          contracting below 1e-4 relative (rounding floor) */
+  double newton_tol;   /* stop Newton / defect correction when the update, or
+                          the error predicted after it from the contraction of
+                          the last two updates, is <= newton_tol * |iterate|
+                          (2-norms); <= 0: default (1e-13 with FP64 state,
+                          1e-5 with FP32 state).  An iteration also stops once
+                          its updates stop contracting below 1e-4 relative
+                          (rounding floor).  Inner PCG tolerances adapt to the
+                          predicted error, never tighter than lin_rtol. */
   double lin_rtol;     /* relative residual of each inner PCG solve; <= 0:
                           default 1e-6 (1e-5 with FP32 state) */
   int max_newton;      /* <= 0: default 30 */
@@ -114,6 +117,8 @@ typedef struct saa_options {
                           grad J); 1: solve all */
   double fallback_tol; /* MR-DINO form: relative error above which the PDE form
                           is used instead; < 0 disables */
+  int timing;          /* 1: time each phase with HIP events on the context's
+                          stream and fill the ms_* fields of the report */
 } saa_options;
 
 typedef struct saa_report {
@@ -126,6 +131,11 @@ typedef struct saa_report {
   int n_adjoints;      /* adjoint solves performed */
   int fallback_used;   /* 1 if the PDE form replaced the surrogate */
   int64_t lin_total;   /* total inner PCG iterations over all samples */
+  int64_t newton_total;/* total Newton iterations over all samples */
+  double ms_state;     /* with opt->timing: device time of the state solve (or
+                          surrogate evaluation) kernel, milliseconds */
+  double ms_adjoint;   /* ... of the adjoint solves */
+  double ms_reduce;    /* ... of the CVaR reductions */
 } saa_report;
 
 typedef struct saa_ctx saa_ctx;

@@ -38,13 +38,15 @@ class COptions(ctypes.Structure):
                 ("t_mode", ctypes.c_int), ("t_in", ctypes.c_double), ("prec", ctypes.c_int),
                 ("newton_tol", ctypes.c_double), ("lin_rtol", ctypes.c_double),
                 ("max_newton", ctypes.c_int), ("max_lin", ctypes.c_int), ("max_dc", ctypes.c_int),
-                ("all_adjoints", ctypes.c_int), ("fallback_tol", ctypes.c_double)]
+                ("all_adjoints", ctypes.c_int), ("fallback_tol", ctypes.c_double), ("timing", ctypes.c_int)]
 
 
 class CReport(ctypes.Structure):
     _fields_ = [("t_star", ctypes.c_double), ("dJ_dt", ctypes.c_double), ("err_estimate", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("newton_max", ctypes.c_int), ("n_unconverged", ctypes.c_int),
-                ("n_adjoints", ctypes.c_int), ("fallback_used", ctypes.c_int), ("lin_total", ctypes.c_int64)]
+                ("n_adjoints", ctypes.c_int), ("fallback_used", ctypes.c_int), ("lin_total", ctypes.c_int64),
+                ("newton_total", ctypes.c_int64), ("ms_state", ctypes.c_double), ("ms_adjoint", ctypes.c_double),
+                ("ms_reduce", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

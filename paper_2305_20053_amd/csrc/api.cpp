@@ -47,14 +47,6 @@ using saa_rt::DevBuf;
 
 namespace {
 
-struct CvarStatsHost {
-  int newton_max;
-  int n_unconverged;
-  int n_adjoints;
-  int pad;
-  long long lin_total;
-};
-
 template <typename TS>
 struct MgStore {
   DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;
@@ -79,6 +71,37 @@ struct MgStore {
 
 bool is_fin(double x) { return std::isfinite(x); }
 
+// Phase timing with HIP events on the context's stream: marks 0..4 bracket
+// [state | reduce 1 | adjoint | reduce 2].
+struct PhaseTimer {
+  bool on = false;
+  hipEvent_t ev[5] = {};
+  void mark(hipStream_t st, int k) {
+    if (on) (void)hipEventRecord(ev[k], st);
+  }
+  int create() {
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return SAA_E_DEVICE;
+    return SAA_OK;
+  }
+  ~PhaseTimer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void ms(double* state, double* adjoint, double* reduce) const {
+    float a = 0, b = 0, d = 0, e = 0;
+    if (!on) return;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&d, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&e, ev[3], ev[4]);
+    *state = a;
+    *reduce = (double)b + e;
+    *adjoint = d;
+  }
+};
+
+
 }  // namespace
 
 struct saa_ctx {
@@ -95,6 +118,7 @@ struct saa_ctx {
   MgStore<float> mg32;
   DevBuf u, f, lam;          // TW node vectors (sized for float64)
   DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
+  PhaseTimer timer;
 };
 
 namespace {
@@ -212,8 +236,8 @@ int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int all, double* go
   return check_hip(hipGetLastError());
 }
 
-int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJdt) {
-  CvarStatsHost s{};
+int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJdt, const PhaseTimer* tm) {
+  CvarStats s{};
   int rc = check_hip(hipMemcpyAsync(&s, c->stats.p, sizeof(s), hipMemcpyDeviceToHost, c->st));
   if (rc) return rc;
   rc = check_hip(hipStreamSynchronize(c->st));
@@ -227,7 +251,10 @@ int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJ
     rep->n_unconverged = s.n_unconverged;
     rep->n_adjoints = s.n_adjoints;
     rep->fallback_used = 0;
-    rep->lin_total = s.lin_total;
+    rep->lin_total = s.lin_state + s.lin_adjoint;
+    rep->newton_total = s.newton_total;
+    rep->ms_state = rep->ms_adjoint = rep->ms_reduce = 0.0;
+    if (tm) tm->ms(&rep->ms_state, &rep->ms_adjoint, &rep->ms_reduce);
   }
   return s.n_unconverged > 0 ? SAA_E_NOCONV : SAA_OK;
 }
@@ -338,7 +365,8 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!rc) rc = c->tstar.alloc(sizeof(double));
   if (!rc) rc = c->zdev.alloc(SAA_MAX_DZ * sizeof(double));
   if (!rc) rc = c->out.alloc((2 + SAA_MAX_DZ) * sizeof(double));
-  if (!rc) rc = c->stats.alloc(sizeof(CvarStatsHost));
+  if (!rc) rc = c->stats.alloc(sizeof(CvarStats));
+  if (!rc) rc = c->timer.create();
   if (rc) {
     delete c;
     return rc;
@@ -414,15 +442,22 @@ int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model,
   const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
   if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
     return rc;
+  PhaseTimer& tm = c->timer;
+  tm.on = opt->timing != 0;
+  tm.mark(c->st, 0);
   if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
+  tm.mark(c->st, 1);
   saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
                    (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, (double*)c->tstar.p, (double*)c->out.p, nullptr,
                    nullptr, nullptr, nullptr, nullptr, nullptr, c->st);
+  tm.mark(c->st, 2);
   if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
+  tm.mark(c->st, 3);
   saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
                    (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, (double*)c->tstar.p, (double*)c->out.p,
                    (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
                    c->stats.p, c->st);
+  tm.mark(c->st, 4);
   if ((rc = check_hip(hipGetLastError()))) return rc;
   double host[2 + SAA_MAX_DZ];
   double t = 0;
@@ -433,7 +468,7 @@ int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model,
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *J = host[0];
   for (int k = 0; k < c->dz; ++k) grad_z[k] = host[2 + k];
-  return fill_report(c, rep, secs, t, host[1]);
+  return fill_report(c, rep, secs, t, host[1], &tm);
 }
 
 int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
@@ -463,7 +498,7 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
   if ((rc = check_hip(hipMemcpyAsync(&t, c->tstar.p, sizeof(double), hipMemcpyDeviceToHost, c->st)))) return rc;
   if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return fill_report(c, rep, secs, t, host[1]);
+  return fill_report(c, rep, secs, t, host[1], nullptr);
 }
 
 int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
@@ -508,7 +543,7 @@ int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, do
   if ((rc = check_hip(hipGetLastError()))) return rc;
   if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return fill_report(c, rep, secs, 0.0, 0.0);
+  return fill_report(c, rep, secs, 0.0, 0.0, nullptr);
 }
 
 int saa_sample_status(saa_ctx* c, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters) {

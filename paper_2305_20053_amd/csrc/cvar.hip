@@ -14,6 +14,7 @@
 // One workgroup does the whole reduction with a fixed summation order, so the
 // result is bitwise reproducible.
 #include "common.h"
+#include "pde.h"
 
 namespace {
 
@@ -39,14 +40,6 @@ __device__ __forceinline__ double sp_d2(double x, double e) {
 
 }  // namespace
 
-// Stats of the per-sample solver flags, reduced alongside the objective.
-struct CvarStats {
-  int newton_max;
-  int n_unconverged;
-  int n_adjoints;
-  int pad;
-  long long lin_total;
-};
 
 // phase & 1: determine t (minimiser, or t_in when t_mode = 1) -> tstar[0].
 // phase & 2: J, dJ/dt, grad -> out[0] = J, out[1] = dJ/dt, out[2..2+dz) = grad.
@@ -61,22 +54,27 @@ __global__ void __launch_bounds__(CBS) saa_k_cvar(const double* q, const double*
   __shared__ double tsh;
   const double target = (double)N * (1.0 - beta);
   if (stats) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double nm = 0.0;
     for (int64_t i = threadIdx.x; i < N; i += CBS) {
-      if (newton) nm = fmax(nm, (double)newton[i]);
+      if (newton) {
+        nm = fmax(nm, (double)newton[i]);
+        s[4] += (double)newton[i];
+      }
       if (flag) s[0] += (flag[i] != 0) ? 1.0 : 0.0;
       if (did) s[1] += (double)did[i];
       if (lin) s[2] += (double)lin[i];
       if (lin_adj) s[3] += (double)lin_adj[i];
     }
-    block_sum<4>(s, red);
+    block_sum<5>(s, red);
     nm = block_max1(nm, red);
     if (threadIdx.x == 0) {
       stats->newton_max = (int)nm;
       stats->n_unconverged = (int)s[0];
       stats->n_adjoints = (int)s[1];
-      stats->lin_total = (long long)(s[2] + s[3]);
+      stats->lin_state = (long long)s[2];
+      stats->lin_adjoint = (long long)s[3];
+      stats->newton_total = (long long)s[4];
     }
   }
   if (phase & 1) {

@@ -48,5 +48,16 @@ struct SolveParams {
   int nu;             // red-black smoothing sweeps before and after each coarse correction
 };
 
+// Solver statistics reduced over the samples by the CVaR kernel.
+struct CvarStats {
+  int newton_max;
+  int n_unconverged;
+  int n_adjoints;
+  int pad;
+  long long lin_state;
+  long long lin_adjoint;
+  long long newton_total;
+};
+
 // Per-sample status flags.
 enum { SAA_FLAG_NEWTON = 1, SAA_FLAG_CG = 2, SAA_FLAG_DC = 4, SAA_FLAG_NAN = 8 };

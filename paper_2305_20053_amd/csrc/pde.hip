@@ -64,6 +64,36 @@ __device__ __forceinline__ bool interior(int i, int j, int n) {
   return i > 0 && j > 0 && i < n && j < n;
 }
 
+// Control of the outer iterations (Newton and defect correction).  After an
+// update delta_k of the iterate x (squared norms d2 = |delta_k|^2,
+// x2 = |x|^2) the iteration has converged when
+//  * |delta_k| <= tol |x|, or
+//  * the error left after this update, predicted from the contraction seen
+//    between the last two updates, |delta_k|^2 / |delta_{k-1}| <= tol |x|, or
+//  * the updates stopped contracting below 1e-4 |x| (rounding floor of the
+//    state precision).
+// Otherwise the next inner solve only needs to shrink the predicted error to
+// tol |x|, so its relative tolerance is 0.1 tol |x| / predicted, kept within
+// [lin_rtol, 0.1].
+struct OuterCtl {
+  double prev2 = INFINITY;
+  double eta;
+};
+
+__device__ __forceinline__ bool outer_converged(OuterCtl& c, double d2, double x2, double tol, double lin_rtol) {
+  bool done = d2 <= tol * tol * x2 || (d2 <= 1e-8 * x2 && d2 > 0.0625 * c.prev2);
+  double eta = lin_rtol;
+  if (!done && c.prev2 < INFINITY && d2 > 0.0) {
+    // predicted^2 = d2^2 / prev2
+    done = d2 * d2 <= tol * tol * x2 * c.prev2;
+    const double e = 0.1 * tol * sqrt(x2 * c.prev2) / d2;
+    eta = fmin(0.1, fmax(lin_rtol, e));
+  }
+  c.prev2 = d2;
+  c.eta = eta;
+  return done;
+}
+
 // FP64 edge weights of the fine stiffness computed from nodal exp(m):
 // WE(i,j) = [2e(i,j) + 2e(i+1,j) + e(i+1,j+1) + e(i,j-1)] / 6
 // WN(i,j) = [2e(i,j) + 2e(i,j+1) + e(i+1,j+1) + e(i-1,j)] / 6
@@ -340,10 +370,11 @@ __device__ int dc_solve(const PdeGeo& g, const MgBufs<TS>& m, const SolveParams&
   });
   __syncthreads();
   int pass = 0;
-  double prev_step = INFINITY;
+  OuterCtl ctl;
+  ctl.eta = sp.lin_rtol;
   for (pass = 0; pass < sp.max_dc; ++pass) {
     bool cg_ok = true;
-    lin += pcg(g, m, sp.lin_rtol, sp.max_lin, sp.nu, red, &cg_ok);
+    lin += pcg(g, m, ctl.eta, sp.max_lin, sp.nu, red, &cg_ok);
     double v[2] = {0.0, 0.0};
     for_nodes(n, [&](int p, int i, int j) {
       if (interior(i, j, n)) {
@@ -359,9 +390,7 @@ __device__ int dc_solve(const PdeGeo& g, const MgBufs<TS>& m, const SolveParams&
       *ok = false;
       break;
     }
-    if (v[0] <= sp.newton_tol * sp.newton_tol * v[1] || (v[0] <= 1e-8 * v[1] && v[0] > 0.0625 * prev_step))
-      break;
-    prev_step = v[0];
+    if (outer_converged(ctl, v[0], v[1], sp.newton_tol, sp.lin_rtol)) break;
     // new defect b - A x in precision TW
     for_nodes(n, [&](int p, int i, int j) {
       if (interior(i, j, n)) {
@@ -539,7 +568,8 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
   __syncthreads();
   int flags = 0, lin = 0, it = 0;
   bool conv = false;
-  double prev_step = INFINITY;
+  OuterCtl ctl;
+  ctl.eta = sp.lin_rtol;
   for (it = 0; it < sp.max_newton; ++it) {
     // residual R = K u + r h^2 u^3 - f; CG right-hand side -R
     for_nodes(n, [&](int p, int i, int j) {
@@ -552,7 +582,7 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
     __syncthreads();
     build_diagonals<TW, TS>(g, m, u);
     bool ok = true;
-    lin += pcg(g, m, sp.lin_rtol, sp.max_lin, sp.nu, red, &ok);
+    lin += pcg(g, m, ctl.eta, sp.max_lin, sp.nu, red, &ok);
     if (!ok) flags |= SAA_FLAG_CG;
     double v[2] = {0.0, 0.0};
     for_nodes(n, [&](int p, int i, int j) {
@@ -569,16 +599,11 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
       flags |= SAA_FLAG_NAN;
       break;
     }
-    // converged: the update is below tolerance, or the iteration has reached
-    // the rounding floor of the state precision (updates in the asymptotic
-    // regime stopped contracting)
-    if (v[0] <= sp.newton_tol * sp.newton_tol * v[1] ||
-        (v[0] <= 1e-8 * v[1] && v[0] > 0.0625 * prev_step)) {
+    if (outer_converged(ctl, v[0], v[1], sp.newton_tol, sp.lin_rtol)) {
       conv = true;
       ++it;
       break;
     }
-    prev_step = v[0];
   }
   if (!conv) flags |= SAA_FLAG_NEWTON;
   // QoI: q = u^T M_II u - 2 ut h^2 sum u + ut^2 (the full mass has row sum h^2
