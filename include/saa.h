@@ -197,7 +197,50 @@ int saa_per_sample(saa_ctx* ctx, const double* z, int form, const void* model,
 int saa_solve_states(saa_ctx* ctx, const double* Z_dev, const saa_options* opt,
                      double* u_dev, double* q_dev, double* dudz_dev, saa_report* report);
 
-/* Per-sample solver status of the last saa_objective_grad, saa_per_sample or
+/* ------------------------------------------------------------------------
+ * MR-DINO surrogate (Sec. 3.3, eq. (rbnet)): u_w = Phi phi_w(m_r, z) + b.
+ * phi_w is a dense network on x = [m_r; z]: `depth` hidden layers of `width`
+ * units with GELU (erf form), then a linear layer to r_u reduced state
+ * coordinates.  m_r are the r_m leading whitened KL coordinates of the sample
+ * (modes ordered by increasing j^2 + k^2, ties by increasing (j, k)).  For the
+ * quadratic tracking QoI the reduced evaluation of Sec. 3.3 gives
+ * q = |phi + c|^2 + c0 (c, c0 from the POD basis, see mrdino_set_qoi), and
+ * dq/dz is obtained by reverse-mode differentiation of the network
+ * (eq. (neural_operator_gradient)).
+ * ------------------------------------------------------------------------ */
+typedef struct mrdino_dims {
+  int r_m;     /* input KL coordinates (1..128) */
+  int d_z;     /* controls (1..32); must equal the context's d_Z */
+  int r_u;     /* reduced state coordinates (1..width) */
+  int width;   /* hidden width (256) */
+  int depth;   /* hidden layers (4) */
+} mrdino_dims;
+
+typedef struct mrdino_model mrdino_model;
+
+/* Number of parameters of a network with these dimensions.  Packed order:
+ * W_0 (width x (r_m + d_z), row-major), b_0 (width), W_1 (width x width), b_1,
+ * ..., W_depth (r_u x width), b_depth. */
+int mrdino_num_params(const mrdino_dims* dims, int64_t* n);
+
+/* Create a model (parameters zero) whose device work runs on `hip_stream`.
+ * Returns SAA_E_INVALID for unsupported dimensions. */
+int mrdino_create(const mrdino_dims* dims, void* hip_stream, mrdino_model** out);
+
+/* Free a model (NULL is ignored). */
+void mrdino_free(mrdino_model* model);
+
+/* Set / get the FP32 parameters (host, n = mrdino_num_params, packed order
+ * above).  Setting rebuilds the device operands (BF16 MFMA copies). */
+int mrdino_set_params(mrdino_model* model, const float* params, int64_t n);
+int mrdino_get_params(const mrdino_model* model, float* params, int64_t n);
+
+/* Reduced QoI terms: c (host, r_u) and c0, so that q = |phi + c|^2 + c0.  For
+ * an M-orthonormal POD basis Phi and mean state b: c = Phi^T (M (b - u_t))_I
+ * and c0 = |b - u_t|_M^2 - |c|^2. */
+int mrdino_set_qoi(mrdino_model* model, const double* c, double c0);
+
+/* Per-sample status of the last saa_objective_grad, saa_per_sample or
  * saa_solve_states call on this context.  Host arrays of N entries each (any
  * may be NULL): flags (bit 1: Newton not converged, 2: an inner PCG hit
  * max_lin or broke down, 4: adjoint / linearised defect correction not

@@ -41,6 +41,11 @@ class COptions(ctypes.Structure):
                 ("all_adjoints", ctypes.c_int), ("fallback_tol", ctypes.c_double), ("timing", ctypes.c_int)]
 
 
+class CDims(ctypes.Structure):
+    _fields_ = [("r_m", ctypes.c_int), ("d_z", ctypes.c_int), ("r_u", ctypes.c_int), ("width", ctypes.c_int),
+                ("depth", ctypes.c_int)]
+
+
 class CReport(ctypes.Structure):
     _fields_ = [("t_star", ctypes.c_double), ("dJ_dt", ctypes.c_double), ("err_estimate", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("newton_max", ctypes.c_int), ("n_unconverged", ctypes.c_int),
@@ -68,6 +73,12 @@ _SIGS = {
                                       ctypes.POINTER(CReport)]),
     "saa_solve_states": (ctypes.c_int, [_P, _P, ctypes.POINTER(COptions), _P, _P, _P, ctypes.POINTER(CReport)]),
     "saa_sample_status": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "mrdino_num_params": (ctypes.c_int, [ctypes.POINTER(None), ctypes.POINTER(ctypes.c_int64)]),
+    "mrdino_create": (ctypes.c_int, [ctypes.POINTER(None), _P, ctypes.POINTER(_P)]),
+    "mrdino_free": (None, [_P]),
+    "mrdino_set_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "mrdino_get_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    "mrdino_set_qoi": (ctypes.c_int, [_P, _P, ctypes.c_double]),
 }
 
 _lib = None
@@ -262,3 +273,55 @@ class Context:
         _check(self._lib.saa_solve_states(self._h, _P(_ptr(Z)), ctypes.byref(opt), _P(_ptr(u)), _P(_ptr(q)),
                                           _P(_ptr(dudz)) if want_dudz else None, ctypes.byref(rep)))
         return u, q, dudz, rep.as_dict()
+
+
+class Model:
+    """MR-DINO network (Sec. 3.3): FP32 parameters on the device plus the
+    reduced-QoI terms c, c0."""
+
+    def __init__(self, r_m=100, d_z=25, r_u=200, width=256, depth=4, stream=None):
+        self._lib = _load()
+        self.dims = CDims(r_m, d_z, r_u, width, depth)
+        n = ctypes.c_int64()
+        _check(self._lib.mrdino_num_params(ctypes.byref(self.dims), ctypes.byref(n)))
+        self.n_params = n.value
+        h = _P()
+        st = _stream_handle() if stream is None else stream
+        _check(self._lib.mrdino_create(ctypes.byref(self.dims), _P(st), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h.value
+
+    def widths(self):
+        d = self.dims
+        return [d.r_m + d.d_z] + [d.width] * d.depth + [d.r_u]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mrdino_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        """flat: float32-convertible vector in the packed order of include/saa.h."""
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(flat, dtype=np.float32))
+        _check(self._lib.mrdino_set_params(self._h, p.ctypes.data, p.size))
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(self._lib.mrdino_get_params(self._h, p.ctypes.data, p.size))
+        return p
+
+    def set_qoi(self, c, c0):
+        import numpy as np
+        cc = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+        _check(self._lib.mrdino_set_qoi(self._h, cc.ctypes.data, float(c0)))

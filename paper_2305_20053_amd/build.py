@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaa.so")
-SOURCES = ["api.cpp", "pde.hip", "cvar.hip"]
+SOURCES = ["api.cpp", "model.cpp", "pde.hip", "cvar.hip", "mlp.hip"]
 ARCH = os.environ.get("SAA_OFFLOAD_ARCH", "gfx950")
 
 
@@ -31,7 +31,9 @@ def build(verbose: bool = False) -> str:
         cmd = [hipcc()] + flags + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.PIPE)
+        res = subprocess.run(cmd, stderr=None if verbose else subprocess.PIPE, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr or ''}")
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

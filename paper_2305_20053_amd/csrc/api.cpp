@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
+#include <array>
 #include <new>
+#include <vector>
 
 #include "../../include/saa.h"
 #include "pde.h"
@@ -43,87 +46,13 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
           const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, hipStream_t st);
 }  // namespace saa_launch
 
-using saa_rt::DevBuf;
+#include "ctx.h"
+#include "model.h"
+
+using namespace saa_rt;
 
 namespace {
 
-template <typename TS>
-struct MgStore {
-  DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;
-  bool allocated = false;
-  bool built = false;
-  MgBufs<TS> view() const {
-    MgBufs<TS> m;
-    m.WE = (TS*)WE.p;
-    m.WN = (TS*)WN.p;
-    m.KD = (TS*)KD.p;
-    m.D = (TS*)D.p;
-    m.X = (TS*)X.p;
-    m.B = (TS*)B.p;
-    m.T = (TS*)T.p;
-    m.cx = (TS*)cx.p;
-    m.cr = (TS*)cr.p;
-    m.cp = (TS*)cp.p;
-    m.cq = (TS*)cq.p;
-    return m;
-  }
-};
-
-bool is_fin(double x) { return std::isfinite(x); }
-
-// Phase timing with HIP events on the context's stream: marks 0..4 bracket
-// [state | reduce 1 | adjoint | reduce 2].
-struct PhaseTimer {
-  bool on = false;
-  hipEvent_t ev[5] = {};
-  void mark(hipStream_t st, int k) {
-    if (on) (void)hipEventRecord(ev[k], st);
-  }
-  int create() {
-    for (auto& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) return SAA_E_DEVICE;
-    return SAA_OK;
-  }
-  ~PhaseTimer() {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-  }
-  void ms(double* state, double* adjoint, double* reduce) const {
-    float a = 0, b = 0, d = 0, e = 0;
-    if (!on) return;
-    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
-    (void)hipEventElapsedTime(&d, ev[2], ev[3]);
-    (void)hipEventElapsedTime(&e, ev[3], ev[4]);
-    *state = a;
-    *reduce = (double)b + e;
-    *adjoint = d;
-  }
-};
-
-
-}  // namespace
-
-struct saa_ctx {
-  saa_problem prob{};
-  int64_t N_max = 0;
-  int64_t N = 0;
-  hipStream_t st = nullptr;
-  PdeGeo geo{};
-  int K1 = 0, dz = 0;
-  int64_t nodes = 0, d_u = 0;
-  DevBuf FT, S, amp, em, xi, kap;
-  int64_t kstride = 0, kchunk = 0;
-  MgStore<double> mg64;
-  MgStore<float> mg32;
-  DevBuf u, f, lam;          // TW node vectors (sized for float64)
-  DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
-  PhaseTimer timer;
-};
-
-namespace {
-
-int check_hip(hipError_t e) { return e == hipSuccess ? SAA_OK : SAA_E_DEVICE; }
 
 template <typename TS>
 int alloc_mg(saa_ctx* c, MgStore<TS>& m) {
@@ -185,6 +114,12 @@ int validate_options(const saa_options* o) {
 // Launch the state solve for the requested PDE precision.
 int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const SolveParams& sp) {
   int rc;
+  if (!c->u.p) {  // PDE-form node vectors are allocated at first use
+    const size_t tw = (size_t)c->N_max * c->nodes * sizeof(double);
+    if ((rc = c->u.alloc_zero(tw, c->st)) || (rc = c->f.alloc_zero(tw, c->st)) ||
+        (rc = c->lam.alloc_zero(tw, c->st)))
+      return rc;
+  }
   switch (prec) {
     case SAA_FP64:
       if (!c->mg64.built && (rc = build_mg(c, c->mg64))) return rc;
@@ -257,6 +192,27 @@ int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJ
     if (tm) tm->ms(&rep->ms_state, &rep->ms_adjoint, &rep->ms_reduce);
   }
   return s.n_unconverged > 0 ? SAA_E_NOCONV : SAA_OK;
+}
+
+// Common validation of an objective / per-sample call.
+int validate_call(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt) {
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  if (c->N < 1) return SAA_E_INVALID;
+  for (int k = 0; k < c->dz; ++k)
+    if (!is_fin(z[k])) return SAA_E_INVALID;
+  if (form == SAA_FORM_PDE) {
+    if (model != nullptr) return SAA_E_INVALID;
+    if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
+  } else if (form == SAA_FORM_MRDINO) {
+    if (model == nullptr) return SAA_E_INVALID;
+    if (opt->prec != SAA_FP32 && opt->prec != SAA_BF16) return SAA_E_INVALID;
+    const mrdino_model* m = (const mrdino_model*)model;
+    if (m->dims.d_z != c->dz || m->dims.r_m > c->K1 * c->K1) return SAA_E_MODEL;
+  } else {
+    return SAA_E_INVALID;
+  }
+  return SAA_OK;
 }
 
 }  // namespace
@@ -352,9 +308,6 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!rc) rc = c->amp.alloc((size_t)c->K1 * c->K1 * sizeof(double));
   if (!rc) rc = c->em.alloc(tw);
   if (!rc) rc = c->xi.alloc((size_t)N_max * c->K1 * c->K1 * sizeof(double));
-  if (!rc) rc = c->u.alloc_zero(tw, c->st);
-  if (!rc) rc = c->f.alloc_zero(tw, c->st);
-  if (!rc) rc = c->lam.alloc_zero(tw, c->st);
   if (!rc) rc = c->q.alloc((size_t)N_max * sizeof(double));
   if (!rc) rc = c->g.alloc((size_t)N_max * c->dz * sizeof(double));
   if (!rc) rc = c->newton.alloc_zero((size_t)N_max * sizeof(int), c->st);
@@ -367,9 +320,20 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!rc) rc = c->out.alloc((2 + SAA_MAX_DZ) * sizeof(double));
   if (!rc) rc = c->stats.alloc(sizeof(CvarStats));
   if (!rc) rc = c->timer.create();
+  if (!rc) rc = c->order.alloc(sizeof(int) * (size_t)c->K1 * c->K1);
   if (rc) {
     delete c;
     return rc;
+  }
+  {  // KL modes by increasing j^2 + k^2, ties by increasing (j, k): index (j-1) K1 + (k-1)
+    std::vector<std::array<int, 3>> modes;
+    for (int j = 1; j <= c->K1; ++j)
+      for (int k = 1; k <= c->K1; ++k) modes.push_back({j * j + k * k, j, k});
+    std::sort(modes.begin(), modes.end());
+    std::vector<int> ord;
+    for (const auto& md : modes) ord.push_back((md[1] - 1) * c->K1 + (md[2] - 1));
+    rc = check_hip(hipMemcpyAsync(c->order.p, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
   }
   // shared operators: sine table, KL amplitudes, lumped source matrix
   {
@@ -430,33 +394,40 @@ int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
 int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
                        double* J, double* grad_z, saa_report* rep) {
   if (!c || !z || !J || !grad_z) return SAA_E_INVALID;
-  int rc = validate_options(opt);
+  int rc = validate_call(c, z, form, model, opt);
   if (rc) return rc;
-  if (c->N < 1) return SAA_E_INVALID;
-  for (int k = 0; k < c->dz; ++k)
-    if (!is_fin(z[k])) return SAA_E_INVALID;
-  if (form != SAA_FORM_PDE || model != nullptr) return SAA_E_INVALID;
-  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
-
   const auto t0 = std::chrono::steady_clock::now();
-  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
   if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
     return rc;
   PhaseTimer& tm = c->timer;
   tm.on = opt->timing != 0;
   tm.mark(c->st, 0);
-  if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
-  tm.mark(c->st, 1);
-  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                   (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, (double*)c->tstar.p, (double*)c->out.p, nullptr,
-                   nullptr, nullptr, nullptr, nullptr, nullptr, c->st);
-  tm.mark(c->st, 2);
-  if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
-  tm.mark(c->st, 3);
-  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                   (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, (double*)c->tstar.p, (double*)c->out.p,
-                   (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
-                   c->stats.p, c->st);
+  if (form == SAA_FORM_PDE) {
+    const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+    if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
+    tm.mark(c->st, 1);
+    saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
+                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, (double*)c->tstar.p, (double*)c->out.p,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->st);
+    tm.mark(c->st, 2);
+    if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
+    tm.mark(c->st, 3);
+    saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
+                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, (double*)c->tstar.p, (double*)c->out.p,
+                     (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
+                     c->stats.p, c->st);
+  } else {
+    // surrogate: q and dq/dz of every sample in one fused launch, then the reduction
+    if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p,
+                             (double*)c->g.p)))
+      return rc;
+    tm.mark(c->st, 1);
+    tm.mark(c->st, 2);
+    tm.mark(c->st, 3);
+    saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
+                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, c->stats.p, c->st);
+  }
   tm.mark(c->st, 4);
   if ((rc = check_hip(hipGetLastError()))) return rc;
   double host[2 + SAA_MAX_DZ];
@@ -474,24 +445,27 @@ int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model,
 int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
                    double* q_dev, double* g_dev, saa_report* rep) {
   if (!c || !z || !q_dev || !g_dev) return SAA_E_INVALID;
-  int rc = validate_options(opt);
+  int rc = validate_call(c, z, form, model, opt);
   if (rc) return rc;
-  if (c->N < 1) return SAA_E_INVALID;
-  for (int k = 0; k < c->dz; ++k)
-    if (!is_fin(z[k])) return SAA_E_INVALID;
-  if (form != SAA_FORM_PDE || model != nullptr) return SAA_E_INVALID;
-  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
   const auto t0 = std::chrono::steady_clock::now();
-  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
   if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
     return rc;
-  if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
-  if ((rc = run_adjoint(c, opt->prec, sp, 1, g_dev))) return rc;
-  if ((rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
-    return rc;
-  saa_launch::cvar((double*)c->q.p, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p,
-                   opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p,
-                   (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats.p, c->st);
+  if (form == SAA_FORM_PDE) {
+    const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+    if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
+    if ((rc = run_adjoint(c, opt->prec, sp, 1, g_dev))) return rc;
+    if ((rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
+      return rc;
+    saa_launch::cvar((double*)c->q.p, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p,
+                     opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p,
+                     (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats.p, c->st);
+  } else {
+    if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, q_dev, g_dev)))
+      return rc;
+    saa_launch::cvar(q_dev, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p, opt->t_mode,
+                     opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, c->stats.p, c->st);
+  }
   if ((rc = check_hip(hipGetLastError()))) return rc;
   double t = 0, host[2];
   if ((rc = check_hip(hipMemcpyAsync(host, c->out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, c->st)))) return rc;

@@ -1,0 +1,89 @@
+// Internal definition of the SAA context, shared by the host runtime files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/saa.h"
+#include "pde.h"
+#include "runtime.h"
+
+namespace saa_rt {
+
+template <typename TS>
+struct MgStore {
+  DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;
+  bool allocated = false;
+  bool built = false;
+  MgBufs<TS> view() const {
+    MgBufs<TS> m;
+    m.WE = (TS*)WE.p;
+    m.WN = (TS*)WN.p;
+    m.KD = (TS*)KD.p;
+    m.D = (TS*)D.p;
+    m.X = (TS*)X.p;
+    m.B = (TS*)B.p;
+    m.T = (TS*)T.p;
+    m.cx = (TS*)cx.p;
+    m.cr = (TS*)cr.p;
+    m.cp = (TS*)cp.p;
+    m.cq = (TS*)cq.p;
+    return m;
+  }
+};
+
+inline bool is_fin(double x) { return std::isfinite(x); }
+
+// Phase timing with HIP events on the context's stream: marks 0..4 bracket
+// [state | reduce 1 | adjoint | reduce 2].
+struct PhaseTimer {
+  bool on = false;
+  hipEvent_t ev[5] = {};
+  void mark(hipStream_t st, int k) {
+    if (on) (void)hipEventRecord(ev[k], st);
+  }
+  int create() {
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return SAA_E_DEVICE;
+    return SAA_OK;
+  }
+  ~PhaseTimer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void ms(double* state, double* adjoint, double* reduce) const {
+    float a = 0, b = 0, d = 0, e = 0;
+    if (!on) return;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&d, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&e, ev[3], ev[4]);
+    *state = a;
+    *reduce = (double)b + e;
+    *adjoint = d;
+  }
+};
+
+
+inline int check_hip(hipError_t e) { return e == hipSuccess ? SAA_OK : SAA_E_DEVICE; }
+
+}  // namespace saa_rt
+
+struct saa_ctx {
+  saa_problem prob{};
+  int64_t N_max = 0;
+  int64_t N = 0;
+  hipStream_t st = nullptr;
+  PdeGeo geo{};
+  int K1 = 0, dz = 0;
+  int64_t nodes = 0, d_u = 0;
+  saa_rt::DevBuf FT, S, amp, em, xi, kap;
+  int64_t kstride = 0, kchunk = 0;
+  saa_rt::MgStore<double> mg64;
+  saa_rt::MgStore<float> mg32;
+  saa_rt::DevBuf u, f, lam;   // PDE-form node vectors (sized for float64; allocated at first use)
+  saa_rt::DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
+  saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
+  saa_rt::PhaseTimer timer;
+};

@@ -1,0 +1,28 @@
+// MR-DINO network layout shared by the HIP kernels and the host runtime.
+#pragma once
+#include <stdint.h>
+
+#define MLP_MAX_DEPTH 8
+
+// Device weight views of one network.  Layer L = 0 maps the encoded input
+// (r_m KL coordinates; the control part of W_0 is folded into an effective
+// bias per call) to width W, layers 1..depth-1 are W x W, layer `depth` maps W
+// to the r_u reduced state coordinates (rows padded to W with zeros).
+struct MlpDev {
+  int r_m, d_z, r_u, width, depth, kin;  // kin: r_m padded to a multiple of 32
+  // FP32 master parameters, packed: W_0 (width x (r_m+d_z)), b_0, W_1, b_1, ...
+  const float* master;
+  int64_t off_w[MLP_MAX_DEPTH + 1];      // offsets of W_L and b_L in `master`
+  int64_t off_b[MLP_MAX_DEPTH + 1];
+  // BF16 MFMA operands (see mlp.hip for the k-permutation):
+  const void* wp[MLP_MAX_DEPTH + 1];     // forward: rows = outputs, cols = inputs
+  const void* wt[MLP_MAX_DEPTH + 1];     // backward (L >= 1): rows = inputs, cols = outputs
+  const void* w0z;                       // 32 x width: d_Z rows of W_0^T
+  const float* bias[MLP_MAX_DEPTH + 1];  // FP32 biases, padded to width
+  const float* b0eff;                    // b_0 + W_0[:, r_m:] z (per call)
+  const float* c;                        // reduced-QoI shift, padded to width
+  double c0;
+  // FP32 reference operands: natural W_L (out x in) and its transpose (in x out)
+  const float* wn[MLP_MAX_DEPTH + 1];
+  const float* wtn[MLP_MAX_DEPTH + 1];
+};

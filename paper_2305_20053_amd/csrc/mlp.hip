@@ -1,0 +1,388 @@
+// MR-DINO surrogate evaluation (paper Sec. 3.3, eq. (rbnet); Sec. 3.1,
+// eq. (neural_operator_risk) / (neural_operator_gradient)):
+//
+//   x = [xi_hat (r_m leading KL coordinates); z]
+//   a_L = W_L h_{L-1} + b_L, h_L = GELU(a_L), L = 0..depth-1;  phi = W_depth h + b
+//   q = |phi + c|^2 + c0                 (reduced quadratic QoI, Sec. 3.3)
+//   dq/dz by reverse mode: delta = 2 (phi + c), back through the layers with
+//   GELU'(a_L), and finally the control columns of W_0.
+//
+// BF16 kernel (MFMA v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Each wave
+// carries 16 samples through the whole network.  Products are formed
+// transposed, C = W_L * H^T: output features run along the MFMA M dimension and
+// samples along N, so one lane holds, for its sample, 4 consecutive features of
+// every 16-feature tile.  That accumulator layout is the B-operand layout of the
+// next layer up to a fixed permutation inside every 32-feature block
+// (slot 8g + t holds feature 4g + t for t < 4 and 16 + 4g + t - 4 for t >= 4);
+// the permutation is folded into the stored weight copies, so activations never
+// leave registers between layers.  GELU'(a_L) of every layer is kept in LDS as
+// fp16 for the reverse pass.
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "mlp.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ int kperm(int k) {
+  const int b = k & ~31, kk = k & 31, g = kk >> 3, t = kk & 7;
+  return b + (t < 4 ? 4 * g + t : 16 + 4 * g + (t - 4));
+}
+
+__device__ __forceinline__ float gelu_f(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
+__device__ __forceinline__ float dgelu_f(float a) {
+  return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * __expf(-0.5f * a * a);
+}
+
+// acc[mt] += A(mt, ks) * hb[ks] over ks < NK, where A(mt, ks) is the 16 x 32
+// bf16 fragment of rows 16 mt.. and columns 32 ks.. of a row-major operand with
+// leading dimension ld.  The A fragments of step ks + 1 are loaded while the
+// MFMAs of step ks run (two register stages); scheduling barriers keep the
+// compiler from hoisting further loads.
+template <int MT, int NK, int KSA>
+__device__ __forceinline__ void mfma_gemm(const __bf16* w, int ld, const bf16x8 (&hb)[KSA], f32x4 (&acc)[MT],
+                                          int c16, int g) {
+  bf16x8 a[2][MT];
+  const __bf16* base = w + (int64_t)c16 * ld + 8 * g;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) a[0][mt] = *(const bf16x8*)(base + (int64_t)16 * mt * ld);
+#pragma unroll
+  for (int ks = 0; ks < NK; ++ks) {
+    if (ks + 1 < NK) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        a[(ks + 1) & 1][mt] = *(const bf16x8*)(base + (int64_t)16 * mt * ld + 32 * (ks + 1));
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks & 1][mt], hb[ks], acc[mt], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Weight packing (after every change of the FP32 master parameters)
+// ---------------------------------------------------------------------------
+
+// Forward BF16 operand: dst[m][k] (rows x cols) = W[m][kperm(k)] (or natural
+// order when `natural`), zero outside the source.  W is src_rows x src_ld.
+__global__ void saa_k_pack_fwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
+                               int src_ld, int natural) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * cols) return;
+  const int m = (int)(t / cols), k = (int)(t % cols);
+  const int ks = natural ? k : kperm(k);
+  float v = 0.0f;
+  if (m < src_rows && ks < src_cols) v = src[(int64_t)m * src_ld + ks];
+  dst[t] = (__bf16)v;
+}
+
+// Backward BF16 operand: dst[m][k] = W[kperm(k)][col0 + m], zero outside.
+__global__ void saa_k_pack_bwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
+                               int src_ld, int col0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * cols) return;
+  const int m = (int)(t / cols), k = (int)(t % cols);
+  const int o = kperm(k);
+  float v = 0.0f;
+  if (o < src_rows && m < src_cols) v = src[(int64_t)o * src_ld + col0 + m];
+  dst[t] = (__bf16)v;
+}
+
+// FP32 transpose: dst[k][m] = W[m][k] (W rows x cols).
+__global__ void saa_k_transpose(float* dst, const float* src, int rows, int cols, int src_ld) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * cols) return;
+  const int k = (int)(t / rows), m = (int)(t % rows);
+  dst[t] = src[(int64_t)m * src_ld + k];
+}
+
+// Zero-padded copy of a vector.
+__global__ void saa_k_pad(float* dst, const float* src, int n_src, int n_dst) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_dst) dst[t] = t < n_src ? src[t] : 0.0f;
+}
+
+// b0eff[f] = b_0[f] + sum_k W_0[f][r_m + k] z_k  (the control enters only
+// through the first layer and is shared by all samples).
+__global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m,
+                            int d_z) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= width) return;
+  const float* w = W0 + (int64_t)f * (r_m + d_z) + r_m;
+  float acc = b0[f];
+  for (int k = 0; k < d_z; ++k) acc += w[k] * (float)z[k];
+  b0eff[f] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Fused BF16 forward + reverse kernel
+// ---------------------------------------------------------------------------
+template <int W, int KIN, int DEPTH, int WAVES, int NZT>
+__global__ void __launch_bounds__(WAVES * 64, 1)
+    saa_k_mlp_bf16(MlpDev net, const double* xi, int nkl, const int* order, int64_t N, double* q_out,
+                   double* g_out) {
+  constexpr int MT = W / 16;   // 16-feature tiles of a layer output
+  constexpr int KS = W / 32;   // 32-feature k-steps of a layer input
+  constexpr int KS1 = KIN / 32;
+  extern __shared__ _Float16 sdg[];   // [WAVES][DEPTH][MT][64 lanes][4]
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, c16 = ln & 15;
+  _Float16* my = sdg + (size_t)wv * DEPTH * MT * 256;
+  const int r_m = net.r_m, r_u = net.r_u, d_z = net.d_z;
+
+  // one 16 * WAVES-sample tile per workgroup (a persistent loop would let the
+  // compiler hoist every bias load out of it and spill)
+  {
+    const int64_t base = (int64_t)blockIdx.x * (16 * WAVES);
+    const int64_t s = base + wv * 16 + c16;
+    const bool valid = s < N;
+    bf16x8 hb[KS];
+    f32x4 acc[MT];
+    // encoded input: leading r_m KL coordinates, natural k order, zero padded
+#pragma unroll
+    for (int ks = 0; ks < KS1; ++ks)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = 32 * ks + 8 * g + t;
+        const float v = (valid && k < r_m) ? (float)xi[s * nkl + order[k]] : 0.0f;
+        hb[ks][t] = (__bf16)v;
+      }
+#pragma unroll
+    for (int ks = KS1; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) hb[ks][t] = (__bf16)0.0f;
+
+    // forward through the hidden layers
+#pragma unroll
+    for (int L = 0; L < DEPTH; ++L) {
+      const __bf16* wl = (const __bf16*)net.wp[L];
+      const int ld = (L == 0) ? KIN : W;
+      const float* bl = (L == 0) ? net.b0eff : net.bias[L];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (L == 0) mfma_gemm<MT, KS1, KS>(wl, ld, hb, acc, c16, g);
+      else mfma_gemm<MT, KS, KS>(wl, ld, hb, acc, c16, g);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float a = acc[mt][r] + bl[16 * mt + 4 * g + r];
+          my[((L * MT + mt) * 64 + ln) * 4 + r] = (_Float16)dgelu_f(a);
+          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)gelu_f(a);
+        }
+    }
+    // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
+    {
+      const __bf16* wl = (const __bf16*)net.wp[DEPTH];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      mfma_gemm<MT, KS, KS>(wl, W, hb, acc, c16, g);
+      float qs = 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = 16 * mt + 4 * g + r;
+          const float v = (f < r_u) ? acc[mt][r] + net.bias[DEPTH][f] + net.c[f] : 0.0f;
+          qs += v * v;
+          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)(2.0f * v);
+        }
+      qs += __shfl_xor(qs, 16, 64);
+      qs += __shfl_xor(qs, 32, 64);
+      if (g == 0 && valid) q_out[s] = (double)qs + net.c0;
+    }
+    // reverse pass: delta h_{L} = W_{L+1}^T delta a_{L+1}; delta a_L = GELU'(a_L) delta h_L
+#pragma unroll
+    for (int L = DEPTH; L >= 1; --L) {
+      const __bf16* wl = (const __bf16*)net.wt[L];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      mfma_gemm<MT, KS, KS>(wl, W, hb, acc, c16, g);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float d = acc[mt][r] * (float)my[(((L - 1) * MT + mt) * 64 + ln) * 4 + r];
+          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)d;
+        }
+    }
+    // dq/dz = W_0[:, r_m:]^T delta a_0
+    {
+      f32x4 accz[NZT];
+#pragma unroll
+      for (int zt = 0; zt < NZT; ++zt) accz[zt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const __bf16* wz = (const __bf16*)net.w0z;
+      mfma_gemm<NZT, KS, KS>(wz, W, hb, accz, c16, g);
+      if (valid) {
+#pragma unroll
+        for (int zt = 0; zt < NZT; ++zt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int zi = 16 * zt + 4 * g + r;
+            if (zi < d_z) g_out[s * d_z + zi] = (double)accz[zt][r];
+          }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 reference kernel (plain FMA): one wave carries 2 samples; each lane
+// owns output features lane, lane + 64, ...; activations in LDS.
+// ---------------------------------------------------------------------------
+template <int W, int DEPTH>
+__global__ void __launch_bounds__(256) saa_k_mlp_fp32(MlpDev net, const double* xi, int nkl, const int* order,
+                                                      int64_t N, double* q_out, double* g_out) {
+  constexpr int S = 2;          // samples per wave
+  constexpr int J = W / 64;     // outputs per lane
+  __shared__ float hbuf[4][S][W];
+  __shared__ float dg[4][DEPTH][S][W];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int r_m = net.r_m, r_u = net.r_u, d_z = net.d_z;
+  const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * S;   // waves past N compute on zeros
+  float (*h)[W] = hbuf[wv];
+  for (int si = 0; si < S; ++si)
+    for (int k = ln; k < W; k += 64) {
+      const int64_t s = s0 + si;
+      h[si][k] = (s < N && k < r_m) ? (float)xi[s * nkl + order[k]] : 0.0f;
+    }
+  __syncthreads();
+  for (int L = 0; L <= DEPTH; ++L) {
+    const int kin = (L == 0) ? r_m : W;
+    const int rows = (L == DEPTH) ? r_u : W;
+    const float* wt = net.wtn[L];   // kin_L x rows (transposed natural), contiguous in output
+    float a[S][J];
+    for (int si = 0; si < S; ++si)
+      for (int j = 0; j < J; ++j) a[si][j] = 0.0f;
+    for (int k = 0; k < kin; ++k) {
+      float wk[J];
+      for (int j = 0; j < J; ++j) {
+        const int m = ln + 64 * j;
+        wk[j] = (m < rows) ? wt[(int64_t)k * rows + m] : 0.0f;
+      }
+      for (int si = 0; si < S; ++si) {
+        const float hk = h[si][k];
+        for (int j = 0; j < J; ++j) a[si][j] += wk[j] * hk;
+      }
+    }
+    __syncthreads();
+    for (int si = 0; si < S; ++si)
+      for (int j = 0; j < J; ++j) {
+        const int m = ln + 64 * j;
+        const float b = (L == 0) ? net.b0eff[m] : net.bias[L][m];
+        const float v = a[si][j] + b;
+        if (L < DEPTH) {
+          dg[wv][L][si][m] = dgelu_f(v);
+          h[si][m] = gelu_f(v);
+        } else {
+          h[si][m] = (m < r_u) ? v + net.c[m] : 0.0f;   // phi + c
+        }
+      }
+    __syncthreads();
+  }
+  // q and delta = 2 (phi + c)
+  for (int si = 0; si < S; ++si) {
+    float qs = 0.0f;
+    for (int m = ln; m < W; m += 64) qs += h[si][m] * h[si][m];
+    qs = wave_sum(qs);
+    const int64_t s = s0 + si;
+    if (ln == 0 && s < N) q_out[s] = (double)qs + net.c0;
+  }
+  __syncthreads();
+  for (int si = 0; si < S; ++si)
+    for (int m = ln; m < W; m += 64) h[si][m] *= 2.0f;
+  __syncthreads();
+  // reverse: dh_{L-1}[k] = sum_m W_L[m][k] da_L[m]
+  for (int L = DEPTH; L >= 1; --L) {
+    const int rows = (L == DEPTH) ? r_u : W;
+    const float* w = net.wn[L];   // rows x W natural
+    float a[S][J];
+    for (int si = 0; si < S; ++si)
+      for (int j = 0; j < J; ++j) a[si][j] = 0.0f;
+    for (int m = 0; m < rows; ++m) {
+      float wk[J];
+      for (int j = 0; j < J; ++j) wk[j] = w[(int64_t)m * W + ln + 64 * j];
+      for (int si = 0; si < S; ++si) {
+        const float dm = h[si][m];
+        for (int j = 0; j < J; ++j) a[si][j] += wk[j] * dm;
+      }
+    }
+    __syncthreads();
+    for (int si = 0; si < S; ++si)
+      for (int j = 0; j < J; ++j) {
+        const int k = ln + 64 * j;
+        h[si][k] = a[si][j] * dg[wv][L - 1][si][k];
+      }
+    __syncthreads();
+  }
+  // dq/dz_i = sum_m W_0[m][r_m + i] da_0[m]
+  const float* w0 = net.wn[0];
+  for (int si = 0; si < S; ++si) {
+    const int64_t s = s0 + si;
+    for (int zi = ln; zi < d_z; zi += 64) {
+      float acc = 0.0f;
+      for (int m = 0; m < W; ++m) acc += w0[(int64_t)m * (r_m + d_z) + r_m + zi] * h[si][m];
+      if (s < N) g_out[s * d_z + zi] = (double)acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+namespace saa_launch {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void mlp_pack_fwd(void* dst, const float* src, int rows, int cols, int src_rows, int src_cols, int src_ld,
+                  int natural, hipStream_t st) {
+  saa_k_pack_fwd<<<nblk((int64_t)rows * cols, 256), 256, 0, st>>>((__bf16*)dst, src, rows, cols, src_rows,
+                                                                  src_cols, src_ld, natural);
+}
+void mlp_pack_bwd(void* dst, const float* src, int rows, int cols, int src_rows, int src_cols, int src_ld,
+                  int col0, hipStream_t st) {
+  saa_k_pack_bwd<<<nblk((int64_t)rows * cols, 256), 256, 0, st>>>((__bf16*)dst, src, rows, cols, src_rows,
+                                                                  src_cols, src_ld, col0);
+}
+void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld, hipStream_t st) {
+  saa_k_transpose<<<nblk((int64_t)rows * cols, 256), 256, 0, st>>>(dst, src, rows, cols, src_ld);
+}
+void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st) {
+  saa_k_pad<<<nblk(n_dst, 256), 256, 0, st>>>(dst, src, n_src, n_dst);
+}
+void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
+               hipStream_t st) {
+  saa_k_b0eff<<<nblk(width, 256), 256, 0, st>>>(b0eff, W0, b0, z, width, r_m, d_z);
+}
+
+// Supported shapes: width 256, depth 4, r_m <= 128, d_z <= 32.
+int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, int64_t N,
+             double* q, double* g, int n_cu, hipStream_t st) {
+  if (net.width != 256 || net.depth != 4 || net.r_m > 128 || net.d_z > 32 || net.r_u > 256) return -1;
+  if (prec_bf16) {
+    constexpr int WAVES = 4;
+    const size_t lds = (size_t)WAVES * 4 * (256 / 16) * 256 * sizeof(_Float16);
+    const int64_t tiles = (N + 16 * WAVES - 1) / (16 * WAVES);
+    const unsigned grid = (unsigned)tiles;
+    (void)n_cu;
+    static bool attr_set = false;
+    if (!attr_set) {
+      if (hipFuncSetAttribute((const void*)saa_k_mlp_bf16<256, 128, 4, WAVES, 2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -2;
+      attr_set = true;
+    }
+    saa_k_mlp_bf16<256, 128, 4, WAVES, 2><<<grid, WAVES * 64, lds, st>>>(net, xi, nkl, order, N, q, g);
+  } else {
+    const int64_t blocks = (N + 7) / 8;
+    saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);
+  }
+  return 0;
+}
+
+}  // namespace saa_launch

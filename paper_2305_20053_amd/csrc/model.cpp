@@ -1,0 +1,203 @@
+// MR-DINO model object: parameters, packed device operands, evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ctx.h"
+#include "mlp.h"
+#include "model.h"
+
+namespace saa_launch {
+void mlp_pack_fwd(void* dst, const float* src, int rows, int cols, int src_rows, int src_cols, int src_ld,
+                  int natural, hipStream_t st);
+void mlp_pack_bwd(void* dst, const float* src, int rows, int cols, int src_rows, int src_cols, int src_ld,
+                  int col0, hipStream_t st);
+void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld, hipStream_t st);
+void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st);
+void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
+               hipStream_t st);
+int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, int64_t N,
+             double* q, double* g, int n_cu, hipStream_t st);
+}  // namespace saa_launch
+
+using namespace saa_rt;
+
+namespace saa_model {
+
+int64_t param_count(const mrdino_dims& d) {
+  int64_t n = 0;
+  int in = d.r_m + d.d_z;
+  for (int L = 0; L <= d.depth; ++L) {
+    const int out = (L == d.depth) ? d.r_u : d.width;
+    n += (int64_t)out * in + out;
+    in = out;
+  }
+  return n;
+}
+
+bool dims_supported(const mrdino_dims& d) {
+  return d.width == 256 && d.depth == 4 && d.r_m >= 1 && d.r_m <= 128 && d.d_z >= 1 && d.d_z <= 32 &&
+         d.r_u >= 1 && d.r_u <= 256;
+}
+
+MlpDev view(const mrdino_model* m) {
+  MlpDev v{};
+  const mrdino_dims& d = m->dims;
+  v.r_m = d.r_m;
+  v.d_z = d.d_z;
+  v.r_u = d.r_u;
+  v.width = d.width;
+  v.depth = d.depth;
+  v.kin = m->kin;
+  v.master = (const float*)m->master.p;
+  for (int L = 0; L <= d.depth; ++L) {
+    v.off_w[L] = m->off_w[L];
+    v.off_b[L] = m->off_b[L];
+    v.wp[L] = m->wp[L].p;
+    v.wt[L] = m->wt[L].p;
+    v.bias[L] = (const float*)m->bias[L].p;
+    v.wn[L] = (const float*)m->master.p + m->off_w[L];
+    v.wtn[L] = (const float*)m->wtn[L].p;
+  }
+  v.w0z = m->w0z.p;
+  v.b0eff = (const float*)m->b0eff.p;
+  v.c = (const float*)m->c.p;
+  v.c0 = m->c0;
+  return v;
+}
+
+// Rebuild every derived operand from the FP32 master parameters.
+int pack(mrdino_model* m) {
+  const mrdino_dims& d = m->dims;
+  const int W = d.width;
+  const float* P = (const float*)m->master.p;
+  hipStream_t st = m->st;
+  for (int L = 0; L <= d.depth; ++L) {
+    const int in = (L == 0) ? d.r_m + d.d_z : W;
+    const int rows = (L == d.depth) ? d.r_u : W;
+    const float* w = P + m->off_w[L];
+    if (L == 0) {
+      saa_launch::mlp_pack_fwd(m->wp[0].p, w, W, m->kin, W, d.r_m, in, 1, st);
+      saa_launch::mlp_transpose((float*)m->wtn[0].p, w, W, d.r_m, in, st);   // r_m x W
+    } else {
+      saa_launch::mlp_pack_fwd(m->wp[L].p, w, W, W, rows, W, W, 0, st);
+      saa_launch::mlp_pack_bwd(m->wt[L].p, w, W, W, rows, W, W, 0, st);
+      saa_launch::mlp_transpose((float*)m->wtn[L].p, w, rows, W, W, st);     // W x rows
+    }
+    saa_launch::mlp_pad((float*)m->bias[L].p, P + m->off_b[L], rows, W, st);
+  }
+  saa_launch::mlp_pack_bwd(m->w0z.p, P + m->off_w[0], 32, W, W, d.d_z, d.r_m + d.d_z, d.r_m, st);
+  return check_hip(hipGetLastError());
+}
+
+}  // namespace saa_model
+
+using namespace saa_model;
+
+extern "C" {
+
+int mrdino_num_params(const mrdino_dims* d, int64_t* n) {
+  if (!d || !n || d->width < 1 || d->depth < 1 || d->depth > MLP_MAX_DEPTH || d->r_m < 1 || d->d_z < 1 ||
+      d->r_u < 1)
+    return SAA_E_INVALID;
+  *n = param_count(*d);
+  return SAA_OK;
+}
+
+int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
+  if (!d || !out) return SAA_E_INVALID;
+  *out = nullptr;
+  if (!dims_supported(*d)) return SAA_E_INVALID;
+  mrdino_model* m = new (std::nothrow) mrdino_model();
+  if (!m) return SAA_E_OOM;
+  m->dims = *d;
+  m->st = (hipStream_t)hip_stream;
+  m->kin = (d->r_m + 31) / 32 * 32;
+  m->n_params = param_count(*d);
+  int64_t off = 0;
+  int in = d->r_m + d->d_z;
+  for (int L = 0; L <= d->depth; ++L) {
+    const int rows = (L == d->depth) ? d->r_u : d->width;
+    m->off_w[L] = off;
+    off += (int64_t)rows * in;
+    m->off_b[L] = off;
+    off += rows;
+    in = rows;
+  }
+  const int W = d->width;
+  int rc = m->master.alloc_zero(sizeof(float) * m->n_params, m->st);
+  for (int L = 0; L <= d->depth && !rc; ++L) {
+    const int cols = (L == 0) ? m->kin : W;
+    rc = m->wp[L].alloc_zero(2 * (size_t)W * cols, m->st);
+    if (!rc && L > 0) rc = m->wt[L].alloc_zero(2 * (size_t)W * W, m->st);
+    if (!rc) rc = m->bias[L].alloc_zero(sizeof(float) * W, m->st);
+    if (!rc) rc = m->wtn[L].alloc_zero(sizeof(float) * (size_t)W * (L == 0 ? d->r_m : W), m->st);
+  }
+  if (!rc) rc = m->w0z.alloc_zero(2 * (size_t)32 * W, m->st);
+  if (!rc) rc = m->b0eff.alloc_zero(sizeof(float) * W, m->st);
+  if (!rc) rc = m->c.alloc_zero(sizeof(float) * W, m->st);
+  if (!rc) rc = m->zdev.alloc_zero(sizeof(double) * 64, m->st);
+  if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return SAA_OK;
+}
+
+void mrdino_free(mrdino_model* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->st);
+  delete m;
+}
+
+int mrdino_set_params(mrdino_model* m, const float* params, int64_t n) {
+  if (!m || !params || n != m->n_params) return SAA_E_INVALID;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return SAA_E_INVALID;
+  int rc = check_hip(hipMemcpyAsync(m->master.p, params, sizeof(float) * n, hipMemcpyHostToDevice, m->st));
+  if (!rc) rc = pack(m);
+  if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  return rc;
+}
+
+int mrdino_get_params(const mrdino_model* m, float* params, int64_t n) {
+  if (!m || !params || n != m->n_params) return SAA_E_INVALID;
+  int rc = check_hip(hipMemcpyAsync(params, m->master.p, sizeof(float) * n, hipMemcpyDeviceToHost, m->st));
+  if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  return rc;
+}
+
+int mrdino_set_qoi(mrdino_model* m, const double* c, double c0) {
+  if (!m || !c || !std::isfinite(c0)) return SAA_E_INVALID;
+  const int W = m->dims.width;
+  std::vector<float> buf(W, 0.0f);
+  for (int i = 0; i < m->dims.r_u; ++i) {
+    if (!std::isfinite(c[i])) return SAA_E_INVALID;
+    buf[i] = (float)c[i];
+  }
+  m->c0 = c0;
+  int rc = check_hip(hipMemcpyAsync(m->c.p, buf.data(), sizeof(float) * W, hipMemcpyHostToDevice, m->st));
+  if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  return rc;
+}
+
+}  // extern "C"
+
+// Per-sample q and dq/dz of the surrogate for the samples installed in ctx, on
+// the context's stream.  z_dev: device, d_Z.  prec: SAA_FP32 or SAA_BF16.
+int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, double* q, double* g) {
+  const mrdino_dims& d = m->dims;
+  if (d.d_z != c->dz || d.r_m > c->K1 * c->K1) return SAA_E_MODEL;
+  if (prec != SAA_FP32 && prec != SAA_BF16) return SAA_E_INVALID;
+  saa_launch::mlp_b0eff((float*)m->b0eff.p, (const float*)m->master.p + m->off_w[0],
+                        (const float*)m->master.p + m->off_b[0], z_dev, d.width, d.r_m, d.d_z, c->st);
+  const MlpDev v = view(m);
+  const int rc = saa_launch::mlp_eval(v, prec == SAA_BF16, (const double*)c->xi.p, c->K1 * c->K1,
+                                      (const int*)c->order.p, c->N, q, g, 0, c->st);
+  if (rc) return SAA_E_DEVICE;
+  return check_hip(hipGetLastError());
+}

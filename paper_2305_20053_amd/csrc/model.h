@@ -1,0 +1,27 @@
+// Internal definition of the MR-DINO model object.
+#pragma once
+#include "ctx.h"
+#include "mlp.h"
+
+struct mrdino_model {
+  mrdino_dims dims{};
+  hipStream_t st = nullptr;
+  int kin = 0;                              // r_m padded to a multiple of 32
+  int64_t n_params = 0;
+  int64_t off_w[MLP_MAX_DEPTH + 1] = {};   // offsets of W_L, b_L in the packed parameters
+  int64_t off_b[MLP_MAX_DEPTH + 1] = {};
+  saa_rt::DevBuf master;                    // FP32 parameters
+  saa_rt::DevBuf wp[MLP_MAX_DEPTH + 1], wt[MLP_MAX_DEPTH + 1], w0z;   // BF16 MFMA operands
+  saa_rt::DevBuf bias[MLP_MAX_DEPTH + 1];   // FP32 biases padded to width
+  saa_rt::DevBuf wtn[MLP_MAX_DEPTH + 1];    // FP32 transposed weights (reference kernel)
+  saa_rt::DevBuf b0eff, c, zdev;
+  double c0 = 0.0;
+};
+
+namespace saa_model {
+int pack(mrdino_model* m);
+MlpDev view(const mrdino_model* m);
+}  // namespace saa_model
+
+// Surrogate q and dq/dz for the installed samples (device outputs, ctx stream).
+int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, double* q, double* g);
