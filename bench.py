@@ -80,6 +80,66 @@ def cpu_baseline(prob, xi, z, seconds_target=15.0):
                       f"QoI and adjoint per sample (float64 scipy), {workers} worker processes, {wall:.1f} s"}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+VEC_FP32_PEAK_TFLOPS = 157.3
+# Algorithmic FLOPs per sample of the surrogate (r_m=100, d_Z=25, width 256,
+# depth 4, r_u=200): forward 2 (125*256 + 3*256^2 + 256*200) and reverse
+# 2 (200*256 + 3*256^2 + 256*25).
+MRDINO_FLOP_PER_SAMPLE = 2 * (125 * 256 + 3 * 256 ** 2 + 256 * 200) + 2 * (200 * 256 + 3 * 256 ** 2 + 256 * 25)
+
+
+def bench_mrdino(saa, si, steps, warmup, zs, pde_value):
+    """Surrogate form at N = 65536 samples (n = 128 KL field, 16 x 16 modes):
+    BF16 MFMA kernel timed like the PDE form, FP32 reference kernel for the
+    error at the same (random Glorot) weights."""
+    import numpy as np
+    import torch
+    prob = saa.problem_medium()
+    N = 65536
+    xi = si.kl_coefficients(si.SEED_XI_LARGE, N, prob.kl_per_dim)
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    model = saa.Model(100, 25, 200, 256, 4)
+    layers = si.glorot_mlp(2313, model.widths())
+    model.set_params(np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers]))
+    model.set_qoi(0.1 * np.random.default_rng(2314).standard_normal(200), 0.01)
+    out = {}
+    for name, prec in (("bf16", saa.BF16), ("fp32", saa.FP32)):
+        opt = saa.options(prec=prec, timing=1)
+        nsteps = steps if prec == saa.BF16 else max(2, steps // 4)
+        for k in range(warmup):
+            ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model, opt=opt)
+        torch.cuda.synchronize()
+        reps = []
+        t0 = time.perf_counter()
+        for k in range(nsteps):
+            J, g, rep = ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model, opt=opt)
+            reps.append(rep)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_k = float(np.mean([r["ms_state"] for r in reps]))
+        ms_r = float(np.mean([r["ms_reduce"] for r in reps]))
+        flops = MRDINO_FLOP_PER_SAMPLE * N
+        peak = MFMA_BF16_PEAK_TFLOPS if prec == saa.BF16 else VEC_FP32_PEAK_TFLOPS
+        ach = flops / (ms_k * 1e-3) / 1e12
+        out[name] = {"value": N * nsteps / wall, "ms_per_step": 1e3 * wall / nsteps, "kernel_ms": ms_k,
+                     "reduce_ms": ms_r,
+                     "roofline": {"bound": "mfma" if prec == saa.BF16 else "alu", "achieved": ach, "peak": peak,
+                                  "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                                  "kernel": "saa_k_mlp_bf16" if prec == saa.BF16 else "saa_k_mlp_fp32",
+                                  "alg_flop_per_launch": flops}}
+    Jb, gb, _ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
+    Jf, gf, _ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32))
+    out["bf16_vs_fp32"] = {"J_rel": abs(Jb - Jf) / abs(Jf),
+                           "grad_rel": float(np.linalg.norm(gb - gf) / np.linalg.norm(gf))}
+    out["N"] = N
+    out["weights"] = "random Glorot init (throughput does not depend on the values)"
+    out["ratio_bf16_over_pde"] = out["bf16"]["value"] / pde_value
+    model.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +147,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="fp32_dc64", choices=["fp64", "fp32", "fp32_dc64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mrdino", action="store_true", help="skip the surrogate-form leg")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -174,10 +235,12 @@ def main():
                    "newton_max": reps[-1]["newton_max"]},
         "error": err,
     }
+    ctx.close()
+    if not args.no_mrdino:
+        out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs, value)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, xi, zs[0])
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -5,14 +5,18 @@
 // with the C^2 quartic smoothing s_eps of the plus function.  t* minimises
 // J_hat over t: Phi(t) = sum_i s_eps'(q_i - t) is continuous, non-increasing,
 // equals N at min(q) - eps and 0 at max(q), and t* solves Phi = N (1-beta).
-// The root is bracketed and bisected until the midpoint stops moving, then
-// polished by one Newton step kept inside the final bracket.  The gradient
+// The root is bracketed by [min q - eps, max q] and found by a safeguarded
+// Newton iteration (bisection whenever the Newton step leaves the bracket or
+// stalls), then polished by one Newton step kept inside the final bracket.
+// The gradient
 // is the chain rule (eq. (ouu_risk_gradient)) with weights
 // w_i = s_eps'(q_i - t*) / (N (1-beta)); since dJ_hat/dt = 0 at t*, no t*
 // derivative enters it.
 //
 // One workgroup does the whole reduction with a fixed summation order, so the
 // result is bitwise reproducible.
+#include <cfloat>
+
 #include "common.h"
 #include "pde.h"
 
@@ -89,19 +93,41 @@ __global__ void __launch_bounds__(CBS) saa_k_cvar(const double* q, const double*
       }
       double lo = block_min1(mn, red) - eps;
       double hi = block_max1(mx, red);
-      // A NaN or empty bracket skips the loop; a float64 bracket halves at
-      // most ~2100 times before the midpoint stops moving, so the cap never
-      // binds on finite input.
+      // Safeguarded Newton on Phi(t) = target inside the bracket [lo, hi]
+      // (Phi(lo) > target >= Phi(hi)): every pass evaluates Phi and Phi',
+      // shrinks the bracket by the sign of Phi - target, and takes the Newton
+      // step when it lands strictly inside the bracket and at least halves the
+      // previous step, else the midpoint.  It ends when the bracket stops
+      // shrinking (as the plain bisection) or the Newton step reaches the
+      // float64 rounding level of t; the polish below then takes one more
+      // Newton step.  A handful of passes instead of ~60 bisections.  A NaN or
+      // empty bracket skips the loop; the cap never binds on finite input.
+      double tc = 0.5 * (lo + hi);
+      t = tc;
+      double dx_old = hi - lo;
       for (int guard = 0; guard < 4096 && lo < hi; ++guard) {
+        double v[2] = {0.0, 0.0};
+        for (int64_t i = threadIdx.x; i < N; i += CBS) {
+          v[0] += sp_d1(q[i] - tc, eps);
+          v[1] += sp_d2(q[i] - tc, eps);
+        }
+        block_sum<2>(v, red);
+        if (v[0] > target) lo = tc;
+        else hi = tc;
         const double mid = 0.5 * (lo + hi);
+        t = mid;
         if (mid <= lo || mid >= hi) break;
-        double ph = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += CBS) ph += sp_d1(q[i] - mid, eps);
-        ph = block_sum1(ph, red);
-        if (ph > target) lo = mid;
-        else hi = mid;
+        double tn = mid;
+        if (v[1] > 0.0) {
+          const double tnew = tc + (v[0] - target) / v[1];   // Phi' = -sum s''
+          if (tnew > lo && tnew < hi && fabs(tnew - tc) <= 0.5 * dx_old) tn = tnew;
+        }
+        const double dx = fabs(tn - tc);
+        dx_old = dx;
+        tc = tn;
+        t = tn;
+        if (dx <= 4.0 * DBL_EPSILON * fabs(tn)) break;
       }
-      t = 0.5 * (lo + hi);
       double v[2] = {0.0, 0.0};
       for (int64_t i = threadIdx.x; i < N; i += CBS) {
         v[0] += sp_d1(q[i] - t, eps);

@@ -28,7 +28,7 @@
 #include "pde.h"
 
 #ifndef SAA_PDE_BLOCK
-#define SAA_PDE_BLOCK 512
+#define SAA_PDE_BLOCK 1024
 #endif
 
 namespace {
