@@ -240,6 +240,80 @@ int mrdino_get_params(const mrdino_model* model, float* params, int64_t n);
  * and c0 = |b - u_t|_M^2 - |c|^2. */
 int mrdino_set_qoi(mrdino_model* model, const double* c, double c0);
 
+/* ------------------------------------------------------------------------
+ * MR-DINO construction (Sec. 3.3-3.4): training data from the PDE form,
+ * weighted POD, derivative-informed training.
+ * ------------------------------------------------------------------------ */
+typedef struct mrdino_data mrdino_data;
+
+/* Training data for the samples installed in ctx at per-sample controls
+ * Z_dev (device, N x d_Z float64; the auxiliary control law of Sec. 3.1):
+ *  1. states u_i and control Jacobians du_i/dz by the PDE form (opt->prec,
+ *     tolerances) with d_Z linearised solves per sample (Sec. 3.4);
+ *  2. weighted POD (Sec. 3.3) from the first n_pod states: mean b, Gram
+ *     G = D^T M D of the centred snapshots, G V = V Lambda (host
+ *     eigensolver), Phi = D V_r Lambda_r^{-1/2} (M-orthonormal; each column of
+ *     V signed so its largest-magnitude entry is positive);
+ *  3. reduced data y_i = Phi^T M (u_i - b) and J_i = Phi^T M du_i/dz
+ *     (eq. (reduced_basis_derivative_equivalence)); inputs x_i = [m_r; z_i];
+ *  4. reduced-QoI terms c, c0 (see mrdino_set_qoi).
+ * 2 <= N, 1 <= r_u <= n_pod <= min(N, 8192), 1 <= r_m <= K1^2.  Device memory
+ * during construction: about 8 (d_Z + 2) N d_U bytes.  Returns SAA_E_INVALID
+ * also when the Gram matrix has rank below r_u. */
+int mrdino_data_create(saa_ctx* ctx, const double* Z_dev, int r_m, int r_u, int n_pod, const saa_options* opt,
+                       mrdino_data** out, saa_report* report);
+
+/* Free training data (NULL is ignored). */
+void mrdino_data_free(mrdino_data* data);
+
+/* Sizes and reduced-QoI terms: N, c (host, r_u), c0, Gram eigenvalues (host,
+ * n_pod, decreasing); any pointer may be NULL. */
+int mrdino_data_info(const mrdino_data* data, int64_t* N, double* c, double* c0, double* lam);
+
+/* Copy a data array to host memory: which = 0 inputs X (float, N x (r_m+d_Z)),
+ * 1 Y (float, N x r_u), 2 J (float, (N d_Z) x r_u, row i d_Z + k holds
+ * d/dz_k of sample i), 3 Phi^T (double, r_u x d_U), 4 mean state b (double,
+ * d_U).  n is the element count of the array. */
+int mrdino_data_get(const mrdino_data* data, int which, void* host, int64_t n);
+
+/* Batch-mean training loss L = 1/B sum_b |phi_b - y_b|^2 + |dphi_b/dz - J_b|_F^2
+ * (dino = 1; dino = 0 drops the Jacobian term: the L2-only MR-NO loss) of the
+ * data rows idx (host, B indices) in FP32, and its gradient (host, n_params
+ * floats, packed order; may be NULL) by the hand-written reverse pass through
+ * the forward-mode Jacobian recurrence. */
+int mrdino_loss_grad(mrdino_model* model, mrdino_data* data, const int* idx, int B, int dino, double* loss,
+                     float* grad);
+
+typedef struct mrdino_train_cfg {
+  int batch;          /* minibatch size */
+  int epochs;
+  int lr_drop_epoch;  /* from this epoch on lr_late is used (<= 0: never) */
+  double lr, lr_late; /* Adam step sizes */
+  double beta1, beta2, adam_eps;
+  int dino;           /* 1: DINO loss (MR-DINO); 0: L2-only loss (MR-NO) */
+  uint64_t seed;      /* minibatch order: splitmix64 stream, Fisher-Yates per epoch */
+} mrdino_train_cfg;
+
+/* Train the model's FP32 parameters with Adam (the optimiser of Sec. 4.2.1) on
+ * the data; every epoch visits floor(N / batch) minibatches of a fresh
+ * permutation.  Adam moments persist in the model across calls.  On return the
+ * device operands are repacked and the model's reduced-QoI terms are set from
+ * the data.  epoch_loss (host, epochs, may be NULL) receives the mean loss of
+ * each epoch; seconds (may be NULL) the device time of the loop. */
+int mrdino_train(mrdino_model* model, mrdino_data* data, const mrdino_train_cfg* cfg, double* epoch_loss,
+                 double* seconds);
+
+/* Relative reduced-space errors of the model on a data set:
+ * err_state = sqrt(sum_i |phi_i - y_i|^2 / sum_i |y_i|^2),
+ * err_jac = sqrt(sum_i |dphi_i/dz - J_i|_F^2 / sum_i |J_i|_F^2). */
+int mrdino_data_errors(mrdino_model* model, mrdino_data* data, double* err_state, double* err_jac);
+
+/* Host symmetric eigensolver used for the POD Gram matrix (Householder
+ * tridiagonalisation, implicit QL with Wilkinson shifts).  A: n x n row-major
+ * (symmetrised), w: eigenvalues in decreasing order, V: n x n row-major with
+ * the eigenvectors as columns.  Needs no GPU. */
+int saa_sym_eig(int n, const double* A, double* w, double* V);
+
 /* Per-sample status of the last saa_objective_grad, saa_per_sample or
  * saa_solve_states call on this context.  Host arrays of N entries each (any
  * may be NULL): flags (bit 1: Newton not converged, 2: an inner PCG hit

@@ -325,3 +325,122 @@ class Model:
         import numpy as np
         cc = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
         _check(self._lib.mrdino_set_qoi(self._h, cc.ctypes.data, float(c0)))
+
+
+class CTrainCfg(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr_drop_epoch", ctypes.c_int),
+                ("lr", ctypes.c_double), ("lr_late", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("adam_eps", ctypes.c_double), ("dino", ctypes.c_int),
+                ("seed", ctypes.c_uint64)]
+
+
+_SIGS.update({
+    "mrdino_data_create": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(COptions), ctypes.POINTER(_P), ctypes.POINTER(CReport)]),
+    "mrdino_data_free": (None, [_P]),
+    "mrdino_data_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "mrdino_data_get": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int64]),
+    "mrdino_loss_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]),
+    "mrdino_train": (ctypes.c_int, [_P, _P, ctypes.POINTER(CTrainCfg), _P, ctypes.POINTER(ctypes.c_double)]),
+    "mrdino_data_errors": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "saa_sym_eig": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
+})
+
+
+def sym_eig(A):
+    """Eigenvalues (decreasing) and eigenvectors (columns) of a symmetric
+    matrix by the library's host eigensolver (no GPU needed)."""
+    import numpy as np
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    _check(_load().saa_sym_eig(n, A.ctypes.data, w.ctypes.data, V.ctypes.data))
+    return w, V
+
+
+def train_cfg(batch=256, epochs=1600, lr_drop_epoch=800, lr=1e-3, lr_late=2.5e-4, dino=1, seed=2305,
+              beta1=0.9, beta2=0.999, adam_eps=1e-8) -> CTrainCfg:
+    """Adam schedule of Sec. 4.2.1 (lr 1e-3, 2.5e-4 after 800 of 1600 epochs)."""
+    return CTrainCfg(batch, epochs, lr_drop_epoch, lr, lr_late, beta1, beta2, adam_eps, dino, seed)
+
+
+class TrainData:
+    """Reduced training data built on the GPU from the PDE form (Sec. 3.3-3.4)."""
+
+    def __init__(self, ctx: Context, Z, r_m=100, r_u=200, n_pod=512, opt=None):
+        self._lib = _load()
+        opt = opt if opt is not None else options()
+        Z = Z.contiguous()
+        h = _P()
+        rep = CReport()
+        _check(self._lib.mrdino_data_create(ctx.handle, _P(_ptr(Z)), r_m, r_u, n_pod, ctypes.byref(opt),
+                                            ctypes.byref(h), ctypes.byref(rep)))
+        self._h = h
+        self.report = rep.as_dict()
+        self.r_m, self.r_u, self.n_pod, self.d_z, self.d_u = r_m, r_u, n_pod, ctx.d_z, ctx.d_u
+        n = ctypes.c_int64()
+        _check(self._lib.mrdino_data_info(h, ctypes.byref(n), None, None, None))
+        self.n = n.value
+
+    @property
+    def handle(self):
+        return self._h.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mrdino_data_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        """(c, c0, eigenvalues of the POD Gram matrix)."""
+        import numpy as np
+        c = np.zeros(self.r_u)
+        lam = np.zeros(self.n_pod)
+        c0 = ctypes.c_double()
+        _check(self._lib.mrdino_data_info(self._h, None, c.ctypes.data, ctypes.byref(c0), lam.ctypes.data))
+        return c, c0.value, lam
+
+    def get(self, which: str):
+        """'X', 'Y', 'J' (float32) or 'PhiT', 'ubar' (float64) as numpy arrays."""
+        import numpy as np
+        shapes = {"X": ((self.n, self.r_m + self.d_z), np.float32, 0), "Y": ((self.n, self.r_u), np.float32, 1),
+                  "J": ((self.n * self.d_z, self.r_u), np.float32, 2),
+                  "PhiT": ((self.r_u, self.d_u), np.float64, 3), "ubar": ((self.d_u,), np.float64, 4)}
+        shape, dt, code = shapes[which]
+        a = np.zeros(shape, dtype=dt)
+        _check(self._lib.mrdino_data_get(self._h, code, a.ctypes.data, a.size))
+        return a
+
+
+def loss_grad(model: Model, data: TrainData, idx, dino=True, want_grad=True):
+    """FP32 batch loss and gradient (packed order) of the rows idx."""
+    import numpy as np
+    ii = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+    loss = ctypes.c_double()
+    g = np.zeros(model.n_params, dtype=np.float32) if want_grad else None
+    _check(_load().mrdino_loss_grad(model._h, data.handle, ii.ctypes.data, ii.size, int(dino), ctypes.byref(loss),
+                                    g.ctypes.data if want_grad else None))
+    return loss.value, g
+
+
+def train(model: Model, data: TrainData, cfg: CTrainCfg):
+    """Run Adam training; returns (per-epoch mean loss, device seconds)."""
+    import numpy as np
+    hist = np.zeros(max(1, cfg.epochs))
+    sec = ctypes.c_double()
+    _check(_load().mrdino_train(model._h, data.handle, ctypes.byref(cfg), hist.ctypes.data, ctypes.byref(sec)))
+    return hist[:cfg.epochs], sec.value
+
+
+def data_errors(model: Model, data: TrainData):
+    """(relative reduced state error, relative reduced Jacobian error)."""
+    es, ej = ctypes.c_double(), ctypes.c_double()
+    _check(_load().mrdino_data_errors(model._h, data.handle, ctypes.byref(es), ctypes.byref(ej)))
+    return es.value, ej.value

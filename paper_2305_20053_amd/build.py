@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaa.so")
-SOURCES = ["api.cpp", "model.cpp", "pde.hip", "cvar.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "model.cpp", "train.cpp", "linalg.cpp", "pde.hip", "cvar.hip", "mlp.hip", "train.hip"]
 ARCH = os.environ.get("SAA_OFFLOAD_ARCH", "gfx950")
 
 
@@ -27,7 +27,7 @@ def build(verbose: bool = False) -> str:
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
     for src in SOURCES:
-        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(bdir, src + ".o")
         cmd = [hipcc()] + flags + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

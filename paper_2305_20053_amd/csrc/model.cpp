@@ -96,6 +96,8 @@ int pack(mrdino_model* m) {
 
 using namespace saa_model;
 
+mrdino_model::~mrdino_model() { saa_model_free_train(this); }
+
 extern "C" {
 
 int mrdino_num_params(const mrdino_dims* d, int64_t* n) {

@@ -16,7 +16,12 @@ struct mrdino_model {
   saa_rt::DevBuf wtn[MLP_MAX_DEPTH + 1];    // FP32 transposed weights (reference kernel)
   saa_rt::DevBuf b0eff, c, zdev;
   double c0 = 0.0;
+  void* train = nullptr;                    // training workspace and Adam state (train.cpp)
+  ~mrdino_model();
 };
+
+// Releases the training state of a model (train.cpp).
+void saa_model_free_train(mrdino_model* m);
 
 namespace saa_model {
 int pack(mrdino_model* m);

@@ -1,0 +1,110 @@
+"""GPU parity of MR-DINO construction against the oracle: training data
+(states, control Jacobians, weighted POD, reduced projections, QoI terms) and
+the FP32 training loss and its hand-written gradient."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2305_20053_amd as saa
+import saa_inputs as si
+from oracle import fem2d, training
+
+pytestmark = pytest.mark.gpu
+
+N, R_M, R_U, N_POD = 40, 12, 8, 30
+
+
+def _oprob(p):
+    return fem2d.Problem2D(n=p.n, n_src_per_dim=p.n_src_per_dim, src_sigma=p.src_sigma, kl_per_dim=p.kl_per_dim,
+                           kl_shift=p.kl_shift, kl_exp=p.kl_exp, kl_amp=p.kl_amp, reaction=p.reaction,
+                           u_target=p.u_target)
+
+
+@pytest.fixture(scope="module")
+def small(gpu_lib):
+    prob = saa.Problem(n=16, kl_per_dim=4, kl_amp=20.0)
+    xi = si.kl_coefficients(5001, N, 4)
+    Z = si.controls(5002, N)
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    data = saa.TrainData(ctx, torch.from_numpy(Z).cuda(), r_m=R_M, r_u=R_U, n_pod=N_POD,
+                         opt=saa.options(prec=saa.FP32_DC64))
+    ops = fem2d.operators(_oprob(prob))
+    smp = [fem2d.solve_sample(ops, xi[i], Z[i]) for i in range(N)]
+    U = np.stack([s["u"] for s in smp])
+    jac = np.stack([fem2d.control_jacobian(ops, s) for s in smp])      # N x d_U x d_Z
+    ubar, Phi, lam = training.pod(U[:N_POD], ops.M, R_U)
+    Y = training.project(Phi, ops.M, ubar, U)
+    JY = np.einsum("pr,ipk->irk", ops.M @ Phi, jac)                      # N x r_u x d_Z
+    c = Phi.T @ (ops.M_full @ (fem2d.extend(ops, ubar) - ops.t_full))[ops.interior]
+    c0 = fem2d.qoi(ops, ubar) - c @ c
+    ref = dict(ubar=ubar, Phi=Phi, lam=lam, Y=Y, JY=JY, c=c, c0=c0, xi=xi, Z=Z)
+    return prob, ctx, data, ref
+
+
+def test_training_data_matches_oracle(small):
+    prob, ctx, data, ref = small
+    ub = data.get("ubar")
+    assert np.linalg.norm(ub - ref["ubar"]) <= 1e-10 * np.linalg.norm(ref["ubar"])
+    c, c0, lam = data.info()
+    np.testing.assert_allclose(lam[:R_U], ref["lam"][:R_U], rtol=1e-8)
+    PhiT = data.get("PhiT")
+    sgn = np.sign(np.sum(PhiT * ref["Phi"].T, axis=1))
+    assert np.all(sgn == 1.0), sgn            # same sign convention as the oracle
+    np.testing.assert_allclose(PhiT, ref["Phi"].T, atol=1e-7 * np.abs(ref["Phi"]).max())
+    Y = data.get("Y")
+    np.testing.assert_allclose(Y, ref["Y"], rtol=0, atol=2e-6 * np.abs(ref["Y"]).max())
+    J = data.get("J").reshape(N, ctx.d_z, R_U).transpose(0, 2, 1)
+    np.testing.assert_allclose(J, ref["JY"], rtol=0, atol=2e-6 * np.abs(ref["JY"]).max())
+    np.testing.assert_allclose(c, ref["c"], rtol=1e-8, atol=1e-12)
+    assert abs(c0 - ref["c0"]) <= 1e-9 * abs(ref["c0"]) + 1e-13
+    X = data.get("X")
+    from oracle import surrogate
+    np.testing.assert_allclose(X[:, :R_M], surrogate.encode(ref["xi"], R_M).astype(np.float32), rtol=0, atol=0)
+    np.testing.assert_allclose(X[:, R_M:], ref["Z"].astype(np.float32), rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("dino", [True, False])
+def test_loss_and_gradient_match_oracle(small, dino):
+    prob, ctx, data, ref = small
+    widths = [R_M + ctx.d_z, 256, 256, 256, 256, R_U]
+    flat = training.flatten(si.random_mlp(5003, widths, bias_scale=0.1)).astype(np.float32)
+    model = saa.Model(R_M, ctx.d_z, R_U, 256, 4)
+    model.set_params(flat)
+    idx = np.array([3, 7, 0, 39, 12, 5, 21], dtype=np.int32)          # ragged batch
+    loss, g = saa.loss_grad(model, data, idx, dino=dino)
+    X = data.get("X").astype(np.float64)[idx]
+    Y = data.get("Y").astype(np.float64)[idx]
+    JY = data.get("J").astype(np.float64).reshape(N, ctx.d_z, R_U)[idx].transpose(0, 2, 1)
+    layers = training.unflatten(flat.astype(np.float64), widths)
+    lref, gref = training.loss_and_grad(layers, X, Y, JY, R_M, dino=dino)
+    gref = training.flatten(gref)
+    print(f"dino={dino} loss {loss:.8e} ref {lref:.8e}; grad rel "
+          f"{np.linalg.norm(g - gref) / np.linalg.norm(gref):.3e}")
+    assert abs(loss - lref) <= 1e-5 * abs(lref)
+    assert np.linalg.norm(g - gref) <= 1e-4 * np.linalg.norm(gref)
+    # per layer as well (no layer may hide behind a larger one)
+    off = 0
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        for size in (fo * fi, fo):
+            a, b = g[off:off + size], gref[off:off + size]
+            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b) + 1e-9
+            off += size
+    model.close()
+
+
+def test_training_decreases_loss_and_sets_qoi(small):
+    prob, ctx, data, ref = small
+    widths = [R_M + ctx.d_z, 256, 256, 256, 256, R_U]
+    model = saa.Model(R_M, ctx.d_z, R_U, 256, 4)
+    model.set_params(training.flatten(si.glorot_mlp(5004, widths)))
+    e0 = saa.data_errors(model, data)
+    hist, secs = saa.train(model, data, saa.train_cfg(batch=8, epochs=40, lr_drop_epoch=30, seed=11))
+    e1 = saa.data_errors(model, data)
+    print("loss", hist[0], hist[-1], "errors", e0, e1, "seconds", secs)
+    assert hist[-1] < 0.5 * hist[0]
+    assert e1[0] < e0[0] and e1[1] < e0[1]
+    # the model now evaluates q with the data's reduced QoI terms
+    q, g, _ = ctx.per_sample(ref["Z"][0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32))
+    assert np.all(np.isfinite(q.cpu().numpy())) and np.all(np.isfinite(g.cpu().numpy()))
+    model.close()
