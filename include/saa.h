@@ -257,11 +257,13 @@ typedef struct mrdino_data mrdino_data;
  *  3. reduced data y_i = Phi^T M (u_i - b) and J_i = Phi^T M du_i/dz
  *     (eq. (reduced_basis_derivative_equivalence)); inputs x_i = [m_r; z_i];
  *  4. reduced-QoI terms c, c0 (see mrdino_set_qoi).
- * 2 <= N, 1 <= r_u <= n_pod <= min(N, 8192), 1 <= r_m <= K1^2.  Device memory
- * during construction: about 8 (d_Z + 2) N d_U bytes.  Returns SAA_E_INVALID
- * also when the Gram matrix has rank below r_u. */
+ * 2 <= N, 1 <= r_u <= n_pod <= min(N, 8192), 1 <= r_m <= K1^2.  With a
+ * non-NULL `basis` (held-out data) steps 2 and 4 are skipped: its mean, POD
+ * basis and QoI terms are reused (n_pod is ignored; r_u and the problem must
+ * match).  Device memory during construction: about 8 (d_Z + 2) N d_U bytes.
+ * Returns SAA_E_INVALID also when the Gram matrix has rank below r_u. */
 int mrdino_data_create(saa_ctx* ctx, const double* Z_dev, int r_m, int r_u, int n_pod, const saa_options* opt,
-                       mrdino_data** out, saa_report* report);
+                       const mrdino_data* basis, mrdino_data** out, saa_report* report);
 
 /* Free training data (NULL is ignored). */
 void mrdino_data_free(mrdino_data* data);

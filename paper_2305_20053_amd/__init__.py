@@ -336,7 +336,7 @@ class CTrainCfg(ctypes.Structure):
 
 _SIGS.update({
     "mrdino_data_create": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                          ctypes.POINTER(COptions), ctypes.POINTER(_P), ctypes.POINTER(CReport)]),
+                                          ctypes.POINTER(COptions), _P, ctypes.POINTER(_P), ctypes.POINTER(CReport)]),
     "mrdino_data_free": (None, [_P]),
     "mrdino_data_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, ctypes.POINTER(ctypes.c_double), _P]),
     "mrdino_data_get": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int64]),
@@ -368,14 +368,18 @@ def train_cfg(batch=256, epochs=1600, lr_drop_epoch=800, lr=1e-3, lr_late=2.5e-4
 class TrainData:
     """Reduced training data built on the GPU from the PDE form (Sec. 3.3-3.4)."""
 
-    def __init__(self, ctx: Context, Z, r_m=100, r_u=200, n_pod=512, opt=None):
+    def __init__(self, ctx: Context, Z, r_m=100, r_u=200, n_pod=512, opt=None, basis=None):
+        """basis: another TrainData whose POD basis is reused (held-out data)."""
         self._lib = _load()
         opt = opt if opt is not None else options()
         Z = Z.contiguous()
         h = _P()
         rep = CReport()
         _check(self._lib.mrdino_data_create(ctx.handle, _P(_ptr(Z)), r_m, r_u, n_pod, ctypes.byref(opt),
-                                            ctypes.byref(h), ctypes.byref(rep)))
+                                            _P(basis.handle if basis is not None else None), ctypes.byref(h),
+                                            ctypes.byref(rep)))
+        if basis is not None:
+            n_pod = basis.n_pod
         self._h = h
         self.report = rep.as_dict()
         self.r_m, self.r_u, self.n_pod, self.d_z, self.d_u = r_m, r_u, n_pod, ctx.d_z, ctx.d_u

@@ -238,13 +238,18 @@ void saa_model_free_train(mrdino_model* m) {
 extern "C" {
 
 int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_pod, const saa_options* opt,
-                       mrdino_data** out, saa_report* rep) {
+                       const mrdino_data* basis, mrdino_data** out, saa_report* rep) {
   if (!c || !Z_dev || !opt || !out) return SAA_E_INVALID;
   *out = nullptr;
   const int64_t N = c->N, du = c->d_u;
   const int dz = c->dz;
-  if (N < 2 || r_m < 1 || r_m > c->K1 * c->K1 || r_u < 1 || n_pod < r_u || n_pod > N || n_pod > 8192)
+  if (basis) {
+    if (basis->d_u != du || basis->r_u != r_u || basis->d_z != dz || basis->n != c->prob.n) return SAA_E_INVALID;
+    n_pod = basis->n_pod;
+    if (N < 1 || r_m < 1 || r_m > c->K1 * c->K1) return SAA_E_INVALID;
+  } else if (N < 2 || r_m < 1 || r_m > c->K1 * c->K1 || r_u < 1 || n_pod < r_u || n_pod > N || n_pod > 8192) {
     return SAA_E_INVALID;
+  }
   hipStream_t st = c->st;
   mrdino_data* D = new (std::nothrow) mrdino_data();
   if (!D) return SAA_E_OOM;
@@ -267,6 +272,17 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   // 1. states and control Jacobians of the training samples (Sec. 3.4)
   rc = saa_solve_states(c, Z_dev, opt, (double*)U.p, nullptr, (double*)dUdz.p, rep);
   if (rc) return fail(rc);
+  if (basis) {  // held-out data: reuse the training basis and QoI terms
+    if ((rc = D->ubar.alloc(sizeof(double) * du)) || (rc = D->PhiT.alloc(sizeof(double) * r_u * du)) ||
+        (rc = MPhiT.alloc(sizeof(double) * r_u * du)))
+      return fail(rc);
+    if ((rc = check_hip(hipMemcpyAsync(D->ubar.p, basis->ubar.p, sizeof(double) * du, hipMemcpyDeviceToDevice, st))) ||
+        (rc = check_hip(hipMemcpyAsync(D->PhiT.p, basis->PhiT.p, sizeof(double) * r_u * du, hipMemcpyDeviceToDevice,
+                                       st))))
+      return fail(rc);
+    D->lam = basis->lam;
+    saa_launch::mass_rows((double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
+  } else {
   // 2. weighted POD from the first n_pod states (Sec. 3.3; the paper uses 512)
   if ((rc = D->ubar.alloc(sizeof(double) * du)) || (rc = Dm.alloc(sizeof(double) * n_pod * du)) ||
       (rc = MD.alloc(sizeof(double) * n_pod * du)) || (rc = G.alloc(sizeof(double) * n_pod * n_pod)))
@@ -303,6 +319,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   saa_launch::mass_rows((double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
   Dm.release();
   MD.release();
+  }
   // 3. reduced data: y = Phi^T M (u - ubar), J_r = Phi^T M du/dz (eq. (projected_sensitivity))
   if ((rc = Yd.alloc(sizeof(double) * N * r_u)) || (rc = JYd.alloc(sizeof(double) * N * dz * r_u))) return fail(rc);
   saa_launch::center_rows((double*)U.p, (double*)D->ubar.p, (double*)U.p, du, N, st);
