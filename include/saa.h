@@ -180,6 +180,17 @@ int saa_objective_grad(saa_ctx* ctx, const double* z, int form, const void* mode
                        const saa_options* opt, double* J, double* grad_z,
                        saa_report* report);
 
+/* Attach (holdout != NULL) or detach (NULL) a context of held-out samples of
+ * the same problem.  With a holdout attached, saa_objective_grad in the MR-DINO
+ * form with opt->fallback_tol >= 0 also evaluates the surrogate and the PDE
+ * form (FP32_DC64) on the held-out samples at the same z, sets
+ * report->err_estimate = max(|J_s - J_p| / |J_p|, |grad_s - grad_p| / |grad_p|)
+ * and, when it exceeds fallback_tol, returns the PDE form on the main samples
+ * with status SAA_W_FALLBACK and report->fallback_used = 1.  Without a holdout
+ * err_estimate is -1.  The caller keeps ownership; the holdout must stay alive
+ * while attached. */
+int saa_attach_holdout(saa_ctx* ctx, saa_ctx* holdout);
+
 /* Per-sample QoI and gradient at control z (host, d_Z): q_dev (device, N
  * float64) and g_dev (device, N x d_Z float64, row-major) receive q_i and
  * dq_i/dz for every sample (all adjoints are solved).  report may be NULL. */

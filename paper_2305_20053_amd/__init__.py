@@ -344,7 +344,14 @@ _SIGS.update({
     "mrdino_train": (ctypes.c_int, [_P, _P, ctypes.POINTER(CTrainCfg), _P, ctypes.POINTER(ctypes.c_double)]),
     "mrdino_data_errors": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "saa_sym_eig": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
+    "saa_attach_holdout": (ctypes.c_int, [_P, _P]),
 })
+
+
+def attach_holdout(ctx: Context, holdout):
+    """Attach (or, with None, detach) held-out samples for the surrogate error
+    estimate and PDE fallback of MR-DINO evaluations."""
+    _check(_load().saa_attach_holdout(ctx.handle, holdout.handle if holdout is not None else None))
 
 
 def sym_eig(A):

@@ -180,7 +180,7 @@ int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJ
   if (rep) {
     rep->t_star = t;
     rep->dJ_dt = dJdt;
-    rep->err_estimate = 0.0;
+    rep->err_estimate = -1.0;
     rep->seconds = seconds;
     rep->newton_max = s.newton_max;
     rep->n_unconverged = s.n_unconverged;
@@ -391,7 +391,7 @@ int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
   return check_hip(hipStreamSynchronize(c->st));
 }
 
-int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
+static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
                        double* J, double* grad_z, saa_report* rep) {
   if (!c || !z || !J || !grad_z) return SAA_E_INVALID;
   int rc = validate_call(c, z, form, model, opt);
@@ -440,6 +440,55 @@ int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model,
   *J = host[0];
   for (int k = 0; k < c->dz; ++k) grad_z[k] = host[2 + k];
   return fill_report(c, rep, secs, t, host[1], &tm);
+}
+
+int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
+                       double* J, double* grad_z, saa_report* rep) {
+  saa_report own{};
+  saa_report* r = rep ? rep : &own;
+  int rc = objective_grad_impl(c, z, form, model, opt, J, grad_z, r);
+  if (rc < 0 || form != SAA_FORM_MRDINO || !(opt->fallback_tol >= 0.0) || !c->holdout) return rc;
+  // Error estimate (surrogate vs PDE form on the held-out samples) and fallback.
+  saa_ctx* h = c->holdout;
+  saa_options o = *opt;
+  o.fallback_tol = -1.0;
+  o.timing = 0;
+  double Js = 0, Jp = 0, gs[SAA_MAX_DZ], gp[SAA_MAX_DZ];
+  saa_report hr{};
+  if ((rc = objective_grad_impl(h, z, SAA_FORM_MRDINO, model, &o, &Js, gs, &hr)) < 0) return rc;
+  o.prec = SAA_FP32_DC64;
+  if ((rc = objective_grad_impl(h, z, SAA_FORM_PDE, nullptr, &o, &Jp, gp, &hr)) < 0) return rc;
+  double dg = 0.0, ng = 0.0;
+  for (int k = 0; k < c->dz; ++k) {
+    dg += (gs[k] - gp[k]) * (gs[k] - gp[k]);
+    ng += gp[k] * gp[k];
+  }
+  const double e_J = std::fabs(Js - Jp) / std::fmax(std::fabs(Jp), 1e-300);
+  const double e_g = std::sqrt(dg / std::fmax(ng, 1e-300));
+  const double err = std::fmax(e_J, e_g);
+  const double t_est = r->seconds;
+  r->err_estimate = err;
+  if (err <= opt->fallback_tol) return SAA_OK;
+  // fall back to the PDE form on the main samples
+  if ((rc = objective_grad_impl(c, z, SAA_FORM_PDE, nullptr, &o, J, grad_z, r)) < 0) return rc;
+  r->err_estimate = err;
+  r->fallback_used = 1;
+  r->seconds += t_est;
+  return rc == SAA_OK ? SAA_W_FALLBACK : rc;
+}
+
+int saa_attach_holdout(saa_ctx* c, saa_ctx* holdout) {
+  if (!c || holdout == c) return SAA_E_INVALID;
+  if (holdout) {
+    const saa_problem& a = c->prob;
+    const saa_problem& b = holdout->prob;
+    if (a.dim != b.dim || a.n != b.n || a.n_src_per_dim != b.n_src_per_dim || a.src_sigma != b.src_sigma ||
+        a.kl_per_dim != b.kl_per_dim || a.kl_shift != b.kl_shift || a.kl_exp != b.kl_exp || a.kl_amp != b.kl_amp ||
+        a.reaction != b.reaction || a.u_target != b.u_target || holdout->N < 1)
+      return SAA_E_INVALID;
+  }
+  c->holdout = holdout;
+  return SAA_OK;
 }
 
 int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,

@@ -86,4 +86,5 @@ struct saa_ctx {
   saa_rt::DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
   saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
   saa_rt::PhaseTimer timer;
+  saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)
 };

@@ -62,3 +62,33 @@ def test_dino_improves_saa_gradient(trained):
     print(errs)
     for beta in (0.0, 0.5):
         assert errs[("dino", beta)][1] < errs[("no", beta)][1]
+
+
+def test_error_estimate_and_pde_fallback(trained):
+    """The estimate compares surrogate and PDE form on held-out samples; a
+    poor surrogate (MR-NO) or a tight tolerance switches to the PDE form."""
+    prob, vctx, out = trained
+    N = 300
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_HELDOUT, N, 16)).cuda())
+    saa.attach_holdout(ctx, vctx)
+    z = si.control(si.SEED_Z_EVAL[2])
+    Jpde, gpde, _ = ctx.objective_grad(z, opt=saa.options())
+    # loose tolerance: surrogate result, estimate reported
+    Js, gs, rep = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=out["dino"]["model"],
+                                     opt=saa.options(prec=saa.FP32, fallback_tol=10.0))
+    assert rep["status"] == saa.SAA_OK and rep["fallback_used"] == 0 and 0.0 < rep["err_estimate"] < 10.0
+    Jv, gv, _ = vctx.objective_grad(z, form=saa.FORM_MRDINO, model=out["dino"]["model"], opt=saa.options(prec=saa.FP32))
+    Jvp, gvp, _ = vctx.objective_grad(z, opt=saa.options())
+    manual = max(abs(Jv - Jvp) / abs(Jvp), np.linalg.norm(gv - gvp) / np.linalg.norm(gvp))
+    assert abs(rep["err_estimate"] - manual) <= 1e-9 * manual
+    # tight tolerance: the PDE form on the main samples, flagged
+    Jf, gf, rep = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=out["no"]["model"],
+                                     opt=saa.options(prec=saa.FP32, fallback_tol=1e-6))
+    assert rep["status"] == saa.SAA_W_FALLBACK and rep["fallback_used"] == 1
+    assert Jf == Jpde and np.array_equal(gf, gpde)
+    # detached: no estimate
+    saa.attach_holdout(ctx, None)
+    _, _, rep = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=out["no"]["model"], opt=saa.options(prec=saa.FP32))
+    assert rep["err_estimate"] == -1.0 and rep["fallback_used"] == 0
+    ctx.close()
