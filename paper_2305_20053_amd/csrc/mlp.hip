@@ -42,19 +42,25 @@ __device__ __forceinline__ float dgelu_f(float a) {
 // leading dimension ld.  The A fragments of step ks + 1 are loaded while the
 // MFMAs of step ks run (two register stages); scheduling barriers keep the
 // compiler from hoisting further loads.
+//
+// Operands are stored fragment-major: the 16 x 32 fragment (mt, ks) of a
+// matrix with ld columns occupies 1 KB at ((mt * ld/32 + ks) * 64 + lane) * 8,
+// lane 16 g + c holding row 16 mt + c, columns 32 ks + 8 g .. + 8, so every
+// wave-wide fragment load is one contiguous 1 KB block.
 template <int MT, int NK, int KSA>
 __device__ __forceinline__ void mfma_gemm(const __bf16* w, int ld, const bf16x8 (&hb)[KSA], f32x4 (&acc)[MT],
                                           int c16, int g) {
   bf16x8 a[2][MT];
-  const __bf16* base = w + (int64_t)c16 * ld + 8 * g;
+  const int nks = ld >> 5;
+  const __bf16* base = w + (int64_t)(16 * g + c16) * 8;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) a[0][mt] = *(const bf16x8*)(base + (int64_t)16 * mt * ld);
+  for (int mt = 0; mt < MT; ++mt) a[0][mt] = *(const bf16x8*)(base + (int64_t)(mt * nks) * 512);
 #pragma unroll
   for (int ks = 0; ks < NK; ++ks) {
     if (ks + 1 < NK) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        a[(ks + 1) & 1][mt] = *(const bf16x8*)(base + (int64_t)16 * mt * ld + 32 * (ks + 1));
+        a[(ks + 1) & 1][mt] = *(const bf16x8*)(base + (int64_t)(mt * nks + ks + 1) * 512);
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -69,25 +75,41 @@ __device__ __forceinline__ void mfma_gemm(const __bf16* w, int ld, const bf16x8 
 // Weight packing (after every change of the FP32 master parameters)
 // ---------------------------------------------------------------------------
 
-// Forward BF16 operand: dst[m][k] (rows x cols) = W[m][kperm(k)] (or natural
-// order when `natural`), zero outside the source.  W is src_rows x src_ld.
+// Position t of a fragment-major stored rows x cols operand (see mfma_gemm)
+// -> logical (row m, column k).
+__device__ __forceinline__ void frag_pos(int64_t t, int cols, int& m, int& k) {
+  const int e = (int)(t & 7);
+  const int ln = (int)((t >> 3) & 63);
+  const int64_t f = t >> 9;                // fragment index mt * (cols/32) + ks
+  const int nks = cols >> 5;
+  const int mt = (int)(f / nks), ks = (int)(f % nks);
+  m = 16 * mt + (ln & 15);
+  k = 32 * ks + 8 * (ln >> 4) + e;
+}
+
+// Forward BF16 operand (fragment-major): logical [m][k] = W[m][kperm(k)] (or
+// natural order when `natural`), zero outside the source.  W is src_rows x
+// src_ld.  rows % 16 == 0, cols % 32 == 0.
 __global__ void saa_k_pack_fwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
                                int src_ld, int natural) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)rows * cols) return;
-  const int m = (int)(t / cols), k = (int)(t % cols);
+  int m, k;
+  frag_pos(t, cols, m, k);
   const int ks = natural ? k : kperm(k);
   float v = 0.0f;
   if (m < src_rows && ks < src_cols) v = src[(int64_t)m * src_ld + ks];
   dst[t] = (__bf16)v;
 }
 
-// Backward BF16 operand: dst[m][k] = W[kperm(k)][col0 + m], zero outside.
+// Backward BF16 operand (fragment-major): logical [m][k] = W[kperm(k)][col0 + m],
+// zero outside.
 __global__ void saa_k_pack_bwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
                                int src_ld, int col0) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)rows * cols) return;
-  const int m = (int)(t / cols), k = (int)(t % cols);
+  int m, k;
+  frag_pos(t, cols, m, k);
   const int o = kperm(k);
   float v = 0.0f;
   if (o < src_rows && m < src_cols) v = src[(int64_t)o * src_ld + col0 + m];

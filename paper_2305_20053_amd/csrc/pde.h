@@ -36,6 +36,15 @@ struct MgBufs {
   TS* cr;  // CG residual
   TS* cp;  // CG search direction
   TS* cq;  // A p
+  // LDS copies of the coarse levels (1..L-1) of WE, WN, D, X, B, T, stacked
+  // like the global arrays from off[1] on; null when the coarse levels live
+  // in HBM.
+  TS* lWE = nullptr;
+  TS* lWN = nullptr;
+  TS* lD = nullptr;
+  TS* lX = nullptr;
+  TS* lB = nullptr;
+  TS* lT = nullptr;
 };
 
 // Solver controls passed to the persistent kernels.

@@ -127,14 +127,20 @@ struct Level {
   const TS* D;
 };
 
+// Array `gbase` (level-stacked, HBM) at level l, or its LDS copy for l >= 1.
+template <typename TS>
+__device__ __forceinline__ TS* at_level(TS* gbase, TS* lbase, const PdeGeo& g, int l) {
+  return (l > 0 && lbase) ? lbase + (g.off[l] - g.off[1]) : gbase + g.off[l];
+}
+
 template <typename TS>
 __device__ __forceinline__ Level<TS> level(const PdeGeo& g, const MgBufs<TS>& m, int l) {
   Level<TS> L;
   L.n = g.n[l];
   L.np = g.n[l] + 1;
-  L.WE = m.WE + g.off[l];
-  L.WN = m.WN + g.off[l];
-  L.D = m.D + g.off[l];
+  L.WE = at_level(m.WE, m.lWE, g, l);
+  L.WN = at_level(m.WN, m.lWN, g, l);
+  L.D = at_level(m.D, m.lD, g, l);
   return L;
 }
 
@@ -205,29 +211,29 @@ __device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int n
   const int L = g.L;
   for (int l = 0; l < L - 1; ++l) {
     const Level<TS> lv = level(g, m, l);
-    const TS* b = (l == 0) ? b0 : m.B + g.off[l];
-    TS* x = m.X + g.off[l];
-    TS* t = m.T + g.off[l];
+    const TS* b = (l == 0) ? b0 : at_level(m.B, m.lB, g, l);
+    TS* x = at_level(m.X, m.lX, g, l);
+    TS* t = at_level(m.T, m.lT, g, l);
     for (int s = 0; s < nu; ++s) {
       gs_half(lv, b, x, 0, s == 0);
       gs_half(lv, b, x, 1, false);
     }
     residual_level(lv, b, x, t);
-    restrict_level(g.n[l], t, g.n[l + 1], m.B + g.off[l + 1]);
+    restrict_level(g.n[l], t, g.n[l + 1], at_level(m.B, m.lB, g, l + 1));
   }
   {  // coarsest level: a single unknown at node (1,1) of the n = 2 grid
     const int l = L - 1;
     if (threadIdx.x == 0) {
       const int p = 1 * (g.n[l] + 1) + 1;
-      m.X[g.off[l] + p] = m.B[g.off[l] + p] / m.D[g.off[l] + p];
+      at_level(m.X, m.lX, g, l)[p] = at_level(m.B, m.lB, g, l)[p] / at_level(m.D, m.lD, g, l)[p];
     }
     __syncthreads();
   }
   for (int l = L - 2; l >= 0; --l) {
     const Level<TS> lv = level(g, m, l);
-    const TS* b = (l == 0) ? b0 : m.B + g.off[l];
-    TS* x = m.X + g.off[l];
-    prolong_add(g.n[l], x, g.n[l + 1], m.X + g.off[l + 1]);
+    const TS* b = (l == 0) ? b0 : at_level(m.B, m.lB, g, l);
+    TS* x = at_level(m.X, m.lX, g, l);
+    prolong_add(g.n[l], x, g.n[l + 1], at_level(m.X, m.lX, g, l + 1));
     for (int s = 0; s < nu; ++s) {
       gs_half(lv, b, x, 1, false);
       gs_half(lv, b, x, 0, false);
@@ -250,13 +256,35 @@ __device__ void build_diagonals(const PdeGeo& g, const MgBufs<TS>& m, const TW* 
   });
   __syncthreads();
   for (int l = 0; l < g.L - 1; ++l) {
-    restrict_level(g.n[l], m.T + g.off[l], g.n[l + 1], m.T + g.off[l + 1]);
-    const int64_t o = g.off[l + 1];
+    TS* tc = at_level(m.T, m.lT, g, l + 1);
+    TS* dc = at_level(m.D, m.lD, g, l + 1);
+    const TS* kd = m.KD + g.off[l + 1];
+    restrict_level(g.n[l], at_level(m.T, m.lT, g, l), g.n[l + 1], tc);
     for_nodes(g.n[l + 1], [&](int p, int i, int j) {
-      if (interior(i, j, g.n[l + 1])) m.D[o + p] = m.KD[o + p] + m.T[o + p];
+      if (interior(i, j, g.n[l + 1])) dc[p] = kd[p] + tc[p];
     });
     __syncthreads();
   }
+}
+
+// Move the coarse levels (1..L-1) of one sample into LDS: zero WE, WN, D, X,
+// B, T there (boundary entries stay zero) and copy the edge weights.
+template <typename TS>
+__device__ void setup_lds_levels(const PdeGeo& g, MgBufs<TS>& m, TS* lds) {
+  const int64_t cs = g.lstride - g.off[1];
+  m.lWE = lds;
+  m.lWN = lds + cs;
+  m.lD = lds + 2 * cs;
+  m.lX = lds + 3 * cs;
+  m.lB = lds + 4 * cs;
+  m.lT = lds + 5 * cs;
+  for (int64_t i = threadIdx.x; i < 6 * cs; i += BS) lds[i] = (TS)0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < cs; i += BS) {
+    m.lWE[i] = m.WE[g.off[1] + i];
+    m.lWN[i] = m.WN[g.off[1] + i];
+  }
+  __syncthreads();
 }
 
 // Preconditioned CG on A x = b with b in m.cr (overwritten by the residual),
@@ -539,7 +567,7 @@ __global__ void __launch_bounds__(BS) saa_k_hierarchy(PdeGeo g, const double* em
 // the QoI q = (u - ut)^T M (u - ut) over all nodes.  One block per sample.
 // Z: controls, sample s uses Z + s * z_stride (z_stride = 0: shared control).
 // ---------------------------------------------------------------------------
-template <typename TW, typename TS>
+template <typename TW, typename TS, bool LDSC>
 __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, const double* Z,
                                                   int64_t z_stride, const double* em_all, TW* u_all,
                                                   TW* f_all, MgBufs<TS> all, SolveParams sp, double* q_out,
@@ -552,7 +580,11 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
   const double* em = em_all + s * g.nodes;
   TW* u = u_all + s * g.nodes;
   TW* f = f_all + s * g.nodes;
-  const MgBufs<TS> m = sample_bufs(all, g, s);
+  MgBufs<TS> m = sample_bufs(all, g, s);
+  if (LDSC) {
+    extern __shared__ char dyn_lds[];
+    setup_lds_levels(g, m, (TS*)dyn_lds);
+  }
   if (threadIdx.x < g.dz) zs[threadIdx.x] = Z[s * z_stride + threadIdx.x];
   __syncthreads();
   const double c = g.r * g.h2;
@@ -632,7 +664,7 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
 // block per sample.  Samples with q_i <= t (zero CVaR weight: s_eps'(q - t) = 0)
 // are skipped unless `all`; their g row is written as 0.
 // ---------------------------------------------------------------------------
-template <typename TW, typename TS>
+template <typename TW, typename TS, bool LDSC>
 __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, const double* em_all,
                                                     const TW* u_all, TW* b_all, TW* lam_all, MgBufs<TS> all,
                                                     SolveParams sp, const double* q, const double* tstar,
@@ -655,7 +687,11 @@ __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, 
   const TW* u = u_all + s * g.nodes;
   TW* b = b_all + s * g.nodes;
   TW* lam = lam_all + s * g.nodes;
-  const MgBufs<TS> m = sample_bufs(all, g, s);
+  MgBufs<TS> m = sample_bufs(all, g, s);
+  if (LDSC) {
+    extern __shared__ char dyn_lds[];
+    setup_lds_levels(g, m, (TS*)dyn_lds);
+  }
   const double h2 = g.h2;
   for_nodes(n, [&](int p, int i, int j) {
     double v = 0.0;
@@ -702,7 +738,7 @@ __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, 
 // state's multigrid hierarchy (Sec. 3.4, eq. (projected_sensitivity)).
 // Output dudz[s][k][interior index] in float64.  One block per sample.
 // ---------------------------------------------------------------------------
-template <typename TW, typename TS>
+template <typename TW, typename TS, bool LDSC>
 __global__ void __launch_bounds__(BS) saa_k_linearized(PdeGeo g, const double* FT, const double* em_all,
                                                        const TW* u_all, TW* b_all, TW* x_all, MgBufs<TS> all,
                                                        SolveParams sp, double* dudz, int* lin_out, int* flag_out,
@@ -716,7 +752,11 @@ __global__ void __launch_bounds__(BS) saa_k_linearized(PdeGeo g, const double* F
   const TW* u = u_all + s * g.nodes;
   TW* b = b_all + s * g.nodes;
   TW* x = x_all + s * g.nodes;
-  const MgBufs<TS> m = sample_bufs(all, g, s);
+  MgBufs<TS> m = sample_bufs(all, g, s);
+  if (LDSC) {
+    extern __shared__ char dyn_lds[];
+    setup_lds_levels(g, m, (TS*)dyn_lds);
+  }
   build_diagonals<TW, TS>(g, m, u);
   int lin = 0;
   bool ok_all = true;
@@ -756,6 +796,21 @@ __global__ void saa_k_interior(const TW* u_all, double* out, int n, int64_t N) {
 // ---------------------------------------------------------------------------
 namespace saa_launch {
 
+// Dynamic LDS for the coarse levels (6 arrays), or 0 when they stay in HBM:
+// used for FP32 solver arrays when they fit next to the static reduction
+// buffers in the 160 KB of a workgroup.
+template <typename TS>
+static size_t coarse_lds_bytes(const PdeGeo& g) {
+  if (sizeof(TS) != 4 || g.L < 2) return 0;
+  const size_t b = 6 * (size_t)(g.lstride - g.off[1]) * sizeof(TS);
+  const size_t static_lds = (size_t)SAA_MAX_DZ * (BS / SAA_WAVE) * sizeof(double) + SAA_MAX_DZ * sizeof(double);
+  return (b + static_lds <= 150 * 1024) ? b : 0;
+}
+
+static bool set_lds_attr(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
 void sine_table(double* S, int K1, int n, hipStream_t st) {
   const int total = K1 * (n + 1);
   saa_k_sine_table<<<(total + 255) / 256, 256, 0, st>>>(S, K1, n);
@@ -789,22 +844,44 @@ template <typename TW, typename TS>
 void state(const PdeGeo& g, const double* FT, const double* Z, int64_t z_stride, const double* em, TW* u, TW* f,
            const MgBufs<TS>& b, const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N,
            hipStream_t st) {
-  saa_k_state<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, FT, Z, z_stride, em, u, f, b, sp, q, newton, lin, flag, N);
+  const size_t lds = coarse_lds_bytes<TS>(g);
+  if (lds) {
+    static bool attr = set_lds_attr((const void*)saa_k_state<TW, TS, true>, lds);
+    (void)attr;
+    saa_k_state<TW, TS, true><<<(unsigned)N, BS, lds, st>>>(g, FT, Z, z_stride, em, u, f, b, sp, q, newton, lin, flag, N);
+  } else {
+    saa_k_state<TW, TS, false><<<(unsigned)N, BS, 0, st>>>(g, FT, Z, z_stride, em, u, f, b, sp, q, newton, lin, flag, N);
+  }
 }
 
 template <typename TW, typename TS>
 void adjoint(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* lam,
              const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int all_samples,
              double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st) {
-  saa_k_adjoint<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, all_samples, gout,
-                                                    lin, flag, did, N);
+  const size_t lds = coarse_lds_bytes<TS>(g);
+  if (lds) {
+    static bool attr = set_lds_attr((const void*)saa_k_adjoint<TW, TS, true>, lds);
+    (void)attr;
+    saa_k_adjoint<TW, TS, true><<<(unsigned)N, BS, lds, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, all_samples,
+                                                              gout, lin, flag, did, N);
+  } else {
+    saa_k_adjoint<TW, TS, false><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, all_samples,
+                                                               gout, lin, flag, did, N);
+  }
 }
 
 template <typename TW, typename TS>
 void linearized(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* x,
                 const MgBufs<TS>& b, const SolveParams& sp, double* dudz, int* lin, int* flag, int64_t N,
                 hipStream_t st) {
-  saa_k_linearized<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, x, b, sp, dudz, lin, flag, N);
+  const size_t lds = coarse_lds_bytes<TS>(g);
+  if (lds) {
+    static bool attr = set_lds_attr((const void*)saa_k_linearized<TW, TS, true>, lds);
+    (void)attr;
+    saa_k_linearized<TW, TS, true><<<(unsigned)N, BS, lds, st>>>(g, FT, em, u, bvec, x, b, sp, dudz, lin, flag, N);
+  } else {
+    saa_k_linearized<TW, TS, false><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, x, b, sp, dudz, lin, flag, N);
+  }
 }
 
 template <typename TW>
