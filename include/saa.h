@@ -106,7 +106,9 @@ typedef struct saa_options {
                           1e-5 with FP32 state).  An iteration also stops once
                           its updates stop contracting below 1e-4 relative
                           (rounding floor).  Inner PCG tolerances adapt to the
-                          predicted error, never tighter than lin_rtol. */
+                          predicted error, never tighter than lin_rtol.
+                          Adjoint and linearised solves use
+                          max(newton_tol, 1e-11) with FP64 state. */
   double lin_rtol;     /* relative residual of each inner PCG solve; <= 0:
                           default 1e-6 (1e-5 with FP32 state) */
   int max_newton;      /* <= 0: default 30 */

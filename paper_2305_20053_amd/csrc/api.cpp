@@ -43,7 +43,9 @@ template <typename TW>
 void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st);
 void cvar(const double* q, const double* g, int64_t N, int dz, double beta, double eps, double alpha,
           const double* z, int t_mode, double t_in, int phase, double* tstar, double* out, const int* newton,
-          const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, hipStream_t st);
+          const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
+          hipStream_t st);
+size_t cvar_work_bytes();
 }  // namespace saa_launch
 
 #include "ctx.h"
@@ -92,6 +94,9 @@ SolveParams solve_params(const saa_options* o, bool fp32_state) {
   SolveParams sp;
   sp.newton_tol = o->newton_tol > 0 ? o->newton_tol : (fp32_state ? 1e-5 : 1e-13);
   sp.lin_rtol = o->lin_rtol > 0 ? o->lin_rtol : (fp32_state ? 1e-5 : 1e-6);
+  // adjoint / linearised solves feed gradients and Jacobians only: 1e-11 is
+  // two orders below the 1e-9 gradient target
+  sp.adj_tol = fp32_state ? sp.newton_tol : std::fmax(sp.newton_tol, 1e-11);
   sp.max_newton = o->max_newton > 0 ? o->max_newton : 30;
   sp.max_lin = o->max_lin > 0 ? o->max_lin : 200;
   sp.max_dc = o->max_dc > 0 ? o->max_dc : 10;
@@ -319,6 +324,7 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!rc) rc = c->zdev.alloc(SAA_MAX_DZ * sizeof(double));
   if (!rc) rc = c->out.alloc((2 + SAA_MAX_DZ) * sizeof(double));
   if (!rc) rc = c->stats.alloc(sizeof(CvarStats));
+  if (!rc) rc = c->cwork.alloc(saa_launch::cvar_work_bytes());
   if (!rc) rc = c->timer.create();
   if (!rc) rc = c->order.alloc(sizeof(int) * (size_t)c->K1 * c->K1);
   if (rc) {
@@ -408,14 +414,14 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     tm.mark(c->st, 1);
     saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
                      (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, (double*)c->tstar.p, (double*)c->out.p,
-                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->st);
+                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->cwork.p, c->st);
     tm.mark(c->st, 2);
     if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
     tm.mark(c->st, 3);
     saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
                      (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, (double*)c->tstar.p, (double*)c->out.p,
                      (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
-                     c->stats.p, c->st);
+                     c->stats.p, c->cwork.p, c->st);
   } else {
     // surrogate: q and dq/dz of every sample in one fused launch, then the reduction
     if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p,
@@ -426,7 +432,7 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     tm.mark(c->st, 3);
     saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
                      (double*)c->zdev.p, opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p,
-                     nullptr, nullptr, nullptr, nullptr, nullptr, c->stats.p, c->st);
+                     nullptr, nullptr, nullptr, nullptr, nullptr, c->stats.p, c->cwork.p, c->st);
   }
   tm.mark(c->st, 4);
   if ((rc = check_hip(hipGetLastError()))) return rc;
@@ -507,13 +513,14 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
       return rc;
     saa_launch::cvar((double*)c->q.p, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p,
                      opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p,
-                     (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats.p, c->st);
+                     (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats.p,
+                     c->cwork.p, c->st);
   } else {
     if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, q_dev, g_dev)))
       return rc;
     saa_launch::cvar(q_dev, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p, opt->t_mode,
                      opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, nullptr, nullptr, nullptr, nullptr,
-                     nullptr, c->stats.p, c->st);
+                     nullptr, c->stats.p, c->cwork.p, c->st);
   }
   if ((rc = check_hip(hipGetLastError()))) return rc;
   double t = 0, host[2];
@@ -562,7 +569,7 @@ int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, do
   // stats only (phase 0)
   saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, 0.0, 1.0, 0.0, (double*)c->zdev.p, 1, 0.0, 0,
                    (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
-                   (int*)c->lin_adj.p, nullptr, c->stats.p, c->st);
+                   (int*)c->lin_adj.p, nullptr, c->stats.p, c->cwork.p, c->st);
   if ((rc = check_hip(hipGetLastError()))) return rc;
   if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -84,6 +84,7 @@ struct saa_ctx {
   saa_rt::MgStore<float> mg32;
   saa_rt::DevBuf u, f, lam;   // PDE-form node vectors (sized for float64; allocated at first use)
   saa_rt::DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
+  saa_rt::DevBuf cwork;       // CVaR reduction workspace (partials, probe histograms, active set)
   saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
   saa_rt::PhaseTimer timer;
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)

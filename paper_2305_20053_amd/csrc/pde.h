@@ -50,6 +50,7 @@ struct MgBufs {
 // Solver controls passed to the persistent kernels.
 struct SolveParams {
   double newton_tol;  // stop when |update| <= newton_tol |iterate|
+  double adj_tol;     // same for the adjoint / linearised defect corrections
   double lin_rtol;    // inner PCG relative residual
   int max_newton;
   int max_lin;

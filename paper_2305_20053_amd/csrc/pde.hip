@@ -418,7 +418,7 @@ __device__ int dc_solve(const PdeGeo& g, const MgBufs<TS>& m, const SolveParams&
       *ok = false;
       break;
     }
-    if (outer_converged(ctl, v[0], v[1], sp.newton_tol, sp.lin_rtol)) break;
+    if (outer_converged(ctl, v[0], v[1], sp.adj_tol, sp.lin_rtol)) break;
     // new defect b - A x in precision TW
     for_nodes(n, [&](int p, int i, int j) {
       if (interior(i, j, n)) {
