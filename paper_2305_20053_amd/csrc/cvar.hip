@@ -18,24 +18,24 @@
 //     NP equispaced probes (exact binary search over the probe values) and
 //     the bracket shrinks about NP/2-fold, until it is a few eps wide;
 //  3. compact (G workgroups): samples in (lo, hi + eps) are the only ones
-//     whose s_eps' varies inside the bracket; they are gathered into a small
-//     "active" set and the samples at or above hi + eps are counted (their
-//     s_eps' is 1 throughout the bracket);
-//  4. solve (1 workgroup): the active set is sorted in LDS (a fixed summation
-//     order) and a safeguarded Newton iteration on
+//     whose s_eps' varies inside the bracket; each workgroup gathers its
+//     "active" samples in index order and counts those at or above hi + eps
+//     (their s_eps' is 1 throughout the bracket);
+//  4. solve (1 workgroup): the active samples are concatenated in workgroup
+//     order in LDS and a safeguarded Newton iteration on
 //         Phi(t) = #{q >= hi + eps} + sum_active s_eps'(q_a - t)
 //     runs inside the bracket (bisection when a step leaves it or stalls),
 //     followed by one polish step.  If the active set overflows its capacity
 //     the same iteration runs over all N samples.
-// Every workgroup recomputes the bracket from the previous launches' results
-// with the same arithmetic, so all of them agree on it without a grid barrier.
+// Every wave recomputes the bracket from the previous launches' results with
+// the same arithmetic, so all of them agree on it without a grid barrier.
 // For beta = 0 (target = N) every t <= min(q) - eps is a minimiser with the
 // same J and weights; t* = min(q) - eps is returned.
 //
 // The value and gradient (eq. (ouu_risk_gradient), chain rule with weights
 // w_i = s_eps'(q_i - t*) / (N (1-beta)); dJ_hat/dt = 0 at t*, so no t*
 // derivative enters) are per-workgroup partial sums over contiguous chunks,
-// reduced in chunk order by one workgroup.  All sums have a fixed order, so
+// reduced in chunk order by one workgroup.  Every sum has a fixed order, so
 // results are bitwise reproducible.
 #include <cfloat>
 
@@ -46,20 +46,26 @@ namespace {
 
 constexpr int RBS = 256;          // threads of the multi-workgroup passes
 constexpr int SBS = 1024;         // threads of the single-workgroup kernels
-constexpr int NP = 64;            // probes per bracketing pass
+constexpr int NP = 64;            // probes per bracketing pass (one per lane)
 constexpr int NB = NP + 1;        // histogram bins: number of probes below q
 constexpr int PASSES = 4;         // bracketing passes (shrink ~32x each)
 constexpr int CAP = 8192;         // active-set capacity (doubles in LDS)
+constexpr int SEG = 2048;         // active-set capacity per workgroup
 constexpr int GMAX = 256;         // workgroups of the multi-workgroup passes
+constexpr int TILE = 4 * RBS;     // samples per compaction tile
 constexpr int PSTRIDE = 2 + SAA_MAX_DZ;
+constexpr int WAVE_NEWTON = 256;  // active sets up to this size are solved by one wave
+static_assert(NP == SAA_WAVE, "one probe per lane");
+static_assert(SAA_MAX_DZ <= SAA_WAVE, "one gradient component per lane");
 
 // Device workspace, carved from one allocation of cvar_work_bytes().
 struct CvarWork {
-  double* mm;                  // [GMAX][2] partial min / max of q
-  unsigned long long* hist;    // [PASSES][2][NB] probe histograms
-  unsigned long long* act;     // [0] active-set size, [1] #{q >= hi + eps}
-  double* aval;                // [CAP] active q values
-  double* part;                // [GMAX][PSTRIDE] partial sums of the value / gradient
+  double* mm;     // [GMAX][2] partial min / max of q
+  double* part;   // [GMAX][PSTRIDE] partial sums of the value / gradient
+  double* aval;   // [GMAX][SEG] active q values per workgroup, in index order
+  int* hist;      // [PASSES][2][NB] probe histograms
+  int* nact;      // [GMAX] active samples per workgroup
+  int* nabove;    // [GMAX] samples at or above hi + eps per workgroup
 };
 
 __device__ __forceinline__ double sp_val(double x, double e) {
@@ -99,36 +105,39 @@ struct Bracket {
   bool live;   // the bracketing passes are still refining it
 };
 
-// Bracket after `passes` bracketing passes, recomputed from the workspace.
-// Called by every thread of a block; all threads get the same result.
-// `sh` holds 2 NB counts of LDS, `red` the block_sum scratch.
-__device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double eps, double target, double N,
-                                 double* red, unsigned long long* sh) {
+// Bracket after `passes` bracketing passes, recomputed from the workspace by
+// each wave on its own (lane j evaluates probe j); every wave of every
+// workgroup gets the same result.  No LDS, no barrier.
+__device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double eps, double target, double N) {
+  const int lane = threadIdx.x & (SAA_WAVE - 1);
   double mn = INFINITY, mx = -INFINITY;
-  for (int b = threadIdx.x; b < G; b += blockDim.x) {
+  for (int b = lane; b < G; b += SAA_WAVE) {
     mn = fmin(mn, w.mm[2 * b]);
     mx = fmax(mx, w.mm[2 * b + 1]);
   }
   Bracket br;
-  br.lo = block_min1(mn, red) - eps;
-  br.hi = block_max1(mx, red);
+  br.lo = wave_min(mn) - eps;
+  br.hi = wave_max(mx);
   br.live = target < N;
   for (int p = 0; p < passes; ++p) {
     br.live = br.live && (br.hi - br.lo > 4.0 * eps);
     if (!br.live) break;
-    for (int k = threadIdx.x; k < 2 * NB; k += blockDim.x) sh[k] = w.hist[(size_t)p * 2 * NB + k];
-    __syncthreads();
-    const double step = (br.hi - br.lo) / (NP + 1);
-    unsigned long long c1 = 0, c2 = 0;   // #{q > probe j}, #{q > probe j + eps}
-    double nlo = br.lo, nhi = br.hi;
-    for (int j = NP - 1; j >= 0; --j) {
-      c1 += sh[j + 1];
-      c2 += sh[NB + j + 1];
-      const double pj = probe(br.lo, step, j);
-      if ((double)c2 > target && pj > nlo) nlo = pj;
-      if ((double)c1 <= target && pj < nhi) nhi = pj;
+    const int* h = w.hist + p * 2 * NB;
+    // suffix sums over the bins above probe `lane`: #{q > probe}, #{q > probe + eps}
+    int c1 = h[lane + 1], c2 = h[NB + lane + 1];
+#pragma unroll
+    for (int off = 1; off < SAA_WAVE; off <<= 1) {
+      const int y1 = __shfl_down(c1, off, SAA_WAVE);
+      const int y2 = __shfl_down(c2, off, SAA_WAVE);
+      if (lane + off < SAA_WAVE) {
+        c1 += y1;
+        c2 += y2;
+      }
     }
-    __syncthreads();
+    const double step = (br.hi - br.lo) / (NP + 1);
+    const double pj = probe(br.lo, step, lane);
+    const double nlo = wave_max((double)c2 > target ? pj : br.lo);
+    const double nhi = wave_min((double)c1 <= target ? pj : br.hi);
     if (!(nhi - nlo < br.hi - br.lo)) {
       br.live = false;
       break;
@@ -146,7 +155,7 @@ __device__ __forceinline__ void chunk_of(int64_t N, int G, int64_t& i0, int64_t&
 }
 
 // Safeguarded Newton for Phi(t) = target inside [lo, hi]; phi(t, v) returns
-// v[0] = Phi(t), v[1] = -Phi'(t) = sum s_eps''.  Block-uniform.
+// v[0] = Phi(t), v[1] = -Phi'(t) = sum s_eps''.  Uniform over its callers.
 template <class F>
 __device__ double newton_in_bracket(double lo, double hi, double target, F phi) {
   double tc = 0.5 * (lo + hi);
@@ -180,9 +189,32 @@ __device__ double newton_in_bracket(double lo, double hi, double target, F phi) 
   return t;
 }
 
+// Exclusive prefix sum over the block of one int per thread (thread order);
+// returns the block total.  `sh` holds blockDim.x / 64 ints of LDS.
+__device__ int block_scan(int v, int* excl, int* sh) {
+  const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
+  const int nw = blockDim.x / SAA_WAVE;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < SAA_WAVE; off <<= 1) {
+    const int y = __shfl_up(x, off, SAA_WAVE);
+    if (lane >= off) x += y;
+  }
+  if (lane == SAA_WAVE - 1) sh[wid] = x;
+  __syncthreads();
+  int base = 0, total = 0;
+  for (int k = 0; k < nw; ++k) {
+    base += k < wid ? sh[k] : 0;
+    total += sh[k];
+  }
+  __syncthreads();
+  *excl = base + x - v;
+  return total;
+}
+
 }  // namespace
 
-// 1. partial min / max per workgroup; workgroup 0 clears the counters.
+// 1. partial min / max per workgroup; workgroup 0 clears the histograms.
 __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_t N, CvarWork w, int G) {
   __shared__ double red[RBS / SAA_WAVE];
   int64_t i0, i1;
@@ -198,170 +230,245 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_
     w.mm[2 * blockIdx.x] = mn;
     w.mm[2 * blockIdx.x + 1] = mx;
   }
-  if (blockIdx.x == 0) {
+  if (blockIdx.x == 0)
     for (int k = threadIdx.x; k < PASSES * 2 * NB; k += RBS) w.hist[k] = 0;
-    if (threadIdx.x < 2) w.act[threadIdx.x] = 0;
-  }
 }
 
 // 2. bracketing pass p: probe histograms of this workgroup's chunk.
 __global__ void __launch_bounds__(RBS) saa_k_cvar_probe(const double* q, int64_t N, CvarWork w, int G, int p,
                                                         double eps, double target) {
-  __shared__ double red[RBS / SAA_WAVE];
-  __shared__ unsigned long long sh[2 * NB];
-  __shared__ unsigned int hl[2 * NB];
-  const Bracket br = bracket_after(w, G, p, eps, target, (double)N, red, sh);
+  __shared__ int hl[2 * NB];
+  const Bracket br = bracket_after(w, G, p, eps, target, (double)N);
   if (!(br.live && br.hi - br.lo > 4.0 * eps)) return;
   for (int k = threadIdx.x; k < 2 * NB; k += RBS) hl[k] = 0;
   __syncthreads();
   const double step = (br.hi - br.lo) / (NP + 1);
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
+  // most samples fall outside the bracket (bins 0 and NP): count those in
+  // registers, so the LDS atomics only see the few in between
+  int edge[4] = {0, 0, 0, 0};
   for (int64_t i = i0 + threadIdx.x; i < i1; i += RBS) {
     const double qi = q[i];
-    atomicAdd(&hl[probes_below(qi, br.lo, step, 0.0)], 1u);
-    atomicAdd(&hl[NB + probes_below(qi, br.lo, step, eps)], 1u);
+    const int b1 = probes_below(qi, br.lo, step, 0.0);
+    const int b2 = probes_below(qi, br.lo, step, eps);
+    if (b1 == 0) ++edge[0];
+    else if (b1 == NP) ++edge[1];
+    else atomicAdd(&hl[b1], 1);
+    if (b2 == 0) ++edge[2];
+    else if (b2 == NP) ++edge[3];
+    else atomicAdd(&hl[NB + b2], 1);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) edge[k] = wave_sum(edge[k]);
+  if ((threadIdx.x & (SAA_WAVE - 1)) == 0) {
+    atomicAdd(&hl[0], edge[0]);
+    atomicAdd(&hl[NP], edge[1]);
+    atomicAdd(&hl[NB], edge[2]);
+    atomicAdd(&hl[NB + NP], edge[3]);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < 2 * NB; k += RBS)
-    if (hl[k]) atomicAdd(&w.hist[(size_t)p * 2 * NB + k], (unsigned long long)hl[k]);
+    if (hl[k]) atomicAdd(&w.hist[p * 2 * NB + k], hl[k]);
 }
 
-// 3. gather the active set (lo < q < hi + eps); count q >= hi + eps.
+// 3. gather this workgroup's active samples (lo < q < hi + eps) in index
+// order; count the samples at or above hi + eps.
 __global__ void __launch_bounds__(RBS) saa_k_cvar_compact(const double* q, int64_t N, CvarWork w, int G,
                                                           double eps, double target) {
-  __shared__ double red[RBS / SAA_WAVE];
-  __shared__ unsigned long long sh[2 * NB];
-  const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N, red, sh);
+  __shared__ int sh[RBS / SAA_WAVE];
+  const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N);
   if (!(target < (double)N)) return;
   const double top = br.hi + eps;
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
-  double above = 0.0;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += RBS) {
-    const double qi = q[i];
-    if (qi >= top) {
-      above += 1.0;
-    } else if (qi > br.lo) {
-      const unsigned long long k = atomicAdd(&w.act[0], 1ull);
-      if (k < (unsigned long long)CAP) w.aval[k] = qi;
+  double* seg = w.aval + (size_t)blockIdx.x * SEG;
+  int base = 0, above = 0;
+  for (int64_t t0 = i0; t0 < i1; t0 += TILE) {
+    double v[4];
+    bool a[4];
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {   // thread-contiguous samples keep index order
+      const int64_t i = t0 + 4 * threadIdx.x + r;
+      v[r] = i < i1 ? q[i] : -INFINITY;
+      above += v[r] >= top ? 1 : 0;
+      a[r] = v[r] < top && v[r] > br.lo;
+      n += a[r] ? 1 : 0;
     }
+    int pos;
+    const int tot = block_scan(n, &pos, sh);
+    pos += base;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (a[r]) {
+        if (pos < SEG) seg[pos] = v[r];
+        ++pos;
+      }
+    }
+    base += tot;
   }
-  above = block_sum1(above, red);
-  if (threadIdx.x == 0 && above > 0.0) atomicAdd(&w.act[1], (unsigned long long)above);
+  above = wave_sum(above);
+  if ((threadIdx.x & (SAA_WAVE - 1)) == 0) sh[threadIdx.x / SAA_WAVE] = above;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0;
+    for (int k = 0; k < RBS / SAA_WAVE; ++k) a += sh[k];
+    w.nact[blockIdx.x] = base;
+    w.nabove[blockIdx.x] = a;
+  }
 }
 
 // 4. t* (or t_in when t_mode = 1) -> tstar[0].
 __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t N, CvarWork w, int G, double eps,
                                                         double target, int t_mode, double t_in, double* tstar) {
   __shared__ double red[2 * (SBS / SAA_WAVE)];
-  __shared__ unsigned long long sh[2 * NB];
+  __shared__ int off[GMAX + 1];
+  __shared__ int sh[SBS / SAA_WAVE];
   __shared__ double s[CAP];
-  double t;
   if (t_mode == 1) {
-    t = t_in;
-  } else {
-    const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N, red, sh);
-    if (!(target < (double)N)) {
-      t = br.lo;   // beta = 0: every t <= min q - eps is a minimiser
-    } else {
-      const unsigned long long na = w.act[0];
-      if (na <= (unsigned long long)CAP) {
-        const int n = (int)na;
-        const double above = (double)w.act[1];
-        int npad = 1;
-        while (npad < n) npad <<= 1;
-        for (int i = threadIdx.x; i < npad; i += SBS) s[i] = i < n ? w.aval[i] : INFINITY;
-        __syncthreads();
-        // bitonic sort: the arrival order of the active set is not fixed
-        for (int k = 2; k <= npad; k <<= 1) {
-          for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < npad; i += SBS) {
-              const int l = i ^ j;
-              if (l > i) {
-                const double a = s[i], b = s[l];
-                if ((a > b) == ((i & k) == 0)) {
-                  s[i] = b;
-                  s[l] = a;
-                }
-              }
-            }
-            __syncthreads();
-          }
-        }
-        t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
-          double a[2] = {0.0, 0.0};
-          for (int i = threadIdx.x; i < n; i += SBS) {
-            a[0] += sp_d1(s[i] - tc, eps);
-            a[1] += sp_d2(s[i] - tc, eps);
-          }
-          block_sum<2>(a, red);
-          v[0] = above + a[0];
-          v[1] = a[1];
-        });
-      } else {
-        t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
-          double a[2] = {0.0, 0.0};
-          for (int64_t i = threadIdx.x; i < N; i += SBS) {
-            a[0] += sp_d1(q[i] - tc, eps);
-            a[1] += sp_d2(q[i] - tc, eps);
-          }
-          block_sum<2>(a, red);
-          v[0] = a[0];
-          v[1] = a[1];
-        });
+    if (threadIdx.x == 0) tstar[0] = t_in;
+    return;
+  }
+  const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N);
+  if (!(target < (double)N)) {   // beta = 0: every t <= min q - eps is a minimiser
+    if (threadIdx.x == 0) tstar[0] = br.lo;
+    return;
+  }
+  // concatenate the per-workgroup active sets in workgroup order
+  const int cb = threadIdx.x < G ? w.nact[threadIdx.x] : 0;
+  const int ab = threadIdx.x < G ? w.nabove[threadIdx.x] : 0;
+  bool fits = true;
+  int ex;
+  const int n = block_scan(cb, &ex, sh);
+  if (threadIdx.x < G) off[threadIdx.x] = ex;
+  if (threadIdx.x < G && cb > SEG) fits = false;
+  int ex2;
+  const double above = (double)block_scan(ab, &ex2, sh);
+  fits = __syncthreads_and(fits) && n <= CAP;
+  if (threadIdx.x == 0) off[G] = n;
+  __syncthreads();
+  double t;
+  if (fits) {
+    for (int r = threadIdx.x; r < n; r += SBS) {
+      int a = 0, b = G;   // last workgroup with off <= r
+      while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (off[m] <= r) a = m;
+        else b = m;
       }
+      s[r] = w.aval[(size_t)a * SEG + (r - off[a])];
     }
+    __syncthreads();
+    if (n <= WAVE_NEWTON) {   // one wave, no barriers
+      if (threadIdx.x >= SAA_WAVE) return;
+      t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int i = threadIdx.x; i < n; i += SAA_WAVE) {
+          a0 += sp_d1(s[i] - tc, eps);
+          a1 += sp_d2(s[i] - tc, eps);
+        }
+        v[0] = above + wave_sum(a0);
+        v[1] = wave_sum(a1);
+      });
+    } else {
+      t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
+        double a[2] = {0.0, 0.0};
+        for (int i = threadIdx.x; i < n; i += SBS) {
+          a[0] += sp_d1(s[i] - tc, eps);
+          a[1] += sp_d2(s[i] - tc, eps);
+        }
+        block_sum<2>(a, red);
+        v[0] = above + a[0];
+        v[1] = a[1];
+      });
+    }
+  } else {
+    t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
+      double a[2] = {0.0, 0.0};
+      for (int64_t i = threadIdx.x; i < N; i += SBS) {
+        a[0] += sp_d1(q[i] - tc, eps);
+        a[1] += sp_d2(q[i] - tc, eps);
+      }
+      block_sum<2>(a, red);
+      v[0] = a[0];
+      v[1] = a[1];
+    });
   }
   if (threadIdx.x == 0) tstar[0] = t;
 }
 
 // 5. per-workgroup partial sums: sum s_eps, sum s_eps', sum s_eps' dq/dz.
+// The weighted samples of each tile are listed in LDS; wave k of the block
+// then takes every (RBS/64)-th of them with lane c accumulating component c.
 __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const double* g, int64_t N, int dz,
                                                        CvarWork w, int G, double eps, const double* tstar) {
-  __shared__ double red[8 * (RBS / SAA_WAVE)];
+  __shared__ double red[2 * (RBS / SAA_WAVE)];
+  __shared__ int sh[RBS / SAA_WAVE];
+  __shared__ int li[TILE];
+  __shared__ double lw[TILE];
+  __shared__ double gw[RBS / SAA_WAVE][SAA_WAVE];
+  const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
   const double t = tstar[0];
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
   double v[2] = {0.0, 0.0};
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += RBS) {
-    const double x = q[i] - t;
-    v[0] += sp_val(x, eps);
-    v[1] += sp_d1(x, eps);
+  double acc = 0.0;
+  for (int64_t t0 = i0; t0 < i1; t0 += TILE) {
+    double d[4];
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = t0 + 4 * threadIdx.x + r;
+      d[r] = 0.0;
+      if (i < i1) {
+        const double x = q[i] - t;
+        v[0] += sp_val(x, eps);
+        d[r] = sp_d1(x, eps);
+        v[1] += d[r];
+      }
+      n += d[r] != 0.0 ? 1 : 0;
+    }
+    int pos;
+    const int tot = block_scan(n, &pos, sh);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (d[r] != 0.0) {
+        li[pos] = 4 * threadIdx.x + r;
+        lw[pos] = d[r];
+        ++pos;
+      }
+    }
+    __syncthreads();
+    if (lane < dz)
+      for (int r = wid; r < tot; r += RBS / SAA_WAVE) acc += lw[r] * g[(t0 + li[r]) * dz + lane];
+    __syncthreads();
   }
   block_sum<2>(v, red);
+  gw[wid][lane] = acc;
+  __syncthreads();
   double* pp = w.part + (size_t)blockIdx.x * PSTRIDE;
   if (threadIdx.x == 0) {
     pp[0] = v[0];
     pp[1] = v[1];
   }
-  for (int k0 = 0; k0 < dz; k0 += 8) {
-    double a[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) a[c] = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += RBS) {
-      const double wi = sp_d1(q[i] - t, eps);
-      if (wi != 0.0) {
-        const double* gi = g + i * dz;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (k0 + c < dz) a[c] += wi * gi[k0 + c];
-      }
-    }
-    block_sum<8>(a, red);
-    if (threadIdx.x == 0)
-      for (int c = 0; c < 8 && k0 + c < dz; ++c) pp[2 + k0 + c] = a[c];
+  if (threadIdx.x < dz) {
+    double a = 0.0;
+    for (int k = 0; k < RBS / SAA_WAVE; ++k) a += gw[k][threadIdx.x];
+    pp[2 + threadIdx.x] = a;
   }
 }
 
-// 6. reduce the partials in chunk order -> out[0] = J, out[1] = dJ/dt,
+// 6. reduce the partials in a fixed order -> out[0] = J, out[1] = dJ/dt,
 // out[2..2+dz) = grad (when `outputs`); optional per-sample solver stats.
 __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarWork w, int G, double target,
                                                         double alpha, const double* z, const double* tstar,
                                                         int outputs, double* out, const int* newton, const int* lin,
                                                         const int* flag, const int* lin_adj, const int* did,
                                                         CvarStats* stats) {
-  __shared__ double red[5 * (SBS / SAA_WAVE)];
+  constexpr int NW = SBS / SAA_WAVE;
+  __shared__ double red[5 * NW];
+  __shared__ double col[NW][PSTRIDE];
   if (stats) {
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double nm = 0.0;
@@ -387,10 +494,20 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
     }
   }
   if (!outputs) return;
+  // wave k sums the partials of workgroups k, k + NW, ...; then column sums
+  // over the waves in order
+  const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
+  const int ncol = 2 + dz;
+  for (int c = lane; c < ncol; c += SAA_WAVE) {
+    double a = 0.0;
+    for (int b = wid; b < G; b += NW) a += w.part[(size_t)b * PSTRIDE + c];
+    col[wid][c] = a;
+  }
+  __syncthreads();
   const int k = threadIdx.x;
-  if (k >= 2 + dz) return;
+  if (k >= ncol) return;
   double acc = 0.0;
-  for (int b = 0; b < G; ++b) acc += w.part[(size_t)b * PSTRIDE + k];
+  for (int r = 0; r < NW; ++r) acc += col[r][k];
   const double scale = 1.0 / target;
   if (k == 0) {
     double zz = 0.0;
@@ -406,8 +523,8 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
 namespace saa_launch {
 
 size_t cvar_work_bytes() {
-  return sizeof(double) * 2 * GMAX + sizeof(unsigned long long) * (PASSES * 2 * NB + 2) + sizeof(double) * CAP +
-         sizeof(double) * (size_t)GMAX * PSTRIDE;
+  return sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
+         sizeof(int) * ((size_t)PASSES * 2 * NB + 2 * GMAX);
 }
 
 // phase & 1: t (minimiser, or t_in when t_mode = 1) -> tstar[0];
@@ -423,10 +540,12 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
   w.part = (double*)p;
   p += sizeof(double) * (size_t)GMAX * PSTRIDE;
   w.aval = (double*)p;
-  p += sizeof(double) * CAP;
-  w.hist = (unsigned long long*)p;
-  p += sizeof(unsigned long long) * PASSES * 2 * NB;
-  w.act = (unsigned long long*)p;
+  p += sizeof(double) * (size_t)GMAX * SEG;
+  w.hist = (int*)p;
+  p += sizeof(int) * PASSES * 2 * NB;
+  w.nact = (int*)p;
+  p += sizeof(int) * GMAX;
+  w.nabove = (int*)p;
   const int64_t gw = (N + 1023) / 1024;
   const int G = (int)(gw < 1 ? 1 : gw > GMAX ? GMAX : gw);
   const double target = (double)N * (1.0 - beta);
