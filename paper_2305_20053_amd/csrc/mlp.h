@@ -9,12 +9,16 @@
 // bias per call) to width W, layers 1..depth-1 are W x W, layer `depth` maps W
 // to the r_u reduced state coordinates (rows padded to W with zeros).
 struct MlpDev {
-  int r_m, d_z, r_u, width, depth, kin;  // kin: r_m padded to a multiple of 32
+  int r_m, d_z, r_u, width, depth, kin;  // kin: columns of the BF16 layer-0 operand (r_m zero padded)
   // FP32 master parameters, packed: W_0 (width x (r_m+d_z)), b_0, W_1, b_1, ...
   const float* master;
   int64_t off_w[MLP_MAX_DEPTH + 1];      // offsets of W_L and b_L in `master`
   int64_t off_b[MLP_MAX_DEPTH + 1];
-  // BF16 MFMA operands (see mlp.hip for the k-permutation):
+  // BF16 MFMA operands (see mlp.hip for the k-permutation and the fragment
+  // order), stored back to back in the order the kernel reads them:
+  // wp[0..depth], wt[depth..1], w0z.
+  const void* ws;                        // the whole weight stream
+  int64_t ws_frags;                      // its length in 1 KB fragments
   const void* wp[MLP_MAX_DEPTH + 1];     // forward: rows = outputs, cols = inputs
   const void* wt[MLP_MAX_DEPTH + 1];     // backward (L >= 1): rows = inputs, cols = outputs
   const void* w0z;                       // 32 x width: d_Z rows of W_0^T

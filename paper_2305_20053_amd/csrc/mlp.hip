@@ -17,6 +17,13 @@
 // the permutation is folded into the stored weight copies, so activations never
 // leave registers between layers.  GELU'(a_L) of every layer is kept in LDS as
 // fp16 for the reverse pass.
+//
+// The weights (A operands) reach the MFMAs through LDS: every BF16 fragment of
+// every layer is stored once, in the order the kernel consumes it, in one
+// "weight stream"; the waves of a workgroup copy it to LDS together, F
+// fragments (one stage) at a time, two stages ahead in registers and double
+// buffered in LDS, and all of them read their fragments from that shared copy.
+// Each weight byte thus crosses L2 once per workgroup instead of once per wave.
 #include <hip/hip_fp16.h>
 
 #include "common.h"
@@ -24,6 +31,7 @@
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -32,40 +40,86 @@ __device__ __forceinline__ int kperm(int k) {
   return b + (t < 4 ? 4 * g + t : 16 + 4 * g + (t - 4));
 }
 
+// GELU and its derivative for the BF16 kernel, branch-free: Phi(a) =
+// (1 + erf(a / sqrt 2)) / 2 with erf from Abramowitz & Stegun (1964), formula
+// 7.1.26 (absolute error <= 1.5e-7, far below BF16 rounding); the factor
+// exp(-a^2 / 2) is shared with GELU'(a) = Phi(a) + a phi(a).
+__device__ __forceinline__ void gelu_pair(float a, float& h, float& dh) {
+  const float x = fabsf(a) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  const float p =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float e = __expf(-x * x);
+  const float phi2 = 0.5f * copysignf(1.0f - p * e, a) + 0.5f;   // Phi(a)
+  h = a * phi2;
+  dh = fmaf(a * 0.39894228040143268f, e, phi2);
+}
+
 __device__ __forceinline__ float gelu_f(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
 __device__ __forceinline__ float dgelu_f(float a) {
   return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * __expf(-0.5f * a * a);
 }
 
-// acc[mt] += A(mt, ks) * hb[ks] over ks < NK, where A(mt, ks) is the 16 x 32
-// bf16 fragment of rows 16 mt.. and columns 32 ks.. of a row-major operand with
-// leading dimension ld.  The A fragments of step ks + 1 are loaded while the
-// MFMAs of step ks run (two register stages); scheduling barriers keep the
-// compiler from hoisting further loads.
-//
-// Operands are stored fragment-major: the 16 x 32 fragment (mt, ks) of a
-// matrix with ld columns occupies 1 KB at ((mt * ld/32 + ks) * 64 + lane) * 8,
-// lane 16 g + c holding row 16 mt + c, columns 32 ks + 8 g .. + 8, so every
-// wave-wide fragment load is one contiguous 1 KB block.
-template <int MT, int NK, int KSA>
-__device__ __forceinline__ void mfma_gemm(const __bf16* w, int ld, const bf16x8 (&hb)[KSA], f32x4 (&acc)[MT],
-                                          int c16, int g) {
-  bf16x8 a[2][MT];
-  const int nks = ld >> 5;
-  const __bf16* base = w + (int64_t)(16 * g + c16) * 8;
+// Weight stream staged through LDS (see the header).  A fragment is 16 rows x
+// 32 columns of BF16 (1 KB); lane 16 g + c holds row c, columns 8 g .. 8 g + 8.
+// The stream holds the fragments of every operand in consumption order:
+// operand by operand, and inside one operand k-step by k-step, 16-row tile by
+// tile.  Stage s = fragments [s F, (s + 1) F) = one contiguous F KB block.
+template <int WAVES, int F>
+struct WStream {
+  static constexpr int FR = F;
+  static constexpr int PER = F / WAVES;   // 16-byte units per thread per stage
+  static constexpr int UNITS = F * 64;    // 16-byte units per stage
+  static_assert(F % WAVES == 0, "a stage splits evenly over the threads");
+  const uint4* src;   // the stream
+  uint4* buf;         // two LDS stage buffers
+  int nst;            // stages in the stream
+  int s;              // stage being consumed (held in buf[s & 1])
+  uint4 ra[PER];      // stage s + 1
+  uint4 rb[PER];      // stage s + 2
+  // stages past the end re-read the last one (never published)
+  __device__ __forceinline__ void load(uint4 (&r)[PER], int stage) {
+    const int64_t b = (int64_t)(stage < nst ? stage : nst - 1) * UNITS + threadIdx.x;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) a[0][mt] = *(const bf16x8*)(base + (int64_t)(mt * nks) * 512);
+    for (int k = 0; k < PER; ++k) r[k] = src[b + k * WAVES * 64];
+  }
+  __device__ __forceinline__ void store(const uint4 (&r)[PER], int b) {
 #pragma unroll
-  for (int ks = 0; ks < NK; ++ks) {
-    if (ks + 1 < NK) {
+    for (int k = 0; k < PER; ++k) buf[b * UNITS + threadIdx.x + k * WAVES * 64] = r[k];
+  }
+  __device__ __forceinline__ void begin() {
+    load(ra, 0);
+    store(ra, 0);
+    load(ra, 1);
+    load(rb, 2);
+    s = 0;
+    __syncthreads();
+  }
+  __device__ __forceinline__ bf16x8 frag(int j) const {
+    return *(const bf16x8*)(buf + (s & 1) * UNITS + j * 64 + (threadIdx.x & 63));
+  }
+  // End of stage s: publish stage s + 1 (its buffer held stage s - 1, which
+  // every wave finished before the previous barrier), then prefetch s + 3.
+  __device__ __forceinline__ void advance() {
+    store(ra, (s + 1) & 1);
+    __syncthreads();
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-        a[(ks + 1) & 1][mt] = *(const bf16x8*)(base + (int64_t)(mt * nks + ks + 1) * 512);
-    }
+    for (int k = 0; k < PER; ++k) ra[k] = rb[k];
+    load(rb, s + 3);
+    ++s;
+  }
+};
+
+// acc[mt] += A(mt, ks) * hb[ks] for ks < NK, mt < MT, with the A fragments
+// taken from the stream in order.
+template <int MT, int NK, int KSA, class S>
+__device__ __forceinline__ void stream_gemm(S& ws, const bf16x8 (&hb)[KSA], f32x4 (&acc)[MT]) {
+  static_assert((MT * NK) % S::FR == 0, "operands start and end on stage boundaries");
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks & 1][mt], hb[ks], acc[mt], 0, 0, 0);
-    __builtin_amdgcn_sched_barrier(0);
+  for (int f = 0; f < MT * NK; ++f) {
+    const int ks = f / MT, mt = f % MT;
+    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ws.frag(f % S::FR), hb[ks], acc[mt], 0, 0, 0);
+    if (f % S::FR == S::FR - 1) ws.advance();
   }
 }
 
@@ -75,19 +129,19 @@ __device__ __forceinline__ void mfma_gemm(const __bf16* w, int ld, const bf16x8 
 // Weight packing (after every change of the FP32 master parameters)
 // ---------------------------------------------------------------------------
 
-// Position t of a fragment-major stored rows x cols operand (see mfma_gemm)
+// Position t of a stored rows x cols operand (stream order, see WStream)
 // -> logical (row m, column k).
-__device__ __forceinline__ void frag_pos(int64_t t, int cols, int& m, int& k) {
+__device__ __forceinline__ void frag_pos(int64_t t, int rows, int& m, int& k) {
   const int e = (int)(t & 7);
   const int ln = (int)((t >> 3) & 63);
-  const int64_t f = t >> 9;                // fragment index mt * (cols/32) + ks
-  const int nks = cols >> 5;
-  const int mt = (int)(f / nks), ks = (int)(f % nks);
+  const int64_t f = t >> 9;                // fragment index ks * (rows/16) + mt
+  const int nmt = rows >> 4;
+  const int ks = (int)(f / nmt), mt = (int)(f % nmt);
   m = 16 * mt + (ln & 15);
   k = 32 * ks + 8 * (ln >> 4) + e;
 }
 
-// Forward BF16 operand (fragment-major): logical [m][k] = W[m][kperm(k)] (or
+// Forward BF16 operand (stream order): logical [m][k] = W[m][kperm(k)] (or
 // natural order when `natural`), zero outside the source.  W is src_rows x
 // src_ld.  rows % 16 == 0, cols % 32 == 0.
 __global__ void saa_k_pack_fwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
@@ -95,21 +149,21 @@ __global__ void saa_k_pack_fwd(__bf16* dst, const float* src, int rows, int cols
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)rows * cols) return;
   int m, k;
-  frag_pos(t, cols, m, k);
+  frag_pos(t, rows, m, k);
   const int ks = natural ? k : kperm(k);
   float v = 0.0f;
   if (m < src_rows && ks < src_cols) v = src[(int64_t)m * src_ld + ks];
   dst[t] = (__bf16)v;
 }
 
-// Backward BF16 operand (fragment-major): logical [m][k] = W[kperm(k)][col0 + m],
+// Backward BF16 operand (stream order): logical [m][k] = W[kperm(k)][col0 + m],
 // zero outside.
 __global__ void saa_k_pack_bwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
                                int src_ld, int col0) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)rows * cols) return;
   int m, k;
-  frag_pos(t, cols, m, k);
+  frag_pos(t, rows, m, k);
   const int o = kperm(k);
   float v = 0.0f;
   if (o < src_rows && m < src_cols) v = src[(int64_t)o * src_ld + col0 + m];
@@ -145,16 +199,22 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
 // ---------------------------------------------------------------------------
 // Fused BF16 forward + reverse kernel
 // ---------------------------------------------------------------------------
-template <int W, int KIN, int DEPTH, int WAVES, int NZT>
+template <int W, int KIN, int DEPTH, int WAVES, int NZT, int F>
 __global__ void __launch_bounds__(WAVES * 64, 1)
     saa_k_mlp_bf16(MlpDev net, const double* xi, int nkl, const int* order, int64_t N, double* q_out,
                    double* g_out) {
   constexpr int MT = W / 16;   // 16-feature tiles of a layer output
   constexpr int KS = W / 32;   // 32-feature k-steps of a layer input
   constexpr int KS1 = KIN / 32;
-  extern __shared__ _Float16 sdg[];   // [WAVES][DEPTH][MT][64 lanes][4]
+  // LDS: two weight-stream stages, then GELU'(a) as [WAVES][DEPTH][MT][64 lanes][4] fp16
+  extern __shared__ uint4 lds[];
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, c16 = ln & 15;
-  _Float16* my = sdg + (size_t)wv * DEPTH * MT * 256;
+  _Float16* my = (_Float16*)(lds + 2 * F * 64) + (size_t)wv * DEPTH * MT * 256;
+  WStream<WAVES, F> ws;
+  ws.src = (const uint4*)net.ws;
+  ws.buf = lds;
+  ws.nst = net.ws_frags / F;
+  ws.begin();
   const int r_m = net.r_m, r_u = net.r_u, d_z = net.d_z;
 
   // one 16 * WAVES-sample tile per workgroup (a persistent loop would let the
@@ -182,28 +242,31 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     // forward through the hidden layers
 #pragma unroll
     for (int L = 0; L < DEPTH; ++L) {
-      const __bf16* wl = (const __bf16*)net.wp[L];
-      const int ld = (L == 0) ? KIN : W;
       const float* bl = (L == 0) ? net.b0eff : net.bias[L];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (L == 0) mfma_gemm<MT, KS1, KS>(wl, ld, hb, acc, c16, g);
-      else mfma_gemm<MT, KS, KS>(wl, ld, hb, acc, c16, g);
+      if (L == 0) stream_gemm<MT, KS1>(ws, hb, acc);
+      else stream_gemm<MT, KS>(ws, hb, acc);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
+        const float4 b4 = *(const float4*)(bl + 16 * mt + 4 * g);
+        const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+        f16x4 d4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float a = acc[mt][r] + bl[16 * mt + 4 * g + r];
-          my[((L * MT + mt) * 64 + ln) * 4 + r] = (_Float16)dgelu_f(a);
-          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)gelu_f(a);
+          float h, dh;
+          gelu_pair(acc[mt][r] + bb[r], h, dh);
+          d4[r] = (_Float16)dh;
+          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)h;
         }
+        *(f16x4*)(my + ((L * MT + mt) * 64 + ln) * 4) = d4;
+      }
     }
     // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
     {
-      const __bf16* wl = (const __bf16*)net.wp[DEPTH];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      mfma_gemm<MT, KS, KS>(wl, W, hb, acc, c16, g);
+      stream_gemm<MT, KS>(ws, hb, acc);
       float qs = 0.0f;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -221,25 +284,22 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     // reverse pass: delta h_{L} = W_{L+1}^T delta a_{L+1}; delta a_L = GELU'(a_L) delta h_L
 #pragma unroll
     for (int L = DEPTH; L >= 1; --L) {
-      const __bf16* wl = (const __bf16*)net.wt[L];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      mfma_gemm<MT, KS, KS>(wl, W, hb, acc, c16, g);
+      stream_gemm<MT, KS>(ws, hb, acc);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
+        const f16x4 d4 = *(const f16x4*)(my + (((L - 1) * MT + mt) * 64 + ln) * 4);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float d = acc[mt][r] * (float)my[(((L - 1) * MT + mt) * 64 + ln) * 4 + r];
-          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)d;
-        }
+        for (int r = 0; r < 4; ++r) hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)(acc[mt][r] * (float)d4[r]);
+      }
     }
     // dq/dz = W_0[:, r_m:]^T delta a_0
     {
       f32x4 accz[NZT];
 #pragma unroll
       for (int zt = 0; zt < NZT; ++zt) accz[zt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const __bf16* wz = (const __bf16*)net.w0z;
-      mfma_gemm<NZT, KS, KS>(wz, W, hb, accz, c16, g);
+      stream_gemm<NZT, KS>(ws, hb, accz);
       if (valid) {
 #pragma unroll
         for (int zt = 0; zt < NZT; ++zt)
@@ -387,19 +447,21 @@ int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const 
              double* q, double* g, int n_cu, hipStream_t st) {
   if (net.width != 256 || net.depth != 4 || net.r_m > 128 || net.d_z > 32 || net.r_u > 256) return -1;
   if (prec_bf16) {
-    constexpr int WAVES = 4;
-    const size_t lds = (size_t)WAVES * 4 * (256 / 16) * 256 * sizeof(_Float16);
+    constexpr int WAVES = 4, F = 16;
+    // the stream must hold exactly the operands the kernel consumes
+    if (net.kin != 128 || net.ws_frags != 16 * 4 + 4 * 16 * 8 + 4 * 16 * 8 + 2 * 8 || net.ws_frags % F) return -1;
+    const size_t lds = 2 * F * 1024 + (size_t)WAVES * 4 * (256 / 16) * 256 * sizeof(_Float16);
     const int64_t tiles = (N + 16 * WAVES - 1) / (16 * WAVES);
     const unsigned grid = (unsigned)tiles;
     (void)n_cu;
     static bool attr_set = false;
     if (!attr_set) {
-      if (hipFuncSetAttribute((const void*)saa_k_mlp_bf16<256, 128, 4, WAVES, 2>,
+      if (hipFuncSetAttribute((const void*)saa_k_mlp_bf16<256, 128, 4, WAVES, 2, F>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return -2;
       attr_set = true;
     }
-    saa_k_mlp_bf16<256, 128, 4, WAVES, 2><<<grid, WAVES * 64, lds, st>>>(net, xi, nkl, order, N, q, g);
+    saa_k_mlp_bf16<256, 128, 4, WAVES, 2, F><<<grid, WAVES * 64, lds, st>>>(net, xi, nkl, order, N, q, g);
   } else {
     const int64_t blocks = (N + 7) / 8;
     saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);

@@ -55,13 +55,15 @@ MlpDev view(const mrdino_model* m) {
   for (int L = 0; L <= d.depth; ++L) {
     v.off_w[L] = m->off_w[L];
     v.off_b[L] = m->off_b[L];
-    v.wp[L] = m->wp[L].p;
-    v.wt[L] = m->wt[L].p;
+    v.wp[L] = (const char*)m->ws.p + 1024 * m->f_wp[L];
+    v.wt[L] = (const char*)m->ws.p + 1024 * m->f_wt[L];
     v.bias[L] = (const float*)m->bias[L].p;
     v.wn[L] = (const float*)m->master.p + m->off_w[L];
     v.wtn[L] = (const float*)m->wtn[L].p;
   }
-  v.w0z = m->w0z.p;
+  v.w0z = (const char*)m->ws.p + 1024 * m->f_w0z;
+  v.ws = m->ws.p;
+  v.ws_frags = m->ws_frags;
   v.b0eff = (const float*)m->b0eff.p;
   v.c = (const float*)m->c.p;
   v.c0 = m->c0;
@@ -78,17 +80,19 @@ int pack(mrdino_model* m) {
     const int in = (L == 0) ? d.r_m + d.d_z : W;
     const int rows = (L == d.depth) ? d.r_u : W;
     const float* w = P + m->off_w[L];
+    char* wsb = (char*)m->ws.p;
     if (L == 0) {
-      saa_launch::mlp_pack_fwd(m->wp[0].p, w, W, m->kin, W, d.r_m, in, 1, st);
+      saa_launch::mlp_pack_fwd(wsb + 1024 * m->f_wp[0], w, W, m->kin, W, d.r_m, in, 1, st);
       saa_launch::mlp_transpose((float*)m->wtn[0].p, w, W, d.r_m, in, st);   // r_m x W
     } else {
-      saa_launch::mlp_pack_fwd(m->wp[L].p, w, W, W, rows, W, W, 0, st);
-      saa_launch::mlp_pack_bwd(m->wt[L].p, w, W, W, rows, W, W, 0, st);
+      saa_launch::mlp_pack_fwd(wsb + 1024 * m->f_wp[L], w, W, W, rows, W, W, 0, st);
+      saa_launch::mlp_pack_bwd(wsb + 1024 * m->f_wt[L], w, W, W, rows, W, W, 0, st);
       saa_launch::mlp_transpose((float*)m->wtn[L].p, w, rows, W, W, st);     // W x rows
     }
     saa_launch::mlp_pad((float*)m->bias[L].p, P + m->off_b[L], rows, W, st);
   }
-  saa_launch::mlp_pack_bwd(m->w0z.p, P + m->off_w[0], 32, W, W, d.d_z, d.r_m + d.d_z, d.r_m, st);
+  saa_launch::mlp_pack_bwd((char*)m->ws.p + 1024 * m->f_w0z, P + m->off_w[0], 32, W, W, d.d_z, d.r_m + d.d_z,
+                           d.r_m, st);
   return check_hip(hipGetLastError());
 }
 
@@ -116,7 +120,7 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
   if (!m) return SAA_E_OOM;
   m->dims = *d;
   m->st = (hipStream_t)hip_stream;
-  m->kin = (d->r_m + 31) / 32 * 32;
+  m->kin = 128;   // the BF16 kernel reads a fixed 128-column layer-0 operand (r_m <= 128)
   m->n_params = param_count(*d);
   int64_t off = 0;
   int in = d->r_m + d->d_z;
@@ -130,14 +134,24 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
   }
   const int W = d->width;
   int rc = m->master.alloc_zero(sizeof(float) * m->n_params, m->st);
+  // weight stream: wp[0..depth], wt[depth..1], w0z (the kernel's reading order)
+  int64_t nf = 0;
+  for (int L = 0; L <= d->depth; ++L) {
+    m->f_wp[L] = nf;
+    nf += (int64_t)(W / 16) * (((L == 0) ? m->kin : W) / 32);
+  }
+  for (int L = d->depth; L >= 1; --L) {
+    m->f_wt[L] = nf;
+    nf += (int64_t)(W / 16) * (W / 32);
+  }
+  m->f_w0z = nf;
+  nf += 2 * (W / 32);
+  m->ws_frags = nf;
+  if (!rc) rc = m->ws.alloc_zero(1024 * (size_t)nf, m->st);
   for (int L = 0; L <= d->depth && !rc; ++L) {
-    const int cols = (L == 0) ? m->kin : W;
-    rc = m->wp[L].alloc_zero(2 * (size_t)W * cols, m->st);
-    if (!rc && L > 0) rc = m->wt[L].alloc_zero(2 * (size_t)W * W, m->st);
-    if (!rc) rc = m->bias[L].alloc_zero(sizeof(float) * W, m->st);
+    rc = m->bias[L].alloc_zero(sizeof(float) * W, m->st);
     if (!rc) rc = m->wtn[L].alloc_zero(sizeof(float) * (size_t)W * (L == 0 ? d->r_m : W), m->st);
   }
-  if (!rc) rc = m->w0z.alloc_zero(2 * (size_t)32 * W, m->st);
   if (!rc) rc = m->b0eff.alloc_zero(sizeof(float) * W, m->st);
   if (!rc) rc = m->c.alloc_zero(sizeof(float) * W, m->st);
   if (!rc) rc = m->zdev.alloc_zero(sizeof(double) * 64, m->st);

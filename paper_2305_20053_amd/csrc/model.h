@@ -6,12 +6,16 @@
 struct mrdino_model {
   mrdino_dims dims{};
   hipStream_t st = nullptr;
-  int kin = 0;                              // r_m padded to a multiple of 32
+  int kin = 0;                              // columns of the BF16 layer-0 operand
   int64_t n_params = 0;
   int64_t off_w[MLP_MAX_DEPTH + 1] = {};   // offsets of W_L, b_L in the packed parameters
   int64_t off_b[MLP_MAX_DEPTH + 1] = {};
   saa_rt::DevBuf master;                    // FP32 parameters
-  saa_rt::DevBuf wp[MLP_MAX_DEPTH + 1], wt[MLP_MAX_DEPTH + 1], w0z;   // BF16 MFMA operands
+  saa_rt::DevBuf ws;                        // BF16 MFMA operands (weight stream)
+  int64_t ws_frags = 0;                     // stream length in 1 KB fragments
+  int64_t f_wp[MLP_MAX_DEPTH + 1] = {};     // fragment offsets of the operands in the stream
+  int64_t f_wt[MLP_MAX_DEPTH + 1] = {};
+  int64_t f_w0z = 0;
   saa_rt::DevBuf bias[MLP_MAX_DEPTH + 1];   // FP32 biases padded to width
   saa_rt::DevBuf wtn[MLP_MAX_DEPTH + 1];    // FP32 transposed weights (reference kernel)
   saa_rt::DevBuf b0eff, c, zdev;
