@@ -243,6 +243,19 @@ int mrdino_create(const mrdino_dims* dims, void* hip_stream, mrdino_model** out)
 /* Free a model (NULL is ignored). */
 void mrdino_free(mrdino_model* model);
 
+/* Save a model (dimensions, FP32 parameters, c, c0) to a file, and load one
+ * into a new model whose device work runs on `hip_stream`.  Format: the bytes
+ * "SAADINO1", uint32 version 1, int32 r_m d_z r_u width depth, int64
+ * n_params, float64 c0, float64 c[r_u], float32 params[n_params] and the
+ * 64-bit FNV-1a hash of all preceding bytes, in native byte order.  Loading
+ * validates the whole file before any device work: a missing, truncated,
+ * altered or unsupported file returns SAA_E_IO and *out stays NULL.  Training
+ * state (Adam moments) is not saved. */
+int mrdino_save(const mrdino_model* model, const char* path);
+/* Dimensions of a model (e.g. one returned by mrdino_load). */
+int mrdino_get_dims(const mrdino_model* model, mrdino_dims* dims);
+int mrdino_load(const char* path, void* hip_stream, mrdino_model** out);
+
 /* Set / get the FP32 parameters (host, n = mrdino_num_params, packed order
  * above).  Setting rebuilds the device operands (BF16 MFMA copies). */
 int mrdino_set_params(mrdino_model* model, const float* params, int64_t n);
@@ -252,6 +265,23 @@ int mrdino_get_params(const mrdino_model* model, float* params, int64_t n);
  * an M-orthonormal POD basis Phi and mean state b: c = Phi^T (M (b - u_t))_I
  * and c0 = |b - u_t|_M^2 - |c|^2. */
 int mrdino_set_qoi(mrdino_model* model, const double* c, double c0);
+
+/* Network outputs for the samples installed in ctx at the control z (host,
+ * d_Z float64): x_i = [m_r(xi_i); z] (Sec. 3.3, eq. (rbnet)).  `want` is a
+ * bitmask of the outputs to write (device pointers; the others may be NULL):
+ *   MRDINO_WANT_Q       q_dev      N float64: q_i = |phi_i + c|^2 + c0
+ *   MRDINO_WANT_DQDZ    dqdz_dev   N x d_Z float64: dq_i/dz (reverse mode)
+ *   MRDINO_WANT_PHI     phi_dev    N x r_u float32: reduced state phi_i
+ *   MRDINO_WANT_DPHIDZ  dphidz_dev N x d_Z x r_u float32: entry (i, k, j) =
+ *                       d phi_ij / d z_k (forward mode, eq. (rbnet) derivative)
+ * q and dq/dz come from the fused evaluation kernel in `prec` (SAA_FP32 or
+ * SAA_BF16); phi and dphi/dz always in float32, through the training forward
+ * in batches (its workspace stays allocated in the model).  Runs on the
+ * model's stream after synchronising the context's; returns once the outputs
+ * are written. */
+enum { MRDINO_WANT_Q = 1, MRDINO_WANT_DQDZ = 2, MRDINO_WANT_PHI = 4, MRDINO_WANT_DPHIDZ = 8 };
+int mrdino_eval(mrdino_model* model, saa_ctx* ctx, const double* z, int want, int prec, double* q_dev,
+                double* dqdz_dev, float* phi_dev, float* dphidz_dev);
 
 /* ------------------------------------------------------------------------
  * MR-DINO construction (Sec. 3.3-3.4): training data from the PDE form,

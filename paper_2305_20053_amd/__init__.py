@@ -18,6 +18,7 @@ SAA_OK, SAA_W_FALLBACK = 0, 1
 SAA_E_INVALID, SAA_E_NOCONV, SAA_E_DEVICE, SAA_E_OOM, SAA_E_MODEL, SAA_E_IO = -1, -2, -3, -4, -5, -6
 FORM_PDE, FORM_MRDINO = 0, 1
 FP64, FP32, FP32_DC64, BF16, FP8 = 0, 1, 2, 3, 4
+WANT_Q, WANT_DQDZ, WANT_PHI, WANT_DPHIDZ = 1, 2, 4, 8
 
 
 class SaaError(RuntimeError):
@@ -79,6 +80,10 @@ _SIGS = {
     "mrdino_set_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
     "mrdino_get_params": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
     "mrdino_set_qoi": (ctypes.c_int, [_P, _P, ctypes.c_double]),
+    "mrdino_eval": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
+    "mrdino_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "mrdino_get_dims": (ctypes.c_int, [_P, _P]),
+    "mrdino_load": (ctypes.c_int, [ctypes.c_char_p, _P, ctypes.POINTER(_P)]),
 }
 
 _lib = None
@@ -326,6 +331,46 @@ class Model:
         cc = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
         _check(self._lib.mrdino_set_qoi(self._h, cc.ctypes.data, float(c0)))
 
+    def save(self, path):
+        _check(self._lib.mrdino_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, stream=None):
+        lib = _load()
+        h = _P()
+        st = _stream_handle() if stream is None else stream
+        _check(lib.mrdino_load(os.fsencode(path), _P(st), ctypes.byref(h)))
+        d = CDims()
+        self = cls.__new__(cls)
+        self._lib = lib
+        self._h = h
+        _check(lib.mrdino_get_dims(h, ctypes.byref(d)))
+        self.dims = d
+        n = ctypes.c_int64()
+        _check(lib.mrdino_num_params(ctypes.byref(d), ctypes.byref(n)))
+        self.n_params = n.value
+        return self
+
+    def eval(self, ctx, z, want=WANT_Q | WANT_DQDZ | WANT_PHI | WANT_DPHIDZ, prec=FP32):
+        """mrdino_eval on ctx's samples: dict of CUDA tensors q (N,), dqdz
+        (N, d_Z) float64, phi (N, r_u), dphidz (N, d_Z, r_u) float32."""
+        import numpy as np
+        import torch
+        d, n = self.dims, ctx.n
+        zz = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        out = {}
+        if want & WANT_Q:
+            out["q"] = torch.empty(n, dtype=torch.float64, device="cuda")
+        if want & WANT_DQDZ:
+            out["dqdz"] = torch.empty(n, d.d_z, dtype=torch.float64, device="cuda")
+        if want & WANT_PHI:
+            out["phi"] = torch.empty(n, d.r_u, dtype=torch.float32, device="cuda")
+        if want & WANT_DPHIDZ:
+            out["dphidz"] = torch.empty(n, d.d_z, d.r_u, dtype=torch.float32, device="cuda")
+        ptr = [_P(_ptr(out[k])) if k in out else _P(None) for k in ("q", "dqdz", "phi", "dphidz")]
+        _check(self._lib.mrdino_eval(self._h, ctx.handle, zz.ctypes.data, want, prec, *ptr))
+        return out
+
 
 class CTrainCfg(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr_drop_epoch", ctypes.c_int),
@@ -455,3 +500,56 @@ def data_errors(model: Model, data: TrainData):
     es, ej = ctypes.c_double(), ctypes.c_double()
     _check(_load().mrdino_data_errors(model._h, data.handle, ctypes.byref(es), ctypes.byref(ej)))
     return es.value, ej.value
+
+
+def _autograd_functions():
+    """torch.autograd.Function wrappers (built lazily: importing the package
+    must not require torch)."""
+    import numpy as np
+    import torch
+
+    class Objective(torch.autograd.Function):
+        """J(z) as a differentiable function of the host control z (float64
+        CPU tensor); the backward is the library's gradient (Sec. 2.3)."""
+
+        @staticmethod
+        def forward(fctx, z, sctx, form, model, opt):
+            J, g, _ = sctx.objective_grad(z.detach().cpu().numpy(), form=form, model=model, opt=opt)
+            fctx.save_for_backward(torch.from_numpy(g))
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gJ):
+            (g,) = fctx.saved_tensors
+            return gJ * g, None, None, None, None
+
+    class DinoLoss(torch.autograd.Function):
+        """Derivative-informed training loss (Sec. 3.4) of the rows idx of a
+        TrainData as a function of the packed FP32 parameters (CPU tensor);
+        the backward is the hand-written gradient kernel."""
+
+        @staticmethod
+        def forward(fctx, params, model, data, idx, dino):
+            p = params.detach().cpu().numpy().astype(np.float32)
+            model.set_params(p)
+            loss, g = loss_grad(model, data, idx, dino=dino)
+            fctx.save_for_backward(torch.from_numpy(g))
+            return torch.tensor(loss, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gL):
+            (g,) = fctx.saved_tensors
+            return (gL * g.double()).to(torch.float32), None, None, None, None
+
+    return Objective, DinoLoss
+
+
+def objective(z, ctx: Context, form=FORM_PDE, model=None, opt=None):
+    """Differentiable J(z): z is a float64 CPU tensor of d_Z controls."""
+    return _autograd_functions()[0].apply(z, ctx, form, model, opt)
+
+
+def dino_loss(params, model: Model, data: TrainData, idx, dino=True):
+    """Differentiable training loss of the rows idx at the packed FP32
+    parameters `params` (CPU tensor); sets the model's parameters."""
+    return _autograd_functions()[1].apply(params, model, data, idx, dino)

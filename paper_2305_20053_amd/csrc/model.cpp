@@ -1,6 +1,7 @@
 // MR-DINO model object: parameters, packed device operands, evaluation.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -196,9 +197,114 @@ int mrdino_set_qoi(mrdino_model* m, const double* c, double c0) {
     buf[i] = (float)c[i];
   }
   m->c0 = c0;
+  m->c_host.assign(c, c + m->dims.r_u);
   int rc = check_hip(hipMemcpyAsync(m->c.p, buf.data(), sizeof(float) * W, hipMemcpyHostToDevice, m->st));
   if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
   return rc;
+}
+
+}  // extern "C"
+
+// Model file: "SAADINO1", uint32 version 1, int32 r_m d_z r_u width depth,
+// int64 n_params, float64 c0, float64 c[r_u], float32 params[n_params], then
+// the 64-bit FNV-1a hash of everything before it.  Native byte order.
+namespace {
+constexpr char kMagic[8] = {'S', 'A', 'A', 'D', 'I', 'N', 'O', '1'};
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 0x100000001b3ull;
+  return h;
+}
+
+template <typename T>
+void append(std::vector<unsigned char>& b, const T* v, size_t n) {
+  const unsigned char* p = (const unsigned char*)v;
+  b.insert(b.end(), p, p + sizeof(T) * n);
+}
+
+template <typename T>
+bool take(const std::vector<unsigned char>& b, size_t& off, T* v, size_t n) {
+  if (off + sizeof(T) * n > b.size()) return false;
+  std::memcpy(v, b.data() + off, sizeof(T) * n);
+  off += sizeof(T) * n;
+  return true;
+}
+}  // namespace
+
+extern "C" {
+
+int mrdino_get_dims(const mrdino_model* m, mrdino_dims* d) {
+  if (!m || !d) return SAA_E_INVALID;
+  *d = m->dims;
+  return SAA_OK;
+}
+
+int mrdino_save(const mrdino_model* m, const char* path) {
+  if (!m || !path) return SAA_E_INVALID;
+  std::vector<float> params(m->n_params);
+  int rc = mrdino_get_params(m, params.data(), m->n_params);
+  if (rc) return rc;
+  std::vector<double> c(m->c_host);
+  c.resize(m->dims.r_u, 0.0);
+  const uint32_t version = 1;
+  const int32_t dims[5] = {m->dims.r_m, m->dims.d_z, m->dims.r_u, m->dims.width, m->dims.depth};
+  std::vector<unsigned char> b;
+  append(b, kMagic, 8);
+  append(b, &version, 1);
+  append(b, dims, 5);
+  append(b, &m->n_params, 1);
+  append(b, &m->c0, 1);
+  append(b, c.data(), c.size());
+  append(b, params.data(), params.size());
+  const uint64_t h = fnv1a(b.data(), b.size());
+  append(b, &h, 1);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return SAA_E_IO;
+  const bool ok = std::fwrite(b.data(), 1, b.size(), f) == b.size();
+  return (std::fclose(f) == 0 && ok) ? SAA_OK : SAA_E_IO;
+}
+
+int mrdino_load(const char* path, void* hip_stream, mrdino_model** out) {
+  if (!path || !out) return SAA_E_INVALID;
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return SAA_E_IO;
+  std::vector<unsigned char> b;
+  unsigned char chunk[1 << 16];
+  size_t got;
+  while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) b.insert(b.end(), chunk, chunk + got);
+  std::fclose(f);
+  // the whole file is validated before any device work
+  if (b.size() < 8 + sizeof(uint64_t)) return SAA_E_IO;
+  uint64_t h;
+  std::memcpy(&h, b.data() + b.size() - sizeof(h), sizeof(h));
+  if (std::memcmp(b.data(), kMagic, 8) != 0 || fnv1a(b.data(), b.size() - sizeof(h)) != h) return SAA_E_IO;
+  size_t off = 8;
+  uint32_t version = 0;
+  int32_t dims[5];
+  int64_t n = 0;
+  double c0 = 0.0;
+  if (!take(b, off, &version, 1) || version != 1 || !take(b, off, dims, 5) || !take(b, off, &n, 1) ||
+      !take(b, off, &c0, 1))
+    return SAA_E_IO;
+  const mrdino_dims d{dims[0], dims[1], dims[2], dims[3], dims[4]};
+  if (!dims_supported(d) || n != param_count(d)) return SAA_E_IO;
+  std::vector<double> c(d.r_u);
+  std::vector<float> params(n);
+  if (!take(b, off, c.data(), c.size()) || !take(b, off, params.data(), params.size()) ||
+      off + sizeof(h) != b.size())
+    return SAA_E_IO;
+  mrdino_model* m = nullptr;
+  int rc = mrdino_create(&d, hip_stream, &m);
+  if (!rc) rc = mrdino_set_params(m, params.data(), n);
+  if (!rc) rc = mrdino_set_qoi(m, c.data(), c0);
+  if (rc) {
+    mrdino_free(m);
+    return rc;
+  }
+  *out = m;
+  return SAA_OK;
 }
 
 }  // extern "C"

@@ -1,5 +1,7 @@
 // Internal definition of the MR-DINO model object.
 #pragma once
+#include <vector>
+
 #include "ctx.h"
 #include "mlp.h"
 
@@ -20,6 +22,7 @@ struct mrdino_model {
   saa_rt::DevBuf wtn[MLP_MAX_DEPTH + 1];    // FP32 transposed weights (reference kernel)
   saa_rt::DevBuf b0eff, c, zdev;
   double c0 = 0.0;
+  std::vector<double> c_host;               // c as given to mrdino_set_qoi (zeros until set)
   void* train = nullptr;                    // training workspace and Adam state (train.cpp)
   ~mrdino_model();
 };

@@ -420,6 +420,57 @@ int mrdino_loss_grad(mrdino_model* m, mrdino_data* D, const int* idx, int B, int
   return check_hip(hipGetLastError());
 }
 
+int mrdino_eval(mrdino_model* m, saa_ctx* c, const double* z, int want, int prec, double* q_dev, double* dqdz_dev,
+                float* phi_dev, float* dphidz_dev) {
+  if (!m || !c || !z || want < 1 || want > 15 || c->N < 1) return SAA_E_INVALID;
+  if (((want & MRDINO_WANT_Q) && !q_dev) || ((want & MRDINO_WANT_DQDZ) && !dqdz_dev) ||
+      ((want & MRDINO_WANT_PHI) && !phi_dev) || ((want & MRDINO_WANT_DPHIDZ) && !dphidz_dev))
+    return SAA_E_INVALID;
+  const mrdino_dims& d = m->dims;
+  if (d.d_z != c->dz || d.r_m > c->K1 * c->K1) return SAA_E_MODEL;
+  for (int k = 0; k < d.d_z; ++k)
+    if (!std::isfinite(z[k])) return SAA_E_INVALID;
+  int rc = SAA_OK;
+  if (want & (MRDINO_WANT_Q | MRDINO_WANT_DQDZ)) {
+    if (prec != SAA_FP32 && prec != SAA_BF16) return SAA_E_INVALID;
+    if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * d.d_z, hipMemcpyHostToDevice, c->st))))
+      return rc;
+    double* q = (want & MRDINO_WANT_Q) ? q_dev : (double*)c->q.p;
+    double* g = (want & MRDINO_WANT_DQDZ) ? dqdz_dev : (double*)c->g.p;
+    if ((rc = saa_model_eval(m, c, (const double*)c->zdev.p, prec, q, g))) return rc;
+  }
+  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  if (want & (MRDINO_WANT_PHI | MRDINO_WANT_DPHIDZ)) {
+    const int dino = (want & MRDINO_WANT_DPHIDZ) ? 1 : 0;
+    const int B = (int)std::min<int64_t>(c->N, 512);
+    if ((rc = alloc_ws(m, B))) return rc;
+    TrainWs& w = train_state(m)->ws;
+    DevBuf Zb;
+    std::vector<double> zrep((size_t)B * d.d_z);
+    for (int b = 0; b < B; ++b) std::copy(z, z + d.d_z, zrep.begin() + (size_t)b * d.d_z);
+    if ((rc = Zb.alloc(sizeof(double) * zrep.size()))) return rc;
+    if ((rc = check_hip(hipMemcpyAsync(Zb.p, zrep.data(), sizeof(double) * zrep.size(), hipMemcpyHostToDevice,
+                                       m->st))))
+      return rc;
+    const int nkl = c->K1 * c->K1;
+    for (int64_t b0 = 0; b0 < c->N && !rc; b0 += B) {
+      const int nb = (int)std::min<int64_t>(B, c->N - b0);
+      saa_launch::train_inputs((const double*)c->xi.p + b0 * nkl, nkl, (const int*)c->order.p, d.r_m,
+                               (const double*)Zb.p, d.d_z, nb, F(w.Xb), m->st);
+      forward(m, w, nb, dino);
+      if (want & MRDINO_WANT_PHI)
+        rc = check_hip(hipMemcpyAsync(phi_dev + b0 * d.r_u, w.P.p, sizeof(float) * nb * d.r_u,
+                                      hipMemcpyDeviceToDevice, m->st));
+      if (!rc && dino)
+        rc = check_hip(hipMemcpyAsync(dphidz_dev + b0 * d.d_z * d.r_u, w.JP.p,
+                                      sizeof(float) * (size_t)nb * d.d_z * d.r_u, hipMemcpyDeviceToDevice, m->st));
+    }
+    if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  }
+  if (!rc) rc = check_hip(hipGetLastError());
+  return rc;
+}
+
 int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, double* epoch_loss, double* seconds) {
   if (!m || !D || !cfg || !compatible(m, D)) return SAA_E_INVALID;
   const int B = cfg->batch;

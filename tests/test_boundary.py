@@ -82,3 +82,21 @@ def test_null_arguments_rejected():
     assert lib.saa_solve_states(None, None, ctypes.byref(o), None, None, None, None) == saa.SAA_E_INVALID
     assert lib.saa_sample_status(None, None, None, None, None) == saa.SAA_E_INVALID
     lib.saa_ctx_destroy(None)
+
+
+def test_model_file_rejected_before_device_work(tmp_path):
+    """mrdino_load validates the whole file (magic, version, dimensions, size,
+    FNV-1a hash) before any device allocation."""
+    lib = saa.lib()
+    h = ctypes.c_void_p()
+    missing = os.fsencode(str(tmp_path / "missing.bin"))
+    assert lib.mrdino_load(missing, None, ctypes.byref(h)) == saa.SAA_E_IO and not h.value
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"SAADINO1" + b"\0" * 64)
+    assert lib.mrdino_load(os.fsencode(str(bad)), None, ctypes.byref(h)) == saa.SAA_E_IO and not h.value
+    bad.write_bytes(b"NOTAMODEL")
+    assert lib.mrdino_load(os.fsencode(str(bad)), None, ctypes.byref(h)) == saa.SAA_E_IO and not h.value
+    assert lib.mrdino_load(None, None, ctypes.byref(h)) == saa.SAA_E_INVALID
+    assert lib.mrdino_save(None, os.fsencode(str(bad))) == saa.SAA_E_INVALID
+    assert lib.mrdino_eval(None, None, None, 1, saa.FP32, None, None, None, None) == saa.SAA_E_INVALID
+    assert lib.mrdino_get_dims(None, None) == saa.SAA_E_INVALID

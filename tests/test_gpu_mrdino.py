@@ -82,3 +82,61 @@ def test_mrdino_rejects_pde_precision(setup):
         ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32_DC64))
     with pytest.raises(saa.SaaError):
         ctx.objective_grad(z, form=saa.FORM_MRDINO, model=None, opt=saa.options(prec=saa.BF16))
+
+
+def test_eval_outputs(setup):
+    """mrdino_eval: phi and dphi/dz (forward mode, FP32) against the oracle's
+    forward-mode Jacobian, q and dq/dz against the reverse-mode oracle, and the
+    chain rule dq/dz = 2 (phi + c)^T dphi/dz linking the two modes."""
+    prob, xi, z, model, ctx, q_ref, g_ref = setup
+    print("case mrdino eval all outputs FP32", flush=True)
+    out = model.eval(ctx, z)
+    q, g = out["q"].cpu().numpy(), out["dqdz"].cpu().numpy()
+    phi, dphi = out["phi"].cpu().numpy(), out["dphidz"].cpu().numpy()
+    widths = [R_M + D_Z, 256, 256, 256, 256, R_U]
+    layers64 = training.unflatten(model.get_params().astype(np.float64), widths)
+    x = np.concatenate([surrogate.encode(xi, R_M), np.broadcast_to(z, (xi.shape[0], D_Z))], axis=1)
+    phi_ref, jac_ref = surrogate.jacobian_z(layers64, x, R_M)       # (N, r_u), (N, r_u, d_Z)
+    e_phi = _rel(phi, phi_ref)
+    e_jac = _rel(dphi, np.transpose(jac_ref, (0, 2, 1)))
+    print(f"  phi rel {e_phi:.3e}; dphi/dz rel {e_jac:.3e}; q rel {_rel(q, q_ref):.3e}; dq/dz rel {_rel(g, g_ref):.3e}")
+    assert e_phi <= 1e-5 and e_jac <= 1e-5
+    assert _rel(q, q_ref) <= 1e-5 and _rel(g, g_ref) <= 1e-4
+    rng = np.random.default_rng(4004)
+    c = 0.3 * rng.standard_normal(R_U)
+    chain = 2.0 * np.einsum("nj,nkj->nk", phi.astype(np.float64) + c, dphi.astype(np.float64))
+    assert _rel(chain, g) <= 1e-4
+    bf = model.eval(ctx, z, want=saa.WANT_Q | saa.WANT_DQDZ, prec=saa.BF16)
+    assert set(bf) == {"q", "dqdz"}
+    assert _rel(bf["q"].cpu().numpy(), q_ref) <= 2e-2 and _rel(bf["dqdz"].cpu().numpy(), g_ref) <= 2e-2
+
+
+def test_eval_rejects_bad_requests(setup):
+    prob, xi, z, model, ctx, q_ref, g_ref = setup
+    lib = saa._load()
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    P = saa._P
+    assert lib.mrdino_eval(model.handle, ctx.handle, zz.ctypes.data, 0, saa.FP32, P(None), P(None), P(None),
+                           P(None)) == saa.SAA_E_INVALID
+    assert lib.mrdino_eval(model.handle, ctx.handle, zz.ctypes.data, saa.WANT_PHI, saa.FP32, P(None), P(None),
+                           P(None), P(None)) == saa.SAA_E_INVALID
+    q = torch.empty(ctx.n, dtype=torch.float64, device="cuda")
+    assert lib.mrdino_eval(model.handle, ctx.handle, zz.ctypes.data, saa.WANT_Q, saa.FP32_DC64,
+                           P(q.data_ptr()), P(None), P(None), P(None)) == saa.SAA_E_INVALID
+
+
+def test_save_load_roundtrip(setup, tmp_path):
+    prob, xi, z, model, ctx, q_ref, g_ref = setup
+    path = str(tmp_path / "model.bin")
+    model.save(path)
+    m2 = saa.Model.load(path)
+    assert (m2.dims.r_m, m2.dims.d_z, m2.dims.r_u, m2.dims.width, m2.dims.depth) == (R_M, D_Z, R_U, 256, 4)
+    assert np.array_equal(m2.get_params(), model.get_params())
+    a = model.eval(ctx, z, want=saa.WANT_Q | saa.WANT_DQDZ, prec=saa.BF16)
+    b = m2.eval(ctx, z, want=saa.WANT_Q | saa.WANT_DQDZ, prec=saa.BF16)
+    assert torch.equal(a["q"], b["q"]) and torch.equal(a["dqdz"], b["dqdz"])
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 1
+    open(path, "wb").write(bytes(raw))
+    with pytest.raises(saa.SaaError):
+        saa.Model.load(path)

@@ -177,3 +177,25 @@ def test_medium_fp32_vs_fp64(medium):
     Jdc, gdc, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32_DC64))
     assert abs(J32 - J64) <= 1e-4 * abs(J64) and _rel(g32, g64) <= 1e-4
     assert abs(Jdc - J64) <= 1e-10 * abs(J64) and _rel(gdc, g64) <= 1e-9
+
+
+def test_objective_autograd_and_finite_differences(small):
+    """J(z) behind torch.autograd: backward returns the library gradient, and
+    central differences of the FP64 GPU objective along two directions agree
+    with it (eps = 1e-2 keeps the third derivative of s_eps moderate)."""
+    prob, xi, z, ref, ctx = small
+    opt = saa.options(prec=saa.FP64, eps=1e-2)
+    zt = torch.tensor(z, dtype=torch.float64, requires_grad=True)
+    J = saa.objective(zt, ctx, opt=opt)
+    J.backward()
+    Jl, gl, _ = ctx.objective_grad(z, opt=opt)
+    assert J.item() == Jl and np.array_equal(zt.grad.numpy(), gl)
+    rng = np.random.default_rng(7)
+    for v in (gl / np.linalg.norm(gl), rng.standard_normal(z.size)):
+        v = v / np.linalg.norm(v)
+        h = 1e-4
+        jp = ctx.objective_grad(z + h * v, opt=opt)[0]
+        jm = ctx.objective_grad(z - h * v, opt=opt)[0]
+        fd, an = (jp - jm) / (2 * h), float(gl @ v)
+        print(f"  directional derivative: FD {fd:.10e} analytic {an:.10e}")
+        assert abs(fd - an) <= 1e-6 * np.linalg.norm(gl)

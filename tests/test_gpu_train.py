@@ -108,3 +108,27 @@ def test_training_decreases_loss_and_sets_qoi(small):
     q, g, _ = ctx.per_sample(ref["Z"][0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32))
     assert np.all(np.isfinite(q.cpu().numpy())) and np.all(np.isfinite(g.cpu().numpy()))
     model.close()
+
+
+def test_dino_loss_autograd_matches_finite_differences(small):
+    """The DINO loss behind torch.autograd: its backward (the hand-written
+    gradient kernel) against central finite differences of the forward along
+    the gradient direction and along a random direction."""
+    prob, ctx, data, ref = small
+    widths = [R_M + ctx.d_z, 256, 256, 256, 256, R_U]
+    flat = training.flatten(si.random_mlp(5004, widths, bias_scale=0.1)).astype(np.float32)
+    model = saa.Model(R_M, ctx.d_z, R_U, 256, 4)
+    idx = np.arange(N, dtype=np.int32)
+    p = torch.from_numpy(flat).requires_grad_(True)
+    loss = saa.dino_loss(p, model, data, idx)
+    loss.backward()
+    g = p.grad.double().numpy()
+    rng = np.random.default_rng(5005)
+    r = rng.standard_normal(flat.size)
+    for v in (g / np.linalg.norm(g), r / np.linalg.norm(r)):
+        h = 1e-2
+        lp = saa.dino_loss(torch.from_numpy((flat + h * v).astype(np.float32)), model, data, idx).item()
+        lm = saa.dino_loss(torch.from_numpy((flat - h * v).astype(np.float32)), model, data, idx).item()
+        fd, an = (lp - lm) / (2 * h), float(g @ v)
+        print(f"  directional derivative: FD {fd:.6e} analytic {an:.6e}")
+        assert abs(fd - an) <= 2e-3 * abs(g @ (g / np.linalg.norm(g))) + 1e-6
