@@ -386,6 +386,7 @@ int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
                                     hipMemcpyDeviceToDevice, c->st));
   if (rc) return rc;
   c->N = N;
+  c->enc_rm = -1;
   saa_launch::field((const double*)c->xi.p, (const double*)c->S.p, (const double*)c->amp.p, (double*)c->em.p,
                     c->K1, c->prob.n, N, c->st);
   rc = check_hip(hipGetLastError());

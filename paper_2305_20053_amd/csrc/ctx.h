@@ -85,6 +85,8 @@ struct saa_ctx {
   saa_rt::DevBuf u, f, lam;   // PDE-form node vectors (sized for float64; allocated at first use)
   saa_rt::DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
   saa_rt::DevBuf cwork;       // CVaR reduction workspace (partials, probe histograms, active set)
+  saa_rt::DevBuf enc;         // surrogate input: leading KL coordinates as BF16, N_max x 128
+  int enc_rm = -1;            // r_m that `enc` holds for the installed samples (-1: stale)
   saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
   saa_rt::PhaseTimer timer;
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)

@@ -25,6 +25,7 @@ struct MlpDev {
   const float* bias[MLP_MAX_DEPTH + 1];  // FP32 biases, padded to width
   const float* b0eff;                    // b_0 + W_0[:, r_m:] z (per call)
   const float* c;                        // reduced-QoI shift, padded to width
+  const float* bc;                       // output bias + c, zero padded to width
   double c0;
   // FP32 reference operands: natural W_L (out x in) and its transpose (in x out)
   const float* wn[MLP_MAX_DEPTH + 1];

@@ -184,6 +184,23 @@ __global__ void saa_k_pad(float* dst, const float* src, int n_src, int n_dst) {
   if (t < n_dst) dst[t] = t < n_src ? src[t] : 0.0f;
 }
 
+// BF16 surrogate input of every installed sample: X[s][k] = xi_s[order[k]] for
+// k < r_m, 0 up to 128 (the leading KL coordinates, Sec. 3.3).  The samples
+// are fixed, so this runs once per sample set.
+__global__ void saa_k_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, __bf16* X) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * 128) return;
+  const int64_t s = t >> 7;
+  const int k = (int)(t & 127);
+  X[t] = (__bf16)(k < r_m ? (float)xi[s * nkl + order[k]] : 0.0f);
+}
+
+// dst[i] = a[i] + b[i] for i < n, 0 for n <= i < w.
+__global__ void saa_k_add_pad(float* dst, const float* a, const float* b, int n, int w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < w) dst[i] = i < n ? a[i] + b[i] : 0.0f;
+}
+
 // b0eff[f] = b_0[f] + sum_k W_0[f][r_m + k] z_k  (the control enters only
 // through the first layer and is shared by all samples).
 __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m,
@@ -201,8 +218,7 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
 // ---------------------------------------------------------------------------
 template <int W, int KIN, int DEPTH, int WAVES, int NZT, int F>
 __global__ void __launch_bounds__(WAVES * 64, 1)
-    saa_k_mlp_bf16(MlpDev net, const double* xi, int nkl, const int* order, int64_t N, double* q_out,
-                   double* g_out) {
+    saa_k_mlp_bf16(MlpDev net, const __bf16* xenc, int64_t N, double* q_out, double* g_out) {
   constexpr int MT = W / 16;   // 16-feature tiles of a layer output
   constexpr int KS = W / 32;   // 32-feature k-steps of a layer input
   constexpr int KS1 = KIN / 32;
@@ -225,15 +241,12 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     const bool valid = s < N;
     bf16x8 hb[KS];
     f32x4 acc[MT];
-    // encoded input: leading r_m KL coordinates, natural k order, zero padded
+    // encoded input (KIN BF16 per sample, see saa_k_encode)
 #pragma unroll
-    for (int ks = 0; ks < KS1; ++ks)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = 32 * ks + 8 * g + t;
-        const float v = (valid && k < r_m) ? (float)xi[s * nkl + order[k]] : 0.0f;
-        hb[ks][t] = (__bf16)v;
-      }
+    for (int ks = 0; ks < KS1; ++ks) {
+      hb[ks] = bf16x8{};
+      if (valid) hb[ks] = *(const bf16x8*)(xenc + s * KIN + 32 * ks + 8 * g);
+    }
 #pragma unroll
     for (int ks = KS1; ks < KS; ++ks)
 #pragma unroll
@@ -269,14 +282,17 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       stream_gemm<MT, KS>(ws, hb, acc);
       float qs = 0.0f;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
+        // rows past r_u have zero weights and zero bias + c, so v = 0 there
+        const float4 b4 = *(const float4*)(net.bc + 16 * mt + 4 * g);
+        const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int f = 16 * mt + 4 * g + r;
-          const float v = (f < r_u) ? acc[mt][r] + net.bias[DEPTH][f] + net.c[f] : 0.0f;
+          const float v = acc[mt][r] + bb[r];
           qs += v * v;
           hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)(2.0f * v);
         }
+      }
       qs += __shfl_xor(qs, 16, 64);
       qs += __shfl_xor(qs, 32, 64);
       if (g == 0 && valid) q_out[s] = (double)qs + net.c0;
@@ -437,14 +453,20 @@ void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld,
 void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st) {
   saa_k_pad<<<nblk(n_dst, 256), 256, 0, st>>>(dst, src, n_src, n_dst);
 }
+void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, void* X, hipStream_t st) {
+  saa_k_encode<<<nblk(N * 128, 256), 256, 0, st>>>(xi, nkl, order, r_m, N, (__bf16*)X);
+}
+void mlp_add_pad(float* dst, const float* a, const float* b, int n, int w, hipStream_t st) {
+  saa_k_add_pad<<<nblk(w, 256), 256, 0, st>>>(dst, a, b, n, w);
+}
 void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
                hipStream_t st) {
   saa_k_b0eff<<<nblk(width, 256), 256, 0, st>>>(b0eff, W0, b0, z, width, r_m, d_z);
 }
 
 // Supported shapes: width 256, depth 4, r_m <= 128, d_z <= 32.
-int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, int64_t N,
-             double* q, double* g, int n_cu, hipStream_t st) {
+int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, const void* xenc,
+             int64_t N, double* q, double* g, int n_cu, hipStream_t st) {
   if (net.width != 256 || net.depth != 4 || net.r_m > 128 || net.d_z > 32 || net.r_u > 256) return -1;
   if (prec_bf16) {
     constexpr int WAVES = 4, F = 16;
@@ -461,7 +483,7 @@ int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const 
         return -2;
       attr_set = true;
     }
-    saa_k_mlp_bf16<256, 128, 4, WAVES, 2, F><<<grid, WAVES * 64, lds, st>>>(net, xi, nkl, order, N, q, g);
+    saa_k_mlp_bf16<256, 128, 4, WAVES, 2, F><<<grid, WAVES * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
   } else {
     const int64_t blocks = (N + 7) / 8;
     saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);

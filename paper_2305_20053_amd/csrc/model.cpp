@@ -19,8 +19,10 @@ void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld,
 void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st);
 void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
                hipStream_t st);
-int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, int64_t N,
-             double* q, double* g, int n_cu, hipStream_t st);
+int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, const void* xenc,
+             int64_t N, double* q, double* g, int n_cu, hipStream_t st);
+void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, void* X, hipStream_t st);
+void mlp_add_pad(float* dst, const float* a, const float* b, int n, int w, hipStream_t st);
 }  // namespace saa_launch
 
 using namespace saa_rt;
@@ -67,6 +69,7 @@ MlpDev view(const mrdino_model* m) {
   v.ws_frags = m->ws_frags;
   v.b0eff = (const float*)m->b0eff.p;
   v.c = (const float*)m->c.p;
+  v.bc = (const float*)m->bc.p;
   v.c0 = m->c0;
   return v;
 }
@@ -92,6 +95,7 @@ int pack(mrdino_model* m) {
     }
     saa_launch::mlp_pad((float*)m->bias[L].p, P + m->off_b[L], rows, W, st);
   }
+  saa_launch::mlp_add_pad((float*)m->bc.p, (const float*)m->bias[d.depth].p, (const float*)m->c.p, d.r_u, W, st);
   saa_launch::mlp_pack_bwd((char*)m->ws.p + 1024 * m->f_w0z, P + m->off_w[0], 32, W, W, d.d_z, d.r_m + d.d_z,
                            d.r_m, st);
   return check_hip(hipGetLastError());
@@ -155,6 +159,7 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
   }
   if (!rc) rc = m->b0eff.alloc_zero(sizeof(float) * W, m->st);
   if (!rc) rc = m->c.alloc_zero(sizeof(float) * W, m->st);
+  if (!rc) rc = m->bc.alloc_zero(sizeof(float) * W, m->st);
   if (!rc) rc = m->zdev.alloc_zero(sizeof(double) * 64, m->st);
   if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
   if (rc) {
@@ -199,6 +204,11 @@ int mrdino_set_qoi(mrdino_model* m, const double* c, double c0) {
   m->c0 = c0;
   m->c_host.assign(c, c + m->dims.r_u);
   int rc = check_hip(hipMemcpyAsync(m->c.p, buf.data(), sizeof(float) * W, hipMemcpyHostToDevice, m->st));
+  if (!rc) {
+    saa_launch::mlp_add_pad((float*)m->bc.p, (const float*)m->bias[m->dims.depth].p, (const float*)m->c.p,
+                            m->dims.r_u, W, m->st);
+    rc = check_hip(hipGetLastError());
+  }
   if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
   return rc;
 }
@@ -318,8 +328,16 @@ int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, d
   saa_launch::mlp_b0eff((float*)m->b0eff.p, (const float*)m->master.p + m->off_w[0],
                         (const float*)m->master.p + m->off_b[0], z_dev, d.width, d.r_m, d.d_z, c->st);
   const MlpDev v = view(m);
+  if (prec == SAA_BF16 && c->enc_rm != d.r_m) {   // encode the installed samples once
+    int rc = c->enc.p ? SAA_OK : c->enc.alloc(sizeof(uint16_t) * 128 * (size_t)c->N_max);
+    if (rc) return rc;
+    saa_launch::mlp_encode((const double*)c->xi.p, c->K1 * c->K1, (const int*)c->order.p, d.r_m, c->N, c->enc.p,
+                           c->st);
+    if ((rc = check_hip(hipGetLastError()))) return rc;
+    c->enc_rm = d.r_m;
+  }
   const int rc = saa_launch::mlp_eval(v, prec == SAA_BF16, (const double*)c->xi.p, c->K1 * c->K1,
-                                      (const int*)c->order.p, c->N, q, g, 0, c->st);
+                                      (const int*)c->order.p, c->enc.p, c->N, q, g, 0, c->st);
   if (rc) return SAA_E_DEVICE;
   return check_hip(hipGetLastError());
 }
