@@ -155,19 +155,19 @@ int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int all, double* go
     case SAA_FP64:
       saa_launch::adjoint<double, double>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
                                           (double*)c->f.p, (double*)c->lam.p, c->mg64.view(), sp, (double*)c->q.p,
-                                          (double*)c->tstar.p, all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                          c->tstar(), all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
                                           (int*)c->did.p, c->N, c->st);
       break;
     case SAA_FP32_DC64:
       saa_launch::adjoint<double, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
                                          (double*)c->f.p, (double*)c->lam.p, c->mg32.view(), sp, (double*)c->q.p,
-                                         (double*)c->tstar.p, all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                         c->tstar(), all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
                                          (int*)c->did.p, c->N, c->st);
       break;
     case SAA_FP32:
       saa_launch::adjoint<float, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (float*)c->u.p,
                                         (float*)c->f.p, (float*)c->lam.p, c->mg32.view(), sp, (double*)c->q.p,
-                                        (double*)c->tstar.p, all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                        c->tstar(), all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
                                         (int*)c->did.p, c->N, c->st);
       break;
     default:
@@ -176,12 +176,19 @@ int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int all, double* go
   return check_hip(hipGetLastError());
 }
 
-int fill_report(saa_ctx* c, saa_report* rep, double seconds, double t, double dJdt, const PhaseTimer* tm) {
-  CvarStats s{};
-  int rc = check_hip(hipMemcpyAsync(&s, c->stats.p, sizeof(s), hipMemcpyDeviceToHost, c->st));
-  if (rc) return rc;
-  rc = check_hip(hipStreamSynchronize(c->st));
-  if (rc) return rc;
+// Bring the result block to the host (one copy) and wait for the stream.
+int fetch_results(saa_ctx* c) {
+  int rc = check_hip(hipMemcpyAsync(c->hres.p, c->res.p, RES_BYTES, hipMemcpyDeviceToHost, c->st));
+  if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+  return rc;
+}
+
+// Report from the host copy of the result block (fetch_results first).
+int fill_report(saa_ctx* c, saa_report* rep, double seconds, const PhaseTimer* tm) {
+  CvarStats s;
+  std::memcpy(&s, (const char*)c->hres.p + RES_STATS, sizeof(s));
+  const double* h = (const double*)c->hres.p;
+  const double t = h[RES_T], dJdt = h[1];
   if (rep) {
     rep->t_star = t;
     rep->dJ_dt = dJdt;
@@ -320,10 +327,9 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!rc) rc = c->lin_adj.alloc_zero((size_t)N_max * sizeof(int), c->st);
   if (!rc) rc = c->flag.alloc_zero((size_t)N_max * sizeof(int), c->st);
   if (!rc) rc = c->did.alloc_zero((size_t)N_max * sizeof(int), c->st);
-  if (!rc) rc = c->tstar.alloc(sizeof(double));
   if (!rc) rc = c->zdev.alloc(SAA_MAX_DZ * sizeof(double));
-  if (!rc) rc = c->out.alloc((2 + SAA_MAX_DZ) * sizeof(double));
-  if (!rc) rc = c->stats.alloc(sizeof(CvarStats));
+  if (!rc) rc = c->res.alloc_zero(RES_BYTES, c->st);
+  if (!rc) rc = c->hres.alloc(RES_BYTES);
   if (!rc) rc = c->cwork.alloc(saa_launch::cvar_work_bytes());
   if (!rc) rc = c->timer.create();
   if (!rc) rc = c->order.alloc(sizeof(int) * (size_t)c->K1 * c->K1);
@@ -414,15 +420,15 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
     tm.mark(c->st, 1);
     saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, (double*)c->tstar.p, (double*)c->out.p,
+                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, c->tstar(), c->out(),
                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->cwork.p, c->st);
     tm.mark(c->st, 2);
     if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
     tm.mark(c->st, 3);
     saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, (double*)c->tstar.p, (double*)c->out.p,
+                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, c->tstar(), c->out(),
                      (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
-                     c->stats.p, c->cwork.p, c->st);
+                     c->stats(), c->cwork.p, c->st);
   } else {
     // surrogate: q and dq/dz of every sample in one fused launch, then the reduction
     if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p,
@@ -432,21 +438,17 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     tm.mark(c->st, 2);
     tm.mark(c->st, 3);
     saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p,
-                     nullptr, nullptr, nullptr, nullptr, nullptr, c->stats.p, c->cwork.p, c->st);
+                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 3, c->tstar(), c->out(),
+                     nullptr, nullptr, nullptr, nullptr, nullptr, c->stats(), c->cwork.p, c->st);
   }
   tm.mark(c->st, 4);
   if ((rc = check_hip(hipGetLastError()))) return rc;
-  double host[2 + SAA_MAX_DZ];
-  double t = 0;
-  if ((rc = check_hip(hipMemcpyAsync(host, c->out.p, sizeof(double) * (2 + c->dz), hipMemcpyDeviceToHost, c->st))))
-    return rc;
-  if ((rc = check_hip(hipMemcpyAsync(&t, c->tstar.p, sizeof(double), hipMemcpyDeviceToHost, c->st)))) return rc;
-  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  if ((rc = fetch_results(c))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const double* host = (const double*)c->hres.p;
   *J = host[0];
   for (int k = 0; k < c->dz; ++k) grad_z[k] = host[2 + k];
-  return fill_report(c, rep, secs, t, host[1], &tm);
+  return fill_report(c, rep, secs, &tm);
 }
 
 int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model, const saa_options* opt,
@@ -513,23 +515,20 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
     if ((rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
       return rc;
     saa_launch::cvar((double*)c->q.p, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p,
-                     opt->t_mode, opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p,
-                     (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats.p,
+                     opt->t_mode, opt->t_in, 3, c->tstar(), c->out(), (int*)c->newton.p,
+                     (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats(),
                      c->cwork.p, c->st);
   } else {
     if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, q_dev, g_dev)))
       return rc;
     saa_launch::cvar(q_dev, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p, opt->t_mode,
-                     opt->t_in, 3, (double*)c->tstar.p, (double*)c->out.p, nullptr, nullptr, nullptr, nullptr,
-                     nullptr, c->stats.p, c->cwork.p, c->st);
+                     opt->t_in, 3, c->tstar(), c->out(), nullptr, nullptr, nullptr, nullptr,
+                     nullptr, c->stats(), c->cwork.p, c->st);
   }
   if ((rc = check_hip(hipGetLastError()))) return rc;
-  double t = 0, host[2];
-  if ((rc = check_hip(hipMemcpyAsync(host, c->out.p, sizeof(double) * 2, hipMemcpyDeviceToHost, c->st)))) return rc;
-  if ((rc = check_hip(hipMemcpyAsync(&t, c->tstar.p, sizeof(double), hipMemcpyDeviceToHost, c->st)))) return rc;
-  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  if ((rc = fetch_results(c))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return fill_report(c, rep, secs, t, host[1], nullptr);
+  return fill_report(c, rep, secs, nullptr);
 }
 
 int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
@@ -569,12 +568,14 @@ int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, do
   }
   // stats only (phase 0)
   saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, 0.0, 1.0, 0.0, (double*)c->zdev.p, 1, 0.0, 0,
-                   (double*)c->tstar.p, (double*)c->out.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
-                   (int*)c->lin_adj.p, nullptr, c->stats.p, c->cwork.p, c->st);
+                   c->tstar(), c->out(), (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
+                   (int*)c->lin_adj.p, nullptr, c->stats(), c->cwork.p, c->st);
   if ((rc = check_hip(hipGetLastError()))) return rc;
-  if ((rc = check_hip(hipStreamSynchronize(c->st)))) return rc;
+  if ((rc = fetch_results(c))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return fill_report(c, rep, secs, 0.0, 0.0, nullptr);
+  rc = fill_report(c, rep, secs, nullptr);
+  if (rep) rep->t_star = rep->dJ_dt = 0.0;   // no CVaR reduction here
+  return rc;
 }
 
 int saa_sample_status(saa_ctx* c, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters) {

@@ -70,6 +70,10 @@ inline int check_hip(hipError_t e) { return e == hipSuccess ? SAA_OK : SAA_E_DEV
 
 }  // namespace saa_rt
 
+constexpr size_t RES_T = 2 + SAA_MAX_DZ;                   // index of t (doubles)
+constexpr size_t RES_STATS = sizeof(double) * (RES_T + 1);   // byte offset of the statistics
+constexpr size_t RES_BYTES = RES_STATS + sizeof(CvarStats);
+
 struct saa_ctx {
   saa_problem prob{};
   int64_t N_max = 0;
@@ -83,11 +87,19 @@ struct saa_ctx {
   saa_rt::MgStore<double> mg64;
   saa_rt::MgStore<float> mg32;
   saa_rt::DevBuf u, f, lam;   // PDE-form node vectors (sized for float64; allocated at first use)
-  saa_rt::DevBuf q, g, newton, lin, lin_adj, flag, did, tstar, zdev, out, stats;
+  saa_rt::DevBuf q, g, newton, lin, lin_adj, flag, did, zdev;
+  // Results of one call, contiguous so that one copy brings them to the host:
+  // doubles [0] J, [1] dJ/dt, [2, 2 + d_Z) grad, [2 + SAA_MAX_DZ] t, then the
+  // solver statistics (CvarStats) at byte RES_STATS.
+  saa_rt::DevBuf res;
+  saa_rt::HostBuf hres;       // pinned host copy of `res`
   saa_rt::DevBuf cwork;       // CVaR reduction workspace (partials, probe histograms, active set)
   saa_rt::DevBuf enc;         // surrogate input: leading KL coordinates as BF16, N_max x 128
   int enc_rm = -1;            // r_m that `enc` holds for the installed samples (-1: stale)
   saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
   saa_rt::PhaseTimer timer;
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)
+  double* out() { return (double*)res.p; }
+  double* tstar() { return (double*)res.p + RES_T; }
+  void* stats() { return (char*)res.p + RES_STATS; }
 };

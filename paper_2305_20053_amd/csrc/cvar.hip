@@ -110,21 +110,34 @@ struct Bracket {
 // workgroup gets the same result.  No LDS, no barrier.
 __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double eps, double target, double N) {
   const int lane = threadIdx.x & (SAA_WAVE - 1);
+  // every load is issued up front (none depends on the bracket): one memory
+  // round trip instead of one per pass
   double mn = INFINITY, mx = -INFINITY;
-  for (int b = lane; b < G; b += SAA_WAVE) {
-    mn = fmin(mn, w.mm[2 * b]);
-    mx = fmax(mx, w.mm[2 * b + 1]);
+  int hc1[PASSES], hc2[PASSES];
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) {
+    hc1[p] = p < passes ? w.hist[p * 2 * NB + lane + 1] : 0;
+    hc2[p] = p < passes ? w.hist[p * 2 * NB + NB + lane + 1] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < GMAX / SAA_WAVE; ++k) {
+    const int b = lane + k * SAA_WAVE;
+    if (b < G) {
+      mn = fmin(mn, w.mm[2 * b]);
+      mx = fmax(mx, w.mm[2 * b + 1]);
+    }
   }
   Bracket br;
   br.lo = wave_min(mn) - eps;
   br.hi = wave_max(mx);
   br.live = target < N;
-  for (int p = 0; p < passes; ++p) {
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) {
+    if (p >= passes) break;
     br.live = br.live && (br.hi - br.lo > 4.0 * eps);
     if (!br.live) break;
-    const int* h = w.hist + p * 2 * NB;
     // suffix sums over the bins above probe `lane`: #{q > probe}, #{q > probe + eps}
-    int c1 = h[lane + 1], c2 = h[NB + lane + 1];
+    int c1 = hc1[p], c2 = hc2[p];
 #pragma unroll
     for (int off = 1; off < SAA_WAVE; off <<= 1) {
       const int y1 = __shfl_down(c1, off, SAA_WAVE);
@@ -505,13 +518,16 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
   }
   __syncthreads();
   const int k = threadIdx.x;
+  double zz = 0.0;
+  if (k < SAA_WAVE) {   // |z|^2 by the whole of wave 0, one load per lane
+    const double zl = k < dz ? z[k] : 0.0;
+    zz = wave_sum(zl * zl);
+  }
   if (k >= ncol) return;
   double acc = 0.0;
   for (int r = 0; r < NW; ++r) acc += col[r][k];
   const double scale = 1.0 / target;
   if (k == 0) {
-    double zz = 0.0;
-    for (int c = 0; c < dz; ++c) zz += z[c] * z[c];
     out[0] = tstar[0] + scale * acc + 0.5 * alpha * zz;
   } else if (k == 1) {
     out[1] = 1.0 - scale * acc;

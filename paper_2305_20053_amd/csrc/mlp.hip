@@ -209,7 +209,9 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
   if (f >= width) return;
   const float* w = W0 + (int64_t)f * (r_m + d_z) + r_m;
   float acc = b0[f];
-  for (int k = 0; k < d_z; ++k) acc += w[k] * (float)z[k];
+#pragma unroll
+  for (int k = 0; k < 32; ++k)   // d_z <= 32: every load issued at once
+    if (k < d_z) acc += w[k] * (float)z[k];
   b0eff[f] = acc;
 }
 

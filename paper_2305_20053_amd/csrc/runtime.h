@@ -9,6 +9,27 @@
 namespace saa_rt {
 
 // Owning device allocation; freed on destruction.
+// Pinned host memory (hipHostMalloc), freed with the owner.
+struct HostBuf {
+  void* p = nullptr;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  int alloc(size_t n) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return SAA_E_OOM;
+    }
+    return SAA_OK;
+  }
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
