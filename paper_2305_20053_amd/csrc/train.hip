@@ -5,6 +5,8 @@
 // Layouts (row-major): activations H, A are B x W; tangents are (B d_Z) x W
 // with row b d_Z + k holding the derivative with respect to z_k of sample b;
 // reduced targets Y are B x r_u and JY (B d_Z) x r_u.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -81,6 +83,18 @@ __global__ void __launch_bounds__(256) saa_k_gemm(int M, int N, int K, T alpha, 
       *c = alpha * acc[i][j] + (beta == (T)0 ? (T)0 : beta * *c);
     }
   }
+}
+
+// Split-K epilogue: C = alpha * sum_z P[z] + beta * C, slices summed in order
+// (deterministic).  P holds S partial M x N products (row-major).
+template <typename T>
+__global__ void saa_k_splitk_sum(int M, int N, int S, const T* P, T alpha, T beta, T* C, int ldc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)M * N) return;
+  T acc = (T)0;
+  for (int z = 0; z < S; ++z) acc += P[(int64_t)z * M * N + t];
+  T* c = C + (t / N) * (int64_t)ldc + (t % N);
+  *c = alpha * acc + (beta == (T)0 ? (T)0 : beta * *c);
 }
 
 // out[s][p] = (M_II (u_s - ubar))_p on the (n-1)^2 interior grid (dense
@@ -207,22 +221,35 @@ __global__ void saa_k_layer_back(float* gH, float* gJH, const float* A, const fl
 }
 
 // Column sums (bias gradients): out[c] = sum_r X[r][c].
-__global__ void saa_k_colsum(const float* X, int64_t rows, int cols, float* out, int accumulate) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// Column sums over `rows` rows: 256 threads = 8 row groups x 32 columns; the
+// groups are summed in order (deterministic).
+__device__ __forceinline__ float colsum_block(const float* X, int64_t rows, int64_t ld, int cols, int c) {
+  __shared__ float part[8][32];
+  const int cl = threadIdx.x & 31, rg = threadIdx.x >> 5;
   float s = 0.0f;
-  for (int64_t r = 0; r < rows; ++r) s += X[r * cols + c];
-  out[c] = accumulate ? out[c] + s : s;
+  if (c < cols)
+    for (int64_t r = rg; r < rows; r += 8) s += X[r * ld + c];
+  part[rg][cl] = s;
+  __syncthreads();
+  float t = 0.0f;
+  for (int k = 0; k < 8; ++k) t += part[k][cl];
+  return t;
+}
+
+// out[c] (+)= sum_r X[r][c], X rows x cols row-major.
+__global__ void __launch_bounds__(256) saa_k_colsum(const float* X, int64_t rows, int cols, float* out,
+                                                    int accumulate) {
+  const int c = blockIdx.x * 32 + (threadIdx.x & 31);
+  const float t = colsum_block(X, rows, cols, cols, c);
+  if (threadIdx.x < 32 && c < cols) out[c] = accumulate ? out[c] + t : t;
 }
 
 // dW_0[f][r_m + k] += sum_b gJA_0[b d_Z + k][f]  (the constant first-layer tangent).
-__global__ void saa_k_w0z_grad(const float* gJA, int B, int d_z, int W, int r_m, int ldw, float* dW0) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d_z * W) return;
-  const int k = t / W, f = t % W;
-  float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += gJA[((int64_t)b * d_z + k) * W + f];
-  dW0[(int64_t)f * ldw + r_m + k] += s;
+__global__ void __launch_bounds__(256) saa_k_w0z_grad(const float* gJA, int B, int d_z, int W, int r_m, int ldw,
+                                                      float* dW0) {
+  const int c = blockIdx.x * 32 + (threadIdx.x & 31);   // c = k W + f
+  const float t = colsum_block(gJA, B, (int64_t)d_z * W, d_z * W, c);
+  if (threadIdx.x < 32 && c < d_z * W) dW0[(int64_t)(c % W) * ldw + r_m + c / W] += t;
 }
 
 // Adam (bias-corrected), FP32 master parameters.
@@ -275,17 +302,38 @@ static inline unsigned nb(int64_t n, int b = 256) { return (unsigned)((n + b - 1
 
 template <typename T>
 void gemm(bool ta, bool tb, int M, int N, int K, T alpha, const T* A, int lda, int64_t sA, const T* B, int ldb,
-          int64_t sB, T beta, T* C, int ldc, int64_t sC, int batch, hipStream_t st) {
+          int64_t sB, T beta, T* C, int ldc, int64_t sC, int batch, hipStream_t st, T* work, int64_t work_elems) {
   dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, batch);
+  // few output tiles and a long K (weight gradients: K = batch x tangents):
+  // split K into S equal slices computed in parallel, then summed in order
+  const int64_t tiles = (int64_t)grid.x * grid.y;
+  int S = 1;
+  if (work && batch == 1 && tiles < 128 && K >= 2048)
+    for (int s = (int)std::min<int64_t>(64, 512 / tiles); s >= 2; --s)
+      if (K % s == 0 && (int64_t)s * M * N <= work_elems) {
+        S = s;
+        break;
+      }
+  if (S > 1) {
+    const int ks = K / S;
+    const int64_t zA = ta ? (int64_t)ks * lda : ks, zB = tb ? ks : (int64_t)ks * ldb, zC = (int64_t)M * N;
+    dim3 g2(grid.x, grid.y, S);
+    if (!ta && !tb) saa_k_gemm<T, false, false><<<g2, 256, 0, st>>>(M, N, ks, (T)1, A, lda, zA, B, ldb, zB, (T)0, work, N, zC);
+    else if (ta && !tb) saa_k_gemm<T, true, false><<<g2, 256, 0, st>>>(M, N, ks, (T)1, A, lda, zA, B, ldb, zB, (T)0, work, N, zC);
+    else if (!ta && tb) saa_k_gemm<T, false, true><<<g2, 256, 0, st>>>(M, N, ks, (T)1, A, lda, zA, B, ldb, zB, (T)0, work, N, zC);
+    else saa_k_gemm<T, true, true><<<g2, 256, 0, st>>>(M, N, ks, (T)1, A, lda, zA, B, ldb, zB, (T)0, work, N, zC);
+    saa_k_splitk_sum<T><<<nb((int64_t)M * N), 256, 0, st>>>(M, N, S, work, alpha, beta, C, ldc);
+    return;
+  }
   if (!ta && !tb) saa_k_gemm<T, false, false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (ta && !tb) saa_k_gemm<T, true, false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else if (!ta && tb) saa_k_gemm<T, false, true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
   else saa_k_gemm<T, true, true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
 }
 template void gemm<float>(bool, bool, int, int, int, float, const float*, int, int64_t, const float*, int, int64_t,
-                          float, float*, int, int64_t, int, hipStream_t);
+                          float, float*, int, int64_t, int, hipStream_t, float*, int64_t);
 template void gemm<double>(bool, bool, int, int, int, double, const double*, int, int64_t, const double*, int,
-                           int64_t, double, double*, int, int64_t, int, hipStream_t);
+                           int64_t, double, double*, int, int64_t, int, hipStream_t, double*, int64_t);
 
 void mass_rows(const double* U, int64_t ldu, const double* ubar, double* out, int64_t ldo, int n, int64_t rows,
                hipStream_t st) {
@@ -321,10 +369,10 @@ void layer_back(float* gH, float* gJH, const float* A, const float* JA, int B, i
   saa_k_layer_back<<<nb((int64_t)B * W), 256, 0, st>>>(gH, gJH, A, JA, B, d_z, W, dino);
 }
 void colsum(const float* X, int64_t rows, int cols, float* out, int accumulate, hipStream_t st) {
-  saa_k_colsum<<<nb(cols), 256, 0, st>>>(X, rows, cols, out, accumulate);
+  saa_k_colsum<<<(unsigned)((cols + 31) / 32), 256, 0, st>>>(X, rows, cols, out, accumulate);
 }
 void w0z_grad(const float* gJA, int B, int d_z, int W, int r_m, int ldw, float* dW0, hipStream_t st) {
-  saa_k_w0z_grad<<<nb((int64_t)d_z * W), 256, 0, st>>>(gJA, B, d_z, W, r_m, ldw, dW0);
+  saa_k_w0z_grad<<<(unsigned)((d_z * W + 31) / 32), 256, 0, st>>>(gJA, B, d_z, W, r_m, ldw, dW0);
 }
 void adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps, float c1,
           float c2, hipStream_t st) {
