@@ -3,6 +3,7 @@
 // with Wilkinson shifts, accumulating the orthogonal transformations.
 #include <cmath>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "../../include/saa.h"
@@ -58,15 +59,23 @@ void tridiagonalize(int n, double* A, double* d, double* e) {
   std::vector<double> Q((int64_t)n * n, 0.0);
   auto q = [&](int i, int j) -> double& { return Q[(int64_t)i * n + j]; };
   for (int i = 0; i < n; ++i) q(i, i) = 1.0;
+  std::vector<double> sv(n);
   for (int k = 2; k < n; ++k) {
     const double h = d[k];
     if (h == 0.0) continue;
-    // Q <- (I - u u^T / h) Q on rows 0..k-1 (u = stored row k, length k)
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < k; ++i) s += a(k, i) * q(i, j);
-      s /= h;
-      for (int i = 0; i < k; ++i) q(i, j) -= s * a(k, i);
+    // Q <- (I - u u^T / h) Q on rows 0..k-1 (u = stored row k, length k):
+    // s = u^T Q / h, then Q -= u s^T, both as row sweeps
+    for (int j = 0; j < n; ++j) sv[j] = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const double ui = a(k, i);
+      const double* qi = &q(i, 0);
+      for (int j = 0; j < n; ++j) sv[j] += ui * qi[j];
+    }
+    for (int j = 0; j < n; ++j) sv[j] /= h;
+    for (int i = 0; i < k; ++i) {
+      const double ui = a(k, i);
+      double* qi = &q(i, 0);
+      for (int j = 0; j < n; ++j) qi[j] -= ui * sv[j];
     }
   }
   for (int i = 0; i < n; ++i) d[i] = a(i, i);
@@ -74,8 +83,9 @@ void tridiagonalize(int n, double* A, double* d, double* e) {
 }
 
 // Eigenvalues of the symmetric tridiagonal (d, e) by implicit QL with
-// Wilkinson shifts; the rotations are applied to the columns of Z.
-int tridiagonal_ql(int n, double* d, double* e, double* Z) {
+// Wilkinson shifts; the rotations are applied to the rows of Zt (= Z^T, so
+// that row i of Zt ends as eigenvector i).
+int tridiagonal_ql(int n, double* d, double* e, double* Zt) {
   for (int i = 1; i < n; ++i) e[i - 1] = e[i];
   if (n > 0) e[n - 1] = 0.0;
   for (int l = 0; l < n; ++l) {
@@ -111,10 +121,12 @@ int tridiagonal_ql(int n, double* d, double* e, double* Z) {
         p = s * r;
         d[i + 1] = g + p;
         g = c * r - b;
-        for (int k = 0; k < n; ++k) {   // rotate columns i, i+1 of Z
-          f = Z[(int64_t)k * n + i + 1];
-          Z[(int64_t)k * n + i + 1] = s * Z[(int64_t)k * n + i] + c * f;
-          Z[(int64_t)k * n + i] = c * Z[(int64_t)k * n + i] - s * f;
+        double* zi = Zt + (int64_t)i * n;   // rotate rows i, i+1 of Zt
+        double* zj = zi + n;
+        for (int k = 0; k < n; ++k) {
+          f = zj[k];
+          zj[k] = s * zi[k] + c * f;
+          zi[k] = c * zi[k] - s * f;
         }
       }
       if (r == 0.0 && i >= l) continue;
@@ -140,8 +152,13 @@ extern "C" int saa_sym_eig(int n, const double* A, double* w, double* V) {
       M[(int64_t)i * n + j] = M[(int64_t)j * n + i] = s;
     }
   tridiagonalize(n, M.data(), d.data(), e.data());
+  // transpose Q so that the QL rotations work on contiguous rows
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) std::swap(M[(int64_t)i * n + j], M[(int64_t)j * n + i]);
   int rc = tridiagonal_ql(n, d.data(), e.data(), M.data());
   if (rc) return rc;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) std::swap(M[(int64_t)i * n + j], M[(int64_t)j * n + i]);
   // sort descending, columns of V are the eigenvectors
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
