@@ -55,6 +55,8 @@ constexpr int GMAX = 256;         // workgroups of the multi-workgroup passes
 constexpr int TILE = 4 * RBS;     // samples per compaction tile
 constexpr int PSTRIDE = 2 + SAA_MAX_DZ;
 constexpr int WAVE_NEWTON = 256;  // active sets up to this size are solved by one wave
+constexpr int RPASSES = 4;        // refinement passes when the active set overflows
+constexpr double FIX_SCALE = 274877906944.0;   // 2^38: fixed-point scale of the refinement sums
 static_assert(NP == SAA_WAVE, "one probe per lane");
 static_assert(SAA_MAX_DZ <= SAA_WAVE, "one gradient component per lane");
 
@@ -66,24 +68,27 @@ struct CvarWork {
   int* hist;      // [PASSES][2][NB] probe histograms
   int* nact;      // [GMAX] active samples per workgroup
   int* nabove;    // [GMAX] samples at or above hi + eps per workgroup
+  int* act_total; // [1] active samples over all workgroups
+  unsigned long long* fix;   // [RPASSES][NP] Phi at the refinement probes, fixed point 2^38
 };
 
-__device__ __forceinline__ double sp_val(double x, double e) {
+// s_eps and its derivatives; ie = 1 / e (one division per kernel, not per sample)
+__device__ __forceinline__ double sp_val(double x, double e, double ie) {
   if (x <= 0.0) return 0.0;
   if (x >= e) return x - 0.5 * e;
-  const double r = x / e;
+  const double r = x * ie;
   return x * r * r * (1.0 - 0.5 * r);      // x^3/e^2 - x^4/(2 e^3)
 }
-__device__ __forceinline__ double sp_d1(double x, double e) {
+__device__ __forceinline__ double sp_d1(double x, double e, double ie) {
   if (x <= 0.0) return 0.0;
   if (x >= e) return 1.0;
-  const double r = x / e;
+  const double r = x * ie;
   return r * r * (3.0 - 2.0 * r);          // 3x^2/e^2 - 2x^3/e^3
 }
-__device__ __forceinline__ double sp_d2(double x, double e) {
+__device__ __forceinline__ double sp_d2(double x, double e, double ie) {
   if (x <= 0.0 || x >= e) return 0.0;
-  const double r = x / e;
-  return 6.0 * r * (1.0 - r) / e;          // 6x/e^2 - 6x^2/e^3
+  const double r = x * ie;
+  return 6.0 * r * (1.0 - r) * ie;         // 6x/e^2 - 6x^2/e^3
 }
 
 // Probe j of a pass over [lo, hi]; non-decreasing in j for any rounding.
@@ -243,8 +248,11 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_
     w.mm[2 * blockIdx.x] = mn;
     w.mm[2 * blockIdx.x + 1] = mx;
   }
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < PASSES * 2 * NB; k += RBS) w.hist[k] = 0;
+    for (int k = threadIdx.x; k < RPASSES * NP; k += RBS) w.fix[k] = 0;
+    if (threadIdx.x == 0) w.act_total[0] = 0;
+  }
 }
 
 // 2. bracketing pass p: probe histograms of this workgroup's chunk.
@@ -329,6 +337,78 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_compact(const double* q, int64
     for (int k = 0; k < RBS / SAA_WAVE; ++k) a += sh[k];
     w.nact[blockIdx.x] = base;
     w.nabove[blockIdx.x] = a;
+    // a segment overflow counts as an overflow of the whole active set
+    if (base > 0) atomicAdd(w.act_total, base > SEG ? base + CAP + 1 : base);
+  }
+}
+
+// Bracket after the count passes and `passes` refinement passes.  Pass r
+// evaluated Phi exactly at the 64 points lo + j (hi - lo) / 63 (sums over all
+// workgroups in 2^-38 fixed point, so their order does not matter); the new
+// bracket is the pair of neighbouring points where Phi crosses the target.
+// plo, phi hold Phi at the ends once a refinement pass has run (else -1).
+// Every wave gets the same result.
+__device__ Bracket bracket_refined(const CvarWork& w, int G, int passes, double eps, double target, double N,
+                                   double& plo, double& phi) {
+  const int lane = threadIdx.x & (SAA_WAVE - 1);
+  Bracket br = bracket_after(w, G, PASSES, eps, target, N);
+  plo = phi = -1.0;
+  unsigned long long f[RPASSES];
+#pragma unroll
+  for (int r = 0; r < RPASSES; ++r) f[r] = r < passes ? w.fix[r * NP + lane] : 0ull;
+#pragma unroll
+  for (int r = 0; r < RPASSES; ++r) {
+    if (r >= passes || !(br.hi - br.lo > 8.0 * DBL_EPSILON * fmax(fabs(br.lo), fabs(br.hi)))) break;
+    const double step = (br.hi - br.lo) / (NP - 1);
+    const double pv = (double)f[r] * (1.0 / FIX_SCALE);
+    const int jl = (int)wave_max((double)((lane < NP - 1 && pv > target) ? lane : 0));
+    const double tl = br.lo + (double)jl * step;
+    const double th = jl + 1 == NP - 1 ? br.hi : br.lo + (double)(jl + 1) * step;
+    plo = __shfl(pv, jl, SAA_WAVE);
+    phi = __shfl(pv, jl + 1, SAA_WAVE);
+    br.lo = tl;
+    br.hi = th;
+  }
+  return br;
+}
+
+// 3b. refinement pass r (only when the active set overflowed its capacity):
+// Phi at 64 points of the current bracket, lane j evaluating point j over the
+// window samples of this workgroup's chunk.
+__global__ void __launch_bounds__(RBS) saa_k_cvar_refine(const double* q, int64_t N, CvarWork w, int G, int r,
+                                                         double eps, double target) {
+  __shared__ double part[RBS / SAA_WAVE][NP];
+  __shared__ double qt[TILE];
+  if (!(target < (double)N) || w.act_total[0] <= CAP) return;
+  double plo, phi;
+  const Bracket br = bracket_refined(w, G, r, eps, target, (double)N, plo, phi);
+  if (!(br.hi - br.lo > 8.0 * DBL_EPSILON * fmax(fabs(br.lo), fabs(br.hi)))) return;
+  const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
+  const double ie = 1.0 / eps;
+  const double step = (br.hi - br.lo) / (NP - 1);
+  const double tj = lane == NP - 1 ? br.hi : br.lo + (double)lane * step;
+  const double top = br.hi + eps;
+  int64_t i0, i1;
+  chunk_of(N, G, i0, i1);
+  double acc = 0.0;
+  for (int64_t t0 = i0; t0 < i1; t0 += TILE) {
+    const int nt = (int)(i1 - t0 < TILE ? i1 - t0 : TILE);
+    for (int i = threadIdx.x; i < nt; i += RBS) qt[i] = q[t0 + i];
+    __syncthreads();
+    // wave wid takes every 4th sample of the tile; all lanes see the same sample
+    for (int i = wid; i < nt; i += RBS / SAA_WAVE) {
+      const double x = qt[i];
+      if (x >= top) acc += 1.0;
+      else if (x > br.lo) acc += sp_d1(x - tj, eps, ie);
+    }
+    __syncthreads();
+  }
+  part[wid][lane] = acc;
+  __syncthreads();
+  if (wid == 0) {
+    double v = 0.0;
+    for (int k = 0; k < RBS / SAA_WAVE; ++k) v += part[k][lane];
+    if (v > 0.0) atomicAdd(&w.fix[r * NP + lane], (unsigned long long)llrint(v * FIX_SCALE));
   }
 }
 
@@ -339,6 +419,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
   __shared__ int off[GMAX + 1];
   __shared__ int sh[SBS / SAA_WAVE];
   __shared__ double s[CAP];
+  const double ie = 1.0 / eps;
   if (t_mode == 1) {
     if (threadIdx.x == 0) tstar[0] = t_in;
     return;
@@ -358,7 +439,9 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
   if (threadIdx.x < G && cb > SEG) fits = false;
   int ex2;
   const double above = (double)block_scan(ab, &ex2, sh);
-  fits = __syncthreads_and(fits) && n <= CAP;
+  // the same test as the refinement passes (a segment overflow also pushes
+  // act_total above CAP)
+  fits = __syncthreads_and(fits) && n <= CAP && w.act_total[0] <= CAP;
   if (threadIdx.x == 0) off[G] = n;
   __syncthreads();
   double t;
@@ -378,8 +461,8 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
       t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
         double a0 = 0.0, a1 = 0.0;
         for (int i = threadIdx.x; i < n; i += SAA_WAVE) {
-          a0 += sp_d1(s[i] - tc, eps);
-          a1 += sp_d2(s[i] - tc, eps);
+          a0 += sp_d1(s[i] - tc, eps, ie);
+          a1 += sp_d2(s[i] - tc, eps, ie);
         }
         v[0] = above + wave_sum(a0);
         v[1] = wave_sum(a1);
@@ -388,8 +471,8 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
       t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
         double a[2] = {0.0, 0.0};
         for (int i = threadIdx.x; i < n; i += SBS) {
-          a[0] += sp_d1(s[i] - tc, eps);
-          a[1] += sp_d2(s[i] - tc, eps);
+          a[0] += sp_d1(s[i] - tc, eps, ie);
+          a[1] += sp_d2(s[i] - tc, eps, ie);
         }
         block_sum<2>(a, red);
         v[0] = above + a[0];
@@ -397,16 +480,15 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
       });
     }
   } else {
-    t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
-      double a[2] = {0.0, 0.0};
-      for (int64_t i = threadIdx.x; i < N; i += SBS) {
-        a[0] += sp_d1(q[i] - tc, eps);
-        a[1] += sp_d2(q[i] - tc, eps);
-      }
-      block_sum<2>(a, red);
-      v[0] = a[0];
-      v[1] = a[1];
-    });
+    // the refinement passes narrowed the bracket to (hi - lo) ~ 4 eps / 63^4;
+    // a secant step between its ends (where Phi is known) finishes t*
+    double plo, phi;
+    const Bracket rb = bracket_refined(w, G, RPASSES, eps, target, (double)N, plo, phi);
+    t = 0.5 * (rb.lo + rb.hi);
+    if (plo >= 0.0 && phi >= 0.0 && plo > phi) {
+      const double tn = rb.lo + (plo - target) / (plo - phi) * (rb.hi - rb.lo);
+      if (tn >= rb.lo && tn <= rb.hi) t = tn;
+    }
   }
   if (threadIdx.x == 0) tstar[0] = t;
 }
@@ -423,6 +505,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
   __shared__ double gw[RBS / SAA_WAVE][SAA_WAVE];
   const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
   const double t = tstar[0];
+  const double ie = 1.0 / eps;
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
   double v[2] = {0.0, 0.0};
@@ -436,8 +519,8 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
       d[r] = 0.0;
       if (i < i1) {
         const double x = q[i] - t;
-        v[0] += sp_val(x, eps);
-        d[r] = sp_d1(x, eps);
+        v[0] += sp_val(x, eps, ie);
+        d[r] = sp_d1(x, eps, ie);
         v[1] += d[r];
       }
       n += d[r] != 0.0 ? 1 : 0;
@@ -540,7 +623,7 @@ namespace saa_launch {
 
 size_t cvar_work_bytes() {
   return sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
-         sizeof(int) * ((size_t)PASSES * 2 * NB + 2 * GMAX);
+         sizeof(unsigned long long) * RPASSES * NP + sizeof(int) * ((size_t)PASSES * 2 * NB + 2 * GMAX + 2);
 }
 
 // phase & 1: t (minimiser, or t_in when t_mode = 1) -> tstar[0];
@@ -557,12 +640,16 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
   p += sizeof(double) * (size_t)GMAX * PSTRIDE;
   w.aval = (double*)p;
   p += sizeof(double) * (size_t)GMAX * SEG;
+  w.fix = (unsigned long long*)p;
+  p += sizeof(unsigned long long) * RPASSES * NP;
   w.hist = (int*)p;
   p += sizeof(int) * PASSES * 2 * NB;
   w.nact = (int*)p;
   p += sizeof(int) * GMAX;
   w.nabove = (int*)p;
-  const int64_t gw = (N + 1023) / 1024;
+  p += sizeof(int) * GMAX;
+  w.act_total = (int*)p;
+  const int64_t gw = (N + 255) / 256;   // 256 samples per workgroup, up to GMAX workgroups
   const int G = (int)(gw < 1 ? 1 : gw > GMAX ? GMAX : gw);
   const double target = (double)N * (1.0 - beta);
   if (phase & 1) {
@@ -570,6 +657,7 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
       saa_k_cvar_minmax<<<G, RBS, 0, st>>>(q, N, w, G);
       for (int ps = 0; ps < PASSES; ++ps) saa_k_cvar_probe<<<G, RBS, 0, st>>>(q, N, w, G, ps, eps, target);
       saa_k_cvar_compact<<<G, RBS, 0, st>>>(q, N, w, G, eps, target);
+      for (int r = 0; r < RPASSES; ++r) saa_k_cvar_refine<<<G, RBS, 0, st>>>(q, N, w, G, r, eps, target);
     }
     saa_k_cvar_solve<<<1, SBS, 0, st>>>(q, N, w, G, eps, target, t_mode, t_in, tstar);
   }

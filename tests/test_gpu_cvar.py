@@ -7,8 +7,8 @@ The per-sample values come from the surrogate form with a random network:
 N = 20000 samples is large enough to use many workgroups, and the cases span
 the regimes of the t* search: a few probe passes then an active set of a few
 samples (eps = 1e-4), a wide smoothing zone, an active set larger than its
-capacity (eps far above the spread of q: the search falls back to all N
-samples), beta = 0 (degenerate minimiser), a tail of 20 samples, and a
+capacity (eps far above, or comparable to, the spread of q: multi-workgroup
+refinement passes then a secant step), beta = 0 (degenerate minimiser), a tail of 20 samples, and a
 prescribed t.  Tolerance: 1e-12 relative (only the summation order differs).
 """
 import numpy as np
@@ -47,6 +47,7 @@ def data(gpu_lib):
     (0.95, 1e-4, 0),
     (0.9, 1e-2, 0),
     (0.5, 1e3, 0),       # every sample inside the smoothing zone: active-set overflow
+    (0.95, 2.0, 0),      # eps comparable to the spread of q (trained surrogates): overflow, refinement passes
     (0.0, 1e-4, 0),      # beta = 0: t* = min q - eps
     (0.999, 1e-6, 0),    # tail of 20 samples
     (0.95, 1e-4, 1),     # prescribed t
