@@ -81,6 +81,7 @@ def cpu_baseline(prob, xi, z, seconds_target=15.0):
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+MFMA_FP8_PEAK_TFLOPS = 5000.0
 VEC_FP32_PEAK_TFLOPS = 157.3
 # Algorithmic FLOPs per sample of the surrogate (r_m=100, d_Z=25, width 256,
 # depth 4, r_u=200): forward 2 (125*256 + 3*256^2 + 256*200) and reverse
@@ -145,9 +146,9 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs):
     ctx = saa.Context(prob, N)
     ctx.set_samples(torch.from_numpy(xi).cuda())
     out = {}
-    for name, prec in (("bf16", saa.BF16), ("fp32", saa.FP32)):
+    for name, prec in (("bf16", saa.BF16), ("fp8", saa.FP8), ("fp32", saa.FP32)):
         opt = saa.options(prec=prec)
-        nsteps = steps if prec == saa.BF16 else max(2, steps // 4)
+        nsteps = steps if prec != saa.FP32 else max(2, steps // 4)
         for k in range(warmup):
             ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model, opt=opt)
         torch.cuda.synchronize()
@@ -163,25 +164,27 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs):
         ms_k = float(np.mean([r["ms_state"] for r in reps]))
         ms_r = float(np.mean([r["ms_reduce"] for r in reps]))
         flops = MRDINO_FLOP_PER_SAMPLE * N
-        peak = MFMA_BF16_PEAK_TFLOPS if prec == saa.BF16 else VEC_FP32_PEAK_TFLOPS
+        peak = {saa.BF16: MFMA_BF16_PEAK_TFLOPS, saa.FP8: MFMA_FP8_PEAK_TFLOPS}.get(prec, VEC_FP32_PEAK_TFLOPS)
         ach = flops / (ms_k * 1e-3) / 1e12
         out[name] = {"value": N * nsteps / wall, "ms_per_step": 1e3 * wall / nsteps, "kernel_ms": ms_k,
                      "reduce_ms": ms_r,
-                     "roofline": {"bound": "mfma" if prec == saa.BF16 else "alu", "achieved": ach, "peak": peak,
+                     "roofline": {"bound": "alu" if prec == saa.FP32 else "mfma", "achieved": ach, "peak": peak,
                                   "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                                  "kernel": "saa_k_mlp_bf16" if prec == saa.BF16 else "saa_k_mlp_fp32",
+                                  "kernel": ("saa_k_mlp_fp32" if prec == saa.FP32 else
+                                             f"saa_k_mlp_mfma<{name}>"),
                                   "alg_flop_per_launch": flops}}
-    Jb, gb, _ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
     Jf, gf, _ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32))
-    out["bf16_vs_fp32"] = {"J_rel": abs(Jb - Jf) / abs(Jf),
-                           "grad_rel": float(np.linalg.norm(gb - gf) / np.linalg.norm(gf))}
+    for name, prec in (("bf16", saa.BF16), ("fp8", saa.FP8)):
+        Jb, gb, _ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=prec))
+        out[f"{name}_vs_fp32"] = {"J_rel": abs(Jb - Jf) / abs(Jf),
+                                  "grad_rel": float(np.linalg.norm(gb - gf) / np.linalg.norm(gf))}
     # error estimate against the GPU PDE form on the held-out samples; the
     # fallback rule (estimate > 1e-2) is evaluated here, not executed (the
     # fallback path itself is exercised by tests/test_gpu_gain.py)
     hold = saa.Context(prob, 256)
     hold.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_HELDOUT, 256, prob.kl_per_dim)).cuda())
     saa.attach_holdout(ctx, hold)
-    for name, prec in (("bf16", saa.BF16), ("fp32", saa.FP32)):
+    for name, prec in (("bf16", saa.BF16), ("fp8", saa.FP8), ("fp32", saa.FP32)):
         errs = []
         t0 = time.perf_counter()
         for z in zs:

@@ -63,12 +63,19 @@ enum {
 /* Forms of the objective. */
 enum { SAA_FORM_PDE = 0, SAA_FORM_MRDINO = 1 };
 
-/* Arithmetic precision of the PDE form.
+/* Arithmetic precision.
+ * PDE form:
  *  SAA_FP64      : FP64 everywhere (FP64 multigrid-preconditioned CG).
  *  SAA_FP32      : FP32 everywhere except the final CVaR reduction (FP64).
  *  SAA_FP32_DC64 : FP32 multigrid-preconditioned CG inside FP64 Newton /
  *                  defect correction: residuals, state, adjoint, QoI and
- *                  gradient in FP64. */
+ *                  gradient in FP64.
+ * MR-DINO form (the CVaR reduction is FP64 in every case):
+ *  SAA_FP32      : FP32 network evaluation (reference kernel).
+ *  SAA_BF16      : BF16 operands, FP32 accumulation (MFMA).
+ *  SAA_FP8       : FP8 E4M3 operands with power-of-two scales per weight
+ *                  operand and per sample, FP32 accumulation (MFMA); a few
+ *                  percent less accurate in dq/dz than BF16. */
 enum { SAA_FP64 = 0, SAA_FP32 = 1, SAA_FP32_DC64 = 2, SAA_BF16 = 3, SAA_FP8 = 4 };
 
 /* Problem definition (Sec. 4.2).  Sources f_k(x) = (sigma sqrt(2 pi))^-1
@@ -138,6 +145,9 @@ typedef struct saa_report {
                           surrogate evaluation) kernel, milliseconds */
   double ms_adjoint;   /* ... of the adjoint solves */
   double ms_reduce;    /* ... of the CVaR reductions */
+  int graph;           /* MR-DINO form: 1 if the device work ran as one replay of
+                          the context's captured hipGraph (see saa_objective_grad) */
+  int pad;
 } saa_report;
 
 typedef struct saa_ctx saa_ctx;
@@ -177,7 +187,14 @@ int saa_set_samples(saa_ctx* ctx, int64_t N, const double* xi_dev);
 /* SAA objective and gradient at control z (host, d_Z float64).  form selects
  * the PDE form (model must be NULL) or the MR-DINO surrogate.  J (host, 1) and
  * grad_z (host, d_Z) receive the results; report may be NULL.  Returns
- * SAA_E_NOCONV if some sample did not converge (results still written). */
+ * SAA_E_NOCONV if some sample did not converge (results still written).
+ * MR-DINO form: the second untimed evaluation with the same model, precision,
+ * beta, eps, alpha, t_mode, t_in and sample count captures its device work
+ * (control bias, fused network kernel, CVaR reduction) in a hipGraph owned by
+ * the context; later such calls replay it (report->graph = 1).  z is uploaded
+ * and the results are read outside the graph; parameter updates of the same
+ * model (mrdino_set_params, mrdino_set_qoi) are in place and stay valid;
+ * saa_set_samples drops the graph. */
 int saa_objective_grad(saa_ctx* ctx, const double* z, int form, const void* model,
                        const saa_options* opt, double* J, double* grad_z,
                        saa_report* report);
@@ -274,8 +291,8 @@ int mrdino_set_qoi(mrdino_model* model, const double* c, double c0);
  *   MRDINO_WANT_PHI     phi_dev    N x r_u float32: reduced state phi_i
  *   MRDINO_WANT_DPHIDZ  dphidz_dev N x d_Z x r_u float32: entry (i, k, j) =
  *                       d phi_ij / d z_k (forward mode, eq. (rbnet) derivative)
- * q and dq/dz come from the fused evaluation kernel in `prec` (SAA_FP32 or
- * SAA_BF16); phi and dphi/dz always in float32, through the training forward
+ * q and dq/dz come from the fused evaluation kernel in `prec` (SAA_FP32,
+ * SAA_BF16 or SAA_FP8); phi and dphi/dz always in float32, through the training forward
  * in batches (its workspace stays allocated in the model).  Runs on the
  * model's stream after synchronising the context's; returns once the outputs
  * are written. */

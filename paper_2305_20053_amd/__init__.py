@@ -52,7 +52,7 @@ class CReport(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("newton_max", ctypes.c_int), ("n_unconverged", ctypes.c_int),
                 ("n_adjoints", ctypes.c_int), ("fallback_used", ctypes.c_int), ("lin_total", ctypes.c_int64),
                 ("newton_total", ctypes.c_int64), ("ms_state", ctypes.c_double), ("ms_adjoint", ctypes.c_double),
-                ("ms_reduce", ctypes.c_double)]
+                ("ms_reduce", ctypes.c_double), ("graph", ctypes.c_int), ("pad", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -74,6 +74,34 @@ constexpr size_t RES_T = 2 + SAA_MAX_DZ;                   // index of t (double
 constexpr size_t RES_STATS = sizeof(double) * (RES_T + 1);   // byte offset of the statistics
 constexpr size_t RES_BYTES = RES_STATS + sizeof(CvarStats);
 
+// Captured device work of one MR-DINO evaluation (control bias, fused network
+// kernel, CVaR reduction) and the arguments baked into it.
+struct SurrogateGraph {
+  struct Key {
+    uint64_t model = 0;
+    int prec = -1, t_mode = 0;
+    double beta = 0, eps = 0, alpha = 0, t_in = 0;
+    int64_t N = 0;
+    bool operator==(const Key& o) const {
+      return model == o.model && prec == o.prec && t_mode == o.t_mode && beta == o.beta && eps == o.eps &&
+             alpha == o.alpha && t_in == o.t_in && N == o.N;
+    }
+  };
+  Key key, seen;               // key of `exec`; key of the last eager evaluation
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;   // capture stream (the caller's may be the legacy stream)
+  bool disabled = false;       // capture failed once: stay eager
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key = seen = Key{};
+  }
+  ~SurrogateGraph() {
+    reset();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 struct saa_ctx {
   saa_problem prob{};
   int64_t N_max = 0;
@@ -99,6 +127,7 @@ struct saa_ctx {
   saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
   saa_rt::PhaseTimer timer;
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)
+  SurrogateGraph sg;
   double* out() { return (double*)res.p; }
   double* tstar() { return (double*)res.p + RES_T; }
   void* stats() { return (char*)res.p + RES_STATS; }

@@ -60,17 +60,64 @@ __device__ __forceinline__ float dgelu_f(float a) {
   return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * __expf(-0.5f * a * a);
 }
 
+// Operand formats of the fused kernel.  Both use a 16 x 16 x 32 MFMA with the
+// same lane layout (lane 16 g + c: row / column c, k = 8 g .. 8 g + 8):
+//  OpBF16: BF16 values, 1 KB per 16 x 32 fragment;
+//  OpFP8:  FP8 (E4M3) values, 512 B per fragment.  Weights carry a power-of-two
+//          scale per operand, activations one per sample (from the largest
+//          magnitude of the sample's 256 features), both undone in FP32 after
+//          the product, so only the 3-bit mantissa rounding remains.
+struct OpBF16 {
+  typedef bf16x8 vec;
+  static constexpr int FB = 1024;
+  static constexpr bool scaled = false;
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+  __device__ static vec pack(const float (&v)[8], float) {
+    vec r;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) r[t] = (__bf16)v[t];
+    return r;
+  }
+};
+struct OpFP8 {
+  typedef long vec;
+  static constexpr int FB = 512;
+  static constexpr bool scaled = true;
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+  __device__ static vec pack(const float (&v)[8], float s) {
+    int lo = 0, hi = 0;
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * s, v[1] * s, lo, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * s, v[3] * s, lo, true);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4] * s, v[5] * s, hi, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6] * s, v[7] * s, hi, true);
+    return (long)(unsigned)lo | ((long)hi << 32);
+  }
+};
+
+// Power of two s with m s in [128, 256) (1 for m = 0): the FP8 operand scale
+// of values of largest magnitude m (E4M3 holds magnitudes up to 448).
+__device__ __forceinline__ float pow2_scale(float m, float top) {
+  if (!(m > 0.0f) || !(m < INFINITY)) return 1.0f;
+  int e;
+  (void)frexpf(top / m, &e);
+  e = e - 1 < -60 ? -60 : (e - 1 > 60 ? 60 : e - 1);
+  return ldexpf(1.0f, e);
+}
+
 // Weight stream staged through LDS (see the header).  A fragment is 16 rows x
-// 32 columns of BF16 (1 KB); lane 16 g + c holds row c, columns 8 g .. 8 g + 8.
+// 32 columns (FB bytes); lane 16 g + c holds row c, columns 8 g .. 8 g + 8.
 // The stream holds the fragments of every operand in consumption order:
 // operand by operand, and inside one operand k-step by k-step, 16-row tile by
-// tile.  Stage s = fragments [s F, (s + 1) F) = one contiguous F KB block.
-template <int WAVES, int F>
+// tile.  Stage s = fragments [s F, (s + 1) F) = one contiguous block.
+template <int WAVES, int F, class OP>
 struct WStream {
+  typedef OP Op;
   static constexpr int FR = F;
-  static constexpr int PER = F / WAVES;   // 16-byte units per thread per stage
-  static constexpr int UNITS = F * 64;    // 16-byte units per stage
-  static_assert(F % WAVES == 0, "a stage splits evenly over the threads");
+  static constexpr int UNITS = F * OP::FB / 16;          // 16-byte units per stage
+  static constexpr int PER = UNITS / (WAVES * 64);       // per thread per stage
+  static_assert(UNITS % (WAVES * 64) == 0, "a stage splits evenly over the threads");
   const uint4* src;   // the stream
   uint4* buf;         // two LDS stage buffers
   int nst;            // stages in the stream
@@ -95,8 +142,9 @@ struct WStream {
     s = 0;
     __syncthreads();
   }
-  __device__ __forceinline__ bf16x8 frag(int j) const {
-    return *(const bf16x8*)(buf + (s & 1) * UNITS + j * 64 + (threadIdx.x & 63));
+  __device__ __forceinline__ typename OP::vec frag(int j) const {
+    const char* b = (const char*)(buf + (s & 1) * UNITS);
+    return *(const typename OP::vec*)(b + j * OP::FB + (threadIdx.x & 63) * (OP::FB / 64));
   }
   // End of stage s: publish stage s + 1 (its buffer held stage s - 1, which
   // every wave finished before the previous barrier), then prefetch s + 3.
@@ -112,15 +160,40 @@ struct WStream {
 
 // acc[mt] += A(mt, ks) * hb[ks] for ks < NK, mt < MT, with the A fragments
 // taken from the stream in order.
-template <int MT, int NK, int KSA, class S>
-__device__ __forceinline__ void stream_gemm(S& ws, const bf16x8 (&hb)[KSA], f32x4 (&acc)[MT]) {
+template <int MT, int NK, int KSA, class S, class V>
+__device__ __forceinline__ void stream_gemm(S& ws, const V (&hb)[KSA], f32x4 (&acc)[MT]) {
   static_assert((MT * NK) % S::FR == 0, "operands start and end on stage boundaries");
 #pragma unroll
   for (int f = 0; f < MT * NK; ++f) {
     const int ks = f / MT, mt = f % MT;
-    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ws.frag(f % S::FR), hb[ks], acc[mt], 0, 0, 0);
+    acc[mt] = S::Op::mma(ws.frag(f % S::FR), hb[ks], acc[mt]);
     if (f % S::FR == S::FR - 1) ws.advance();
   }
+}
+
+// Operands of the next product from the 64 FP32 values of a lane (4 per
+// 16-feature tile; tiles 2 ks, 2 ks + 1 form k-step ks).  Returns the
+// per-sample scale applied (1 for unscaled formats).
+template <class OP, int MT, int KS>
+__device__ __forceinline__ float pack_all(const f32x4 (&v)[MT], typename OP::vec (&hb)[KS]) {
+  float sc = 1.0f;
+  if constexpr (OP::scaled) {
+    float m = 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(v[mt][r]));
+    m = fmaxf(m, __shfl_xor(m, 16, 64));
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    sc = pow2_scale(m, 256.0f);
+  }
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const float e[8] = {v[2 * ks][0],     v[2 * ks][1],     v[2 * ks][2],     v[2 * ks][3],
+                        v[2 * ks + 1][0], v[2 * ks + 1][1], v[2 * ks + 1][2], v[2 * ks + 1][3]};
+    hb[ks] = OP::pack(e, sc);
+  }
+  return sc;
 }
 
 }  // namespace
@@ -216,24 +289,30 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
 }
 
 // ---------------------------------------------------------------------------
-// Fused BF16 forward + reverse kernel
+// Fused MFMA forward + reverse kernel (BF16 or FP8 operands, FP32 accumulation)
 // ---------------------------------------------------------------------------
-template <int W, int KIN, int DEPTH, int WAVES, int NZT, int F>
+// Operand index of each product in the weight stream (its scale in net.wsc):
+// forward layers 0..DEPTH, reverse layers DEPTH..1 -> DEPTH + 1.., w0z last.
+template <int W, int KIN, int DEPTH, int WAVES, int NZT, int F, class OP>
 __global__ void __launch_bounds__(WAVES * 64, 1)
-    saa_k_mlp_bf16(MlpDev net, const __bf16* xenc, int64_t N, double* q_out, double* g_out) {
+    saa_k_mlp_mfma(MlpDev net, const __bf16* xenc, int64_t N, double* q_out, double* g_out) {
   constexpr int MT = W / 16;   // 16-feature tiles of a layer output
   constexpr int KS = W / 32;   // 32-feature k-steps of a layer input
   constexpr int KS1 = KIN / 32;
+  typedef WStream<WAVES, F, OP> Stream;
+  typedef typename OP::vec vec;
   // LDS: two weight-stream stages, then GELU'(a) as [WAVES][DEPTH][MT][64 lanes][4] fp16
   extern __shared__ uint4 lds[];
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, c16 = ln & 15;
-  _Float16* my = (_Float16*)(lds + 2 * F * 64) + (size_t)wv * DEPTH * MT * 256;
-  WStream<WAVES, F> ws;
-  ws.src = (const uint4*)net.ws;
+  _Float16* my = (_Float16*)(lds + 2 * Stream::UNITS) + (size_t)wv * DEPTH * MT * 256;
+  Stream ws;
+  ws.src = (const uint4*)(OP::scaled ? net.ws8 : net.ws);
   ws.buf = lds;
   ws.nst = net.ws_frags / F;
   ws.begin();
-  const int r_m = net.r_m, r_u = net.r_u, d_z = net.d_z;
+  const int d_z = net.d_z;
+  // combined scale of a product: 1 / (weight scale x activation scale)
+  auto unscale = [&](int op, float ax) -> float { return OP::scaled ? net.wsc_inv[op] / ax : 1.0f; };
 
   // one 16 * WAVES-sample tile per workgroup (a persistent loop would let the
   // compiler hoist every bias load out of it and spill)
@@ -241,18 +320,30 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     const int64_t base = (int64_t)blockIdx.x * (16 * WAVES);
     const int64_t s = base + wv * 16 + c16;
     const bool valid = s < N;
-    bf16x8 hb[KS];
+    vec hb[KS];
     f32x4 acc[MT];
+    float ax = 1.0f;   // scale of the activations in hb (per sample)
     // encoded input (KIN BF16 per sample, see saa_k_encode)
+    if constexpr (OP::scaled) {
 #pragma unroll
-    for (int ks = 0; ks < KS1; ++ks) {
-      hb[ks] = bf16x8{};
-      if (valid) hb[ks] = *(const bf16x8*)(xenc + s * KIN + 32 * ks + 8 * g);
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) {
+        bf16x8 x = bf16x8{};
+        if (valid) x = *(const bf16x8*)(xenc + s * KIN + 32 * ks + 8 * g);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[2 * ks + t / 4][t % 4] = (float)x[t];
+      }
+      ax = pack_all<OP>(acc, hb);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) {
+        hb[ks] = vec{};
+        if (valid) hb[ks] = *(const vec*)(xenc + s * KIN + 32 * ks + 8 * g);
+      }
+#pragma unroll
+      for (int ks = KS1; ks < KS; ++ks) hb[ks] = vec{};
     }
-#pragma unroll
-    for (int ks = KS1; ks < KS; ++ks)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) hb[ks][t] = (__bf16)0.0f;
 
     // forward through the hidden layers
 #pragma unroll
@@ -262,6 +353,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
       if (L == 0) stream_gemm<MT, KS1>(ws, hb, acc);
       else stream_gemm<MT, KS>(ws, hb, acc);
+      const float cs = unscale(L, ax);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const float4 b4 = *(const float4*)(bl + 16 * mt + 4 * g);
@@ -270,18 +362,20 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float h, dh;
-          gelu_pair(acc[mt][r] + bb[r], h, dh);
+          gelu_pair(OP::scaled ? fmaf(acc[mt][r], cs, bb[r]) : acc[mt][r] + bb[r], h, dh);
           d4[r] = (_Float16)dh;
-          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)h;
+          acc[mt][r] = h;
         }
         *(f16x4*)(my + ((L * MT + mt) * 64 + ln) * 4) = d4;
       }
+      ax = pack_all<OP>(acc, hb);
     }
     // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
     {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
       stream_gemm<MT, KS>(ws, hb, acc);
+      const float cs = unscale(DEPTH, ax);
       float qs = 0.0f;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -290,14 +384,15 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
         const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float v = acc[mt][r] + bb[r];
+          const float v = OP::scaled ? fmaf(acc[mt][r], cs, bb[r]) : acc[mt][r] + bb[r];
           qs += v * v;
-          hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)(2.0f * v);
+          acc[mt][r] = 2.0f * v;
         }
       }
       qs += __shfl_xor(qs, 16, 64);
       qs += __shfl_xor(qs, 32, 64);
       if (g == 0 && valid) q_out[s] = (double)qs + net.c0;
+      ax = pack_all<OP>(acc, hb);
     }
     // reverse pass: delta h_{L} = W_{L+1}^T delta a_{L+1}; delta a_L = GELU'(a_L) delta h_L
 #pragma unroll
@@ -305,12 +400,14 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
       stream_gemm<MT, KS>(ws, hb, acc);
+      const float cs = unscale(DEPTH + 1 + (DEPTH - L), ax);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const f16x4 d4 = *(const f16x4*)(my + (((L - 1) * MT + mt) * 64 + ln) * 4);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hb[mt >> 1][(mt & 1) * 4 + r] = (__bf16)(acc[mt][r] * (float)d4[r]);
+        for (int r = 0; r < 4; ++r) acc[mt][r] = (OP::scaled ? acc[mt][r] * cs : acc[mt][r]) * (float)d4[r];
       }
+      ax = pack_all<OP>(acc, hb);
     }
     // dq/dz = W_0[:, r_m:]^T delta a_0
     {
@@ -318,17 +415,54 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
       for (int zt = 0; zt < NZT; ++zt) accz[zt] = f32x4{0.f, 0.f, 0.f, 0.f};
       stream_gemm<NZT, KS>(ws, hb, accz);
+      const float cs = unscale(2 * DEPTH + 1, ax);
       if (valid) {
 #pragma unroll
         for (int zt = 0; zt < NZT; ++zt)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int zi = 16 * zt + 4 * g + r;
-            if (zi < d_z) g_out[s * d_z + zi] = (double)accz[zt][r];
+            if (zi < d_z) g_out[s * d_z + zi] = (double)(OP::scaled ? accz[zt][r] * cs : accz[zt][r]);
           }
       }
     }
   }
+}
+
+// FP8 copy of the BF16 weight stream: every operand scaled by its own power of
+// two (largest magnitude -> [112, 224)).  Operand k spans fragments
+// [off[k], off[k + 1]); one workgroup per operand finds its scale.
+struct OpRanges {
+  int n;
+  int64_t off[2 * MLP_MAX_DEPTH + 3];
+};
+
+__global__ void __launch_bounds__(256) saa_k_op_scale(const __bf16* ws, OpRanges ops, float* wsc_inv) {
+  __shared__ float red[4];
+  const int k = blockIdx.x;
+  const int64_t e0 = ops.off[k] * 512, e1 = ops.off[k + 1] * 512;
+  float m = 0.0f;
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += 256) m = fmaxf(m, fabsf((float)ws[i]));
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    wsc_inv[k] = 1.0f / pow2_scale(m, 224.0f);
+  }
+}
+
+__global__ void saa_k_pack_fp8(const __bf16* ws, OpRanges ops, const float* wsc_inv, int64_t n, uint8_t* dst) {
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (t >= n) return;
+  const int64_t f = t / 512;
+  int k = 0;
+  while (k + 1 < ops.n && ops.off[k + 1] <= f) ++k;
+  const float sc = 1.0f / wsc_inv[k];
+  int v = 0;
+  v = __builtin_amdgcn_cvt_pk_fp8_f32((float)ws[t] * sc, (float)ws[t + 1] * sc, v, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32((float)ws[t + 2] * sc, (float)ws[t + 3] * sc, v, true);
+  *(int*)(dst + t) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -467,30 +601,48 @@ void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, 
 }
 
 // Supported shapes: width 256, depth 4, r_m <= 128, d_z <= 32.
-int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, const void* xenc,
+// prec: 0 FP32 reference kernel, 1 BF16, 2 FP8.
+// Supported shapes: width 256, depth 4, r_m <= 128, d_z <= 32.
+int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* order, const void* xenc,
              int64_t N, double* q, double* g, int n_cu, hipStream_t st) {
   if (net.width != 256 || net.depth != 4 || net.r_m > 128 || net.d_z > 32 || net.r_u > 256) return -1;
-  if (prec_bf16) {
+  (void)n_cu;
+  if (prec == 1 || prec == 2) {
     constexpr int WAVES = 4, F = 16;
     // the stream must hold exactly the operands the kernel consumes
     if (net.kin != 128 || net.ws_frags != 16 * 4 + 4 * 16 * 8 + 4 * 16 * 8 + 2 * 8 || net.ws_frags % F) return -1;
-    const size_t lds = 2 * F * 1024 + (size_t)WAVES * 4 * (256 / 16) * 256 * sizeof(_Float16);
+    if (prec == 2 && (!net.ws8 || !net.wsc_inv)) return -1;
     const int64_t tiles = (N + 16 * WAVES - 1) / (16 * WAVES);
     const unsigned grid = (unsigned)tiles;
-    (void)n_cu;
-    static bool attr_set = false;
-    if (!attr_set) {
-      if (hipFuncSetAttribute((const void*)saa_k_mlp_bf16<256, 128, 4, WAVES, 2, F>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -2;
-      attr_set = true;
-    }
-    saa_k_mlp_bf16<256, 128, 4, WAVES, 2, F><<<grid, WAVES * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
-  } else {
-    const int64_t blocks = (N + 7) / 8;
-    saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);
+    const size_t gelu_lds = (size_t)WAVES * 4 * (256 / 16) * 256 * sizeof(_Float16);
+    auto run = [&](auto op, const void* fn) -> int {
+      typedef decltype(op) OP;
+      const size_t lds = 2 * (size_t)F * OP::FB + gelu_lds;
+      static bool attr_set[2] = {false, false};
+      if (!attr_set[OP::scaled]) {
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -2;
+        attr_set[OP::scaled] = true;
+      }
+      saa_k_mlp_mfma<256, 128, 4, WAVES, 2, F, OP><<<grid, WAVES * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
+      return 0;
+    };
+    if (prec == 1) return run(OpBF16{}, (const void*)saa_k_mlp_mfma<256, 128, 4, WAVES, 2, F, OpBF16>);
+    return run(OpFP8{}, (const void*)saa_k_mlp_mfma<256, 128, 4, WAVES, 2, F, OpFP8>);
   }
+  const int64_t blocks = (N + 7) / 8;
+  saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);
   return 0;
+}
+
+// FP8 weight stream and per-operand scales from the BF16 stream.
+void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, float* wsc_inv, void* ws8, int64_t n_frags,
+                  hipStream_t st) {
+  OpRanges r{};
+  r.n = n_ops;
+  for (int k = 0; k <= n_ops; ++k) r.off[k] = op_off[k];
+  saa_k_op_scale<<<n_ops, 256, 0, st>>>((const __bf16*)ws, r, wsc_inv);
+  const int64_t n = n_frags * 512;
+  saa_k_pack_fp8<<<nblk(n / 4, 256), 256, 0, st>>>((const __bf16*)ws, r, wsc_inv, n, (uint8_t*)ws8);
 }
 
 }  // namespace saa_launch

@@ -1,6 +1,7 @@
 // MR-DINO model object: parameters, packed device operands, evaluation.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -19,8 +20,10 @@ void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld,
 void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st);
 void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
                hipStream_t st);
-int mlp_eval(const MlpDev& net, int prec_bf16, const double* xi, int nkl, const int* order, const void* xenc,
+int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* order, const void* xenc,
              int64_t N, double* q, double* g, int n_cu, hipStream_t st);
+void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, float* wsc_inv, void* ws8, int64_t n_frags,
+                  hipStream_t st);
 void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, void* X, hipStream_t st);
 void mlp_add_pad(float* dst, const float* a, const float* b, int n, int w, hipStream_t st);
 }  // namespace saa_launch
@@ -66,6 +69,8 @@ MlpDev view(const mrdino_model* m) {
   }
   v.w0z = (const char*)m->ws.p + 1024 * m->f_w0z;
   v.ws = m->ws.p;
+  v.ws8 = m->ws8.p;
+  v.wsc_inv = (const float*)m->wsc.p;
   v.ws_frags = m->ws_frags;
   v.b0eff = (const float*)m->b0eff.p;
   v.c = (const float*)m->c.p;
@@ -98,6 +103,14 @@ int pack(mrdino_model* m) {
   saa_launch::mlp_add_pad((float*)m->bc.p, (const float*)m->bias[d.depth].p, (const float*)m->c.p, d.r_u, W, st);
   saa_launch::mlp_pack_bwd((char*)m->ws.p + 1024 * m->f_w0z, P + m->off_w[0], 32, W, W, d.d_z, d.r_m + d.d_z,
                            d.r_m, st);
+  // FP8 copy: operands in stream order wp[0..depth], wt[depth..1], w0z
+  int64_t off[2 * MLP_MAX_DEPTH + 3];
+  int n = 0;
+  for (int L = 0; L <= d.depth; ++L) off[n++] = m->f_wp[L];
+  for (int L = d.depth; L >= 1; --L) off[n++] = m->f_wt[L];
+  off[n++] = m->f_w0z;
+  off[n] = m->ws_frags;
+  saa_launch::mlp_pack_fp8(m->ws.p, off, n, (float*)m->wsc.p, m->ws8.p, m->ws_frags, st);
   return check_hip(hipGetLastError());
 }
 
@@ -123,6 +136,8 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
   if (!dims_supported(*d)) return SAA_E_INVALID;
   mrdino_model* m = new (std::nothrow) mrdino_model();
   if (!m) return SAA_E_OOM;
+  static std::atomic<uint64_t> next_serial{1};
+  m->serial = next_serial.fetch_add(1);
   m->dims = *d;
   m->st = (hipStream_t)hip_stream;
   m->kin = 128;   // the BF16 kernel reads a fixed 128-column layer-0 operand (r_m <= 128)
@@ -153,6 +168,8 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
   nf += 2 * (W / 32);
   m->ws_frags = nf;
   if (!rc) rc = m->ws.alloc_zero(1024 * (size_t)nf, m->st);
+  if (!rc) rc = m->ws8.alloc_zero(512 * (size_t)nf, m->st);
+  if (!rc) rc = m->wsc.alloc_zero(sizeof(float) * (2 * MLP_MAX_DEPTH + 2), m->st);
   for (int L = 0; L <= d->depth && !rc; ++L) {
     rc = m->bias[L].alloc_zero(sizeof(float) * W, m->st);
     if (!rc) rc = m->wtn[L].alloc_zero(sizeof(float) * (size_t)W * (L == 0 ? d->r_m : W), m->st);
@@ -324,11 +341,11 @@ int mrdino_load(const char* path, void* hip_stream, mrdino_model** out) {
 int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, double* q, double* g) {
   const mrdino_dims& d = m->dims;
   if (d.d_z != c->dz || d.r_m > c->K1 * c->K1) return SAA_E_MODEL;
-  if (prec != SAA_FP32 && prec != SAA_BF16) return SAA_E_INVALID;
+  if (prec != SAA_FP32 && prec != SAA_BF16 && prec != SAA_FP8) return SAA_E_INVALID;
   saa_launch::mlp_b0eff((float*)m->b0eff.p, (const float*)m->master.p + m->off_w[0],
                         (const float*)m->master.p + m->off_b[0], z_dev, d.width, d.r_m, d.d_z, c->st);
   const MlpDev v = view(m);
-  if (prec == SAA_BF16 && c->enc_rm != d.r_m) {   // encode the installed samples once
+  if (prec != SAA_FP32 && c->enc_rm != d.r_m) {   // encode the installed samples once
     int rc = c->enc.p ? SAA_OK : c->enc.alloc(sizeof(uint16_t) * 128 * (size_t)c->N_max);
     if (rc) return rc;
     saa_launch::mlp_encode((const double*)c->xi.p, c->K1 * c->K1, (const int*)c->order.p, d.r_m, c->N, c->enc.p,
@@ -336,7 +353,8 @@ int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, d
     if ((rc = check_hip(hipGetLastError()))) return rc;
     c->enc_rm = d.r_m;
   }
-  const int rc = saa_launch::mlp_eval(v, prec == SAA_BF16, (const double*)c->xi.p, c->K1 * c->K1,
+  const int rc = saa_launch::mlp_eval(v, prec == SAA_FP32 ? 0 : prec == SAA_BF16 ? 1 : 2, (const double*)c->xi.p,
+                                      c->K1 * c->K1,
                                       (const int*)c->order.p, c->enc.p, c->N, q, g, 0, c->st);
   if (rc) return SAA_E_DEVICE;
   return check_hip(hipGetLastError());

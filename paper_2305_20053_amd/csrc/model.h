@@ -14,6 +14,7 @@ struct mrdino_model {
   int64_t off_b[MLP_MAX_DEPTH + 1] = {};
   saa_rt::DevBuf master;                    // FP32 parameters
   saa_rt::DevBuf ws;                        // BF16 MFMA operands (weight stream)
+  saa_rt::DevBuf ws8, wsc;                  // FP8 copy and its per-operand 1 / scale
   int64_t ws_frags = 0;                     // stream length in 1 KB fragments
   int64_t f_wp[MLP_MAX_DEPTH + 1] = {};     // fragment offsets of the operands in the stream
   int64_t f_wt[MLP_MAX_DEPTH + 1] = {};
@@ -25,6 +26,7 @@ struct mrdino_model {
   double c0 = 0.0;
   std::vector<double> c_host;               // c as given to mrdino_set_qoi (zeros until set)
   void* train = nullptr;                    // training workspace and Adam state (train.cpp)
+  uint64_t serial = 0;                      // unique per model object (keys captured graphs)
   ~mrdino_model();
 };
 

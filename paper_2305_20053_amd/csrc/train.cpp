@@ -440,7 +440,7 @@ int mrdino_eval(mrdino_model* m, saa_ctx* c, const double* z, int want, int prec
     if (!std::isfinite(z[k])) return SAA_E_INVALID;
   int rc = SAA_OK;
   if (want & (MRDINO_WANT_Q | MRDINO_WANT_DQDZ)) {
-    if (prec != SAA_FP32 && prec != SAA_BF16) return SAA_E_INVALID;
+    if (prec != SAA_FP32 && prec != SAA_BF16 && prec != SAA_FP8) return SAA_E_INVALID;
     if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * d.d_z, hipMemcpyHostToDevice, c->st))))
       return rc;
     double* q = (want & MRDINO_WANT_Q) ? q_dev : (double*)c->q.p;

@@ -3,7 +3,9 @@ evaluated with the same (float32-rounded) weights.
 
 Tolerances: FP32 kernel 1e-5 relative on q, dq/dz, J and grad J; BF16 MFMA
 kernel 2e-2 relative on J and grad J (per-sample values reported and bounded
-loosely).
+loosely).  FP8 (E4M3 operands with power-of-two scales) has no accuracy
+target: its bounds are the measured errors (q 1.3e-2, dq/dz median 9 %, J 1e-3,
+grad J 8 %) with margin, so a regression still fails.
 """
 import numpy as np
 import pytest
@@ -53,7 +55,7 @@ def test_params_roundtrip(setup):
     assert np.array_equal(model.get_params(), p)
 
 
-@pytest.mark.parametrize("prec,tol_q,tol_g", [(saa.FP32, 1e-5, 1e-4), (saa.BF16, 2e-2, 2e-1)])
+@pytest.mark.parametrize("prec,tol_q,tol_g", [(saa.FP32, 1e-5, 1e-4), (saa.BF16, 2e-2, 2e-1), (saa.FP8, 5e-2, 6e-1)])
 def test_per_sample(setup, prec, tol_q, tol_g):
     prob, xi, z, model, ctx, q_ref, g_ref = setup
     print(f"case mrdino per_sample prec={prec}", flush=True)
@@ -66,14 +68,14 @@ def test_per_sample(setup, prec, tol_q, tol_g):
     assert np.median(eg) <= tol_g / 4 and eg.max() <= tol_g
 
 
-@pytest.mark.parametrize("prec,tol", [(saa.FP32, 1e-5), (saa.BF16, 2e-2)])
-def test_objective(setup, prec, tol):
+@pytest.mark.parametrize("prec,tol,tol_g", [(saa.FP32, 1e-5, 1e-5), (saa.BF16, 2e-2, 2e-2), (saa.FP8, 1e-2, 0.15)])
+def test_objective(setup, prec, tol, tol_g):
     prob, xi, z, model, ctx, q_ref, g_ref = setup
     ref = cvar.objective(q_ref, g_ref, z, 0.95, 1e-4, 1e-3)
     J, grad, rep = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=prec))
     print(f"  prec={prec} relJ {abs(J - ref['J']) / abs(ref['J']):.3e} relgrad {_rel(grad, ref['grad']):.3e}")
     assert abs(J - ref["J"]) <= tol * abs(ref["J"])
-    assert _rel(grad, ref["grad"]) <= tol
+    assert _rel(grad, ref["grad"]) <= tol_g
 
 
 def test_mrdino_rejects_pde_precision(setup):
@@ -140,3 +142,33 @@ def test_save_load_roundtrip(setup, tmp_path):
     open(path, "wb").write(bytes(raw))
     with pytest.raises(saa.SaaError):
         saa.Model.load(path)
+
+
+def test_graph_replay_matches_eager(setup):
+    """Untimed MR-DINO evaluations replay a captured hipGraph from the second
+    call on; every replay, with eager work on the same stream in between, is
+    bitwise equal to the eager (timed) evaluation, also after the parameters
+    are changed in place."""
+    prob, xi, z, model, ctx, q_ref, g_ref = setup
+    zs = [si.control(s) for s in si.SEED_Z_EVAL]
+    eager_opt = saa.options(prec=saa.BF16, timing=1)
+    eager = [ctx.objective_grad(zz, form=saa.FORM_MRDINO, model=model, opt=eager_opt) for zz in zs]
+    assert all(e[2]["graph"] == 0 for e in eager)
+    used = []
+    for _ in range(3):
+        for k, zz in enumerate(zs):
+            J, g, r = ctx.objective_grad(zz, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
+            used.append(r["graph"])
+            assert J == eager[k][0] and np.array_equal(g, eager[k][1])
+            ctx.per_sample(zz, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32))
+    print("graph replays", sum(used), "of", len(used))
+    assert all(used)   # the timed eager calls above already were the first evaluation
+    p = model.get_params()
+    try:
+        model.set_params(p * np.float32(1.01))
+        J1, g1, r1 = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
+        Je, ge, re_ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=eager_opt)
+        assert r1["graph"] == 1 and re_["graph"] == 0
+        assert J1 == Je and np.array_equal(g1, ge) and J1 != eager[0][0]
+    finally:
+        model.set_params(p)
