@@ -164,10 +164,19 @@ template <int MT, int NK, int KSA, class S, class V>
 __device__ __forceinline__ void stream_gemm(S& ws, const V (&hb)[KSA], f32x4 (&acc)[MT]) {
   static_assert((MT * NK) % S::FR == 0, "operands start and end on stage boundaries");
 #pragma unroll
-  for (int f = 0; f < MT * NK; ++f) {
-    const int ks = f / MT, mt = f % MT;
-    acc[mt] = S::Op::mma(ws.frag(f % S::FR), hb[ks], acc[mt]);
-    if (f % S::FR == S::FR - 1) ws.advance();
+  for (int f0 = 0; f0 < MT * NK; f0 += S::FR) {
+    // all fragment reads of the stage first, so that their LDS latencies
+    // overlap instead of stalling each MFMA
+    typename S::Op::vec a[S::FR];
+#pragma unroll
+    for (int j = 0; j < S::FR; ++j) a[j] = ws.frag(j);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < S::FR; ++j) {
+      const int f = f0 + j, ks = f / MT, mt = f % MT;
+      acc[mt] = S::Op::mma(a[j], hb[ks], acc[mt]);
+    }
+    ws.advance();
   }
 }
 
