@@ -7,23 +7,22 @@
 //   dq/dz by reverse mode: delta = 2 (phi + c), back through the layers with
 //   GELU'(a_L), and finally the control columns of W_0.
 //
-// BF16 kernel (MFMA v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Each wave
-// carries 16 samples through the whole network.  Products are formed
-// transposed, C = W_L * H^T: output features run along the MFMA M dimension and
-// samples along N, so one lane holds, for its sample, 4 consecutive features of
-// every 16-feature tile.  That accumulator layout is the B-operand layout of the
-// next layer up to a fixed permutation inside every 32-feature block
-// (slot 8g + t holds feature 4g + t for t < 4 and 16 + 4g + t - 4 for t >= 4);
-// the permutation is folded into the stored weight copies, so activations never
-// leave registers between layers.  GELU'(a_L) of every layer is kept in LDS as
-// fp16 for the reverse pass.
+// MFMA kernel (v_mfma_f32_16x16x32_bf16, or _fp8_fp8; FP32 accumulation).
+// Products are formed transposed, C = W_L * H^T: output features run along
+// the MFMA M dimension and samples along N, so one lane holds, for its sample,
+// 4 consecutive features of every 16-feature tile.  That accumulator layout is
+// the B-operand layout of the next layer up to a fixed permutation inside
+// every 32-feature block (slot 8g + t holds feature 4g + t for t < 4 and
+// 16 + 4g + t - 4 for t >= 4); the permutation is folded into the stored
+// weight copies, so a lane's outputs are published to the next product
+// without any shuffle.  A workgroup carries 64 samples and splits every
+// product's output features over its waves (see the kernel).  GELU'(a_L) of
+// every layer is kept in LDS as fp16 for the reverse pass.
 //
-// The weights (A operands) reach the MFMAs through LDS: every BF16 fragment of
-// every layer is stored once, in the order the kernel consumes it, in one
-// "weight stream"; the waves of a workgroup copy it to LDS together, F
-// fragments (one stage) at a time, two stages ahead in registers and double
-// buffered in LDS, and all of them read their fragments from that shared copy.
-// Each weight byte thus crosses L2 once per workgroup instead of once per wave.
+// The weights (A operands) are stored once per format, every 16 x 32 fragment
+// contiguous (64 lanes x 16 B for BF16), in the order
+// wp[0..depth], wt[depth..1], w0z; a wave reads its fragments straight from
+// L2, where the whole set (1.1 MB in BF16) stays resident.
 #include <hip/hip_fp16.h>
 
 #include "common.h"
@@ -106,113 +105,14 @@ __device__ __forceinline__ float pow2_scale(float m, float top) {
   return ldexpf(1.0f, e);
 }
 
-// Weight stream staged through LDS (see the header).  A fragment is 16 rows x
-// 32 columns (FB bytes); lane 16 g + c holds row c, columns 8 g .. 8 g + 8.
-// The stream holds the fragments of every operand in consumption order:
-// operand by operand, and inside one operand k-step by k-step, 16-row tile by
-// tile.  Stage s = fragments [s F, (s + 1) F) = one contiguous block.
-template <int WAVES, int F, class OP>
-struct WStream {
-  typedef OP Op;
-  static constexpr int FR = F;
-  static constexpr int UNITS = F * OP::FB / 16;          // 16-byte units per stage
-  static constexpr int PER = UNITS / (WAVES * 64);       // per thread per stage
-  static_assert(UNITS % (WAVES * 64) == 0, "a stage splits evenly over the threads");
-  const uint4* src;   // the stream
-  uint4* buf;         // two LDS stage buffers
-  int nst;            // stages in the stream
-  int s;              // stage being consumed (held in buf[s & 1])
-  uint4 ra[PER];      // stage s + 1
-  uint4 rb[PER];      // stage s + 2
-  // stages past the end re-read the last one (never published)
-  __device__ __forceinline__ void load(uint4 (&r)[PER], int stage) {
-    const int64_t b = (int64_t)(stage < nst ? stage : nst - 1) * UNITS + threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) r[k] = src[b + k * WAVES * 64];
-  }
-  __device__ __forceinline__ void store(const uint4 (&r)[PER], int b) {
-#pragma unroll
-    for (int k = 0; k < PER; ++k) buf[b * UNITS + threadIdx.x + k * WAVES * 64] = r[k];
-  }
-  __device__ __forceinline__ void begin() {
-    load(ra, 0);
-    store(ra, 0);
-    load(ra, 1);
-    load(rb, 2);
-    s = 0;
-    __syncthreads();
-  }
-  __device__ __forceinline__ typename OP::vec frag(int j) const {
-    const char* b = (const char*)(buf + (s & 1) * UNITS);
-    return *(const typename OP::vec*)(b + j * OP::FB + (threadIdx.x & 63) * (OP::FB / 64));
-  }
-  // End of stage s: publish stage s + 1 (its buffer held stage s - 1, which
-  // every wave finished before the previous barrier), then prefetch s + 3.
-  __device__ __forceinline__ void advance() {
-    store(ra, (s + 1) & 1);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) ra[k] = rb[k];
-    load(rb, s + 3);
-    ++s;
-  }
-};
-
-// acc[mt] += A(mt, ks) * hb[ks] for ks < NK, mt < MT, with the A fragments
-// taken from the stream in order.
-template <int MT, int NK, int KSA, class S, class V>
-__device__ __forceinline__ void stream_gemm(S& ws, const V (&hb)[KSA], f32x4 (&acc)[MT]) {
-  static_assert((MT * NK) % S::FR == 0, "operands start and end on stage boundaries");
-#pragma unroll
-  for (int f0 = 0; f0 < MT * NK; f0 += S::FR) {
-    // all fragment reads of the stage first, so that their LDS latencies
-    // overlap instead of stalling each MFMA
-    typename S::Op::vec a[S::FR];
-#pragma unroll
-    for (int j = 0; j < S::FR; ++j) a[j] = ws.frag(j);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < S::FR; ++j) {
-      const int f = f0 + j, ks = f / MT, mt = f % MT;
-      acc[mt] = S::Op::mma(a[j], hb[ks], acc[mt]);
-    }
-    ws.advance();
-  }
-}
-
-// Operands of the next product from the 64 FP32 values of a lane (4 per
-// 16-feature tile; tiles 2 ks, 2 ks + 1 form k-step ks).  Returns the
-// per-sample scale applied (1 for unscaled formats).
-template <class OP, int MT, int KS>
-__device__ __forceinline__ float pack_all(const f32x4 (&v)[MT], typename OP::vec (&hb)[KS]) {
-  float sc = 1.0f;
-  if constexpr (OP::scaled) {
-    float m = 0.0f;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(v[mt][r]));
-    m = fmaxf(m, __shfl_xor(m, 16, 64));
-    m = fmaxf(m, __shfl_xor(m, 32, 64));
-    sc = pow2_scale(m, 256.0f);
-  }
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const float e[8] = {v[2 * ks][0],     v[2 * ks][1],     v[2 * ks][2],     v[2 * ks][3],
-                        v[2 * ks + 1][0], v[2 * ks + 1][1], v[2 * ks + 1][2], v[2 * ks + 1][3]};
-    hb[ks] = OP::pack(e, sc);
-  }
-  return sc;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Weight packing (after every change of the FP32 master parameters)
 // ---------------------------------------------------------------------------
 
-// Position t of a stored rows x cols operand (stream order, see WStream)
-// -> logical (row m, column k).
+// Position t of a stored rows x cols operand (fragment (ks, mt) at
+// ks * rows/16 + mt, 64 lanes x 8 values each) -> logical (row m, column k).
 __device__ __forceinline__ void frag_pos(int64_t t, int rows, int& m, int& k) {
   const int e = (int)(t & 7);
   const int ln = (int)((t >> 3) & 63);
@@ -223,7 +123,7 @@ __device__ __forceinline__ void frag_pos(int64_t t, int rows, int& m, int& k) {
   k = 32 * ks + 8 * (ln >> 4) + e;
 }
 
-// Forward BF16 operand (stream order): logical [m][k] = W[m][kperm(k)] (or
+// Forward BF16 operand (fragment order): logical [m][k] = W[m][kperm(k)] (or
 // natural order when `natural`), zero outside the source.  W is src_rows x
 // src_ld.  rows % 16 == 0, cols % 32 == 0.
 __global__ void saa_k_pack_fwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
@@ -238,7 +138,7 @@ __global__ void saa_k_pack_fwd(__bf16* dst, const float* src, int rows, int cols
   dst[t] = (__bf16)v;
 }
 
-// Backward BF16 operand (stream order): logical [m][k] = W[kperm(k)][col0 + m],
+// Backward BF16 operand (fragment order): logical [m][k] = W[kperm(k)][col0 + m],
 // zero outside.
 __global__ void saa_k_pack_bwd(__bf16* dst, const float* src, int rows, int cols, int src_rows, int src_cols,
                                int src_ld, int col0) {
@@ -298,147 +198,254 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
 }
 
 // ---------------------------------------------------------------------------
-// Fused MFMA forward + reverse kernel (BF16 or FP8 operands, FP32 accumulation)
+// Fused MFMA kernel (forward, reduced QoI, reverse pass, dq/dz), feature split.
+// A workgroup of WAVES waves carries 64 samples (4 blocks of 16); wave w
+// computes output tiles MW w .. MW w + MW - 1 of every product for all 64
+// samples, so each A fragment it loads (straight from L2, two k-steps ahead)
+// feeds 4 MFMAs.  A wave's outputs are, lane by lane, whole B fragments of
+// k-steps KW w .. of the next product (the k-permutation of the stored
+// weights); they are exchanged through LDS (two barriers per layer).
+// GELU'(a) stays with the wave that computed a, which is also the wave that
+// needs it in the reverse pass.  Two waves per SIMD let one wave's GELU
+// epilogue overlap the other's MFMAs.
+// FP8: the activations of a sample share one power-of-two scale; each wave
+// posts its per-sample maximum in LDS before the publishing barrier.
 // ---------------------------------------------------------------------------
-// Operand index of each product in the weight stream (its scale in net.wsc):
-// forward layers 0..DEPTH, reverse layers DEPTH..1 -> DEPTH + 1.., w0z last.
-template <int W, int KIN, int DEPTH, int WAVES, int NZT, int F, class OP>
+template <int W, int KIN, int DEPTH, int NZT, int WAVES, class OP>
 __global__ void __launch_bounds__(WAVES * 64, 1)
     saa_k_mlp_mfma(MlpDev net, const __bf16* xenc, int64_t N, double* q_out, double* g_out) {
-  constexpr int MT = W / 16;   // 16-feature tiles of a layer output
-  constexpr int KS = W / 32;   // 32-feature k-steps of a layer input
-  constexpr int KS1 = KIN / 32;
-  typedef WStream<WAVES, F, OP> Stream;
+  constexpr int MT = W / 16, KS = W / 32, KS1 = KIN / 32;
+  constexpr int SB = 4, MW = MT / WAVES;   // sample blocks; output tiles per wave
+  constexpr int KW = MW / 2;               // k-steps a wave publishes
+  constexpr int FB = OP::FB;               // bytes per 16 x 32 fragment
+  static_assert(MW % 2 == 0 && KS == KW * WAVES && NZT <= WAVES, "feature split of width 256");
   typedef typename OP::vec vec;
-  // LDS: two weight-stream stages, then GELU'(a) as [WAVES][DEPTH][MT][64 lanes][4] fp16
   extern __shared__ uint4 lds[];
+  vec* act = (vec*)lds;                                          // [SB][KS][64]: B fragments
+  float* smax = (float*)((char*)lds + SB * KS * FB);             // [WAVES][SB][16] (FP8 only)
+  constexpr int SMAX = OP::scaled ? WAVES * SB * 16 * 4 : 0;
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, c16 = ln & 15;
-  _Float16* my = (_Float16*)(lds + 2 * Stream::UNITS) + (size_t)wv * DEPTH * MT * 256;
-  Stream ws;
-  ws.src = (const uint4*)(OP::scaled ? net.ws8 : net.ws);
-  ws.buf = lds;
-  ws.nst = net.ws_frags / F;
-  ws.begin();
-  const int d_z = net.d_z;
-  // combined scale of a product: 1 / (weight scale x activation scale)
-  auto unscale = [&](int op, float ax) -> float { return OP::scaled ? net.wsc_inv[op] / ax : 1.0f; };
+  _Float16* myg = (_Float16*)((char*)lds + SB * KS * FB + SMAX) + (size_t)wv * DEPTH * MW * SB * 256;
+  float* qs = (float*)lds;                                       // [WAVES][SB][16] (reuses act)
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  f32x4 acc[MW][SB];
+  float ax[SB] = {1.f, 1.f, 1.f, 1.f};   // scale of the current B operands, per sample block (FP8)
+  // operand k of the stream in this format (the FP8 copy has 512-byte fragments)
+  auto operand = [&](const void* bf16_op) -> const char* {
+    if constexpr (OP::scaled)
+      return (const char*)net.ws8 + ((const char*)bf16_op - (const char*)net.ws) / 2;
+    else
+      return (const char*)bf16_op;
+  };
 
-  // one 16 * WAVES-sample tile per workgroup (a persistent loop would let the
-  // compiler hoist every bias load out of it and spill)
-  {
-    const int64_t base = (int64_t)blockIdx.x * (16 * WAVES);
-    const int64_t s = base + wv * 16 + c16;
-    const bool valid = s < N;
-    vec hb[KS];
-    f32x4 acc[MT];
-    float ax = 1.0f;   // scale of the activations in hb (per sample)
-    // encoded input (KIN BF16 per sample, see saa_k_encode)
+  // acc += A(MW wv + j, ks) B(sb, ks); A fragment (ks, mt) of an operand with
+  // mtx row tiles at A + (ks mtx + mt) FB bytes; B from act, or (BF16) from
+  // the encoded input for layer 0
+  auto product = [&](const char* A, int mtx, int nks, bool from_input) {
+#pragma unroll
+    for (int j = 0; j < MW; ++j)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) acc[j][sb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const char* Aw = A + (size_t)(MW * wv) * FB + ln * (FB / 64);
+    vec a[3][MW];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int j = 0; j < MW; ++j)
+        if (p < nks) a[p][j] = *(const vec*)(Aw + (size_t)(p * mtx + j) * FB);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks < nks) {
+        if (ks + 2 < nks) {
+#pragma unroll
+          for (int j = 0; j < MW; ++j) a[(ks + 2) % 3][j] = *(const vec*)(Aw + (size_t)((ks + 2) * mtx + j) * FB);
+        }
+        vec b[SB];
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+          if (!OP::scaled && from_input) {
+            const int64_t smp = base + 16 * sb + c16;
+            b[sb] = vec{};
+            if (smp < N) b[sb] = *(const vec*)(xenc + smp * KIN + 32 * ks + 8 * g);
+          } else {
+            b[sb] = act[(sb * KS + ks) * 64 + ln];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < MW; ++j)
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) acc[j][sb] = OP::mma(a[ks % 3][j], b[sb], acc[j][sb]);
+      }
+    }
+  };
+  // 1 / (weight scale x activation scale) of product `op` for sample block sb
+  auto unscale = [&](int op, int sb) -> float { return OP::scaled ? net.wsc_inv[op] / ax[sb] : 1.0f; };
+  // publish this wave's outputs (acc holds them) as B fragments of k-steps KW wv ..
+  auto publish = [&]() {
+    if constexpr (OP::scaled) {   // per-sample maxima of this wave's features
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        float m = 0.0f;
+#pragma unroll
+        for (int j = 0; j < MW; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(acc[j][sb][r]));
+        m = fmaxf(m, __shfl_xor(m, 16, 64));
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        if (g == 0) smax[(wv * SB + sb) * 16 + c16] = m;
+      }
+    }
+    __syncthreads();   // every wave finished reading act (and posted its maxima)
     if constexpr (OP::scaled) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KS1; ++ks) {
-        bf16x8 x = bf16x8{};
-        if (valid) x = *(const bf16x8*)(xenc + s * KIN + 32 * ks + 8 * g);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc[2 * ks + t / 4][t % 4] = (float)x[t];
+      for (int sb = 0; sb < SB; ++sb) {
+        float m = 0.0f;
+        for (int w = 0; w < WAVES; ++w) m = fmaxf(m, smax[(w * SB + sb) * 16 + c16]);
+        ax[sb] = pow2_scale(m, 256.0f);
       }
-      ax = pack_all<OP>(acc, hb);
-    } else {
-#pragma unroll
-      for (int ks = 0; ks < KS1; ++ks) {
-        hb[ks] = vec{};
-        if (valid) hb[ks] = *(const vec*)(xenc + s * KIN + 32 * ks + 8 * g);
-      }
-#pragma unroll
-      for (int ks = KS1; ks < KS; ++ks) hb[ks] = vec{};
     }
+#pragma unroll
+    for (int jp = 0; jp < KW; ++jp)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        const float e[8] = {acc[2 * jp][sb][0],     acc[2 * jp][sb][1],     acc[2 * jp][sb][2],
+                            acc[2 * jp][sb][3],     acc[2 * jp + 1][sb][0], acc[2 * jp + 1][sb][1],
+                            acc[2 * jp + 1][sb][2], acc[2 * jp + 1][sb][3]};
+        act[(sb * KS + KW * wv + jp) * 64 + ln] = OP::pack(e, ax[sb]);
+      }
+    __syncthreads();
+  };
 
-    // forward through the hidden layers
+  if constexpr (OP::scaled) {   // FP8: scale and publish the encoded input like a layer output
+    static_assert(KS1 <= KS, "input k-steps");
 #pragma unroll
-    for (int L = 0; L < DEPTH; ++L) {
-      const float* bl = (L == 0) ? net.b0eff : net.bias[L];
+    for (int j = 0; j < MW; ++j)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (L == 0) stream_gemm<MT, KS1>(ws, hb, acc);
-      else stream_gemm<MT, KS>(ws, hb, acc);
-      const float cs = unscale(L, ax);
+      for (int sb = 0; sb < SB; ++sb) acc[j][sb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // wave w holds input features of k-steps KW w .. (zero beyond KIN)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const float4 b4 = *(const float4*)(bl + 16 * mt + 4 * g);
-        const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+    for (int jp = 0; jp < KW; ++jp) {
+      const int ks = KW * wv + jp;
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        const int64_t smp = base + 16 * sb + c16;
+        if (ks < KS1 && smp < N) {
+          const bf16x8 x = *(const bf16x8*)(xenc + smp * KIN + 32 * ks + 8 * g);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) acc[2 * jp + t / 4][sb][t % 4] = (float)x[t];
+        }
+      }
+    }
+    publish();
+  }
+
+  // forward through the hidden layers
+#pragma unroll
+  for (int L = 0; L < DEPTH; ++L) {
+    const float* bl = (L == 0) ? net.b0eff : net.bias[L];
+    product(operand(net.wp[L]), MT, L == 0 ? KS1 : KS, L == 0);
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      const float4 b4 = *(const float4*)(bl + 16 * (MW * wv + j) + 4 * g);
+      const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        const float cs = unscale(L, sb);
         f16x4 d4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float h, dh;
-          gelu_pair(OP::scaled ? fmaf(acc[mt][r], cs, bb[r]) : acc[mt][r] + bb[r], h, dh);
+          gelu_pair(OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r], h, dh);
           d4[r] = (_Float16)dh;
-          acc[mt][r] = h;
+          acc[j][sb][r] = h;
         }
-        *(f16x4*)(my + ((L * MT + mt) * 64 + ln) * 4) = d4;
+        *(f16x4*)(myg + (((L * MW + j) * SB + sb) * 64 + ln) * 4) = d4;
       }
-      ax = pack_all<OP>(acc, hb);
     }
-    // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
-    {
+    publish();
+  }
+  // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
+  {
+    product(operand(net.wp[DEPTH]), MT, KS, false);
+    float qp[SB] = {0.f, 0.f, 0.f, 0.f};   // this wave's part of |phi + c|^2
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      stream_gemm<MT, KS>(ws, hb, acc);
-      const float cs = unscale(DEPTH, ax);
-      float qs = 0.0f;
+    for (int j = 0; j < MW; ++j) {
+      // rows past r_u have zero weights and zero bias + c, so v = 0 there
+      const float4 b4 = *(const float4*)(net.bc + 16 * (MW * wv + j) + 4 * g);
+      const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        // rows past r_u have zero weights and zero bias + c, so v = 0 there
-        const float4 b4 = *(const float4*)(net.bc + 16 * mt + 4 * g);
-        const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+      for (int sb = 0; sb < SB; ++sb) {
+        const float cs = unscale(DEPTH, sb);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float v = OP::scaled ? fmaf(acc[mt][r], cs, bb[r]) : acc[mt][r] + bb[r];
-          qs += v * v;
-          acc[mt][r] = 2.0f * v;
+          const float v = OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r];
+          qp[sb] += v * v;
+          acc[j][sb][r] = 2.0f * v;
         }
       }
-      qs += __shfl_xor(qs, 16, 64);
-      qs += __shfl_xor(qs, 32, 64);
-      if (g == 0 && valid) q_out[s] = (double)qs + net.c0;
-      ax = pack_all<OP>(acc, hb);
     }
-    // reverse pass: delta h_{L} = W_{L+1}^T delta a_{L+1}; delta a_L = GELU'(a_L) delta h_L
 #pragma unroll
-    for (int L = DEPTH; L >= 1; --L) {
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      stream_gemm<MT, KS>(ws, hb, acc);
-      const float cs = unscale(DEPTH + 1 + (DEPTH - L), ax);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const f16x4 d4 = *(const f16x4*)(my + (((L - 1) * MT + mt) * 64 + ln) * 4);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[mt][r] = (OP::scaled ? acc[mt][r] * cs : acc[mt][r]) * (float)d4[r];
-      }
-      ax = pack_all<OP>(acc, hb);
+    for (int sb = 0; sb < SB; ++sb) {
+      qp[sb] += __shfl_xor(qp[sb], 16, 64);
+      qp[sb] += __shfl_xor(qp[sb], 32, 64);
     }
-    // dq/dz = W_0[:, r_m:]^T delta a_0
-    {
-      f32x4 accz[NZT];
+    __syncthreads();   // every wave finished reading act: reuse it for the partial sums
+    if (g == 0)
 #pragma unroll
-      for (int zt = 0; zt < NZT; ++zt) accz[zt] = f32x4{0.f, 0.f, 0.f, 0.f};
-      stream_gemm<NZT, KS>(ws, hb, accz);
-      const float cs = unscale(2 * DEPTH + 1, ax);
-      if (valid) {
+      for (int sb = 0; sb < SB; ++sb) qs[(wv * SB + sb) * 16 + c16] = qp[sb];
+    __syncthreads();
+    if (wv == 0) {
+      const int sb = ln >> 4;
+      const int64_t smp = base + ln;
+      float qsum = 0.0f;
+      for (int w = 0; w < WAVES; ++w) qsum += qs[(w * SB + sb) * 16 + c16];
+      if (smp < N) q_out[smp] = (double)qsum + net.c0;
+    }
+    publish();
+  }
+  // reverse pass: delta h_{L-1} = W_L^T delta a_L; delta a_{L-1} = GELU'(a_{L-1}) delta h_{L-1}
 #pragma unroll
-        for (int zt = 0; zt < NZT; ++zt)
+  for (int L = DEPTH; L >= 1; --L) {
+    product(operand(net.wt[L]), MT, KS, false);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int zi = 16 * zt + 4 * g + r;
-            if (zi < d_z) g_out[s * d_z + zi] = (double)(OP::scaled ? accz[zt][r] * cs : accz[zt][r]);
-          }
+    for (int j = 0; j < MW; ++j)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        const float cs = unscale(DEPTH + 1 + (DEPTH - L), sb);
+        const f16x4 d4 = *(const f16x4*)(myg + ((((L - 1) * MW + j) * SB + sb) * 64 + ln) * 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[j][sb][r] = (OP::scaled ? acc[j][sb][r] * cs : acc[j][sb][r]) * (float)d4[r];
       }
+    publish();
+  }
+  // dq/dz = W_0[:, r_m:]^T delta a_0: NZT row tiles, one per wave (waves >= NZT idle)
+  if (wv < NZT) {
+    f32x4 az[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) az[sb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const char* Aw = operand(net.w0z) + (size_t)wv * FB + ln * (FB / 64);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const vec a = *(const vec*)(Aw + (size_t)(ks * NZT) * FB);
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) az[sb] = OP::mma(a, act[(sb * KS + ks) * 64 + ln], az[sb]);
+    }
+    const int d_z = net.d_z;
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const float cs = unscale(2 * DEPTH + 1, sb);
+      const int64_t smp = base + 16 * sb + c16;
+      if (smp < N)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int zi = 16 * wv + 4 * g + r;
+          if (zi < d_z) g_out[smp * d_z + zi] = (double)(OP::scaled ? az[sb][r] * cs : az[sb][r]);
+        }
     }
   }
 }
 
-// FP8 copy of the BF16 weight stream: every operand scaled by its own power of
+// FP8 copy of the BF16 weights: every operand scaled by its own power of
 // two (largest magnitude -> [112, 224)).  Operand k spans fragments
 // [off[k], off[k + 1]); one workgroup per operand finds its scale.
 struct OpRanges {
@@ -617,26 +624,24 @@ int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* 
   if (net.width != 256 || net.depth != 4 || net.r_m > 128 || net.d_z > 32 || net.r_u > 256) return -1;
   (void)n_cu;
   if (prec == 1 || prec == 2) {
-    constexpr int WAVES = 4, F = 16;
-    // the stream must hold exactly the operands the kernel consumes
-    if (net.kin != 128 || net.ws_frags != 16 * 4 + 4 * 16 * 8 + 4 * 16 * 8 + 2 * 8 || net.ws_frags % F) return -1;
+    constexpr int SW = 8;   // waves per workgroup: two per SIMD
+    if (net.kin != 128 || net.ws_frags != 16 * 4 + 4 * 16 * 8 + 4 * 16 * 8 + 2 * 8) return -1;
     if (prec == 2 && (!net.ws8 || !net.wsc_inv)) return -1;
-    const int64_t tiles = (N + 16 * WAVES - 1) / (16 * WAVES);
-    const unsigned grid = (unsigned)tiles;
-    const size_t gelu_lds = (size_t)WAVES * 4 * (256 / 16) * 256 * sizeof(_Float16);
+    const unsigned grid = (unsigned)((N + 63) / 64);
+    const size_t gelu_lds = (size_t)4 * 256 * 2 * 64;   // DEPTH x width x fp16 x 64 samples
     auto run = [&](auto op, const void* fn) -> int {
       typedef decltype(op) OP;
-      const size_t lds = 2 * (size_t)F * OP::FB + gelu_lds;
-      static bool attr_set[2] = {false, false};
-      if (!attr_set[OP::scaled]) {
+      const size_t lds = (size_t)4 * 8 * OP::FB + (OP::scaled ? SW * 4 * 16 * 4 : 0) + gelu_lds;
+      static bool attr_set = false;
+      if (!attr_set) {
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -2;
-        attr_set[OP::scaled] = true;
+        attr_set = true;
       }
-      saa_k_mlp_mfma<256, 128, 4, WAVES, 2, F, OP><<<grid, WAVES * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
+      saa_k_mlp_mfma<256, 128, 4, 2, SW, OP><<<grid, SW * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
       return 0;
     };
-    if (prec == 1) return run(OpBF16{}, (const void*)saa_k_mlp_mfma<256, 128, 4, WAVES, 2, F, OpBF16>);
-    return run(OpFP8{}, (const void*)saa_k_mlp_mfma<256, 128, 4, WAVES, 2, F, OpFP8>);
+    if (prec == 1) return run(OpBF16{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, OpBF16>);
+    return run(OpFP8{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, OpFP8>);
   }
   const int64_t blocks = (N + 7) / 8;
   saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);

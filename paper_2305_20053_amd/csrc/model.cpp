@@ -337,7 +337,7 @@ int mrdino_load(const char* path, void* hip_stream, mrdino_model** out) {
 }  // extern "C"
 
 // Per-sample q and dq/dz of the surrogate for the samples installed in ctx, on
-// the context's stream.  z_dev: device, d_Z.  prec: SAA_FP32 or SAA_BF16.
+// the context's stream.  z_dev: device, d_Z.  prec: SAA_FP32, SAA_BF16 or SAA_FP8.
 int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, double* q, double* g) {
   const mrdino_dims& d = m->dims;
   if (d.d_z != c->dz || d.r_m > c->K1 * c->K1) return SAA_E_MODEL;
