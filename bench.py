@@ -67,7 +67,7 @@ def cpu_baseline(prob, xi, z, seconds_target=15.0):
     from oracle import fem2d, saa as osaa
     usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     workers = max(1, min(16, usable))
-    oprob = fem2d.Problem2D(n=prob.n, kl_per_dim=prob.kl_per_dim)
+    oprob = fem2d.Problem2D(n=prob.n, kl_per_dim=prob.kl_per_dim, target=prob.target)
     t = time.perf_counter()
     osaa.per_sample_parallel(oprob, xi[:workers], z, workers=workers)
     pilot = time.perf_counter() - t

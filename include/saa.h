@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SAA_ABI_VERSION 1
+#define SAA_ABI_VERSION 2
 
 /* Status codes. */
 enum {
@@ -93,8 +93,15 @@ typedef struct saa_problem {
   double kl_exp;       /* > 0 */
   double kl_amp;       /* any finite value */
   double reaction;     /* r >= 0 */
-  double u_target;     /* target state (constant) */
+  double u_target;     /* target state when target = SAA_TARGET_CONST */
+  int target;          /* target state (Sec. 4.2): SAA_TARGET_CONST (u_target
+                          everywhere), SAA_TARGET_SIN (sin(2 pi x) sin(2 pi y)),
+                          SAA_TARGET_QUAD (4 y (1 - y)); interpolated at the
+                          nodes, boundary nodes included */
+  int pad_;
 } saa_problem;
+
+enum { SAA_TARGET_CONST = 0, SAA_TARGET_SIN = 1, SAA_TARGET_QUAD = 2 };
 
 /* Options of one objective evaluation.  Fill with saa_options_default() and
  * override fields as needed. */
@@ -375,6 +382,57 @@ int mrdino_data_errors(mrdino_model* model, mrdino_data* data, double* err_state
  * (symmetrised), w: eigenvalues in decreasing order, V: n x n row-major with
  * the eigenvectors as columns.  Needs no GPU. */
 int saa_sym_eig(int n, const double* A, double* w, double* V);
+
+/* ------------------------------------------------------------------------
+ * Outer OUU solve (Sec. 2.1, eq. (ouu); eq. (CVaR_ouu) for the joint form;
+ * Sec. 4.2 minimises over a box Z_ad with a bound-constrained limited-memory
+ * BFGS).  The solver runs on the host; every objective / gradient is one
+ * saa_objective_grad call (PDE or MR-DINO form, options `opt`).  Variables
+ * at a bound whose gradient points out of the box are held for the
+ * iteration; the direction is the L-BFGS two-loop recursion over the free
+ * variables; the step is backtracked along the projected ray to the Armijo
+ * condition.
+ * ------------------------------------------------------------------------ */
+typedef struct saa_ouu_options {
+  int max_iter;        /* outer iterations (default 200) */
+  int max_eval;        /* objective evaluations, line searches included (1000) */
+  int memory;          /* stored (s, y) pairs, 1..100 (10) */
+  int joint_t;         /* 0: t minimised out inside every evaluation (opt->t_mode
+                          must be 0); 1: (z, t) is the variable, t unbounded,
+                          each evaluation is J_hat(z, t) with t_mode = 1 */
+  double pgtol;        /* stop when |P(x - grad) - x|_inf <= pgtol (1e-6) */
+  double ftol;         /* stop when an accepted step lowers J by at most
+                          ftol max(|J|, 1) (1e-12) */
+} saa_ouu_options;
+
+enum { SAA_OUU_PGTOL = 0, SAA_OUU_FTOL = 1, SAA_OUU_MAXITER = 2, SAA_OUU_MAXEVAL = 3, SAA_OUU_LINESEARCH = 4 };
+
+typedef struct saa_ouu_report {
+  double J;            /* objective at the returned z */
+  double pg_norm;      /* projected-gradient infinity norm there */
+  double t;            /* the t of the returned point (t* or the joint t) */
+  double seconds;      /* wall time of the solve */
+  int iterations;      /* accepted steps */
+  int evaluations;     /* saa_objective_grad calls */
+  int status;          /* SAA_OUU_*: why the iteration stopped */
+  int n_active;        /* components of z held at a bound at the end */
+  int n_fallback;      /* evaluations that fell back to the PDE form */
+  int pad;
+} saa_ouu_report;
+
+/* Defaults above.  SAA_E_INVALID for NULL. */
+int saa_ouu_options_default(saa_ouu_options* oo);
+
+/* Minimise J over z in the box [lb, ub] (host arrays of d_Z, either may be
+ * NULL for no bound; entries may be +-inf) from the start z (host, d_Z; it
+ * is projected onto the box first).  On return z holds the last accepted
+ * iterate and *report describes it.  oo may be NULL (defaults).  Returns
+ * SAA_OK whatever the stopping reason (see report->status); SAA_E_INVALID
+ * for bad arguments (lb > ub, NaN bounds, non-finite z, bad options) before
+ * any device work; a failing evaluation's status (e.g. SAA_E_NOCONV) ends the
+ * solve with z at the last accepted iterate. */
+int saa_ouu_solve(saa_ctx* ctx, int form, const void* model, const saa_options* opt, const saa_ouu_options* oo,
+                  const double* lb, const double* ub, double* z, saa_ouu_report* report);
 
 /* Per-sample status of the last saa_objective_grad, saa_per_sample or
  * saa_solve_states call on this context.  Host arrays of N entries each (any

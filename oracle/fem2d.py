@@ -9,7 +9,9 @@ State equation (paper Sec. 4.2, eq. (elliptic_pde), Dirichlet u = 0):
 with Gaussian sources f_k(x) = (sigma sqrt(2 pi))^{-1} exp(-|x-x_k|^2/(2 sigma^2))
 (Sec. 4.2, source definition) and a log-coefficient m drawn from a sine
 Karhunen-Loeve expansion (the KLE input basis of Sec. 3.3).  The QoI is the
-tracking functional Q(u) = int (u - u_target)^2 dx (Sec. 4.2).  Newton on the
+tracking functional Q(u) = int (u - u_target)^2 dx (Sec. 4.2) with one of the
+two target states of Sec. 4.2, sin(2 pi x) sin(2 pi y) or 4 y (1 - y), or a
+constant, interpolated at the nodes.  Newton on the
 discrete residual uses sparse LU, the adjoint reuses the last factors
 (Sec. 2.3, eq. (ouu_qoi_gradient)).
 
@@ -32,6 +34,20 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
+TARGET_CONST, TARGET_SIN, TARGET_QUAD = 0, 1, 2
+
+
+def target_state(prob, xy: np.ndarray) -> np.ndarray:
+    """u_target at the points xy (Sec. 4.2): sin(2 pi x1) sin(2 pi x2),
+    4 x2 (1 - x2), or the constant u_target."""
+    x, y = xy[:, 0], xy[:, 1]
+    if prob.target == TARGET_SIN:
+        return np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    if prob.target == TARGET_QUAD:
+        return 4.0 * y * (1.0 - y)
+    return np.full(len(xy), prob.u_target)
+
+
 @dataclass(frozen=True)
 class Problem2D:
     n: int = 32                  # cells per side
@@ -42,7 +58,8 @@ class Problem2D:
     kl_exp: float = 1.25
     kl_amp: float = 1.0
     reaction: float = 1.0        # r
-    u_target: float = 0.5
+    u_target: float = 0.5        # the target when target == TARGET_CONST
+    target: int = 0              # TARGET_CONST, TARGET_SIN or TARGET_QUAD
 
     @property
     def h(self) -> float:
@@ -210,7 +227,7 @@ def operators(prob: Problem2D) -> Operators2D:
     w_full = lumped_weights_full(n)
     xy = node_coords(n)
     F_full = w_full[:, None] * source_functions(prob, xy)
-    t_full = np.full(len(xy), prob.u_target)
+    t_full = target_state(prob, xy)
     return Operators2D(prob=prob, interior=interior, M_full=M_full,
                        M=M_full[interior][:, interior].tocsr(),
                        w=w_full[interior], F=F_full[interior], t_full=t_full)

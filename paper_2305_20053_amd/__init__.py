@@ -19,6 +19,8 @@ SAA_E_INVALID, SAA_E_NOCONV, SAA_E_DEVICE, SAA_E_OOM, SAA_E_MODEL, SAA_E_IO = -1
 FORM_PDE, FORM_MRDINO = 0, 1
 FP64, FP32, FP32_DC64, BF16, FP8 = 0, 1, 2, 3, 4
 WANT_Q, WANT_DQDZ, WANT_PHI, WANT_DPHIDZ = 1, 2, 4, 8
+TARGET_CONST, TARGET_SIN, TARGET_QUAD = 0, 1, 2
+OUU_PGTOL, OUU_FTOL, OUU_MAXITER, OUU_MAXEVAL, OUU_LINESEARCH = 0, 1, 2, 3, 4
 
 
 class SaaError(RuntimeError):
@@ -27,11 +29,24 @@ class SaaError(RuntimeError):
         self.status = status
 
 
+class COuuOptions(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("max_eval", ctypes.c_int), ("memory", ctypes.c_int),
+                ("joint_t", ctypes.c_int), ("pgtol", ctypes.c_double), ("ftol", ctypes.c_double)]
+
+
+class COuuReport(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_double), ("pg_norm", ctypes.c_double), ("t", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("iterations", ctypes.c_int), ("evaluations", ctypes.c_int),
+                ("status", ctypes.c_int), ("n_active", ctypes.c_int), ("n_fallback", ctypes.c_int),
+                ("pad", ctypes.c_int)]
+
+
 class CProblem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("n_src_per_dim", ctypes.c_int),
                 ("src_sigma", ctypes.c_double), ("kl_per_dim", ctypes.c_int),
                 ("kl_shift", ctypes.c_double), ("kl_exp", ctypes.c_double), ("kl_amp", ctypes.c_double),
-                ("reaction", ctypes.c_double), ("u_target", ctypes.c_double)]
+                ("reaction", ctypes.c_double), ("u_target", ctypes.c_double), ("target", ctypes.c_int),
+                ("pad_", ctypes.c_int)]
 
 
 class COptions(ctypes.Structure):
@@ -84,6 +99,8 @@ _SIGS = {
     "mrdino_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "mrdino_get_dims": (ctypes.c_int, [_P, _P]),
     "mrdino_load": (ctypes.c_int, [ctypes.c_char_p, _P, ctypes.POINTER(_P)]),
+    "saa_ouu_options_default": (ctypes.c_int, [ctypes.POINTER(None)]),
+    "saa_ouu_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.POINTER(COptions), _P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -146,10 +163,11 @@ class Problem:
     reaction: float = 1.0
     u_target: float = 0.5
     dim: int = 2
+    target: int = 0          # TARGET_CONST (u_target), TARGET_SIN or TARGET_QUAD
 
     def c_struct(self) -> CProblem:
         return CProblem(self.dim, self.n, self.n_src_per_dim, self.src_sigma, self.kl_per_dim,
-                        self.kl_shift, self.kl_exp, self.kl_amp, self.reaction, self.u_target)
+                        self.kl_shift, self.kl_exp, self.kl_amp, self.reaction, self.u_target, self.target, 0)
 
     @property
     def d_z(self) -> int:
@@ -160,14 +178,26 @@ class Problem:
         return (self.n - 1) ** self.dim
 
 
-def problem_small() -> Problem:
-    """n = 32 (1089 nodes), 8 x 8 KL modes: the N = 64 correctness workload."""
-    return Problem(n=32, kl_per_dim=8)
+def problem_small(target: int = None) -> Problem:
+    """n = 32 (1089 nodes), 8 x 8 KL modes: the N = 64 correctness workload;
+    sinusoidal target sin(2 pi x) sin(2 pi y) unless `target` says otherwise."""
+    return Problem(n=32, kl_per_dim=8, target=TARGET_SIN if target is None else target)
 
 
-def problem_medium() -> Problem:
-    """n = 128 (16641 nodes), 16 x 16 KL modes: the N = 1024 PDE workload."""
-    return Problem(n=128, kl_per_dim=16)
+def problem_medium(target: int = None) -> Problem:
+    """n = 128 (16641 nodes), 16 x 16 KL modes: the N = 1024 PDE workload;
+    sinusoidal target unless `target` says otherwise."""
+    return Problem(n=128, kl_per_dim=16, target=TARGET_SIN if target is None else target)
+
+
+def ouu_options(**kw) -> COuuOptions:
+    o = COuuOptions()
+    _check(_load().saa_ouu_options_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown OUU option {k}")
+        setattr(o, k, v)
+    return o
 
 
 def options(**kw) -> COptions:
@@ -256,6 +286,23 @@ class Context:
         out = rep.as_dict()
         out["status"] = st
         return q, g, out
+
+    def ouu_solve(self, z0, lb=None, ub=None, form=FORM_PDE, model=None, opt=None, **ouu):
+        """Bound-constrained L-BFGS over z in [lb, ub] (host solver, device
+        evaluations).  ouu: fields of saa_ouu_options.  Returns (z*, report
+        dict); an evaluation failure raises."""
+        import numpy as np
+        opt = opt if opt is not None else options()
+        oo = ouu_options(**ouu)
+        z = np.ascontiguousarray(np.array(z0, dtype=np.float64))
+        lbp = None if lb is None else np.ascontiguousarray(np.broadcast_to(np.asarray(lb, np.float64), (self.d_z,)))
+        ubp = None if ub is None else np.ascontiguousarray(np.broadcast_to(np.asarray(ub, np.float64), (self.d_z,)))
+        rep = COuuReport()
+        st = self._lib.saa_ouu_solve(self._h, form, _P(model.handle if model else None), ctypes.byref(opt),
+                                     ctypes.byref(oo), None if lbp is None else lbp.ctypes.data,
+                                     None if ubp is None else ubp.ctypes.data, z.ctypes.data, ctypes.byref(rep))
+        _check(st)
+        return z, {name: getattr(rep, name) for name, _ in rep._fields_}
 
     def sample_status(self):
         """Per-sample (flags, newton_iters, lin_iters, adj_lin_iters) of the last call (numpy int32)."""

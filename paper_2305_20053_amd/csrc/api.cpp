@@ -55,6 +55,14 @@ using namespace saa_rt;
 
 namespace {
 
+// Target state at (x, y) (Sec. 4.2).
+double target_value(const saa_problem& p, double x, double y) {
+  switch (p.target) {
+    case SAA_TARGET_SIN: return std::sin(2.0 * M_PI * x) * std::sin(2.0 * M_PI * y);
+    case SAA_TARGET_QUAD: return 4.0 * y * (1.0 - y);
+    default: return p.u_target;
+  }
+}
 
 template <typename TS>
 int alloc_mg(saa_ctx* c, MgStore<TS>& m) {
@@ -282,6 +290,8 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!is_fin(p->kl_shift) || p->kl_shift < 0 || !is_fin(p->kl_exp) || p->kl_exp <= 0) return SAA_E_INVALID;
   if (!is_fin(p->kl_amp) || !is_fin(p->reaction) || p->reaction < 0 || !is_fin(p->u_target))
     return SAA_E_INVALID;
+  if (p->target != SAA_TARGET_CONST && p->target != SAA_TARGET_SIN && p->target != SAA_TARGET_QUAD)
+    return SAA_E_INVALID;
   if (N_max < 1 || N_max > (int64_t)1 << 24) return SAA_E_INVALID;
   // the field synthesis keeps a K1 x (n+1) table and the K1 x K1 coefficients in 64 KB of LDS
   if ((int64_t)p->kl_per_dim * (p->n + 1) + (int64_t)p->kl_per_dim * p->kl_per_dim > 8192) return SAA_E_INVALID;
@@ -309,7 +319,6 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   g.dz = c->dz;
   g.h2 = 1.0 / ((double)p->n * p->n);
   g.r = p->reaction;
-  g.ut = p->u_target;
   int64_t ks = 0;
   for (int l = 0; l < g.L; ++l) ks += 2 * (int64_t)g.n[l] * g.n[l];
   c->kstride = ks;
@@ -335,6 +344,7 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (!rc) rc = c->cwork.alloc(saa_launch::cvar_work_bytes());
   if (!rc) rc = c->timer.create();
   if (!rc) rc = c->order.alloc(sizeof(int) * (size_t)c->K1 * c->K1);
+  if (!rc) rc = c->mt.alloc(sizeof(double) * (size_t)c->nodes);
   if (rc) {
     delete c;
     return rc;
@@ -347,6 +357,36 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
     std::vector<int> ord;
     for (const auto& md : modes) ord.push_back((md[1] - 1) * c->K1 + (md[2] - 1));
     rc = check_hip(hipMemcpyAsync(c->order.p, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+  }
+  // tracking target: (M ut) at the interior nodes and ut^T M ut (P1 mass of
+  // the triangulation with diagonals (i,j)-(i+1,j+1), element matrices
+  // area / 12 [[2,1,1],[1,2,1],[1,1,2]])
+  if (!rc) {
+    const int n = p->n, np = n + 1;
+    std::vector<double> ut((size_t)c->nodes);
+    for (int j = 0; j <= n; ++j)
+      for (int i = 0; i <= n; ++i) ut[(size_t)j * np + i] = target_value(*p, (double)i / n, (double)j / n);
+    const double h2 = 1.0 / ((double)n * n);
+    c->mt_host.assign((size_t)c->nodes, 0.0);
+    for (int j = 1; j < n; ++j)
+      for (int i = 1; i < n; ++i) {
+        const size_t q = (size_t)j * np + i;
+        c->mt_host[q] = (h2 / 12.0) * (6.0 * ut[q] + ut[q + 1] + ut[q - 1] + ut[q + np] + ut[q - np] +
+                                       ut[q + np + 1] + ut[q - np - 1]);
+      }
+    double ctt = 0.0;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const double a = ut[(size_t)j * np + i], b = ut[(size_t)j * np + i + 1], d = ut[(size_t)(j + 1) * np + i + 1],
+                     e = ut[(size_t)(j + 1) * np + i];
+        ctt += (a * a + b * b + d * d + (a + b + d) * (a + b + d)) + (a * a + d * d + e * e + (a + d + e) * (a + d + e));
+      }
+    c->ctt = ctt * (0.5 * h2 / 12.0);
+    g.mt = (const double*)c->mt.p;
+    g.ctt = c->ctt;
+    rc = check_hip(hipMemcpyAsync(c->mt.p, c->mt_host.data(), sizeof(double) * c->mt_host.size(),
+                                  hipMemcpyHostToDevice, c->st));
     if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
   }
   // shared operators: sine table, KL amplitudes, lumped source matrix
@@ -561,7 +601,7 @@ int saa_attach_holdout(saa_ctx* c, saa_ctx* holdout) {
     const saa_problem& b = holdout->prob;
     if (a.dim != b.dim || a.n != b.n || a.n_src_per_dim != b.n_src_per_dim || a.src_sigma != b.src_sigma ||
         a.kl_per_dim != b.kl_per_dim || a.kl_shift != b.kl_shift || a.kl_exp != b.kl_exp || a.kl_amp != b.kl_amp ||
-        a.reaction != b.reaction || a.u_target != b.u_target || holdout->N < 1)
+        a.reaction != b.reaction || a.u_target != b.u_target || a.target != b.target || holdout->N < 1)
       return SAA_E_INVALID;
   }
   c->holdout = holdout;

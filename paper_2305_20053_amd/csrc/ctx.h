@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/saa.h"
 #include "pde.h"
@@ -111,6 +112,9 @@ struct saa_ctx {
   int K1 = 0, dz = 0;
   int64_t nodes = 0, d_u = 0;
   saa_rt::DevBuf FT, S, amp, em, xi, kap;
+  saa_rt::DevBuf mt;                  // (M u_target) at interior nodes (node layout), FP64
+  std::vector<double> mt_host;        // the same on the host
+  double ctt = 0.0;                   // u_target^T M u_target
   int64_t kstride = 0, kchunk = 0;
   saa_rt::MgStore<double> mg64;
   saa_rt::MgStore<float> mg32;

@@ -19,7 +19,8 @@ struct PdeGeo {
   int dz;                       // number of controls
   double h2;                    // h^2 = lumped P1 weight of an interior node
   double r;                     // reaction coefficient
-  double ut;                    // target state
+  const double* mt;             // (M u_target) at interior nodes, 0 on the boundary (node layout)
+  double ctt;                   // u_target^T M u_target over all nodes
 };
 
 // Per-sample multigrid / CG workspaces in the solver precision TS.

@@ -638,8 +638,7 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
     }
   }
   if (!conv) flags |= SAA_FLAG_NEWTON;
-  // QoI: q = u^T M_II u - 2 ut h^2 sum u + ut^2 (the full mass has row sum h^2
-  // at interior nodes and total mass 1).
+  // QoI: q = u^T M_II u - 2 u^T (M ut)_I + ut^T M ut (u = 0 on the boundary).
   const double h2 = g.h2;
   double qa = 0.0;
   for_nodes(n, [&](int p, int i, int j) {
@@ -647,12 +646,12 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
       const double up = (double)u[p];
       const double mu = (h2 / 12.0) * (6.0 * up + (double)u[p + 1] + (double)u[p - 1] + (double)u[p + np] +
                                        (double)u[p - np] + (double)u[p + np + 1] + (double)u[p - np - 1]);
-      qa += up * mu - 2.0 * g.ut * h2 * up;
+      qa += up * (mu - 2.0 * g.mt[p]);
     }
   });
   qa = block_sum1(qa, red);
   if (threadIdx.x == 0) {
-    q_out[s] = qa + g.ut * g.ut;
+    q_out[s] = qa + g.ctt;
     newton_out[s] = it;
     lin_out[s] = lin;
     flag_out[s] = flags;
@@ -699,7 +698,7 @@ __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, 
       const double up = (double)u[p];
       const double mu = (h2 / 12.0) * (6.0 * up + (double)u[p + 1] + (double)u[p - 1] + (double)u[p + np] +
                                        (double)u[p - np] + (double)u[p + np + 1] + (double)u[p - np - 1]);
-      v = 2.0 * mu - 2.0 * g.ut * h2;
+      v = 2.0 * (mu - g.mt[p]);
     }
     b[p] = (TW)v;
   });

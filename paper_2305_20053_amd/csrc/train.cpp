@@ -342,7 +342,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   saa_launch::d2f((double*)JYd.p, (float*)D->JY.p, N * dz * r_u, st);
   saa_launch::train_inputs((const double*)c->xi.p, c->K1 * c->K1, (const int*)c->order.p, r_m, Z_dev, dz, N,
                            (float*)D->X.p, st);
-  // 4. reduced QoI terms c = Phi^T (M ubar - u_t h^2 1), c0 (Sec. 3.3)
+  // 4. reduced QoI terms c = Phi^T (M ubar - (M u_t)_I), c0 (Sec. 3.3)
   if ((rc = Mub.alloc(sizeof(double) * du)) || (rc = vdev.alloc(sizeof(double) * du)) ||
       (rc = cdev.alloc(sizeof(double) * r_u)))
     return fail(rc);
@@ -352,13 +352,16 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
       (rc = check_hip(hipMemcpyAsync(mub.data(), Mub.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
       (rc = check_hip(hipStreamSynchronize(st))))
     return fail(rc);
-  const double ut = c->prob.u_target, h2 = 1.0 / ((double)D->n * D->n);
+  // (M u_t) at the interior nodes, interior order
+  const int nn = D->n;
   std::vector<double> v(du);
-  double quad = 0.0, sum = 0.0;
+  double quad = 0.0, cross = 0.0;
   for (int64_t p = 0; p < du; ++p) {
-    v[p] = mub[p] - ut * h2;
+    const int64_t i = p % (nn - 1) + 1, j = p / (nn - 1) + 1;
+    const double mt = c->mt_host[(size_t)(j * (nn + 1) + i)];
+    v[p] = mub[p] - mt;
     quad += ub[p] * mub[p];
-    sum += ub[p];
+    cross += ub[p] * mt;
   }
   if ((rc = check_hip(hipMemcpyAsync(vdev.p, v.data(), sizeof(double) * du, hipMemcpyHostToDevice, st)))) return fail(rc);
   saa_launch::gemm<double>(false, false, r_u, 1, (int)du, 1.0, (double*)D->PhiT.p, (int)du, 0, (double*)vdev.p, 1, 0,
@@ -369,7 +372,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     return fail(rc);
   double cc = 0.0;
   for (double x : D->c) cc += x * x;
-  D->c0 = quad - 2.0 * ut * h2 * sum + ut * ut - cc;
+  D->c0 = quad - 2.0 * cross + c->ctt - cc;
   if ((rc = check_hip(hipGetLastError()))) return fail(rc);
   *out = D;
   return SAA_OK;

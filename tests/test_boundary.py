@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     lib = saa.lib()
-    assert lib.saa_abi_version() == 1
+    assert lib.saa_abi_version() == 2
     for st in (0, 1, -1, -2, -3, -4, -5, -6):
         assert saa.status_str(st) and saa.status_str(st) != "unknown status"
     assert saa.status_str(12345) == "unknown status"
@@ -56,7 +56,7 @@ def test_options_default():
 @pytest.mark.parametrize("field,value", [("n", 3), ("n", 48), ("n", 0), ("dim", 3), ("n_src_per_dim", 0),
                                          ("src_sigma", 0.0), ("src_sigma", float("nan")), ("kl_per_dim", 0),
                                          ("kl_exp", -1.0), ("reaction", -1.0), ("u_target", float("inf")),
-                                         ("kl_per_dim", 64)])
+                                         ("kl_per_dim", 64), ("target", 3), ("target", -1)])
 def test_ctx_create_rejects_bad_problem_before_device_work(field, value):
     p = saa.problem_small()
     if field == "kl_per_dim" and value == 64:

@@ -19,7 +19,7 @@ TOL = {saa.FP64: 1e-9, saa.FP32_DC64: 1e-9, saa.FP32: 1e-4}
 def _oprob(p: saa.Problem) -> fem2d.Problem2D:
     return fem2d.Problem2D(n=p.n, n_src_per_dim=p.n_src_per_dim, src_sigma=p.src_sigma,
                            kl_per_dim=p.kl_per_dim, kl_shift=p.kl_shift, kl_exp=p.kl_exp,
-                           kl_amp=p.kl_amp, reaction=p.reaction, u_target=p.u_target)
+                           kl_amp=p.kl_amp, reaction=p.reaction, u_target=p.u_target, target=p.target)
 
 
 def _rel(a, b):
@@ -62,6 +62,25 @@ def test_small_objective(small, prec):
         assert abs(rep["t_star"] - ref["t"]) <= 1e-14 * abs(ref["t"]) + 1e-12 * 0
     assert rep["n_unconverged"] == 0
     assert 2 <= rep["newton_max"] <= 8
+
+
+@pytest.mark.parametrize("target", [saa.TARGET_CONST, saa.TARGET_QUAD])
+def test_other_targets_per_sample(gpu_lib, target):
+    """The other tracking targets of Sec. 4.2 (the small fixture uses the
+    sinusoidal one): q_i and dq_i/dz of 16 samples, FP64."""
+    prob = saa.problem_small(target=target)
+    print(f"case target={target} per_sample", flush=True)
+    xi = si.kl_coefficients(si.SEED_XI_SMALL, 16, prob.kl_per_dim)
+    z = si.control(si.SEED_Z_SMALL)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 16)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP64))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= 1e-12
+    for i in range(len(q)):
+        assert _rel(g[i], ref["g"][i]) <= TOL[saa.FP64], i
+    ctx.close()
 
 
 def test_adjoint_skipping_is_exact(small):

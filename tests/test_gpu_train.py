@@ -17,12 +17,12 @@ N, R_M, R_U, N_POD = 40, 12, 8, 30
 def _oprob(p):
     return fem2d.Problem2D(n=p.n, n_src_per_dim=p.n_src_per_dim, src_sigma=p.src_sigma, kl_per_dim=p.kl_per_dim,
                            kl_shift=p.kl_shift, kl_exp=p.kl_exp, kl_amp=p.kl_amp, reaction=p.reaction,
-                           u_target=p.u_target)
+                           u_target=p.u_target, target=p.target)
 
 
 @pytest.fixture(scope="module")
 def small(gpu_lib):
-    prob = saa.Problem(n=16, kl_per_dim=4, kl_amp=20.0)
+    prob = saa.Problem(n=16, kl_per_dim=4, kl_amp=20.0, target=saa.TARGET_QUAD)   # boundary target non-zero
     xi = si.kl_coefficients(5001, N, 4)
     Z = si.controls(5002, N)
     ctx = saa.Context(prob, N)

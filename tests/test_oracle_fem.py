@@ -166,3 +166,28 @@ def test_kl_field_recovered_by_sine_orthogonality():
     np.testing.assert_allclose(rec, surrogate.encode(xi[None], r_m)[0], rtol=0, atol=1e-12)
     a = fem2d.kl_amplitudes(prob)
     assert abs(a[0, 0] - (2 * np.pi ** 2 + 25) ** -1.25) < 1e-18
+
+
+@pytest.mark.parametrize("target,exact", [(fem2d.TARGET_SIN, 0.25), (fem2d.TARGET_QUAD, 8.0 / 15.0),
+                                          (fem2d.TARGET_CONST, 0.25)])
+def test_tracking_qoi_of_zero_state_converges_to_target_norm(target, exact):
+    """Q(0) = int u_target^2 over the unit square (Sec. 4.2 targets):
+    int sin^2(2 pi x) sin^2(2 pi y) = 1/4, int 16 y^2 (1 - y)^2 = 8/15, and a
+    constant 0.5 gives 1/4 exactly.  The mass norm of the nodal interpolant
+    converges at second order; dQ/du(0) = -2 (M u_target)_I, whose sum over
+    the interior plus the boundary rows is -2 int u_target."""
+    errs = []
+    for n in (16, 32, 64):
+        ops = fem2d.operators(fem2d.Problem2D(n=n, target=target, u_target=0.5))
+        q = fem2d.qoi(ops, np.zeros(ops.prob.n_unknowns))
+        errs.append(abs(q - exact))
+        g = fem2d.qoi_gradient(ops, np.zeros(ops.prob.n_unknowns))
+        full = -2.0 * (ops.M_full @ ops.t_full)
+        np.testing.assert_allclose(g, full[ops.interior], rtol=1e-14, atol=1e-16)
+        integral = {fem2d.TARGET_SIN: 0.0, fem2d.TARGET_QUAD: 2.0 / 3.0, fem2d.TARGET_CONST: 0.5}[target]
+        assert abs(-0.5 * full.sum() - integral) <= 4.0 / n ** 2
+    if target == fem2d.TARGET_CONST:
+        assert max(errs) <= 1e-14
+    else:
+        assert errs[2] <= 2e-3
+        assert 3.5 <= errs[0] / errs[1] <= 4.5 and 3.5 <= errs[1] / errs[2] <= 4.5, errs
