@@ -135,7 +135,25 @@ typedef struct saa_options {
                           is used instead; < 0 disables */
   int timing;          /* 1: time each phase with HIP events on the context's
                           stream and fill the ms_* fields of the report */
+  int risk;            /* risk measure rho (Sec. 2.1; SAA estimators Sec. 2.2):
+                          SAA_RISK_CVAR: smoothed CVaR_beta by eq. (CVaR_saa_ouu)
+                            (default);
+                          SAA_RISK_MEAN: E[Q] (risk neutral);
+                          SAA_RISK_MEAN_VAR: E[Q] + risk_kappa Var[Q] (the SAA
+                            variance with 1/N), first two moments;
+                          SAA_RISK_POF: smoothed probability of failure
+                            P[Q > risk_tau] ~ E[s_eps'(Q - risk_tau)] (the
+                            derivative of the same C^2 smoothing, a C^1 step
+                            of width eps).
+                          The non-CVaR measures need t_mode = 0; beta is
+                          ignored; the report's t_star is the mean of q
+                          (MEAN_VAR), risk_tau (POF) or 0 (MEAN), dJ_dt 0. */
+  int pad_;
+  double risk_kappa;   /* MEAN_VAR weight, >= 0 */
+  double risk_tau;     /* POF threshold, finite */
 } saa_options;
+
+enum { SAA_RISK_CVAR = 0, SAA_RISK_MEAN = 1, SAA_RISK_MEAN_VAR = 2, SAA_RISK_POF = 3 };
 
 typedef struct saa_report {
   double t_star;       /* the t used (minimiser, or t_in) */

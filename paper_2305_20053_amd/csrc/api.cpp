@@ -33,8 +33,8 @@ void state(const PdeGeo& g, const double* FT, const double* Z, int64_t z_stride,
            hipStream_t st);
 template <typename TW, typename TS>
 void adjoint(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* lam,
-             const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int all_samples,
-             double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st);
+             const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int act,
+             double act_w, double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st);
 template <typename TW, typename TS>
 void linearized(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* x,
                 const MgBufs<TS>& b, const SolveParams& sp, double* dudz, int* lin, int* flag, int64_t N,
@@ -46,6 +46,9 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
           const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
           hipStream_t st);
 size_t cvar_work_bytes();
+void risk(const double* q, const double* g, int64_t N, int dz, int kind, double eps, double kappa, double tau,
+          double alpha, const double* z, int phase, double* tstar, double* out, const int* newton, const int* lin,
+          const int* flag, const int* lin_adj, const int* did, void* stats, void* work, hipStream_t st);
 }  // namespace saa_launch
 
 #include "ctx.h"
@@ -112,6 +115,27 @@ SolveParams solve_params(const saa_options* o, bool fp32_state) {
   return sp;
 }
 
+// The risk reduction of `opt` over (q, g): CVaR (t* search, eq. (CVaR_saa_ouu))
+// or one of the expectation-type measures.  phase & 1: t (t*, the mean of q,
+// tau or 0) -> tstar; phase & 2: J, dJ/dt, grad -> out.
+void reduce(saa_ctx* c, const double* q, const double* g, const saa_options* opt, int phase, const int* newton,
+            const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats) {
+  if (opt->risk == SAA_RISK_CVAR)
+    saa_launch::cvar(q, g, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p, opt->t_mode,
+                     opt->t_in, phase, c->tstar(), c->out(), newton, lin, flag, lin_adj, did, stats, c->cwork.p,
+                     c->st);
+  else
+    saa_launch::risk(q, g, c->N, c->dz, opt->risk, opt->eps, opt->risk_kappa, opt->risk_tau, opt->alpha,
+                     (double*)c->zdev.p, phase, c->tstar(), c->out(), newton, lin, flag, lin_adj, did, stats,
+                     c->cwork.p, c->st);
+}
+
+// Adjoint activity of the risk measure (see saa_k_adjoint).
+int adjoint_act(const saa_options* opt) {
+  if (opt->all_adjoints) return 1;
+  return opt->risk == SAA_RISK_CVAR ? 0 : opt->risk == SAA_RISK_POF ? 2 : 1;
+}
+
 int validate_options(const saa_options* o) {
   if (!o) return SAA_E_INVALID;
   if (!is_fin(o->beta) || o->beta < 0.0 || o->beta >= 1.0) return SAA_E_INVALID;
@@ -121,6 +145,9 @@ int validate_options(const saa_options* o) {
   if (o->t_mode == 1 && !is_fin(o->t_in)) return SAA_E_INVALID;
   if (o->prec < SAA_FP64 || o->prec > SAA_FP8) return SAA_E_INVALID;
   if (!is_fin(o->newton_tol) || !is_fin(o->lin_rtol)) return SAA_E_INVALID;
+  if (o->risk < SAA_RISK_CVAR || o->risk > SAA_RISK_POF) return SAA_E_INVALID;
+  if (o->risk != SAA_RISK_CVAR && o->t_mode != 0) return SAA_E_INVALID;
+  if (!is_fin(o->risk_kappa) || o->risk_kappa < 0.0 || !is_fin(o->risk_tau)) return SAA_E_INVALID;
   return SAA_OK;
 }
 
@@ -158,24 +185,24 @@ int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const Sol
   return check_hip(hipGetLastError());
 }
 
-int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int all, double* gout) {
+int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int act, double act_w, double* gout) {
   switch (prec) {
     case SAA_FP64:
       saa_launch::adjoint<double, double>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
                                           (double*)c->f.p, (double*)c->lam.p, c->mg64.view(), sp, (double*)c->q.p,
-                                          c->tstar(), all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                          c->tstar(), act, act_w, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
                                           (int*)c->did.p, c->N, c->st);
       break;
     case SAA_FP32_DC64:
       saa_launch::adjoint<double, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
                                          (double*)c->f.p, (double*)c->lam.p, c->mg32.view(), sp, (double*)c->q.p,
-                                         c->tstar(), all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                         c->tstar(), act, act_w, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
                                          (int*)c->did.p, c->N, c->st);
       break;
     case SAA_FP32:
       saa_launch::adjoint<float, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (float*)c->u.p,
                                         (float*)c->f.p, (float*)c->lam.p, c->mg32.view(), sp, (double*)c->q.p,
-                                        c->tstar(), all, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
+                                        c->tstar(), act, act_w, gout, (int*)c->lin_adj.p, (int*)c->flag.p,
                                         (int*)c->did.p, c->N, c->st);
       break;
     default:
@@ -452,9 +479,7 @@ int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
 static int surrogate_work(saa_ctx* c, mrdino_model* m, const saa_options* opt) {
   int rc = saa_model_eval(m, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p, (double*)c->g.p);
   if (rc) return rc;
-  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                   (double*)c->zdev.p, opt->t_mode, opt->t_in, 3, c->tstar(), c->out(), nullptr, nullptr, nullptr,
-                   nullptr, nullptr, c->stats(), c->cwork.p, c->st);
+  reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 3, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats());
   return check_hip(hipGetLastError());
 }
 
@@ -510,24 +535,21 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
     if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
     tm.mark(c->st, 1);
-    saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 1, c->tstar(), c->out(),
-                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->cwork.p, c->st);
+    reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     tm.mark(c->st, 2);
-    if ((rc = run_adjoint(c, opt->prec, sp, opt->all_adjoints, (double*)c->g.p))) return rc;
+    if ((rc = run_adjoint(c, opt->prec, sp, adjoint_act(opt), opt->eps, (double*)c->g.p))) return rc;
     tm.mark(c->st, 3);
-    saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                     (double*)c->zdev.p, opt->t_mode, opt->t_in, 2, c->tstar(), c->out(),
-                     (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p,
-                     c->stats(), c->cwork.p, c->st);
+    reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 2, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
+           (int*)c->lin_adj.p, (int*)c->did.p, c->stats());
   } else {
     // surrogate: q and dq/dz of every sample in one fused launch, then the
     // reduction.  The second evaluation with the same arguments captures this
     // device work in a hipGraph; later ones replay it (untimed calls only).
     mrdino_model* m = (mrdino_model*)model;
     SurrogateGraph& sg = c->sg;
-    const SurrogateGraph::Key key{m->serial, opt->prec, opt->t_mode, opt->beta, opt->eps, opt->alpha, opt->t_in,
-                                  c->N};
+    const SurrogateGraph::Key key{m->serial, opt->prec,      opt->t_mode, opt->beta,       opt->eps,
+                                  opt->alpha, opt->t_in,     c->N,        opt->risk,       opt->risk_kappa,
+                                  opt->risk_tau};
     const bool enc_ready = opt->prec == SAA_FP32 || c->enc_rm == m->dims.r_m;
     if (!tm.on && !sg.disabled && !(sg.exec && sg.key == key) && sg.seen == key && enc_ready &&
         (rc = capture_surrogate(c, m, opt, key)))
@@ -541,9 +563,7 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
       tm.mark(c->st, 1);
       tm.mark(c->st, 2);
       tm.mark(c->st, 3);
-      saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, opt->beta, opt->eps, opt->alpha,
-                       (double*)c->zdev.p, opt->t_mode, opt->t_in, 3, c->tstar(), c->out(), nullptr, nullptr,
-                       nullptr, nullptr, nullptr, c->stats(), c->cwork.p, c->st);
+      reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 3, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats());
       sg.seen = key;
     }
   }
@@ -619,19 +639,15 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
   if (form == SAA_FORM_PDE) {
     const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
     if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
-    if ((rc = run_adjoint(c, opt->prec, sp, 1, g_dev))) return rc;
+    if ((rc = run_adjoint(c, opt->prec, sp, 1, 0.0, g_dev))) return rc;
     if ((rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
       return rc;
-    saa_launch::cvar((double*)c->q.p, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p,
-                     opt->t_mode, opt->t_in, 3, c->tstar(), c->out(), (int*)c->newton.p,
-                     (int*)c->lin.p, (int*)c->flag.p, (int*)c->lin_adj.p, (int*)c->did.p, c->stats(),
-                     c->cwork.p, c->st);
+    reduce(c, (double*)c->q.p, g_dev, opt, 3, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
+           (int*)c->lin_adj.p, (int*)c->did.p, c->stats());
   } else {
     if ((rc = saa_model_eval((mrdino_model*)model, c, (const double*)c->zdev.p, opt->prec, q_dev, g_dev)))
       return rc;
-    saa_launch::cvar(q_dev, g_dev, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p, opt->t_mode,
-                     opt->t_in, 3, c->tstar(), c->out(), nullptr, nullptr, nullptr, nullptr,
-                     nullptr, c->stats(), c->cwork.p, c->st);
+    reduce(c, q_dev, g_dev, opt, 3, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats());
   }
   if ((rc = check_hip(hipGetLastError()))) return rc;
   if ((rc = fetch_results(c))) return rc;

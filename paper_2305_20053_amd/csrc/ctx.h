@@ -83,9 +83,11 @@ struct SurrogateGraph {
     int prec = -1, t_mode = 0;
     double beta = 0, eps = 0, alpha = 0, t_in = 0;
     int64_t N = 0;
+    int risk = 0;
+    double kappa = 0, tau = 0;
     bool operator==(const Key& o) const {
       return model == o.model && prec == o.prec && t_mode == o.t_mode && beta == o.beta && eps == o.eps &&
-             alpha == o.alpha && t_in == o.t_in && N == o.N;
+             alpha == o.alpha && t_in == o.t_in && N == o.N && risk == o.risk && kappa == o.kappa && tau == o.tau;
     }
   };
   Key key, seen;               // key of `exec`; key of the last eager evaluation

@@ -39,6 +39,7 @@
 // results are bitwise reproducible.
 #include <cfloat>
 
+#include "../../include/saa.h"
 #include "common.h"
 #include "pde.h"
 
@@ -493,11 +494,42 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
   if (threadIdx.x == 0) tstar[0] = t;
 }
 
-// 5. per-workgroup partial sums: sum s_eps, sum s_eps', sum s_eps' dq/dz.
+// Per-sample value v and weight d = dv/dq of a risk measure written as a mean
+// of v(q_i) (t = tstar[0]):
+//  RISK_CVAR      v = s_eps(q - t), d = s_eps'(q - t)        (eq. (CVaR_saa_ouu))
+//  RISK_MEAN      v = q,            d = 1                    (eq. (saa))
+//  RISK_MEAN_VAR  v = q + kappa (q - t)^2, d = 1 + 2 kappa (q - t), t = mean q
+//                 (d/dq_i of the SAA variance: the mean's own derivative
+//                 cancels since sum (q - t) = 0)
+//  RISK_POF       v = s_eps'(q - t), d = s_eps''(q - t),     t = tau
+template <int KIND>
+__device__ __forceinline__ void risk_terms(double qi, double t, double eps, double ie, double kappa, double& v,
+                                           double& d) {
+  if (KIND == SAA_RISK_CVAR) {
+    const double x = qi - t;
+    v = sp_val(x, eps, ie);
+    d = sp_d1(x, eps, ie);
+  } else if (KIND == SAA_RISK_MEAN) {
+    v = qi;
+    d = 1.0;
+  } else if (KIND == SAA_RISK_MEAN_VAR) {
+    const double x = qi - t;
+    v = qi + kappa * x * x;
+    d = 1.0 + 2.0 * kappa * x;
+  } else {
+    const double x = qi - t;
+    v = sp_d1(x, eps, ie);
+    d = sp_d2(x, eps, ie);
+  }
+}
+
+// 5. per-workgroup partial sums: sum v, sum d, sum d dq/dz (see risk_terms).
 // The weighted samples of each tile are listed in LDS; wave k of the block
 // then takes every (RBS/64)-th of them with lane c accumulating component c.
+template <int KIND>
 __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const double* g, int64_t N, int dz,
-                                                       CvarWork w, int G, double eps, const double* tstar) {
+                                                       CvarWork w, int G, double eps, double kappa,
+                                                       const double* tstar) {
   __shared__ double red[2 * (RBS / SAA_WAVE)];
   __shared__ int sh[RBS / SAA_WAVE];
   __shared__ int li[TILE];
@@ -518,9 +550,9 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
       const int64_t i = t0 + 4 * threadIdx.x + r;
       d[r] = 0.0;
       if (i < i1) {
-        const double x = q[i] - t;
-        v[0] += sp_val(x, eps, ie);
-        d[r] = sp_d1(x, eps, ie);
+        double vi;
+        risk_terms<KIND>(q[i], t, eps, ie, kappa, vi, d[r]);
+        v[0] += vi;
         v[1] += d[r];
       }
       n += d[r] != 0.0 ? 1 : 0;
@@ -558,7 +590,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
 // 6. reduce the partials in a fixed order -> out[0] = J, out[1] = dJ/dt,
 // out[2..2+dz) = grad (when `outputs`); optional per-sample solver stats.
 __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarWork w, int G, double target,
-                                                        double alpha, const double* z, const double* tstar,
+                                                        int kind, double alpha, const double* z, const double* tstar,
                                                         int outputs, double* out, const int* newton, const int* lin,
                                                         const int* flag, const int* lin_adj, const int* did,
                                                         CvarStats* stats) {
@@ -609,14 +641,39 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
   if (k >= ncol) return;
   double acc = 0.0;
   for (int r = 0; r < NW; ++r) acc += col[r][k];
-  const double scale = 1.0 / target;
+  const double scale = 1.0 / target;   // 1 / (N (1 - beta)) for CVaR, else 1 / N
+  const bool cv = kind == SAA_RISK_CVAR;
   if (k == 0) {
-    out[0] = tstar[0] + scale * acc + 0.5 * alpha * zz;
+    out[0] = (cv ? tstar[0] : 0.0) + scale * acc + 0.5 * alpha * zz;
   } else if (k == 1) {
-    out[1] = 1.0 - scale * acc;
+    out[1] = cv ? 1.0 - scale * acc : 0.0;
   } else {
     out[k] = scale * acc + alpha * z[k - 2];
   }
+}
+
+// Mean of q for RISK_MEAN_VAR: per-workgroup partial sums (chunk order) ...
+__global__ void __launch_bounds__(RBS) saa_k_risk_sum(const double* q, int64_t N, CvarWork w, int G) {
+  __shared__ double red[2 * (RBS / SAA_WAVE)];
+  int64_t i0, i1;
+  chunk_of(N, G, i0, i1);
+  double s[1] = {0.0};
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += RBS) s[0] += q[i];
+  block_sum<1>(s, red);
+  if (threadIdx.x == 0) w.mm[2 * blockIdx.x] = s[0];
+}
+
+// ... reduced in workgroup order by one wave -> tstar[0]; tau (POF), 0 (MEAN).
+__global__ void __launch_bounds__(SAA_WAVE) saa_k_risk_t(int64_t N, CvarWork w, int G, int kind, double tau,
+                                                         double* tstar) {
+  if (kind != SAA_RISK_MEAN_VAR) {
+    if (threadIdx.x == 0) tstar[0] = kind == SAA_RISK_POF ? tau : 0.0;
+    return;
+  }
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int b = 0; b < G; ++b) s += w.mm[2 * b];
+  if (threadIdx.x == 0) tstar[0] = s / (double)N;
 }
 
 namespace saa_launch {
@@ -628,10 +685,7 @@ size_t cvar_work_bytes() {
 
 // phase & 1: t (minimiser, or t_in when t_mode = 1) -> tstar[0];
 // phase & 2: J, dJ/dt, grad -> out; stats (if non-null) -> stats.
-void cvar(const double* q, const double* g, int64_t N, int dz, double beta, double eps, double alpha,
-          const double* z, int t_mode, double t_in, int phase, double* tstar, double* out, const int* newton,
-          const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
-          hipStream_t st) {
+static CvarWork carve(void* work) {
   CvarWork w;
   char* p = (char*)work;
   w.mm = (double*)p;
@@ -649,8 +703,20 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
   w.nabove = (int*)p;
   p += sizeof(int) * GMAX;
   w.act_total = (int*)p;
-  const int64_t gw = (N + 255) / 256;   // 256 samples per workgroup, up to GMAX workgroups
-  const int G = (int)(gw < 1 ? 1 : gw > GMAX ? GMAX : gw);
+  return w;
+}
+
+static int groups(int64_t N) {   // 256 samples per workgroup, up to GMAX workgroups
+  const int64_t gw = (N + 255) / 256;
+  return (int)(gw < 1 ? 1 : gw > GMAX ? GMAX : gw);
+}
+
+void cvar(const double* q, const double* g, int64_t N, int dz, double beta, double eps, double alpha,
+          const double* z, int t_mode, double t_in, int phase, double* tstar, double* out, const int* newton,
+          const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
+          hipStream_t st) {
+  const CvarWork w = carve(work);
+  const int G = groups(N);
   const double target = (double)N * (1.0 - beta);
   if (phase & 1) {
     if (t_mode != 1) {
@@ -661,10 +727,37 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
     }
     saa_k_cvar_solve<<<1, SBS, 0, st>>>(q, N, w, G, eps, target, t_mode, t_in, tstar);
   }
-  if (phase & 2) saa_k_cvar_part<<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, tstar);
+  if (phase & 2) saa_k_cvar_part<SAA_RISK_CVAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, tstar);
   if ((phase & 2) || stats)
-    saa_k_cvar_final<<<1, SBS, 0, st>>>(N, dz, w, G, target, alpha, z, tstar, (phase & 2) ? 1 : 0, out, newton, lin,
-                                        flag, lin_adj, did, (CvarStats*)stats);
+    saa_k_cvar_final<<<1, SBS, 0, st>>>(N, dz, w, G, target, SAA_RISK_CVAR, alpha, z, tstar, (phase & 2) ? 1 : 0,
+                                        out, newton, lin, flag, lin_adj, did, (CvarStats*)stats);
+}
+
+// Expectation-type risk measures (Sec. 2.1): phase & 1: t -> tstar[0] (mean of
+// q for MEAN_VAR, in a fixed order; tau for POF; 0 for MEAN); phase & 2:
+// J = (1/N) sum v_i + alpha/2 |z|^2, dJ/dt = 0, grad = (1/N) sum d_i dq_i/dz
+// + alpha z (risk_terms).  Same workspace and result layout as cvar().
+void risk(const double* q, const double* g, int64_t N, int dz, int kind, double eps, double kappa, double tau,
+          double alpha, const double* z, int phase, double* tstar, double* out, const int* newton, const int* lin,
+          const int* flag, const int* lin_adj, const int* did, void* stats, void* work, hipStream_t st) {
+  const CvarWork w = carve(work);
+  const int G = groups(N);
+  if (phase & 1) {
+    if (kind == SAA_RISK_MEAN_VAR) saa_k_risk_sum<<<G, RBS, 0, st>>>(q, N, w, G);
+    saa_k_risk_t<<<1, SAA_WAVE, 0, st>>>(N, w, G, kind, tau, tstar);
+  }
+  if (phase & 2) {
+    switch (kind) {
+      case SAA_RISK_MEAN: saa_k_cvar_part<SAA_RISK_MEAN><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tstar); break;
+      case SAA_RISK_MEAN_VAR:
+        saa_k_cvar_part<SAA_RISK_MEAN_VAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tstar);
+        break;
+      default: saa_k_cvar_part<SAA_RISK_POF><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tstar);
+    }
+  }
+  if ((phase & 2) || stats)
+    saa_k_cvar_final<<<1, SBS, 0, st>>>(N, dz, w, G, (double)N, kind, alpha, z, tstar, (phase & 2) ? 1 : 0, out,
+                                        newton, lin, flag, lin_adj, did, (CvarStats*)stats);
 }
 
 }  // namespace saa_launch

@@ -660,20 +660,23 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
 
 // ---------------------------------------------------------------------------
 // Adjoint: A(u) lambda = 2 (M (u - ut))_I, g = F^T lambda (Sec. 2.3).  One
-// block per sample.  Samples with q_i <= t (zero CVaR weight: s_eps'(q - t) = 0)
-// are skipped unless `all`; their g row is written as 0.
+// block per sample.  Only samples whose risk weight can be non-zero are
+// solved (act 0: q_i > t, the CVaR weight s_eps'(q - t) > 0; act 1: all;
+// act 2: 0 < q_i - t < act_w, the smoothed failure-probability weight
+// s_eps''(q - t) != 0); the others get a zero g row.
 // ---------------------------------------------------------------------------
 template <typename TW, typename TS, bool LDSC>
 __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, const double* em_all,
                                                     const TW* u_all, TW* b_all, TW* lam_all, MgBufs<TS> all,
                                                     SolveParams sp, const double* q, const double* tstar,
-                                                    int all_samples, double* g_out, int* lin_out, int* flag_out,
-                                                    int* did_out, int64_t N) {
+                                                    int act, double act_w, double* g_out, int* lin_out,
+                                                    int* flag_out, int* did_out, int64_t N) {
   __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
   const int64_t s = blockIdx.x;
   if (s >= N) return;
   const int n = g.n[0], np = n + 1;
-  const bool active = all_samples || (q[s] - tstar[0] > 0.0);
+  const double xq = q[s] - tstar[0];
+  const bool active = act == 1 || (xq > 0.0 && (act == 0 || xq < act_w));
   if (!active) {
     if (threadIdx.x < g.dz) g_out[s * g.dz + threadIdx.x] = 0.0;
     if (threadIdx.x == 0) {
@@ -855,16 +858,16 @@ void state(const PdeGeo& g, const double* FT, const double* Z, int64_t z_stride,
 
 template <typename TW, typename TS>
 void adjoint(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* lam,
-             const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int all_samples,
-             double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st) {
+             const MgBufs<TS>& b, const SolveParams& sp, const double* q, const double* tstar, int act,
+             double act_w, double* gout, int* lin, int* flag, int* did, int64_t N, hipStream_t st) {
   const size_t lds = coarse_lds_bytes<TS>(g);
   if (lds) {
     static bool attr = set_lds_attr((const void*)saa_k_adjoint<TW, TS, true>, lds);
     (void)attr;
-    saa_k_adjoint<TW, TS, true><<<(unsigned)N, BS, lds, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, all_samples,
+    saa_k_adjoint<TW, TS, true><<<(unsigned)N, BS, lds, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, act, act_w,
                                                               gout, lin, flag, did, N);
   } else {
-    saa_k_adjoint<TW, TS, false><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, all_samples,
+    saa_k_adjoint<TW, TS, false><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, lam, b, sp, q, tstar, act, act_w,
                                                                gout, lin, flag, did, N);
   }
 }
@@ -895,7 +898,7 @@ void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st) {
                               hipStream_t);                                                                      \
   template void adjoint<TW, TS>(const PdeGeo&, const double*, const double*, const TW*, TW*, TW*,                \
                                 const MgBufs<TS>&, const SolveParams&, const double*, const double*, int,        \
-                                double*, int*, int*, int*, int64_t, hipStream_t);                                \
+                                double, double*, int*, int*, int*, int64_t, hipStream_t);                                \
   template void linearized<TW, TS>(const PdeGeo&, const double*, const double*, const TW*, TW*, TW*,             \
                                    const MgBufs<TS>&, const SolveParams&, double*, int*, int*, int64_t,          \
                                    hipStream_t);
