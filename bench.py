@@ -80,6 +80,9 @@ def cpu_baseline(prob, xi, z, seconds_target=15.0):
                       f"QoI and adjoint per sample (float64 scipy), {workers} worker processes, {wall:.1f} s"}
 
 
+# admissible box of the controls (Sec. 4.2), also the training control law
+Z_LO, Z_HI = -4.0, 4.0
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 MFMA_FP8_PEAK_TFLOPS = 5000.0
 VEC_FP32_PEAK_TFLOPS = 157.3
@@ -91,7 +94,8 @@ MRDINO_FLOP_PER_SAMPLE = 2 * (125 * 256 + 3 * 256 ** 2 + 256 * 200) + 2 * (200 *
 
 def train_surrogate(saa, si, epochs):
     """The MR-DINO of the 128 x 128 problem (Sec. 3.3-3.4): 2048 training
-    samples (xi seed 2307, z ~ U[0,1]^25 seed 2308) solved by the GPU PDE form
+    samples (xi seed 2307, z ~ U[-4,4]^25 seed 2308, the admissible box of
+    Sec. 4.2) solved by the GPU PDE form
     with their 25 control Jacobians, weighted POD of 1024 snapshots to r_u = 200,
     r_m = 100 KL inputs, width 256 x depth 4 GELU network, DINO loss, Adam
     lr 1e-3 -> 2.5e-4 at half the epochs, batch 256, FP32 training kernels."""
@@ -101,7 +105,7 @@ def train_surrogate(saa, si, epochs):
     t0 = time.perf_counter()
     ctx = saa.Context(prob, 2048)
     ctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_TRAIN, 2048, prob.kl_per_dim)).cuda())
-    Zt = torch.from_numpy(si.controls(si.SEED_Z_TRAIN, 2048)).cuda()
+    Zt = torch.from_numpy(si.controls(si.SEED_Z_TRAIN, 2048, lo=Z_LO, hi=Z_HI)).cuda()
     data = saa.TrainData(ctx, Zt, r_m=100, r_u=200, n_pod=1024)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
@@ -116,15 +120,16 @@ def train_surrogate(saa, si, epochs):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     es, ej = saa.data_errors(model, data)
-    info = {"train_samples": 2048, "n_pod": 1024, "r_m": 100, "r_u": 200, "epochs": epochs, "batch": 256,
+    qoi = {t: data.qoi(t) for t in (saa.TARGET_SIN, saa.TARGET_QUAD)}   # one network, several objectives
+    info = {"train_samples": 2048, "z_box": [Z_LO, Z_HI], "n_pod": 1024, "r_m": 100, "r_u": 200, "epochs": epochs, "batch": 256,
             "data_s": t_data, "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
             "train_rel_err_state": es, "train_rel_err_jacobian": ej}
     data.close()
     ctx.close()
-    return model, info
+    return model, info, qoi
 
 
-def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs):
+def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True):
     """Surrogate form at N = 65536 samples (n = 128 KL field, 16 x 16 modes):
     the trained MR-DINO (or random Glorot weights with epochs = 0) in BF16 and
     FP32, timed like the PDE form; its error against the GPU PDE form on 256
@@ -134,8 +139,9 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs):
     import torch
     prob = saa.problem_medium()
     N = 65536
+    qoi = None
     if epochs > 0:
-        model, tinfo = train_surrogate(saa, si, epochs)
+        model, tinfo, qoi = train_surrogate(saa, si, epochs)
     else:
         model = saa.Model(100, 25, 200, 256, 4)
         layers = si.glorot_mlp(2313, model.widths())
@@ -203,9 +209,65 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs):
         out["training"] = tinfo
     out["ratio_bf16_over_pde"] = out["bf16"]["value"] / pde_value
     hold.close()
+    if qoi is not None and ouu:
+        out["ouu"] = bench_ouu(saa, si, model, qoi, ctx)
     model.close()
     ctx.close()
     return out
+
+
+def bench_ouu(saa, si, model, qoi, ctx_nn):
+    """The OUU experiment of Sec. 4.2 with one trained network reused across
+    objectives: for the sinusoidal and quadratic targets at beta = 0.95 and
+    the sinusoidal one at beta = 0.9 and 0.99, minimise over z in [-4, 4]^25
+    (bound-constrained L-BFGS from z = 0) with the MR-DINO form (BF16,
+    N = 65536) and with the PDE form (FP32-DC64, N = 1024, the reference);
+    both optima are then evaluated by the PDE form on 1024 independent
+    samples (xi seed 2309): relative optimal cost error |J(z_nn) - J(z_ref)| /
+    |J(z_ref)|.  State-solve counts: training samples for the network,
+    evaluations x N for the PDE-form optimisation."""
+    import numpy as np
+    import torch
+    cases = [("sin", saa.TARGET_SIN, 0.95), ("quad", saa.TARGET_QUAD, 0.95), ("sin", saa.TARGET_SIN, 0.9),
+             ("sin", saa.TARGET_SIN, 0.99)]
+    Nref = 1024
+    xi_ref = torch.from_numpy(si.kl_coefficients(si.SEED_XI_MEDIUM, Nref, 16)).cuda()
+    xi_ev = torch.from_numpy(si.kl_coefficients(si.SEED_XI_VALID, Nref, 16)).cuda()
+    ctxs = {}
+    res = []
+    z0 = np.zeros(25)
+    for name, target, beta in cases:
+        if target not in ctxs:
+            p = saa.problem_medium(target=target)
+            a, b = saa.Context(p, Nref), saa.Context(p, Nref)
+            a.set_samples(xi_ref)
+            b.set_samples(xi_ev)
+            ctxs[target] = (a, b)
+        c_ref, c_ev = ctxs[target]
+        c, c0 = qoi[target]
+        model.set_qoi(c, c0)
+        o_nn = saa.options(prec=saa.BF16, beta=beta, fallback_tol=-1.0)
+        z_nn, r_nn = ctx_nn.ouu_solve(z0, Z_LO, Z_HI, form=saa.FORM_MRDINO, model=model, opt=o_nn, pgtol=1e-6)
+        o_pde = saa.options(prec=saa.FP32_DC64, beta=beta)
+        z_ref, r_ref = c_ref.ouu_solve(z0, Z_LO, Z_HI, opt=o_pde, pgtol=1e-6)
+        J_nn = c_ev.objective_grad(z_nn, opt=o_pde)[0]
+        J_ref = c_ev.objective_grad(z_ref, opt=o_pde)[0]
+        J_0 = c_ev.objective_grad(z0, opt=o_pde)[0]
+        res.append({"target": name, "beta": beta, "rel_optimal_cost_error": abs(J_nn - J_ref) / abs(J_ref),
+                    "J_pde_at_z_nn": J_nn, "J_pde_at_z_ref": J_ref, "J_pde_at_z0": J_0,
+                    "z_diff_inf": float(np.abs(z_nn - z_ref).max()),
+                    "nn": {"seconds": r_nn["seconds"], "iterations": r_nn["iterations"],
+                           "evaluations": r_nn["evaluations"], "status": r_nn["status"],
+                           "n_active": r_nn["n_active"], "N": ctx_nn.n, "state_solves": 2048},
+                    "pde": {"seconds": r_ref["seconds"], "iterations": r_ref["iterations"],
+                            "evaluations": r_ref["evaluations"], "status": r_ref["status"],
+                            "n_active": r_ref["n_active"], "N": Nref,
+                            "state_solves": r_ref["evaluations"] * Nref}})
+    for a, b in ctxs.values():
+        a.close()
+        b.close()
+    return {"box": [Z_LO, Z_HI], "optimizer": "bound-constrained L-BFGS (saa_ouu_solve), pgtol 1e-6",
+            "eval_samples": Nref, "cases": res}
 
 
 def main():
@@ -218,6 +280,7 @@ def main():
     ap.add_argument("--no-mrdino", action="store_true", help="skip the surrogate-form leg")
     ap.add_argument("--train-epochs", type=int, default=1600,
                     help="epochs of the MR-DINO trained for the surrogate leg (0: random weights, no training)")
+    ap.add_argument("--no-ouu", action="store_true", help="skip the OUU experiment of the surrogate leg")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -298,8 +361,8 @@ def main():
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "fp32_dc64": "f32+f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "PDE form: 128x128 P1 semilinear elliptic (16641 nodes, 16129 unknowns), "
-                               "N=1024 KL samples (16x16 modes), 25 sources, smoothed CVaR_0.95, "
-                               f"precision {args.prec}",
+                               "N=1024 KL samples (16x16 modes), 25 sources, sinusoidal target, "
+                               f"smoothed CVaR_0.95, precision {args.prec}",
                    "n": prob.n, "N": N, "form": "pde", "prec": args.prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -313,7 +376,9 @@ def main():
     }
     ctx.close()
     if not args.no_mrdino:
-        out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs, value, args.train_epochs)
+        zs_box = [si.control(s, lo=Z_LO, hi=Z_HI) for s in si.SEED_Z_EVAL]
+        out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs_box, value, args.train_epochs,
+                                     not args.no_ouu)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, xi, zs[0])
     print(json.dumps(out), flush=True)

@@ -357,6 +357,13 @@ void mrdino_data_free(mrdino_data* data);
  * n_pod, decreasing); any pointer may be NULL. */
 int mrdino_data_info(const mrdino_data* data, int64_t* N, double* c, double* c0, double* lam);
 
+/* Reduced-QoI terms c (host, r_u) and c0 of the tracking functional for
+ * another target state (target: SAA_TARGET_*, u_target for the constant one)
+ * with the same POD basis: one trained surrogate serves several objectives
+ * (Sec. 4.2 reuses one network across targets and beta).  Pass them to
+ * mrdino_set_qoi.  SAA_E_INVALID for a bad target or NULL pointers. */
+int mrdino_data_qoi(const mrdino_data* data, int target, double u_target, double* c, double* c0);
+
 /* Copy a data array to host memory: which = 0 inputs X (float, N x (r_m+d_Z)),
  * 1 Y (float, N x r_u), 2 J (float, (N d_Z) x r_u, row i d_Z + k holds
  * d/dz_k of sample i), 3 Phi^T (double, r_u x d_U), 4 mean state b (double,

@@ -434,6 +434,7 @@ _SIGS.update({
                                           ctypes.POINTER(COptions), _P, ctypes.POINTER(_P), ctypes.POINTER(CReport)]),
     "mrdino_data_free": (None, [_P]),
     "mrdino_data_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "mrdino_data_qoi": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)]),
     "mrdino_data_get": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int64]),
     "mrdino_loss_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]),
     "mrdino_train": (ctypes.c_int, [_P, _P, ctypes.POINTER(CTrainCfg), _P, ctypes.POINTER(ctypes.c_double)]),
@@ -512,6 +513,14 @@ class TrainData:
         c0 = ctypes.c_double()
         _check(self._lib.mrdino_data_info(self._h, None, c.ctypes.data, ctypes.byref(c0), lam.ctypes.data))
         return c, c0.value, lam
+
+    def qoi(self, target: int, u_target: float = 0.5):
+        """(c, c0) of the tracking QoI for another target with this POD basis."""
+        import numpy as np
+        c = np.zeros(self.r_u)
+        c0 = ctypes.c_double()
+        _check(self._lib.mrdino_data_qoi(self._h, target, u_target, c.ctypes.data, ctypes.byref(c0)))
+        return c, c0.value
 
     def get(self, which: str):
         """'X', 'Y', 'J' (float32) or 'PhiT', 'ubar' (float64) as numpy arrays."""

@@ -56,16 +56,48 @@ void risk(const double* q, const double* g, int64_t N, int dz, int kind, double 
 
 using namespace saa_rt;
 
-namespace {
+namespace saa_rt {
+
+// Tracking target: (M ut) at the interior nodes (node layout, 0 on the
+// boundary) and ut^T M ut over all nodes, for the P1 mass of the
+// triangulation with diagonals (i,j)-(i+1,j+1) (element matrices
+// area / 12 [[2,1,1],[1,2,1],[1,1,2]]).
+double target_value(int target, double u_target, double x, double y);
+void target_mass(int n, int target, double u_target, std::vector<double>& mt, double& ctt) {
+  const int np = n + 1;
+  std::vector<double> ut((size_t)np * np);
+  for (int j = 0; j <= n; ++j)
+    for (int i = 0; i <= n; ++i) ut[(size_t)j * np + i] = target_value(target, u_target, (double)i / n, (double)j / n);
+  const double h2 = 1.0 / ((double)n * n);
+  mt.assign((size_t)np * np, 0.0);
+  for (int j = 1; j < n; ++j)
+    for (int i = 1; i < n; ++i) {
+      const size_t q = (size_t)j * np + i;
+      mt[q] = (h2 / 12.0) *
+              (6.0 * ut[q] + ut[q + 1] + ut[q - 1] + ut[q + np] + ut[q - np] + ut[q + np + 1] + ut[q - np - 1]);
+    }
+  double s = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const double a = ut[(size_t)j * np + i], b = ut[(size_t)j * np + i + 1], d = ut[(size_t)(j + 1) * np + i + 1],
+                   e = ut[(size_t)(j + 1) * np + i];
+      s += (a * a + b * b + d * d + (a + b + d) * (a + b + d)) + (a * a + d * d + e * e + (a + d + e) * (a + d + e));
+    }
+  ctt = s * (0.5 * h2 / 12.0);
+}
 
 // Target state at (x, y) (Sec. 4.2).
-double target_value(const saa_problem& p, double x, double y) {
-  switch (p.target) {
+double target_value(int target, double u_target, double x, double y) {
+  switch (target) {
     case SAA_TARGET_SIN: return std::sin(2.0 * M_PI * x) * std::sin(2.0 * M_PI * y);
     case SAA_TARGET_QUAD: return 4.0 * y * (1.0 - y);
-    default: return p.u_target;
+    default: return u_target;
   }
 }
+
+}  // namespace saa_rt
+
+namespace {
 
 template <typename TS>
 int alloc_mg(saa_ctx* c, MgStore<TS>& m) {
@@ -386,30 +418,8 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
     rc = check_hip(hipMemcpyAsync(c->order.p, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice, c->st));
     if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
   }
-  // tracking target: (M ut) at the interior nodes and ut^T M ut (P1 mass of
-  // the triangulation with diagonals (i,j)-(i+1,j+1), element matrices
-  // area / 12 [[2,1,1],[1,2,1],[1,1,2]])
   if (!rc) {
-    const int n = p->n, np = n + 1;
-    std::vector<double> ut((size_t)c->nodes);
-    for (int j = 0; j <= n; ++j)
-      for (int i = 0; i <= n; ++i) ut[(size_t)j * np + i] = target_value(*p, (double)i / n, (double)j / n);
-    const double h2 = 1.0 / ((double)n * n);
-    c->mt_host.assign((size_t)c->nodes, 0.0);
-    for (int j = 1; j < n; ++j)
-      for (int i = 1; i < n; ++i) {
-        const size_t q = (size_t)j * np + i;
-        c->mt_host[q] = (h2 / 12.0) * (6.0 * ut[q] + ut[q + 1] + ut[q - 1] + ut[q + np] + ut[q - np] +
-                                       ut[q + np + 1] + ut[q - np - 1]);
-      }
-    double ctt = 0.0;
-    for (int j = 0; j < n; ++j)
-      for (int i = 0; i < n; ++i) {
-        const double a = ut[(size_t)j * np + i], b = ut[(size_t)j * np + i + 1], d = ut[(size_t)(j + 1) * np + i + 1],
-                     e = ut[(size_t)(j + 1) * np + i];
-        ctt += (a * a + b * b + d * d + (a + b + d) * (a + b + d)) + (a * a + d * d + e * e + (a + d + e) * (a + d + e));
-      }
-    c->ctt = ctt * (0.5 * h2 / 12.0);
+    saa_rt::target_mass(p->n, p->target, p->u_target, c->mt_host, c->ctt);
     g.mt = (const double*)c->mt.p;
     g.ctt = c->ctt;
     rc = check_hip(hipMemcpyAsync(c->mt.p, c->mt_host.data(), sizeof(double) * c->mt_host.size(),

@@ -12,6 +12,10 @@
 
 namespace saa_rt {
 
+// (M u_target) at the interior nodes (node layout) and u_target^T M u_target
+// for a target kind of saa_problem on the n x n mesh.
+void target_mass(int n, int target, double u_target, std::vector<double>& mt, double& ctt);
+
 template <typename TS>
 struct MgStore {
   DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;

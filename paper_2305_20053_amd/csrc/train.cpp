@@ -243,6 +243,50 @@ void saa_model_free_train(mrdino_model* m) {
   m->train = nullptr;
 }
 
+// Reduced QoI terms of the tracking functional for a target with interior
+// mass vector mt (node layout) and ut^T M ut = ctt (Sec. 3.3):
+//   c = Phi^T (M ubar - (M ut)_I),  c0 = ubar^T M ubar - 2 ubar . (M ut)_I + ctt - |c|^2,
+// so that |u - ut|_M^2 = |phi + c|^2 + c0 for u = ubar + Phi phi (Phi M-orthonormal).
+static int qoi_terms(const mrdino_data* D, const std::vector<double>& mt, double ctt, std::vector<double>& c_out,
+                     double& c0_out) {
+  const int64_t du = (int64_t)(D->n - 1) * (D->n - 1);
+  const int r_u = D->r_u;
+  hipStream_t st = D->st;
+  saa_rt::DevBuf Mub, vdev, cdev;
+  int rc;
+  if ((rc = Mub.alloc(sizeof(double) * du)) || (rc = vdev.alloc(sizeof(double) * du)) ||
+      (rc = cdev.alloc(sizeof(double) * r_u)))
+    return rc;
+  saa_launch::mass_rows((double*)D->ubar.p, du, nullptr, (double*)Mub.p, du, D->n, 1, st);
+  std::vector<double> ub(du), mub(du);
+  if ((rc = check_hip(hipMemcpyAsync(ub.data(), D->ubar.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
+      (rc = check_hip(hipMemcpyAsync(mub.data(), Mub.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
+      (rc = check_hip(hipStreamSynchronize(st))))
+    return rc;
+  // (M u_t) at the interior nodes, interior order
+  const int nn = D->n;
+  std::vector<double> v(du);
+  double quad = 0.0, cross = 0.0;
+  for (int64_t p = 0; p < du; ++p) {
+    const int64_t i = p % (nn - 1) + 1, j = p / (nn - 1) + 1;
+    const double m = mt[(size_t)(j * (nn + 1) + i)];
+    v[p] = mub[p] - m;
+    quad += ub[p] * mub[p];
+    cross += ub[p] * m;
+  }
+  if ((rc = check_hip(hipMemcpyAsync(vdev.p, v.data(), sizeof(double) * du, hipMemcpyHostToDevice, st)))) return rc;
+  saa_launch::gemm<double>(false, false, r_u, 1, (int)du, 1.0, (double*)D->PhiT.p, (int)du, 0, (double*)vdev.p, 1, 0,
+                           0.0, (double*)cdev.p, 1, 0, 1, st);
+  c_out.assign(r_u, 0.0);
+  if ((rc = check_hip(hipMemcpyAsync(c_out.data(), cdev.p, sizeof(double) * r_u, hipMemcpyDeviceToHost, st))) ||
+      (rc = check_hip(hipStreamSynchronize(st))))
+    return rc;
+  double cc = 0.0;
+  for (double x : c_out) cc += x * x;
+  c0_out = quad - 2.0 * cross + ctt - cc;
+  return check_hip(hipGetLastError());
+}
+
 extern "C" {
 
 int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_pod, const saa_options* opt,
@@ -273,7 +317,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     delete D;
     return rc;
   };
-  DevBuf U, dUdz, Dm, MD, G, Vs, MPhiT, Yd, JYd, Mub, vdev, cdev;
+  DevBuf U, dUdz, Dm, MD, G, Vs, MPhiT, Yd, JYd;
   int rc = U.alloc(sizeof(double) * N * du);
   if (!rc) rc = dUdz.alloc(sizeof(double) * N * dz * du);
   if (rc) return fail(rc);
@@ -342,37 +386,8 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   saa_launch::d2f((double*)JYd.p, (float*)D->JY.p, N * dz * r_u, st);
   saa_launch::train_inputs((const double*)c->xi.p, c->K1 * c->K1, (const int*)c->order.p, r_m, Z_dev, dz, N,
                            (float*)D->X.p, st);
-  // 4. reduced QoI terms c = Phi^T (M ubar - (M u_t)_I), c0 (Sec. 3.3)
-  if ((rc = Mub.alloc(sizeof(double) * du)) || (rc = vdev.alloc(sizeof(double) * du)) ||
-      (rc = cdev.alloc(sizeof(double) * r_u)))
-    return fail(rc);
-  saa_launch::mass_rows((double*)D->ubar.p, du, nullptr, (double*)Mub.p, du, D->n, 1, st);
-  std::vector<double> ub(du), mub(du);
-  if ((rc = check_hip(hipMemcpyAsync(ub.data(), D->ubar.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
-      (rc = check_hip(hipMemcpyAsync(mub.data(), Mub.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
-      (rc = check_hip(hipStreamSynchronize(st))))
-    return fail(rc);
-  // (M u_t) at the interior nodes, interior order
-  const int nn = D->n;
-  std::vector<double> v(du);
-  double quad = 0.0, cross = 0.0;
-  for (int64_t p = 0; p < du; ++p) {
-    const int64_t i = p % (nn - 1) + 1, j = p / (nn - 1) + 1;
-    const double mt = c->mt_host[(size_t)(j * (nn + 1) + i)];
-    v[p] = mub[p] - mt;
-    quad += ub[p] * mub[p];
-    cross += ub[p] * mt;
-  }
-  if ((rc = check_hip(hipMemcpyAsync(vdev.p, v.data(), sizeof(double) * du, hipMemcpyHostToDevice, st)))) return fail(rc);
-  saa_launch::gemm<double>(false, false, r_u, 1, (int)du, 1.0, (double*)D->PhiT.p, (int)du, 0, (double*)vdev.p, 1, 0,
-                           0.0, (double*)cdev.p, 1, 0, 1, st);
-  D->c.assign(r_u, 0.0);
-  if ((rc = check_hip(hipMemcpyAsync(D->c.data(), cdev.p, sizeof(double) * r_u, hipMemcpyDeviceToHost, st))) ||
-      (rc = check_hip(hipStreamSynchronize(st))))
-    return fail(rc);
-  double cc = 0.0;
-  for (double x : D->c) cc += x * x;
-  D->c0 = quad - 2.0 * cross + c->ctt - cc;
+  // 4. reduced QoI terms c, c0 for the context's target (Sec. 3.3)
+  if ((rc = qoi_terms(D, c->mt_host, c->ctt, D->c, D->c0))) return fail(rc);
   if ((rc = check_hip(hipGetLastError()))) return fail(rc);
   *out = D;
   return SAA_OK;
@@ -382,6 +397,19 @@ void mrdino_data_free(mrdino_data* D) {
   if (!D) return;
   (void)hipStreamSynchronize(D->st);
   delete D;
+}
+
+int mrdino_data_qoi(const mrdino_data* D, int target, double u_target, double* c, double* c0) {
+  if (!D || !c || !c0 || !std::isfinite(u_target)) return SAA_E_INVALID;
+  if (target != SAA_TARGET_CONST && target != SAA_TARGET_SIN && target != SAA_TARGET_QUAD) return SAA_E_INVALID;
+  std::vector<double> mt, cv;
+  double ctt = 0.0, c0v = 0.0;
+  saa_rt::target_mass(D->n, target, u_target, mt, ctt);
+  const int rc = qoi_terms(D, mt, ctt, cv, c0v);
+  if (rc) return rc;
+  for (int k = 0; k < D->r_u; ++k) c[k] = cv[k];
+  *c0 = c0v;
+  return SAA_OK;
 }
 
 int mrdino_data_info(const mrdino_data* D, int64_t* N, double* c, double* c0, double* lam) {

@@ -13,7 +13,8 @@ problem, paper Sec. 4.2, eq. (elliptic_pde)):
   k = y-frequency fast) or (N, K1, K1, K1) in 3D;
 * z   ~ U[0, 1]^{d_Z} (one control shared by all samples of an SAA call);
 * Z   ~ U[0, 1]^{N x d_Z} (per-sample controls for training data, the
-  auxiliary control law nu_z of Sec. 3.1);
+  auxiliary control law nu_z of Sec. 3.1), or uniform over a box [lo, hi]
+  (Sec. 4.2 trains over the admissible box [-4, 4]^{d_Z});
 * network weights: Glorot-uniform matrices, zero biases.
 """
 from __future__ import annotations
@@ -40,16 +41,16 @@ def kl_coefficients(seed: int, n_samples: int, kl_per_dim: int, dim: int = 2) ->
     return np.ascontiguousarray(rng.standard_normal(shape))
 
 
-def control(seed: int, d_z: int = 25) -> np.ndarray:
-    """z ~ U[0, 1]^{d_z}, float64."""
+def control(seed: int, d_z: int = 25, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """z ~ U[lo, hi]^{d_z}, float64."""
     rng = np.random.default_rng(seed)
-    return rng.uniform(0.0, 1.0, d_z)
+    return rng.uniform(lo, hi, d_z)
 
 
-def controls(seed: int, n_samples: int, d_z: int = 25) -> np.ndarray:
-    """Per-sample controls Z[i, :] ~ U[0, 1]^{d_z}, float64, (n_samples, d_z)."""
+def controls(seed: int, n_samples: int, d_z: int = 25, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Per-sample controls Z[i, :] ~ U[lo, hi]^{d_z}, float64, (n_samples, d_z)."""
     rng = np.random.default_rng(seed)
-    return np.ascontiguousarray(rng.uniform(0.0, 1.0, (n_samples, d_z)))
+    return np.ascontiguousarray(rng.uniform(lo, hi, (n_samples, d_z)))
 
 
 def glorot_mlp(seed: int, widths: list[int]) -> list[tuple[np.ndarray, np.ndarray]]:

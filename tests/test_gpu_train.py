@@ -58,6 +58,19 @@ def test_training_data_matches_oracle(small):
     np.testing.assert_allclose(J, ref["JY"], rtol=0, atol=2e-6 * np.abs(ref["JY"]).max())
     np.testing.assert_allclose(c, ref["c"], rtol=1e-8, atol=1e-12)
     assert abs(c0 - ref["c0"]) <= 1e-9 * abs(ref["c0"]) + 1e-13
+    # the same basis serves other targets (Sec. 4.2): c, c0 of the sinusoidal one
+    cq, c0q = data.qoi(saa.TARGET_QUAD)                    # the context's own target
+    assert np.array_equal(cq, c) and c0q == c0
+    ops_s = fem2d.operators(fem2d.Problem2D(n=prob.n, kl_per_dim=prob.kl_per_dim, kl_amp=prob.kl_amp,
+                                            target=fem2d.TARGET_SIN))
+    Phi = ref["Phi"]
+    c_s = Phi.T @ (ops_s.M_full @ (fem2d.extend(ops_s, ref["ubar"]) - ops_s.t_full))[ops_s.interior]
+    c0_s = fem2d.qoi(ops_s, ref["ubar"]) - c_s @ c_s
+    cg, c0g = data.qoi(saa.TARGET_SIN)
+    np.testing.assert_allclose(cg, c_s, rtol=1e-8, atol=1e-12)
+    assert abs(c0g - c0_s) <= 1e-9 * abs(c0_s) + 1e-13
+    with pytest.raises(saa.SaaError):
+        data.qoi(5)
     X = data.get("X")
     from oracle import surrogate
     np.testing.assert_allclose(X[:, :R_M], surrogate.encode(ref["xi"], R_M).astype(np.float32), rtol=0, atol=0)
