@@ -49,7 +49,7 @@ constexpr int RBS = 256;          // threads of the multi-workgroup passes
 constexpr int SBS = 1024;         // threads of the single-workgroup kernels
 constexpr int NP = 64;            // probes per bracketing pass (one per lane)
 constexpr int NB = NP + 1;        // histogram bins: number of probes below q
-constexpr int PASSES = 4;         // bracketing passes (shrink ~32x each)
+constexpr int PASSES = 3;         // bracketing passes (shrink ~32x each)
 constexpr int CAP = 8192;         // active-set capacity (doubles in LDS)
 constexpr int SEG = 2048;         // active-set capacity per workgroup
 constexpr int GMAX = 256;         // workgroups of the multi-workgroup passes
@@ -425,9 +425,25 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
     if (threadIdx.x == 0) tstar[0] = t_in;
     return;
   }
+  const int total = w.act_total[0];
   const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N);
   if (!(target < (double)N)) {   // beta = 0: every t <= min q - eps is a minimiser
     if (threadIdx.x == 0) tstar[0] = br.lo;
+    return;
+  }
+  if (total > CAP) {
+    // overflow (a segment overflow also pushes act_total above CAP): the
+    // refinement passes narrowed the bracket to (hi - lo) ~ 4 eps / 63^4; a
+    // secant step between its ends (where Phi is known) finishes t*
+    if (threadIdx.x >= SAA_WAVE) return;
+    double plo, phi;
+    const Bracket rb = bracket_refined(w, G, RPASSES, eps, target, (double)N, plo, phi);
+    double t = 0.5 * (rb.lo + rb.hi);
+    if (plo >= 0.0 && phi >= 0.0 && plo > phi) {
+      const double tn = rb.lo + (plo - target) / (plo - phi) * (rb.hi - rb.lo);
+      if (tn >= rb.lo && tn <= rb.hi) t = tn;
+    }
+    if (threadIdx.x == 0) tstar[0] = t;
     return;
   }
   // concatenate the per-workgroup active sets in workgroup order
@@ -440,12 +456,11 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
   if (threadIdx.x < G && cb > SEG) fits = false;
   int ex2;
   const double above = (double)block_scan(ab, &ex2, sh);
-  // the same test as the refinement passes (a segment overflow also pushes
-  // act_total above CAP)
-  fits = __syncthreads_and(fits) && n <= CAP && w.act_total[0] <= CAP;
+  // act_total <= CAP here, so no segment overflowed and n <= CAP
+  fits = __syncthreads_and(fits) && n <= CAP;
   if (threadIdx.x == 0) off[G] = n;
   __syncthreads();
-  double t;
+  double t = 0.5 * (br.lo + br.hi);   // (fits always holds here)
   if (fits) {
     for (int r = threadIdx.x; r < n; r += SBS) {
       int a = 0, b = G;   // last workgroup with off <= r
@@ -479,16 +494,6 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
         v[0] = above + a[0];
         v[1] = a[1];
       });
-    }
-  } else {
-    // the refinement passes narrowed the bracket to (hi - lo) ~ 4 eps / 63^4;
-    // a secant step between its ends (where Phi is known) finishes t*
-    double plo, phi;
-    const Bracket rb = bracket_refined(w, G, RPASSES, eps, target, (double)N, plo, phi);
-    t = 0.5 * (rb.lo + rb.hi);
-    if (plo >= 0.0 && phi >= 0.0 && plo > phi) {
-      const double tn = rb.lo + (plo - target) / (plo - phi) * (rb.hi - rb.lo);
-      if (tn >= rb.lo && tn <= rb.hi) t = tn;
     }
   }
   if (threadIdx.x == 0) tstar[0] = t;
