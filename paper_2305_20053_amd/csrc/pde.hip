@@ -30,10 +30,14 @@
 #ifndef SAA_PDE_BLOCK
 #define SAA_PDE_BLOCK 1024
 #endif
+#ifndef SAA_PDE_LDS_FIRST
+#define SAA_PDE_LDS_FIRST 1
+#endif
 
 namespace {
 
-constexpr int BS = SAA_PDE_BLOCK;
+constexpr int BS = SAA_PDE_BLOCK;      // threads per sample
+constexpr int LF = SAA_PDE_LDS_FIRST;  // first multigrid level kept in LDS (FP32 solver)
 
 // ---------------------------------------------------------------------------
 // Node iteration: the calling thread visits nodes p = tid, tid + BS, ... of an
@@ -130,7 +134,7 @@ struct Level {
 // Array `gbase` (level-stacked, HBM) at level l, or its LDS copy for l >= 1.
 template <typename TS>
 __device__ __forceinline__ TS* at_level(TS* gbase, TS* lbase, const PdeGeo& g, int l) {
-  return (l > 0 && lbase) ? lbase + (g.off[l] - g.off[1]) : gbase + g.off[l];
+  return (l >= LF && lbase) ? lbase + (g.off[l] - g.off[LF]) : gbase + g.off[l];
 }
 
 template <typename TS>
@@ -267,11 +271,11 @@ __device__ void build_diagonals(const PdeGeo& g, const MgBufs<TS>& m, const TW* 
   }
 }
 
-// Move the coarse levels (1..L-1) of one sample into LDS: zero WE, WN, D, X,
+// Move the coarse levels (LF..L-1) of one sample into LDS: zero WE, WN, D, X,
 // B, T there (boundary entries stay zero) and copy the edge weights.
 template <typename TS>
 __device__ void setup_lds_levels(const PdeGeo& g, MgBufs<TS>& m, TS* lds) {
-  const int64_t cs = g.lstride - g.off[1];
+  const int64_t cs = g.lstride - g.off[LF];
   m.lWE = lds;
   m.lWN = lds + cs;
   m.lD = lds + 2 * cs;
@@ -281,8 +285,8 @@ __device__ void setup_lds_levels(const PdeGeo& g, MgBufs<TS>& m, TS* lds) {
   for (int64_t i = threadIdx.x; i < 6 * cs; i += BS) lds[i] = (TS)0;
   __syncthreads();
   for (int64_t i = threadIdx.x; i < cs; i += BS) {
-    m.lWE[i] = m.WE[g.off[1] + i];
-    m.lWN[i] = m.WN[g.off[1] + i];
+    m.lWE[i] = m.WE[g.off[LF] + i];
+    m.lWN[i] = m.WN[g.off[LF] + i];
   }
   __syncthreads();
 }
@@ -803,8 +807,8 @@ namespace saa_launch {
 // buffers in the 160 KB of a workgroup.
 template <typename TS>
 static size_t coarse_lds_bytes(const PdeGeo& g) {
-  if (sizeof(TS) != 4 || g.L < 2) return 0;
-  const size_t b = 6 * (size_t)(g.lstride - g.off[1]) * sizeof(TS);
+  if (sizeof(TS) != 4 || g.L <= LF) return 0;
+  const size_t b = 6 * (size_t)(g.lstride - g.off[LF]) * sizeof(TS);
   const size_t static_lds = (size_t)SAA_MAX_DZ * (BS / SAA_WAVE) * sizeof(double) + SAA_MAX_DZ * sizeof(double);
   return (b + static_lds <= 150 * 1024) ? b : 0;
 }
