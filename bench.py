@@ -211,7 +211,37 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True):
     hold.close()
     if qoi is not None and ouu:
         out["ouu"] = bench_ouu(saa, si, model, qoi, ctx)
+        out["jacobian_modes"] = bench_jacobian_modes(saa, si)
     model.close()
+    ctx.close()
+    return out
+
+
+def bench_jacobian_modes(saa, si):
+    """Reduced control Jacobians of 256 training samples (n = 128) with
+    r_u = 16 < d_Z = 25 and r_u = 64 > d_Z: d_Z forward solves per sample
+    against r_u adjoint solves (Sec. 3.4); wall time of the whole data build
+    (states, POD of the 256 states, Jacobians, projections) and the agreement
+    of the two reduced Jacobians."""
+    import numpy as np
+    import torch
+    prob = saa.problem_medium()
+    ctx = saa.Context(prob, 256)
+    ctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_TRAIN, 256, prob.kl_per_dim)).cuda())
+    Zt = torch.from_numpy(si.controls(si.SEED_Z_TRAIN, 256, lo=Z_LO, hi=Z_HI)).cuda()
+    out = {"samples": 256, "d_z": 25}
+    for r_u in (16, 64):
+        res, Js = {}, {}
+        for name, mode in (("forward", saa.JAC_FORWARD), ("adjoint", saa.JAC_ADJOINT)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d = saa.TrainData(ctx, Zt, r_m=100, r_u=r_u, n_pod=256, opt=saa.options(jac_mode=mode))
+            torch.cuda.synchronize()
+            res[name + "_s"] = time.perf_counter() - t0
+            Js[name] = d.get("J")
+            d.close()
+        res["rel_diff"] = float(np.abs(Js["adjoint"] - Js["forward"]).max() / np.abs(Js["forward"]).max())
+        out[f"r_u_{r_u}"] = res
     ctx.close()
     return out
 

@@ -148,12 +148,18 @@ typedef struct saa_options {
                           The non-CVaR measures need t_mode = 0; beta is
                           ignored; the report's t_star is the mean of q
                           (MEAN_VAR), risk_tau (POF) or 0 (MEAN), dJ_dt 0. */
-  int pad_;
+  int jac_mode;        /* control Jacobians of mrdino_data_create (Sec. 3.4):
+                          SAA_JAC_AUTO (adjoint when d_Z >= r_u, else
+                          forward), SAA_JAC_FORWARD (d_Z linearised solves per
+                          sample), SAA_JAC_ADJOINT (r_u solves with right-hand
+                          sides M phi_k per sample, giving the reduced
+                          Jacobian Phi^T M du/dz directly) */
   double risk_kappa;   /* MEAN_VAR weight, >= 0 */
   double risk_tau;     /* POF threshold, finite */
 } saa_options;
 
 enum { SAA_RISK_CVAR = 0, SAA_RISK_MEAN = 1, SAA_RISK_MEAN_VAR = 2, SAA_RISK_POF = 3 };
+enum { SAA_JAC_AUTO = 0, SAA_JAC_FORWARD = 1, SAA_JAC_ADJOINT = 2 };
 
 typedef struct saa_report {
   double t_star;       /* the t used (minimiser, or t_in) */
@@ -333,19 +339,23 @@ typedef struct mrdino_data mrdino_data;
 
 /* Training data for the samples installed in ctx at per-sample controls
  * Z_dev (device, N x d_Z float64; the auxiliary control law of Sec. 3.1):
- *  1. states u_i and control Jacobians du_i/dz by the PDE form (opt->prec,
- *     tolerances) with d_Z linearised solves per sample (Sec. 3.4);
+ *  1. states u_i by the PDE form (opt->prec, tolerances) and, in forward
+ *     mode (opt->jac_mode), control Jacobians du_i/dz by d_Z linearised
+ *     solves per sample (Sec. 3.4);
  *  2. weighted POD (Sec. 3.3) from the first n_pod states: mean b, Gram
  *     G = D^T M D of the centred snapshots, G V = V Lambda (host
  *     eigensolver), Phi = D V_r Lambda_r^{-1/2} (M-orthonormal; each column of
  *     V signed so its largest-magnitude entry is positive);
  *  3. reduced data y_i = Phi^T M (u_i - b) and J_i = Phi^T M du_i/dz
- *     (eq. (reduced_basis_derivative_equivalence)); inputs x_i = [m_r; z_i];
+ *     (eq. (reduced_basis_derivative_equivalence)), in adjoint mode by r_u
+ *     solves A(u_i) lambda_k = M phi_k and J_i[k, :] = F^T lambda_k;
+ *     inputs x_i = [m_r; z_i];
  *  4. reduced-QoI terms c, c0 (see mrdino_set_qoi).
  * 2 <= N, 1 <= r_u <= n_pod <= min(N, 8192), 1 <= r_m <= K1^2.  With a
  * non-NULL `basis` (held-out data) steps 2 and 4 are skipped: its mean, POD
  * basis and QoI terms are reused (n_pod is ignored; r_u and the problem must
- * match).  Device memory during construction: about 8 (d_Z + 2) N d_U bytes.
+ * match).  Device memory during construction: about 8 (d_Z + 2) N d_U bytes
+ * in forward mode, 16 N d_U + 8 r_u d_U in adjoint mode.
  * Returns SAA_E_INVALID also when the Gram matrix has rank below r_u. */
 int mrdino_data_create(saa_ctx* ctx, const double* Z_dev, int r_m, int r_u, int n_pod, const saa_options* opt,
                        const mrdino_data* basis, mrdino_data** out, saa_report* report);

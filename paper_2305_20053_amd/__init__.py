@@ -21,6 +21,7 @@ FP64, FP32, FP32_DC64, BF16, FP8 = 0, 1, 2, 3, 4
 WANT_Q, WANT_DQDZ, WANT_PHI, WANT_DPHIDZ = 1, 2, 4, 8
 TARGET_CONST, TARGET_SIN, TARGET_QUAD = 0, 1, 2
 RISK_CVAR, RISK_MEAN, RISK_MEAN_VAR, RISK_POF = 0, 1, 2, 3
+JAC_AUTO, JAC_FORWARD, JAC_ADJOINT = 0, 1, 2
 OUU_PGTOL, OUU_FTOL, OUU_MAXITER, OUU_MAXEVAL, OUU_LINESEARCH = 0, 1, 2, 3, 4
 
 
@@ -56,7 +57,7 @@ class COptions(ctypes.Structure):
                 ("newton_tol", ctypes.c_double), ("lin_rtol", ctypes.c_double),
                 ("max_newton", ctypes.c_int), ("max_lin", ctypes.c_int), ("max_dc", ctypes.c_int),
                 ("all_adjoints", ctypes.c_int), ("fallback_tol", ctypes.c_double), ("timing", ctypes.c_int),
-                ("risk", ctypes.c_int), ("pad_", ctypes.c_int), ("risk_kappa", ctypes.c_double),
+                ("risk", ctypes.c_int), ("jac_mode", ctypes.c_int), ("risk_kappa", ctypes.c_double),
                 ("risk_tau", ctypes.c_double)]
 
 

@@ -41,6 +41,10 @@ void linearized(const PdeGeo& g, const double* FT, const double* em, const TW* u
                 hipStream_t st);
 template <typename TW>
 void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st);
+template <typename TW, typename TS>
+void adjoint_jac(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* x,
+                 const MgBufs<TS>& b, const SolveParams& sp, const double* MPhiT, int r_u, double* JY, int* lin,
+                 int* flag, int64_t N, hipStream_t st);
 void cvar(const double* q, const double* g, int64_t N, int dz, double beta, double eps, double alpha,
           const double* z, int t_mode, double t_in, int phase, double* tstar, double* out, const int* newton,
           const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
@@ -180,6 +184,7 @@ int validate_options(const saa_options* o) {
   if (o->risk < SAA_RISK_CVAR || o->risk > SAA_RISK_POF) return SAA_E_INVALID;
   if (o->risk != SAA_RISK_CVAR && o->t_mode != 0) return SAA_E_INVALID;
   if (!is_fin(o->risk_kappa) || o->risk_kappa < 0.0 || !is_fin(o->risk_tau)) return SAA_E_INVALID;
+  if (o->jac_mode < SAA_JAC_AUTO || o->jac_mode > SAA_JAC_ADJOINT) return SAA_E_INVALID;
   return SAA_OK;
 }
 
@@ -301,6 +306,36 @@ int validate_call(saa_ctx* c, const double* z, int form, const void* model, cons
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+namespace saa_rt {
+
+// Reduced control Jacobians of the states of the last saa_solve_states call
+// by adjoints (see saa_k_adjoint_jac): JY (device, N d_Z x r_u).
+int adjoint_jacobians(saa_ctx* c, const saa_options* opt, const double* MPhiT, int r_u, double* JY) {
+  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+  switch (opt->prec) {
+    case SAA_FP64:
+      saa_launch::adjoint_jac<double, double>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
+                                              (double*)c->f.p, (double*)c->lam.p, c->mg64.view(), sp, MPhiT, r_u, JY,
+                                              (int*)c->lin_adj.p, (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32_DC64:
+      saa_launch::adjoint_jac<double, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
+                                             (double*)c->f.p, (double*)c->lam.p, c->mg32.view(), sp, MPhiT, r_u, JY,
+                                             (int*)c->lin_adj.p, (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32:
+      saa_launch::adjoint_jac<float, float>(c->geo, (double*)c->FT.p, (double*)c->em.p, (float*)c->u.p,
+                                            (float*)c->f.p, (float*)c->lam.p, c->mg32.view(), sp, MPhiT, r_u, JY,
+                                            (int*)c->lin_adj.p, (int*)c->flag.p, c->N, c->st);
+      break;
+    default:
+      return SAA_E_INVALID;
+  }
+  return check_hip(hipGetLastError());
+}
+
+}  // namespace saa_rt
+
 extern "C" {
 
 int saa_abi_version(void) { return SAA_ABI_VERSION; }

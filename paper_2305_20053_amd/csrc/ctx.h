@@ -16,6 +16,10 @@ namespace saa_rt {
 // for a target kind of saa_problem on the n x n mesh.
 void target_mass(int n, int target, double u_target, std::vector<double>& mt, double& ctt);
 
+// Reduced control Jacobians by adjoints for the states of the last
+// saa_solve_states call; JY: device, (N d_Z) x r_u.
+int adjoint_jacobians(saa_ctx* c, const saa_options* opt, const double* MPhiT, int r_u, double* JY);
+
 template <typename TS>
 struct MgStore {
   DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;

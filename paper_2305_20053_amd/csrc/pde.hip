@@ -785,6 +785,66 @@ __global__ void __launch_bounds__(BS) saa_k_linearized(PdeGeo g, const double* F
   }
 }
 
+// Reduced control Jacobians by adjoints: J_r = Phi^T M A(u)^{-1} F = (A(u)^{-1}
+// M Phi)^T F since A(u) is symmetric, so r_u solves with right-hand sides
+// M phi_k replace the d_Z linearised ones (Sec. 3.4: the adjoint variant
+// for d_Z >= r_U).  MPhiT: r_u x d_U (interior order); output
+// JY[(s d_Z + kz) r_u + k] = f_kz^T lambda_k.  One block per sample.
+template <typename TW, typename TS, bool LDSC>
+__global__ void __launch_bounds__(BS) saa_k_adjoint_jac(PdeGeo g, const double* FT, const double* em_all,
+                                                        const TW* u_all, TW* b_all, TW* x_all, MgBufs<TS> all,
+                                                        SolveParams sp, const double* MPhiT, int r_u, double* JY,
+                                                        int* lin_out, int* flag_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  const int n = g.n[0];
+  const int64_t du = (int64_t)(n - 1) * (n - 1);
+  const double* em = em_all + s * g.nodes;
+  const TW* u = u_all + s * g.nodes;
+  TW* b = b_all + s * g.nodes;
+  TW* x = x_all + s * g.nodes;
+  MgBufs<TS> m = sample_bufs(all, g, s);
+  if (LDSC) {
+    extern __shared__ char dyn_lds[];
+    setup_lds_levels(g, m, (TS*)dyn_lds);
+  }
+  build_diagonals<TW, TS>(g, m, u);
+  int lin = 0;
+  bool ok_all = true;
+  for (int k = 0; k < r_u; ++k) {
+    const double* rhs = MPhiT + (int64_t)k * du;
+    for_nodes(n, [&](int p, int i, int j) {
+      b[p] = interior(i, j, n) ? (TW)rhs[(int64_t)(j - 1) * (n - 1) + (i - 1)] : (TW)0;
+    });
+    __syncthreads();
+    bool ok = true;
+    int passes = 0;
+    lin += dc_solve<TW, TS>(g, m, sp, em, u, b, x, red, &ok, &passes);
+    ok_all = ok_all && ok;
+    for (int k0 = 0; k0 < g.dz; k0 += 8) {   // f_kz^T lambda, eight controls per pass
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = 0.0;
+      for_nodes(n, [&](int p, int i, int j) {
+        if (interior(i, j, n)) {
+          const double l = (double)x[p];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (k0 + t < g.dz) v[t] += FT[(int64_t)(k0 + t) * g.nodes + p] * l;
+        }
+      });
+      block_sum<8>(v, red);
+      if (threadIdx.x == 0)
+        for (int t = 0; t < 8 && k0 + t < g.dz; ++t) JY[(s * g.dz + k0 + t) * r_u + k] = v[t];
+    }
+  }
+  if (threadIdx.x == 0) {
+    lin_out[s] = lin;
+    if (!ok_all) flag_out[s] |= SAA_FLAG_DC;
+  }
+}
+
 // Copy interior node values to the dense interior-order layout (float64).
 template <typename TW>
 __global__ void saa_k_interior(const TW* u_all, double* out, int n, int64_t N) {
@@ -890,6 +950,22 @@ void linearized(const PdeGeo& g, const double* FT, const double* em, const TW* u
   }
 }
 
+template <typename TW, typename TS>
+void adjoint_jac(const PdeGeo& g, const double* FT, const double* em, const TW* u, TW* bvec, TW* x,
+                 const MgBufs<TS>& b, const SolveParams& sp, const double* MPhiT, int r_u, double* JY, int* lin,
+                 int* flag, int64_t N, hipStream_t st) {
+  const size_t lds = coarse_lds_bytes<TS>(g);
+  if (lds) {
+    static bool attr = set_lds_attr((const void*)saa_k_adjoint_jac<TW, TS, true>, lds);
+    (void)attr;
+    saa_k_adjoint_jac<TW, TS, true><<<(unsigned)N, BS, lds, st>>>(g, FT, em, u, bvec, x, b, sp, MPhiT, r_u, JY, lin,
+                                                                   flag, N);
+  } else {
+    saa_k_adjoint_jac<TW, TS, false><<<(unsigned)N, BS, 0, st>>>(g, FT, em, u, bvec, x, b, sp, MPhiT, r_u, JY, lin,
+                                                                    flag, N);
+  }
+}
+
 template <typename TW>
 void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st) {
   const int64_t total = N * (int64_t)(n - 1) * (n - 1);
@@ -905,7 +981,10 @@ void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st) {
                                 double, double*, int*, int*, int*, int64_t, hipStream_t);                                \
   template void linearized<TW, TS>(const PdeGeo&, const double*, const double*, const TW*, TW*, TW*,             \
                                    const MgBufs<TS>&, const SolveParams&, double*, int*, int*, int64_t,          \
-                                   hipStream_t);
+                                   hipStream_t);                                                                 \
+  template void adjoint_jac<TW, TS>(const PdeGeo&, const double*, const double*, const TW*, TW*, TW*,            \
+                                    const MgBufs<TS>&, const SolveParams&, const double*, int, double*, int*,    \
+                                    int*, int64_t, hipStream_t);
 SAA_INST(double, double)
 SAA_INST(double, float)
 SAA_INST(float, float)

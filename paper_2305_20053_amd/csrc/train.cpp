@@ -318,11 +318,13 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     return rc;
   };
   DevBuf U, dUdz, Dm, MD, G, Vs, MPhiT, Yd, JYd;
+  // control Jacobians: d_Z forward solves, or r_u adjoint solves (Sec. 3.4)
+  const bool adj = opt->jac_mode == SAA_JAC_ADJOINT || (opt->jac_mode == SAA_JAC_AUTO && dz >= r_u);
   int rc = U.alloc(sizeof(double) * N * du);
-  if (!rc) rc = dUdz.alloc(sizeof(double) * N * dz * du);
+  if (!rc && !adj) rc = dUdz.alloc(sizeof(double) * N * dz * du);
   if (rc) return fail(rc);
-  // 1. states and control Jacobians of the training samples (Sec. 3.4)
-  rc = saa_solve_states(c, Z_dev, opt, (double*)U.p, nullptr, (double*)dUdz.p, rep);
+  // 1. states (and forward-mode control Jacobians) of the training samples
+  rc = saa_solve_states(c, Z_dev, opt, (double*)U.p, nullptr, adj ? nullptr : (double*)dUdz.p, rep);
   if (rc) return fail(rc);
   if (basis) {  // held-out data: reuse the training basis and QoI terms
     if ((rc = D->ubar.alloc(sizeof(double) * du)) || (rc = D->PhiT.alloc(sizeof(double) * r_u * du)) ||
@@ -377,8 +379,12 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   saa_launch::center_rows((double*)U.p, (double*)D->ubar.p, (double*)U.p, du, N, st);
   saa_launch::gemm<double>(false, true, (int)N, r_u, (int)du, 1.0, (double*)U.p, (int)du, 0, (double*)MPhiT.p,
                            (int)du, 0, 0.0, (double*)Yd.p, r_u, 0, 1, st);
-  saa_launch::gemm<double>(false, true, (int)(N * dz), r_u, (int)du, 1.0, (double*)dUdz.p, (int)du, 0,
-                           (double*)MPhiT.p, (int)du, 0, 0.0, (double*)JYd.p, r_u, 0, 1, st);
+  if (adj) {   // J_r = (A^{-1} M Phi)^T F, from the states still held by the context
+    if ((rc = saa_rt::adjoint_jacobians(c, opt, (const double*)MPhiT.p, r_u, (double*)JYd.p))) return fail(rc);
+  } else {
+    saa_launch::gemm<double>(false, true, (int)(N * dz), r_u, (int)du, 1.0, (double*)dUdz.p, (int)du, 0,
+                             (double*)MPhiT.p, (int)du, 0, 0.0, (double*)JYd.p, r_u, 0, 1, st);
+  }
   if ((rc = D->X.alloc(sizeof(float) * N * (r_m + dz))) || (rc = D->Y.alloc(sizeof(float) * N * r_u)) ||
       (rc = D->JY.alloc(sizeof(float) * N * dz * r_u)))
     return fail(rc);

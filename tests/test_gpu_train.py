@@ -77,6 +77,22 @@ def test_training_data_matches_oracle(small):
     np.testing.assert_allclose(X[:, R_M:], ref["Z"].astype(np.float32), rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("mode", [saa.JAC_FORWARD, saa.JAC_ADJOINT])
+def test_jacobian_modes_match_oracle(small, mode):
+    """Reduced control Jacobians Phi^T M du/dz by d_Z forward (linearised)
+    solves or by r_u adjoint solves with right-hand sides M phi_k (Sec. 3.4;
+    here r_u = 8 < d_Z = 25, where the adjoint variant is the cheaper one and
+    the default)."""
+    prob, ctx, data, ref = small
+    print(f"case jacobian mode={mode}", flush=True)
+    d2 = saa.TrainData(ctx, torch.from_numpy(ref["Z"]).cuda(), r_m=R_M, r_u=R_U, n_pod=N_POD,
+                       opt=saa.options(prec=saa.FP32_DC64, jac_mode=mode))
+    J = d2.get("J").reshape(N, ctx.d_z, R_U).transpose(0, 2, 1)
+    np.testing.assert_allclose(J, ref["JY"], rtol=0, atol=2e-6 * np.abs(ref["JY"]).max())
+    np.testing.assert_array_equal(d2.get("Y"), data.get("Y"))     # the states do not depend on the mode
+    d2.close()
+
+
 @pytest.mark.parametrize("dino", [True, False])
 def test_loss_and_gradient_match_oracle(small, dino):
     prob, ctx, data, ref = small
