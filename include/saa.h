@@ -418,6 +418,14 @@ int mrdino_data_errors(mrdino_model* model, mrdino_data* data, double* err_state
  * the eigenvectors as columns.  Needs no GPU. */
 int saa_sym_eig(int n, const double* A, double* w, double* V);
 
+/* The same on the GPU (parallel cyclic Jacobi, one kernel per round of n/2
+ * disjoint rotations), used by mrdino_data_create for the POD.  A_dev:
+ * device, n x n row-major (symmetrised, not modified); w: host, n, decreasing;
+ * V_dev: device, n x n row-major, eigenvectors as columns; hip_stream: the
+ * stream (NULL = default); sweeps (may be NULL) receives the Jacobi sweeps
+ * run.  Synchronises the stream.  SAA_E_NOCONV after 60 sweeps. */
+int saa_sym_eig_gpu(int n, const double* A_dev, double* w, double* V_dev, void* hip_stream, int* sweeps);
+
 /* ------------------------------------------------------------------------
  * Outer OUU solve (Sec. 2.1, eq. (ouu); eq. (CVaR_ouu) for the joint form;
  * Sec. 4.2 minimises over a box Z_ad with a bound-constrained limited-memory

@@ -441,6 +441,7 @@ _SIGS.update({
     "mrdino_train": (ctypes.c_int, [_P, _P, ctypes.POINTER(CTrainCfg), _P, ctypes.POINTER(ctypes.c_double)]),
     "mrdino_data_errors": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "saa_sym_eig": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
+    "saa_sym_eig_gpu": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "saa_attach_holdout": (ctypes.c_int, [_P, _P]),
 })
 
@@ -461,6 +462,22 @@ def sym_eig(A):
     V = np.zeros((n, n))
     _check(_load().saa_sym_eig(n, A.ctypes.data, w.ctypes.data, V.ctypes.data))
     return w, V
+
+
+def sym_eig_gpu(A):
+    """Eigenvalues (decreasing, numpy) and eigenvectors (columns, CUDA
+    tensor) of a symmetric CUDA float64 tensor by the library's GPU Jacobi
+    solver; also returns the number of sweeps."""
+    import numpy as np
+    import torch
+    A = A.contiguous()
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = torch.empty(n, n, dtype=torch.float64, device=A.device)
+    sw = ctypes.c_int()
+    _check(_load().saa_sym_eig_gpu(n, _P(_ptr(A)), w.ctypes.data, _P(_ptr(V)),
+                                   _P(torch.cuda.current_stream().cuda_stream), ctypes.byref(sw)))
+    return w, V, sw.value
 
 
 def train_cfg(batch=256, epochs=1600, lr_drop_epoch=800, lr=1e-3, lr_late=2.5e-4, dino=1, seed=2305,

@@ -16,6 +16,7 @@
 #include "model.h"
 
 extern "C" int saa_sym_eig(int n, const double* A, double* w, double* V);
+extern "C" int saa_sym_eig_gpu(int n, const double* A_dev, double* w, double* V_dev, void* hip_stream, int* sweeps);
 
 namespace saa_launch {
 template <typename T>
@@ -346,12 +347,16 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   saa_launch::mass_rows((double*)Dm.p, du, nullptr, (double*)MD.p, du, D->n, n_pod, st);
   saa_launch::gemm<double>(false, true, n_pod, n_pod, (int)du, 1.0, (double*)Dm.p, (int)du, 0, (double*)MD.p,
                            (int)du, 0, 0.0, (double*)G.p, n_pod, 0, 1, st);
-  std::vector<double> Gh((size_t)n_pod * n_pod), V((size_t)n_pod * n_pod);
+  std::vector<double> V((size_t)n_pod * n_pod);
   D->lam.assign(n_pod, 0.0);
-  if ((rc = check_hip(hipMemcpyAsync(Gh.data(), G.p, sizeof(double) * Gh.size(), hipMemcpyDeviceToHost, st))) ||
-      (rc = check_hip(hipStreamSynchronize(st))))
-    return fail(rc);
-  if ((rc = saa_sym_eig(n_pod, Gh.data(), D->lam.data(), V.data()))) return fail(rc);
+  {  // eigenpairs of the Gram matrix on the GPU (parallel Jacobi)
+    DevBuf Vd;
+    if ((rc = Vd.alloc(sizeof(double) * V.size())) ||
+        (rc = saa_sym_eig_gpu(n_pod, (const double*)G.p, D->lam.data(), (double*)Vd.p, st, nullptr)) ||
+        (rc = check_hip(hipMemcpyAsync(V.data(), Vd.p, sizeof(double) * V.size(), hipMemcpyDeviceToHost, st))) ||
+        (rc = check_hip(hipStreamSynchronize(st))))
+      return fail(rc);
+  }
   if (!(D->lam[r_u - 1] > 1e-14 * D->lam[0])) return fail(SAA_E_INVALID);   // rank below r_u
   std::vector<double> vs((size_t)n_pod * r_u);
   for (int col = 0; col < r_u; ++col) {
