@@ -24,16 +24,21 @@ sys.path.insert(0, ROOT)
 METRIC = "SAA CVaR obj+grad samples/s, MR-DINO vs PDE form, 1 GPU, at stated error"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per unknown of the state-solve kernel (FP32 solver
-# arrays, FP64 state): each pass reads / writes each array it needs once.
-#   PCG iteration: A p (5 x 4 B) + x, r update (6 x 4 B) + V-cycle (fine
-#   level 21 x 4 B, coarse levels a third of that) + r.z (2 x 4 B) +
-#   p update (3 x 4 B)                                          = 176 B
-#   PCG start (r.r, x = 0, first V-cycle, r.z and p = z)        = 132 B
+# Algorithmic bytes per unknown of the state-solve kernel: each fine-level
+# pass reads / writes each array it needs once (FP32 solver arrays, FP64
+# state); the coarse multigrid levels live in LDS in the FP32 solver and are
+# not counted (with the FP64 solver they are in HBM: a third of the fine
+# V-cycle bytes more).
+#   PCG iteration: p = z + beta p fused into A p (z, p, D, WE, WN read;
+#   p, q written: 7 x 4 B) + x, r update with the first red half sweep
+#   (7 x 4 B) + fine V-cycle rest (black sweep 4.5, red residual 4.5,
+#   restriction 0.5, prolongation 2, two half sweeps 9: 20.5 x 4 B) = 138 B
+#   PCG start (r.r, x = 0, first V-cycle, r.z and p = z)        = 116 B
 #   Newton step: residual 28 B + diagonals 25 B + update 20 B   =  73 B
 #   per sample: f = F z and u = 0 (16 B) + QoI (8 B)            =  24 B
-BYTES_PCG_ITER_F32 = 176
-BYTES_PCG_START_F32 = 132
+BYTES_PCG_ITER_F32 = 138
+BYTES_PCG_START_F32 = 116
+BYTES_VCYCLE_FINE_F32 = 82
 BYTES_NEWTON_F64 = 73
 BYTES_SAMPLE = 24
 
@@ -350,8 +355,9 @@ def main():
     # that call's own iteration counts
     d_u = prob.d_u
     s_bytes = 4 if prec in (saa.FP32, saa.FP32_DC64) else 8
-    per_iter = BYTES_PCG_ITER_F32 * s_bytes // 4
-    per_start = BYTES_PCG_START_F32 * s_bytes // 4
+    coarse = 0 if s_bytes == 4 else BYTES_VCYCLE_FINE_F32 / 3   # coarse levels in HBM with the FP64 solver
+    per_iter = (BYTES_PCG_ITER_F32 + coarse) * s_bytes / 4
+    per_start = (BYTES_PCG_START_F32 + coarse) * s_bytes / 4
     topt = saa.options(prec=prec, timing=1)
     reps, rates, launch_bytes = [], [], []
     for k in range(min(args.steps, 5)):

@@ -210,10 +210,12 @@ __device__ void prolong_add(int nf, TS* xf, int nc, const TS* xc) {
 
 // Symmetric V-cycle: X_0 = V(b0).  Pre-smoothing nu x (red, black), post
 // smoothing nu x (black, red), so that the preconditioner is symmetric.
+// vcycle_from(l0) runs the part from level l0 down and back to l0 (its right
+// hand side already restricted to B_l0).
 template <typename TS>
-__device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int nu) {
+__device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int nu, int l0) {
   const int L = g.L;
-  for (int l = 0; l < L - 1; ++l) {
+  for (int l = l0; l < L - 1; ++l) {
     const Level<TS> lv = level(g, m, l);
     const TS* b = (l == 0) ? b0 : at_level(m.B, m.lB, g, l);
     TS* x = at_level(m.X, m.lX, g, l);
@@ -233,7 +235,7 @@ __device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int n
     }
     __syncthreads();
   }
-  for (int l = L - 2; l >= 0; --l) {
+  for (int l = L - 2; l >= l0; --l) {
     const Level<TS> lv = level(g, m, l);
     const TS* b = (l == 0) ? b0 : at_level(m.B, m.lB, g, l);
     TS* x = at_level(m.X, m.lX, g, l);
@@ -243,6 +245,56 @@ __device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int n
       gs_half(lv, b, x, 0, false);
     }
   }
+}
+
+template <typename TS>
+__device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int nu) {
+  vcycle_from(g, m, b0, nu, 0);
+}
+
+// Fine-level pieces of a V(1,1) cycle fused with the CG vector passes:
+//  * the first red half sweep x_red = b_red / D (black taken as zero) is
+//    done where the CG residual is updated (pcg);
+//  * after the black half sweep the black residuals vanish (every neighbour
+//    of a black node is red), so only the red residuals are formed and the
+//    restriction reads those: b_c(I,J) = t(2I,2J) + (t(2I+1,2J+1) +
+//    t(2I-1,2J-1)) / 2;
+//  * the post-smoothing half sweeps also accumulate r . z (z final per colour).
+template <typename TS>
+__device__ void residual_red(const Level<TS>& L, const TS* b, const TS* x, TS* t) {
+  for_nodes(L.n, [&](int p, int i, int j) {
+    if (interior(i, j, L.n) && !((i + j) & 1)) t[p] = b[p] - (L.D[p] * x[p] - offdiag_sum(L, x, p));
+  });
+  __syncthreads();
+}
+
+template <typename TS>
+__device__ void restrict_red(int nf, const TS* t, int nc, TS* bc) {
+  const int npf = nf + 1;
+  for_nodes(nc, [&](int pc, int I, int J) {
+    if (interior(I, J, nc)) {
+      const int p = (2 * J) * npf + 2 * I;
+      bc[pc] = t[p] + (TS)0.5 * (t[p + npf + 1] + t[p - npf - 1]);
+    }
+  });
+  __syncthreads();
+}
+
+// Half sweep of colour c that also returns this thread's part of sum b_p x_p
+// over the nodes of that colour (after their update).
+template <typename TS>
+__device__ double gs_half_dot(const Level<TS>& L, const TS* b, TS* x, int c) {
+  double acc = 0.0;
+  for_nodes(L.n, [&](int p, int i, int j) {
+    if (interior(i, j, L.n) && ((i + j) & 1) == c) {
+      const TS bp = b[p];
+      const TS v = (bp + offdiag_sum(L, x, p)) / L.D[p];
+      x[p] = v;
+      acc += (double)bp * (double)v;
+    }
+  });
+  __syncthreads();
+  return acc;
 }
 
 // Lumped reaction 3 r h^2 u^2 on the fine level and its restrictions; sets
@@ -322,15 +374,40 @@ __device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it
   });
   rz = block_sum1(rz, red);
   const double tol2 = rtol * rtol * rr0;
+  const bool fused = nu == 1 && g.L > 1;
+  // search directions alternate between cp and the (otherwise unused) level-0
+  // part of B: from the second iteration on, p = z + beta p_old is formed
+  // inside the product A p (neighbour values recomputed, so no extra pass)
+  TS* pc = m.cp;
+  TS* pn = m.B;
+  TS beta = (TS)0;
   for (int it = 1; it <= max_it; ++it) {
     double pq = 0.0;
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        const TS q = L0.D[p] * m.cp[p] - offdiag_sum(L0, m.cp, p);
-        m.cq[p] = q;
-        pq += (double)m.cp[p] * (double)q;
-      }
-    });
+    if (it == 1) {
+      for_nodes(n, [&](int p, int i, int j) {
+        if (interior(i, j, n)) {
+          const TS q = L0.D[p] * pc[p] - offdiag_sum(L0, pc, p);
+          m.cq[p] = q;
+          pq += (double)pc[p] * (double)q;
+        }
+      });
+    } else {
+      const TS* po = pc;
+      for_nodes(n, [&](int p, int i, int j) {
+        if (interior(i, j, n)) {
+          auto pv = [&](int k) { return z[k] + beta * po[k]; };   // zero on the boundary
+          const TS pp = pv(p);
+          const TS q = L0.D[p] * pp - (L0.WE[p] * pv(p + 1) + L0.WE[p - 1] * pv(p - 1) + L0.WN[p] * pv(p + L0.np) +
+                                       L0.WN[p - L0.np] * pv(p - L0.np));
+          pn[p] = pp;
+          m.cq[p] = q;
+          pq += (double)pp * (double)q;
+        }
+      });
+      TS* t = pc;
+      pc = pn;
+      pn = t;
+    }
     pq = block_sum1(pq, red);
     if (!(pq > 0.0)) {
       *ok = false;
@@ -341,26 +418,33 @@ __device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it
     double rr = 0.0;
     for_nodes(n, [&](int p, int i, int j) {
       if (interior(i, j, n)) {
-        m.cx[p] += a * m.cp[p];
+        m.cx[p] += a * pc[p];
         const TS r = m.cr[p] - a * m.cq[p];
         m.cr[p] = r;
         rr += (double)r * (double)r;
+        if (fused && !((i + j) & 1)) z[p] = r / L0.D[p];   // first red half sweep of the V-cycle
       }
     });
     rr = block_sum1(rr, red);
     if (rr <= tol2) return it;
-    vcycle(g, m, m.cr, nu);
     double rzn = 0.0;
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) rzn += (double)m.cr[p] * (double)z[p];
-    });
+    if (fused) {
+      gs_half(L0, (const TS*)m.cr, z, 1, false);
+      residual_red(L0, (const TS*)m.cr, (const TS*)z, m.T);
+      restrict_red(n, (const TS*)m.T, g.n[1], at_level(m.B, m.lB, g, 1));
+      vcycle_from(g, m, m.cr, nu, 1);
+      prolong_add(n, z, g.n[1], at_level(m.X, m.lX, g, 1));
+      rzn = gs_half_dot(L0, (const TS*)m.cr, z, 1);
+      rzn += gs_half_dot(L0, (const TS*)m.cr, z, 0);
+    } else {
+      vcycle(g, m, m.cr, nu);
+      for_nodes(n, [&](int p, int i, int j) {
+        if (interior(i, j, n)) rzn += (double)m.cr[p] * (double)z[p];
+      });
+    }
     rzn = block_sum1(rzn, red);
-    const TS beta = (TS)(rzn / rz);
+    beta = (TS)(rzn / rz);
     rz = rzn;
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) m.cp[p] = z[p] + beta * m.cp[p];
-    });
-    __syncthreads();
   }
   *ok = false;
   return max_it;
