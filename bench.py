@@ -383,6 +383,20 @@ def main():
            "grad_rel_vs_gpu_fp64": float(np.linalg.norm(gp - g64) / np.linalg.norm(g64)),
            "oracle_parity": "tests/test_gpu_pde.py (<= 1e-9 FP64 / FP32-DC64, <= 1e-4 FP32)"}
 
+    # measured HBM ceiling: a 2 GiB device-to-device copy (read + write), best of 5
+    cp_a = torch.empty(1 << 29, dtype=torch.float32, device="cuda").fill_(1.0)
+    cp_b = torch.empty_like(cp_a)
+    cp_rates = []
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cp_b.copy_(cp_a)
+        e1.record()
+        e1.synchronize()
+        cp_rates.append(2 * cp_a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    copy_gbs = max(cp_rates[1:])
+    del cp_a, cp_b
+
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -401,6 +415,7 @@ def main():
                                f"smoothed CVaR_0.95, precision {args.prec}",
                    "n": prob.n, "N": N, "form": "pde", "prec": args.prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "measured_copy_GBps": copy_gbs, "frac_vs_copy": achieved / copy_gbs,
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "saa_k_state", "alg_bytes_per_launch": bytes_launch,
                      "kernel_ms": ms_state},
