@@ -144,10 +144,16 @@ typedef struct saa_options {
                           SAA_RISK_POF: smoothed probability of failure
                             P[Q > risk_tau] ~ E[s_eps'(Q - risk_tau)] (the
                             derivative of the same C^2 smoothing, a C^1 step
-                            of width eps).
+                            of width eps);
+                          SAA_RISK_BPOE: smoothed buffered probability of
+                            exceedance of risk_tau, min over a >= 0 of
+                            E[s_eps(a (Q - risk_tau) + 1)] (Mafusalov and
+                            Uryasev); a* = infinity (value 0) when no sample
+                            exceeds risk_tau.
                           The non-CVaR measures need t_mode = 0; beta is
                           ignored; the report's t_star is the mean of q
-                          (MEAN_VAR), risk_tau (POF) or 0 (MEAN), dJ_dt 0. */
+                          (MEAN_VAR), risk_tau (POF), a* (BPOE) or 0 (MEAN),
+                          dJ_dt 0. */
   int jac_mode;        /* control Jacobians of mrdino_data_create (Sec. 3.4):
                           SAA_JAC_AUTO (adjoint when d_Z >= r_u, else
                           forward), SAA_JAC_FORWARD (d_Z linearised solves per
@@ -158,7 +164,7 @@ typedef struct saa_options {
   double risk_tau;     /* POF threshold, finite */
 } saa_options;
 
-enum { SAA_RISK_CVAR = 0, SAA_RISK_MEAN = 1, SAA_RISK_MEAN_VAR = 2, SAA_RISK_POF = 3 };
+enum { SAA_RISK_CVAR = 0, SAA_RISK_MEAN = 1, SAA_RISK_MEAN_VAR = 2, SAA_RISK_POF = 3, SAA_RISK_BPOE = 4 };
 enum { SAA_JAC_AUTO = 0, SAA_JAC_FORWARD = 1, SAA_JAC_ADJOINT = 2 };
 
 typedef struct saa_report {

@@ -20,7 +20,7 @@ FORM_PDE, FORM_MRDINO = 0, 1
 FP64, FP32, FP32_DC64, BF16, FP8 = 0, 1, 2, 3, 4
 WANT_Q, WANT_DQDZ, WANT_PHI, WANT_DPHIDZ = 1, 2, 4, 8
 TARGET_CONST, TARGET_SIN, TARGET_QUAD = 0, 1, 2
-RISK_CVAR, RISK_MEAN, RISK_MEAN_VAR, RISK_POF = 0, 1, 2, 3
+RISK_CVAR, RISK_MEAN, RISK_MEAN_VAR, RISK_POF, RISK_BPOE = 0, 1, 2, 3, 4
 JAC_AUTO, JAC_FORWARD, JAC_ADJOINT = 0, 1, 2
 OUU_PGTOL, OUU_FTOL, OUU_MAXITER, OUU_MAXEVAL, OUU_LINESEARCH = 0, 1, 2, 3, 4
 

@@ -169,7 +169,17 @@ void reduce(saa_ctx* c, const double* q, const double* g, const saa_options* opt
 // Adjoint activity of the risk measure (see saa_k_adjoint).
 int adjoint_act(const saa_options* opt) {
   if (opt->all_adjoints) return 1;
-  return opt->risk == SAA_RISK_CVAR ? 0 : opt->risk == SAA_RISK_POF ? 2 : 1;
+  switch (opt->risk) {
+    case SAA_RISK_CVAR: return 0;
+    case SAA_RISK_POF: return 2;
+    case SAA_RISK_BPOE: return 3;
+    default: return 1;
+  }
+}
+
+// Width / threshold that goes with adjoint_act.
+double adjoint_act_w(const saa_options* opt) {
+  return opt->risk == SAA_RISK_BPOE ? opt->risk_tau : opt->eps;
 }
 
 int validate_options(const saa_options* o) {
@@ -181,7 +191,7 @@ int validate_options(const saa_options* o) {
   if (o->t_mode == 1 && !is_fin(o->t_in)) return SAA_E_INVALID;
   if (o->prec < SAA_FP64 || o->prec > SAA_FP8) return SAA_E_INVALID;
   if (!is_fin(o->newton_tol) || !is_fin(o->lin_rtol)) return SAA_E_INVALID;
-  if (o->risk < SAA_RISK_CVAR || o->risk > SAA_RISK_POF) return SAA_E_INVALID;
+  if (o->risk < SAA_RISK_CVAR || o->risk > SAA_RISK_BPOE) return SAA_E_INVALID;
   if (o->risk != SAA_RISK_CVAR && o->t_mode != 0) return SAA_E_INVALID;
   if (!is_fin(o->risk_kappa) || o->risk_kappa < 0.0 || !is_fin(o->risk_tau)) return SAA_E_INVALID;
   if (o->jac_mode < SAA_JAC_AUTO || o->jac_mode > SAA_JAC_ADJOINT) return SAA_E_INVALID;
@@ -582,7 +592,7 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     tm.mark(c->st, 1);
     reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     tm.mark(c->st, 2);
-    if ((rc = run_adjoint(c, opt->prec, sp, adjoint_act(opt), opt->eps, (double*)c->g.p))) return rc;
+    if ((rc = run_adjoint(c, opt->prec, sp, adjoint_act(opt), adjoint_act_w(opt), (double*)c->g.p))) return rc;
     tm.mark(c->st, 3);
     reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 2, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
            (int*)c->lin_adj.p, (int*)c->did.p, c->stats());

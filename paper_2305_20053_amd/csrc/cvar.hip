@@ -507,9 +507,12 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
 //                 (d/dq_i of the SAA variance: the mean's own derivative
 //                 cancels since sum (q - t) = 0)
 //  RISK_POF       v = s_eps'(q - t), d = s_eps''(q - t),     t = tau
+//  RISK_BPOE      v = s_eps(a (q - tau) + 1), d = a s_eps'(a (q - tau) + 1),
+//                 t = a, the minimiser over a >= 0 (d/da of the mean is 0
+//                 there, so a does not move with z); a = infinity: v = d = 0
 template <int KIND>
-__device__ __forceinline__ void risk_terms(double qi, double t, double eps, double ie, double kappa, double& v,
-                                           double& d) {
+__device__ __forceinline__ void risk_terms(double qi, double t, double eps, double ie, double kappa, double tau,
+                                           double& v, double& d) {
   if (KIND == SAA_RISK_CVAR) {
     const double x = qi - t;
     v = sp_val(x, eps, ie);
@@ -521,10 +524,19 @@ __device__ __forceinline__ void risk_terms(double qi, double t, double eps, doub
     const double x = qi - t;
     v = qi + kappa * x * x;
     d = 1.0 + 2.0 * kappa * x;
-  } else {
+  } else if (KIND == SAA_RISK_POF) {
     const double x = qi - t;
     v = sp_d1(x, eps, ie);
     d = sp_d2(x, eps, ie);
+  } else {
+    if (!(t < INFINITY)) {
+      v = 0.0;
+      d = 0.0;
+    } else {
+      const double y = t * (qi - tau) + 1.0;
+      v = sp_val(y, eps, ie);
+      d = t * sp_d1(y, eps, ie);
+    }
   }
 }
 
@@ -533,7 +545,7 @@ __device__ __forceinline__ void risk_terms(double qi, double t, double eps, doub
 // then takes every (RBS/64)-th of them with lane c accumulating component c.
 template <int KIND>
 __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const double* g, int64_t N, int dz,
-                                                       CvarWork w, int G, double eps, double kappa,
+                                                       CvarWork w, int G, double eps, double kappa, double tau,
                                                        const double* tstar) {
   __shared__ double red[2 * (RBS / SAA_WAVE)];
   __shared__ int sh[RBS / SAA_WAVE];
@@ -556,7 +568,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
       d[r] = 0.0;
       if (i < i1) {
         double vi;
-        risk_terms<KIND>(q[i], t, eps, ie, kappa, vi, d[r]);
+        risk_terms<KIND>(q[i], t, eps, ie, kappa, tau, vi, d[r]);
         v[0] += vi;
         v[1] += d[r];
       }
@@ -681,6 +693,48 @@ __global__ void __launch_bounds__(SAA_WAVE) saa_k_risk_t(int64_t N, CvarWork w, 
   if (threadIdx.x == 0) tstar[0] = s / (double)N;
 }
 
+// a* of the buffered probability of exceedance (one workgroup): psi(a) =
+// -sum_i s_eps'(a x_i + 1) x_i with x_i = q_i - tau is non-increasing in a
+// (the mean of s_eps(a x + 1) is convex in a); a* = 0 when psi(0) <= 0, else
+// the root of psi, bracketed by doubling and found by the safeguarded Newton
+// iteration of the t* search; a* = infinity when no q_i exceeds tau.
+__global__ void __launch_bounds__(SBS) saa_k_risk_bpoe(const double* q, int64_t N, double tau, double eps,
+                                                       double* tstar) {
+  __shared__ double red[2 * (SBS / SAA_WAVE)];
+  const double ie = 1.0 / eps;
+  auto psi = [&](double a, double* v) {
+    double s[2] = {0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < N; i += SBS) {
+      const double x = q[i] - tau;
+      const double y = a * x + 1.0;
+      s[0] -= sp_d1(y, eps, ie) * x;
+      s[1] += sp_d2(y, eps, ie) * x * x;
+    }
+    block_sum<2>(s, red);
+    v[0] = s[0];
+    v[1] = s[1];
+  };
+  double qmax = -INFINITY;
+  for (int64_t i = threadIdx.x; i < N; i += SBS) qmax = fmax(qmax, q[i]);
+  qmax = block_max1(qmax, red);
+  double a = 0.0;
+  double v[2];
+  psi(0.0, v);
+  if (!(qmax > tau)) {
+    a = INFINITY;
+  } else if (v[0] > 0.0) {
+    double lo = 0.0, hi = 1.0 / (qmax - tau);
+    for (int k = 0; k < 200; ++k) {   // uniform over the block (block sums)
+      psi(hi, v);
+      if (!(v[0] > 0.0)) break;
+      lo = hi;
+      hi *= 4.0;
+    }
+    a = newton_in_bracket(lo, hi, 0.0, psi);
+  }
+  if (threadIdx.x == 0) tstar[0] = a;
+}
+
 namespace saa_launch {
 
 size_t cvar_work_bytes() {
@@ -732,7 +786,7 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
     }
     saa_k_cvar_solve<<<1, SBS, 0, st>>>(q, N, w, G, eps, target, t_mode, t_in, tstar);
   }
-  if (phase & 2) saa_k_cvar_part<SAA_RISK_CVAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, tstar);
+  if (phase & 2) saa_k_cvar_part<SAA_RISK_CVAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar);
   if ((phase & 2) || stats)
     saa_k_cvar_final<<<1, SBS, 0, st>>>(N, dz, w, G, target, SAA_RISK_CVAR, alpha, z, tstar, (phase & 2) ? 1 : 0,
                                         out, newton, lin, flag, lin_adj, did, (CvarStats*)stats);
@@ -748,16 +802,26 @@ void risk(const double* q, const double* g, int64_t N, int dz, int kind, double 
   const CvarWork w = carve(work);
   const int G = groups(N);
   if (phase & 1) {
-    if (kind == SAA_RISK_MEAN_VAR) saa_k_risk_sum<<<G, RBS, 0, st>>>(q, N, w, G);
-    saa_k_risk_t<<<1, SAA_WAVE, 0, st>>>(N, w, G, kind, tau, tstar);
+    if (kind == SAA_RISK_BPOE) {
+      saa_k_risk_bpoe<<<1, SBS, 0, st>>>(q, N, tau, eps, tstar);
+    } else {
+      if (kind == SAA_RISK_MEAN_VAR) saa_k_risk_sum<<<G, RBS, 0, st>>>(q, N, w, G);
+      saa_k_risk_t<<<1, SAA_WAVE, 0, st>>>(N, w, G, kind, tau, tstar);
+    }
   }
   if (phase & 2) {
     switch (kind) {
-      case SAA_RISK_MEAN: saa_k_cvar_part<SAA_RISK_MEAN><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tstar); break;
-      case SAA_RISK_MEAN_VAR:
-        saa_k_cvar_part<SAA_RISK_MEAN_VAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tstar);
+      case SAA_RISK_MEAN:
+        saa_k_cvar_part<SAA_RISK_MEAN><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
         break;
-      default: saa_k_cvar_part<SAA_RISK_POF><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tstar);
+      case SAA_RISK_MEAN_VAR:
+        saa_k_cvar_part<SAA_RISK_MEAN_VAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
+        break;
+      case SAA_RISK_POF:
+        saa_k_cvar_part<SAA_RISK_POF><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
+        break;
+      default:
+        saa_k_cvar_part<SAA_RISK_BPOE><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
     }
   }
   if ((phase & 2) || stats)

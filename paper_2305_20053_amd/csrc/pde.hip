@@ -751,7 +751,9 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
 // block per sample.  Only samples whose risk weight can be non-zero are
 // solved (act 0: q_i > t, the CVaR weight s_eps'(q - t) > 0; act 1: all;
 // act 2: 0 < q_i - t < act_w, the smoothed failure-probability weight
-// s_eps''(q - t) != 0); the others get a zero g row.
+// s_eps''(q - t) != 0; act 3: a (q_i - act_w) + 1 > 0 with a = t > 0, the
+// buffered-exceedance weight a s_eps'(a (q - tau) + 1)); the others get a
+// zero g row.
 // ---------------------------------------------------------------------------
 template <typename TW, typename TS, bool LDSC>
 __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, const double* em_all,
@@ -764,7 +766,9 @@ __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, 
   if (s >= N) return;
   const int n = g.n[0], np = n + 1;
   const double xq = q[s] - tstar[0];
-  const bool active = act == 1 || (xq > 0.0 && (act == 0 || xq < act_w));
+  const bool active = act == 1 || (act == 3 ? (tstar[0] > 0.0 && tstar[0] < INFINITY &&
+                                               tstar[0] * (q[s] - act_w) + 1.0 > 0.0)
+                                            : (xq > 0.0 && (act == 0 || xq < act_w)));
   if (!active) {
     if (threadIdx.x < g.dz) g_out[s * g.dz + threadIdx.x] = 0.0;
     if (threadIdx.x == 0) {

@@ -1,6 +1,6 @@
 """GPU parity of the expectation-type risk measures (Sec. 2.1-2.2: mean,
-mean + kappa variance, smoothed probability of failure) against the oracle's
-definitions.
+mean + kappa variance, smoothed probability of failure, smoothed buffered
+probability of exceedance) against the oracle's definitions.
 
 Reduction alone (per-sample q, dq/dz read back from the device, N = 20000):
 1e-12 relative.  PDE form end to end (FP64, 64 samples): J and grad J to
@@ -24,6 +24,8 @@ def _ref(kind, q, g, z, kappa, tau, eps, alpha=1e-3):
         return risk.mean(q, g, z, alpha)
     if kind == saa.RISK_MEAN_VAR:
         return risk.mean_var(q, g, z, kappa, alpha)
+    if kind == saa.RISK_BPOE:
+        return risk.bpoe(q, g, z, tau, eps, alpha)
     return risk.pof(q, g, z, tau, eps, alpha)
 
 
@@ -48,11 +50,11 @@ def surr(gpu_lib):
     ctx.close()
 
 
-@pytest.mark.parametrize("kind", [saa.RISK_MEAN, saa.RISK_MEAN_VAR, saa.RISK_POF])
+@pytest.mark.parametrize("kind", [saa.RISK_MEAN, saa.RISK_MEAN_VAR, saa.RISK_POF, saa.RISK_BPOE])
 def test_reduction_matches_oracle(surr, kind):
     ctx, model, z, q, g = surr
     tau = float(np.quantile(q, 0.8))
-    eps = 0.25 * float(np.std(q))
+    eps = 0.25 * float(np.std(q)) if kind != saa.RISK_BPOE else 0.1   # bPOE smooths a dimensionless argument
     print(f"case risk reduction kind={kind}", flush=True)
     opt = saa.options(prec=saa.FP32, risk=kind, risk_kappa=0.7, risk_tau=tau, eps=eps)
     J, grad, rep = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
@@ -61,6 +63,8 @@ def test_reduction_matches_oracle(surr, kind):
     assert abs(J - ref["J"]) <= 1e-12 * abs(ref["J"])
     assert _rel(grad, ref["grad"]) <= 1e-12
     assert abs(rep["t_star"] - ref["t"]) <= 1e-13 * max(1.0, abs(ref["t"])) and rep["dJ_dt"] == 0.0
+    if kind == saa.RISK_BPOE:
+        assert 0.0 < rep["t_star"] < float("inf") and 0.2 < J < 1.0
     # the replayed graph gives the same bits as the eager evaluation
     J2, grad2, rep2 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
     J3, grad3, rep3 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
@@ -79,11 +83,11 @@ def pde(gpu_lib):
     ctx.close()
 
 
-@pytest.mark.parametrize("kind", [saa.RISK_MEAN, saa.RISK_MEAN_VAR, saa.RISK_POF])
+@pytest.mark.parametrize("kind", [saa.RISK_MEAN, saa.RISK_MEAN_VAR, saa.RISK_POF, saa.RISK_BPOE])
 def test_pde_form_matches_oracle(pde, kind):
     ctx, z, q, g = pde
     tau = float(np.quantile(q, 0.7))
-    eps = 0.3 * float(np.std(q))
+    eps = 0.3 * float(np.std(q)) if kind != saa.RISK_BPOE else 0.1
     print(f"case risk pde kind={kind}", flush=True)
     opt = saa.options(prec=saa.FP64, risk=kind, risk_kappa=2.0, risk_tau=tau, eps=eps)
     J, grad, rep = ctx.objective_grad(z, opt=opt)
@@ -91,13 +95,18 @@ def test_pde_form_matches_oracle(pde, kind):
     assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"])
     assert _rel(grad, ref["grad"]) <= 1e-9
     x = q - tau
-    want = 64 if kind != saa.RISK_POF else int(np.sum((x > 0) & (x < eps)))
+    if kind == saa.RISK_POF:
+        want = int(np.sum((x > 0) & (x < eps)))
+    elif kind == saa.RISK_BPOE:
+        want = int(np.sum(ref["t"] * x + 1.0 > 0))
+    else:
+        want = 64
     assert rep["n_adjoints"] == want and 0 < want
 
 
 def test_risk_options_are_validated(pde):
     ctx, z, q, g = pde
-    for kw in [dict(risk=4), dict(risk=-1), dict(risk=saa.RISK_MEAN, t_mode=1, t_in=0.0),
+    for kw in [dict(risk=5), dict(risk=-1), dict(risk=saa.RISK_MEAN, t_mode=1, t_in=0.0),
                dict(risk=saa.RISK_MEAN_VAR, risk_kappa=-1.0), dict(risk=saa.RISK_POF, risk_tau=float("nan"))]:
         with pytest.raises(saa.SaaError) as e:
             ctx.objective_grad(z, opt=saa.options(**kw))

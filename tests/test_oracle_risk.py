@@ -43,7 +43,28 @@ def test_pof_is_the_failure_fraction_away_from_the_threshold():
     assert np.all(r["grad"] == 0.0)
 
 
-@pytest.mark.parametrize("which", ["mean", "mean_var", "pof"])
+def test_bpoe_is_one_minus_beta_at_the_cvar():
+    """bPOE_tau = 1 - beta where tau = CVaR_beta (Mafusalov-Uryasev), here
+    with beta N integer (CVaR = mean of the top k samples) and a tiny eps."""
+    A, b, z = _linear(25)
+    q = A @ z + b
+    for k in (7, 30, 120):
+        tau = float(np.mean(np.sort(q)[-k:]))
+        r = risk.bpoe(q, A, z, tau, 1e-10, 0.0)
+        assert abs(r["J"] - k / len(q)) <= 1e-7, (k, r["J"])
+
+
+def test_bpoe_limits():
+    A, b, z = _linear(26)
+    q = A @ z + b
+    eps = 0.1
+    r = risk.bpoe(q, A, z, float(np.mean(q)) - 0.1, eps, 0.0)      # tau below the mean: a* = 0
+    assert r["t"] == 0.0 and abs(r["J"] - (1.0 - eps / 2)) <= 1e-15 and np.all(r["grad"] == 0.0)
+    r = risk.bpoe(q, A, z, float(np.max(q)) + 1e-3, eps, 0.0)      # no exceedance: a* = inf, 0
+    assert r["t"] == float("inf") and r["J"] == 0.0
+
+
+@pytest.mark.parametrize("which", ["mean", "mean_var", "pof", "bpoe"])
 def test_gradients_match_finite_differences(which):
     A, b, z = _linear(24)
     tau = float(np.median(A @ z + b))
@@ -54,6 +75,8 @@ def test_gradients_match_finite_differences(which):
             return risk.mean(q, A, zz, 0.3)
         if which == "mean_var":
             return risk.mean_var(q, A, zz, 0.8, 0.3)
+        if which == "bpoe":
+            return risk.bpoe(q, A, zz, tau + 1.0, 0.5, 0.3)
         return risk.pof(q, A, zz, tau, 2.0, 0.3)
     g = J(z)["grad"]
     h = 1e-6
