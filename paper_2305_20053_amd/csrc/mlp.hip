@@ -39,19 +39,34 @@ __device__ __forceinline__ int kperm(int k) {
   return b + (t < 4 ? 4 * g + t : 16 + 4 * g + (t - 4));
 }
 
-// GELU and its derivative for the BF16 kernel, branch-free: Phi(a) =
-// (1 + erf(a / sqrt 2)) / 2 with erf from Abramowitz & Stegun (1964), formula
-// 7.1.26 (absolute error <= 1.5e-7, far below BF16 rounding); the factor
-// exp(-a^2 / 2) is shared with GELU'(a) = Phi(a) + a phi(a).
-__device__ __forceinline__ void gelu_pair(float a, float& h, float& dh) {
-  const float x = fabsf(a) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-  const float p =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  const float e = __expf(-x * x);
-  const float phi2 = 0.5f * copysignf(1.0f - p * e, a) + 0.5f;   // Phi(a)
-  h = a * phi2;
-  dh = fmaf(a * 0.39894228040143268f, e, phi2);
+// GELU and its derivative of two pre-activations for the MFMA kernels,
+// branch-free, in packed FP16 (v_pk_fma_f16 and friends; exp2 and rcp per
+// half): Phi(a) = (1 + erf(a / sqrt 2)) / 2 with erf from Abramowitz & Stegun
+// (1964), formula 7.1.26 (absolute error <= 1.5e-7); the factor exp(-a^2 / 2)
+// is shared with GELU'(a) = Phi(a) + a phi(a).  The kernels round h to BF16
+// / FP8 for the next product and keep GELU' as fp16, so FP16 arithmetic
+// (relative rounding 4.9e-4) stays below those roundings.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void gelu_pair2(float a0, float a1, float& h0, float& h1, _Float16& d0, _Float16& d1) {
+  const h2v a = {(_Float16)a0, (_Float16)a1};
+  const h2v x = __builtin_elementwise_abs(a) * (h2v)(_Float16)0.70710678f;
+  const h2v den = __builtin_elementwise_fma((h2v)(_Float16)0.3275911f, x, (h2v)(_Float16)1.0f);
+  const h2v t = {(_Float16)__builtin_amdgcn_rcph(den.x), (_Float16)__builtin_amdgcn_rcph(den.y)};
+  h2v p = __builtin_elementwise_fma(t, (h2v)(_Float16)1.061405429f, (h2v)(_Float16)-1.453152027f);
+  p = __builtin_elementwise_fma(p, t, (h2v)(_Float16)1.421413741f);
+  p = __builtin_elementwise_fma(p, t, (h2v)(_Float16)-0.284496736f);
+  p = __builtin_elementwise_fma(p, t, (h2v)(_Float16)0.254829592f);
+  p = p * t;
+  const h2v e = __builtin_elementwise_exp2((x * x) * (h2v)(_Float16)-1.44269504f);   // exp(-x^2)
+  const h2v erfx = __builtin_elementwise_fma(-p, e, (h2v)(_Float16)1.0f);
+  const h2v phi = __builtin_elementwise_fma(__builtin_elementwise_copysign(erfx, a), (h2v)(_Float16)0.5f,
+                                            (h2v)(_Float16)0.5f);   // Phi(a)
+  const h2v h = a * phi;
+  const h2v dh = __builtin_elementwise_fma(a * (h2v)(_Float16)0.39894228f, e, phi);
+  h0 = (float)h.x;
+  h1 = (float)h.y;
+  d0 = dh.x;
+  d1 = dh.y;
 }
 
 __device__ __forceinline__ float gelu_f(float a) { return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f)); }
@@ -352,13 +367,16 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       for (int sb = 0; sb < SB; ++sb) {
         const float cs = unscale(L, sb);
         f16x4 d4;
+        float av[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float h, dh;
-          gelu_pair(OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r], h, dh);
-          d4[r] = (_Float16)dh;
-          acc[j][sb][r] = h;
-        }
+        for (int r = 0; r < 4; ++r) av[r] = OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r];
+        float hv[4];
+        _Float16 dv[4];
+        gelu_pair2(av[0], av[1], hv[0], hv[1], dv[0], dv[1]);
+        gelu_pair2(av[2], av[3], hv[2], hv[3], dv[2], dv[3]);
+        d4 = f16x4{dv[0], dv[1], dv[2], dv[3]};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[j][sb][r] = hv[r];
         *(f16x4*)(myg + (((L * MW + j) * SB + sb) * 64 + ln) * 4) = d4;
       }
     }
