@@ -21,8 +21,7 @@ extern "C" int saa_sym_eig_gpu(int n, const double* A_dev, double* w, double* V_
 namespace saa_launch {
 template <typename T>
 void gemm(bool ta, bool tb, int M, int N, int K, T alpha, const T* A, int lda, int64_t sA, const T* B, int ldb,
-          int64_t sB, T beta, T* C, int ldc, int64_t sC, int batch, hipStream_t st, T* work = nullptr,
-          int64_t work_elems = 0);
+          int64_t sB, T beta, T* C, int ldc, int64_t sC, int batch, hipStream_t st);
 void mass_rows(const double* U, int64_t ldu, const double* ubar, double* out, int64_t ldo, int n, int64_t rows,
                hipStream_t st);
 void colmean(const double* X, int64_t rows, int cols, int64_t ldx, double* out, hipStream_t st);
@@ -69,7 +68,6 @@ struct TrainWs {
   DevBuf A[MLP_MAX_DEPTH], H[MLP_MAX_DEPTH], JA[MLP_MAX_DEPTH], JH[MLP_MAX_DEPTH];
   DevBuf P, JP, gP, gJP, gH[2], gJH[2];
   DevBuf grad, m, v, parts, loss;
-  DevBuf splitk;   // split-K partial products of the weight-gradient GEMMs
 };
 
 struct TrainState {
@@ -82,10 +80,6 @@ TrainState* train_state(mrdino_model* m) {
   return (TrainState*)m->train;
 }
 
-constexpr int kSplitMax = 32;   // split-K slices of the weight-gradient GEMMs
-int64_t splitk_elems(const mrdino_model* m) {
-  return (int64_t)kSplitMax * m->dims.width * std::max(m->dims.width, m->dims.r_m + m->dims.d_z);
-}
 
 int alloc_ws(mrdino_model* mdl, int B) {
   TrainState* ts = train_state(mdl);
@@ -121,7 +115,6 @@ int alloc_ws(mrdino_model* mdl, int B) {
   if (!rc && !w.v.p) rc = w.v.alloc_zero(f * mdl->n_params, st);
   if (!rc) rc = w.parts.alloc_zero(sizeof(double) * (((size_t)B * d.d_z * d.r_u + 1023) / 1024 + 16), st);
   if (!rc) rc = w.loss.alloc_zero(sizeof(double) * 4, st);
-  if (!rc) rc = w.splitk.alloc(f * (size_t)kSplitMax * W * std::max(W, in));
   if (!rc) w.B = B;
   return rc;
 }
@@ -183,7 +176,7 @@ void loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad) {
                           G + mdl->off_w[L], W, 0, 1, st);
   if (dino)
     saa_launch::gemm<float>(true, false, d.r_u, W, B * dz, 1.0f, F(w.gJP), d.r_u, 0, F(w.JH[L - 1]), W, 0, 1.0f,
-                            G + mdl->off_w[L], W, 0, 1, st, F(w.splitk), splitk_elems(mdl));
+                            G + mdl->off_w[L], W, 0, 1, st);
   saa_launch::colsum(F(w.gP), B, d.r_u, G + mdl->off_b[L], 0, st);
   int cur = 0;
   saa_launch::gemm<float>(false, false, B, W, d.r_u, 1.0f, F(w.gP), d.r_u, 0, P + mdl->off_w[L], W, 0, 0.0f,
@@ -200,7 +193,7 @@ void loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad) {
     if (dino) {
       if (l >= 1)
         saa_launch::gemm<float>(true, false, W, W, B * dz, 1.0f, F(w.gJH[cur]), W, 0, F(w.JH[l - 1]), W, 0, 1.0f,
-                                G + mdl->off_w[l], W, 0, 1, st, F(w.splitk), splitk_elems(mdl));
+                                G + mdl->off_w[l], W, 0, 1, st);
       else
         saa_launch::w0z_grad(F(w.gJH[cur]), B, dz, W, d.r_m, in, G + mdl->off_w[0], st);
     }
