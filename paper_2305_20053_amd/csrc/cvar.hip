@@ -59,6 +59,7 @@ constexpr int WAVE_NEWTON = 256;  // active sets up to this size are solved by o
 constexpr int RPASSES = 4;        // refinement passes when the active set overflows
 constexpr double FIX_SCALE = 274877906944.0;   // 2^38: fixed-point scale of the refinement sums
 static_assert(NP == SAA_WAVE, "one probe per lane");
+static_assert(GMAX % SAA_WAVE == 0, "partial rows per lane in the final reduction");
 static_assert(SAA_MAX_DZ <= SAA_WAVE, "one gradient component per lane");
 
 // Device workspace, carved from one allocation of cvar_work_bytes().
@@ -614,7 +615,9 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
   constexpr int NW = SBS / SAA_WAVE;
   __shared__ double red[5 * NW];
   __shared__ double col[NW][PSTRIDE];
-  if (stats) {
+  if (stats && !newton && !lin && !flag && !lin_adj && !did) {   // no per-sample solver (surrogate)
+    if (threadIdx.x == 0) *stats = CvarStats{};
+  } else if (stats) {
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double nm = 0.0;
     for (int64_t i = threadIdx.x; i < N; i += SBS) {
@@ -639,14 +642,32 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
     }
   }
   if (!outputs) return;
-  // wave k sums the partials of workgroups k, k + NW, ...; then column sums
-  // over the waves in order
+  // wave w sums columns w, w + NW, ... (at most CPW of them); lane l adds the
+  // partial rows l, l + 64, l + 128, l + 192 in that order (loads
+  // unconditional: rows clamped, zero weight past G), then a fixed-order
+  // butterfly across the lanes
   const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
   const int ncol = 2 + dz;
-  for (int c = lane; c < ncol; c += SAA_WAVE) {
+  constexpr int CPW = (PSTRIDE + NW - 1) / NW;
+  constexpr int RPL = GMAX / SAA_WAVE;
+  double x[CPW][RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int b = lane + SAA_WAVE * r < G ? lane + SAA_WAVE * r : G - 1;
+#pragma unroll
+    for (int cc = 0; cc < CPW; ++cc) {
+      const int c = wid + NW * cc < PSTRIDE ? wid + NW * cc : PSTRIDE - 1;
+      x[cc][r] = w.part[(size_t)b * PSTRIDE + c];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < CPW; ++cc) {
     double a = 0.0;
-    for (int b = wid; b < G; b += NW) a += w.part[(size_t)b * PSTRIDE + c];
-    col[wid][c] = a;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) a += lane + SAA_WAVE * r < G ? x[cc][r] : 0.0;
+    a = wave_sum(a);
+    const int c = wid + NW * cc;
+    if (lane == 0 && c < ncol) col[0][c] = a;
   }
   __syncthreads();
   const int k = threadIdx.x;
@@ -656,8 +677,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
     zz = wave_sum(zl * zl);
   }
   if (k >= ncol) return;
-  double acc = 0.0;
-  for (int r = 0; r < NW; ++r) acc += col[r][k];
+  const double acc = col[0][k];
   const double scale = 1.0 / target;   // 1 / (N (1 - beta)) for CVaR, else 1 / N
   const bool cv = kind == SAA_RISK_CVAR;
   if (k == 0) {
