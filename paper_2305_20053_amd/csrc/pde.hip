@@ -344,11 +344,15 @@ __device__ void setup_lds_levels(const PdeGeo& g, MgBufs<TS>& m, TS* lds) {
 }
 
 // Preconditioned CG on A x = b with b in m.cr (overwritten by the residual),
-// x in m.cx.  Returns iterations; sets *ok = false if not converged.
+// x in m.cx.  Returns iterations; sets *ok = false if not converged.  The
+// preconditioner is one V(1,1) cycle (SolveParams.nu = 1); its fine-level
+// passes are folded into the CG vector passes (see vcycle_from and
+// restrict_red) and every piece of it appears once in the code.
 template <typename TS>
-__device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it, int nu,
-                   double* red, bool* ok) {
+__device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it, int nu, double* red, bool* ok) {
+  (void)nu;
   const Level<TS> L0 = level(g, m, 0);
+  const Level<TS>& Ls = L0;   // fine-level smoother operator
   const int n = g.n[0];
   double rr0 = 0.0;
   for_nodes(n, [&](int p, int i, int j) {
@@ -364,34 +368,23 @@ __device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it
     return 0;
   }
   TS* z = m.X;  // level-0 V-cycle output
-  vcycle(g, m, m.cr, nu);
-  double rz = 0.0;
+  // first red half sweep of the first V-cycle (later ones ride on the update)
   for_nodes(n, [&](int p, int i, int j) {
-    if (interior(i, j, n)) {
-      rz += (double)m.cr[p] * (double)z[p];
-      m.cp[p] = z[p];
-    }
+    if (interior(i, j, n) && !((i + j) & 1)) z[p] = m.cr[p] / Ls.D[p];
   });
-  rz = block_sum1(rz, red);
+  __syncthreads();
   const double tol2 = rtol * rtol * rr0;
-  const bool fused = nu == 1 && g.L > 1;
   // search directions alternate between cp and the (otherwise unused) level-0
-  // part of B: from the second iteration on, p = z + beta p_old is formed
-  // inside the product A p (neighbour values recomputed, so no extra pass)
+  // part of B; p = z + beta p_old is formed inside the product A p
+  // (neighbour values recomputed; beta = 0 in the first iteration, and both
+  // buffers only ever hold finite values)
   TS* pc = m.cp;
   TS* pn = m.B;
   TS beta = (TS)0;
-  for (int it = 1; it <= max_it; ++it) {
-    double pq = 0.0;
-    if (it == 1) {
-      for_nodes(n, [&](int p, int i, int j) {
-        if (interior(i, j, n)) {
-          const TS q = L0.D[p] * pc[p] - offdiag_sum(L0, pc, p);
-          m.cq[p] = q;
-          pq += (double)pc[p] * (double)q;
-        }
-      });
-    } else {
+  double rz = 0.0;
+  for (int it = 0; it <= max_it; ++it) {
+    if (it > 0) {
+      double pq = 0.0;
       const TS* po = pc;
       for_nodes(n, [&](int p, int i, int j) {
         if (interior(i, j, n)) {
@@ -407,43 +400,36 @@ __device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it
       TS* t = pc;
       pc = pn;
       pn = t;
-    }
-    pq = block_sum1(pq, red);
-    if (!(pq > 0.0)) {
-      *ok = false;
-      return it;
-    }
-    const double alpha = rz / pq;
-    const TS a = (TS)alpha;
-    double rr = 0.0;
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        m.cx[p] += a * pc[p];
-        const TS r = m.cr[p] - a * m.cq[p];
-        m.cr[p] = r;
-        rr += (double)r * (double)r;
-        if (fused && !((i + j) & 1)) z[p] = r / L0.D[p];   // first red half sweep of the V-cycle
+      pq = block_sum1(pq, red);
+      if (!(pq > 0.0)) {
+        *ok = false;
+        return it;
       }
-    });
-    rr = block_sum1(rr, red);
-    if (rr <= tol2) return it;
-    double rzn = 0.0;
-    if (fused) {
-      gs_half(L0, (const TS*)m.cr, z, 1, false);
-      residual_red(L0, (const TS*)m.cr, (const TS*)z, m.T);
-      restrict_red(n, (const TS*)m.T, g.n[1], at_level(m.B, m.lB, g, 1));
-      vcycle_from(g, m, m.cr, nu, 1);
-      prolong_add(n, z, g.n[1], at_level(m.X, m.lX, g, 1));
-      rzn = gs_half_dot(L0, (const TS*)m.cr, z, 1);
-      rzn += gs_half_dot(L0, (const TS*)m.cr, z, 0);
-    } else {
-      vcycle(g, m, m.cr, nu);
+      const TS a = (TS)(rz / pq);
+      double rr = 0.0;
       for_nodes(n, [&](int p, int i, int j) {
-        if (interior(i, j, n)) rzn += (double)m.cr[p] * (double)z[p];
+        if (interior(i, j, n)) {
+          m.cx[p] += a * pc[p];
+          const TS r = m.cr[p] - a * m.cq[p];
+          m.cr[p] = r;
+          rr += (double)r * (double)r;
+          if (!((i + j) & 1)) z[p] = r / Ls.D[p];   // first red half sweep of the next V-cycle
+        }
       });
+      rr = block_sum1(rr, red);
+      if (rr <= tol2) return it;
     }
+    // rest of the V-cycle: black sweep, red residuals restricted, coarse
+    // levels, prolongation, post-smoothing with r . z
+    gs_half(Ls, (const TS*)m.cr, z, 1, false);
+    residual_red(Ls, (const TS*)m.cr, (const TS*)z, m.T);
+    restrict_red(n, (const TS*)m.T, g.n[1], at_level(m.B, m.lB, g, 1));
+    vcycle_from(g, m, m.cr, 1, 1);
+    prolong_add(n, z, g.n[1], at_level(m.X, m.lX, g, 1));
+    double rzn = gs_half_dot(Ls, (const TS*)m.cr, z, 1);
+    rzn += gs_half_dot(Ls, (const TS*)m.cr, z, 0);
     rzn = block_sum1(rzn, red);
-    beta = (TS)(rzn / rz);
+    beta = (TS)(it > 0 ? rzn / rz : 0.0);
     rz = rzn;
   }
   *ok = false;
