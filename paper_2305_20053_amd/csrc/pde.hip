@@ -247,10 +247,6 @@ __device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, 
   }
 }
 
-template <typename TS>
-__device__ void vcycle(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int nu) {
-  vcycle_from(g, m, b0, nu, 0);
-}
 
 // Fine-level pieces of a V(1,1) cycle fused with the CG vector passes:
 //  * the first red half sweep x_red = b_red / D (black taken as zero) is
