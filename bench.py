@@ -32,14 +32,15 @@ HBM_PEAK_GBS = 8000.0
 #   PCG iteration: p = z + beta p fused into A p (z, p, D, WE, WN read;
 #   p, q written: 7 x 4 B) + x, r update with the first red half sweep
 #   (7 x 4 B) + fine V-cycle rest (black sweep 4.5, red residual 4.5,
-#   restriction 0.5, prolongation 2, two half sweeps 9: 20.5 x 4 B) = 138 B
+#   restriction 0.5, black sweep with the prolongation folded in 4.5, red
+#   sweep 4.5: 18.5 x 4 B)                                        = 130 B
 #   PCG start (r.r and x = 0: 2 x 4 B; the first V-cycle: red half sweep
-#   1.5 x 4 B + the rest as above 20.5 x 4 B)                   =  96 B
+#   1.5 x 4 B + the rest as above 18.5 x 4 B)                   =  88 B
 #   Newton step: residual 28 B + diagonals 25 B + update 20 B   =  73 B
 #   per sample: f = F z and u = 0 (16 B) + QoI (8 B)            =  24 B
-BYTES_PCG_ITER_F32 = 138
-BYTES_PCG_START_F32 = 96
-BYTES_VCYCLE_FINE_F32 = 82
+BYTES_PCG_ITER_F32 = 130
+BYTES_PCG_START_F32 = 88
+BYTES_VCYCLE_FINE_F32 = 74
 BYTES_NEWTON_F64 = 73
 BYTES_SAMPLE = 24
 

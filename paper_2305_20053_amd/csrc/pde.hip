@@ -167,15 +167,6 @@ __device__ void gs_half(const Level<TS>& L, const TS* b, TS* x, int c, bool firs
   __syncthreads();
 }
 
-// t = b - A x on level L.
-template <typename TS>
-__device__ void residual_level(const Level<TS>& L, const TS* b, const TS* x, TS* t) {
-  for_nodes(L.n, [&](int p, int i, int j) {
-    if (interior(i, j, L.n)) t[p] = b[p] - (L.D[p] * x[p] - offdiag_sum(L, x, p));
-  });
-  __syncthreads();
-}
-
 // Restriction R = P^T from the fine level (n) to the coarse level (n/2).
 template <typename TS>
 __device__ void restrict_level(int nf, const TS* t, int nc, TS* bc) {
@@ -188,65 +179,6 @@ __device__ void restrict_level(int nf, const TS* t, int nc, TS* bc) {
   });
   __syncthreads();
 }
-
-// x_f += P x_c (linear interpolation on the nested P1 mesh).
-template <typename TS>
-__device__ void prolong_add(int nf, TS* xf, int nc, const TS* xc) {
-  const int npc = nc + 1;
-  for_nodes(nf, [&](int p, int i, int j) {
-    if (interior(i, j, nf)) {
-      const int I = i >> 1, J = j >> 1;
-      const int q = J * npc + I;
-      TS v;
-      if (!(i & 1) && !(j & 1)) v = xc[q];
-      else if ((i & 1) && !(j & 1)) v = (TS)0.5 * (xc[q] + xc[q + 1]);
-      else if (!(i & 1) && (j & 1)) v = (TS)0.5 * (xc[q] + xc[q + npc]);
-      else v = (TS)0.5 * (xc[q] + xc[q + npc + 1]);
-      xf[p] += v;
-    }
-  });
-  __syncthreads();
-}
-
-// Symmetric V-cycle: X_0 = V(b0).  Pre-smoothing nu x (red, black), post
-// smoothing nu x (black, red), so that the preconditioner is symmetric.
-// vcycle_from(l0) runs the part from level l0 down and back to l0 (its right
-// hand side already restricted to B_l0).
-template <typename TS>
-__device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, const TS* b0, int nu, int l0) {
-  const int L = g.L;
-  for (int l = l0; l < L - 1; ++l) {
-    const Level<TS> lv = level(g, m, l);
-    const TS* b = (l == 0) ? b0 : at_level(m.B, m.lB, g, l);
-    TS* x = at_level(m.X, m.lX, g, l);
-    TS* t = at_level(m.T, m.lT, g, l);
-    for (int s = 0; s < nu; ++s) {
-      gs_half(lv, b, x, 0, s == 0);
-      gs_half(lv, b, x, 1, false);
-    }
-    residual_level(lv, b, x, t);
-    restrict_level(g.n[l], t, g.n[l + 1], at_level(m.B, m.lB, g, l + 1));
-  }
-  {  // coarsest level: a single unknown at node (1,1) of the n = 2 grid
-    const int l = L - 1;
-    if (threadIdx.x == 0) {
-      const int p = 1 * (g.n[l] + 1) + 1;
-      at_level(m.X, m.lX, g, l)[p] = at_level(m.B, m.lB, g, l)[p] / at_level(m.D, m.lD, g, l)[p];
-    }
-    __syncthreads();
-  }
-  for (int l = L - 2; l >= l0; --l) {
-    const Level<TS> lv = level(g, m, l);
-    const TS* b = (l == 0) ? b0 : at_level(m.B, m.lB, g, l);
-    TS* x = at_level(m.X, m.lX, g, l);
-    prolong_add(g.n[l], x, g.n[l + 1], at_level(m.X, m.lX, g, l + 1));
-    for (int s = 0; s < nu; ++s) {
-      gs_half(lv, b, x, 1, false);
-      gs_half(lv, b, x, 0, false);
-    }
-  }
-}
-
 
 // Fine-level pieces of a V(1,1) cycle fused with the CG vector passes:
 //  * the first red half sweep x_red = b_red / D (black taken as zero) is
@@ -291,6 +223,69 @@ __device__ double gs_half_dot(const Level<TS>& L, const TS* b, TS* x, int c) {
   });
   __syncthreads();
   return acc;
+}
+
+// Post-smoothing black half sweep fused with the prolongation x += P x_c:
+// the red neighbours of a black node are read as x_k + (P x_c)_k (linear
+// interpolation at a red fine node: the coincident coarse value at (even,
+// even), the mean of the two diagonal ends at (odd, odd)).  The prolonged
+// values are never stored: black nodes are overwritten here and red nodes by
+// the red half sweep that follows (which reads black neighbours only).
+// Returns this thread's part of sum b_p x_p over the black nodes.
+template <typename TS>
+__device__ double gs_black_prolong(const Level<TS>& L, const TS* b, TS* x, const TS* xc) {
+  const int npc = L.n / 2 + 1;
+  auto xr = [&](int q, int i, int j) -> TS {   // prolonged value at the red node q = (i, j)
+    const int qc = (j >> 1) * npc + (i >> 1);
+    const TS v = (i & 1) ? (TS)0.5 * (xc[qc] + xc[qc + npc + 1]) : xc[qc];
+    return x[q] + v;
+  };
+  double acc = 0.0;
+  for_nodes(L.n, [&](int p, int i, int j) {
+    if (interior(i, j, L.n) && ((i + j) & 1)) {
+      const TS bp = b[p];
+      const TS off = L.WE[p] * xr(p + 1, i + 1, j) + L.WE[p - 1] * xr(p - 1, i - 1, j) +
+                     L.WN[p] * xr(p + L.np, i, j + 1) + L.WN[p - L.np] * xr(p - L.np, i, j - 1);
+      const TS v = (bp + off) / L.D[p];
+      x[p] = v;
+      acc += (double)bp * (double)v;
+    }
+  });
+  __syncthreads();
+  return acc;
+}
+
+// V(1,1) cycle from level l0 down and back to l0, its right-hand side already
+// restricted to B_l0: red, black (with the red residuals restricted, as on
+// the fine level), coarse correction, black fused with the prolongation, red.
+template <typename TS>
+__device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, int l0) {
+  const int L = g.L;
+  for (int l = l0; l < L - 1; ++l) {
+    const Level<TS> lv = level(g, m, l);
+    const TS* b = at_level(m.B, m.lB, g, l);
+    TS* x = at_level(m.X, m.lX, g, l);
+    TS* t = at_level(m.T, m.lT, g, l);
+    gs_half(lv, b, x, 0, true);
+    gs_half(lv, b, x, 1, false);
+    residual_red(lv, b, (const TS*)x, t);
+    restrict_red(g.n[l], (const TS*)t, g.n[l + 1], at_level(m.B, m.lB, g, l + 1));
+  }
+  {  // coarsest level: a single unknown at node (1,1) of the n = 2 grid
+    const int l = L - 1;
+    if (threadIdx.x == 0) {
+      const int p = 1 * (g.n[l] + 1) + 1;
+      at_level(m.X, m.lX, g, l)[p] = at_level(m.B, m.lB, g, l)[p] / at_level(m.D, m.lD, g, l)[p];
+    }
+    __syncthreads();
+  }
+  for (int l = L - 2; l >= l0; --l) {
+    const Level<TS> lv = level(g, m, l);
+    const TS* b = at_level(m.B, m.lB, g, l);
+    TS* x = at_level(m.X, m.lX, g, l);
+    (void)gs_black_prolong(lv, b, x, (const TS*)at_level(m.X, m.lX, g, l + 1));
+    gs_half(lv, b, x, 0, false);
+  }
 }
 
 // Lumped reaction 3 r h^2 u^2 on the fine level and its restrictions; sets
@@ -416,13 +411,13 @@ __device__ int pcg(const PdeGeo& g, const MgBufs<TS>& m, double rtol, int max_it
       if (rr <= tol2) return it;
     }
     // rest of the V-cycle: black sweep, red residuals restricted, coarse
-    // levels, prolongation, post-smoothing with r . z
+    // levels, post-smoothing (the black half fused with the prolongation)
+    // with r . z
     gs_half(Ls, (const TS*)m.cr, z, 1, false);
     residual_red(Ls, (const TS*)m.cr, (const TS*)z, m.T);
     restrict_red(n, (const TS*)m.T, g.n[1], at_level(m.B, m.lB, g, 1));
-    vcycle_from(g, m, m.cr, 1, 1);
-    prolong_add(n, z, g.n[1], at_level(m.X, m.lX, g, 1));
-    double rzn = gs_half_dot(Ls, (const TS*)m.cr, z, 1);
+    vcycle_from(g, m, 1);
+    double rzn = gs_black_prolong(Ls, (const TS*)m.cr, z, (const TS*)at_level(m.X, m.lX, g, 1));
     rzn += gs_half_dot(Ls, (const TS*)m.cr, z, 0);
     rzn = block_sum1(rzn, red);
     beta = (TS)(it > 0 ? rzn / rz : 0.0);
