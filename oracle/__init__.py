@@ -11,6 +11,7 @@ Modules
 -------
 fem2d      P1 finite elements for the semilinear elliptic state equation
            (Sec. 4.2), Newton with sparse LU, QoI, adjoint gradient (Sec. 2.3).
+fem3d      Q1 finite elements for the same equation on the unit cube.
 cvar       smoothed plus function, Rockafellar-Uryasev SAA CVaR, its
            minimiser t* and gradient weights (Sec. 2.1-2.2).
 saa        per-sample (q, dq/dz) and the SAA objective + gradient.

@@ -14,18 +14,23 @@ from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
-from . import cvar, fem2d
+from . import cvar, fem2d, fem3d
 
 
-def per_sample(prob: fem2d.Problem2D, xi: np.ndarray, z: np.ndarray, ops=None,
-               rtol=1e-14):
-    """q (N,) and g (N, d_Z) for samples xi (N, K1, K1) at control z."""
-    ops = ops if ops is not None else fem2d.operators(prob)
+def _fem(prob):
+    """The finite-element module of a problem: Q1 on the cube or P1 on the square."""
+    return fem3d if isinstance(prob, fem3d.Problem3D) else fem2d
+
+
+def per_sample(prob, xi: np.ndarray, z: np.ndarray, ops=None, rtol=1e-14):
+    """q (N,) and g (N, d_Z) for samples xi (N, K1, K1[, K1]) at control z."""
+    fem = _fem(prob)
+    ops = ops if ops is not None else fem.operators(prob)
     n_s = xi.shape[0]
     q = np.empty(n_s)
     g = np.empty((n_s, prob.d_z))
     for i in range(n_s):
-        s = fem2d.solve_sample(ops, xi[i], z, rtol=rtol)
+        s = fem.solve_sample(ops, xi[i], z, rtol=rtol)
         q[i] = s["q"]
         g[i] = s["g"]
     return q, g

@@ -32,6 +32,8 @@ SEED_Z_VALID = 2310
 SEED_XI_LARGE = 2311     # surrogate SAA, N = 65536
 SEED_XI_HELDOUT = 2312   # held-out PDE samples for the surrogate error estimate
 SEED_Z_EVAL = (101, 102, 103, 104, 105)
+SEED_XI_3D = 2313        # 3D problem on 48^3, N = 256
+SEED_Z_3D = 2314         # its control (64 sources)
 
 
 def kl_coefficients(seed: int, n_samples: int, kl_per_dim: int, dim: int = 2) -> np.ndarray:
