@@ -45,6 +45,23 @@ BYTES_NEWTON_F64 = 73
 BYTES_SAMPLE = 24
 
 
+# The same for the 3D state kernel (trilinear elements, 21-point stencil with
+# one kappa per element; all multigrid levels in HBM), FP32 solver arrays:
+#   PCG iteration: A p with p = z + beta p fused (z, p, E, D read; p, q
+#   written: 6 x 4 B) + x, r update with the first Jacobi sweep (8 x 4 B) +
+#   residual (5 x 4 B) + restriction (1.25 x 4 B) + prolongation (2.1 x 4 B)
+#   + post-smoothing sweep with r.z (5 x 4 B) = 109.5 B, plus the coarse
+#   levels (53.5 B per coarse unknown, 1/7 of the fine count) 7.6 B  ~ 117 B
+#   PCG start: r.r, x = 0 and the first sweep (4 x 4 B) + one V-cycle
+#   without the CG passes (61 B)                                  =  77 B
+#   Newton step: residual 28 B + diagonals 20 B + update 20 B      =  68 B
+#   per sample: f = F z and u = 0 (16 B) + QoI (16 B)             =  32 B
+BYTES3_PCG_ITER_F32 = 117
+BYTES3_PCG_START_F32 = 77
+BYTES3_NEWTON_F64 = 68
+BYTES3_SAMPLE = 32
+
+
 def _source_hash(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -224,6 +241,66 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True):
     return out
 
 
+def bench_pde3d(saa, si, steps, warmup):
+    """3D PDE form: 48^3 trilinear elements, N = 256 samples, 64 controls,
+    FP32-DC64; objective + gradient per step, the state kernel's roofline."""
+    import numpy as np
+    import torch
+    prob = saa.problem_3d()
+    N = 256
+    xi = si.kl_coefficients(si.SEED_XI_3D, N, prob.kl_per_dim, dim=3)
+    zs = [si.control(si.SEED_Z_3D, prob.d_z)] + [si.control(s, prob.d_z) for s in si.SEED_Z_EVAL[:2]]
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    opt = saa.options(prec=saa.FP32_DC64)
+    for k in range(warmup):
+        ctx.objective_grad(zs[k % len(zs)], opt=opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ctx.objective_grad(zs[k % len(zs)], opt=opt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    topt = saa.options(prec=saa.FP32_DC64, timing=1)
+    reps, rates, launch_bytes, lins, newtons = [], [], [], [], []
+    for k in range(3):
+        rep = ctx.objective_grad(zs[k % len(zs)], opt=topt)[2]
+        st = ctx.sample_status()
+        lin_state, newton_total = int(st[2].sum()), int(st[1].sum())
+        b = prob.d_u * (BYTES3_PCG_ITER_F32 * lin_state + (BYTES3_NEWTON_F64 + BYTES3_PCG_START_F32) * newton_total +
+                        BYTES3_SAMPLE * N)
+        reps.append(rep)
+        launch_bytes.append(b)
+        lins.append(lin_state)
+        newtons.append(newton_total)
+        rates.append(b / (rep["ms_state"] * 1e-3) / 1e9)
+    J64, g64, _ = ctx.objective_grad(zs[0], opt=saa.options(prec=saa.FP64))
+    Jp, gp, rep_p = ctx.objective_grad(zs[0], opt=opt)
+    src_hash = _source_hash(["paper_2305_20053_amd/csrc/pde3.hip", "paper_2305_20053_amd/csrc/pde3.h"])
+    traffic = _traffic("saa_k_state3/fp32_dc64/n48_N256", src_hash)
+    achieved = float(np.mean(rates))
+    ctx.close()
+    return {"metric": "SAA CVaR obj+grad samples/s (3D PDE form)", "value": N * steps / wall,
+            "unit": "samples/s", "ms_per_step": 1e3 * wall / steps, "steps": steps, "warmup": warmup,
+            "dtype": "f32+f64",
+            "config": {"workload": "PDE form: 48^3 trilinear elements (117649 nodes, 103823 unknowns), N=256 KL "
+                                   "samples (10^3 modes, (pi^2|k|^2+25)^-1.5), 64 sources of width 0.08, constant "
+                                   "target 0.5, smoothed CVaR_0.95, precision fp32_dc64",
+                       "n": prob.n, "N": N, "dim": 3},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "saa_k_state3",
+                         "alg_bytes_per_launch": float(np.mean(launch_bytes)),
+                         "kernel_ms": float(np.mean([r["ms_state"] for r in reps]))},
+            "phases_ms": {"state": float(np.mean([r["ms_state"] for r in reps])),
+                          "adjoint": float(np.mean([r["ms_adjoint"] for r in reps])),
+                          "reduce": float(np.mean([r["ms_reduce"] for r in reps]))},
+            "solver": {"pcg_state_iters": int(np.mean(lins)), "newton_total": int(np.mean(newtons)),
+                       "adjoints": rep_p["n_adjoints"], "newton_max": rep_p["newton_max"]},
+            "error": {"J_rel_vs_gpu_fp64": abs(Jp - J64) / abs(J64),
+                      "grad_rel_vs_gpu_fp64": float(np.linalg.norm(gp - g64) / np.linalg.norm(g64)),
+                      "oracle_parity": "tests/test_gpu_pde3d.py"}}
+
+
 def bench_jacobian_modes(saa, si):
     """Reduced control Jacobians of 256 training samples (n = 128) with
     r_u = 16 < d_Z = 25 and r_u = 64 > d_Z: d_Z forward solves per sample
@@ -318,6 +395,7 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=1600,
                     help="epochs of the MR-DINO trained for the surrogate leg (0: random weights, no training)")
     ap.add_argument("--no-ouu", action="store_true", help="skip the OUU experiment of the surrogate leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D PDE-form leg")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -428,6 +506,8 @@ def main():
         "error": err,
     }
     ctx.close()
+    if not args.no_3d:
+        out["pde3d"] = bench_pde3d(saa, si, args.steps, args.warmup)
     if not args.no_mrdino:
         zs_box = [si.control(s, lo=Z_LO, hi=Z_HI) for s in si.SEED_Z_EVAL]
         out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs_box, value, args.train_epochs,

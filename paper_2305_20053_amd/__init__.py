@@ -194,6 +194,15 @@ def problem_medium(target: int = None) -> Problem:
     return Problem(n=128, kl_per_dim=16, target=TARGET_SIN if target is None else target)
 
 
+def problem_3d(target: int = None) -> Problem:
+    """The same equation on the unit cube: trilinear elements on 48^3 cells
+    (117649 nodes), 10^3 KL modes with amplitudes (pi^2 |k|^2 + 25)^(-1.5),
+    64 sources of width 0.08 on a 4 x 4 x 4 lattice; constant target 0.5
+    unless `target` says otherwise.  PDE form only."""
+    return Problem(dim=3, n=48, n_src_per_dim=4, src_sigma=0.08, kl_per_dim=10, kl_shift=25.0, kl_exp=1.5,
+                   target=TARGET_CONST if target is None else target)
+
+
 def ouu_options(**kw) -> COuuOptions:
     o = COuuOptions()
     _check(_load().saa_ouu_options_default(ctypes.byref(o)))
@@ -255,7 +264,7 @@ class Context:
         return self._h
 
     def set_samples(self, xi):
-        """xi: float64 CUDA tensor (N, K1, K1) of KL coefficients."""
+        """xi: float64 CUDA tensor (N, K1, K1) of KL coefficients ((N, K1, K1, K1) in 3D)."""
         xi = xi.contiguous()
         _check(self._lib.saa_set_samples(self._h, xi.shape[0], _P(_ptr(xi))))
         self.n = xi.shape[0]

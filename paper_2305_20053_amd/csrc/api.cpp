@@ -14,6 +14,7 @@
 
 #include "../../include/saa.h"
 #include "pde.h"
+#include "pde3.h"
 #include "runtime.h"
 
 // ---------------------------------------------------------------------------
@@ -50,6 +51,17 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
           const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
           hipStream_t st);
 size_t cvar_work_bytes();
+void field3(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
+            hipStream_t st);
+template <typename TS>
+void hierarchy3(const Pde3Geo& g, const double* em, double* k64, const Mg3Bufs<TS>& b, int64_t N, hipStream_t st);
+template <typename TW, typename TS>
+void state3(const Pde3Geo& g, const double* Z, const double* k64, TW* u, TW* f, const Mg3Bufs<TS>& b,
+            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, hipStream_t st);
+template <typename TW, typename TS>
+void adjoint3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* lam, const Mg3Bufs<TS>& b,
+              const SolveParams& sp, const double* q, const double* tstar, int act, double act_w, double* gout,
+              int* lin, int* flag, int* did, int64_t N, hipStream_t st);
 void risk(const double* q, const double* g, int64_t N, int dz, int kind, double eps, double kappa, double tau,
           double alpha, const double* z, int phase, double* tstar, double* out, const int* newton, const int* lin,
           const int* flag, const int* lin_adj, const int* did, void* stats, void* work, hipStream_t st);
@@ -99,6 +111,47 @@ double target_value(int target, double u_target, double x, double y) {
   }
 }
 
+// 3D tracking target: the sinusoid becomes sin(2 pi x) sin(2 pi y) sin(2 pi z);
+// the quadratic and constant targets keep their formulas.  The Q1 mass is
+// the tensor product of the 1D mass h/6 tridiag(1, 4, 1) (boundary rows
+// h/6 (2, 1)), so (M ut) and ut^T M ut are computed one direction at a time.
+void target_mass3(int n, int target, double u_target, std::vector<double>& mt, double& ctt) {
+  const int np = n + 1;
+  const size_t nn = (size_t)np * np * np;
+  std::vector<double> ut(nn), a(nn), b(nn);
+  for (int k = 0; k <= n; ++k)
+    for (int j = 0; j <= n; ++j)
+      for (int i = 0; i <= n; ++i) {
+        const double x = (double)i / n, y = (double)j / n, z = (double)k / n;
+        double v = target_value(target, u_target, x, y);
+        if (target == SAA_TARGET_SIN) v *= std::sin(2.0 * M_PI * z);
+        ut[((size_t)k * np + j) * np + i] = v;
+      }
+  const double h6 = 1.0 / (6.0 * n);
+  // apply the 1D mass along direction d (stride st) from `in` to `out`
+  auto apply = [&](const std::vector<double>& in, std::vector<double>& out, size_t st) {
+    for (size_t q = 0; q < nn; ++q) {
+      const int idx = (int)((q / st) % np);
+      const double lo = idx > 0 ? in[q - st] : 0.0, hi = idx < n ? in[q + st] : 0.0;
+      const double diag = (idx == 0 || idx == n) ? 2.0 : 4.0;
+      out[q] = h6 * (diag * in[q] + lo + hi);
+    }
+  };
+  apply(ut, a, 1);
+  apply(a, b, (size_t)np);
+  apply(b, a, (size_t)np * np);
+  mt.assign(nn, 0.0);
+  double s = 0.0;
+  for (size_t q = 0; q < nn; ++q) s += ut[q] * a[q];
+  for (int k = 1; k < n; ++k)
+    for (int j = 1; j < n; ++j)
+      for (int i = 1; i < n; ++i) {
+        const size_t q = ((size_t)k * np + j) * np + i;
+        mt[q] = a[q];
+      }
+  ctt = s;
+}
+
 }  // namespace saa_rt
 
 namespace {
@@ -133,6 +186,27 @@ int build_mg(saa_ctx* c, MgStore<TS>& m) {
   }
   saa_launch::hierarchy<TS>(c->geo, (const double*)c->em.p, (double*)c->kap.p, c->kstride, c->kchunk, m.view(),
                             c->N, c->st);
+  m.built = true;
+  return check_hip(hipGetLastError());
+}
+
+template <typename TS>
+int build_mg3(saa_ctx* c, Mg3Store<TS>& m) {
+  int rc;
+  if (!m.allocated) {
+    const size_t ls = (size_t)c->N_max * c->geo3.lstride * sizeof(TS);
+    const size_t ns = (size_t)c->N_max * c->nodes * sizeof(TS);
+    DevBuf* lv[] = {&m.E, &m.KD, &m.D, &m.X, &m.B, &m.T};
+    for (DevBuf* b : lv)
+      if ((rc = b->alloc_zero(ls, c->st))) return rc;
+    DevBuf* fv[] = {&m.cx, &m.cr, &m.cp, &m.cq};
+    for (DevBuf* b : fv)
+      if ((rc = b->alloc_zero(ns, c->st))) return rc;
+    m.allocated = true;
+  }
+  if (!c->k64.p && (rc = c->k64.alloc((size_t)c->N_max * c->nodes * sizeof(double)))) return rc;
+  if (c->N == 0) return SAA_OK;
+  saa_launch::hierarchy3<TS>(c->geo3, (const double*)c->em.p, (double*)c->k64.p, m.view(), c->N, c->st);
   m.built = true;
   return check_hip(hipGetLastError());
 }
@@ -199,6 +273,35 @@ int validate_options(const saa_options* o) {
 }
 
 // Launch the state solve for the requested PDE precision.
+int run_state3(saa_ctx* c, int prec, const double* Z, const SolveParams& sp) {
+  int rc;
+  const double* K = (const double*)c->k64.p;
+  switch (prec) {
+    case SAA_FP64:
+      if (!c->mg3_64.built && (rc = build_mg3(c, c->mg3_64))) return rc;
+      saa_launch::state3<double, double>(c->geo3, Z, (const double*)c->k64.p, (double*)c->u.p, (double*)c->f.p,
+                                         c->mg3_64.view(), sp, (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
+                                         (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32_DC64:
+      if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
+      saa_launch::state3<double, float>(c->geo3, Z, (const double*)c->k64.p, (double*)c->u.p, (double*)c->f.p,
+                                        c->mg3_32.view(), sp, (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
+                                        (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32:
+      if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
+      saa_launch::state3<float, float>(c->geo3, Z, (const double*)c->k64.p, (float*)c->u.p, (float*)c->f.p,
+                                       c->mg3_32.view(), sp, (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
+                                       (int*)c->flag.p, c->N, c->st);
+      break;
+    default:
+      return SAA_E_INVALID;
+  }
+  (void)K;
+  return check_hip(hipGetLastError());
+}
+
 int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const SolveParams& sp) {
   int rc;
   if (!c->u.p) {  // PDE-form node vectors are allocated at first use
@@ -207,6 +310,7 @@ int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const Sol
         (rc = c->lam.alloc_zero(tw, c->st)))
       return rc;
   }
+  if (c->d3) return z_stride == 0 ? run_state3(c, prec, Z, sp) : SAA_E_INVALID;
   switch (prec) {
     case SAA_FP64:
       if (!c->mg64.built && (rc = build_mg(c, c->mg64))) return rc;
@@ -232,7 +336,32 @@ int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const Sol
   return check_hip(hipGetLastError());
 }
 
+int run_adjoint3(saa_ctx* c, int prec, const SolveParams& sp, int act, double act_w, double* gout) {
+  const double* K = (const double*)c->k64.p;
+  switch (prec) {
+    case SAA_FP64:
+      saa_launch::adjoint3<double, double>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
+                                           c->mg3_64.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
+                                           (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, c->st);
+      break;
+    case SAA_FP32_DC64:
+      saa_launch::adjoint3<double, float>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
+                                          c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
+                                          (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, c->st);
+      break;
+    case SAA_FP32:
+      saa_launch::adjoint3<float, float>(c->geo3, K, (float*)c->u.p, (float*)c->f.p, (float*)c->lam.p,
+                                         c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
+                                         (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, c->st);
+      break;
+    default:
+      return SAA_E_INVALID;
+  }
+  return check_hip(hipGetLastError());
+}
+
 int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int act, double act_w, double* gout) {
+  if (c->d3) return run_adjoint3(c, prec, sp, act, act_w, gout);
   switch (prec) {
     case SAA_FP64:
       saa_launch::adjoint<double, double>(c->geo, (double*)c->FT.p, (double*)c->em.p, (double*)c->u.p,
@@ -301,13 +430,119 @@ int validate_call(saa_ctx* c, const double* z, int form, const void* model, cons
     if (model != nullptr) return SAA_E_INVALID;
     if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
   } else if (form == SAA_FORM_MRDINO) {
-    if (model == nullptr) return SAA_E_INVALID;
+    if (model == nullptr || c->d3) return SAA_E_INVALID;
     if (opt->prec != SAA_FP32 && opt->prec != SAA_BF16 && opt->prec != SAA_FP8) return SAA_E_INVALID;
     const mrdino_model* m = (const mrdino_model*)model;
     if (m->dims.d_z != c->dz || m->dims.r_m > c->K1 * c->K1) return SAA_E_MODEL;
   } else {
     return SAA_E_INVALID;
   }
+  return SAA_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Context of the 3D problem (Q1 on the cube, PDE form only).
+int ctx_create3(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx** out) {
+  // n even and halving down to a coarsest grid of at most 7 cells per side
+  if (p->n < 4 || p->n > 96 || (p->n & 1)) return SAA_E_INVALID;
+  int nc = p->n, L = 1;
+  while (nc % 2 == 0 && nc >= 4) {
+    nc /= 2;
+    ++L;
+  }
+  if (nc > 7 || L > SAA_MAX_LEVELS) return SAA_E_INVALID;
+  if (p->n_src_per_dim < 1 || p->n_src_per_dim > 4) return SAA_E_INVALID;
+  if (!is_fin(p->src_sigma) || p->src_sigma <= 0) return SAA_E_INVALID;
+  if (p->kl_per_dim < 1 || p->kl_per_dim > 16) return SAA_E_INVALID;
+  if (!is_fin(p->kl_shift) || p->kl_shift < 0 || !is_fin(p->kl_exp) || p->kl_exp <= 0) return SAA_E_INVALID;
+  if (!is_fin(p->kl_amp) || !is_fin(p->reaction) || p->reaction < 0 || !is_fin(p->u_target))
+    return SAA_E_INVALID;
+  if (p->target != SAA_TARGET_CONST && p->target != SAA_TARGET_SIN && p->target != SAA_TARGET_QUAD)
+    return SAA_E_INVALID;
+  if (N_max < 1 || N_max > (int64_t)1 << 20) return SAA_E_INVALID;
+
+  saa_ctx* c = new (std::nothrow) saa_ctx();
+  if (!c) return SAA_E_OOM;
+  c->prob = *p;
+  c->N_max = N_max;
+  c->st = (hipStream_t)hip_stream;
+  c->d3 = true;
+  const int n = p->n, np = n + 1, s = p->n_src_per_dim;
+  c->K1 = p->kl_per_dim;
+  c->n_kl = (int64_t)c->K1 * c->K1 * c->K1;
+  c->dz = s * s * s;
+  c->nodes = (int64_t)np * np * np;
+  c->d_u = (int64_t)(n - 1) * (n - 1) * (n - 1);
+  Pde3Geo& g = c->geo3;
+  g.L = L;
+  int64_t off = 0;
+  for (int l = 0, m = n; l < L; ++l, m /= 2) {
+    g.n[l] = m;
+    g.off[l] = off;
+    off += (int64_t)(m + 1) * (m + 1) * (m + 1);
+  }
+  g.lstride = off;
+  g.nodes = c->nodes;
+  g.dz = c->dz;
+  g.s = s;
+  g.h = 1.0 / n;
+  g.r = p->reaction;
+  g.src_c = g.h * g.h * g.h / (p->src_sigma * std::sqrt(2.0 * M_PI));
+
+  int rc = SAA_OK;
+  if (!rc) rc = c->S.alloc((size_t)c->K1 * np * sizeof(double));
+  if (!rc) rc = c->amp.alloc((size_t)c->n_kl * sizeof(double));
+  if (!rc) rc = c->em.alloc((size_t)N_max * c->nodes * sizeof(double));
+  if (!rc) rc = c->xi.alloc((size_t)N_max * c->n_kl * sizeof(double));
+  if (!rc) rc = c->q.alloc((size_t)N_max * sizeof(double));
+  if (!rc) rc = c->g.alloc((size_t)N_max * c->dz * sizeof(double));
+  if (!rc) rc = c->newton.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->lin.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->lin_adj.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->flag.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->did.alloc_zero((size_t)N_max * sizeof(int), c->st);
+  if (!rc) rc = c->zdev.alloc(SAA_MAX_DZ * sizeof(double));
+  if (!rc) rc = c->res.alloc_zero(RES_BYTES, c->st);
+  if (!rc) rc = c->hres.alloc(RES_BYTES);
+  if (!rc) rc = c->cwork.alloc(saa_launch::cvar_work_bytes());
+  if (!rc) rc = c->timer.create();
+  if (!rc) rc = c->mt.alloc(sizeof(double) * (size_t)c->nodes);
+  if (!rc) rc = c->G3.alloc(sizeof(double) * (size_t)s * np);
+  std::vector<double> amp, G;
+  if (!rc) {
+    saa_rt::target_mass3(n, p->target, p->u_target, c->mt_host, c->ctt);
+    g.mt = (const double*)c->mt.p;
+    g.ctt = c->ctt;
+    g.G = (const double*)c->G3.p;
+    // a_jkl = amp (pi^2 (j^2 + k^2 + l^2) + shift)^(-exp) at (j-1) K1^2 + (k-1) K1 + (l-1)
+    for (int j = 1; j <= c->K1; ++j)
+      for (int k = 1; k <= c->K1; ++k)
+        for (int l = 1; l <= c->K1; ++l)
+          amp.push_back(p->kl_amp * std::pow(M_PI * M_PI * (double)(j * j + k * k + l * l) + p->kl_shift, -p->kl_exp));
+    // one Gaussian factor per lattice coordinate c_a = (a+1)/(s+1)
+    for (int a = 0; a < s; ++a)
+      for (int i = 0; i <= n; ++i) {
+        const double d = (double)i / n - (a + 1.0) / (s + 1.0);
+        G.push_back(std::exp(-d * d / (2.0 * p->src_sigma * p->src_sigma)));
+      }
+    rc = check_hip(hipMemcpyAsync(c->mt.p, c->mt_host.data(), sizeof(double) * c->mt_host.size(),
+                                  hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipMemcpyAsync(c->amp.p, amp.data(), sizeof(double) * amp.size(), hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipMemcpyAsync(c->G3.p, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, c->st));
+  }
+  if (!rc) {
+    saa_launch::sine_table((double*)c->S.p, c->K1, n, c->st);
+    rc = check_hip(hipGetLastError());
+  }
+  if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
   return SAA_OK;
 }
 
@@ -321,6 +556,7 @@ namespace saa_rt {
 // Reduced control Jacobians of the states of the last saa_solve_states call
 // by adjoints (see saa_k_adjoint_jac): JY (device, N d_Z x r_u).
 int adjoint_jacobians(saa_ctx* c, const saa_options* opt, const double* MPhiT, int r_u, double* JY) {
+  if (c->d3) return SAA_E_INVALID;
   const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
   switch (opt->prec) {
     case SAA_FP64:
@@ -386,6 +622,7 @@ int saa_options_default(saa_options* o) {
 int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx** out) {
   if (!p || !out) return SAA_E_INVALID;
   *out = nullptr;
+  if (p->dim == 3) return ctx_create3(p, N_max, hip_stream, out);
   if (p->dim != 2) return SAA_E_INVALID;
   if (p->n < 4 || p->n > 4096 || (p->n & (p->n - 1))) return SAA_E_INVALID;
   if (p->n_src_per_dim < 1 || p->n_src_per_dim > 8) return SAA_E_INVALID;
@@ -406,6 +643,7 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   c->N_max = N_max;
   c->st = (hipStream_t)hip_stream;
   c->K1 = p->kl_per_dim;
+  c->n_kl = (int64_t)c->K1 * c->K1;
   c->dz = p->n_src_per_dim * p->n_src_per_dim;
   c->nodes = (int64_t)(p->n + 1) * (p->n + 1);
   c->d_u = (int64_t)(p->n - 1) * (p->n - 1);
@@ -506,18 +744,27 @@ int saa_ctx_dims(const saa_ctx* c, int64_t* d_u, int* d_z, int* n_kl) {
   if (!c) return SAA_E_INVALID;
   if (d_u) *d_u = c->d_u;
   if (d_z) *d_z = c->dz;
-  if (n_kl) *n_kl = c->K1 * c->K1;
+  if (n_kl) *n_kl = (int)c->n_kl;
   return SAA_OK;
 }
 
 int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
   if (!c || !xi_dev || N < 1 || N > c->N_max) return SAA_E_INVALID;
-  int rc = check_hip(hipMemcpyAsync(c->xi.p, xi_dev, sizeof(double) * N * c->K1 * c->K1,
-                                    hipMemcpyDeviceToDevice, c->st));
+  int rc = check_hip(hipMemcpyAsync(c->xi.p, xi_dev, sizeof(double) * N * c->n_kl, hipMemcpyDeviceToDevice, c->st));
   if (rc) return rc;
   c->N = N;
   c->enc_rm = -1;
   c->sg.reset();   // its encode-dependent inputs changed
+  if (c->d3) {
+    saa_launch::field3((const double*)c->xi.p, (const double*)c->S.p, (const double*)c->amp.p, (double*)c->em.p,
+                       c->K1, c->prob.n, N, c->st);
+    if ((rc = check_hip(hipGetLastError()))) return rc;
+    c->mg3_64.built = false;
+    c->mg3_32.built = false;
+    if (c->mg3_64.allocated && (rc = build_mg3(c, c->mg3_64))) return rc;
+    if (c->mg3_32.allocated && (rc = build_mg3(c, c->mg3_32))) return rc;
+    return check_hip(hipStreamSynchronize(c->st));
+  }
   saa_launch::field((const double*)c->xi.p, (const double*)c->S.p, (const double*)c->amp.p, (double*)c->em.p,
                     c->K1, c->prob.n, N, c->st);
   rc = check_hip(hipGetLastError());
@@ -712,7 +959,7 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
 
 int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
                      double* dudz_dev, saa_report* rep) {
-  if (!c || !Z_dev || !u_dev) return SAA_E_INVALID;
+  if (!c || !Z_dev || !u_dev || c->d3) return SAA_E_INVALID;
   int rc = validate_options(opt);
   if (rc) return rc;
   if (c->N < 1) return SAA_E_INVALID;

@@ -8,6 +8,7 @@
 
 #include "../../include/saa.h"
 #include "pde.h"
+#include "pde3.h"
 #include "runtime.h"
 
 namespace saa_rt {
@@ -15,6 +16,10 @@ namespace saa_rt {
 // (M u_target) at the interior nodes (node layout) and u_target^T M u_target
 // for a target kind of saa_problem on the n x n mesh.
 void target_mass(int n, int target, double u_target, std::vector<double>& mt, double& ctt);
+
+// (M u_target) at the interior nodes and u_target^T M u_target on the
+// (n+1)^3 grid (Q1 consistent mass).
+void target_mass3(int n, int target, double u_target, std::vector<double>& mt, double& ctt);
 
 // Reduced control Jacobians by adjoints for the states of the last
 // saa_solve_states call; JY: device, (N d_Z) x r_u.
@@ -29,6 +34,27 @@ struct MgStore {
     MgBufs<TS> m;
     m.WE = (TS*)WE.p;
     m.WN = (TS*)WN.p;
+    m.KD = (TS*)KD.p;
+    m.D = (TS*)D.p;
+    m.X = (TS*)X.p;
+    m.B = (TS*)B.p;
+    m.T = (TS*)T.p;
+    m.cx = (TS*)cx.p;
+    m.cr = (TS*)cr.p;
+    m.cp = (TS*)cp.p;
+    m.cq = (TS*)cq.p;
+    return m;
+  }
+};
+
+template <typename TS>
+struct Mg3Store {
+  DevBuf E, KD, D, X, B, T, cx, cr, cp, cq;
+  bool allocated = false;
+  bool built = false;
+  Mg3Bufs<TS> view() const {
+    Mg3Bufs<TS> m;
+    m.E = (TS*)E.p;
     m.KD = (TS*)KD.p;
     m.D = (TS*)D.p;
     m.X = (TS*)X.p;
@@ -119,7 +145,14 @@ struct saa_ctx {
   int64_t N = 0;
   hipStream_t st = nullptr;
   PdeGeo geo{};
+  bool d3 = false;                    // Q1 on the cube (PDE form only)
+  Pde3Geo geo3{};
+  saa_rt::DevBuf k64;                 // 3D: fine element kappas in FP64, per sample
+  saa_rt::DevBuf G3;                  // 3D: separable source factor table s x (n+1)
+  saa_rt::Mg3Store<double> mg3_64;
+  saa_rt::Mg3Store<float> mg3_32;
   int K1 = 0, dz = 0;
+  int64_t n_kl = 0;                   // K1^dim KL coefficients per sample
   int64_t nodes = 0, d_u = 0;
   saa_rt::DevBuf FT, S, amp, em, xi, kap;
   saa_rt::DevBuf mt;                  // (M u_target) at interior nodes (node layout), FP64

@@ -67,6 +67,22 @@ def test_ctx_create_rejects_bad_problem_before_device_work(field, value):
     assert st == saa.SAA_E_INVALID and not h.value
 
 
+@pytest.mark.parametrize("field,value", [("n", 47), ("n", 36), ("n", 98), ("n", 2), ("n_src_per_dim", 5),
+                                         ("kl_per_dim", 17), ("kl_per_dim", 0), ("src_sigma", -0.1),
+                                         ("target", 7), ("dim", 4)])
+def test_ctx_create_rejects_bad_3d_problem_before_device_work(field, value):
+    """3D: n even in [4, 96] halving to a coarsest grid of at most 7 cells
+    (n = 36 stops at 9), at most 4 sources per dimension (64 controls), K1 in
+    1..16."""
+    p = saa.problem_3d()
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    st = saa.lib().saa_ctx_create(ctypes.byref(p.c_struct()), 16, None, ctypes.byref(h))
+    assert st == saa.SAA_E_INVALID and not h.value
+    st = saa.lib().saa_ctx_create(ctypes.byref(saa.problem_3d().c_struct()), (1 << 20) + 1, None, ctypes.byref(h))
+    assert st == saa.SAA_E_INVALID and not h.value
+
+
 def test_null_arguments_rejected():
     lib = saa.lib()
     p = saa.problem_small().c_struct()

@@ -1,0 +1,168 @@
+"""GPU parity of the 3D PDE form (trilinear elements on the unit cube)
+against the CPU FP64 oracle, through the C ABI.
+
+Tolerances as in 2D (relative, 2-norm): FP64 and FP32-in-FP64-defect-
+correction paths 1e-9 on J, grad J and each dq_i/dz, q_i to 1e-12; pure FP32
+1e-4 (q_i 1e-5).  Sizes: n = 8 (levels 8, 4, 2), n = 12 (coarsest grid of 3
+cells, 64 controls), n = 16 (coarsest 2, quadratic target), and the full
+workload n = 48, N = 256 (levels 48 .. 3), there on the sampled outputs the
+oracle stores in tests/golden/pde3d_n48_samples.json and on properties that
+hold at any size.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2305_20053_amd as saa
+import saa_inputs as si
+from oracle import fem3d, saa as osaa
+
+pytestmark = pytest.mark.gpu
+
+TOL = {saa.FP64: 1e-9, saa.FP32_DC64: 1e-9, saa.FP32: 1e-4}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pde3d_n48_samples.json")
+
+
+def problem3(n, s=2, K1=3, **kw) -> saa.Problem:
+    return saa.Problem(dim=3, n=n, n_src_per_dim=s, src_sigma=0.08, kl_per_dim=K1, kl_shift=25.0, kl_exp=1.5,
+                       **kw)
+
+
+def _oprob(p: saa.Problem) -> fem3d.Problem3D:
+    return fem3d.Problem3D(n=p.n, n_src_per_dim=p.n_src_per_dim, src_sigma=p.src_sigma, kl_per_dim=p.kl_per_dim,
+                           kl_shift=p.kl_shift, kl_exp=p.kl_exp, kl_amp=p.kl_amp, reaction=p.reaction,
+                           u_target=p.u_target, target=p.target)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _check_per_sample(q, g, ref, prec):
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= (1e-12 if prec != saa.FP32 else 1e-5)
+    for i in range(len(q)):
+        assert _rel(g[i], ref["g"][i]) <= TOL[prec], (i, _rel(g[i], ref["g"][i]))
+
+
+@pytest.fixture(scope="module")
+def small3(gpu_lib):
+    prob = problem3(8, s=2, K1=3, kl_amp=20.0, target=saa.TARGET_SIN)
+    N = 12
+    xi = si.kl_coefficients(2401, N, 3, dim=3)
+    z = si.control(2402, prob.d_z, lo=-1.0, hi=3.0)
+    ref = osaa.objective_grad(_oprob(prob), xi, z, beta=0.8)
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    return prob, xi, z, ref, ctx
+
+
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64, saa.FP32])
+def test_small3_per_sample(small3, prec):
+    prob, xi, z, ref, ctx = small3
+    print(f"case 3D n=8 per_sample prec={prec}", flush=True)
+    assert ctx.d_z == 8 and ctx.d_u == 7 ** 3
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=prec))
+    _check_per_sample(q, g, ref, prec)
+    assert rep["n_unconverged"] == 0 and rep["n_adjoints"] == len(xi)
+
+
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64, saa.FP32])
+def test_small3_objective(small3, prec):
+    prob, xi, z, ref, ctx = small3
+    print(f"case 3D n=8 objective prec={prec}", flush=True)
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=prec, beta=0.8))
+    assert abs(J - ref["J"]) / abs(ref["J"]) <= TOL[prec]
+    assert _rel(grad, ref["grad"]) <= TOL[prec]
+    if prec != saa.FP32:
+        assert abs(rep["t_star"] - ref["t"]) <= 1e-12 * abs(ref["t"])
+    assert rep["n_unconverged"] == 0
+    assert 2 <= rep["newton_max"] <= 8
+
+
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64])
+def test_64_controls_odd_coarsest_grid(gpu_lib, prec):
+    """n = 12 (levels 12, 6, 3: the coarsest grid has 8 unknowns and odd
+    size), 4 x 4 x 4 sources, 4^3 KL modes, constant target."""
+    prob = problem3(12, s=4, K1=4, kl_amp=10.0)
+    print(f"case 3D n=12 s=4 prec={prec}", flush=True)
+    xi = si.kl_coefficients(2403, 5, 4, dim=3)
+    z = si.control(2404, prob.d_z)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 5)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=prec))
+    _check_per_sample(q, g, ref, prec)
+    J, grad, _ = ctx.objective_grad(z, opt=saa.options(prec=prec))
+    assert abs(J - ref["J"]) / abs(ref["J"]) <= TOL[prec] and _rel(grad, ref["grad"]) <= TOL[prec]
+
+
+def test_quadratic_target_coarsest_single_unknown(gpu_lib):
+    """n = 16 (levels down to 2 cells: one unknown), 27 controls, the
+    quadratic target 4 y (1 - y), FP32-DC64."""
+    prob = problem3(16, s=3, K1=5, kl_amp=10.0, target=saa.TARGET_QUAD)
+    print("case 3D n=16 quad", flush=True)
+    xi = si.kl_coefficients(2405, 3, 5, dim=3)
+    z = si.control(2406, prob.d_z, lo=-2.0, hi=2.0)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 3)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    q, g, _ = ctx.per_sample(z, opt=saa.options(prec=saa.FP32_DC64))
+    _check_per_sample(q, g, ref, saa.FP32_DC64)
+
+
+@pytest.fixture(scope="module")
+def full3(gpu_lib):
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    prob = saa.problem_3d()
+    assert prob.n == gold["n"] and prob.kl_per_dim == gold["kl_per_dim"]
+    xi = si.kl_coefficients(gold["seed_xi"], gold["N"], prob.kl_per_dim, dim=3)
+    z = si.control(gold["seed_z"], prob.d_z)
+    ctx = saa.Context(prob, gold["N"])
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    return prob, z, gold, ctx
+
+
+def test_full_size_sampled_outputs(full3):
+    """The workload configuration (48^3, N = 256, FP32-DC64, the launch the
+    benchmark times): samples 0 and 255 against stored oracle values."""
+    prob, z, gold, ctx = full3
+    print("case 3D n=48 N=256 sampled", flush=True)
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP32_DC64))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    for key, ref in gold["samples"].items():
+        i = int(key)
+        assert abs(q[i] - ref["q"]) <= 1e-12 * abs(ref["q"]), (i, q[i], ref["q"])
+        assert _rel(g[i], ref["g"]) <= 1e-9, (i, _rel(g[i], ref["g"]))
+    assert rep["n_unconverged"] == 0
+
+
+def test_full_size_precisions_and_taylor(full3):
+    """At full size: FP32-DC64 and FP64 objectives agree to 1e-9, and the
+    FP64 gradient passes a Taylor test (central differences of J along a
+    random direction shrink the mismatch at second order)."""
+    prob, z, gold, ctx = full3
+    print("case 3D n=48 N=256 precisions", flush=True)
+    J64, g64, rep64 = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64))
+    J32, g32, rep32 = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32_DC64))
+    assert abs(J32 - J64) <= 1e-9 * abs(J64) and _rel(g32, g64) <= 1e-9
+    assert rep64["n_unconverged"] == 0 and rep32["n_unconverged"] == 0
+    d = np.random.default_rng(2407).standard_normal(prob.d_z)
+    d /= np.linalg.norm(d)
+    errs = []
+    for h in (0.2, 0.1):
+        Jp, _, _ = ctx.objective_grad(z + h * d, opt=saa.options(prec=saa.FP64))
+        Jm, _, _ = ctx.objective_grad(z - h * d, opt=saa.options(prec=saa.FP64))
+        errs.append(abs((Jp - Jm) / (2 * h) - g64 @ d))
+    print("taylor", errs, g64 @ d)
+    assert errs[1] <= 0.35 * errs[0] or errs[1] <= 1e-10 * abs(g64 @ d)
+
+
+def test_3d_rejects_surrogate_and_training_calls(small3):
+    prob, xi, z, ref, ctx = small3
+    with pytest.raises(saa.SaaError):
+        ctx.solve_states(torch.zeros((len(xi), prob.d_z), dtype=torch.float64, device="cuda"))
