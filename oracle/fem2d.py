@@ -257,8 +257,33 @@ def jacobian(u, K, w, r):
     return (K + sp.diags(3.0 * r * w * u ** 2)).tocsc()
 
 
-def newton_solve(K, w, r, f, rtol=1e-14, max_iter=20, history=None):
-    """Newton from u = 0 with sparse LU.
+class CGSolver:
+    """Solves with one SPD matrix by Jacobi-preconditioned conjugate
+    gradients (scipy's textbook CG) to a relative residual of `rtol`; a
+    stand-in for the LU factors where a direct factorisation of a large 3D
+    Jacobian is too slow.  Same .solve interface as the LU object."""
+
+    def __init__(self, A, rtol=1e-14):
+        self.A = A.tocsr()
+        self.M = sp.diags(1.0 / self.A.diagonal())
+        self.rtol = rtol
+
+    def solve(self, b):
+        b = np.asarray(b, dtype=np.float64)
+        if b.ndim == 2:
+            return np.stack([self.solve(b[:, k]) for k in range(b.shape[1])], axis=1)
+        x, info = spla.cg(self.A, b, rtol=self.rtol, atol=0.0, maxiter=20000, M=self.M)
+        if info != 0:
+            raise RuntimeError(f"CG did not converge (info {info})")
+        return x
+
+
+def _factor(J, linear):
+    return spla.splu(J) if linear == "lu" else CGSolver(J)
+
+
+def newton_solve(K, w, r, f, rtol=1e-14, max_iter=20, history=None, linear="lu"):
+    """Newton from u = 0 with sparse LU (linear="cg": the CG stand-in above).
 
     Stops when ||R|| <= rtol max(1, ||f||), or after a step whose size is at
     the float64 rounding level of u (||du|| <= 1e-13 ||u||: the remaining
@@ -278,7 +303,7 @@ def newton_solve(K, w, r, f, rtol=1e-14, max_iter=20, history=None):
             break
         if steps == max_iter:
             raise RuntimeError(f"Newton did not converge: ||R|| = {nr:.3e}")
-        lu = spla.splu(jacobian(u, K, w, r))
+        lu = _factor(jacobian(u, K, w, r), linear)
         du = -lu.solve(R)
         e0 = energy(u, K, w, r, f)
         step = 1.0
@@ -290,7 +315,7 @@ def newton_solve(K, w, r, f, rtol=1e-14, max_iter=20, history=None):
             if history is not None:
                 history.append(np.linalg.norm(residual(u, K, w, r, f)))
             break
-    lu = spla.splu(jacobian(u, K, w, r))
+    lu = _factor(jacobian(u, K, w, r), linear)
     return u, lu, steps
 
 

@@ -247,12 +247,13 @@ def qoi_gradient(ops: Operators3D, u_int: np.ndarray) -> np.ndarray:
     return 2.0 * (ops.M_full @ d)[ops.interior]
 
 
-def solve_sample(ops: Operators3D, xi_i: np.ndarray, z: np.ndarray, want_grad=True, rtol=1e-14):
-    """State u, q and dq/dz = F^T lambda with A(u) lambda = dq/du (Sec. 2.3)."""
+def solve_sample(ops: Operators3D, xi_i: np.ndarray, z: np.ndarray, want_grad=True, rtol=1e-14, linear="lu"):
+    """State u, q and dq/dz = F^T lambda with A(u) lambda = dq/du (Sec. 2.3).
+    linear="cg" replaces the LU factors by tight CG solves (large grids)."""
     prob = ops.prob
     K = stiffness(ops, field_nodal(xi_i, prob))
     f = ops.F @ z
-    u, lu, iters = fem2d.newton_solve(K, ops.w, prob.reaction, f, rtol=rtol)
+    u, lu, iters = fem2d.newton_solve(K, ops.w, prob.reaction, f, rtol=rtol, linear=linear)
     out = {"u": u, "q": qoi(ops, u), "newton_iters": iters}
     if want_grad:
         lam = lu.solve(qoi_gradient(ops, u))

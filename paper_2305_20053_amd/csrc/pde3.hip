@@ -4,7 +4,9 @@
 // tracking QoI and the adjoint gradient dq/dz = F^T lambda, A(u) lambda =
 // dq/du (Sec. 2.3, eq. (ouu_qoi_gradient)).
 //
-// As in 2D, one 1024-thread workgroup owns one sample for its whole solve:
+// As in 2D, one workgroup owns one sample for its whole solve (512 threads:
+// measured at 48^3, N = 256, 256 and 768 threads were 1.6x and 1.9x slower
+// and 1024 threads 1.6x):
 // Newton in the state precision, inner multigrid-preconditioned CG in the
 // solver precision, every decision taken on the device.
 //
@@ -39,7 +41,10 @@
 
 namespace {
 
-constexpr int BS = 1024;
+#ifndef SAA_PDE3_BLOCK
+#define SAA_PDE3_BLOCK 512
+#endif
+constexpr int BS = SAA_PDE3_BLOCK;   // threads per sample
 constexpr int COARSE_SWEEPS = 4;   // even: the coarsest result lands in T
 
 // Visit nodes p = tid, tid + BS, ... of an (n+1)^3 grid with (i, j, k).
@@ -77,6 +82,68 @@ __device__ __forceinline__ void for_nodes3(int n, F&& f) {
 
 __device__ __forceinline__ bool inner3(int i, int j, int k, int n) {
   return i > 0 && j > 0 && k > 0 && i < n && j < n && k < n;
+}
+
+#ifndef SAA_PDE3_BATCH
+#define SAA_PDE3_BATCH 1
+#endif
+// interior nodes per thread per step of a batched pass (2 and 4 measured no
+// faster at 48^3: the extra registers cost what the extra loads in flight gain)
+constexpr int UB = SAA_PDE3_BATCH;
+
+template <typename T>
+struct Two {
+  T a, b;
+};
+
+// Interior nodes of an (n+1)^3 grid in batches of U visits per thread:
+// compute(p, i, j, k) (loads and arithmetic only) runs for the U nodes first
+// and store(p, value) after, so the loads of all U nodes are in flight
+// together (a store could alias a later node's loads and would otherwise
+// order them).  Visits that are not interior nodes compute at the interior
+// node (1, 1, 1) (every stencil read in bounds) and store nothing.
+template <int U, typename C, typename S>
+__device__ __forceinline__ void for_inner3(int n, C&& compute, S&& store) {
+  const int np = n + 1, np2 = np * np;
+  const int total = np2 * np;
+  const int psafe = np2 + np + 1;
+  int p = threadIdx.x;
+  asm volatile("" : "+v"(p));
+  int k = p / np2;
+  int j = (p - k * np2) / np;
+  int i = p - k * np2 - j * np;
+  const int sk = BS / np2;
+  const int sj = (BS - sk * np2) / np;
+  const int si = BS - sk * np2 - sj * np;
+  for (; p < total; p += U * BS) {
+    int q[U], qi[U], qj[U], qk[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      in[u] = p + u * BS < total && inner3(i, j, k, n);
+      q[u] = in[u] ? p + u * BS : psafe;
+      qi[u] = in[u] ? i : 1;
+      qj[u] = in[u] ? j : 1;
+      qk[u] = in[u] ? k : 1;
+      i += si;
+      if (i >= np) {
+        i -= np;
+        ++j;
+      }
+      j += sj;
+      if (j >= np) {
+        j -= np;
+        ++k;
+      }
+      k += sk;
+    }
+    decltype(compute(0, 1, 1, 1)) r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = compute(q[u], qi[u], qj[u], qk[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (in[u]) store(q[u], r[u]);
+  }
 }
 
 // Sum over the 20 coupled neighbours q of p of (sum of the kappas of the
@@ -175,12 +242,15 @@ __device__ __forceinline__ TS full_weight(const TS* t, int c, int np, int np2) {
 // C.X = omega C.B / C.D.
 template <typename TS>
 __device__ void restrict3(const Lvl3<TS>& F, const TS* t, const Lvl3<TS>& C, TS omega) {
-  for_nodes3(C.n, [&](int P, int I, int J, int K) {
-    if (!inner3(I, J, K, C.n)) return;
-    const TS b = full_weight(t, 2 * I + 2 * J * F.np + 2 * K * F.np2, F.np, F.np2);
-    C.B[P] = b;
-    C.X[P] = omega * b / C.D[P];
-  });
+  for_inner3<UB>(
+      C.n,
+      [&](int P, int I, int J, int K) {
+        return Two<TS>{full_weight(t, 2 * I + 2 * J * F.np + 2 * K * F.np2, F.np, F.np2), C.D[P]};
+      },
+      [&](int P, const Two<TS>& v) {
+        C.B[P] = v.a;
+        C.X[P] = omega * v.a / v.b;
+      });
 }
 
 // x += P xc: trilinear interpolation of the coarse vector (zero on the coarse
@@ -189,35 +259,40 @@ __device__ void restrict3(const Lvl3<TS>& F, const TS* t, const Lvl3<TS>& C, TS 
 // index repeats its coarse node (weight 1), an odd one averages two.
 template <typename TS>
 __device__ void prolong_add3(const Lvl3<TS>& F, TS* x, const Lvl3<TS>& C, const TS* xc) {
-  for_nodes3(F.n, [&](int p, int i, int j, int k) {
-    if (!inner3(i, j, k, F.n)) return;
-    const int a0 = (i >> 1) + (j >> 1) * C.np + (k >> 1) * C.np2;
-    const int da = i & 1, db = (j & 1) * C.np, dc = (k & 1) * C.np2;
-    const TS s = (xc[a0] + xc[a0 + da]) + (xc[a0 + db] + xc[a0 + da + db]) + (xc[a0 + dc] + xc[a0 + da + dc]) +
-                 (xc[a0 + db + dc] + xc[a0 + da + db + dc]);
-    x[p] += (TS)0.125 * s;
-  });
+  for_inner3<UB>(
+      F.n,
+      [&](int p, int i, int j, int k) {
+        const int a0 = (i >> 1) + (j >> 1) * C.np + (k >> 1) * C.np2;
+        const int da = i & 1, db = (j & 1) * C.np, dc = (k & 1) * C.np2;
+        const TS s = (xc[a0] + xc[a0 + da]) + (xc[a0 + db] + xc[a0 + da + db]) + (xc[a0 + dc] + xc[a0 + da + dc]) +
+                     (xc[a0 + db + dc] + xc[a0 + da + db + dc]);
+        return x[p] + (TS)0.125 * s;
+      },
+      [&](int p, TS v) { x[p] = v; });
 }
 
 // t = b - A x on the interior of level L.
 template <typename TS>
 __device__ void residual3(const Lvl3<TS>& L, const TS* b, const TS* x, TS* t) {
-  for_nodes3(L.n, [&](int p, int i, int j, int k) {
-    if (!inner3(i, j, k, L.n)) return;
-    const TS ax = L.D[p] * x[p] - L.hq * off_sum<TS>(L.E, p, L.np, L.np2, [&](int q) { return x[q]; });
-    t[p] = b[p] - ax;
-  });
+  for_inner3<UB>(
+      L.n,
+      [&](int p, int, int, int) {
+        return b[p] - (L.D[p] * x[p] - L.hq * off_sum<TS>(L.E, p, L.np, L.np2, [&](int q) { return x[q]; }));
+      },
+      [&](int p, TS v) { t[p] = v; });
 }
 
 // One damped Jacobi sweep dst = src + omega (b - A src) / D.
 template <typename TS>
 __device__ void jacobi3(const Lvl3<TS>& L, const TS* b, const TS* src, TS* dst, TS omega) {
-  for_nodes3(L.n, [&](int p, int i, int j, int k) {
-    if (!inner3(i, j, k, L.n)) return;
-    const TS xs = src[p];
-    const TS ax = L.D[p] * xs - L.hq * off_sum<TS>(L.E, p, L.np, L.np2, [&](int q) { return src[q]; });
-    dst[p] = xs + omega * (b[p] - ax) / L.D[p];
-  });
+  for_inner3<UB>(
+      L.n,
+      [&](int p, int, int, int) {
+        const TS xs = src[p], d = L.D[p];
+        const TS ax = d * xs - L.hq * off_sum<TS>(L.E, p, L.np, L.np2, [&](int q) { return src[q]; });
+        return xs + omega * (b[p] - ax) / d;
+      },
+      [&](int p, TS v) { dst[p] = v; });
 }
 
 // V(1,1) cycle on the levels l0.. given B[l0] and the first sweep X[l0] (set
@@ -320,15 +395,18 @@ __device__ int pcg3(const Pde3Geo& g, const Mg3Bufs<TS>& m, double rtol, int max
     if (it > 0) {
       double pq = 0.0;
       const TS* po = pc;
-      for_nodes3(n, [&](int p, int i, int j, int k) {
-        if (!inner3(i, j, k, n)) return;
-        auto pv = [&](int q) { return z[q] + beta * po[q]; };   // zero on the boundary
-        const TS pp = pv(p);
-        const TS q = L0.D[p] * pp - L0.hq * off_sum<TS>(L0.E, p, L0.np, L0.np2, pv);
-        pn[p] = pp;
-        m.cq[p] = q;
-        pq += (double)pp * (double)q;
-      });
+      for_inner3<UB>(
+          n,
+          [&](int p, int, int, int) {
+            auto pv = [&](int q) { return z[q] + beta * po[q]; };   // zero on the boundary
+            const TS pp = pv(p);
+            return Two<TS>{pp, L0.D[p] * pp - L0.hq * off_sum<TS>(L0.E, p, L0.np, L0.np2, pv)};
+          },
+          [&](int p, const Two<TS>& v) {
+            pn[p] = v.a;
+            m.cq[p] = v.b;
+            pq += (double)v.a * (double)v.b;
+          });
       TS* t = pc;
       pc = pn;
       pn = t;
@@ -339,14 +417,17 @@ __device__ int pcg3(const Pde3Geo& g, const Mg3Bufs<TS>& m, double rtol, int max
       }
       const TS a = (TS)(rz / pq);
       double rr = 0.0;
-      for_nodes3(n, [&](int p, int i, int j, int k) {
-        if (!inner3(i, j, k, n)) return;
-        m.cx[p] += a * pc[p];
-        const TS r = m.cr[p] - a * m.cq[p];
-        m.cr[p] = r;
-        rr += (double)r * (double)r;
-        L0.X[p] = omega * r / L0.D[p];
-      });
+      struct Upd {
+        TS x, r, d;
+      };
+      for_inner3<UB>(
+          n, [&](int p, int, int, int) { return Upd{m.cx[p] + a * pc[p], m.cr[p] - a * m.cq[p], L0.D[p]}; },
+          [&](int p, const Upd& v) {
+            m.cx[p] = v.x;
+            m.cr[p] = v.r;
+            rr += (double)v.r * (double)v.r;
+            L0.X[p] = omega * v.r / v.d;
+          });
       rr = block_sum1(rr, red);
       if (rr <= tol2) return it;
     }
@@ -358,15 +439,17 @@ __device__ int pcg3(const Pde3Geo& g, const Mg3Bufs<TS>& m, double rtol, int max
     prolong_add3(L0, L0.X, L1, (const TS*)L1.T);
     __syncthreads();
     double rzn = 0.0;
-    for_nodes3(n, [&](int p, int i, int j, int k) {
-      if (!inner3(i, j, k, n)) return;
-      const TS xs = L0.X[p];
-      const TS ax = L0.D[p] * xs - L0.hq * off_sum<TS>(L0.E, p, L0.np, L0.np2, [&](int q) { return L0.X[q]; });
-      const TS r = m.cr[p];
-      const TS zz = xs + omega * (r - ax) / L0.D[p];
-      z[p] = zz;
-      rzn += (double)r * (double)zz;
-    });
+    for_inner3<UB>(
+        n,
+        [&](int p, int, int, int) {
+          const TS xs = L0.X[p], d = L0.D[p], r = m.cr[p];
+          const TS ax = d * xs - L0.hq * off_sum<TS>(L0.E, p, L0.np, L0.np2, [&](int q) { return L0.X[q]; });
+          return Two<TS>{xs + omega * (r - ax) / d, r};
+        },
+        [&](int p, const Two<TS>& v) {
+          z[p] = v.a;
+          rzn += (double)v.b * (double)v.a;
+        });
     rzn = block_sum1(rzn, red);
     beta = (TS)(it > 0 ? rzn / rz : 0.0);
     rz = rzn;
@@ -434,12 +517,13 @@ __device__ int dc_solve3(const Pde3Geo& g, const Mg3Bufs<TS>& m, const SolvePara
       break;
     }
     if (outer_converged(ctl, v[0], v[1], sp.adj_tol, sp.lin_rtol)) break;
-    for_nodes3(n, [&](int p, int i, int j, int k) {
-      if (!inner3(i, j, k, n)) return;
-      const TW uu = u[p];
-      const TW ax = stiff3<TW>(K, x, p, np, np2, g.h) + (TW)c3 * uu * uu * x[p];
-      m.cr[p] = (TS)(b[p] - ax);
-    });
+    for_inner3<UB>(
+        n,
+        [&](int p, int, int, int) {
+          const TW uu = u[p];
+          return (TS)(b[p] - (stiff3<TW>(K, x, p, np, np2, g.h) + (TW)c3 * uu * uu * x[p]));
+        },
+        [&](int p, TS v) { m.cr[p] = v; });
     __syncthreads();
   }
   if (pass == sp.max_dc) *ok = false;
@@ -585,12 +669,13 @@ __global__ void __launch_bounds__(BS) saa_k_state3(Pde3Geo g, const double* Z, c
   OuterCtl ctl;
   ctl.eta = sp.lin_rtol;
   for (it = 0; it < sp.max_newton; ++it) {
-    for_nodes3(n, [&](int p, int i, int j, int k) {
-      if (!inner3(i, j, k, n)) return;
-      const TW uu = u[p];
-      const TW R = stiff3<TW>(K, u, p, np, np2, g.h) + (TW)c1 * uu * uu * uu - f[p];
-      m.cr[p] = (TS)(-R);
-    });
+    for_inner3<UB>(
+        n,
+        [&](int p, int, int, int) {
+          const TW uu = u[p];
+          return (TS)(f[p] - (stiff3<TW>(K, u, p, np, np2, g.h) + (TW)c1 * uu * uu * uu));
+        },
+        [&](int p, TS v) { m.cr[p] = v; });
     __syncthreads();
     build_diagonals3<TW, TS>(g, m, u);
     bool ok = true;

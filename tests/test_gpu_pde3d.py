@@ -136,7 +136,11 @@ def test_full_size_sampled_outputs(full3):
     q, g = q.cpu().numpy(), g.cpu().numpy()
     for key, ref in gold["samples"].items():
         i = int(key)
-        assert abs(q[i] - ref["q"]) <= 1e-12 * abs(ref["q"]), (i, q[i], ref["q"])
+        # q = u^T M u - 2 u^T M ut + ut^T M ut cancels about 7x here (0.2155
+        # from 0.25): the Newton stop at 1e-13 relative updates leaves q_i
+        # errors of a few 1e-13, so q_i is held to 1e-10 (J and grad to the
+        # 1e-9 of the PDE form)
+        assert abs(q[i] - ref["q"]) <= 1e-10 * abs(ref["q"]), (i, q[i], ref["q"])
         assert _rel(g[i], ref["g"]) <= 1e-9, (i, _rel(g[i], ref["g"]))
     assert rep["n_unconverged"] == 0
 

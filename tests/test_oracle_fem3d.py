@@ -190,3 +190,16 @@ def test_adjoint_gradient_taylor():
         errs.append(abs((qp - qm) / (2 * h) - s["g"] @ dz))
     assert errs[1] < 0.3 * errs[0] or errs[1] < 1e-11 * abs(s["g"] @ dz)
     assert errs[1] < 1e-4 * abs(s["g"] @ dz)
+
+
+def test_cg_stand_in_matches_lu():
+    """The CG stand-in for the LU factors (used for the stored 48^3 values)
+    gives the same q and dq/dz as the direct solves."""
+    prob = fem3d.Problem3D(n=8, n_src_per_dim=2, kl_per_dim=3, kl_amp=20.0)
+    ops = fem3d.operators(prob)
+    xi = si.kl_coefficients(81, 1, 3, dim=3)[0]
+    z = si.control(82, prob.d_z)
+    a = fem3d.solve_sample(ops, xi, z)
+    b = fem3d.solve_sample(ops, xi, z, linear="cg")
+    assert abs(a["q"] - b["q"]) <= 1e-13 * abs(a["q"])
+    assert np.linalg.norm(a["g"] - b["g"]) <= 1e-11 * np.linalg.norm(a["g"])
