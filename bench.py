@@ -274,6 +274,7 @@ def bench_pde3d(saa, si, steps, warmup):
         lins.append(lin_state)
         newtons.append(newton_total)
         rates.append(b / (rep["ms_state"] * 1e-3) / 1e9)
+    bs_state, bs_adj = ctx.launch3(saa.FP32_DC64)
     J64, g64, _ = ctx.objective_grad(zs[0], opt=saa.options(prec=saa.FP64))
     Jp, gp, rep_p = ctx.objective_grad(zs[0], opt=opt)
     src_hash = _source_hash(["paper_2305_20053_amd/csrc/pde3.hip", "paper_2305_20053_amd/csrc/pde3.h"])
@@ -286,7 +287,8 @@ def bench_pde3d(saa, si, steps, warmup):
             "config": {"workload": "PDE form: 48^3 trilinear elements (117649 nodes, 103823 unknowns), N=256 KL "
                                    "samples (10^3 modes, (pi^2|k|^2+25)^-1.5), 64 sources of width 0.08, constant "
                                    "target 0.5, smoothed CVaR_0.95, precision fp32_dc64",
-                       "n": prob.n, "N": N, "dim": 3},
+                       "n": prob.n, "N": N, "dim": 3,
+                       "threads_per_sample": {"state": bs_state, "adjoint": bs_adj, "chosen_by": "timing (saa_ctx_launch3)"}},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "saa_k_state3",
                          "alg_bytes_per_launch": float(np.mean(launch_bytes)),

@@ -82,11 +82,24 @@ enum { SAA_FP64 = 0, SAA_FP32 = 1, SAA_FP32_DC64 = 2, SAA_BF16 = 3, SAA_FP8 = 4 
  * exp(-|x - x_k|^2 / (2 sigma^2)) sit on the interior lattice
  * x_k = ((a+1)/(s+1), (b+1)/(s+1)), k = s b + a, s = n_src_per_dim.
  * The log-coefficient is m(x) = sum_{j,k=1..K1} a_jk xi_jk sin(j pi x) sin(k pi y)
- * with a_jk = kl_amp (pi^2 (j^2 + k^2) + kl_shift)^(-kl_exp). */
+ * with a_jk = kl_amp (pi^2 (j^2 + k^2) + kl_shift)^(-kl_exp).
+ *
+ * dim = 3: the same equation on the unit cube with trilinear (Q1) elements
+ * on n^3 cells (n even, 4 <= n <= 96, halving to a coarsest grid of at most
+ * 7 cells: 48, 32, 40, 56 ... are accepted, 36 is not), sources on the
+ * s x s x s lattice ((a+1)/(s+1), (b+1)/(s+1), (c+1)/(s+1)), k = a + s b +
+ * s^2 c, d_Z = s^3 (s in 1..4), field sum_{j,k,l} a_jkl xi_jkl sin sin sin
+ * with a_jkl = kl_amp (pi^2 (j^2 + k^2 + l^2) + kl_shift)^(-kl_exp) (K1 in
+ * 1..16, xi laid out (N, K1, K1, K1) with j the x-frequency), kappa per
+ * element the mean of exp(m) over its 8 vertices, lumped reaction and
+ * source, consistent Q1 mass in the QoI; the sinusoidal target is
+ * sin(2 pi x) sin(2 pi y) sin(2 pi z).  PDE form only: the MR-DINO form,
+ * saa_solve_states and the training calls return SAA_E_INVALID; N_max up to
+ * 2^20. */
 typedef struct saa_problem {
-  int dim;             /* 2 */
-  int n;               /* cells per side; a power of two >= 4 */
-  int n_src_per_dim;   /* s: d_Z = s^2 controls (1..8) */
+  int dim;             /* 2, or 3 (see above) */
+  int n;               /* cells per side; 2D: a power of two >= 4 */
+  int n_src_per_dim;   /* s: d_Z = s^2 controls (1..8); 3D: s^3 (1..4) */
   double src_sigma;    /* source width sigma > 0 */
   int kl_per_dim;      /* K1 in 1..64 */
   double kl_shift;     /* >= 0 */
@@ -491,6 +504,17 @@ int saa_ouu_solve(saa_ctx* ctx, int form, const void* model, const saa_options* 
  * state solve, PCG iterations of the adjoint / linearised solves.  N is the
  * number of installed samples.  Synchronises the context's stream. */
 int saa_sample_status(saa_ctx* ctx, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters);
+
+/* Threads per sample of the 3D state and adjoint kernels for the PDE
+ * precision prec (SAA_FP64, SAA_FP32 or SAA_FP32_DC64).  The kernels exist
+ * for 256, 512 and 1024 threads; while a size is 0 the next call of that
+ * precision times the three on the context's stream (HIP events; the
+ * launches recompute all their outputs, so results do not depend on the
+ * extra runs) and records the fastest.  set = 0: *bs_state and *bs_adjoint
+ * receive the recorded sizes (0 = not chosen yet); set = 1: they are
+ * installed (256, 512, 1024, or 0 to time again).  SAA_E_INVALID for a 2D
+ * context, NULL pointers, another prec or another size. */
+int saa_ctx_launch3(saa_ctx* ctx, int prec, int* bs_state, int* bs_adjoint, int set);
 
 #ifdef __cplusplus
 }

@@ -93,6 +93,8 @@ _SIGS = {
                                       ctypes.POINTER(CReport)]),
     "saa_solve_states": (ctypes.c_int, [_P, _P, ctypes.POINTER(COptions), _P, _P, _P, ctypes.POINTER(CReport)]),
     "saa_sample_status": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "saa_ctx_launch3": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.c_int]),
     "mrdino_num_params": (ctypes.c_int, [ctypes.POINTER(None), ctypes.POINTER(ctypes.c_int64)]),
     "mrdino_create": (ctypes.c_int, [ctypes.POINTER(None), _P, ctypes.POINTER(_P)]),
     "mrdino_free": (None, [_P]),
@@ -323,6 +325,16 @@ class Context:
         arrs = [np.zeros(self.n, dtype=np.int32) for _ in range(4)]
         _check(self._lib.saa_sample_status(self._h, *[a.ctypes.data for a in arrs]))
         return tuple(arrs)
+
+    def launch3(self, prec=FP32_DC64, state=None, adjoint=None):
+        """3D contexts: threads per sample of the state / adjoint kernels for
+        `prec`.  With no sizes given returns the recorded (state, adjoint)
+        pair (0: chosen by timing at the next call); otherwise installs them
+        (256, 512, 1024, or 0 to time again)."""
+        a, b = ctypes.c_int(state or 0), ctypes.c_int(adjoint or 0)
+        setting = state is not None or adjoint is not None
+        _check(self._lib.saa_ctx_launch3(self._h, prec, ctypes.byref(a), ctypes.byref(b), 1 if setting else 0))
+        return a.value, b.value
 
     def solve_states(self, Z, want_dudz=False, opt=None):
         """Z: float64 CUDA tensor (N, d_Z).  Returns (u (N, d_U), q (N,),

@@ -57,11 +57,11 @@ template <typename TS>
 void hierarchy3(const Pde3Geo& g, const double* em, double* k64, const Mg3Bufs<TS>& b, int64_t N, hipStream_t st);
 template <typename TW, typename TS>
 void state3(const Pde3Geo& g, const double* Z, const double* k64, TW* u, TW* f, const Mg3Bufs<TS>& b,
-            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, hipStream_t st);
+            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, int bs, hipStream_t st);
 template <typename TW, typename TS>
 void adjoint3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* lam, const Mg3Bufs<TS>& b,
               const SolveParams& sp, const double* q, const double* tstar, int act, double act_w, double* gout,
-              int* lin, int* flag, int* did, int64_t N, hipStream_t st);
+              int* lin, int* flag, int* did, int64_t N, int bs, hipStream_t st);
 void risk(const double* q, const double* g, int64_t N, int dz, int kind, double eps, double kappa, double tau,
           double alpha, const double* z, int phase, double* tstar, double* out, const int* newton, const int* lin,
           const int* flag, const int* lin_adj, const int* did, void* stats, void* work, hipStream_t st);
@@ -273,33 +273,78 @@ int validate_options(const saa_options* o) {
 }
 
 // Launch the state solve for the requested PDE precision.
+// Threads per sample for a 3D kernel: the recorded choice, or, when none is
+// recorded, the fastest of 256, 512 and 1024 threads timed with HIP events on
+// the context's stream (the launches are idempotent: every output is
+// recomputed from the inputs); the chosen size then runs once more so that
+// the outputs come from it.
+template <typename F>
+int launch3(saa_ctx* c, int& choice, F&& launch) {
+  if (choice) {
+    launch(choice);
+    return check_hip(hipGetLastError());
+  }
+  static const int cand[3] = {256, 512, 1024};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = check_hip(hipEventCreate(&e0));
+  if (!rc) rc = check_hip(hipEventCreate(&e1));
+  float best = INFINITY;
+  int pick = 512;
+  for (int k = 0; k < 3 && !rc; ++k) {
+    rc = check_hip(hipEventRecord(e0, c->st));
+    launch(cand[k]);
+    if (!rc) rc = check_hip(hipGetLastError());
+    if (!rc) rc = check_hip(hipEventRecord(e1, c->st));
+    if (!rc) rc = check_hip(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1));
+    if (!rc && ms < best) {
+      best = ms;
+      pick = cand[k];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  choice = pick;
+  if (pick != cand[2]) launch(pick);
+  return check_hip(hipGetLastError());
+}
+
 int run_state3(saa_ctx* c, int prec, const double* Z, const SolveParams& sp) {
   int rc;
-  const double* K = (const double*)c->k64.p;
+  int& bs = c->bs3_state[prec];
+  // c->k64 is allocated by the first build_mg3: read it at launch time
+  auto K = [c]() { return (const double*)c->k64.p; };
+  if (!c->u.p || !c->f.p) return SAA_E_INVALID;
   switch (prec) {
     case SAA_FP64:
       if (!c->mg3_64.built && (rc = build_mg3(c, c->mg3_64))) return rc;
-      saa_launch::state3<double, double>(c->geo3, Z, (const double*)c->k64.p, (double*)c->u.p, (double*)c->f.p,
-                                         c->mg3_64.view(), sp, (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
-                                         (int*)c->flag.p, c->N, c->st);
-      break;
+      if (!K() || !c->mg3_64.E.p) return SAA_E_INVALID;
+      return launch3(c, bs, [&](int b) {
+        saa_launch::state3<double, double>(c->geo3, Z, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_64.view(), sp,
+                                           (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
+                                           b, c->st);
+      });
     case SAA_FP32_DC64:
       if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
-      saa_launch::state3<double, float>(c->geo3, Z, (const double*)c->k64.p, (double*)c->u.p, (double*)c->f.p,
-                                        c->mg3_32.view(), sp, (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
-                                        (int*)c->flag.p, c->N, c->st);
-      break;
+      if (!K() || !c->mg3_32.E.p) return SAA_E_INVALID;
+      return launch3(c, bs, [&](int b) {
+        saa_launch::state3<double, float>(c->geo3, Z, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_32.view(), sp,
+                                          (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
+                                          b, c->st);
+      });
     case SAA_FP32:
       if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
-      saa_launch::state3<float, float>(c->geo3, Z, (const double*)c->k64.p, (float*)c->u.p, (float*)c->f.p,
-                                       c->mg3_32.view(), sp, (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
-                                       (int*)c->flag.p, c->N, c->st);
-      break;
+      if (!K() || !c->mg3_32.E.p) return SAA_E_INVALID;
+      return launch3(c, bs, [&](int b) {
+        saa_launch::state3<float, float>(c->geo3, Z, K(), (float*)c->u.p, (float*)c->f.p, c->mg3_32.view(), sp,
+                                         (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
+                                         b, c->st);
+      });
     default:
       return SAA_E_INVALID;
   }
-  (void)K;
-  return check_hip(hipGetLastError());
 }
 
 int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const SolveParams& sp) {
@@ -337,27 +382,31 @@ int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const Sol
 }
 
 int run_adjoint3(saa_ctx* c, int prec, const SolveParams& sp, int act, double act_w, double* gout) {
+  int& bs = c->bs3_adj[prec];
+  if (!c->k64.p || !c->u.p) return SAA_E_INVALID;   // the state solve has not run
   const double* K = (const double*)c->k64.p;
   switch (prec) {
     case SAA_FP64:
-      saa_launch::adjoint3<double, double>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
-                                           c->mg3_64.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
-                                           (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, c->st);
-      break;
+      return launch3(c, bs, [&](int b) {
+        saa_launch::adjoint3<double, double>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
+                                             c->mg3_64.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
+                                             (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, b, c->st);
+      });
     case SAA_FP32_DC64:
-      saa_launch::adjoint3<double, float>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
-                                          c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
-                                          (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, c->st);
-      break;
+      return launch3(c, bs, [&](int b) {
+        saa_launch::adjoint3<double, float>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
+                                            c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
+                                            (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, b, c->st);
+      });
     case SAA_FP32:
-      saa_launch::adjoint3<float, float>(c->geo3, K, (float*)c->u.p, (float*)c->f.p, (float*)c->lam.p,
-                                         c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
-                                         (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, c->st);
-      break;
+      return launch3(c, bs, [&](int b) {
+        saa_launch::adjoint3<float, float>(c->geo3, K, (float*)c->u.p, (float*)c->f.p, (float*)c->lam.p,
+                                           c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
+                                           (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, b, c->st);
+      });
     default:
       return SAA_E_INVALID;
   }
-  return check_hip(hipGetLastError());
 }
 
 int run_adjoint(saa_ctx* c, int prec, const SolveParams& sp, int act, double act_w, double* gout) {
@@ -1002,6 +1051,20 @@ int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, do
   rc = fill_report(c, rep, secs, nullptr);
   if (rep) rep->t_star = rep->dJ_dt = 0.0;   // no CVaR reduction here
   return rc;
+}
+
+int saa_ctx_launch3(saa_ctx* c, int prec, int* bs_state, int* bs_adjoint, int set) {
+  if (!c || !c->d3 || !bs_state || !bs_adjoint || prec < SAA_FP64 || prec > SAA_FP32_DC64) return SAA_E_INVALID;
+  if (set) {
+    auto ok = [](int b) { return b == 0 || b == 256 || b == 512 || b == 1024; };
+    if (!ok(*bs_state) || !ok(*bs_adjoint)) return SAA_E_INVALID;
+    c->bs3_state[prec] = *bs_state;
+    c->bs3_adj[prec] = *bs_adjoint;
+  } else {
+    *bs_state = c->bs3_state[prec];
+    *bs_adjoint = c->bs3_adj[prec];
+  }
+  return SAA_OK;
 }
 
 int saa_sample_status(saa_ctx* c, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters) {

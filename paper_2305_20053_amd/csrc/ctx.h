@@ -151,6 +151,10 @@ struct saa_ctx {
   saa_rt::DevBuf G3;                  // 3D: separable source factor table s x (n+1)
   saa_rt::Mg3Store<double> mg3_64;
   saa_rt::Mg3Store<float> mg3_32;
+  // 3D threads per sample of the state / adjoint kernels per PDE precision
+  // (SAA_FP64, SAA_FP32, SAA_FP32_DC64); 0: chosen by timing at the next call
+  int bs3_state[3] = {0, 0, 0};
+  int bs3_adj[3] = {0, 0, 0};
   int K1 = 0, dz = 0;
   int64_t n_kl = 0;                   // K1^dim KL coefficients per sample
   int64_t nodes = 0, d_u = 0;

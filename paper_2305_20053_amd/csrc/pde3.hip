@@ -4,9 +4,9 @@
 // tracking QoI and the adjoint gradient dq/dz = F^T lambda, A(u) lambda =
 // dq/du (Sec. 2.3, eq. (ouu_qoi_gradient)).
 //
-// As in 2D, one workgroup owns one sample for its whole solve (512 threads:
-// measured at 48^3, N = 256, 256 and 768 threads were 1.6x and 1.9x slower
-// and 1024 threads 1.6x):
+// As in 2D, one workgroup owns one sample for its whole solve (256, 512 or
+// 1024 threads, chosen by timing; at 48^3, N = 256 512 threads are fastest,
+// 256 and 1024 take 1.6x as long):
 // Newton in the state precision, inner multigrid-preconditioned CG in the
 // solver precision, every decision taken on the device.
 //
@@ -41,13 +41,14 @@
 
 namespace {
 
-#ifndef SAA_PDE3_BLOCK
-#define SAA_PDE3_BLOCK 512
-#endif
-constexpr int BS = SAA_PDE3_BLOCK;   // threads per sample
+// Threads per sample: the state and adjoint kernels are instantiated for
+// 256, 512 and 1024 threads (template BSZ) and the runtime times the three
+// once per context and precision (see saa_rt::tune3); the node loops step by
+// blockDim.x.  The setup kernel uses HB threads.
+constexpr int HB = 512;
 constexpr int COARSE_SWEEPS = 4;   // even: the coarsest result lands in T
 
-// Visit nodes p = tid, tid + BS, ... of an (n+1)^3 grid with (i, j, k).
+// Visit nodes p = tid, tid + blockDim.x, ... of an (n+1)^3 grid with (i, j, k).
 template <typename F>
 __device__ __forceinline__ void for_nodes3(int n, F&& f) {
   const int np = n + 1, np2 = np * np;
@@ -61,10 +62,11 @@ __device__ __forceinline__ void for_nodes3(int n, F&& f) {
   int k = p / np2;
   int j = (p - k * np2) / np;
   int i = p - k * np2 - j * np;
-  const int sk = BS / np2;
-  const int sj = (BS - sk * np2) / np;
-  const int si = BS - sk * np2 - sj * np;
-  for (; p < total; p += BS) {
+  const int bs = (int)blockDim.x;
+  const int sk = bs / np2;
+  const int sj = (bs - sk * np2) / np;
+  const int si = bs - sk * np2 - sj * np;
+  for (; p < total; p += bs) {
     f(p, i, j, k);
     i += si;
     if (i >= np) {
@@ -112,16 +114,17 @@ __device__ __forceinline__ void for_inner3(int n, C&& compute, S&& store) {
   int k = p / np2;
   int j = (p - k * np2) / np;
   int i = p - k * np2 - j * np;
-  const int sk = BS / np2;
-  const int sj = (BS - sk * np2) / np;
-  const int si = BS - sk * np2 - sj * np;
-  for (; p < total; p += U * BS) {
+  const int bs = (int)blockDim.x;
+  const int sk = bs / np2;
+  const int sj = (bs - sk * np2) / np;
+  const int si = bs - sk * np2 - sj * np;
+  for (; p < total; p += U * bs) {
     int q[U], qi[U], qj[U], qk[U];
     bool in[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      in[u] = p + u * BS < total && inner3(i, j, k, n);
-      q[u] = in[u] ? p + u * BS : psafe;
+      in[u] = p + u * bs < total && inner3(i, j, k, n);
+      q[u] = in[u] ? p + u * bs : psafe;
       qi[u] = in[u] ? i : 1;
       qj[u] = in[u] ? j : 1;
       qk[u] = in[u] ? k : 1;
@@ -576,7 +579,7 @@ __global__ void __launch_bounds__(256) saa_k_field3(const double* xi, const doub
 // FP64 for the residuals; coarse: mean of the eight children) and the
 // stiffness diagonals.  One block per sample.
 template <typename TS>
-__global__ void __launch_bounds__(BS) saa_k_hierarchy3(Pde3Geo g, const double* em_all, double* k64_all,
+__global__ void __launch_bounds__(HB) saa_k_hierarchy3(Pde3Geo g, const double* em_all, double* k64_all,
                                                        Mg3Bufs<TS> all, int64_t N) {
   const int64_t s = blockIdx.x;
   if (s >= N) return;
@@ -630,11 +633,11 @@ __global__ void __launch_bounds__(BS) saa_k_hierarchy3(Pde3Geo g, const double* 
 // State solve: Newton (precision TW) with inner MG-PCG (precision TS), then
 // q = (u - ut)^T M (u - ut).  One block per sample; all samples share z.
 // ---------------------------------------------------------------------------
-template <typename TW, typename TS>
-__global__ void __launch_bounds__(BS) saa_k_state3(Pde3Geo g, const double* Z, const double* k64_all, TW* u_all,
+template <typename TW, typename TS, int BSZ>
+__global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, const double* k64_all, TW* u_all,
                                                    TW* f_all, Mg3Bufs<TS> all, SolveParams sp, double* q_out,
                                                    int* newton_out, int* lin_out, int* flag_out, int64_t N) {
-  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
   __shared__ double zs[SAA_MAX_DZ];
   __shared__ double Gs[4 * 97];
   const int64_t s = blockIdx.x;
@@ -645,7 +648,7 @@ __global__ void __launch_bounds__(BS) saa_k_state3(Pde3Geo g, const double* Z, c
   TW* f = f_all + s * g.nodes;
   Mg3Bufs<TS> m = sample_bufs3(all, g, s);
   if (threadIdx.x < g.dz) zs[threadIdx.x] = Z[threadIdx.x];
-  for (int t = threadIdx.x; t < ns * np; t += BS) Gs[t] = g.G[t];
+  for (int t = threadIdx.x; t < ns * np; t += BSZ) Gs[t] = g.G[t];
   __syncthreads();
   // f = F z: lumped separable sources; u = 0
   for_nodes3(n, [&](int p, int i, int j, int k) {
@@ -723,12 +726,12 @@ __global__ void __launch_bounds__(BS) saa_k_state3(Pde3Geo g, const double* Z, c
 // kernel: act 0 CVaR tail q > t, 1 all, 2 0 < q - t < act_w, 3 buffered
 // exceedance); the others get a zero g row.
 // ---------------------------------------------------------------------------
-template <typename TW, typename TS>
-__global__ void __launch_bounds__(BS) saa_k_adjoint3(Pde3Geo g, const double* k64_all, const TW* u_all, TW* b_all,
+template <typename TW, typename TS, int BSZ>
+__global__ void __launch_bounds__(BSZ) saa_k_adjoint3(Pde3Geo g, const double* k64_all, const TW* u_all, TW* b_all,
                                                      TW* lam_all, Mg3Bufs<TS> all, SolveParams sp, const double* q,
                                                      const double* tstar, int act, double act_w, double* g_out,
                                                      int* lin_out, int* flag_out, int* did_out, int64_t N) {
-  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
   __shared__ double Gs[4 * 97];
   const int64_t s = blockIdx.x;
   if (s >= N) return;
@@ -750,7 +753,7 @@ __global__ void __launch_bounds__(BS) saa_k_adjoint3(Pde3Geo g, const double* k6
   TW* b = b_all + s * g.nodes;
   TW* lam = lam_all + s * g.nodes;
   Mg3Bufs<TS> m = sample_bufs3(all, g, s);
-  for (int t = threadIdx.x; t < ns * np; t += BS) Gs[t] = g.G[t];
+  for (int t = threadIdx.x; t < ns * np; t += BSZ) Gs[t] = g.G[t];
   const double h3 = g.h * g.h * g.h;
   for_nodes3(n, [&](int p, int i, int j, int k) {
     double v = 0.0;
@@ -799,7 +802,7 @@ void field3(const double* xi, const double* S, const double* amp, double* em, in
 
 template <typename TS>
 void hierarchy3(const Pde3Geo& g, const double* em, double* k64, const Mg3Bufs<TS>& b, int64_t N, hipStream_t st) {
-  saa_k_hierarchy3<TS><<<(unsigned)N, BS, 0, st>>>(g, em, k64, b, N);
+  saa_k_hierarchy3<TS><<<(unsigned)N, HB, 0, st>>>(g, em, k64, b, N);
 }
 template void hierarchy3<float>(const Pde3Geo&, const double*, double*, const Mg3Bufs<float>&, int64_t, hipStream_t);
 template void hierarchy3<double>(const Pde3Geo&, const double*, double*, const Mg3Bufs<double>&, int64_t,
@@ -807,24 +810,40 @@ template void hierarchy3<double>(const Pde3Geo&, const double*, double*, const M
 
 template <typename TW, typename TS>
 void state3(const Pde3Geo& g, const double* Z, const double* k64, TW* u, TW* f, const Mg3Bufs<TS>& b,
-            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, hipStream_t st) {
-  saa_k_state3<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N);
+            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, int bs,
+            hipStream_t st) {
+  switch (bs) {
+    case 256: saa_k_state3<TW, TS, 256><<<(unsigned)N, 256, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N); break;
+    case 1024: saa_k_state3<TW, TS, 1024><<<(unsigned)N, 1024, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N); break;
+    default: saa_k_state3<TW, TS, 512><<<(unsigned)N, 512, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N);
+  }
 }
 
 template <typename TW, typename TS>
 void adjoint3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* lam, const Mg3Bufs<TS>& b,
               const SolveParams& sp, const double* q, const double* tstar, int act, double act_w, double* gout,
-              int* lin, int* flag, int* did, int64_t N, hipStream_t st) {
-  saa_k_adjoint3<TW, TS><<<(unsigned)N, BS, 0, st>>>(g, k64, u, bvec, lam, b, sp, q, tstar, act, act_w, gout, lin,
-                                                     flag, did, N);
+              int* lin, int* flag, int* did, int64_t N, int bs, hipStream_t st) {
+  switch (bs) {
+    case 256:
+      saa_k_adjoint3<TW, TS, 256><<<(unsigned)N, 256, 0, st>>>(g, k64, u, bvec, lam, b, sp, q, tstar, act, act_w, gout,
+                                                               lin, flag, did, N);
+      break;
+    case 1024:
+      saa_k_adjoint3<TW, TS, 1024><<<(unsigned)N, 1024, 0, st>>>(g, k64, u, bvec, lam, b, sp, q, tstar, act, act_w,
+                                                                 gout, lin, flag, did, N);
+      break;
+    default:
+      saa_k_adjoint3<TW, TS, 512><<<(unsigned)N, 512, 0, st>>>(g, k64, u, bvec, lam, b, sp, q, tstar, act, act_w, gout,
+                                                               lin, flag, did, N);
+  }
 }
 
 #define SAA_INST3(TW, TS)                                                                                    \
   template void state3<TW, TS>(const Pde3Geo&, const double*, const double*, TW*, TW*, const Mg3Bufs<TS>&,   \
-                               const SolveParams&, double*, int*, int*, int*, int64_t, hipStream_t);           \
+                               const SolveParams&, double*, int*, int*, int*, int64_t, int, hipStream_t);      \
   template void adjoint3<TW, TS>(const Pde3Geo&, const double*, const TW*, TW*, TW*, const Mg3Bufs<TS>&,       \
                                  const SolveParams&, const double*, const double*, int, double, double*, int*, \
-                                 int*, int*, int64_t, hipStream_t);
+                                 int*, int*, int64_t, int, hipStream_t);
 SAA_INST3(double, double)
 SAA_INST3(double, float)
 SAA_INST3(float, float)

@@ -83,6 +83,11 @@ def test_ctx_create_rejects_bad_3d_problem_before_device_work(field, value):
     assert st == saa.SAA_E_INVALID and not h.value
 
 
+def test_launch3_rejects_without_context():
+    a, b = ctypes.c_int(512), ctypes.c_int(512)
+    assert saa.lib().saa_ctx_launch3(None, saa.FP32_DC64, ctypes.byref(a), ctypes.byref(b), 1) == saa.SAA_E_INVALID
+
+
 def test_null_arguments_rejected():
     lib = saa.lib()
     p = saa.problem_small().c_struct()

@@ -83,6 +83,25 @@ def test_small3_objective(small3, prec):
     assert 2 <= rep["newton_max"] <= 8
 
 
+def test_block_sizes_and_autotune(small3):
+    """The 256-, 512- and 1024-thread instances of the 3D kernels each match
+    the oracle; with no size recorded, the next call times the three and
+    records one of them."""
+    prob, xi, z, ref, ctx = small3
+    for bs in (256, 512, 1024):
+        print(f"case 3D n=8 block {bs}", flush=True)
+        assert ctx.launch3(saa.FP64, bs, bs) == (bs, bs)
+        q, g, _ = ctx.per_sample(z, opt=saa.options(prec=saa.FP64))
+        _check_per_sample(q, g, ref, saa.FP64)
+    assert ctx.launch3(saa.FP64, 0, 0) == (0, 0)
+    J, grad, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64, beta=0.8))
+    st, ad = ctx.launch3(saa.FP64)
+    assert st in (256, 512, 1024) and ad in (256, 512, 1024)
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
+    with pytest.raises(saa.SaaError):
+        ctx.launch3(saa.FP64, 384, 512)
+
+
 @pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64])
 def test_64_controls_odd_coarsest_grid(gpu_lib, prec):
     """n = 12 (levels 12, 6, 3: the coarsest grid has 8 unknowns and odd
