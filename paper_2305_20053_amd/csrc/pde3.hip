@@ -171,6 +171,103 @@ __device__ __forceinline__ TA off_sum(const TE* E, int p, int np, int np2, XF&& 
   return s;
 }
 
+// Column march over the interior nodes of an n^3-cell grid.  Work item w
+// takes the interior column (i, j) = (1 + c % (n-1), 1 + c / (n-1)),
+// c = w mod (n-1)^2, and one half of its k range (items below (n-1)^2: k = 1
+// .. n/2, the others k = n/2 + 1 .. n - 1), so consecutive threads walk
+// neighbouring columns and their loads coalesce.  At step k the window holds
+// x at (i + dx, j + dy, k + dz), dx, dy, dz in {-1, 0, 1}, and the kappas of
+// the 8 elements with lowest corners (i - 1 + a, j - 1 + b, k - 1 + c);
+// plane k + 2 of x and element plane k + 1 are loaded before the body of step
+// k runs (the body's stores would otherwise order the next step's loads
+// behind them).  Plane indices are clamped to n, inside the (n+1)^3 arrays.
+template <typename TA>
+struct Win3 {
+  TA x[3][3][3];   // x[dz + 1][dy + 1][dx + 1]
+  TA e[2][2][2];   // e[c][b][a]: element with lowest corner (i - 1 + a, j - 1 + b, k - 1 + c)
+  __device__ __forceinline__ TA centre() const { return x[1][1][1]; }
+};
+
+// off_sum on a window: the element e_abc of off_sum (lowest corner
+// p - a - b np - c np2) is e[1 - c][1 - b][1 - a].
+template <typename TA>
+__device__ __forceinline__ TA off_sum_w(const Win3<TA>& w) {
+  const TA e000 = w.e[1][1][1], e100 = w.e[1][1][0], e010 = w.e[1][0][1], e110 = w.e[1][0][0];
+  const TA e001 = w.e[0][1][1], e101 = w.e[0][1][0], e011 = w.e[0][0][1], e111 = w.e[0][0][0];
+  auto u = [&](int dx, int dy, int dz) { return w.x[dz + 1][dy + 1][dx + 1]; };
+  TA s = (e000 + e001) * u(1, 1, 0) + (e100 + e101) * u(-1, 1, 0) + (e010 + e011) * u(1, -1, 0) +
+         (e110 + e111) * u(-1, -1, 0);
+  s += (e000 + e010) * u(1, 0, 1) + (e100 + e110) * u(-1, 0, 1) + (e001 + e011) * u(1, 0, -1) +
+       (e101 + e111) * u(-1, 0, -1);
+  s += (e000 + e100) * u(0, 1, 1) + (e010 + e110) * u(0, -1, 1) + (e001 + e101) * u(0, 1, -1) +
+       (e011 + e111) * u(0, -1, -1);
+  s += e000 * u(1, 1, 1) + e100 * u(-1, 1, 1) + e010 * u(1, -1, 1) + e110 * u(-1, -1, 1) + e001 * u(1, 1, -1) +
+       e101 * u(-1, 1, -1) + e011 * u(1, -1, -1) + e111 * u(-1, -1, -1);
+  return s;
+}
+
+template <typename TA>
+__device__ __forceinline__ TA kappa_sum_w(const Win3<TA>& w) {
+  return ((w.e[0][0][0] + w.e[0][0][1]) + (w.e[0][1][0] + w.e[0][1][1])) +
+         ((w.e[1][0][0] + w.e[1][0][1]) + (w.e[1][1][0] + w.e[1][1][1]));
+}
+
+template <typename TA, typename XL, typename EL, typename Body>
+__device__ __forceinline__ void march3(int n, XL&& xload, EL&& eload, Body&& body) {
+  const int np = n + 1, np2 = np * np, nc = n - 1, ncol = nc * nc, kh = n / 2;
+  int w = threadIdx.x;
+  asm volatile("" : "+v"(w));
+  for (; w < 2 * ncol; w += (int)blockDim.x) {
+    const int half = w >= ncol ? 1 : 0;
+    const int c = w - half * ncol;
+    const int j = 1 + c / nc, i = 1 + c - (j - 1) * nc;
+    const int k0 = half ? kh + 1 : 1, k1 = half ? n - 1 : kh;
+    if (k0 > k1) continue;
+    const int base = i + j * np;   // node (i, j, 0)
+    auto xplane = [&](TA (&d)[3][3], int kk) {
+      const int q = base + kk * np2;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) d[dy + 1][dx + 1] = xload(q + dy * np + dx);
+    };
+    auto eplane = [&](TA (&d)[2][2], int kk) {
+      const int q = base + kk * np2 - np - 1;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) d[b][a] = eload(q + b * np + a);
+    };
+    Win3<TA> W;
+    xplane(W.x[0], k0 - 1);
+    xplane(W.x[1], k0);
+    xplane(W.x[2], k0 + 1);
+    eplane(W.e[0], k0 - 1);
+    eplane(W.e[1], k0);
+    for (int k = k0; k <= k1; ++k) {
+      TA xa[3][3], ea[2][2];
+      xplane(xa, k + 2 <= n ? k + 2 : n);
+      eplane(ea, k + 1 <= n - 1 ? k + 1 : n - 1);
+      body(base + k * np2, W);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          W.x[0][dy][dx] = W.x[1][dy][dx];
+          W.x[1][dy][dx] = W.x[2][dy][dx];
+          W.x[2][dy][dx] = xa[dy][dx];
+        }
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          W.e[0][b][a] = W.e[1][b][a];
+          W.e[1][b][a] = ea[b][a];
+        }
+    }
+  }
+}
+
 template <typename TE>
 __device__ __forceinline__ double kappa_sum8(const TE* E, int p, int np, int np2) {
   return (double)E[p] + (double)E[p - 1] + (double)E[p - np] + (double)E[p - np - 1] + (double)E[p - np2] +
@@ -274,9 +371,19 @@ __device__ void prolong_add3(const Lvl3<TS>& F, TS* x, const Lvl3<TS>& C, const 
       [&](int p, TS v) { x[p] = v; });
 }
 
+// Grids of at least this many cells per side run their stencil passes as
+// column marches; smaller ones have too few columns to occupy the threads.
+constexpr int MARCH_MIN_N = 16;
+
 // t = b - A x on the interior of level L.
 template <typename TS>
 __device__ void residual3(const Lvl3<TS>& L, const TS* b, const TS* x, TS* t) {
+  if (L.n >= MARCH_MIN_N) {
+    march3<TS>(
+        L.n, [&](int q) { return x[q]; }, [&](int q) { return L.E[q]; },
+        [&](int p, const Win3<TS>& W) { t[p] = b[p] - (L.D[p] * W.centre() - L.hq * off_sum_w(W)); });
+    return;
+  }
   for_inner3<UB>(
       L.n,
       [&](int p, int, int, int) {
@@ -288,6 +395,15 @@ __device__ void residual3(const Lvl3<TS>& L, const TS* b, const TS* x, TS* t) {
 // One damped Jacobi sweep dst = src + omega (b - A src) / D.
 template <typename TS>
 __device__ void jacobi3(const Lvl3<TS>& L, const TS* b, const TS* src, TS* dst, TS omega) {
+  if (L.n >= MARCH_MIN_N) {
+    march3<TS>(
+        L.n, [&](int q) { return src[q]; }, [&](int q) { return L.E[q]; },
+        [&](int p, const Win3<TS>& W) {
+          const TS xs = W.centre(), d = L.D[p];
+          dst[p] = xs + omega * (b[p] - (d * xs - L.hq * off_sum_w(W))) / d;
+        });
+    return;
+  }
   for_inner3<UB>(
       L.n,
       [&](int p, int, int, int) {
@@ -398,17 +514,15 @@ __device__ int pcg3(const Pde3Geo& g, const Mg3Bufs<TS>& m, double rtol, int max
     if (it > 0) {
       double pq = 0.0;
       const TS* po = pc;
-      for_inner3<UB>(
-          n,
-          [&](int p, int, int, int) {
-            auto pv = [&](int q) { return z[q] + beta * po[q]; };   // zero on the boundary
-            const TS pp = pv(p);
-            return Two<TS>{pp, L0.D[p] * pp - L0.hq * off_sum<TS>(L0.E, p, L0.np, L0.np2, pv)};
-          },
-          [&](int p, const Two<TS>& v) {
-            pn[p] = v.a;
-            m.cq[p] = v.b;
-            pq += (double)v.a * (double)v.b;
+      march3<TS>(
+          n, [&](int q) { return z[q] + beta * po[q]; },   // zero on the boundary
+          [&](int q) { return L0.E[q]; },
+          [&](int p, const Win3<TS>& W) {
+            const TS pp = W.centre();
+            const TS q = L0.D[p] * pp - L0.hq * off_sum_w(W);
+            pn[p] = pp;
+            m.cq[p] = q;
+            pq += (double)pp * (double)q;
           });
       TS* t = pc;
       pc = pn;
@@ -434,7 +548,9 @@ __device__ int pcg3(const Pde3Geo& g, const Mg3Bufs<TS>& m, double rtol, int max
       rr = block_sum1(rr, red);
       if (rr <= tol2) return it;
     }
-    residual3(L0, (const TS*)m.cr, (const TS*)L0.X, L0.T);
+    march3<TS>(
+        n, [&](int q) { return L0.X[q]; }, [&](int q) { return L0.E[q]; },
+        [&](int p, const Win3<TS>& W) { L0.T[p] = m.cr[p] - (L0.D[p] * W.centre() - L0.hq * off_sum_w(W)); });
     __syncthreads();
     restrict3(L0, (const TS*)L0.T, L1, omega);
     __syncthreads();
@@ -442,16 +558,13 @@ __device__ int pcg3(const Pde3Geo& g, const Mg3Bufs<TS>& m, double rtol, int max
     prolong_add3(L0, L0.X, L1, (const TS*)L1.T);
     __syncthreads();
     double rzn = 0.0;
-    for_inner3<UB>(
-        n,
-        [&](int p, int, int, int) {
-          const TS xs = L0.X[p], d = L0.D[p], r = m.cr[p];
-          const TS ax = d * xs - L0.hq * off_sum<TS>(L0.E, p, L0.np, L0.np2, [&](int q) { return L0.X[q]; });
-          return Two<TS>{xs + omega * (r - ax) / d, r};
-        },
-        [&](int p, const Two<TS>& v) {
-          z[p] = v.a;
-          rzn += (double)v.b * (double)v.a;
+    march3<TS>(
+        n, [&](int q) { return L0.X[q]; }, [&](int q) { return L0.E[q]; },
+        [&](int p, const Win3<TS>& W) {
+          const TS xs = W.centre(), d = L0.D[p], r = m.cr[p];
+          const TS zz = xs + omega * (r - (d * xs - L0.hq * off_sum_w(W))) / d;
+          z[p] = zz;
+          rzn += (double)r * (double)zz;
         });
     rzn = block_sum1(rzn, red);
     beta = (TS)(it > 0 ? rzn / rz : 0.0);
@@ -520,13 +633,13 @@ __device__ int dc_solve3(const Pde3Geo& g, const Mg3Bufs<TS>& m, const SolvePara
       break;
     }
     if (outer_converged(ctl, v[0], v[1], sp.adj_tol, sp.lin_rtol)) break;
-    for_inner3<UB>(
-        n,
-        [&](int p, int, int, int) {
-          const TW uu = u[p];
-          return (TS)(b[p] - (stiff3<TW>(K, x, p, np, np2, g.h) + (TW)c3 * uu * uu * x[p]));
-        },
-        [&](int p, TS v) { m.cr[p] = v; });
+    march3<TW>(
+        n, [&](int q) { return x[q]; }, [&](int q) { return (TW)K[q]; },
+        [&](int p, const Win3<TW>& W) {
+          const TW uu = u[p], xc = W.centre();
+          const TW kx = (TW)(g.h / 3.0) * kappa_sum_w(W) * xc - (TW)(g.h / 12.0) * off_sum_w(W);
+          m.cr[p] = (TS)(b[p] - (kx + (TW)c3 * uu * uu * xc));
+        });
     __syncthreads();
   }
   if (pass == sp.max_dc) *ok = false;
@@ -672,13 +785,13 @@ __global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, 
   OuterCtl ctl;
   ctl.eta = sp.lin_rtol;
   for (it = 0; it < sp.max_newton; ++it) {
-    for_inner3<UB>(
-        n,
-        [&](int p, int, int, int) {
-          const TW uu = u[p];
-          return (TS)(f[p] - (stiff3<TW>(K, u, p, np, np2, g.h) + (TW)c1 * uu * uu * uu));
-        },
-        [&](int p, TS v) { m.cr[p] = v; });
+    march3<TW>(
+        n, [&](int q) { return u[q]; }, [&](int q) { return (TW)K[q]; },
+        [&](int p, const Win3<TW>& W) {
+          const TW uu = W.centre();
+          const TW ku = (TW)(g.h / 3.0) * kappa_sum_w(W) * uu - (TW)(g.h / 12.0) * off_sum_w(W);
+          m.cr[p] = (TS)(f[p] - (ku + (TW)c1 * uu * uu * uu));
+        });
     __syncthreads();
     build_diagonals3<TW, TS>(g, m, u);
     bool ok = true;
