@@ -189,3 +189,58 @@ def test_3d_rejects_surrogate_and_training_calls(small3):
     prob, xi, z, ref, ctx = small3
     with pytest.raises(saa.SaaError):
         ctx.solve_states(torch.zeros((len(xi), prob.d_z), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("kind", [saa.RISK_MEAN, saa.RISK_MEAN_VAR, saa.RISK_POF, saa.RISK_BPOE])
+def test_3d_risk_measures(small3, kind):
+    """The expectation-type risk measures on the 3D PDE form (FP64), with the
+    adjoint activity rules of each (all samples; 0 < q - tau < eps; the
+    buffered-exceedance weight), against the oracle's reductions of the
+    oracle's q_i, dq_i/dz."""
+    from oracle import risk
+    prob, xi, z, ref, ctx = small3
+    q, g = ref["q"], ref["g"]
+    tau = float(np.quantile(q, 0.7))
+    eps = 0.3 * float(np.std(q)) if kind != saa.RISK_BPOE else 0.1
+    print(f"case 3D risk kind={kind}", flush=True)
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64, risk=kind, risk_kappa=2.0, risk_tau=tau,
+                                                         eps=eps))
+    if kind == saa.RISK_MEAN:
+        r = risk.mean(q, g, z, 1e-3)
+    elif kind == saa.RISK_MEAN_VAR:
+        r = risk.mean_var(q, g, z, 2.0, 1e-3)
+    elif kind == saa.RISK_POF:
+        r = risk.pof(q, g, z, tau, eps, 1e-3)
+    else:
+        r = risk.bpoe(q, g, z, tau, eps, 1e-3)
+    assert abs(J - r["J"]) <= 1e-9 * abs(r["J"]) and _rel(grad, r["grad"]) <= 1e-9
+    x = q - tau
+    want = {saa.RISK_POF: int(np.sum((x > 0) & (x < eps))),
+            saa.RISK_BPOE: int(np.sum(r["t"] * x + 1.0 > 0))}.get(kind, len(q))
+    assert rep["n_adjoints"] == want and 0 < want
+
+
+def test_3d_ouu_matches_oracle(gpu_lib):
+    """Outer OUU solve (bound-constrained L-BFGS) on the 3D PDE form against
+    scipy's L-BFGS-B on the oracle objective, same start: optimal J to 1e-9,
+    z* to 1e-5, and first-order optimality under the oracle gradient."""
+    from oracle import ouu
+    prob = problem3(8, s=2, K1=3, kl_amp=20.0, target=saa.TARGET_SIN)
+    xi = si.kl_coefficients(2408, 6, 3, dim=3)
+    lb, ub = -1.5, 1.5
+    op = _oprob(prob)
+
+    def fg(zz):
+        r = osaa.objective_grad(op, xi, zz)
+        return r["J"], r["grad"]
+    print("case 3D ouu", flush=True)
+    z_ref, J_ref, _ = ouu.solve(fg, np.full(prob.d_z, 0.5), lb, ub, pgtol=1e-10)
+    ctx = saa.Context(prob, 6)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    z, rep = ctx.ouu_solve(np.full(prob.d_z, 0.5), lb, ub, opt=saa.options(prec=saa.FP64), pgtol=1e-10, ftol=0.0)
+    print(f"  J {rep['J']:.15g} ref {J_ref:.15g} it {rep['iterations']} active {rep['n_active']}")
+    assert abs(rep["J"] - J_ref) <= 1e-9 * abs(J_ref)
+    assert np.abs(z - z_ref).max() <= 1e-5
+    J_o, g_o = fg(z)
+    assert np.abs(ouu.projected_gradient(z, g_o, lb, ub)).max() <= 1e-7
+    ctx.close()
