@@ -153,7 +153,43 @@ def train_surrogate(saa, si, epochs):
     return model, info, qoi
 
 
-def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True):
+def measure_ceilings():
+    """The box's own ceilings, measured with library kernels (measurement
+    only): a 2 GiB device-to-device copy and a STREAM triad a = b + 2 c over
+    three 1 GiB arrays (HBM GB/s), and an 8192^3 BF16 GEMM with contiguous
+    operands (torch.mm; TFLOP/s).  Best of 5 after one warm-up each."""
+    import torch
+
+    def best(fn, work, reps=6):
+        rates = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            rates.append(work / (e0.elapsed_time(e1) * 1e-3))
+        return max(rates[1:])
+    a = torch.empty(1 << 29, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    copy = best(lambda: b.copy_(a), 2 * a.numel() * 4) / 1e9
+    del a, b
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a).fill_(2.0)
+    c = torch.empty_like(a).fill_(3.0)
+    triad = best(lambda: torch.add(b, c, alpha=2.0, out=a), 3 * a.numel() * 4) / 1e9
+    del a, b, c
+    n = 8192
+    x = torch.randn(n, n, device="cuda").to(torch.bfloat16).contiguous()
+    y = torch.randn(n, n, device="cuda").to(torch.bfloat16).contiguous()
+    gemm = best(lambda: torch.mm(x, y), 2.0 * n ** 3) / 1e12
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_GBps": copy, "triad_GBps": triad, "bf16_gemm_TFLOPs": gemm,
+            "method": "torch copy_, torch.add triad over 1 GiB arrays, torch.mm 8192^3 BF16 (contiguous); best of 5"}
+
+
+def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True, ceil=None):
     """Surrogate form at N = 65536 samples (n = 128 KL field, 16 x 16 modes):
     the trained MR-DINO (or random Glorot weights with epochs = 0) in BF16 and
     FP32, timed like the PDE form; its error against the GPU PDE form on 256
@@ -199,6 +235,8 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True):
         out[name] = {"value": N * nsteps / wall, "ms_per_step": 1e3 * wall / nsteps, "kernel_ms": ms_k,
                      "reduce_ms": ms_r,
                      "roofline": {"bound": "alu" if prec == saa.FP32 else "mfma", "achieved": ach, "peak": peak,
+                                  "measured_bf16_gemm_TFLOPs": (ceil or {}).get("bf16_gemm_TFLOPs") if prec == saa.BF16 else None,
+                                  "frac_vs_measured": ach / ceil["bf16_gemm_TFLOPs"] if (ceil and prec == saa.BF16) else None,
                                   "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                                   "kernel": ("saa_k_mlp_fp32" if prec == saa.FP32 else
                                              f"saa_k_mlp_mfma<{name}>"),
@@ -465,19 +503,9 @@ def main():
            "grad_rel_vs_gpu_fp64": float(np.linalg.norm(gp - g64) / np.linalg.norm(g64)),
            "oracle_parity": "tests/test_gpu_pde.py (<= 1e-9 FP64 / FP32-DC64, <= 1e-4 FP32)"}
 
-    # measured HBM ceiling: a 2 GiB device-to-device copy (read + write), best of 5
-    cp_a = torch.empty(1 << 29, dtype=torch.float32, device="cuda").fill_(1.0)
-    cp_b = torch.empty_like(cp_a)
-    cp_rates = []
-    for _ in range(6):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        cp_b.copy_(cp_a)
-        e1.record()
-        e1.synchronize()
-        cp_rates.append(2 * cp_a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
-    copy_gbs = max(cp_rates[1:])
-    del cp_a, cp_b
+    # measured ceilings of this machine (HBM copy and triad, BF16 GEMM)
+    ceil = measure_ceilings()
+    copy_gbs = ceil["copy_GBps"]
 
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
@@ -498,6 +526,7 @@ def main():
                    "n": prob.n, "N": N, "form": "pde", "prec": args.prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "measured_copy_GBps": copy_gbs, "frac_vs_copy": achieved / copy_gbs,
+                     "measured_triad_GBps": ceil["triad_GBps"], "frac_vs_triad": achieved / ceil["triad_GBps"],
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "saa_k_state", "alg_bytes_per_launch": bytes_launch,
                      "kernel_ms": ms_state},
@@ -510,10 +539,14 @@ def main():
     ctx.close()
     if not args.no_3d:
         out["pde3d"] = bench_pde3d(saa, si, args.steps, args.warmup)
+        r3 = out["pde3d"]["roofline"]
+        r3["frac_vs_copy"] = r3["achieved"] / ceil["copy_GBps"]
+        r3["frac_vs_triad"] = r3["achieved"] / ceil["triad_GBps"]
     if not args.no_mrdino:
         zs_box = [si.control(s, lo=Z_LO, hi=Z_HI) for s in si.SEED_Z_EVAL]
         out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs_box, value, args.train_epochs,
-                                     not args.no_ouu)
+                                     not args.no_ouu, ceil)
+    out["ceilings"] = ceil
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, xi, zs[0])
     print(json.dumps(out), flush=True)
