@@ -98,7 +98,7 @@ enum { SAA_FP64 = 0, SAA_FP32 = 1, SAA_FP32_DC64 = 2, SAA_BF16 = 3, SAA_FP8 = 4 
  * 2^20. */
 typedef struct saa_problem {
   int dim;             /* 2, or 3 (see above) */
-  int n;               /* cells per side; 2D: a power of two >= 4 */
+  int n;               /* cells per side; 2D: 2^k or 3 * 2^k, 4 <= n <= 4096 */
   int n_src_per_dim;   /* s: d_Z = s^2 controls (1..8); 3D: s^3 (1..4) */
   double src_sigma;    /* source width sigma > 0 */
   int kl_per_dim;      /* K1 in 1..64 */

@@ -673,7 +673,13 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   *out = nullptr;
   if (p->dim == 3) return ctx_create3(p, N_max, hip_stream, out);
   if (p->dim != 2) return SAA_E_INVALID;
-  if (p->n < 4 || p->n > 4096 || (p->n & (p->n - 1))) return SAA_E_INVALID;
+  // n halves down to a coarsest grid of 2 or 3 cells: 2^k or 3 * 2^k
+  if (p->n < 4 || p->n > 4096) return SAA_E_INVALID;
+  {
+    int m = p->n;
+    while (m > 3 && !(m & 1)) m >>= 1;
+    if (m > 3) return SAA_E_INVALID;
+  }
   if (p->n_src_per_dim < 1 || p->n_src_per_dim > 8) return SAA_E_INVALID;
   if (!is_fin(p->src_sigma) || p->src_sigma <= 0) return SAA_E_INVALID;
   if (p->kl_per_dim < 1 || p->kl_per_dim > 64) return SAA_E_INVALID;
@@ -699,11 +705,12 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   PdeGeo& g = c->geo;
   g.L = 0;
   int64_t off = 0;
-  for (int n = p->n; n >= 2; n >>= 1) {
+  for (int n = p->n;; n >>= 1) {
     g.n[g.L] = n;
     g.off[g.L] = off;
     off += (int64_t)(n + 1) * (n + 1);
     ++g.L;
+    if (n <= 3) break;
   }
   g.lstride = off;
   g.nodes = c->nodes;

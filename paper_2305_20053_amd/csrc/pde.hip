@@ -242,11 +242,46 @@ __device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, int l0) {
     residual_red(lv, b, (const TS*)x, t);
     restrict_red(g.n[l], (const TS*)t, g.n[l + 1], at_level(m.B, m.lB, g, l + 1));
   }
-  {  // coarsest level: a single unknown at node (1,1) of the n = 2 grid
+  {  // coarsest level, solved exactly: one unknown (n = 2) or the 2 x 2
+     // interior nodes of the n = 3 grid (Gaussian elimination in FP64)
     const int l = L - 1;
     if (threadIdx.x == 0) {
-      const int p = 1 * (g.n[l] + 1) + 1;
-      at_level(m.X, m.lX, g, l)[p] = at_level(m.B, m.lB, g, l)[p] / at_level(m.D, m.lD, g, l)[p];
+      const Level<TS> lc = level(g, m, l);
+      TS* X = at_level(m.X, m.lX, g, l);
+      const TS* B = at_level(m.B, m.lB, g, l);
+      const int np = lc.np;
+      if (lc.n == 2) {
+        const int p = np + 1;
+        X[p] = B[p] / lc.D[p];
+      } else {
+        const int id[4] = {np + 1, np + 2, 2 * np + 1, 2 * np + 2};
+        double A[4][5];
+        for (int a = 0; a < 4; ++a) {
+          for (int b = 0; b < 4; ++b) {
+            const int pa = id[a], pb = id[b];
+            double v = 0.0;
+            if (pb == pa) v = (double)lc.D[pa];
+            else if (pb == pa + 1) v = -(double)lc.WE[pa];
+            else if (pb == pa - 1) v = -(double)lc.WE[pb];
+            else if (pb == pa + np) v = -(double)lc.WN[pa];
+            else if (pb == pa - np) v = -(double)lc.WN[pb];
+            A[a][b] = v;
+          }
+          A[a][4] = (double)B[id[a]];
+        }
+        for (int c = 0; c < 4; ++c)   // SPD: no pivoting
+          for (int r = c + 1; r < 4; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k < 5; ++k) A[r][k] -= f * A[c][k];
+          }
+        double x[4];
+        for (int r = 3; r >= 0; --r) {
+          double v = A[r][4];
+          for (int k = r + 1; k < 4; ++k) v -= A[r][k] * x[k];
+          x[r] = v / A[r][r];
+        }
+        for (int a = 0; a < 4; ++a) X[id[a]] = (TS)x[a];
+      }
     }
     __syncthreads();
   }

@@ -53,7 +53,7 @@ def test_options_default():
     assert saa.lib().saa_options_default(None) == saa.SAA_E_INVALID
 
 
-@pytest.mark.parametrize("field,value", [("n", 3), ("n", 48), ("n", 0), ("dim", 3), ("n_src_per_dim", 0),
+@pytest.mark.parametrize("field,value", [("n", 3), ("n", 80), ("n", 40), ("n", 0), ("dim", 3), ("n_src_per_dim", 0),
                                          ("src_sigma", 0.0), ("src_sigma", float("nan")), ("kl_per_dim", 0),
                                          ("kl_exp", -1.0), ("reaction", -1.0), ("u_target", float("inf")),
                                          ("kl_per_dim", 64), ("target", 3), ("target", -1)])

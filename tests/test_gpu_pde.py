@@ -218,3 +218,28 @@ def test_objective_autograd_and_finite_differences(small):
         fd, an = (jp - jm) / (2 * h), float(gl @ v)
         print(f"  directional derivative: FD {fd:.10e} analytic {an:.10e}")
         assert abs(fd - an) <= 1e-6 * np.linalg.norm(gl)
+
+
+@pytest.mark.parametrize("n", [24, 96])
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64])
+def test_three_times_power_of_two_grids(gpu_lib, n, prec):
+    """n = 3 * 2^k: the multigrid hierarchy ends on the 3-cell grid (four
+    unknowns, solved exactly) instead of the 2-cell one; n = 96 is the middle
+    2D companion of the 3D workload.  q_i and dq_i/dz of 8 samples and the
+    CVaR objective against the oracle."""
+    prob = saa.Problem(n=n, kl_per_dim=8, target=saa.TARGET_SIN)
+    print(f"case 2D n={n} prec={prec}", flush=True)
+    xi = si.kl_coefficients(2409, 8, prob.kl_per_dim)
+    z = si.control(2410)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 8)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    q, g, _ = ctx.per_sample(z, opt=saa.options(prec=prec))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= 1e-12
+    for i in range(len(q)):
+        assert _rel(g[i], ref["g"][i]) <= 1e-9, (i, _rel(g[i], ref["g"][i]))
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=prec))
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
+    assert rep["n_unconverged"] == 0
+    ctx.close()
