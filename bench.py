@@ -341,6 +341,34 @@ def bench_pde3d(saa, si, steps, warmup):
                       "oracle_parity": "tests/test_gpu_pde3d.py"}}
 
 
+def bench_companions(saa, si, steps, warmup):
+    """The 2D instances that accompany the 3D workload: n = 64, 96 and 128
+    (sinusoidal target, 16 x 16 KL modes), N = 256 samples each, FP32-DC64;
+    each in its own context and launch sequence."""
+    import torch
+    out = {}
+    for n in (64, 96, 128):
+        prob = saa.Problem(n=n, kl_per_dim=16, target=saa.TARGET_SIN)
+        xi = si.kl_coefficients(si.SEED_XI_3D, 256, prob.kl_per_dim)
+        zs = [si.control(s) for s in si.SEED_Z_EVAL]
+        ctx = saa.Context(prob, 256)
+        ctx.set_samples(torch.from_numpy(xi).cuda())
+        opt = saa.options(prec=saa.FP32_DC64)
+        for k in range(warmup):
+            ctx.objective_grad(zs[k % len(zs)], opt=opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ctx.objective_grad(zs[k % len(zs)], opt=opt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rep = ctx.objective_grad(zs[0], opt=saa.options(prec=saa.FP32_DC64, timing=1))[2]
+        out[f"n{n}"] = {"samples_per_s": 256 * steps / wall, "ms_per_step": 1e3 * wall / steps,
+                        "ms_state": rep["ms_state"], "ms_adjoint": rep["ms_adjoint"], "levels_coarsest": 3 if n == 96 else 2}
+        ctx.close()
+    return out
+
+
 def bench_jacobian_modes(saa, si):
     """Reduced control Jacobians of 256 training samples (n = 128) with
     r_u = 16 < d_Z = 25 and r_u = 64 > d_Z: d_Z forward solves per sample
@@ -542,6 +570,7 @@ def main():
         r3 = out["pde3d"]["roofline"]
         r3["frac_vs_copy"] = r3["achieved"] / ceil["copy_GBps"]
         r3["frac_vs_triad"] = r3["achieved"] / ceil["triad_GBps"]
+        out["pde3d"]["companions_2d_N256"] = bench_companions(saa, si, args.steps, args.warmup)
     if not args.no_mrdino:
         zs_box = [si.control(s, lo=Z_LO, hi=Z_HI) for s in si.SEED_Z_EVAL]
         out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs_box, value, args.train_epochs,

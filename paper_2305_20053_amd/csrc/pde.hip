@@ -229,6 +229,31 @@ __device__ double gs_black_prolong(const Level<TS>& L, const TS* b, TS* x, const
 // V(1,1) cycle from level l0 down and back to l0, its right-hand side already
 // restricted to B_l0: red, black (with the red residuals restricted, as on
 // the fine level), coarse correction, black fused with the prolongation, red.
+// Exact solve on the 3-cell grid: red nodes (1,1), (2,2) and black nodes
+// (2,1), (1,2); eliminating the black unknowns leaves a 2 x 2 Schur
+// complement (FP64).
+template <typename TS>
+__device__ __noinline__ void coarsest3(const Level<TS> lc, const TS* B, TS* X) {
+  const int np = lc.np;
+  const int r0 = np + 1, r1 = 2 * np + 2, b0 = np + 2, b1 = 2 * np + 1;
+  // couplings C[r][b] (edge weights): r0-b0 horizontal, r0-b1 vertical,
+  // r1-b0 vertical, r1-b1 horizontal
+  const double c00 = lc.WE[r0], c01 = lc.WN[r0], c10 = lc.WN[b0], c11 = lc.WE[b1];
+  const double ib0 = 1.0 / (double)lc.D[b0], ib1 = 1.0 / (double)lc.D[b1];
+  const double s00 = (double)lc.D[r0] - (c00 * c00 * ib0 + c01 * c01 * ib1);
+  const double s11 = (double)lc.D[r1] - (c10 * c10 * ib0 + c11 * c11 * ib1);
+  const double s01 = -(c00 * c10 * ib0 + c01 * c11 * ib1);
+  const double bb0 = B[b0], bb1 = B[b1];
+  const double h0 = (double)B[r0] + c00 * bb0 * ib0 + c01 * bb1 * ib1;
+  const double h1 = (double)B[r1] + c10 * bb0 * ib0 + c11 * bb1 * ib1;
+  const double idet = 1.0 / (s00 * s11 - s01 * s01);
+  const double x0 = (s11 * h0 - s01 * h1) * idet, x1 = (s00 * h1 - s01 * h0) * idet;
+  X[r0] = (TS)x0;
+  X[r1] = (TS)x1;
+  X[b0] = (TS)((bb0 + c00 * x0 + c10 * x1) * ib0);
+  X[b1] = (TS)((bb1 + c01 * x0 + c11 * x1) * ib1);
+}
+
 template <typename TS>
 __device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, int l0) {
   const int L = g.L;
@@ -242,45 +267,19 @@ __device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, int l0) {
     residual_red(lv, b, (const TS*)x, t);
     restrict_red(g.n[l], (const TS*)t, g.n[l + 1], at_level(m.B, m.lB, g, l + 1));
   }
-  {  // coarsest level, solved exactly: one unknown (n = 2) or the 2 x 2
-     // interior nodes of the n = 3 grid (Gaussian elimination in FP64)
+  {  // coarsest level, solved exactly: one unknown (n = 2); the 3-cell grid
+     // of 3 * 2^k hierarchies goes to an out-of-line solver (inlined, its
+     // code slows the CG loop of the power-of-two grids by 11 %)
     const int l = L - 1;
     if (threadIdx.x == 0) {
       const Level<TS> lc = level(g, m, l);
       TS* X = at_level(m.X, m.lX, g, l);
       const TS* B = at_level(m.B, m.lB, g, l);
-      const int np = lc.np;
       if (lc.n == 2) {
-        const int p = np + 1;
+        const int p = lc.np + 1;
         X[p] = B[p] / lc.D[p];
       } else {
-        const int id[4] = {np + 1, np + 2, 2 * np + 1, 2 * np + 2};
-        double A[4][5];
-        for (int a = 0; a < 4; ++a) {
-          for (int b = 0; b < 4; ++b) {
-            const int pa = id[a], pb = id[b];
-            double v = 0.0;
-            if (pb == pa) v = (double)lc.D[pa];
-            else if (pb == pa + 1) v = -(double)lc.WE[pa];
-            else if (pb == pa - 1) v = -(double)lc.WE[pb];
-            else if (pb == pa + np) v = -(double)lc.WN[pa];
-            else if (pb == pa - np) v = -(double)lc.WN[pb];
-            A[a][b] = v;
-          }
-          A[a][4] = (double)B[id[a]];
-        }
-        for (int c = 0; c < 4; ++c)   // SPD: no pivoting
-          for (int r = c + 1; r < 4; ++r) {
-            const double f = A[r][c] / A[c][c];
-            for (int k = c; k < 5; ++k) A[r][k] -= f * A[c][k];
-          }
-        double x[4];
-        for (int r = 3; r >= 0; --r) {
-          double v = A[r][4];
-          for (int k = r + 1; k < 4; ++k) v -= A[r][k] * x[k];
-          x[r] = v / A[r][r];
-        }
-        for (int a = 0; a < 4; ++a) X[id[a]] = (TS)x[a];
+        coarsest3(lc, B, X);
       }
     }
     __syncthreads();
