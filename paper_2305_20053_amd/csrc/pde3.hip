@@ -356,19 +356,41 @@ __device__ void restrict3(const Lvl3<TS>& F, const TS* t, const Lvl3<TS>& C, TS 
 // x += P xc: trilinear interpolation of the coarse vector (zero on the coarse
 // boundary).  With i0 = i / 2 and i1 = i0 + (i mod 2) per coordinate, the
 // interpolant is the mean of the 8 values at (i0|i1, j0|j1, k0|k1): an even
-// index repeats its coarse node (weight 1), an odd one averages two.
+// index repeats its coarse node (weight 1), an odd one averages two.  Fine
+// columns (i, j) march in k: the bilinear mean over (i0|i1, j0|j1) of coarse
+// plane K serves the fine planes 2K - 1, 2K and 2K + 1, so a fine node costs
+// about two coarse loads instead of eight.
 template <typename TS>
 __device__ void prolong_add3(const Lvl3<TS>& F, TS* x, const Lvl3<TS>& C, const TS* xc) {
-  for_inner3<UB>(
-      F.n,
-      [&](int p, int i, int j, int k) {
-        const int a0 = (i >> 1) + (j >> 1) * C.np + (k >> 1) * C.np2;
-        const int da = i & 1, db = (j & 1) * C.np, dc = (k & 1) * C.np2;
-        const TS s = (xc[a0] + xc[a0 + da]) + (xc[a0 + db] + xc[a0 + da + db]) + (xc[a0 + dc] + xc[a0 + da + dc]) +
-                     (xc[a0 + db + dc] + xc[a0 + da + db + dc]);
-        return x[p] + (TS)0.125 * s;
-      },
-      [&](int p, TS v) { x[p] = v; });
+  const int n = F.n, nc = n - 1, ncol = nc * nc, kh = n / 2;
+  int w = threadIdx.x;
+  asm volatile("" : "+v"(w));
+  for (; w < 2 * ncol; w += (int)blockDim.x) {
+    const int half = w >= ncol ? 1 : 0;
+    const int c = w - half * ncol;
+    const int j = 1 + c / nc, i = 1 + c - (j - 1) * nc;
+    const int k0 = half ? kh + 1 : 1, k1 = half ? n - 1 : kh;
+    if (k0 > k1) continue;
+    const int a0 = (i >> 1) + (j >> 1) * C.np;   // coarse (i0, j0, 0)
+    const int da = i & 1, db = (j & 1) * C.np;
+    auto bil = [&](int K) {
+      const int q = a0 + K * C.np2;
+      return (TS)0.25 * ((xc[q] + xc[q + da]) + (xc[q + db] + xc[q + da + db]));
+    };
+    int K = k0 >> 1;
+    TS lo = bil(K);                                   // coarse plane K = k >> 1
+    TS hi = (k0 & 1) ? bil(K + 1) : lo;               // plane K + (k & 1)
+    for (int k = k0; k <= k1; ++k) {
+      const int p = i + j * F.np + k * F.np2;
+      x[p] += (TS)0.5 * (lo + hi);
+      // next fine plane k + 1: K' = (k + 1) >> 1
+      if (k & 1) {   // k odd -> k + 1 even: both ends are plane K + 1
+        lo = hi;
+      } else if (k < k1) {   // k even -> k + 1 odd: planes K and K + 1
+        hi = bil((k >> 1) + 1);
+      }
+    }
+  }
 }
 
 // Grids of at least this many cells per side run their stencil passes as
