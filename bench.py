@@ -343,17 +343,18 @@ def bench_pde3d(saa, si, steps, warmup):
 
 def bench_companions(saa, si, steps, warmup):
     """The 2D instances that accompany the 3D workload: n = 64, 96 and 128
-    (sinusoidal target, 16 x 16 KL modes), N = 256 samples each, FP32-DC64;
-    each in its own context and launch sequence."""
+    (sinusoidal target, 16 x 16 KL modes), N = 256 samples each, FP32-DC64:
+    each in its own launch sequence, then all three in one state launch and
+    one adjoint launch (saa_objective_grad_multi)."""
     import torch
-    out = {}
+    out, ctxs = {}, []
+    zs = [si.control(s) for s in si.SEED_Z_EVAL]
+    opt = saa.options(prec=saa.FP32_DC64)
     for n in (64, 96, 128):
         prob = saa.Problem(n=n, kl_per_dim=16, target=saa.TARGET_SIN)
         xi = si.kl_coefficients(si.SEED_XI_3D, 256, prob.kl_per_dim)
-        zs = [si.control(s) for s in si.SEED_Z_EVAL]
         ctx = saa.Context(prob, 256)
         ctx.set_samples(torch.from_numpy(xi).cuda())
-        opt = saa.options(prec=saa.FP32_DC64)
         for k in range(warmup):
             ctx.objective_grad(zs[k % len(zs)], opt=opt)
         torch.cuda.synchronize()
@@ -365,7 +366,20 @@ def bench_companions(saa, si, steps, warmup):
         rep = ctx.objective_grad(zs[0], opt=saa.options(prec=saa.FP32_DC64, timing=1))[2]
         out[f"n{n}"] = {"samples_per_s": 256 * steps / wall, "ms_per_step": 1e3 * wall / steps,
                         "ms_state": rep["ms_state"], "ms_adjoint": rep["ms_adjoint"], "levels_coarsest": 3 if n == 96 else 2}
-        ctx.close()
+        ctxs.append(ctx)
+    for k in range(warmup):
+        saa.objective_grad_multi(ctxs, [zs[k % len(zs)]] * 3, opt=opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        saa.objective_grad_multi(ctxs, [zs[k % len(zs)]] * 3, opt=opt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sep = sum(v["ms_per_step"] for v in out.values())
+    out["one_launch"] = {"samples_per_s": 768 * steps / wall, "ms_per_step": 1e3 * wall / steps,
+                         "separate_ms_per_step_sum": sep}
+    for c in ctxs:
+        c.close()
     return out
 
 

@@ -505,6 +505,19 @@ int saa_ouu_solve(saa_ctx* ctx, int form, const void* model, const saa_options* 
  * number of installed samples.  Synchronises the context's stream. */
 int saa_sample_status(saa_ctx* ctx, int* flags, int* newton_iters, int* lin_iters, int* adj_lin_iters);
 
+/* PDE-form objective and gradient of `count` 2D contexts (1..4, any grid
+ * sizes, all on one stream, distinct) at their controls z[k] (host, d_Z of
+ * context k): one state launch and one adjoint launch serve all of them
+ * (the samples of context k take a contiguous range of the launch's
+ * workgroups), with each context's CVaR reduction in between.  J[k],
+ * grad_z[k] (host) and reports[k] (may be NULL) are the results of
+ * saa_objective_grad on each context alone, bit for bit.  opt applies to
+ * all (PDE precisions only; timing must be 0).  SAA_E_INVALID for a 3D
+ * context, a repeated context, contexts on different streams or a bad
+ * argument; otherwise the worst status of the contexts. */
+int saa_objective_grad_multi(int count, saa_ctx* const* ctx, const double* const* z, const saa_options* opt,
+                             double* J, double* const* grad_z, saa_report* reports);
+
 /* Threads per sample of the 3D state and adjoint kernels for the PDE
  * precision prec (SAA_FP64, SAA_FP32 or SAA_FP32_DC64).  The kernels exist
  * for 256, 512 and 1024 threads; while a size is 0 the next call of that

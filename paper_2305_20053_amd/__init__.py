@@ -93,6 +93,9 @@ _SIGS = {
                                       ctypes.POINTER(CReport)]),
     "saa_solve_states": (ctypes.c_int, [_P, _P, ctypes.POINTER(COptions), _P, _P, _P, ctypes.POINTER(CReport)]),
     "saa_sample_status": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "saa_objective_grad_multi": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                                ctypes.POINTER(COptions), _P, ctypes.POINTER(_P),
+                                                ctypes.POINTER(CReport)]),
     "saa_ctx_launch3": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                        ctypes.c_int]),
     "mrdino_num_params": (ctypes.c_int, [ctypes.POINTER(None), ctypes.POINTER(ctypes.c_int64)]),
@@ -194,6 +197,25 @@ def problem_medium(target: int = None) -> Problem:
     """n = 128 (16641 nodes), 16 x 16 KL modes: the N = 1024 PDE workload;
     sinusoidal target unless `target` says otherwise."""
     return Problem(n=128, kl_per_dim=16, target=TARGET_SIN if target is None else target)
+
+
+def objective_grad_multi(contexts, zs, opt=None):
+    """J and grad of several 2D PDE-form contexts (up to 4, any sizes, one
+    stream) with one state launch and one adjoint launch for all of them.
+    Returns a list of (J, grad, report dict), one per context."""
+    import numpy as np
+    opt = opt if opt is not None else options()
+    k = len(contexts)
+    zz = [np.ascontiguousarray(np.asarray(z, dtype=np.float64)) for z in zs]
+    grads = [np.zeros(c.d_z) for c in contexts]
+    J = np.zeros(k)
+    reps = (CReport * k)()
+    hs = (_P * k)(*[c._h for c in contexts])
+    zp = (_P * k)(*[z.ctypes.data for z in zz])
+    gp = (_P * k)(*[g.ctypes.data for g in grads])
+    _check(lib().saa_objective_grad_multi(k, hs, zp, ctypes.byref(opt), J.ctypes.data, gp, reps))
+    return [(float(J[i]), grads[i], {name: getattr(reps[i], name) for name, _ in reps[i]._fields_})
+            for i in range(k)]
 
 
 def problem_3d(target: int = None) -> Problem:

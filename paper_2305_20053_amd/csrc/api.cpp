@@ -53,6 +53,14 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
 size_t cvar_work_bytes();
 void field3(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
             hipStream_t st);
+template <typename TW, typename TS>
+void state_multi(const StateJob<TW, TS>* jobs, int count, int64_t blocks, size_t lds, const SolveParams& sp,
+                 hipStream_t st);
+template <typename TW, typename TS>
+void adjoint_multi(const AdjointJob<TW, TS>* jobs, int count, int64_t blocks, size_t lds, const SolveParams& sp,
+                   int act, double act_w, hipStream_t st);
+template <typename TS>
+size_t coarse_lds(const PdeGeo& g);
 template <typename TS>
 void hierarchy3(const Pde3Geo& g, const double* em, double* k64, const Mg3Bufs<TS>& b, int64_t N, hipStream_t st);
 template <typename TW, typename TS>
@@ -597,6 +605,60 @@ int ctx_create3(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx**
 
 }  // namespace
 
+namespace {
+
+// Device work of a multi-problem evaluation in precision (TW, TS): the job
+// tables go to ctx[0]'s job buffer (state jobs first, adjoint jobs after).
+template <typename TW, typename TS>
+int multi_work(int count, saa_ctx* const* ctx, const saa_options* opt, MgStore<TS> saa_ctx::*store) {
+  saa_ctx* c0 = ctx[0];
+  hipStream_t st = c0->st;
+  const SolveParams sp = solve_params(opt, sizeof(TW) == 4);
+  StateJob<TW, TS> sj[SAA_MAX_JOBS];
+  AdjointJob<TW, TS> aj[SAA_MAX_JOBS];
+  int64_t blocks = 0;
+  size_t lds = 0;
+  bool all_lds = true;
+  for (int k = 0; k < count; ++k) {
+    saa_ctx* c = ctx[k];
+    MgStore<TS>& m = c->*store;
+    const size_t l = saa_launch::coarse_lds<TS>(c->geo);
+    if (!l) all_lds = false;
+    lds = std::max(lds, l);
+    sj[k] = StateJob<TW, TS>{c->geo, (const double*)c->FT.p, (const double*)c->zdev.p, (const double*)c->em.p,
+                              (TW*)c->u.p, (TW*)c->f.p, m.view(), (double*)c->q.p, (int*)c->newton.p,
+                              (int*)c->lin.p, (int*)c->flag.p, c->N, blocks};
+    aj[k] = AdjointJob<TW, TS>{c->geo, (const double*)c->FT.p, (const double*)c->em.p, (const TW*)c->u.p,
+                                (TW*)c->f.p, (TW*)c->lam.p, m.view(), (const double*)c->q.p, c->tstar(),
+                                (double*)c->g.p, (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, blocks};
+    blocks += c->N;
+  }
+  if (!all_lds) lds = 0;
+  const size_t sb = sizeof(sj[0]) * SAA_MAX_JOBS, ab = sizeof(aj[0]) * SAA_MAX_JOBS;
+  int rc;
+  if (c0->jobs.bytes < sb + ab && (rc = c0->jobs.alloc(sb + ab))) return rc;
+  if ((rc = check_hip(hipMemcpyAsync(c0->jobs.p, sj, sizeof(sj[0]) * count, hipMemcpyHostToDevice, st))) ||
+      (rc = check_hip(hipMemcpyAsync((char*)c0->jobs.p + sb, aj, sizeof(aj[0]) * count, hipMemcpyHostToDevice, st))))
+    return rc;
+  saa_launch::state_multi<TW, TS>((const StateJob<TW, TS>*)c0->jobs.p, count, blocks, lds, sp, st);
+  if ((rc = check_hip(hipGetLastError()))) return rc;
+  for (int k = 0; k < count; ++k)
+    reduce(ctx[k], (double*)ctx[k]->q.p, (double*)ctx[k]->g.p, opt, 1, nullptr, nullptr, nullptr, nullptr, nullptr,
+           nullptr);
+  saa_launch::adjoint_multi<TW, TS>((const AdjointJob<TW, TS>*)((char*)c0->jobs.p + sb), count, blocks, lds, sp,
+                                    adjoint_act(opt), adjoint_act_w(opt), st);
+  if ((rc = check_hip(hipGetLastError()))) return rc;
+  for (int k = 0; k < count; ++k) {
+    saa_ctx* c = ctx[k];
+    reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 2, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
+           (int*)c->lin_adj.p, (int*)c->did.p, c->stats());
+    if ((rc = check_hip(hipMemcpyAsync(c->hres.p, c->res.p, RES_BYTES, hipMemcpyDeviceToHost, st)))) return rc;
+  }
+  return check_hip(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1058,6 +1120,57 @@ int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, do
   rc = fill_report(c, rep, secs, nullptr);
   if (rep) rep->t_star = rep->dJ_dt = 0.0;   // no CVaR reduction here
   return rc;
+}
+
+int saa_objective_grad_multi(int count, saa_ctx* const* ctx, const double* const* z, const saa_options* opt,
+                             double* J, double* const* grad_z, saa_report* reports) {
+  if (count < 1 || count > SAA_MAX_JOBS || !ctx || !z || !J || !grad_z) return SAA_E_INVALID;
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
+  if (opt->timing) return SAA_E_INVALID;
+  int64_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    if (!ctx[k] || !z[k] || !grad_z[k] || ctx[k]->d3 || ctx[k]->N < 1 || ctx[k]->st != ctx[0]->st) return SAA_E_INVALID;
+    for (int j = 0; j < k; ++j)
+      if (ctx[j] == ctx[k]) return SAA_E_INVALID;
+    for (int i = 0; i < ctx[k]->dz; ++i)
+      if (!is_fin(z[k][i])) return SAA_E_INVALID;
+    total += ctx[k]->N;
+  }
+  if (total > ((int64_t)1 << 31) - 1) return SAA_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int k = 0; k < count; ++k) {
+    saa_ctx* c = ctx[k];
+    if (!c->u.p) {
+      const size_t tw = (size_t)c->N_max * c->nodes * sizeof(double);
+      if ((rc = c->u.alloc_zero(tw, c->st)) || (rc = c->f.alloc_zero(tw, c->st)) || (rc = c->lam.alloc_zero(tw, c->st)))
+        return rc;
+    }
+    if (opt->prec == SAA_FP64) {
+      if (!c->mg64.built && (rc = build_mg(c, c->mg64))) return rc;
+    } else if (!c->mg32.built && (rc = build_mg(c, c->mg32))) {
+      return rc;
+    }
+    if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z[k], sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
+      return rc;
+  }
+  switch (opt->prec) {
+    case SAA_FP64: rc = multi_work<double, double>(count, ctx, opt, &saa_ctx::mg64); break;
+    case SAA_FP32_DC64: rc = multi_work<double, float>(count, ctx, opt, &saa_ctx::mg32); break;
+    default: rc = multi_work<float, float>(count, ctx, opt, &saa_ctx::mg32); break;
+  }
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = SAA_OK;
+  for (int k = 0; k < count; ++k) {
+    const double* h = (const double*)ctx[k]->hres.p;
+    J[k] = h[0];
+    for (int i = 0; i < ctx[k]->dz; ++i) grad_z[k][i] = h[2 + i];
+    const int r = fill_report(ctx[k], reports ? &reports[k] : nullptr, secs, nullptr);
+    if (r) worst = r;
+  }
+  return worst;
 }
 
 int saa_ctx_launch3(saa_ctx* c, int prec, int* bs_state, int* bs_adjoint, int set) {

@@ -172,6 +172,7 @@ struct saa_ctx {
   // solver statistics (CvarStats) at byte RES_STATS.
   saa_rt::DevBuf res;
   saa_rt::HostBuf hres;       // pinned host copy of `res`
+  saa_rt::DevBuf jobs;        // job tables of multi-problem launches led by this context
   saa_rt::DevBuf cwork;       // CVaR reduction workspace (partials, probe histograms, active set)
   saa_rt::DevBuf enc;         // surrogate input: leading KL coordinates as BF16, N_max x 128
   int enc_rm = -1;            // r_m that `enc` holds for the installed samples (-1: stale)

@@ -72,3 +72,42 @@ struct CvarStats {
 
 // Per-sample status flags.
 enum { SAA_FLAG_NEWTON = 1, SAA_FLAG_CG = 2, SAA_FLAG_DC = 4, SAA_FLAG_NAN = 8 };
+
+// One problem of a multi-size launch (several 2D contexts in one grid):
+// blocks [first, first + N) of the launch solve its samples 0 .. N-1.
+#define SAA_MAX_JOBS 4
+template <typename TW, typename TS>
+struct StateJob {
+  PdeGeo g;
+  const double* FT;
+  const double* Z;    // the problem's control (shared by its samples)
+  const double* em;
+  TW* u;
+  TW* f;
+  MgBufs<TS> b;
+  double* q;
+  int* newton;
+  int* lin;
+  int* flag;
+  int64_t N;
+  int64_t first;
+};
+
+template <typename TW, typename TS>
+struct AdjointJob {
+  PdeGeo g;
+  const double* FT;
+  const double* em;
+  const TW* u;
+  TW* bvec;
+  TW* lam;
+  MgBufs<TS> b;
+  const double* q;
+  const double* tstar;
+  double* gout;
+  int* lin;
+  int* flag;
+  int* did;
+  int64_t N;
+  int64_t first;
+};

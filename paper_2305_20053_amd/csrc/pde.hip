@@ -637,15 +637,12 @@ __global__ void __launch_bounds__(BS) saa_k_hierarchy(PdeGeo g, const double* em
 // the QoI q = (u - ut)^T M (u - ut) over all nodes.  One block per sample.
 // Z: controls, sample s uses Z + s * z_stride (z_stride = 0: shared control).
 // ---------------------------------------------------------------------------
+// One sample's state solve (shared by the single- and multi-problem kernels).
 template <typename TW, typename TS, bool LDSC>
-__global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, const double* Z,
-                                                  int64_t z_stride, const double* em_all, TW* u_all,
-                                                  TW* f_all, MgBufs<TS> all, SolveParams sp, double* q_out,
-                                                  int* newton_out, int* lin_out, int* flag_out, int64_t N) {
-  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
-  __shared__ double zs[SAA_MAX_DZ];
-  const int64_t s = blockIdx.x;
-  if (s >= N) return;
+__device__ __forceinline__ void state_sample(const PdeGeo& g, const double* FT, const double* Z, int64_t z_stride,
+                                             const double* em_all, TW* u_all, TW* f_all, const MgBufs<TS>& all,
+                                             const SolveParams& sp, double* q_out, int* newton_out, int* lin_out,
+                                             int* flag_out, int64_t s, double* red, double* zs) {
   const int n = g.n[0], np = n + 1;
   const double* em = em_all + s * g.nodes;
   TW* u = u_all + s * g.nodes;
@@ -728,6 +725,34 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
   }
 }
 
+template <typename TW, typename TS, bool LDSC>
+__global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, const double* Z,
+                                                  int64_t z_stride, const double* em_all, TW* u_all,
+                                                  TW* f_all, MgBufs<TS> all, SolveParams sp, double* q_out,
+                                                  int* newton_out, int* lin_out, int* flag_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  __shared__ double zs[SAA_MAX_DZ];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  state_sample<TW, TS, LDSC>(g, FT, Z, z_stride, em_all, u_all, f_all, all, sp, q_out, newton_out, lin_out, flag_out,
+                             s, red, zs);
+}
+
+// Several problems in one launch: block b belongs to the last job whose first
+// block is <= b (job descriptors in device memory, read uniformly).
+template <typename TW, typename TS, bool LDSC>
+__global__ void __launch_bounds__(BS) saa_k_state_multi(const StateJob<TW, TS>* jobs, int count, SolveParams sp) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  __shared__ double zs[SAA_MAX_DZ];
+  int p = 0;
+  for (int k = 1; k < count; ++k)
+    if ((int64_t)blockIdx.x >= jobs[k].first) p = k;
+  const StateJob<TW, TS>& J = jobs[p];
+  const int64_t s = (int64_t)blockIdx.x - J.first;
+  if (s >= J.N) return;
+  state_sample<TW, TS, LDSC>(J.g, J.FT, J.Z, 0, J.em, J.u, J.f, J.b, sp, J.q, J.newton, J.lin, J.flag, s, red, zs);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint: A(u) lambda = 2 (M (u - ut))_I, g = F^T lambda (Sec. 2.3).  One
 // block per sample.  Only samples whose risk weight can be non-zero are
@@ -737,15 +762,13 @@ __global__ void __launch_bounds__(BS) saa_k_state(PdeGeo g, const double* FT, co
 // buffered-exceedance weight a s_eps'(a (q - tau) + 1)); the others get a
 // zero g row.
 // ---------------------------------------------------------------------------
+// One sample's adjoint (shared by the single- and multi-problem kernels).
 template <typename TW, typename TS, bool LDSC>
-__global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, const double* em_all,
-                                                    const TW* u_all, TW* b_all, TW* lam_all, MgBufs<TS> all,
-                                                    SolveParams sp, const double* q, const double* tstar,
-                                                    int act, double act_w, double* g_out, int* lin_out,
-                                                    int* flag_out, int* did_out, int64_t N) {
-  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
-  const int64_t s = blockIdx.x;
-  if (s >= N) return;
+__device__ __forceinline__ void adjoint_sample(const PdeGeo& g, const double* FT, const double* em_all,
+                                               const TW* u_all, TW* b_all, TW* lam_all, const MgBufs<TS>& all,
+                                               const SolveParams& sp, const double* q, const double* tstar, int act,
+                                               double act_w, double* g_out, int* lin_out, int* flag_out,
+                                               int* did_out, int64_t s, double* red) {
   const int n = g.n[0], np = n + 1;
   const double xq = q[s] - tstar[0];
   const bool active = act == 1 || (act == 3 ? (tstar[0] > 0.0 && tstar[0] < INFINITY &&
@@ -814,6 +837,33 @@ __global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, 
 // state's multigrid hierarchy (Sec. 3.4, eq. (projected_sensitivity)).
 // Output dudz[s][k][interior index] in float64.  One block per sample.
 // ---------------------------------------------------------------------------
+template <typename TW, typename TS, bool LDSC>
+__global__ void __launch_bounds__(BS) saa_k_adjoint(PdeGeo g, const double* FT, const double* em_all,
+                                                    const TW* u_all, TW* b_all, TW* lam_all, MgBufs<TS> all,
+                                                    SolveParams sp, const double* q, const double* tstar,
+                                                    int act, double act_w, double* g_out, int* lin_out,
+                                                    int* flag_out, int* did_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  adjoint_sample<TW, TS, LDSC>(g, FT, em_all, u_all, b_all, lam_all, all, sp, q, tstar, act, act_w, g_out, lin_out,
+                               flag_out, did_out, s, red);
+}
+
+template <typename TW, typename TS, bool LDSC>
+__global__ void __launch_bounds__(BS) saa_k_adjoint_multi(const AdjointJob<TW, TS>* jobs, int count, SolveParams sp,
+                                                          int act, double act_w) {
+  __shared__ double red[SAA_MAX_DZ * (BS / SAA_WAVE)];
+  int p = 0;
+  for (int k = 1; k < count; ++k)
+    if ((int64_t)blockIdx.x >= jobs[k].first) p = k;
+  const AdjointJob<TW, TS>& J = jobs[p];
+  const int64_t s = (int64_t)blockIdx.x - J.first;
+  if (s >= J.N) return;
+  adjoint_sample<TW, TS, LDSC>(J.g, J.FT, J.em, J.u, J.bvec, J.lam, J.b, sp, J.q, J.tstar, act, act_w, J.gout, J.lin,
+                               J.flag, J.did, s, red);
+}
+
 template <typename TW, typename TS, bool LDSC>
 __global__ void __launch_bounds__(BS) saa_k_linearized(PdeGeo g, const double* FT, const double* em_all,
                                                        const TW* u_all, TW* b_all, TW* x_all, MgBufs<TS> all,
@@ -1042,7 +1092,38 @@ void interior_copy(const TW* u, double* out, int n, int64_t N, hipStream_t st) {
   saa_k_interior<TW><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(u, out, n, N);
 }
 
+template <typename TW, typename TS>
+void state_multi(const StateJob<TW, TS>* jobs, int count, int64_t blocks, size_t lds, const SolveParams& sp,
+                 hipStream_t st) {
+  if (lds) {
+    (void)set_lds_attr((const void*)saa_k_state_multi<TW, TS, true>, lds);
+    saa_k_state_multi<TW, TS, true><<<(unsigned)blocks, BS, lds, st>>>(jobs, count, sp);
+  } else {
+    saa_k_state_multi<TW, TS, false><<<(unsigned)blocks, BS, 0, st>>>(jobs, count, sp);
+  }
+}
+
+template <typename TW, typename TS>
+void adjoint_multi(const AdjointJob<TW, TS>* jobs, int count, int64_t blocks, size_t lds, const SolveParams& sp,
+                   int act, double act_w, hipStream_t st) {
+  if (lds) {
+    (void)set_lds_attr((const void*)saa_k_adjoint_multi<TW, TS, true>, lds);
+    saa_k_adjoint_multi<TW, TS, true><<<(unsigned)blocks, BS, lds, st>>>(jobs, count, sp, act, act_w);
+  } else {
+    saa_k_adjoint_multi<TW, TS, false><<<(unsigned)blocks, BS, 0, st>>>(jobs, count, sp, act, act_w);
+  }
+}
+
+template <typename TS>
+size_t coarse_lds(const PdeGeo& g) {
+  return coarse_lds_bytes<TS>(g);
+}
+
 #define SAA_INST(TW, TS)                                                                                         \
+  template void state_multi<TW, TS>(const StateJob<TW, TS>*, int, int64_t, size_t, const SolveParams&,           \
+                                    hipStream_t);                                                                \
+  template void adjoint_multi<TW, TS>(const AdjointJob<TW, TS>*, int, int64_t, size_t, const SolveParams&, int,  \
+                                      double, hipStream_t);                                                      \
   template void state<TW, TS>(const PdeGeo&, const double*, const double*, int64_t, const double*, TW*, TW*,     \
                               const MgBufs<TS>&, const SolveParams&, double*, int*, int*, int*, int64_t,         \
                               hipStream_t);                                                                      \
@@ -1059,6 +1140,8 @@ SAA_INST(double, double)
 SAA_INST(double, float)
 SAA_INST(float, float)
 #undef SAA_INST
+template size_t coarse_lds<float>(const PdeGeo&);
+template size_t coarse_lds<double>(const PdeGeo&);
 template void interior_copy<double>(const double*, double*, int, int64_t, hipStream_t);
 template void interior_copy<float>(const float*, double*, int, int64_t, hipStream_t);
 

@@ -243,3 +243,33 @@ def test_three_times_power_of_two_grids(gpu_lib, n, prec):
     assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
     assert rep["n_unconverged"] == 0
     ctx.close()
+
+
+def test_multi_size_launch_matches_separate_calls(gpu_lib):
+    """Three 2D grids (n = 24, 32, 64; the first ends on the 3-cell grid) in
+    one state launch and one adjoint launch: J, grad and the solver counts of
+    each equal the separate evaluations bit for bit."""
+    sizes, ns = (24, 32, 64), (6, 9, 5)
+    ctxs, zs = [], []
+    for k, (n, N) in enumerate(zip(sizes, ns)):
+        prob = saa.Problem(n=n, kl_per_dim=8, target=saa.TARGET_SIN)
+        xi = si.kl_coefficients(2420 + k, N, prob.kl_per_dim)
+        c = saa.Context(prob, N)
+        c.set_samples(torch.from_numpy(xi).cuda())
+        ctxs.append(c)
+        zs.append(si.control(2430 + k))
+    print("case multi-size launch", flush=True)
+    for prec in (saa.FP64, saa.FP32_DC64):
+        opt = saa.options(prec=prec)
+        multi = saa.objective_grad_multi(ctxs, zs, opt=opt)
+        for c, z, (J, g, rep) in zip(ctxs, zs, multi):
+            J1, g1, rep1 = c.objective_grad(z, opt=opt)
+            assert J == J1 and np.array_equal(g, g1), (prec, J, J1)
+            assert rep["newton_total"] == rep1["newton_total"] and rep["lin_total"] == rep1["lin_total"]
+            assert rep["n_adjoints"] == rep1["n_adjoints"] and rep["t_star"] == rep1["t_star"]
+    with pytest.raises(saa.SaaError):
+        saa.objective_grad_multi([ctxs[0], ctxs[0]], [zs[0], zs[0]])
+    with pytest.raises(saa.SaaError):
+        saa.objective_grad_multi(ctxs, zs, opt=saa.options(timing=1))
+    for c in ctxs:
+        c.close()
