@@ -83,6 +83,19 @@ def test_ctx_create_rejects_bad_3d_problem_before_device_work(field, value):
     assert st == saa.SAA_E_INVALID and not h.value
 
 
+def test_multi_rejects_bad_arguments_before_device_work():
+    lib = saa.lib()
+    J = (ctypes.c_double * 4)()
+    o = saa.options()
+    for count in (0, 5, -1):
+        assert lib.saa_objective_grad_multi(count, None, None, ctypes.byref(o), ctypes.cast(J, ctypes.c_void_p),
+                                            None, None) == saa.SAA_E_INVALID
+    hs = (ctypes.c_void_p * 1)(None)
+    zp = (ctypes.c_void_p * 1)(None)
+    assert lib.saa_objective_grad_multi(1, hs, zp, ctypes.byref(o), ctypes.cast(J, ctypes.c_void_p), zp,
+                                        None) == saa.SAA_E_INVALID
+
+
 def test_launch3_rejects_without_context():
     a, b = ctypes.c_int(512), ctypes.c_int(512)
     assert saa.lib().saa_ctx_launch3(None, saa.FP32_DC64, ctypes.byref(a), ctypes.byref(b), 1) == saa.SAA_E_INVALID
