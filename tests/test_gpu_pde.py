@@ -273,3 +273,16 @@ def test_multi_size_launch_matches_separate_calls(gpu_lib):
         saa.objective_grad_multi(ctxs, zs, opt=saa.options(timing=1))
     for c in ctxs:
         c.close()
+
+
+def test_multi_with_one_context_equals_single_call(gpu_lib):
+    prob = saa.Problem(n=32, kl_per_dim=8, target=saa.TARGET_QUAD)
+    xi = si.kl_coefficients(2442, 3, prob.kl_per_dim)
+    z = si.control(2443)
+    ctx = saa.Context(prob, 3)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    print("case multi count=1", flush=True)
+    (J, g, _), = saa.objective_grad_multi([ctx], [z], opt=saa.options(prec=saa.FP64))
+    J1, g1, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64))
+    assert J == J1 and np.array_equal(g, g1)
+    ctx.close()

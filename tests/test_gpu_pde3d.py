@@ -244,3 +244,18 @@ def test_3d_ouu_matches_oracle(gpu_lib):
     J_o, g_o = fg(z)
     assert np.abs(ouu.projected_gradient(z, g_o, lb, ub)).max() <= 1e-7
     ctx.close()
+
+
+def test_3d_single_sample(gpu_lib):
+    """N = 1: the CVaR of one sample (t* at its q, every weight on it)."""
+    prob = problem3(8, s=2, K1=3, kl_amp=20.0)
+    xi = si.kl_coefficients(2440, 1, 3, dim=3)
+    z = si.control(2441, prob.d_z)
+    print("case 3D N=1", flush=True)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 1)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64))
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
+    assert rep["n_adjoints"] == 1
+    ctx.close()
