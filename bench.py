@@ -482,7 +482,7 @@ def main():
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (samples shard across GPUs with one context each, not measured here)"}))
         sys.exit(2)
 
     import numpy as np
