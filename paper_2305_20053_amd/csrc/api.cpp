@@ -751,8 +751,6 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (p->target != SAA_TARGET_CONST && p->target != SAA_TARGET_SIN && p->target != SAA_TARGET_QUAD)
     return SAA_E_INVALID;
   if (N_max < 1 || N_max > (int64_t)1 << 24) return SAA_E_INVALID;
-  // the field synthesis keeps a K1 x (n+1) table and the K1 x K1 coefficients in 64 KB of LDS
-  if ((int64_t)p->kl_per_dim * (p->n + 1) + (int64_t)p->kl_per_dim * p->kl_per_dim > 8192) return SAA_E_INVALID;
 
   saa_ctx* c = new (std::nothrow) saa_ctx();
   if (!c) return SAA_E_OOM;

@@ -24,6 +24,8 @@
 //    coarse edges take the mean of the two end values) and the Galerkin
 //    coarse stiffness is again the P1 stencil with each coarse triangle's
 //    kappa equal to the mean over its four child triangles.
+#include <algorithm>
+
 #include "common.h"
 #include "outer.h"
 #include "pde.h"
@@ -39,6 +41,7 @@ namespace {
 
 constexpr int BS = SAA_PDE_BLOCK;      // threads per sample
 constexpr int LF = SAA_PDE_LDS_FIRST;  // first multigrid level kept in LDS (FP32 solver)
+constexpr int FIELD_BAND = 2048;       // doubles of the field kernel's T band in LDS
 
 // ---------------------------------------------------------------------------
 // Node iteration: the calling thread visits nodes p = tid, tid + BS, ... of an
@@ -539,31 +542,36 @@ __global__ void saa_k_source_matrix(double* FT, int n, int s, double sigma) {
 }
 
 // Nodal exp(m) of each sample: m = sum_jk a_jk xi_jk sin(j pi x) sin(k pi y),
-// evaluated separably (a K1 x (n+1) intermediate in LDS).  One block per sample.
+// evaluated separably.  The K1 x (n+1) intermediate T[j][y] = sum_k a_jk
+// xi_jk sin(k pi y) is built in LDS a band of `rows` grid rows at a time, so
+// the LDS footprint does not grow with n.  One block per sample.
 __global__ void __launch_bounds__(256) saa_k_field(const double* xi, const double* S, const double* amp,
-                                                   double* em, int K1, int n, int64_t N) {
+                                                   double* em, int K1, int n, int rows, int64_t N) {
   extern __shared__ double sh[];
   const int64_t s = blockIdx.x;
   if (s >= N) return;
   const int np = n + 1;
-  double* Tjy = sh;                 // K1 x np : sum_k a_jk xi_jk sin(k pi y)
-  double* axi = sh + K1 * np;       // K1 x K1
+  double* axi = sh;                 // K1 x K1
+  double* Tjy = sh + K1 * K1;       // K1 x rows: the current band of T
   const double* x = xi + s * K1 * K1;
   for (int t = threadIdx.x; t < K1 * K1; t += blockDim.x) axi[t] = amp[t] * x[t];
-  __syncthreads();
-  for (int t = threadIdx.x; t < K1 * np; t += blockDim.x) {
-    const int j = t / np, y = t - j * np;
-    double acc = 0.0;
-    for (int k = 0; k < K1; ++k) acc += axi[j * K1 + k] * S[k * np + y];
-    Tjy[t] = acc;
-  }
-  __syncthreads();
   double* e = em + s * (int64_t)np * np;
-  for (int p = threadIdx.x; p < np * np; p += blockDim.x) {
-    const int y = p / np, xx = p - y * np;
-    double acc = 0.0;
-    for (int j = 0; j < K1; ++j) acc += Tjy[j * np + y] * S[j * np + xx];
-    e[p] = exp(acc);
+  for (int y0 = 0; y0 < np; y0 += rows) {
+    const int ny = (np - y0 < rows) ? (np - y0) : rows;
+    __syncthreads();  // axi written / previous band consumed
+    for (int t = threadIdx.x; t < K1 * ny; t += blockDim.x) {
+      const int j = t / ny, y = t - j * ny;
+      double acc = 0.0;
+      for (int k = 0; k < K1; ++k) acc += axi[j * K1 + k] * S[k * np + y0 + y];
+      Tjy[t] = acc;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < ny * np; p += blockDim.x) {
+      const int y = p / np, xx = p - y * np;
+      double acc = 0.0;
+      for (int j = 0; j < K1; ++j) acc += Tjy[j * ny + y] * S[j * np + xx];
+      e[(int64_t)(y0 + y) * np + xx] = exp(acc);
+    }
   }
 }
 
@@ -1009,8 +1017,11 @@ void source_matrix(double* FT, int n, int s, double sigma, hipStream_t st) {
 
 void field(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
            hipStream_t st) {
-  const size_t lds = sizeof(double) * ((size_t)K1 * (n + 1) + (size_t)K1 * K1);
-  saa_k_field<<<(unsigned)N, 256, lds, st>>>(xi, S, amp, em, K1, n, N);
+  // band of T rows: K1 * rows <= FIELD_BAND doubles (with K1 <= 64 the block
+  // needs at most 48 KB of LDS)
+  const int rows = std::max(1, std::min(n + 1, FIELD_BAND / K1));
+  const size_t lds = sizeof(double) * ((size_t)K1 * K1 + (size_t)K1 * rows);
+  saa_k_field<<<(unsigned)N, 256, lds, st>>>(xi, S, amp, em, K1, n, rows, N);
 }
 
 template <typename TS>

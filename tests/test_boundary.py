@@ -56,11 +56,9 @@ def test_options_default():
 @pytest.mark.parametrize("field,value", [("n", 3), ("n", 80), ("n", 40), ("n", 0), ("dim", 3), ("n_src_per_dim", 0),
                                          ("src_sigma", 0.0), ("src_sigma", float("nan")), ("kl_per_dim", 0),
                                          ("kl_exp", -1.0), ("reaction", -1.0), ("u_target", float("inf")),
-                                         ("kl_per_dim", 64), ("target", 3), ("target", -1)])
+                                         ("kl_per_dim", 65), ("target", 3), ("target", -1)])
 def test_ctx_create_rejects_bad_problem_before_device_work(field, value):
     p = saa.problem_small()
-    if field == "kl_per_dim" and value == 64:
-        p.n = 256      # LDS table K1 (n+1) + K1^2 too large
     setattr(p, field, value)
     h = ctypes.c_void_p()
     st = saa.lib().saa_ctx_create(ctypes.byref(p.c_struct()), 16, None, ctypes.byref(h))

@@ -286,3 +286,67 @@ def test_multi_with_one_context_equals_single_call(gpu_lib):
     J1, g1, _ = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64))
     assert J == J1 and np.array_equal(g, g1)
     ctx.close()
+
+
+def test_fp32_solver_with_coarse_levels_in_hbm(gpu_lib):
+    """n = 256: the FP32 solver's coarse multigrid levels no longer fit in
+    LDS and stay in HBM (at n <= 128 they live in LDS), and the K1 = 16
+    field table spans three LDS bands.  q_i and dq_i/dz of 4 samples and the
+    CVaR objective against the oracle."""
+    prob = saa.Problem(n=256, kl_per_dim=16, target=saa.TARGET_SIN)
+    print("case 2D n=256 K1=16 fp32_dc64 (coarse levels in HBM)", flush=True)
+    xi = si.kl_coefficients(2411, 4, prob.kl_per_dim)
+    z = si.control(2412)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 4)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP32_DC64))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= 1e-12
+    for i in range(len(q)):
+        assert _rel(g[i], ref["g"][i]) <= 1e-9, (i, _rel(g[i], ref["g"][i]))
+    assert rep["n_unconverged"] == 0
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=saa.FP32_DC64))
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
+    ctx.close()
+
+
+def test_largest_grid_converges_at_second_order(gpu_lib):
+    """n = 4096, the largest grid the library accepts (twelve multigrid
+    levels), is beyond the oracle's reach (its assembly alone takes minutes
+    and tens of GB), so it is checked by properties that hold at any size.
+    The same two samples are solved on n = 256, 512, ..., 4096: the n = 256
+    member equals the oracle, and successive differences of q_h shrink by
+    1/4 (second-order P1 convergence; the oracle's own n = 128, 256, 512
+    sequence gives 0.2501 on these inputs), which a wrong operator, load or
+    QoI on the finer grids would break.  FP64 and FP32-DC64 agree at
+    n = 4096."""
+    xi = si.kl_coefficients(2413, 2, 16)
+    z = si.control(2414)
+    qs, gs = {}, {}
+    for n in (256, 512, 1024, 2048, 4096):
+        prob = saa.Problem(n=n, kl_per_dim=16, target=saa.TARGET_SIN)
+        print(f"case 2D n={n} K1=16 N=2 fp32_dc64", flush=True)
+        ctx = saa.Context(prob, 2)
+        ctx.set_samples(torch.from_numpy(xi).cuda())
+        q, g, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP32_DC64))
+        assert rep["n_unconverged"] == 0, (n, rep)
+        qs[n], gs[n] = q.cpu().numpy(), g.cpu().numpy()
+        if n == 4096:
+            print("case 2D n=4096 fp64", flush=True)
+            q64, g64, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP64))
+            assert rep["n_unconverged"] == 0
+            assert np.max(np.abs(q64.cpu().numpy() - qs[n]) / np.abs(qs[n])) <= 1e-11
+            for i in range(2):
+                assert _rel(gs[n][i], g64.cpu().numpy()[i]) <= 1e-9
+        ctx.close()
+    ops = fem2d.operators(_oprob(saa.Problem(n=256, kl_per_dim=16, target=saa.TARGET_SIN)))
+    for i in range(2):
+        ref = fem2d.solve_sample(ops, xi[i], z)
+        assert abs(qs[256][i] - ref["q"]) <= 1e-12 * abs(ref["q"])
+        assert _rel(gs[256][i], ref["g"]) <= 1e-9
+    ns = sorted(qs)
+    for a, b, c in zip(ns, ns[1:], ns[2:]):
+        ratio = (qs[c] - qs[b]) / (qs[b] - qs[a])
+        print(f"ratio n={a},{b},{c}: {ratio}", flush=True)
+        assert np.all(np.abs(ratio - 0.25) <= 5e-3), (a, b, c, ratio)
