@@ -259,3 +259,43 @@ def test_3d_single_sample(gpu_lib):
     assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
     assert rep["n_adjoints"] == 1
     ctx.close()
+
+
+def test_largest_3d_grid_converges_at_second_order(gpu_lib):
+    """n = 96, the largest cube the library accepts, with the largest KL
+    basis (K1 = 16) and source lattice (s = 4).  The oracle needs minutes per
+    sample from n = 32 on, so the chain n = 12, 24, 48, 96 is checked by
+    properties: the n = 12 member equals the oracle, and successive
+    differences of q_h shrink towards 1/4 (Q1 elements converge at second
+    order; the oracle's own n = 8, 16, 32 sequence gives 0.289 here, still
+    pre-asymptotic, and the excess over 1/4 falls about fourfold per
+    halving).  FP64 and FP32-DC64 agree at n = 96."""
+    xi = si.kl_coefficients(2417, 2, 16, dim=3)
+    z = si.control(2418, d_z=64)
+    qs, gs = {}, {}
+    for n in (12, 24, 48, 96):
+        prob = problem3(n, s=4, K1=16, target=saa.TARGET_SIN)
+        print(f"case 3D n={n} K1=16 s=4 N=2 fp32_dc64", flush=True)
+        ctx = saa.Context(prob, 2)
+        ctx.set_samples(torch.from_numpy(xi).cuda())
+        q, g, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP32_DC64))
+        assert rep["n_unconverged"] == 0, (n, rep)
+        qs[n], gs[n] = q.cpu().numpy(), g.cpu().numpy()
+        if n == 96:
+            print("case 3D n=96 fp64", flush=True)
+            q64, g64, rep = ctx.per_sample(z, opt=saa.options(prec=saa.FP64))
+            assert rep["n_unconverged"] == 0
+            assert np.max(np.abs(q64.cpu().numpy() - qs[n]) / np.abs(qs[n])) <= 1e-11
+            for i in range(2):
+                assert _rel(gs[n][i], g64.cpu().numpy()[i]) <= 1e-9
+        ctx.close()
+    ops = fem3d.operators(_oprob(problem3(12, s=4, K1=16, target=saa.TARGET_SIN)))
+    for i in range(2):
+        ref = fem3d.solve_sample(ops, xi[i], z)
+        assert abs(qs[12][i] - ref["q"]) <= 1e-12 * abs(ref["q"])
+        assert _rel(gs[12][i], ref["g"]) <= 1e-9
+    r1 = (qs[48] - qs[24]) / (qs[24] - qs[12])
+    r2 = (qs[96] - qs[48]) / (qs[48] - qs[24])
+    print(f"ratios n=12,24,48: {r1}  n=24,48,96: {r2}", flush=True)
+    assert np.all((r2 >= 0.23) & (r2 <= 0.28)), r2
+    assert np.all(np.abs(r2 - 0.25) <= 0.5 * np.abs(r1 - 0.25) + 2e-3), (r1, r2)
