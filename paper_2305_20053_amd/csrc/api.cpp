@@ -780,7 +780,10 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   int64_t ks = 0;
   for (int l = 0; l < g.L; ++l) ks += 2 * (int64_t)g.n[l] * g.n[l];
   c->kstride = ks;
-  c->kchunk = N_max < 256 ? N_max : 256;
+  // samples per hierarchy launch: one launch fills the chip with 256 blocks,
+  // and the per-triangle kappa scratch of a launch stays within 4 GiB
+  // (at n = 4096 a sample needs 358 MB of it)
+  c->kchunk = std::max<int64_t>(1, std::min<int64_t>({N_max, 256, ((int64_t)4 << 30) / (8 * ks)}));
 
   int rc = SAA_OK;
   const size_t tw = (size_t)N_max * c->nodes * sizeof(double);
