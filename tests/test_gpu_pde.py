@@ -350,3 +350,28 @@ def test_largest_grid_converges_at_second_order(gpu_lib):
         ratio = (qs[c] - qs[b]) / (qs[b] - qs[a])
         print(f"ratio n={a},{b},{c}: {ratio}", flush=True)
         assert np.all(np.abs(ratio - 0.25) <= 5e-3), (a, b, c, ratio)
+
+
+def test_empty_and_oversized_sample_sets_rejected(gpu_lib):
+    """Empty input: an evaluation before any samples are set, and sample
+    sets of size 0 or above N_max, are rejected with SAA_E_INVALID before
+    any kernel runs, and the context stays usable (a later valid set
+    evaluates against the oracle)."""
+    prob = saa.Problem(n=16, kl_per_dim=4)
+    print("case 2D empty and oversized sample sets", flush=True)
+    ctx = saa.Context(prob, 4)
+    z = si.control(2419)
+    for call in (lambda: ctx.objective_grad(z), lambda: ctx.per_sample(z)):
+        with pytest.raises(saa.SaaError) as e:
+            call()
+        assert e.value.status == saa.SAA_E_INVALID
+    for n in (0, 5):
+        with pytest.raises(saa.SaaError) as e:
+            ctx.set_samples(torch.zeros(n, 4, 4, dtype=torch.float64, device="cuda"))
+        assert e.value.status == saa.SAA_E_INVALID
+    xi = si.kl_coefficients(2420, 4, 4)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    J, grad, rep = ctx.objective_grad(z)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
+    ctx.close()
