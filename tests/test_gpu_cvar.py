@@ -76,3 +76,46 @@ def test_reduction_is_deterministic(data):
     runs = [ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt) for _ in range(3)]
     for J, grad, rep in runs[1:]:
         assert J == runs[0][0] and np.array_equal(grad, runs[0][1]) and rep["t_star"] == runs[0][2]["t_star"]
+
+
+@pytest.fixture(scope="module")
+def many(gpu_lib):
+    """N = 1000003 (not a multiple of any tile): the multi-workgroup passes
+    keep their 256 workgroups and each walks a contiguous chunk of about
+    3900 samples tile by tile, so a workgroup's own active segment can
+    overflow; the 20000-sample set above gives each thread at most one
+    sample.  A 4 x 4 grid keeps the context small (the surrogate form does
+    not touch it)."""
+    prob = saa.Problem(n=4, kl_per_dim=10)
+    N = 1000003
+    xi = si.kl_coefficients(5005, N, prob.kl_per_dim)
+    z = si.control(5006)
+    widths = [R_M + D_Z, 256, 256, 256, 256, R_U]
+    layers = si.random_mlp(5007, widths, bias_scale=0.1)
+    model = saa.Model(R_M, D_Z, R_U, 256, 4)
+    model.set_params(training.flatten(layers).astype(np.float32))
+    rng = np.random.default_rng(5008)
+    model.set_qoi(0.3 * rng.standard_normal(R_U), 0.05)
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    del xi
+    q, g, _ = ctx.per_sample(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.FP32))
+    return ctx, model, z, q.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("beta,eps", [
+    (0.95, 1e-4),
+    (0.5, 1e3),          # every sample inside the smoothing zone: per-workgroup overflow, refinement passes
+])
+def test_reduction_many_samples_per_workgroup(many, beta, eps):
+    ctx, model, z, q, g = many
+    print(f"case cvar N={q.size} beta={beta} eps={eps}", flush=True)
+    opt = saa.options(prec=saa.FP32, beta=beta, eps=eps)
+    J, grad, rep = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
+    ref = cvar.objective(q, g, z, beta, eps, 1e-3)
+    et = abs(rep["t_star"] - ref["t"]) / max(abs(ref["t"]), 1e-300)
+    eJ = abs(J - ref["J"]) / abs(ref["J"])
+    eg = np.linalg.norm(grad - ref["grad"]) / np.linalg.norm(ref["grad"])
+    print(f"  t* rel {et:.2e}; J rel {eJ:.2e}; grad rel {eg:.2e}; dJ/dt {rep['dJ_dt']:.2e}")
+    assert et <= TOL and eJ <= TOL and eg <= TOL
+    assert abs(rep["dJ_dt"]) <= 1e-10
