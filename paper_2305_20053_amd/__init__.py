@@ -189,14 +189,15 @@ class Problem:
 
 def problem_small(target: int = None) -> Problem:
     """n = 32 (1089 nodes), 8 x 8 KL modes: the N = 64 correctness workload;
-    sinusoidal target sin(2 pi x) sin(2 pi y) unless `target` says otherwise."""
-    return Problem(n=32, kl_per_dim=8, target=TARGET_SIN if target is None else target)
+    q = int (u - 0.5)^2 (constant target) unless `target` selects the
+    sinusoidal or quadratic target of Sec. 4.2."""
+    return Problem(n=32, kl_per_dim=8, target=TARGET_CONST if target is None else target)
 
 
 def problem_medium(target: int = None) -> Problem:
     """n = 128 (16641 nodes), 16 x 16 KL modes: the N = 1024 PDE workload;
-    sinusoidal target unless `target` says otherwise."""
-    return Problem(n=128, kl_per_dim=16, target=TARGET_SIN if target is None else target)
+    constant target 0.5 unless `target` says otherwise."""
+    return Problem(n=128, kl_per_dim=16, target=TARGET_CONST if target is None else target)
 
 
 def objective_grad_multi(contexts, zs, opt=None):

@@ -1,6 +1,7 @@
 """Build the C-ABI shared library libsaa.so for gfx950 with hipcc (in-tree)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -27,15 +28,24 @@ def build(verbose: bool = False) -> str:
              # packed FP32 instructions are kept out of all device code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+    cmds = []
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        cmd = [hipcc()] + flags + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append((src, [hipcc()] + flags + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]))
+        objs.append(obj)
+
+    def compile_one(item):
+        src, cmd = item
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, stderr=None if verbose else subprocess.PIPE, text=True)
-        if res.returncode != 0:
-            raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr or ''}")
-        objs.append(obj)
+        return src, res.returncode, res.stderr or ""
+
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for src, rc, err in ex.map(compile_one, cmds):
+            if rc != 0:
+                raise RuntimeError(f"hipcc failed on {src}:\n{err}")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lrocblas"]
     subprocess.run(cmd, check=True)

@@ -968,9 +968,9 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     // device work in a hipGraph; later ones replay it (untimed calls only).
     mrdino_model* m = (mrdino_model*)model;
     SurrogateGraph& sg = c->sg;
-    const SurrogateGraph::Key key{m->serial, opt->prec,      opt->t_mode, opt->beta,       opt->eps,
-                                  opt->alpha, opt->t_in,     c->N,        opt->risk,       opt->risk_kappa,
-                                  opt->risk_tau};
+    const SurrogateGraph::Key key{m->serial, m->version, opt->prec,  opt->t_mode,     opt->beta,
+                                  opt->eps,   opt->alpha,  opt->t_in, c->N,            opt->risk,
+                                  opt->risk_kappa, opt->risk_tau};
     const bool enc_ready = opt->prec == SAA_FP32 || c->enc_rm == m->dims.r_m;
     if (!tm.on && !sg.disabled && !(sg.exec && sg.key == key) && sg.seen == key && enc_ready &&
         (rc = capture_surrogate(c, m, opt, key)))

@@ -113,14 +113,14 @@ constexpr size_t RES_BYTES = RES_STATS + sizeof(CvarStats);
 // kernel, CVaR reduction) and the arguments baked into it.
 struct SurrogateGraph {
   struct Key {
-    uint64_t model = 0;
+    uint64_t model = 0, version = 0;
     int prec = -1, t_mode = 0;
     double beta = 0, eps = 0, alpha = 0, t_in = 0;
     int64_t N = 0;
     int risk = 0;
     double kappa = 0, tau = 0;
     bool operator==(const Key& o) const {
-      return model == o.model && prec == o.prec && t_mode == o.t_mode && beta == o.beta && eps == o.eps &&
+      return model == o.model && version == o.version && prec == o.prec && t_mode == o.t_mode && beta == o.beta && eps == o.eps &&
              alpha == o.alpha && t_in == o.t_in && N == o.N && risk == o.risk && kappa == o.kappa && tau == o.tau;
     }
   };

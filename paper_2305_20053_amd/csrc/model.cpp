@@ -111,6 +111,7 @@ int pack(mrdino_model* m) {
   off[n++] = m->f_w0z;
   off[n] = m->ws_frags;
   saa_launch::mlp_pack_fp8(m->ws.p, off, n, (float*)m->wsc.p, m->ws8.p, m->ws_frags, st);
+  ++m->version;
   return check_hip(hipGetLastError());
 }
 
@@ -220,6 +221,7 @@ int mrdino_set_qoi(mrdino_model* m, const double* c, double c0) {
   }
   m->c0 = c0;
   m->c_host.assign(c, c + m->dims.r_u);
+  ++m->version;
   int rc = check_hip(hipMemcpyAsync(m->c.p, buf.data(), sizeof(float) * W, hipMemcpyHostToDevice, m->st));
   if (!rc) {
     saa_launch::mlp_add_pad((float*)m->bc.p, (const float*)m->bias[m->dims.depth].p, (const float*)m->c.p,

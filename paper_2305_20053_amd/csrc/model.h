@@ -27,6 +27,8 @@ struct mrdino_model {
   std::vector<double> c_host;               // c as given to mrdino_set_qoi (zeros until set)
   void* train = nullptr;                    // training workspace and Adam state (train.cpp)
   uint64_t serial = 0;                      // unique per model object (keys captured graphs)
+  uint64_t version = 0;                     // bumped whenever c, c0 or the packed operands change: a
+                                            // captured graph holds c0 by value, so it keys graphs too
   ~mrdino_model();
 };
 

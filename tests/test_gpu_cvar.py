@@ -9,7 +9,9 @@ the regimes of the t* search: a few probe passes then an active set of a few
 samples (eps = 1e-4), a wide smoothing zone, an active set larger than its
 capacity (eps far above, or comparable to, the spread of q: multi-workgroup
 refinement passes then a secant step), beta = 0 (degenerate minimiser), a tail of 20 samples, and a
-prescribed t.  Tolerance: 1e-12 relative (only the summation order differs).
+prescribed t.  Tolerance: 1e-12 relative on J and grad J (only the
+summation order differs); t* to 1e-14 relative, since grad J moves with t*
+through s_eps'' (at most 1.5 / eps).
 """
 import numpy as np
 import pytest
@@ -23,6 +25,7 @@ pytestmark = pytest.mark.gpu
 
 R_M, D_Z, R_U = 100, 25, 200
 TOL = 1e-12
+TOL_T = 1e-14
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +67,7 @@ def test_reduction_matches_oracle(data, beta, eps, t_mode):
     eg = np.linalg.norm(grad - ref["grad"]) / np.linalg.norm(ref["grad"])
     ed = abs(rep["dJ_dt"] - ref["dJdt"])
     print(f"  t* {rep['t_star']:.17g} rel {et:.2e}; J rel {eJ:.2e}; grad rel {eg:.2e}; dJ/dt diff {ed:.2e}")
-    assert et <= TOL and eJ <= TOL and eg <= TOL
+    assert et <= TOL_T and eJ <= TOL and eg <= TOL
     assert ed <= 1e-10
     if t_mode == 0:
         assert abs(rep["dJ_dt"]) <= 1e-10          # stationarity in t
@@ -117,5 +120,5 @@ def test_reduction_many_samples_per_workgroup(many, beta, eps):
     eJ = abs(J - ref["J"]) / abs(ref["J"])
     eg = np.linalg.norm(grad - ref["grad"]) / np.linalg.norm(ref["grad"])
     print(f"  t* rel {et:.2e}; J rel {eJ:.2e}; grad rel {eg:.2e}; dJ/dt {rep['dJ_dt']:.2e}")
-    assert et <= TOL and eJ <= TOL and eg <= TOL
+    assert et <= TOL_T and eJ <= TOL and eg <= TOL
     assert abs(rep["dJ_dt"]) <= 1e-10

@@ -172,3 +172,45 @@ def test_graph_replay_matches_eager(setup):
         assert J1 == Je and np.array_equal(g1, ge) and J1 != eager[0][0]
     finally:
         model.set_params(p)
+
+
+def test_graph_replay_after_set_qoi(setup):
+    """A captured surrogate graph must not outlive a change of the reduced-QoI
+    terms c, c0 (Sec. 3.3: q = |phi + c|^2 + c0): after set_qoi, replays on the
+    main context and on the held-out context of the error estimate are
+    bitwise equal to eager evaluations with the new terms."""
+    prob, xi, z, model, ctx, q_ref, g_ref = setup
+    hold = saa.Context(prob, 48)
+    hold.set_samples(torch.from_numpy(si.kl_coefficients(4005, 48, prob.kl_per_dim)).cuda())
+    saa.attach_holdout(ctx, hold)
+    c_old = 0.3 * np.random.default_rng(4004).standard_normal(R_U)   # the fixture's c, c0 = 0.05
+    rng = np.random.default_rng(4006)
+    c_new = 0.3 * rng.standard_normal(R_U)
+    c0_new = 0.11
+    opt = saa.options(prec=saa.BF16, fallback_tol=1e30)
+    try:
+        for _ in range(3):      # capture on the second call, replay from the third
+            J0, g0, r0 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
+        for _ in range(3):
+            hold.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
+        assert r0["graph"] == 1
+        model.set_qoi(c_new, c0_new)
+        J1, g1, r1 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
+        J2, g2, r2 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
+        Je, ge, _ = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16, timing=1))
+        assert J1 == Je and J2 == Je and np.array_equal(g1, ge) and np.array_equal(g2, ge)
+        assert r2["graph"] == 1 and J1 != J0
+        # held-out context: its own replay against its eager evaluation, and
+        # the error estimate of the main call recomputed from eager values
+        Jh, gh, rh = hold.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
+        Jh2, gh2, rh2 = hold.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16))
+        Jhe, ghe, _ = hold.objective_grad(z, form=saa.FORM_MRDINO, model=model,
+                                          opt=saa.options(prec=saa.BF16, timing=1))
+        assert rh2["graph"] == 1 and Jh2 == Jhe and np.array_equal(gh2, ghe) and Jh == Jhe
+        Jp, gp, _ = hold.objective_grad(z, form=saa.FORM_PDE, opt=saa.options(prec=saa.FP32_DC64))
+        err = max(abs(Jhe - Jp) / abs(Jp), np.linalg.norm(ghe - gp) / np.linalg.norm(gp))
+        assert abs(r2["err_estimate"] - err) <= 1e-12 * err
+    finally:
+        saa.attach_holdout(ctx, None)
+        model.set_qoi(c_old, 0.05)
+        hold.close()

@@ -23,7 +23,7 @@ LB, UB = -1.5, 1.5
 
 @pytest.fixture(scope="module")
 def pde(gpu_lib):
-    prob = saa.problem_small()
+    prob = saa.problem_small(target=saa.TARGET_SIN)
     xi = si.kl_coefficients(si.SEED_XI_SMALL, 16, prob.kl_per_dim)
     oprob = fem2d.Problem2D(n=prob.n, kl_per_dim=prob.kl_per_dim, target=prob.target)
 

@@ -3,6 +3,9 @@
 Tolerances (relative, 2-norm): FP64 and FP32-in-FP64-defect-correction paths
 1e-9 on J and grad J; pure FP32 1e-4.  t* to 1e-14 relative.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -64,10 +67,10 @@ def test_small_objective(small, prec):
     assert 2 <= rep["newton_max"] <= 8
 
 
-@pytest.mark.parametrize("target", [saa.TARGET_CONST, saa.TARGET_QUAD])
+@pytest.mark.parametrize("target", [saa.TARGET_SIN, saa.TARGET_QUAD])
 def test_other_targets_per_sample(gpu_lib, target):
     """The other tracking targets of Sec. 4.2 (the small fixture uses the
-    sinusoidal one): q_i and dq_i/dz of 16 samples, FP64."""
+    constant one, q = int (u - 0.5)^2): q_i and dq_i/dz of 16 samples, FP64."""
     prob = saa.problem_small(target=target)
     print(f"case target={target} per_sample", flush=True)
     xi = si.kl_coefficients(si.SEED_XI_SMALL, 16, prob.kl_per_dim)
@@ -187,6 +190,55 @@ def test_medium_sampled_parity(medium, prec):
     assert abs(J - r["J"]) <= 1e-12 * abs(r["J"])
     assert _rel(grad, r["grad"]) <= 1e-10
     assert abs(rep2["t_star"] - r["t"]) <= 1e-14 * abs(r["t"])
+
+
+GOLDEN_2D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pde2d_n128_N1024.json")
+
+
+@pytest.fixture(scope="module")
+def medium_gold(medium):
+    """Oracle q_i, dq_i/dz of all 1024 samples of the n = 128 workload
+    (written by tests/golden/make_pde2d_n128.py, which calls only the
+    oracle) and the oracle's CVaR objective on them."""
+    prob, xi, z, ctx = medium
+    with open(GOLDEN_2D) as f:
+        gold = json.load(f)
+    assert (gold["n"], gold["N"], gold["kl_per_dim"], gold["target"]) == (prob.n, 1024, prob.kl_per_dim, "const")
+    assert gold["seed_xi"] == si.SEED_XI_MEDIUM and gold["seed_z"] == si.SEED_Z_EVAL[0]
+    assert prob.target == saa.TARGET_CONST and prob.u_target == gold["u_target"]
+    q, g = np.asarray(gold["q"]), np.asarray(gold["g"])
+    return q, g, cvar.objective(q, g, z, 0.95, 1e-4, 1e-3)
+
+
+@pytest.mark.parametrize("prec", [saa.FP32_DC64, saa.FP64, saa.FP32])
+def test_medium_full_parity(medium, medium_gold, prec):
+    """n = 128, N = 1024, q = int (u - 0.5)^2, in the launch the benchmark
+    times: every sample's q_i (1e-12) and dq_i/dz (1e-9) against the oracle
+    for FP64 and FP32-DC64; J and grad J against the oracle's objective at
+    1e-9 (FP64, FP32-DC64) and 1e-4 (pure FP32); t* against the oracle's
+    root on the GPU's own q_i at 1e-14 and on the oracle's q_i at the q_i
+    tolerance."""
+    prob, xi, z, ctx = medium
+    q_o, g_o, ref = medium_gold
+    print(f"case medium full N=1024 prec={prec}", flush=True)
+    q, g, rep = ctx.per_sample(z, opt=saa.options(prec=prec))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert rep["n_unconverged"] == 0
+    eq = np.abs(q - q_o) / np.abs(q_o)
+    eg = np.linalg.norm(g - g_o, axis=1) / np.linalg.norm(g_o, axis=1)
+    print(f"  q_i max rel {eq.max():.2e}, g_i max rel {eg.max():.2e}", flush=True)
+    if prec != saa.FP32:
+        assert eq.max() <= 1e-12 and eg.max() <= 1e-9
+    else:
+        assert eq.max() <= 1e-5 and eg.max() <= 1e-4
+    J, grad, rep2 = ctx.objective_grad(z, opt=saa.options(prec=prec))
+    tol = TOL[prec]
+    eJ, eG = abs(J - ref["J"]) / abs(ref["J"]), _rel(grad, ref["grad"])
+    print(f"  J rel {eJ:.2e}, grad rel {eG:.2e}, adjoints {rep2['n_adjoints']}", flush=True)
+    assert eJ <= tol and eG <= tol
+    own = cvar.objective(q, g, z, 0.95, 1e-4, 1e-3)
+    assert abs(rep2["t_star"] - own["t"]) <= 1e-14 * abs(own["t"])
+    assert abs(rep2["t_star"] - ref["t"]) <= (1e-11 if prec != saa.FP32 else 1e-5) * abs(ref["t"])
 
 
 def test_medium_fp32_vs_fp64(medium):

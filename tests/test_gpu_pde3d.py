@@ -156,10 +156,11 @@ def test_full_size_sampled_outputs(full3):
     for key, ref in gold["samples"].items():
         i = int(key)
         # q = u^T M u - 2 u^T M ut + ut^T M ut cancels about 7x here (0.2155
-        # from 0.25): the Newton stop at 1e-13 relative updates leaves q_i
-        # errors of a few 1e-13, so q_i is held to 1e-10 (J and grad to the
-        # 1e-9 of the PDE form)
-        assert abs(q[i] - ref["q"]) <= 1e-10 * abs(ref["q"]), (i, q[i], ref["q"])
+        # from 0.25): the Newton stop at 1e-13 relative updates and the
+        # stored values' CG solves (relative residual 1e-14) leave q_i errors
+        # of a few 1e-13 absolute, about 1e-12 relative; held to 5e-12
+        print("q rel err", i, abs(q[i] - ref["q"]) / abs(ref["q"]), "g rel err", _rel(g[i], ref["g"]), flush=True)
+        assert abs(q[i] - ref["q"]) <= 5e-12 * abs(ref["q"]), (i, q[i], ref["q"])
         assert _rel(g[i], ref["g"]) <= 1e-9, (i, _rel(g[i], ref["g"]))
     assert rep["n_unconverged"] == 0
 

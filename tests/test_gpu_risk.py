@@ -73,7 +73,7 @@ def test_reduction_matches_oracle(surr, kind):
 
 @pytest.fixture(scope="module")
 def pde(gpu_lib):
-    prob = saa.problem_small()
+    prob = saa.problem_small(target=saa.TARGET_SIN)
     xi = si.kl_coefficients(si.SEED_XI_SMALL, 64, prob.kl_per_dim)
     z = si.control(si.SEED_Z_SMALL)
     oref = osaa.objective_grad(fem2d.Problem2D(n=prob.n, kl_per_dim=prob.kl_per_dim, target=prob.target), xi, z)
