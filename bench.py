@@ -44,6 +44,17 @@ BYTES_VCYCLE_FINE_F32 = 74
 BYTES_NEWTON_F64 = 73
 BYTES_SAMPLE = 24
 
+# The roofline's algorithmic bytes use the per-unit model of the workload's
+# scope table instead (it also counts the coarse multigrid levels, as if
+# they lived in HBM): 190 B per unknown per PCG iteration (stencil with kappa
+# recomputed from exp(m) 16 B, PCG vectors 40 B, V-cycle about 4
+# stencil-equivalents x 20 B x 4/3 plus transfers) and 40 B per unknown per
+# Newton step (FP64 residual, update and QoI, 5 x 8 B).  The narrower count
+# above (passes as they run, coarse levels in LDS not counted) is reported
+# next to it.
+MODEL_BYTES_PCG_ITER = 190
+MODEL_BYTES_NEWTON = 40
+
 
 # The same for the 3D state kernel (trilinear elements, 21-point stencil with
 # one kappa per element; all multigrid levels in HBM), FP32 solver arrays:
@@ -100,8 +111,10 @@ def cpu_baseline(prob, xi, z, seconds_target=15.0):
     osaa.per_sample_parallel(oprob, xi[:n_s], z, workers=workers)
     wall = time.perf_counter() - t
     return {"value": n_s / wall, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "usable_cores": usable,
             "sample": f"first {n_s} of the {len(xi)} samples at n={prob.n}: Newton with sparse LU, "
-                      f"QoI and adjoint per sample (float64 scipy), {workers} worker processes, {wall:.1f} s"}
+                      f"QoI and adjoint per sample (float64 scipy), {workers} worker processes "
+                      f"(one per usable core, at most 16), {wall:.1f} s, run before the GPU is touched"}
 
 
 # admissible box of the controls (Sec. 4.2), also the training control law
@@ -116,23 +129,28 @@ VEC_FP32_PEAK_TFLOPS = 157.3
 MRDINO_FLOP_PER_SAMPLE = 2 * (125 * 256 + 3 * 256 ** 2 + 256 * 200) + 2 * (200 * 256 + 3 * 256 ** 2 + 256 * 25)
 
 
-def train_surrogate(saa, si, epochs):
+def train_surrogate(saa, si, epochs, lo=0.0, hi=1.0, n_pod=2048):
     """The MR-DINO of the 128 x 128 problem (Sec. 3.3-3.4): 2048 training
-    samples (xi seed 2307, z ~ U[-4,4]^25 seed 2308, the admissible box of
-    Sec. 4.2) solved by the GPU PDE form
-    with their 25 control Jacobians, weighted POD of 1024 snapshots to r_u = 200,
-    r_m = 100 KL inputs, width 256 x depth 4 GELU network, DINO loss, Adam
-    lr 1e-3 -> 2.5e-4 at half the epochs, batch 256, FP32 training kernels."""
+    samples (xi seed 2307, z ~ U[lo, hi]^25 seed 2308) solved by the GPU PDE
+    form with their 25 control Jacobians, weighted POD of n_pod snapshots to
+    r_u = 200, r_m = 100 KL inputs, width 256 x depth 4 GELU network, DINO
+    loss, Adam lr 1e-3 -> 2.5e-4 at half the epochs, batch 256, products in
+    BF16 with FP32 accumulation and FP32 master weights."""
     import numpy as np
     import torch
     prob = saa.problem_medium()
     t0 = time.perf_counter()
     ctx = saa.Context(prob, 2048)
     ctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_TRAIN, 2048, prob.kl_per_dim)).cuda())
-    Zt = torch.from_numpy(si.controls(si.SEED_Z_TRAIN, 2048, lo=Z_LO, hi=Z_HI)).cuda()
-    data = saa.TrainData(ctx, Zt, r_m=100, r_u=200, n_pod=1024)
+    Zt = torch.from_numpy(si.controls(si.SEED_Z_TRAIN, 2048, lo=lo, hi=hi)).cuda()
+    data = saa.TrainData(ctx, Zt, r_m=100, r_u=200, n_pod=n_pod)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    # held-out reduced errors on 256 validation samples (xi 2309, z 2310) in the training basis
+    vctx = saa.Context(prob, 256)
+    vctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_VALID, 256, prob.kl_per_dim)).cuda())
+    vdata = saa.TrainData(vctx, torch.from_numpy(si.controls(si.SEED_Z_VALID, 256, lo=lo, hi=hi)).cuda(),
+                          r_m=100, r_u=200, basis=data)
     model = saa.Model(100, 25, 200, 256, 4)
     layers = si.glorot_mlp(2315, model.widths())
     model.set_params(np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers]))
@@ -140,14 +158,19 @@ def train_surrogate(saa, si, epochs):
     model.set_qoi(c, c0)
     t0 = time.perf_counter()
     hist, _ = saa.train(model, data, saa.train_cfg(batch=256, epochs=epochs, lr_drop_epoch=epochs // 2, dino=1,
-                                                   seed=7))
+                                                   seed=7, prec=saa.BF16))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     es, ej = saa.data_errors(model, data)
-    qoi = {t: data.qoi(t) for t in (saa.TARGET_SIN, saa.TARGET_QUAD)}   # one network, several objectives
-    info = {"train_samples": 2048, "z_box": [Z_LO, Z_HI], "n_pod": 1024, "r_m": 100, "r_u": 200, "epochs": epochs, "batch": 256,
+    vs, vj = saa.data_errors(model, vdata)
+    qoi = {t: data.qoi(t) for t in (saa.TARGET_CONST, saa.TARGET_SIN, saa.TARGET_QUAD)}   # one network, several objectives
+    info = {"train_samples": 2048, "z_box": [lo, hi], "n_pod": n_pod, "r_m": 100, "r_u": 200, "epochs": epochs,
+            "batch": 256, "steps": epochs * (2048 // 256), "precision": "bf16 products, fp32 accumulation and master",
             "data_s": t_data, "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
-            "train_rel_err_state": es, "train_rel_err_jacobian": ej}
+            "train_rel_err_state": es, "train_rel_err_jacobian": ej,
+            "heldout_rel_err_state": vs, "heldout_rel_err_jacobian": vj}
+    vdata.close()
+    vctx.close()
     data.close()
     ctx.close()
     return model, info, qoi
@@ -190,18 +213,23 @@ def measure_ceilings():
 
 
 def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True, ceil=None):
-    """Surrogate form at N = 65536 samples (n = 128 KL field, 16 x 16 modes):
-    the trained MR-DINO (or random Glorot weights with epochs = 0) in BF16 and
-    FP32, timed like the PDE form; its error against the GPU PDE form on 256
-    held-out samples (xi seed 2312) at the five evaluation controls, with the
-    PDE fallback rule at 1e-2."""
+    """Surrogate form at N = 65536 samples (n = 128 KL field, 16 x 16 modes,
+    q = int (u - 0.5)^2): the MR-DINO trained as in the training workload (z ~
+    U[0,1]^25, POD of all 2048 training states; random Glorot weights with
+    epochs = 0) in BF16, FP8 and FP32, timed like the PDE form at the same
+    evaluation controls; its error against the GPU PDE form on 256 held-out
+    samples (xi seed 2312) at the five controls, timed separately.  The
+    MR-DINO / PDE-form ratio is quoted only when that estimate is at most the
+    stated 1e-2; otherwise the throughput of the call with the PDE fallback
+    is reported instead.  The OUU experiment of Sec. 4.2 (box [-4, 4]^25)
+    uses a second network trained on controls drawn from that box."""
     import numpy as np
     import torch
     prob = saa.problem_medium()
     N = 65536
     qoi = None
     if epochs > 0:
-        model, tinfo, qoi = train_surrogate(saa, si, epochs)
+        model, tinfo, qoi = train_surrogate(saa, si, epochs, 0.0, 1.0, 2048)
     else:
         model = saa.Model(100, 25, 200, 256, 4)
         layers = si.glorot_mlp(2313, model.widths())
@@ -246,9 +274,9 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True, ceil=N
         Jb, gb, _ = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=prec))
         out[f"{name}_vs_fp32"] = {"J_rel": abs(Jb - Jf) / abs(Jf),
                                   "grad_rel": float(np.linalg.norm(gb - gf) / np.linalg.norm(gf))}
-    # error estimate against the GPU PDE form on the held-out samples; the
-    # fallback rule (estimate > 1e-2) is evaluated here, not executed (the
-    # fallback path itself is exercised by tests/test_gpu_gain.py)
+    # error estimate against the GPU PDE form on the held-out samples (timed
+    # separately from the surrogate evaluation)
+    tol = 1e-2
     hold = saa.Context(prob, 256)
     hold.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_HELDOUT, 256, prob.kl_per_dim)).cuda())
     saa.attach_holdout(ctx, hold)
@@ -260,19 +288,44 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True, ceil=N
                                            opt=saa.options(prec=prec, fallback_tol=1e30))
             errs.append(rep["err_estimate"])
         wall = time.perf_counter() - t0
-        out[name]["heldout"] = {"err_estimate": errs, "max": max(errs), "tol": 1e-2,
-                                "would_fall_back": int(sum(e > 1e-2 for e in errs)), "samples": 256,
+        out[name]["heldout"] = {"err_estimate": errs, "max": max(errs), "tol": tol,
+                                "would_fall_back": int(sum(e > tol for e in errs)), "samples": 256,
                                 "ms_per_step_with_estimate": 1e3 * wall / len(zs)}
+    met = out["bf16"]["heldout"]["max"] <= tol
+    stated = {"tol": tol, "bf16_max_err_estimate": out["bf16"]["heldout"]["max"], "met": bool(met),
+              "estimate_ms_per_call": out["bf16"]["heldout"]["ms_per_step_with_estimate"] - out["bf16"]["ms_per_step"]}
+    if met:
+        stated["ratio_bf16_over_pde"] = out["bf16"]["value"] / pde_value
+        stated["quoted"] = "MR-DINO BF16 samples/s / PDE-form samples/s (estimate within tol at every control)"
+    else:
+        # what a caller gets under the rule: the PDE form on the same samples
+        opt = saa.options(prec=saa.BF16, fallback_tol=tol)
+        ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nfb = 2
+        for k in range(nfb):
+            r = ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model, opt=opt)[2]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stated["fallback_value"] = N * nfb / wall
+        stated["fallback_used"] = r["fallback_used"]
+        stated["ratio_with_fallback_over_pde"] = stated["fallback_value"] / pde_value
+        stated["quoted"] = "estimate above tol: throughput of the call with the PDE fallback"
     saa.attach_holdout(ctx, None)
     out["N"] = N
+    out["stated_error"] = stated
+    out["ratio_bf16_over_pde_unqualified"] = out["bf16"]["value"] / pde_value
     out["weights"] = ("trained MR-DINO (DINO loss, GPU PDE-form data)" if tinfo else
                       "random Glorot init (throughput does not depend on the values)")
     if tinfo:
         out["training"] = tinfo
-    out["ratio_bf16_over_pde"] = out["bf16"]["value"] / pde_value
     hold.close()
     if qoi is not None and ouu:
-        out["ouu"] = bench_ouu(saa, si, model, qoi, ctx)
+        model_box, tinfo_box, qoi_box = train_surrogate(saa, si, epochs, Z_LO, Z_HI, 2048)
+        out["ouu"] = bench_ouu(saa, si, model_box, qoi_box, ctx)
+        out["ouu"]["training"] = tinfo_box
+        model_box.close()
         out["jacobian_modes"] = bench_jacobian_modes(saa, si)
     model.close()
     ctx.close()
@@ -343,7 +396,7 @@ def bench_pde3d(saa, si, steps, warmup):
 
 def bench_companions(saa, si, steps, warmup):
     """The 2D instances that accompany the 3D workload: n = 64, 96 and 128
-    (sinusoidal target, 16 x 16 KL modes), N = 256 samples each, FP32-DC64:
+    (constant target 0.5, 16 x 16 KL modes), N = 256 samples each, FP32-DC64:
     each in its own launch sequence, then all three in one state launch and
     one adjoint launch (saa_objective_grad_multi)."""
     import torch
@@ -351,7 +404,7 @@ def bench_companions(saa, si, steps, warmup):
     zs = [si.control(s) for s in si.SEED_Z_EVAL]
     opt = saa.options(prec=saa.FP32_DC64)
     for n in (64, 96, 128):
-        prob = saa.Problem(n=n, kl_per_dim=16, target=saa.TARGET_SIN)
+        prob = saa.Problem(n=n, kl_per_dim=16, target=saa.TARGET_CONST)
         xi = si.kl_coefficients(si.SEED_XI_3D, 256, prob.kl_per_dim)
         ctx = saa.Context(prob, 256)
         ctx.set_samples(torch.from_numpy(xi).cuda())
@@ -486,17 +539,21 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import paper_2305_20053_amd as saa
     import saa_inputs as si
 
-    saa.require_gpu()
-    prec = {"fp64": saa.FP64, "fp32": saa.FP32, "fp32_dc64": saa.FP32_DC64}[args.prec]
     prob = saa.problem_medium()
     N = 1024
     xi = si.kl_coefficients(si.SEED_XI_MEDIUM, N, prob.kl_per_dim)
     zs = [si.control(s) for s in si.SEED_Z_EVAL]
+    # the CPU oracle runs first, so that its worker processes never fork from
+    # a process that holds the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(prob, xi, zs[0])
+
+    import torch
+    saa.require_gpu()
+    prec = {"fp64": saa.FP64, "fp32": saa.FP32, "fp32_dc64": saa.FP32_DC64}[args.prec]
     ctx = saa.Context(prob, N)
     ctx.set_samples(torch.from_numpy(xi).cuda())
     opt = saa.options(prec=prec)
@@ -521,12 +578,14 @@ def main():
     per_iter = (BYTES_PCG_ITER_F32 + coarse) * s_bytes / 4
     per_start = (BYTES_PCG_START_F32 + coarse) * s_bytes / 4
     topt = saa.options(prec=prec, timing=1)
-    reps, rates, launch_bytes = [], [], []
+    reps, rates, launch_bytes, run_bytes = [], [], [], []
     for k in range(min(args.steps, 5)):
         rep = ctx.objective_grad(zs[k % len(zs)], opt=topt)[2]
         st = ctx.sample_status()
         lin_state, newton_total = int(st[2].sum()), int(st[1].sum())
-        b = d_u * (per_iter * lin_state + (BYTES_NEWTON_F64 + per_start) * newton_total + BYTES_SAMPLE * N)
+        b = d_u * (MODEL_BYTES_PCG_ITER * s_bytes / 4 * lin_state + MODEL_BYTES_NEWTON * newton_total)
+        run_bytes.append(d_u * (per_iter * lin_state + (BYTES_NEWTON_F64 + per_start) * newton_total +
+                                BYTES_SAMPLE * N))
         reps.append(rep)
         launch_bytes.append(b)
         rates.append(b / (rep["ms_state"] * 1e-3) / 1e9)
@@ -563,14 +622,18 @@ def main():
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "fp32_dc64": "f32+f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "PDE form: 128x128 P1 semilinear elliptic (16641 nodes, 16129 unknowns), "
-                               "N=1024 KL samples (16x16 modes), 25 sources, sinusoidal target, "
-                               f"smoothed CVaR_0.95, precision {args.prec}",
+                               "N=1024 KL samples (16x16 modes), 25 sources, q = int (u - 0.5)^2, "
+                               f"smoothed CVaR_0.95 + 1e-3/2 |z|^2, z ~ U[0,1]^25, precision {args.prec}",
                    "n": prob.n, "N": N, "form": "pde", "prec": args.prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "measured_copy_GBps": copy_gbs, "frac_vs_copy": achieved / copy_gbs,
                      "measured_triad_GBps": ceil["triad_GBps"], "frac_vs_triad": achieved / ceil["triad_GBps"],
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "saa_k_state", "alg_bytes_per_launch": bytes_launch,
+                     "byte_model": "190 B per unknown per PCG iteration + 40 B per unknown per Newton step "
+                                   "(x2 for the FP64 solver's PCG), iteration counts of each timed call",
+                     "as_run_bytes_per_launch": float(np.mean(run_bytes)),
+                     "frac_as_run": float(np.mean(run_bytes)) / (ms_state * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "kernel_ms": ms_state},
         "phases_ms": {"state": ms_state, "adjoint": ms_adj, "reduce": ms_red},
         "solver": {"newton_total": newton_total, "pcg_state_iters": lin_state,
@@ -586,12 +649,11 @@ def main():
         r3["frac_vs_triad"] = r3["achieved"] / ceil["triad_GBps"]
         out["pde3d"]["companions_2d_N256"] = bench_companions(saa, si, args.steps, args.warmup)
     if not args.no_mrdino:
-        zs_box = [si.control(s, lo=Z_LO, hi=Z_HI) for s in si.SEED_Z_EVAL]
-        out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs_box, value, args.train_epochs,
+        out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs, value, args.train_epochs,
                                      not args.no_ouu, ceil)
     out["ceilings"] = ceil
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, xi, zs[0])
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

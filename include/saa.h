@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SAA_ABI_VERSION 2
+#define SAA_ABI_VERSION 3
 
 /* Status codes. */
 enum {
@@ -95,7 +95,9 @@ enum { SAA_FP64 = 0, SAA_FP32 = 1, SAA_FP32_DC64 = 2, SAA_BF16 = 3, SAA_FP8 = 4 
  * source, consistent Q1 mass in the QoI; the sinusoidal target is
  * sin(2 pi x) sin(2 pi y) sin(2 pi z).  PDE form only: the MR-DINO form,
  * saa_solve_states and the training calls return SAA_E_INVALID; N_max up to
- * 2^20. */
+ * min(2^20, floor((2^32 - 1) / (256 (n + 1)))), so that every launch grid
+ * (N (n + 1) workgroups of 256 threads for the field) fits 2^32 - 1
+ * work-items: 172960 at n = 96, 986895 at n = 16. */
 typedef struct saa_problem {
   int dim;             /* 2, or 3 (see above) */
   int n;               /* cells per side; 2D: 2^k or 3 * 2^k, 4 <= n <= 4096 */
@@ -222,7 +224,9 @@ int saa_options_default(saa_options* opt);
  * workspaces of a precision are allocated at its first use), plus d_Z x
  * (n+1)^2 doubles of source matrix and at most 4 GiB of set-up scratch for
  * saa_set_samples; SAA_E_OOM when an allocation fails, SAA_E_INVALID for a
- * problem outside the ranges above (checked before any device work). */
+ * problem outside the ranges above or N_max outside 1 .. 4194303 in 2D (one
+ * 1024-thread workgroup per sample must fit a grid of 2^32 - 1 work-items;
+ * the 3D bound is stated above), checked before any device work. */
 int saa_ctx_create(const saa_problem* prob, int64_t N_max, void* hip_stream, saa_ctx** out);
 
 /* Free a context and everything it owns (NULL is ignored). */
@@ -315,14 +319,18 @@ int mrdino_create(const mrdino_dims* dims, void* hip_stream, mrdino_model** out)
 /* Free a model (NULL is ignored). */
 void mrdino_free(mrdino_model* model);
 
-/* Save a model (dimensions, FP32 parameters, c, c0) to a file, and load one
- * into a new model whose device work runs on `hip_stream`.  Format: the bytes
- * "SAADINO1", uint32 version 1, int32 r_m d_z r_u width depth, int64
- * n_params, float64 c0, float64 c[r_u], float32 params[n_params] and the
- * 64-bit FNV-1a hash of all preceding bytes, in native byte order.  Loading
+/* Save a model (dimensions, FP32 parameters, c, c0 and, once trained, the
+ * optimiser state) to a file, and load one into a new model whose device work
+ * runs on `hip_stream`.  Format: the bytes "SAADINO1", uint32 version 2, int32
+ * r_m d_z r_u width depth, int64 n_params, float64 c0, float64 c[r_u], float32
+ * params[n_params], int32 has_train and, when it is 1, int64 Adam step, int64
+ * completed epochs, uint64 minibatch-stream state, float32 m[n_params],
+ * float32 v[n_params]; then the 64-bit FNV-1a hash of all preceding bytes, in
+ * native byte order.  Version 1 files (no has_train field) also load.  Loading
  * validates the whole file before any device work: a missing, truncated,
- * altered or unsupported file returns SAA_E_IO and *out stays NULL.  Training
- * state (Adam moments) is not saved. */
+ * altered or unsupported file returns SAA_E_IO and *out stays NULL.  A loaded
+ * model with optimiser state continues training exactly where the saved one
+ * stopped (mrdino_train_cfg.resume = 1). */
 int mrdino_save(const mrdino_model* model, const char* path);
 /* Dimensions of a model (e.g. one returned by mrdino_load). */
 int mrdino_get_dims(const mrdino_model* model, mrdino_dims* dims);
@@ -406,11 +414,15 @@ int mrdino_data_get(const mrdino_data* data, int which, void* host, int64_t n);
 
 /* Batch-mean training loss L = 1/B sum_b |phi_b - y_b|^2 + |dphi_b/dz - J_b|_F^2
  * (dino = 1; dino = 0 drops the Jacobian term: the L2-only MR-NO loss) of the
- * data rows idx (host, B indices) in FP32, and its gradient (host, n_params
- * floats, packed order; may be NULL) by the hand-written reverse pass through
- * the forward-mode Jacobian recurrence. */
-int mrdino_loss_grad(mrdino_model* model, mrdino_data* data, const int* idx, int B, int dino, double* loss,
-                     float* grad);
+ * data rows idx (host, B indices), and its gradient (host, n_params floats,
+ * packed order; may be NULL) by the hand-written reverse pass through the
+ * forward-mode Jacobian recurrence (Sec. 3.4,
+ * eq. (reduced_basis_derivative_equivalence)).  prec: SAA_BF16 (products with
+ * BF16 operands and FP32 accumulation, the training precision) or SAA_FP32
+ * (FP32 operands); elementwise work and the loss sums are FP32 / FP64 either
+ * way.  Other precisions return SAA_E_INVALID. */
+int mrdino_loss_grad(mrdino_model* model, mrdino_data* data, const int* idx, int B, int dino, int prec,
+                     double* loss, float* grad);
 
 typedef struct mrdino_train_cfg {
   int batch;          /* minibatch size */
@@ -420,14 +432,21 @@ typedef struct mrdino_train_cfg {
   double beta1, beta2, adam_eps;
   int dino;           /* 1: DINO loss (MR-DINO); 0: L2-only loss (MR-NO) */
   uint64_t seed;      /* minibatch order: splitmix64 stream, Fisher-Yates per epoch */
+  int prec;           /* SAA_BF16 (BF16 operands, FP32 accumulation and master weights) or SAA_FP32 */
+  int resume;         /* 0: new optimisation (Adam moments zero, epoch clock 0, stream from seed);
+                         1: continue the model's optimiser state (e.g. from mrdino_load) */
 } mrdino_train_cfg;
 
 /* Train the model's FP32 parameters with Adam (the optimiser of Sec. 4.2.1) on
  * the data; every epoch visits floor(N / batch) minibatches of a fresh
- * permutation.  Adam moments persist in the model across calls.  On return the
- * device operands are repacked and the model's reduced-QoI terms are set from
- * the data.  epoch_loss (host, epochs, may be NULL) receives the mean loss of
- * each epoch; seconds (may be NULL) the device time of the loop. */
+ * permutation.  The optimiser state (Adam moments and step, completed epochs,
+ * which drive lr_drop_epoch, and the minibatch stream) lives in the model:
+ * cfg.resume = 1 continues it, so k epochs then m more give bitwise the same
+ * parameters as k + m epochs in one call.  On return the device operands are
+ * repacked and the model's reduced-QoI terms are set from the data.
+ * epoch_loss (host, epochs, may be NULL) receives the mean loss of each epoch;
+ * seconds (may be NULL) the device time of the loop.  Invalid settings return
+ * SAA_E_INVALID before any device work; a failed launch SAA_E_DEVICE. */
 int mrdino_train(mrdino_model* model, mrdino_data* data, const mrdino_train_cfg* cfg, double* epoch_loss,
                  double* seconds);
 
@@ -500,6 +519,27 @@ int saa_ouu_options_default(saa_ouu_options* oo);
  * solve with z at the last accepted iterate. */
 int saa_ouu_solve(saa_ctx* ctx, int form, const void* model, const saa_options* opt, const saa_ouu_options* oo,
                   const double* lb, const double* ub, double* z, saa_ouu_report* report);
+
+/* Largest sample count of saa_risk_reduce (its per-workgroup counters are 32-bit). */
+#define SAA_REDUCE_MAX_N 2147483647LL
+
+/* The risk reduction alone (Sec. 2.1-2.2, eq. (CVaR_saa_ouu) and the chain
+ * rule of eq. (ouu_risk_gradient)) on per-sample values the caller already
+ * holds: q_dev (N float64) and g_dev (N x d_Z float64, row-major dq_i/dz),
+ * z_dev (d_Z float64), all device memory.  opt selects the risk measure and
+ * its parameters (beta, eps, alpha, t_mode / t_in, risk, risk_kappa,
+ * risk_tau; the solver fields are ignored).  Results go to device memory:
+ * out_dev[0] = J, out_dev[1] = dJ/dt, out_dev[2 .. 2 + d_Z) = grad J; t_dev[0]
+ * = t* (CVaR), the mean of q (mean + kappa Var), tau (probability of
+ * failure), a* (buffered probability of exceedance) or 0 (mean).  Work is
+ * enqueued on `hip_stream` (a hipStream_t, NULL = default); the library
+ * allocates a workspace of about 4.3 MB for the call and synchronises the
+ * stream before releasing it.  SAA_E_INVALID (before any device work) for
+ * null pointers, N outside 1 .. SAA_REDUCE_MAX_N, d_Z outside 1 ..
+ * SAA_MAX_DZ (64) or invalid options; SAA_E_OOM, SAA_E_DEVICE on failure.
+ * Results are bitwise those of the reduction inside saa_objective_grad. */
+int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
+                    const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream);
 
 /* Per-sample status of the last saa_objective_grad, saa_per_sample or
  * saa_solve_states call on this context.  Host arrays of N entries each (any

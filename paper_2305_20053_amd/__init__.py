@@ -471,7 +471,7 @@ class CTrainCfg(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr_drop_epoch", ctypes.c_int),
                 ("lr", ctypes.c_double), ("lr_late", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("adam_eps", ctypes.c_double), ("dino", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("prec", ctypes.c_int), ("resume", ctypes.c_int)]
 
 
 _SIGS.update({
@@ -481,13 +481,35 @@ _SIGS.update({
     "mrdino_data_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, ctypes.POINTER(ctypes.c_double), _P]),
     "mrdino_data_qoi": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)]),
     "mrdino_data_get": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int64]),
-    "mrdino_loss_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]),
+    "mrdino_loss_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), _P]),
     "mrdino_train": (ctypes.c_int, [_P, _P, ctypes.POINTER(CTrainCfg), _P, ctypes.POINTER(ctypes.c_double)]),
     "mrdino_data_errors": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "saa_sym_eig": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
     "saa_sym_eig_gpu": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "saa_attach_holdout": (ctypes.c_int, [_P, _P]),
+    "saa_risk_reduce": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(COptions), _P, _P,
+                                       _P]),
 })
+
+
+def risk_reduce(q, g, z, opt=None):
+    """Risk reduction alone over per-sample values already on the device:
+    q (N,) and g (N, d_Z) float64 CUDA tensors, z (d_Z) host array.  Returns
+    (J, dJ/dt, grad (numpy d_Z), t) from saa_risk_reduce."""
+    import numpy as np
+    import torch
+    opt = opt if opt is not None else options()
+    q = q.contiguous()
+    g = g.contiguous()
+    N, dz = g.shape
+    zd = torch.as_tensor(np.asarray(z, dtype=np.float64)).to(q.device)
+    out = torch.empty(2 + dz, dtype=torch.float64, device=q.device)
+    t = torch.empty(1, dtype=torch.float64, device=q.device)
+    _check(_load().saa_risk_reduce(_P(_ptr(q)), _P(_ptr(g)), N, dz, _P(_ptr(zd)), ctypes.byref(opt), _P(_ptr(out)),
+                                   _P(_ptr(t)), _P(torch.cuda.current_stream().cuda_stream)))
+    o = out.cpu().numpy()
+    return float(o[0]), float(o[1]), o[2:].copy(), float(t.item())
 
 
 def attach_holdout(ctx: Context, holdout):
@@ -525,9 +547,12 @@ def sym_eig_gpu(A):
 
 
 def train_cfg(batch=256, epochs=1600, lr_drop_epoch=800, lr=1e-3, lr_late=2.5e-4, dino=1, seed=2305,
-              beta1=0.9, beta2=0.999, adam_eps=1e-8) -> CTrainCfg:
-    """Adam schedule of Sec. 4.2.1 (lr 1e-3, 2.5e-4 after 800 of 1600 epochs)."""
-    return CTrainCfg(batch, epochs, lr_drop_epoch, lr, lr_late, beta1, beta2, adam_eps, dino, seed)
+              beta1=0.9, beta2=0.999, adam_eps=1e-8, prec=None, resume=0) -> CTrainCfg:
+    """Adam schedule of Sec. 4.2.1 (lr 1e-3, 2.5e-4 after 800 of 1600 epochs);
+    products in BF16 with FP32 accumulation unless prec = FP32; resume = 1
+    continues the model's optimiser state."""
+    return CTrainCfg(batch, epochs, lr_drop_epoch, lr, lr_late, beta1, beta2, adam_eps, dino, seed,
+                     BF16 if prec is None else prec, resume)
 
 
 class TrainData:
@@ -596,13 +621,15 @@ class TrainData:
         return a
 
 
-def loss_grad(model: Model, data: TrainData, idx, dino=True, want_grad=True):
-    """FP32 batch loss and gradient (packed order) of the rows idx."""
+def loss_grad(model: Model, data: TrainData, idx, dino=True, want_grad=True, prec=None):
+    """Batch loss and gradient (packed order) of the rows idx; products in
+    FP32 (default) or BF16 (prec = BF16, the training precision)."""
     import numpy as np
     ii = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
     loss = ctypes.c_double()
     g = np.zeros(model.n_params, dtype=np.float32) if want_grad else None
-    _check(_load().mrdino_loss_grad(model._h, data.handle, ii.ctypes.data, ii.size, int(dino), ctypes.byref(loss),
+    _check(_load().mrdino_loss_grad(model._h, data.handle, ii.ctypes.data, ii.size, int(dino),
+                                    FP32 if prec is None else prec, ctypes.byref(loss),
                                     g.ctypes.data if want_grad else None))
     return loss.value, g
 

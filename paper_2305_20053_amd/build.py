@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaa.so")
 SOURCES = ["api.cpp", "model.cpp", "train.cpp", "linalg.cpp", "ouu.cpp", "pde.hip", "pde3.hip", "cvar.hip", "mlp.hip", "train.hip",
-           "eig.hip"]
+           "eig.hip", "gemm.hip"]
 ARCH = os.environ.get("SAA_OFFLOAD_ARCH", "gfx950")
 
 

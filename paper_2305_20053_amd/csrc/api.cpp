@@ -248,6 +248,19 @@ void reduce(saa_ctx* c, const double* q, const double* g, const saa_options* opt
                      c->cwork.p, c->st);
 }
 
+// The same reduction on caller-provided device arrays: z_dev (d_Z), results
+// out_dev = [J, dJ/dt, grad (d_Z)] and t_dev, workspace `work` of
+// saa_launch::cvar_work_bytes() bytes; no solver statistics.
+void reduce_raw(const double* q, const double* g, int64_t N, int dz, const double* z_dev, const saa_options* opt,
+                double* out_dev, double* t_dev, void* work, hipStream_t st) {
+  if (opt->risk == SAA_RISK_CVAR)
+    saa_launch::cvar(q, g, N, dz, opt->beta, opt->eps, opt->alpha, z_dev, opt->t_mode, opt->t_in, 3, t_dev, out_dev,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, work, st);
+  else
+    saa_launch::risk(q, g, N, dz, opt->risk, opt->eps, opt->risk_kappa, opt->risk_tau, opt->alpha, z_dev, 3, t_dev,
+                     out_dev, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, work, st);
+}
+
 // Adjoint activity of the risk measure (see saa_k_adjoint).
 int adjoint_act(const saa_options* opt) {
   if (opt->all_adjoints) return 1;
@@ -501,6 +514,13 @@ int validate_call(saa_ctx* c, const double* z, int form, const void* model, cons
 
 namespace {
 
+// Largest sample counts whose launches fit a grid of 2^32 - 1 work-items.
+constexpr int64_t kMaxSamples2D = ((int64_t)1 << 32) / 1024 - 1;
+int64_t max_samples3d(int n) {
+  return std::min<int64_t>({(int64_t)1 << 20, (((int64_t)1 << 32) - 1) / (256 * (int64_t)(n + 1)),
+                            (((int64_t)1 << 32) - 1) / 1024});
+}
+
 // Context of the 3D problem (Q1 on the cube, PDE form only).
 int ctx_create3(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx** out) {
   // n even and halving down to a coarsest grid of at most 7 cells per side
@@ -519,7 +539,9 @@ int ctx_create3(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx**
     return SAA_E_INVALID;
   if (p->target != SAA_TARGET_CONST && p->target != SAA_TARGET_SIN && p->target != SAA_TARGET_QUAD)
     return SAA_E_INVALID;
-  if (N_max < 1 || N_max > (int64_t)1 << 20) return SAA_E_INVALID;
+  // the field kernel launches N (n + 1) workgroups of 256 threads, the solvers
+  // N workgroups of up to 1024: both grids must fit the 32-bit extent
+  if (N_max < 1 || N_max > max_samples3d(p->n)) return SAA_E_INVALID;
 
   saa_ctx* c = new (std::nothrow) saa_ctx();
   if (!c) return SAA_E_OOM;
@@ -750,7 +772,9 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
     return SAA_E_INVALID;
   if (p->target != SAA_TARGET_CONST && p->target != SAA_TARGET_SIN && p->target != SAA_TARGET_QUAD)
     return SAA_E_INVALID;
-  if (N_max < 1 || N_max > (int64_t)1 << 24) return SAA_E_INVALID;
+  // one 1024-thread workgroup per sample: N x 1024 work-items must fit the
+  // 32-bit grid extent of a launch
+  if (N_max < 1 || N_max > kMaxSamples2D) return SAA_E_INVALID;
 
   saa_ctx* c = new (std::nothrow) saa_ctx();
   if (!c) return SAA_E_OOM;
@@ -1033,6 +1057,22 @@ int saa_objective_grad(saa_ctx* c, const double* z, int form, const void* model,
   r->fallback_used = 1;
   r->seconds += t_est;
   return rc == SAA_OK ? SAA_W_FALLBACK : rc;
+}
+
+int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
+                    const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream) {
+  if (!q_dev || !g_dev || !z_dev || !out_dev || !t_dev) return SAA_E_INVALID;
+  if (N < 1 || N > SAA_REDUCE_MAX_N || d_z < 1 || d_z > SAA_MAX_DZ) return SAA_E_INVALID;
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  saa_rt::DevBuf work;
+  if ((rc = work.alloc(saa_launch::cvar_work_bytes()))) return rc;
+  reduce_raw(q_dev, g_dev, N, d_z, z_dev, opt, out_dev, t_dev, work.p, st);
+  rc = check_hip(hipGetLastError());
+  // the workspace is released only after the kernels that use it have finished
+  const int rs = check_hip(hipStreamSynchronize(st));
+  return rc ? rc : rs;
 }
 
 int saa_attach_holdout(saa_ctx* c, saa_ctx* holdout) {

@@ -101,7 +101,6 @@ struct PhaseTimer {
 };
 
 
-inline int check_hip(hipError_t e) { return e == hipSuccess ? SAA_OK : SAA_E_DEVICE; }
 
 }  // namespace saa_rt
 

@@ -111,7 +111,6 @@ int pack(mrdino_model* m) {
   off[n++] = m->f_w0z;
   off[n] = m->ws_frags;
   saa_launch::mlp_pack_fp8(m->ws.p, off, n, (float*)m->wsc.p, m->ws8.p, m->ws_frags, st);
-  ++m->version;
   return check_hip(hipGetLastError());
 }
 
@@ -234,9 +233,13 @@ int mrdino_set_qoi(mrdino_model* m, const double* c, double c0) {
 
 }  // extern "C"
 
-// Model file: "SAADINO1", uint32 version 1, int32 r_m d_z r_u width depth,
-// int64 n_params, float64 c0, float64 c[r_u], float32 params[n_params], then
-// the 64-bit FNV-1a hash of everything before it.  Native byte order.
+// Model file: "SAADINO1", uint32 version, int32 r_m d_z r_u width depth,
+// int64 n_params, float64 c0, float64 c[r_u], float32 params[n_params];
+// version 2 continues with int32 has_train and, if 1, the optimiser state:
+// int64 Adam step, int64 completed epochs, uint64 minibatch-stream state,
+// float32 m[n_params], float32 v[n_params]; then the 64-bit FNV-1a hash of
+// everything before it.  Native byte order.  Version 1 files (no optimiser
+// state) still load.
 namespace {
 constexpr char kMagic[8] = {'S', 'A', 'A', 'D', 'I', 'N', 'O', '1'};
 
@@ -276,7 +279,9 @@ int mrdino_save(const mrdino_model* m, const char* path) {
   if (rc) return rc;
   std::vector<double> c(m->c_host);
   c.resize(m->dims.r_u, 0.0);
-  const uint32_t version = 1;
+  TrainCheckpoint ck;
+  if ((rc = saa_model_get_train_state(m, ck))) return rc;
+  const uint32_t version = 2;
   const int32_t dims[5] = {m->dims.r_m, m->dims.d_z, m->dims.r_u, m->dims.width, m->dims.depth};
   std::vector<unsigned char> b;
   append(b, kMagic, 8);
@@ -286,6 +291,15 @@ int mrdino_save(const mrdino_model* m, const char* path) {
   append(b, &m->c0, 1);
   append(b, c.data(), c.size());
   append(b, params.data(), params.size());
+  const int32_t has_train = ck.present ? 1 : 0;
+  append(b, &has_train, 1);
+  if (ck.present) {
+    append(b, &ck.step, 1);
+    append(b, &ck.epoch, 1);
+    append(b, &ck.rng, 1);
+    append(b, ck.m.data(), ck.m.size());
+    append(b, ck.v.data(), ck.v.size());
+  }
   const uint64_t h = fnv1a(b.data(), b.size());
   append(b, &h, 1);
   FILE* f = std::fopen(path, "wb");
@@ -314,20 +328,34 @@ int mrdino_load(const char* path, void* hip_stream, mrdino_model** out) {
   int32_t dims[5];
   int64_t n = 0;
   double c0 = 0.0;
-  if (!take(b, off, &version, 1) || version != 1 || !take(b, off, dims, 5) || !take(b, off, &n, 1) ||
-      !take(b, off, &c0, 1))
+  if (!take(b, off, &version, 1) || (version != 1 && version != 2) || !take(b, off, dims, 5) ||
+      !take(b, off, &n, 1) || !take(b, off, &c0, 1))
     return SAA_E_IO;
   const mrdino_dims d{dims[0], dims[1], dims[2], dims[3], dims[4]};
   if (!dims_supported(d) || n != param_count(d)) return SAA_E_IO;
   std::vector<double> c(d.r_u);
   std::vector<float> params(n);
-  if (!take(b, off, c.data(), c.size()) || !take(b, off, params.data(), params.size()) ||
-      off + sizeof(h) != b.size())
-    return SAA_E_IO;
+  if (!take(b, off, c.data(), c.size()) || !take(b, off, params.data(), params.size())) return SAA_E_IO;
+  TrainCheckpoint ck;
+  if (version == 2) {
+    int32_t has_train = 0;
+    if (!take(b, off, &has_train, 1) || (has_train != 0 && has_train != 1)) return SAA_E_IO;
+    if (has_train) {
+      ck.present = true;
+      ck.m.resize(n);
+      ck.v.resize(n);
+      if (!take(b, off, &ck.step, 1) || !take(b, off, &ck.epoch, 1) || !take(b, off, &ck.rng, 1) ||
+          !take(b, off, ck.m.data(), ck.m.size()) || !take(b, off, ck.v.data(), ck.v.size()) || ck.step < 0 ||
+          ck.epoch < 0)
+        return SAA_E_IO;
+    }
+  }
+  if (off + sizeof(h) != b.size()) return SAA_E_IO;
   mrdino_model* m = nullptr;
   int rc = mrdino_create(&d, hip_stream, &m);
   if (!rc) rc = mrdino_set_params(m, params.data(), n);
   if (!rc) rc = mrdino_set_qoi(m, c.data(), c0);
+  if (!rc) rc = saa_model_set_train_state(m, ck);
   if (rc) {
     mrdino_free(m);
     return rc;

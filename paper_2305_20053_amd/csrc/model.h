@@ -27,13 +27,26 @@ struct mrdino_model {
   std::vector<double> c_host;               // c as given to mrdino_set_qoi (zeros until set)
   void* train = nullptr;                    // training workspace and Adam state (train.cpp)
   uint64_t serial = 0;                      // unique per model object (keys captured graphs)
-  uint64_t version = 0;                     // bumped whenever c, c0 or the packed operands change: a
-                                            // captured graph holds c0 by value, so it keys graphs too
+  uint64_t version = 0;                     // bumped whenever c, c0 change: a captured graph holds c0
+                                            // by value, so it keys graphs too (weights and c are read
+                                            // from device buffers whose addresses never change)
   ~mrdino_model();
 };
 
 // Releases the training state of a model (train.cpp).
 void saa_model_free_train(mrdino_model* m);
+
+// Optimiser state of a model for checkpoints (train.cpp): Adam moments, step,
+// completed epochs and the minibatch-order stream.  present = false: the
+// model has not been trained.
+struct TrainCheckpoint {
+  bool present = false;
+  int64_t step = 0, epoch = 0;
+  uint64_t rng = 0;
+  std::vector<float> m, v;
+};
+int saa_model_get_train_state(const mrdino_model* m, TrainCheckpoint& ck);
+int saa_model_set_train_state(mrdino_model* m, const TrainCheckpoint& ck);
 
 namespace saa_model {
 int pack(mrdino_model* m);

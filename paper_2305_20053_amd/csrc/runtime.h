@@ -8,6 +8,9 @@
 
 namespace saa_rt {
 
+// HIP runtime status -> library status.
+inline int check_hip(hipError_t e) { return e == hipSuccess ? SAA_OK : SAA_E_DEVICE; }
+
 // Owning device allocation; freed on destruction.
 // Pinned host memory (hipHostMalloc), freed with the owner.
 struct HostBuf {

@@ -18,10 +18,15 @@
 extern "C" int saa_sym_eig(int n, const double* A, double* w, double* V);
 extern "C" int saa_sym_eig_gpu(int n, const double* A_dev, double* w, double* V_dev, void* hip_stream, int* sweeps);
 
+#include <rocblas/rocblas.h>
+
 namespace saa_launch {
-template <typename T>
-void gemm(bool ta, bool tb, int M, int N, int K, T alpha, const T* A, int lda, int64_t sA, const T* B, int ldb,
-          int64_t sB, T beta, T* C, int ldc, int64_t sC, int batch, hipStream_t st);
+int gemm_mfma(bool bf16, bool ta, bool tb, int M, int N, int K, float alpha, const float* A, int lda, const float* B,
+              int ldb, float beta, float* C, int ldc, float* ws, int64_t ws_floats, hipStream_t st);
+int dgemm(rocblas_handle h, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+rocblas_handle blas_create();
+void blas_destroy(rocblas_handle h);
 void mass_rows(const double* U, int64_t ldu, const double* ubar, double* out, int64_t ldo, int n, int64_t rows,
                hipStream_t st);
 void colmean(const double* X, int64_t rows, int cols, int64_t ldx, double* out, hipStream_t st);
@@ -57,6 +62,8 @@ struct mrdino_data {
   std::vector<double> c;    // reduced QoI terms
   double c0 = 0.0;
   hipStream_t st = nullptr;
+  rocblas_handle blas = nullptr;   // FP64 POD products (library GEMM), owned
+  ~mrdino_data() { saa_launch::blas_destroy(blas); }
 };
 
 namespace {
@@ -68,11 +75,16 @@ struct TrainWs {
   DevBuf A[MLP_MAX_DEPTH], H[MLP_MAX_DEPTH], JA[MLP_MAX_DEPTH], JH[MLP_MAX_DEPTH];
   DevBuf P, JP, gP, gJP, gH[2], gJH[2];
   DevBuf grad, m, v, parts, loss;
+  DevBuf gws;               // partial products of k-split GEMMs
+  int64_t gws_floats = 0;
 };
 
 struct TrainState {
   TrainWs ws;
-  int64_t step = 0;
+  int64_t step = 0;    // Adam steps taken
+  int64_t epoch = 0;   // epochs completed (the learning-rate schedule's clock)
+  uint64_t rng = 0;    // minibatch-order stream
+  bool started = false;
 };
 
 TrainState* train_state(mrdino_model* m) {
@@ -115,50 +127,72 @@ int alloc_ws(mrdino_model* mdl, int B) {
   if (!rc && !w.v.p) rc = w.v.alloc_zero(f * mdl->n_params, st);
   if (!rc) rc = w.parts.alloc_zero(sizeof(double) * (((size_t)B * d.d_z * d.r_u + 1023) / 1024 + 16), st);
   if (!rc) rc = w.loss.alloc_zero(sizeof(double) * 4, st);
+  // up to 16 k slices of the largest weight-gradient product
+  const int64_t wmax = std::max<int64_t>((int64_t)W * std::max(W, in), (int64_t)d.r_u * W);
+  if (!rc && w.gws_floats < 16 * wmax) {
+    rc = w.gws.alloc(sizeof(float) * 16 * wmax);
+    w.gws_floats = rc ? 0 : 16 * wmax;
+  }
   if (!rc) w.B = B;
   return rc;
 }
 
 float* F(DevBuf& b) { return (float*)b.p; }
 
-// Forward (and, with dino, forward-mode tangents) of the batch in ws.Xb.
-void forward(mrdino_model* mdl, TrainWs& w, int B, int dino) {
+// One training product C = alpha op(A) op(B) + beta C on the MFMA kernels,
+// operands in BF16 (bf) or FP32, FP32 accumulation.
+struct Mm {
+  TrainWs& w;
+  bool bf;
+  hipStream_t st;
+  int rc = SAA_OK;
+  void operator()(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float beta,
+                  float* C, int ldc) {
+    const int e = saa_launch::gemm_mfma(bf, ta, tb, M, N, K, 1.0f, A, lda, B, ldb, beta, C, ldc, (float*)w.gws.p,
+                                        w.gws_floats, st);
+    if (!rc) rc = e;
+  }
+};
+
+// Forward (and, with dino, forward-mode tangents) of the batch in ws.Xb:
+// a_l = H_{l-1} W_l^T, h_l = GELU(a_l + b_l); tangents J_l = GELU'(a_l) (J_{l-1} W_l^T),
+// J_0 = GELU'(a_0) W_0[:, r_m:]^T; phi = H W^T + b, dphi/dz = J W^T.
+int forward(mrdino_model* mdl, TrainWs& w, int B, int dino, bool bf) {
   const mrdino_dims& d = mdl->dims;
   const int W = d.width, in = d.r_m + d.d_z, dz = d.d_z;
   const float* P = (const float*)mdl->master.p;
   hipStream_t st = mdl->st;
+  Mm mm{w, bf, st};
   const float* hin = F(w.Xb);
   int kin = in;
   for (int l = 0; l < d.depth; ++l) {
-    saa_launch::gemm<float>(false, true, B, W, kin, 1.0f, hin, kin, 0, P + mdl->off_w[l], kin, 0, 0.0f, F(w.A[l]), W,
-                            0, 1, st);
+    mm(false, true, B, W, kin, hin, kin, P + mdl->off_w[l], kin, 0.0f, F(w.A[l]), W);
     saa_launch::bias_gelu(F(w.A[l]), P + mdl->off_b[l], F(w.H[l]), B, W, 1, st);
     hin = F(w.H[l]);
     kin = W;
   }
-  saa_launch::gemm<float>(false, true, B, d.r_u, W, 1.0f, hin, W, 0, P + mdl->off_w[d.depth], W, 0, 0.0f, F(w.P),
-                          d.r_u, 0, 1, st);
+  mm(false, true, B, d.r_u, W, hin, W, P + mdl->off_w[d.depth], W, 0.0f, F(w.P), d.r_u);
   saa_launch::bias_gelu(F(w.P), P + mdl->off_b[d.depth], nullptr, B, d.r_u, 0, st);
-  if (!dino) return;
+  if (!dino) return mm.rc;
   saa_launch::tangent0(P + mdl->off_w[0], in, d.r_m, dz, F(w.A[0]), B, W, F(w.JA[0]), F(w.JH[0]), st);
   for (int l = 1; l < d.depth; ++l) {
-    saa_launch::gemm<float>(false, true, B * dz, W, W, 1.0f, F(w.JH[l - 1]), W, 0, P + mdl->off_w[l], W, 0, 0.0f,
-                            F(w.JA[l]), W, 0, 1, st);
+    mm(false, true, B * dz, W, W, F(w.JH[l - 1]), W, P + mdl->off_w[l], W, 0.0f, F(w.JA[l]), W);
     saa_launch::tangent_scale(F(w.JA[l]), F(w.A[l]), B, dz, W, F(w.JH[l]), st);
   }
-  saa_launch::gemm<float>(false, true, B * dz, d.r_u, W, 1.0f, F(w.JH[d.depth - 1]), W, 0, P + mdl->off_w[d.depth],
-                          W, 0, 0.0f, F(w.JP), d.r_u, 0, 1, st);
+  mm(false, true, B * dz, d.r_u, W, F(w.JH[d.depth - 1]), W, P + mdl->off_w[d.depth], W, 0.0f, F(w.JP), d.r_u);
+  return mm.rc;
 }
 
 // Loss (ws.loss[0] = state part, [1] = Jacobian part, unnormalised sums) and,
 // with want_grad, the gradient of L = (1/B) sum (|e|^2 + |E_J|_F^2) into ws.grad.
-void loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad) {
+int loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad, bool bf) {
   const mrdino_dims& d = mdl->dims;
   const int W = d.width, in = d.r_m + d.d_z, dz = d.d_z;
   const float* P = (const float*)mdl->master.p;
   hipStream_t st = mdl->st;
   double* loss = (double*)w.loss.p;
-  forward(mdl, w, B, dino);
+  int rc = forward(mdl, w, B, dino, bf);
+  if (rc) return rc;
   const float sc = 2.0f / (float)B;
   int nb = saa_launch::residual(F(w.P), F(w.Yb), (int64_t)B * d.r_u, sc, F(w.gP), (double*)w.parts.p, st);
   saa_launch::sum_parts((double*)w.parts.p, nb, loss + 0, 0, st);
@@ -166,48 +200,39 @@ void loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad) {
     nb = saa_launch::residual(F(w.JP), F(w.JYb), (int64_t)B * dz * d.r_u, sc, F(w.gJP), (double*)w.parts.p, st);
     saa_launch::sum_parts((double*)w.parts.p, nb, loss + 1, 0, st);
   } else {
-    (void)hipMemsetAsync(loss + 1, 0, sizeof(double), st);
+    saa_launch::sum_parts((double*)w.parts.p, 0, loss + 1, 0, st);   // zero
   }
-  if (!want_grad) return;
+  if (!want_grad) return check_hip(hipGetLastError());
+  Mm mm{w, bf, st};
   float* G = F(w.grad);
   const int L = d.depth;
-  // output layer
-  saa_launch::gemm<float>(true, false, d.r_u, W, B, 1.0f, F(w.gP), d.r_u, 0, F(w.H[L - 1]), W, 0, 0.0f,
-                          G + mdl->off_w[L], W, 0, 1, st);
-  if (dino)
-    saa_launch::gemm<float>(true, false, d.r_u, W, B * dz, 1.0f, F(w.gJP), d.r_u, 0, F(w.JH[L - 1]), W, 0, 1.0f,
-                            G + mdl->off_w[L], W, 0, 1, st);
+  // output layer: dW = gP^T H (+ gJP^T JH), db = column sums of gP
+  mm(true, false, d.r_u, W, B, F(w.gP), d.r_u, F(w.H[L - 1]), W, 0.0f, G + mdl->off_w[L], W);
+  if (dino) mm(true, false, d.r_u, W, B * dz, F(w.gJP), d.r_u, F(w.JH[L - 1]), W, 1.0f, G + mdl->off_w[L], W);
   saa_launch::colsum(F(w.gP), B, d.r_u, G + mdl->off_b[L], 0, st);
   int cur = 0;
-  saa_launch::gemm<float>(false, false, B, W, d.r_u, 1.0f, F(w.gP), d.r_u, 0, P + mdl->off_w[L], W, 0, 0.0f,
-                          F(w.gH[cur]), W, 0, 1, st);
-  if (dino)
-    saa_launch::gemm<float>(false, false, B * dz, W, d.r_u, 1.0f, F(w.gJP), d.r_u, 0, P + mdl->off_w[L], W, 0, 0.0f,
-                            F(w.gJH[cur]), W, 0, 1, st);
+  mm(false, false, B, W, d.r_u, F(w.gP), d.r_u, P + mdl->off_w[L], W, 0.0f, F(w.gH[cur]), W);
+  if (dino) mm(false, false, B * dz, W, d.r_u, F(w.gJP), d.r_u, P + mdl->off_w[L], W, 0.0f, F(w.gJH[cur]), W);
   for (int l = L - 1; l >= 0; --l) {
     saa_launch::layer_back(F(w.gH[cur]), F(w.gJH[cur]), F(w.A[l]), F(w.JA[l]), B, dz, W, dino, st);
     const int kin = (l == 0) ? in : W;
     const float* hprev = (l == 0) ? F(w.Xb) : F(w.H[l - 1]);
-    saa_launch::gemm<float>(true, false, W, kin, B, 1.0f, F(w.gH[cur]), W, 0, hprev, kin, 0, 0.0f,
-                            G + mdl->off_w[l], kin, 0, 1, st);
+    mm(true, false, W, kin, B, F(w.gH[cur]), W, hprev, kin, 0.0f, G + mdl->off_w[l], kin);
     if (dino) {
       if (l >= 1)
-        saa_launch::gemm<float>(true, false, W, W, B * dz, 1.0f, F(w.gJH[cur]), W, 0, F(w.JH[l - 1]), W, 0, 1.0f,
-                                G + mdl->off_w[l], W, 0, 1, st);
+        mm(true, false, W, W, B * dz, F(w.gJH[cur]), W, F(w.JH[l - 1]), W, 1.0f, G + mdl->off_w[l], W);
       else
         saa_launch::w0z_grad(F(w.gJH[cur]), B, dz, W, d.r_m, in, G + mdl->off_w[0], st);
     }
     saa_launch::colsum(F(w.gH[cur]), B, W, G + mdl->off_b[l], 0, st);
     if (l >= 1) {
       const int nxt = cur ^ 1;
-      saa_launch::gemm<float>(false, false, B, W, W, 1.0f, F(w.gH[cur]), W, 0, P + mdl->off_w[l], W, 0, 0.0f,
-                              F(w.gH[nxt]), W, 0, 1, st);
-      if (dino)
-        saa_launch::gemm<float>(false, false, B * dz, W, W, 1.0f, F(w.gJH[cur]), W, 0, P + mdl->off_w[l], W, 0, 0.0f,
-                                F(w.gJH[nxt]), W, 0, 1, st);
+      mm(false, false, B, W, W, F(w.gH[cur]), W, P + mdl->off_w[l], W, 0.0f, F(w.gH[nxt]), W);
+      if (dino) mm(false, false, B * dz, W, W, F(w.gJH[cur]), W, P + mdl->off_w[l], W, 0.0f, F(w.gJH[nxt]), W);
       cur = nxt;
     }
   }
+  return mm.rc ? mm.rc : check_hip(hipGetLastError());
 }
 
 // Gather the minibatch rows idx_dev[0..B) (device indices) of the data set.
@@ -235,6 +260,44 @@ uint64_t splitmix64(uint64_t& s) {
 void saa_model_free_train(mrdino_model* m) {
   delete (TrainState*)m->train;
   m->train = nullptr;
+}
+
+int saa_model_get_train_state(const mrdino_model* m, TrainCheckpoint& ck) {
+  const TrainState* ts = (const TrainState*)m->train;
+  ck.present = ts && ts->started && ts->ws.m.p && ts->ws.v.p;
+  if (!ck.present) return SAA_OK;
+  ck.step = ts->step;
+  ck.epoch = ts->epoch;
+  ck.rng = ts->rng;
+  ck.m.resize(m->n_params);
+  ck.v.resize(m->n_params);
+  int rc = check_hip(hipMemcpyAsync(ck.m.data(), ts->ws.m.p, sizeof(float) * m->n_params, hipMemcpyDeviceToHost, m->st));
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(ck.v.data(), ts->ws.v.p, sizeof(float) * m->n_params, hipMemcpyDeviceToHost, m->st));
+  if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  return rc;
+}
+
+int saa_model_set_train_state(mrdino_model* m, const TrainCheckpoint& ck) {
+  if (!ck.present) return SAA_OK;
+  if ((int64_t)ck.m.size() != m->n_params || (int64_t)ck.v.size() != m->n_params) return SAA_E_INVALID;
+  TrainState* ts = train_state(m);
+  if (!ts) return SAA_E_OOM;
+  TrainWs& w = ts->ws;
+  int rc = SAA_OK;
+  if (!w.m.p) rc = w.m.alloc(sizeof(float) * m->n_params);
+  if (!rc && !w.v.p) rc = w.v.alloc(sizeof(float) * m->n_params);
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(w.m.p, ck.m.data(), sizeof(float) * m->n_params, hipMemcpyHostToDevice, m->st));
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(w.v.p, ck.v.data(), sizeof(float) * m->n_params, hipMemcpyHostToDevice, m->st));
+  if (!rc) rc = check_hip(hipStreamSynchronize(m->st));
+  if (rc) return rc;
+  ts->step = ck.step;
+  ts->epoch = ck.epoch;
+  ts->rng = ck.rng;
+  ts->started = true;
+  return SAA_OK;
 }
 
 // Reduced QoI terms of the tracking functional for a target with interior
@@ -269,8 +332,9 @@ static int qoi_terms(const mrdino_data* D, const std::vector<double>& mt, double
     cross += ub[p] * m;
   }
   if ((rc = check_hip(hipMemcpyAsync(vdev.p, v.data(), sizeof(double) * du, hipMemcpyHostToDevice, st)))) return rc;
-  saa_launch::gemm<double>(false, false, r_u, 1, (int)du, 1.0, (double*)D->PhiT.p, (int)du, 0, (double*)vdev.p, 1, 0,
-                           0.0, (double*)cdev.p, 1, 0, 1, st);
+  if ((rc = saa_launch::dgemm(D->blas, false, false, r_u, 1, (int)du, 1.0, (double*)D->PhiT.p, (int)du,
+                              (double*)vdev.p, 1, 0.0, (double*)cdev.p, 1, st)))
+    return rc;
   c_out.assign(r_u, 0.0);
   if ((rc = check_hip(hipMemcpyAsync(c_out.data(), cdev.p, sizeof(double) * r_u, hipMemcpyDeviceToHost, st))) ||
       (rc = check_hip(hipStreamSynchronize(st))))
@@ -311,6 +375,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     delete D;
     return rc;
   };
+  if (!(D->blas = saa_launch::blas_create())) return fail(SAA_E_DEVICE);
   DevBuf U, dUdz, Dm, MD, G, Vs, MPhiT, Yd, JYd;
   // control Jacobians: d_Z forward solves, or r_u adjoint solves (Sec. 3.4)
   const bool adj = opt->jac_mode == SAA_JAC_ADJOINT || (opt->jac_mode == SAA_JAC_AUTO && dz >= r_u);
@@ -338,8 +403,9 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   saa_launch::colmean((double*)U.p, n_pod, (int)du, du, (double*)D->ubar.p, st);
   saa_launch::center_rows((double*)U.p, (double*)D->ubar.p, (double*)Dm.p, du, n_pod, st);
   saa_launch::mass_rows((double*)Dm.p, du, nullptr, (double*)MD.p, du, D->n, n_pod, st);
-  saa_launch::gemm<double>(false, true, n_pod, n_pod, (int)du, 1.0, (double*)Dm.p, (int)du, 0, (double*)MD.p,
-                           (int)du, 0, 0.0, (double*)G.p, n_pod, 0, 1, st);
+  if ((rc = saa_launch::dgemm(D->blas, false, true, n_pod, n_pod, (int)du, 1.0, (double*)Dm.p, (int)du,
+                              (double*)MD.p, (int)du, 0.0, (double*)G.p, n_pod, st)))
+    return fail(rc);
   std::vector<double> V((size_t)n_pod * n_pod);
   D->lam.assign(n_pod, 0.0);
   {  // eigenpairs of the Gram matrix on the GPU (parallel Jacobi)
@@ -366,8 +432,9 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   if ((rc = check_hip(hipMemcpyAsync(Vs.p, vs.data(), sizeof(double) * vs.size(), hipMemcpyHostToDevice, st))))
     return fail(rc);
   // Phi^T = (V_r Lambda_r^{-1/2})^T D  (rows M-orthonormal)
-  saa_launch::gemm<double>(true, false, r_u, (int)du, n_pod, 1.0, (double*)Vs.p, r_u, 0, (double*)Dm.p, (int)du, 0,
-                           0.0, (double*)D->PhiT.p, (int)du, 0, 1, st);
+  if ((rc = saa_launch::dgemm(D->blas, true, false, r_u, (int)du, n_pod, 1.0, (double*)Vs.p, r_u, (double*)Dm.p,
+                              (int)du, 0.0, (double*)D->PhiT.p, (int)du, st)))
+    return fail(rc);
   saa_launch::mass_rows((double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
   Dm.release();
   MD.release();
@@ -375,13 +442,15 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   // 3. reduced data: y = Phi^T M (u - ubar), J_r = Phi^T M du/dz (eq. (projected_sensitivity))
   if ((rc = Yd.alloc(sizeof(double) * N * r_u)) || (rc = JYd.alloc(sizeof(double) * N * dz * r_u))) return fail(rc);
   saa_launch::center_rows((double*)U.p, (double*)D->ubar.p, (double*)U.p, du, N, st);
-  saa_launch::gemm<double>(false, true, (int)N, r_u, (int)du, 1.0, (double*)U.p, (int)du, 0, (double*)MPhiT.p,
-                           (int)du, 0, 0.0, (double*)Yd.p, r_u, 0, 1, st);
+  if ((rc = saa_launch::dgemm(D->blas, false, true, (int)N, r_u, (int)du, 1.0, (double*)U.p, (int)du,
+                              (double*)MPhiT.p, (int)du, 0.0, (double*)Yd.p, r_u, st)))
+    return fail(rc);
   if (adj) {   // J_r = (A^{-1} M Phi)^T F, from the states still held by the context
     if ((rc = saa_rt::adjoint_jacobians(c, opt, (const double*)MPhiT.p, r_u, (double*)JYd.p))) return fail(rc);
   } else {
-    saa_launch::gemm<double>(false, true, (int)(N * dz), r_u, (int)du, 1.0, (double*)dUdz.p, (int)du, 0,
-                             (double*)MPhiT.p, (int)du, 0, 0.0, (double*)JYd.p, r_u, 0, 1, st);
+    if ((rc = saa_launch::dgemm(D->blas, false, true, (int)(N * dz), r_u, (int)du, 1.0, (double*)dUdz.p, (int)du,
+                                (double*)MPhiT.p, (int)du, 0.0, (double*)JYd.p, r_u, st)))
+      return fail(rc);
   }
   if ((rc = D->X.alloc(sizeof(float) * N * (r_m + dz))) || (rc = D->Y.alloc(sizeof(float) * N * r_u)) ||
       (rc = D->JY.alloc(sizeof(float) * N * dz * r_u)))
@@ -443,8 +512,10 @@ int mrdino_data_get(const mrdino_data* D, int which, void* host, int64_t n) {
   return rc;
 }
 
-int mrdino_loss_grad(mrdino_model* m, mrdino_data* D, const int* idx, int B, int dino, double* loss, float* grad) {
+int mrdino_loss_grad(mrdino_model* m, mrdino_data* D, const int* idx, int B, int dino, int prec, double* loss,
+                     float* grad) {
   if (!m || !D || !idx || B < 1 || !loss || !compatible(m, D)) return SAA_E_INVALID;
+  if (prec != SAA_BF16 && prec != SAA_FP32) return SAA_E_INVALID;
   for (int b = 0; b < B; ++b)
     if (idx[b] < 0 || idx[b] >= D->N) return SAA_E_INVALID;
   int rc = alloc_ws(m, B);
@@ -452,7 +523,7 @@ int mrdino_loss_grad(mrdino_model* m, mrdino_data* D, const int* idx, int B, int
   TrainWs& w = train_state(m)->ws;
   if ((rc = check_hip(hipMemcpyAsync(w.idx.p, idx, sizeof(int) * B, hipMemcpyHostToDevice, m->st)))) return rc;
   load_batch(m, D, w, (const int*)w.idx.p, B);
-  loss_grad(m, w, B, dino, grad != nullptr);
+  if ((rc = loss_grad(m, w, B, dino, grad != nullptr, prec == SAA_BF16))) return rc;
   double l[2];
   if ((rc = check_hip(hipMemcpyAsync(l, w.loss.p, sizeof(l), hipMemcpyDeviceToHost, m->st)))) return rc;
   if (grad && (rc = check_hip(hipMemcpyAsync(grad, w.grad.p, sizeof(float) * m->n_params, hipMemcpyDeviceToHost,
@@ -500,7 +571,7 @@ int mrdino_eval(mrdino_model* m, saa_ctx* c, const double* z, int want, int prec
       const int nb = (int)std::min<int64_t>(B, c->N - b0);
       saa_launch::train_inputs((const double*)c->xi.p + b0 * nkl, nkl, (const int*)c->order.p, d.r_m,
                                (const double*)Zb.p, d.d_z, nb, F(w.Xb), m->st);
-      forward(m, w, nb, dino);
+      if ((rc = forward(m, w, nb, dino, false))) break;
       if (want & MRDINO_WANT_PHI)
         rc = check_hip(hipMemcpyAsync(phi_dev + b0 * d.r_u, w.P.p, sizeof(float) * nb * d.r_u,
                                       hipMemcpyDeviceToDevice, m->st));
@@ -518,19 +589,30 @@ int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, d
   if (!m || !D || !cfg || !compatible(m, D)) return SAA_E_INVALID;
   const int B = cfg->batch;
   if (B < 1 || B > D->N || cfg->epochs < 0 || !(cfg->lr > 0) || !(cfg->lr_late > 0) || !(cfg->beta1 >= 0) ||
-      !(cfg->beta1 < 1) || !(cfg->beta2 >= 0) || !(cfg->beta2 < 1) || !(cfg->adam_eps > 0))
+      !(cfg->beta1 < 1) || !(cfg->beta2 >= 0) || !(cfg->beta2 < 1) || !(cfg->adam_eps > 0) ||
+      (cfg->prec != SAA_BF16 && cfg->prec != SAA_FP32))
     return SAA_E_INVALID;
+  const bool bf = cfg->prec == SAA_BF16;
   int rc = alloc_ws(m, B);
   if (rc) return rc;
   TrainState* ts = train_state(m);
   TrainWs& w = ts->ws;
   hipStream_t st = m->st;
+  if (!cfg->resume || !ts->started) {   // a new optimisation: fresh moments, schedule and minibatch stream
+    if ((rc = check_hip(hipMemsetAsync(w.m.p, 0, sizeof(float) * m->n_params, st))) ||
+        (rc = check_hip(hipMemsetAsync(w.v.p, 0, sizeof(float) * m->n_params, st))))
+      return rc;
+    ts->step = 0;
+    ts->epoch = 0;
+    ts->rng = cfg->seed;
+    ts->started = true;
+  }
   DevBuf perm_dev;
   if ((rc = perm_dev.alloc(sizeof(int) * D->N))) return rc;
   std::vector<int> perm(D->N);
   const int steps = (int)(D->N / B);
   double* loss = (double*)w.loss.p;
-  uint64_t rng = cfg->seed;
+  uint64_t& rng = ts->rng;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -543,11 +625,12 @@ int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, d
     }
     if ((rc = check_hip(hipMemcpyAsync(perm_dev.p, perm.data(), sizeof(int) * D->N, hipMemcpyHostToDevice, st))))
       break;
-    (void)hipMemsetAsync(loss + 2, 0, sizeof(double), st);
-    const float lr = (float)((cfg->lr_drop_epoch > 0 && ep >= cfg->lr_drop_epoch) ? cfg->lr_late : cfg->lr);
+    saa_launch::sum_parts(loss, 0, loss + 2, 0, st);   // zero the epoch sum
+    const float lr =
+        (float)((cfg->lr_drop_epoch > 0 && ts->epoch >= cfg->lr_drop_epoch) ? cfg->lr_late : cfg->lr);
     for (int s = 0; s < steps; ++s) {
       load_batch(m, D, w, (const int*)perm_dev.p + (int64_t)s * B, B);
-      loss_grad(m, w, B, cfg->dino, true);
+      if ((rc = loss_grad(m, w, B, cfg->dino, true, bf))) break;
       saa_launch::sum_parts(loss, 2, loss + 2, 1, st);
       ++ts->step;
       const float c1 = 1.0f - std::pow((float)cfg->beta1, (float)ts->step);
@@ -555,6 +638,8 @@ int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, d
       saa_launch::adam((float*)m->master.p, F(w.grad), F(w.m), F(w.v), m->n_params, lr, (float)cfg->beta1,
                        (float)cfg->beta2, (float)cfg->adam_eps, c1, c2, st);
     }
+    if (rc) break;
+    ++ts->epoch;
     if (epoch_loss) {
       double tot = 0.0;
       if ((rc = check_hip(hipMemcpyAsync(&tot, loss + 2, sizeof(double), hipMemcpyDeviceToHost, st))) ||
@@ -592,7 +677,7 @@ int mrdino_data_errors(mrdino_model* m, mrdino_data* D, double* err_state, doubl
   for (int64_t s0 = 0; s0 < D->N; s0 += B) {
     const int b = (int)std::min<int64_t>(B, D->N - s0);
     load_batch(m, D, w, (const int*)seq.p + s0, b);
-    loss_grad(m, w, b, 1, false);
+    if ((rc = loss_grad(m, w, b, 1, false, false))) return rc;
     saa_launch::sum_parts(loss + 0, 1, a + 0, 1, st);
     saa_launch::sum_parts(loss + 1, 1, a + 1, 1, st);
   }

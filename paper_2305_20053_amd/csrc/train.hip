@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "runtime.h"
 
 namespace {
 
@@ -222,35 +223,34 @@ namespace saa_launch {
 
 static inline unsigned nb(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-// Row-major C = op(A) op(B) (batched with strides) by rocBLAS, a plain
-// library GEMM: in column-major terms C^T = op(B)^T op(A)^T, so B comes first
-// and each operand keeps its transpose flag.  Atomics are disallowed in the
-// handle so results are reproducible.
-static rocblas_handle blas_handle() {
-  static rocblas_handle h = nullptr;
-  if (!h && rocblas_create_handle(&h) == rocblas_status_success)
-    (void)rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
-  return h;
-}
-
-template <typename T>
-void gemm(bool ta, bool tb, int M, int N, int K, T alpha, const T* A, int lda, int64_t sA, const T* B, int ldb,
-          int64_t sB, T beta, T* C, int ldc, int64_t sC, int batch, hipStream_t st) {
-  rocblas_handle h = blas_handle();
-  (void)rocblas_set_stream(h, st);
+// Row-major FP64 C = op(A) op(B) of the POD (Gram matrix, basis,
+// projections) by rocBLAS, a plain library GEMM, on the caller's handle: in
+// column-major terms C^T = op(B)^T op(A)^T, so B comes first and each operand
+// keeps its transpose flag.  Any rocBLAS status other than success is a
+// device error.
+int dgemm(rocblas_handle h, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st) {
+  if (!h) return SAA_E_DEVICE;
+  if (rocblas_set_stream(h, st) != rocblas_status_success) return SAA_E_DEVICE;
   const rocblas_operation oB = tb ? rocblas_operation_transpose : rocblas_operation_none;
   const rocblas_operation oA = ta ? rocblas_operation_transpose : rocblas_operation_none;
-  if constexpr (sizeof(T) == 4)
-    (void)rocblas_sgemm_strided_batched(h, oB, oA, N, M, K, (const float*)&alpha, (const float*)B, ldb, sB,
-                                        (const float*)A, lda, sA, (const float*)&beta, (float*)C, ldc, sC, batch);
-  else
-    (void)rocblas_dgemm_strided_batched(h, oB, oA, N, M, K, (const double*)&alpha, (const double*)B, ldb, sB,
-                                        (const double*)A, lda, sA, (const double*)&beta, (double*)C, ldc, sC, batch);
+  const rocblas_status s = rocblas_dgemm(h, oB, oA, N, M, K, &alpha, B, ldb, A, lda, &beta, C, ldc);
+  return s == rocblas_status_success ? SAA_OK : SAA_E_DEVICE;
 }
-template void gemm<float>(bool, bool, int, int, int, float, const float*, int, int64_t, const float*, int, int64_t,
-                          float, float*, int, int64_t, int, hipStream_t);
-template void gemm<double>(bool, bool, int, int, int, double, const double*, int, int64_t, const double*, int,
-                           int64_t, double, double*, int, int64_t, int, hipStream_t);
+
+// A rocBLAS handle with atomics disallowed (reproducible results), or null.
+rocblas_handle blas_create() {
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+  if (rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success) {
+    (void)rocblas_destroy_handle(h);
+    return nullptr;
+  }
+  return h;
+}
+void blas_destroy(rocblas_handle h) {
+  if (h) (void)rocblas_destroy_handle(h);
+}
 
 void mass_rows(const double* U, int64_t ldu, const double* ubar, double* out, int64_t ldo, int n, int64_t rows,
                hipStream_t st) {

@@ -37,9 +37,10 @@ def test_cpu_baseline_record():
     prob = saa.Problem(n=8, kl_per_dim=4)
     xi = si.kl_coefficients(2421, 64, prob.kl_per_dim)
     rec = bench.cpu_baseline(prob, xi, si.control(2422), seconds_target=0.5)
-    assert set(rec) == {"value", "unit", "cores", "kind", "sample"}
+    assert set(rec) == {"value", "unit", "cores", "kind", "sample", "host_cpu_count", "usable_cores"}
     assert rec["kind"] == "oracle" and rec["unit"] == "samples/s"
     assert 1 <= rec["cores"] <= 16 and rec["value"] > 0
+    assert rec["cores"] == min(16, rec["usable_cores"]) and rec["host_cpu_count"] == os.cpu_count()
     assert "n=8" in rec["sample"]
 
 

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     lib = saa.lib()
-    assert lib.saa_abi_version() == 2
+    assert lib.saa_abi_version() == 3
     for st in (0, 1, -1, -2, -3, -4, -5, -6):
         assert saa.status_str(st) and saa.status_str(st) != "unknown status"
     assert saa.status_str(12345) == "unknown status"
@@ -79,6 +79,28 @@ def test_ctx_create_rejects_bad_3d_problem_before_device_work(field, value):
     assert st == saa.SAA_E_INVALID and not h.value
     st = saa.lib().saa_ctx_create(ctypes.byref(saa.problem_3d().c_struct()), (1 << 20) + 1, None, ctypes.byref(h))
     assert st == saa.SAA_E_INVALID and not h.value
+
+
+@pytest.mark.parametrize("dim,n,n_max,ok", [(2, 32, 4194303, True), (2, 32, 4194304, False), (2, 4, 1 << 24, False),
+                                            (3, 16, 986895, True), (3, 16, 986896, False), (3, 96, 172960, True),
+                                            (3, 96, 172961, False), (3, 4, 1 << 20, True), (3, 4, (1 << 20) + 1, False)])
+def test_sample_count_cap_fits_every_launch_grid(dim, n, n_max, ok):
+    """N_max is capped so that every kernel's grid (2D: one 1024-thread
+    workgroup per sample; 3D: N (n + 1) workgroups of 256 threads for the
+    field) stays within 2^32 - 1 work-items.  Accepted counts are checked by
+    the bound itself (creating such a context needs a GPU); refused ones must
+    fail before any device work."""
+    if dim == 2:
+        bound = ((1 << 32) - 1) // 1024
+        p = saa.Problem(n=n, kl_per_dim=4)
+    else:
+        bound = min(1 << 20, ((1 << 32) - 1) // (256 * (n + 1)))
+        p = saa.Problem(dim=3, n=n, n_src_per_dim=2, src_sigma=0.08, kl_per_dim=3, kl_exp=1.5)
+    assert (n_max <= bound) == ok
+    if not ok:
+        h = ctypes.c_void_p()
+        st = saa.lib().saa_ctx_create(ctypes.byref(p.c_struct()), n_max, None, ctypes.byref(h))
+        assert st == saa.SAA_E_INVALID and not h.value
 
 
 def test_multi_rejects_bad_arguments_before_device_work():

@@ -197,7 +197,9 @@ def test_graph_replay_after_set_qoi(setup):
         model.set_qoi(c_new, c0_new)
         J1, g1, r1 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
         J2, g2, r2 = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=opt)
-        Je, ge, _ = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model, opt=saa.options(prec=saa.BF16, timing=1))
+        Je, ge, re_ = ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model,
+                                         opt=saa.options(prec=saa.BF16, timing=1, fallback_tol=1e30))
+        assert re_["fallback_used"] == 0 and r1["fallback_used"] == 0
         assert J1 == Je and J2 == Je and np.array_equal(g1, ge) and np.array_equal(g2, ge)
         assert r2["graph"] == 1 and J1 != J0
         # held-out context: its own replay against its eager evaluation, and

@@ -427,3 +427,47 @@ def test_empty_and_oversized_sample_sets_rejected(gpu_lib):
     ref = osaa.objective_grad(_oprob(prob), xi, z)
     assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(grad, ref["grad"]) <= 1e-9
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64])
+def test_forced_nonconvergence_reports_every_sample(small, prec):
+    """A Newton budget of one step cannot reach the stopping rule from
+    u = 0 (every sample needs at least two): the call returns SAA_E_NOCONV
+    with all outputs written, every sample flagged (bit 1) with one Newton
+    step, and the context then converges again with the default budget."""
+    prob, xi, z, ref, ctx = small
+    print(f"case forced NOCONV prec={prec}", flush=True)
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=prec, max_newton=1), allow_noconv=True)
+    assert rep["status"] == saa.SAA_E_NOCONV and rep["n_unconverged"] == 64
+    assert np.isfinite(J) and np.all(np.isfinite(grad))
+    flags, newton, lin, adj = ctx.sample_status()
+    assert np.all(flags & 1) and np.all(newton == 1)
+    with pytest.raises(saa.SaaError) as e:
+        ctx.objective_grad(z, opt=saa.options(prec=prec, max_newton=1))
+    assert e.value.status == saa.SAA_E_NOCONV
+    J2, g2, rep2 = ctx.objective_grad(z, opt=saa.options(prec=prec))
+    assert rep2["status"] == saa.SAA_OK and rep2["n_unconverged"] == 0
+    assert abs(J2 - ref["J"]) <= 1e-9 * abs(ref["J"])
+    flags, newton, lin, adj = ctx.sample_status()
+    assert not np.any(flags) and np.all(newton >= 2)
+
+
+def test_non_finite_control_is_rejected_before_device_work(small):
+    """A NaN or infinite control, or a non-finite option, returns
+    SAA_E_INVALID before any device work; the context stays usable."""
+    prob, xi, z, ref, ctx = small
+    for bad in (np.nan, np.inf, -np.inf):
+        zz = z.copy()
+        zz[3] = bad
+        with pytest.raises(saa.SaaError) as e:
+            ctx.objective_grad(zz)
+        assert e.value.status == saa.SAA_E_INVALID
+        with pytest.raises(saa.SaaError) as e:
+            ctx.per_sample(zz)
+        assert e.value.status == saa.SAA_E_INVALID
+    for field, value in (("beta", np.nan), ("eps", 0.0), ("beta", 1.0), ("alpha", np.inf)):
+        with pytest.raises(saa.SaaError) as e:
+            ctx.objective_grad(z, opt=saa.options(**{field: value}))
+        assert e.value.status == saa.SAA_E_INVALID
+    J, grad, rep = ctx.objective_grad(z, opt=saa.options(prec=saa.FP64))
+    assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"])
