@@ -541,6 +541,22 @@ int saa_ouu_solve(saa_ctx* ctx, int form, const void* model, const saa_options* 
 int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
                     const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream);
 
+/* saa_risk_reduce for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, but the workspace is a static
+ * device array of SAA_REDUCE_SCRATCH_BYTES (about 4.3 MB) that each GPU the
+ * library runs on holds until the process ends.  Nothing is allocated or
+ * freed and the stream is not synchronised: results are ready when the work
+ * enqueued on `hip_stream` completes.  Every call on one GPU shares that
+ * GPU's workspace (the kernels re-initialise what they read), so calls that
+ * overlap on one GPU (several streams or threads) race and must be
+ * serialised by the caller.  Sizes beyond N = SAA_REDUCE_MAX_N or d_Z = 64
+ * return SAA_E_INVALID before any device work; SAA_E_DEVICE if the
+ * workspace's device address cannot be obtained or a launch fails. */
+#define SAA_REDUCE_SCRATCH_BYTES 4339232
+int saa_risk_reduce_noalloc(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
+                            const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream);
+
 /* Per-sample status of the last saa_objective_grad, saa_per_sample or
  * saa_solve_states call on this context.  Host arrays of N entries each (any
  * may be NULL): flags (bit 1: Newton not converged, 2: an inner PCG hit

@@ -490,13 +490,16 @@ _SIGS.update({
     "saa_attach_holdout": (ctypes.c_int, [_P, _P]),
     "saa_risk_reduce": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(COptions), _P, _P,
                                        _P]),
+    "saa_risk_reduce_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(COptions),
+                                               _P, _P, _P]),
 })
 
 
-def risk_reduce(q, g, z, opt=None):
+def risk_reduce(q, g, z, opt=None, noalloc=False):
     """Risk reduction alone over per-sample values already on the device:
     q (N,) and g (N, d_Z) float64 CUDA tensors, z (d_Z) host array.  Returns
-    (J, dJ/dt, grad (numpy d_Z), t) from saa_risk_reduce."""
+    (J, dJ/dt, grad (numpy d_Z), t) from saa_risk_reduce, or from
+    saa_risk_reduce_noalloc (static workspace, no allocation) with noalloc."""
     import numpy as np
     import torch
     opt = opt if opt is not None else options()
@@ -506,8 +509,9 @@ def risk_reduce(q, g, z, opt=None):
     zd = torch.as_tensor(np.asarray(z, dtype=np.float64)).to(q.device)
     out = torch.empty(2 + dz, dtype=torch.float64, device=q.device)
     t = torch.empty(1, dtype=torch.float64, device=q.device)
-    _check(_load().saa_risk_reduce(_P(_ptr(q)), _P(_ptr(g)), N, dz, _P(_ptr(zd)), ctypes.byref(opt), _P(_ptr(out)),
-                                   _P(_ptr(t)), _P(torch.cuda.current_stream().cuda_stream)))
+    fn = _load().saa_risk_reduce_noalloc if noalloc else _load().saa_risk_reduce
+    _check(fn(_P(_ptr(q)), _P(_ptr(g)), N, dz, _P(_ptr(zd)), ctypes.byref(opt), _P(_ptr(out)), _P(_ptr(t)),
+              _P(torch.cuda.current_stream().cuda_stream)))
     o = out.cpu().numpy()
     return float(o[0]), float(o[1]), o[2:].copy(), float(t.item())
 

@@ -51,6 +51,7 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
           const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
           hipStream_t st);
 size_t cvar_work_bytes();
+int cvar_scratch(void** out);
 void field3(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
             hipStream_t st);
 template <typename TW, typename TS>
@@ -1073,6 +1074,18 @@ int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z
   // the workspace is released only after the kernels that use it have finished
   const int rs = check_hip(hipStreamSynchronize(st));
   return rc ? rc : rs;
+}
+
+int saa_risk_reduce_noalloc(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
+                            const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream) {
+  if (!q_dev || !g_dev || !z_dev || !out_dev || !t_dev) return SAA_E_INVALID;
+  if (N < 1 || N > SAA_REDUCE_MAX_N || d_z < 1 || d_z > SAA_MAX_DZ) return SAA_E_INVALID;
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  void* work = nullptr;   // this device's static workspace: nothing is allocated
+  if ((rc = saa_launch::cvar_scratch(&work))) return rc;
+  reduce_raw(q_dev, g_dev, N, d_z, z_dev, opt, out_dev, t_dev, work, (hipStream_t)hip_stream);
+  return check_hip(hipGetLastError());
 }
 
 int saa_attach_holdout(saa_ctx* c, saa_ctx* holdout) {

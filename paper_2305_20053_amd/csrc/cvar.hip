@@ -38,6 +38,7 @@
 // reduced in chunk order by one workgroup.  Every sum has a fixed order, so
 // results are bitwise reproducible.
 #include <cfloat>
+#include <mutex>
 
 #include "../../include/saa.h"
 #include "common.h"
@@ -58,6 +59,14 @@ constexpr int PSTRIDE = 2 + SAA_MAX_DZ;
 constexpr int WAVE_NEWTON = 256;  // active sets up to this size are solved by one wave
 constexpr int RPASSES = 4;        // refinement passes when the active set overflows
 constexpr double FIX_SCALE = 274877906944.0;   // 2^38: fixed-point scale of the refinement sums
+
+// Workspace of one reduction: per-workgroup min / max and partial sums, the
+// active-set segments, the refinement sums, the probe histograms and the
+// active-set counters (about 4.3 MB, independent of N).
+constexpr size_t kCvarWorkBytes =
+    sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
+    sizeof(unsigned long long) * RPASSES * NP + sizeof(int) * ((size_t)PASSES * 2 * NB + 2 * GMAX + 2);
+constexpr int kMaxDevices = 64;
 static_assert(NP == SAA_WAVE, "one probe per lane");
 static_assert(GMAX % SAA_WAVE == 0, "partial rows per lane in the final reduction");
 static_assert(SAA_MAX_DZ <= SAA_WAVE, "one gradient component per lane");
@@ -755,11 +764,38 @@ __global__ void __launch_bounds__(SBS) saa_k_risk_bpoe(const double* q, int64_t 
   if (threadIdx.x == 0) tstar[0] = a;
 }
 
+// The workspace of the allocation-free reduction (saa_risk_reduce_noalloc):
+// one copy per device, held until the process ends; every call on a device
+// shares it (overlapping calls on one device race).
+static_assert(kCvarWorkBytes == SAA_REDUCE_SCRATCH_BYTES, "the header states the workspace size");
+static __device__ __align__(256) unsigned char scratch[kCvarWorkBytes];
+
 namespace saa_launch {
 
-size_t cvar_work_bytes() {
-  return sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
-         sizeof(unsigned long long) * RPASSES * NP + sizeof(int) * ((size_t)PASSES * 2 * NB + 2 * GMAX + 2);
+size_t cvar_work_bytes() { return kCvarWorkBytes; }
+
+// Device address of this device's copy of `scratch` (the workspace of the
+// allocation-free reduction), looked up once per device with that device
+// current and kept; the array's host-side name is never passed to a kernel.
+int cvar_scratch(void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return SAA_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return SAA_E_DEVICE;
+    }
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return SAA_OK;
 }
 
 // phase & 1: t (minimiser, or t_in when t_mode = 1) -> tstar[0];
