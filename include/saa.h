@@ -93,8 +93,9 @@ enum { SAA_FP64 = 0, SAA_FP32 = 1, SAA_FP32_DC64 = 2, SAA_BF16 = 3, SAA_FP8 = 4 
  * 1..16, xi laid out (N, K1, K1, K1) with j the x-frequency), kappa per
  * element the mean of exp(m) over its 8 vertices, lumped reaction and
  * source, consistent Q1 mass in the QoI; the sinusoidal target is
- * sin(2 pi x) sin(2 pi y) sin(2 pi z).  PDE form only: the MR-DINO form,
- * saa_solve_states and the training calls return SAA_E_INVALID; N_max up to
+ * sin(2 pi x) sin(2 pi y) sin(2 pi z).  Both forms are available; the
+ * training data use forward control Jacobians only (jac_mode ADJOINT
+ * returns SAA_E_INVALID), projected in chunks of samples; N_max up to
  * min(2^20, floor((2^32 - 1) / (256 (n + 1)))), so that every launch grid
  * (N (n + 1) workgroups of 256 threads for the field) fits 2^32 - 1
  * work-items: 172960 at n = 96, 986895 at n = 16. */
@@ -291,17 +292,17 @@ int saa_solve_states(saa_ctx* ctx, const double* Z_dev, const saa_options* opt,
  * phi_w is a dense network on x = [m_r; z]: `depth` hidden layers of `width`
  * units with GELU (erf form), then a linear layer to r_u reduced state
  * coordinates.  m_r are the r_m leading whitened KL coordinates of the sample
- * (modes ordered by increasing j^2 + k^2, ties by increasing (j, k)).  For the
+ * (modes ordered by increasing j^2 + k^2 [+ l^2], ties by increasing (j, k[, l])).  For the
  * quadratic tracking QoI the reduced evaluation of Sec. 3.3 gives
  * q = |phi + c|^2 + c0 (c, c0 from the POD basis, see mrdino_set_qoi), and
  * dq/dz is obtained by reverse-mode differentiation of the network
  * (eq. (neural_operator_gradient)).
  * ------------------------------------------------------------------------ */
 typedef struct mrdino_dims {
-  int r_m;     /* input KL coordinates (1..128) */
-  int d_z;     /* controls (1..32); must equal the context's d_Z */
+  int r_m;     /* input KL coordinates (1..128 at width 256, 1..256 at width 512) */
+  int d_z;     /* controls (1..32 at width 256, 1..64 at width 512); must equal the context's d_Z */
   int r_u;     /* reduced state coordinates (1..width) */
-  int width;   /* hidden width (256) */
+  int width;   /* hidden width: 256 or 512 */
   int depth;   /* hidden layers (4) */
 } mrdino_dims;
 

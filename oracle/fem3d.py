@@ -254,9 +254,15 @@ def solve_sample(ops: Operators3D, xi_i: np.ndarray, z: np.ndarray, want_grad=Tr
     K = stiffness(ops, field_nodal(xi_i, prob))
     f = ops.F @ z
     u, lu, iters = fem2d.newton_solve(K, ops.w, prob.reaction, f, rtol=rtol, linear=linear)
-    out = {"u": u, "q": qoi(ops, u), "newton_iters": iters}
+    out = {"u": u, "q": qoi(ops, u), "newton_iters": iters, "lu": lu}
     if want_grad:
         lam = lu.solve(qoi_gradient(ops, u))
         out["lam"] = lam
         out["g"] = ops.F.T @ lam
     return out
+
+
+def control_jacobian(ops: Operators3D, sample: dict) -> np.ndarray:
+    """du/dz = A(u)^{-1} F (d_U x d_Z): the d_Z linearised solves with the
+    factors of the converged state (Sec. 3.4, eq. (projected_sensitivity))."""
+    return sample["lu"].solve(ops.F)

@@ -65,8 +65,15 @@ size_t coarse_lds(const PdeGeo& g);
 template <typename TS>
 void hierarchy3(const Pde3Geo& g, const double* em, double* k64, const Mg3Bufs<TS>& b, int64_t N, hipStream_t st);
 template <typename TW, typename TS>
-void state3(const Pde3Geo& g, const double* Z, const double* k64, TW* u, TW* f, const Mg3Bufs<TS>& b,
-            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, int bs, hipStream_t st);
+void state3(const Pde3Geo& g, const double* Z, int64_t z_stride, const double* k64, TW* u, TW* f,
+            const Mg3Bufs<TS>& b, const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N,
+            int bs, hipStream_t st);
+template <typename TW, typename TS>
+void linearized3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* x, const Mg3Bufs<TS>& b,
+                 const SolveParams& sp, int64_t s0, int64_t ns, int k0, int nk, double* out, int64_t ld, int* lin,
+                 int* flag, int64_t N, hipStream_t st);
+template <typename TW>
+void interior_copy3(const TW* u, double* out, int n, int64_t nodes, int64_t N, hipStream_t st);
 template <typename TW, typename TS>
 void adjoint3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* lam, const Mg3Bufs<TS>& b,
               const SolveParams& sp, const double* q, const double* tstar, int act, double act_w, double* gout,
@@ -333,7 +340,7 @@ int launch3(saa_ctx* c, int& choice, F&& launch) {
   return check_hip(hipGetLastError());
 }
 
-int run_state3(saa_ctx* c, int prec, const double* Z, const SolveParams& sp) {
+int run_state3(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const SolveParams& sp) {
   int rc;
   int& bs = c->bs3_state[prec];
   // c->k64 is allocated by the first build_mg3: read it at launch time
@@ -344,7 +351,7 @@ int run_state3(saa_ctx* c, int prec, const double* Z, const SolveParams& sp) {
       if (!c->mg3_64.built && (rc = build_mg3(c, c->mg3_64))) return rc;
       if (!K() || !c->mg3_64.E.p) return SAA_E_INVALID;
       return launch3(c, bs, [&](int b) {
-        saa_launch::state3<double, double>(c->geo3, Z, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_64.view(), sp,
+        saa_launch::state3<double, double>(c->geo3, Z, z_stride, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_64.view(), sp,
                                            (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
                                            b, c->st);
       });
@@ -352,7 +359,7 @@ int run_state3(saa_ctx* c, int prec, const double* Z, const SolveParams& sp) {
       if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
       if (!K() || !c->mg3_32.E.p) return SAA_E_INVALID;
       return launch3(c, bs, [&](int b) {
-        saa_launch::state3<double, float>(c->geo3, Z, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_32.view(), sp,
+        saa_launch::state3<double, float>(c->geo3, Z, z_stride, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_32.view(), sp,
                                           (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
                                           b, c->st);
       });
@@ -360,7 +367,7 @@ int run_state3(saa_ctx* c, int prec, const double* Z, const SolveParams& sp) {
       if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
       if (!K() || !c->mg3_32.E.p) return SAA_E_INVALID;
       return launch3(c, bs, [&](int b) {
-        saa_launch::state3<float, float>(c->geo3, Z, K(), (float*)c->u.p, (float*)c->f.p, c->mg3_32.view(), sp,
+        saa_launch::state3<float, float>(c->geo3, Z, z_stride, K(), (float*)c->u.p, (float*)c->f.p, c->mg3_32.view(), sp,
                                          (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
                                          b, c->st);
       });
@@ -377,7 +384,7 @@ int run_state(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const Sol
         (rc = c->lam.alloc_zero(tw, c->st)))
       return rc;
   }
-  if (c->d3) return z_stride == 0 ? run_state3(c, prec, Z, sp) : SAA_E_INVALID;
+  if (c->d3) return run_state3(c, prec, Z, z_stride, sp);
   switch (prec) {
     case SAA_FP64:
       if (!c->mg64.built && (rc = build_mg(c, c->mg64))) return rc;
@@ -501,10 +508,10 @@ int validate_call(saa_ctx* c, const double* z, int form, const void* model, cons
     if (model != nullptr) return SAA_E_INVALID;
     if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
   } else if (form == SAA_FORM_MRDINO) {
-    if (model == nullptr || c->d3) return SAA_E_INVALID;
+    if (model == nullptr) return SAA_E_INVALID;
     if (opt->prec != SAA_FP32 && opt->prec != SAA_BF16 && opt->prec != SAA_FP8) return SAA_E_INVALID;
     const mrdino_model* m = (const mrdino_model*)model;
-    if (m->dims.d_z != c->dz || m->dims.r_m > c->K1 * c->K1) return SAA_E_MODEL;
+    if (m->dims.d_z != c->dz || m->dims.r_m > c->n_kl) return SAA_E_MODEL;
   } else {
     return SAA_E_INVALID;
   }
@@ -591,6 +598,18 @@ int ctx_create3(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx**
   if (!rc) rc = c->timer.create();
   if (!rc) rc = c->mt.alloc(sizeof(double) * (size_t)c->nodes);
   if (!rc) rc = c->G3.alloc(sizeof(double) * (size_t)s * np);
+  if (!rc) rc = c->order.alloc(sizeof(int) * (size_t)c->n_kl);
+  if (!rc) {   // KL modes by increasing j^2 + k^2 + l^2, ties by increasing (j, k, l)
+    std::vector<std::array<int, 4>> modes;
+    for (int j = 1; j <= c->K1; ++j)
+      for (int k = 1; k <= c->K1; ++k)
+        for (int l = 1; l <= c->K1; ++l) modes.push_back({j * j + k * k + l * l, j, k, l});
+    std::sort(modes.begin(), modes.end());
+    std::vector<int> ord;
+    for (const auto& md : modes) ord.push_back(((md[1] - 1) * c->K1 + (md[2] - 1)) * c->K1 + (md[3] - 1));
+    rc = check_hip(hipMemcpyAsync(c->order.p, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
+  }
   std::vector<double> amp, G;
   if (!rc) {
     saa_rt::target_mass3(n, p->target, p->u_target, c->mt_host, c->ctt);
@@ -686,6 +705,13 @@ int multi_work(int count, saa_ctx* const* ctx, const saa_options* opt, MgStore<T
 // C ABI
 // ---------------------------------------------------------------------------
 namespace saa_rt {
+
+int run_linearized3(saa_ctx* c, int prec, const SolveParams& sp, int64_t s0, int64_t ns, double* out, int64_t ld);
+
+int jacobians3(saa_ctx* c, const saa_options* opt, int64_t s0, int64_t ns, double* out, int64_t ld) {
+  if (!c->d3 || s0 < 0 || ns < 1 || s0 + ns > c->N) return SAA_E_INVALID;
+  return run_linearized3(c, opt->prec, solve_params(opt, opt->prec == SAA_FP32), s0, ns, out, ld);
+}
 
 // Reduced control Jacobians of the states of the last saa_solve_states call
 // by adjoints (see saa_k_adjoint_jac): JY (device, N d_Z x r_u).
@@ -996,7 +1022,7 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     const SurrogateGraph::Key key{m->serial, m->version, opt->prec,  opt->t_mode,     opt->beta,
                                   opt->eps,   opt->alpha,  opt->t_in, c->N,            opt->risk,
                                   opt->risk_kappa, opt->risk_tau};
-    const bool enc_ready = opt->prec == SAA_FP32 || c->enc_rm == m->dims.r_m;
+    const bool enc_ready = opt->prec == SAA_FP32 || c->enc_rm == enc_key(m->dims.r_m, m->kin);
     if (!tm.on && !sg.disabled && !(sg.exec && sg.key == key) && sg.seen == key && enc_ready &&
         (rc = capture_surrogate(c, m, opt, key)))
       return rc;
@@ -1129,9 +1155,92 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
   return fill_report(c, rep, secs, nullptr);
 }
 
+}  // extern "C"
+
+namespace saa_rt {
+
+// Control Jacobians of samples [s0, s0 + ns) of a 3D context after its state
+// solve: out[((s - s0) d_Z + k) ld + p] = (du_s/dz_k)_p (interior order).
+int run_linearized3(saa_ctx* c, int prec, const SolveParams& sp, int64_t s0, int64_t ns, double* out, int64_t ld) {
+  if (!c->k64.p || !c->u.p) return SAA_E_INVALID;
+  const double* K = (const double*)c->k64.p;
+  switch (prec) {
+    case SAA_FP64:
+      saa_launch::linearized3<double, double>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
+                                              c->mg3_64.view(), sp, s0, ns, 0, c->dz, out, ld, (int*)c->lin_adj.p,
+                                              (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32_DC64:
+      saa_launch::linearized3<double, float>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
+                                             c->mg3_32.view(), sp, s0, ns, 0, c->dz, out, ld, (int*)c->lin_adj.p,
+                                             (int*)c->flag.p, c->N, c->st);
+      break;
+    case SAA_FP32:
+      saa_launch::linearized3<float, float>(c->geo3, K, (float*)c->u.p, (float*)c->f.p, (float*)c->lam.p,
+                                            c->mg3_32.view(), sp, s0, ns, 0, c->dz, out, ld, (int*)c->lin_adj.p,
+                                            (int*)c->flag.p, c->N, c->st);
+      break;
+    default:
+      return SAA_E_INVALID;
+  }
+  return check_hip(hipGetLastError());
+}
+
+}  // namespace saa_rt
+
+namespace {
+
+// States (interior, FP64) of a 3D context at per-sample controls Z_dev
+// (device, N x d_Z); the solver statistics of the call go to c->stats().
+int states3(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
+            SolveParams* sp_out) {
+  int rc = validate_options(opt);
+  if (rc) return rc;
+  if (c->N < 1) return SAA_E_INVALID;
+  if (opt->prec != SAA_FP64 && opt->prec != SAA_FP32 && opt->prec != SAA_FP32_DC64) return SAA_E_INVALID;
+  const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
+  if (sp_out) *sp_out = sp;
+  if ((rc = run_state(c, opt->prec, Z_dev, c->dz, sp))) return rc;
+  if (opt->prec == SAA_FP32) saa_launch::interior_copy3<float>((float*)c->u.p, u_dev, c->prob.n, c->nodes, c->N, c->st);
+  else saa_launch::interior_copy3<double>((double*)c->u.p, u_dev, c->prob.n, c->nodes, c->N, c->st);
+  if (q_dev &&
+      (rc = check_hip(hipMemcpyAsync(q_dev, c->q.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->st))))
+    return rc;
+  return check_hip(hipMemsetAsync(c->lin_adj.p, 0, sizeof(int) * c->N, c->st));
+}
+
+// Solver statistics of the last 3D state / linearised solves into the report.
+int states3_report(saa_ctx* c, saa_report* rep, std::chrono::steady_clock::time_point t0) {
+  saa_launch::cvar((double*)c->q.p, (double*)c->g.p, c->N, c->dz, 0.0, 1.0, 0.0, (double*)c->zdev.p, 1, 0.0, 0,
+                   c->tstar(), c->out(), (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
+                   (int*)c->lin_adj.p, nullptr, c->stats(), c->cwork.p, c->st);
+  int rc = check_hip(hipGetLastError());
+  if (!rc) rc = fetch_results(c);
+  if (rc) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  rc = fill_report(c, rep, secs, nullptr);
+  if (rep) rep->t_star = rep->dJ_dt = 0.0;
+  return rc;
+}
+
+int solve_states3(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
+                  double* dudz_dev, saa_report* rep) {
+  const auto t0 = std::chrono::steady_clock::now();
+  SolveParams sp;
+  int rc = states3(c, Z_dev, opt, u_dev, q_dev, &sp);
+  if (!rc && dudz_dev) rc = saa_rt::run_linearized3(c, opt->prec, sp, 0, c->N, dudz_dev, c->d_u);
+  if (rc) return rc;
+  return states3_report(c, rep, t0);
+}
+
+}  // namespace
+
+extern "C" {
+
 int saa_solve_states(saa_ctx* c, const double* Z_dev, const saa_options* opt, double* u_dev, double* q_dev,
                      double* dudz_dev, saa_report* rep) {
-  if (!c || !Z_dev || !u_dev || c->d3) return SAA_E_INVALID;
+  if (!c || !Z_dev || !u_dev) return SAA_E_INVALID;
+  if (c->d3) return solve_states3(c, Z_dev, opt, u_dev, q_dev, dudz_dev, rep);
   int rc = validate_options(opt);
   if (rc) return rc;
   if (c->N < 1) return SAA_E_INVALID;

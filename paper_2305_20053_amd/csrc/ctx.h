@@ -25,6 +25,11 @@ void target_mass3(int n, int target, double u_target, std::vector<double>& mt, d
 // saa_solve_states call; JY: device, (N d_Z) x r_u.
 int adjoint_jacobians(saa_ctx* c, const saa_options* opt, const double* MPhiT, int r_u, double* JY);
 
+// 3D: control Jacobians du/dz of samples [s0, s0 + ns) for the states of the
+// last saa_solve_states call (d_Z linearised solves per sample);
+// out (device): ((s - s0) d_Z + k) ld + interior index.
+int jacobians3(saa_ctx* c, const saa_options* opt, int64_t s0, int64_t ns, double* out, int64_t ld);
+
 template <typename TS>
 struct MgStore {
   DevBuf WE, WN, KD, D, X, B, T, cx, cr, cp, cq;
@@ -173,9 +178,9 @@ struct saa_ctx {
   saa_rt::HostBuf hres;       // pinned host copy of `res`
   saa_rt::DevBuf jobs;        // job tables of multi-problem launches led by this context
   saa_rt::DevBuf cwork;       // CVaR reduction workspace (partials, probe histograms, active set)
-  saa_rt::DevBuf enc;         // surrogate input: leading KL coordinates as BF16, N_max x 128
-  int enc_rm = -1;            // r_m that `enc` holds for the installed samples (-1: stale)
-  saa_rt::DevBuf order;       // KL modes by increasing j^2 + k^2 (ties lexicographic)
+  saa_rt::DevBuf enc;         // surrogate input: leading KL coordinates as BF16, N_max x kin
+  int enc_rm = -1;            // enc_key(r_m, kin) of what `enc` holds for the installed samples (-1: stale)
+  saa_rt::DevBuf order;       // KL modes by increasing |k|^2 (ties lexicographic), K1^dim entries
   saa_rt::PhaseTimer timer;
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)
   SurrogateGraph sg;

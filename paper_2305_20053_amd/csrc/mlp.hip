@@ -182,13 +182,13 @@ __global__ void saa_k_pad(float* dst, const float* src, int n_src, int n_dst) {
 }
 
 // BF16 surrogate input of every installed sample: X[s][k] = xi_s[order[k]] for
-// k < r_m, 0 up to 128 (the leading KL coordinates, Sec. 3.3).  The samples
+// k < r_m, 0 up to kin (the leading KL coordinates, Sec. 3.3).  The samples
 // are fixed, so this runs once per sample set.
-__global__ void saa_k_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, __bf16* X) {
+__global__ void saa_k_encode(const double* xi, int nkl, const int* order, int r_m, int kin, int64_t N, __bf16* X) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N * 128) return;
-  const int64_t s = t >> 7;
-  const int k = (int)(t & 127);
+  if (t >= N * kin) return;
+  const int64_t s = t / kin;
+  const int k = (int)(t - s * kin);
   X[t] = (__bf16)(k < r_m ? (float)xi[s * nkl + order[k]] : 0.0f);
 }
 
@@ -207,7 +207,7 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
   const float* w = W0 + (int64_t)f * (r_m + d_z) + r_m;
   float acc = b0[f];
 #pragma unroll
-  for (int k = 0; k < 32; ++k)   // d_z <= 32: every load issued at once
+  for (int k = 0; k < 64; ++k)   // d_z <= 64: every load issued at once
     if (k < d_z) acc += w[k] * (float)z[k];
   b0eff[f] = acc;
 }
@@ -226,14 +226,15 @@ __global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, cons
 // FP8: the activations of a sample share one power-of-two scale; each wave
 // posts its per-sample maximum in LDS before the publishing barrier.
 // ---------------------------------------------------------------------------
-template <int W, int KIN, int DEPTH, int NZT, int WAVES, class OP>
+template <int W, int KIN, int DEPTH, int NZT, int WAVES, int SB, class OP>
 __global__ void __launch_bounds__(WAVES * 64, 1)
     saa_k_mlp_mfma(MlpDev net, const __bf16* xenc, int64_t N, double* q_out, double* g_out) {
   constexpr int MT = W / 16, KS = W / 32, KS1 = KIN / 32;
-  constexpr int SB = 4, MW = MT / WAVES;   // sample blocks; output tiles per wave
+  constexpr int MW = MT / WAVES;           // output tiles per wave (SB blocks of 16 samples)
   constexpr int KW = MW / 2;               // k-steps a wave publishes
   constexpr int FB = OP::FB;               // bytes per 16 x 32 fragment
-  static_assert(MW % 2 == 0 && KS == KW * WAVES && NZT <= WAVES, "feature split of width 256");
+  static_assert(MW % 2 == 0 && KS == KW * WAVES && NZT <= WAVES && SB >= 1 && SB <= 4 && KS1 <= KS,
+                "feature split of the width over the waves");
   typedef typename OP::vec vec;
   extern __shared__ uint4 lds[];
   vec* act = (vec*)lds;                                          // [SB][KS][64]: B fragments
@@ -242,9 +243,11 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, c16 = ln & 15;
   _Float16* myg = (_Float16*)((char*)lds + SB * KS * FB + SMAX) + (size_t)wv * DEPTH * MW * SB * 256;
   float* qs = (float*)lds;                                       // [WAVES][SB][16] (reuses act)
-  const int64_t base = (int64_t)blockIdx.x * 64;
+  const int64_t base = (int64_t)blockIdx.x * (16 * SB);
   f32x4 acc[MW][SB];
-  float ax[SB] = {1.f, 1.f, 1.f, 1.f};   // scale of the current B operands, per sample block (FP8)
+  float ax[SB];                          // scale of the current B operands, per sample block (FP8)
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) ax[sb] = 1.0f;
   // operand k of the stream in this format (the FP8 copy has 512-byte fragments)
   auto operand = [&](const void* bf16_op) -> const char* {
     if constexpr (OP::scaled)
@@ -332,7 +335,6 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   };
 
   if constexpr (OP::scaled) {   // FP8: scale and publish the encoded input like a layer output
-    static_assert(KS1 <= KS, "input k-steps");
 #pragma unroll
     for (int j = 0; j < MW; ++j)
 #pragma unroll
@@ -385,7 +387,9 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
   {
     product(operand(net.wp[DEPTH]), MT, KS, false);
-    float qp[SB] = {0.f, 0.f, 0.f, 0.f};   // this wave's part of |phi + c|^2
+    float qp[SB];                          // this wave's part of |phi + c|^2
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) qp[sb] = 0.0f;
 #pragma unroll
     for (int j = 0; j < MW; ++j) {
       // rows past r_u have zero weights and zero bias + c, so v = 0 there
@@ -412,7 +416,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) qs[(wv * SB + sb) * 16 + c16] = qp[sb];
     __syncthreads();
-    if (wv == 0) {
+    if (wv == 0 && ln < 16 * SB) {
       const int sb = ln >> 4;
       const int64_t smp = base + ln;
       float qsum = 0.0f;
@@ -623,8 +627,8 @@ void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld,
 void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st) {
   saa_k_pad<<<nblk(n_dst, 256), 256, 0, st>>>(dst, src, n_src, n_dst);
 }
-void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, void* X, hipStream_t st) {
-  saa_k_encode<<<nblk(N * 128, 256), 256, 0, st>>>(xi, nkl, order, r_m, N, (__bf16*)X);
+void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int kin, int64_t N, void* X, hipStream_t st) {
+  saa_k_encode<<<nblk(N * kin, 256), 256, 0, st>>>(xi, nkl, order, r_m, kin, N, (__bf16*)X);
 }
 void mlp_add_pad(float* dst, const float* a, const float* b, int n, int w, hipStream_t st) {
   saa_k_add_pad<<<nblk(w, 256), 256, 0, st>>>(dst, a, b, n, w);
@@ -634,35 +638,64 @@ void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, 
   saa_k_b0eff<<<nblk(width, 256), 256, 0, st>>>(b0eff, W0, b0, z, width, r_m, d_z);
 }
 
-// Supported shapes: width 256, depth 4, r_m <= 128, d_z <= 32.
-// prec: 0 FP32 reference kernel, 1 BF16, 2 FP8.
-// Supported shapes: width 256, depth 4, r_m <= 128, d_z <= 32.
+// Network shapes of the fused kernel (and of the FP32 reference kernel):
+// width 256 (r_m <= 128, d_z <= 32, 64 samples per 8-wave workgroup) or
+// width 512 (r_m <= 256, d_z <= 64, 32 samples per workgroup: the fp16
+// GELU' of 4 layers x 512 features x 32 samples fills 128 KB of LDS), depth
+// 4, r_u <= width.  prec: 0 FP32 reference kernel, 1 BF16, 2 FP8.
+struct MlpShape256 {
+  static constexpr int W = 256, KIN = 128, NZT = 2, SB = 4;
+};
+struct MlpShape512 {
+  static constexpr int W = 512, KIN = 256, NZT = 4, SB = 2;
+};
+int mlp_kin(int width) { return width == 512 ? 256 : 128; }
+int mlp_nzt(int width) { return width == 512 ? 4 : 2; }
+bool mlp_shape_ok(int width, int depth, int r_m, int d_z, int r_u) {
+  if (depth != 4 || r_m < 1 || d_z < 1 || r_u < 1 || r_u > width) return false;
+  if (width == 256) return r_m <= 128 && d_z <= 32;
+  if (width == 512) return r_m <= 256 && d_z <= 64;
+  return false;
+}
+
 int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* order, const void* xenc,
              int64_t N, double* q, double* g, int n_cu, hipStream_t st) {
-  if (net.width != 256 || net.depth != 4 || net.r_m > 128 || net.d_z > 32 || net.r_u > 256) return -1;
+  if (!mlp_shape_ok(net.width, net.depth, net.r_m, net.d_z, net.r_u)) return -1;
   (void)n_cu;
+  const int W = net.width;
   if (prec == 1 || prec == 2) {
     constexpr int SW = 8;   // waves per workgroup: two per SIMD
-    if (net.kin != 128 || net.ws_frags != 16 * 4 + 4 * 16 * 8 + 4 * 16 * 8 + 2 * 8) return -1;
+    const int kin = mlp_kin(W), nzt = mlp_nzt(W);
+    // wp[0], wp[1..4] and wt[4..1], w0z (the stream of the model's packing)
+    const int64_t frags =
+        (int64_t)(W / 16) * (kin / 32) + 8 * (int64_t)(W / 16) * (W / 32) + (int64_t)nzt * (W / 32);
+    if (net.kin != kin || net.ws_frags != frags) return -1;
     if (prec == 2 && (!net.ws8 || !net.wsc_inv)) return -1;
-    const unsigned grid = (unsigned)((N + 63) / 64);
-    const size_t gelu_lds = (size_t)4 * 256 * 2 * 64;   // DEPTH x width x fp16 x 64 samples
-    auto run = [&](auto op, const void* fn) -> int {
+    auto run = [&](auto op, auto shape, const void* fn) -> int {
       typedef decltype(op) OP;
-      const size_t lds = (size_t)4 * 8 * OP::FB + (OP::scaled ? SW * 4 * 16 * 4 : 0) + gelu_lds;
+      typedef decltype(shape) SH;
+      const size_t gelu_lds = (size_t)4 * SH::W * 2 * 16 * SH::SB;   // DEPTH x width x fp16 x samples
+      const size_t lds = (size_t)SH::SB * (SH::W / 32) * OP::FB + (OP::scaled ? SW * SH::SB * 16 * 4 : 0) + gelu_lds;
       static bool attr_set = false;
       if (!attr_set) {
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -2;
         attr_set = true;
       }
-      saa_k_mlp_mfma<256, 128, 4, 2, SW, OP><<<grid, SW * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
+      const unsigned grid = (unsigned)((N + 16 * SH::SB - 1) / (16 * SH::SB));
+      saa_k_mlp_mfma<SH::W, SH::KIN, 4, SH::NZT, SW, SH::SB, OP>
+          <<<grid, SW * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
       return 0;
     };
-    if (prec == 1) return run(OpBF16{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, OpBF16>);
-    return run(OpFP8{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, OpFP8>);
+    if (W == 256) {
+      if (prec == 1) return run(OpBF16{}, MlpShape256{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, 4, OpBF16>);
+      return run(OpFP8{}, MlpShape256{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, 4, OpFP8>);
+    }
+    if (prec == 1) return run(OpBF16{}, MlpShape512{}, (const void*)saa_k_mlp_mfma<512, 256, 4, 4, SW, 2, OpBF16>);
+    return run(OpFP8{}, MlpShape512{}, (const void*)saa_k_mlp_mfma<512, 256, 4, 4, SW, 2, OpFP8>);
   }
   const int64_t blocks = (N + 7) / 8;
-  saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);
+  if (W == 256) saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);
+  else saa_k_mlp_fp32<512, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);
   return 0;
 }
 

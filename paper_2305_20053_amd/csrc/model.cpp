@@ -24,7 +24,10 @@ int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* 
              int64_t N, double* q, double* g, int n_cu, hipStream_t st);
 void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, float* wsc_inv, void* ws8, int64_t n_frags,
                   hipStream_t st);
-void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int64_t N, void* X, hipStream_t st);
+void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int kin, int64_t N, void* X, hipStream_t st);
+int mlp_kin(int width);
+int mlp_nzt(int width);
+bool mlp_shape_ok(int width, int depth, int r_m, int d_z, int r_u);
 void mlp_add_pad(float* dst, const float* a, const float* b, int n, int w, hipStream_t st);
 }  // namespace saa_launch
 
@@ -44,8 +47,7 @@ int64_t param_count(const mrdino_dims& d) {
 }
 
 bool dims_supported(const mrdino_dims& d) {
-  return d.width == 256 && d.depth == 4 && d.r_m >= 1 && d.r_m <= 128 && d.d_z >= 1 && d.d_z <= 32 &&
-         d.r_u >= 1 && d.r_u <= 256;
+  return saa_launch::mlp_shape_ok(d.width, d.depth, d.r_m, d.d_z, d.r_u);
 }
 
 MlpDev view(const mrdino_model* m) {
@@ -101,8 +103,8 @@ int pack(mrdino_model* m) {
     saa_launch::mlp_pad((float*)m->bias[L].p, P + m->off_b[L], rows, W, st);
   }
   saa_launch::mlp_add_pad((float*)m->bc.p, (const float*)m->bias[d.depth].p, (const float*)m->c.p, d.r_u, W, st);
-  saa_launch::mlp_pack_bwd((char*)m->ws.p + 1024 * m->f_w0z, P + m->off_w[0], 32, W, W, d.d_z, d.r_m + d.d_z,
-                           d.r_m, st);
+  saa_launch::mlp_pack_bwd((char*)m->ws.p + 1024 * m->f_w0z, P + m->off_w[0], 16 * saa_launch::mlp_nzt(W), W, W,
+                           d.d_z, d.r_m + d.d_z, d.r_m, st);
   // FP8 copy: operands in stream order wp[0..depth], wt[depth..1], w0z
   int64_t off[2 * MLP_MAX_DEPTH + 3];
   int n = 0;
@@ -140,7 +142,7 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
   m->serial = next_serial.fetch_add(1);
   m->dims = *d;
   m->st = (hipStream_t)hip_stream;
-  m->kin = 128;   // the BF16 kernel reads a fixed 128-column layer-0 operand (r_m <= 128)
+  m->kin = saa_launch::mlp_kin(d->width);   // columns of the BF16 layer-0 operand (r_m zero padded)
   m->n_params = param_count(*d);
   int64_t off = 0;
   int in = d->r_m + d->d_z;
@@ -165,7 +167,7 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
     nf += (int64_t)(W / 16) * (W / 32);
   }
   m->f_w0z = nf;
-  nf += 2 * (W / 32);
+  nf += saa_launch::mlp_nzt(W) * (W / 32);
   m->ws_frags = nf;
   if (!rc) rc = m->ws.alloc_zero(1024 * (size_t)nf, m->st);
   if (!rc) rc = m->ws8.alloc_zero(512 * (size_t)nf, m->st);
@@ -370,22 +372,22 @@ int mrdino_load(const char* path, void* hip_stream, mrdino_model** out) {
 // the context's stream.  z_dev: device, d_Z.  prec: SAA_FP32, SAA_BF16 or SAA_FP8.
 int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, double* q, double* g) {
   const mrdino_dims& d = m->dims;
-  if (d.d_z != c->dz || d.r_m > c->K1 * c->K1) return SAA_E_MODEL;
+  if (d.d_z != c->dz || d.r_m > c->n_kl) return SAA_E_MODEL;
   if (prec != SAA_FP32 && prec != SAA_BF16 && prec != SAA_FP8) return SAA_E_INVALID;
   saa_launch::mlp_b0eff((float*)m->b0eff.p, (const float*)m->master.p + m->off_w[0],
                         (const float*)m->master.p + m->off_b[0], z_dev, d.width, d.r_m, d.d_z, c->st);
   const MlpDev v = view(m);
-  if (prec != SAA_FP32 && c->enc_rm != d.r_m) {   // encode the installed samples once
-    int rc = c->enc.p ? SAA_OK : c->enc.alloc(sizeof(uint16_t) * 128 * (size_t)c->N_max);
+  if (prec != SAA_FP32 && c->enc_rm != enc_key(d.r_m, m->kin)) {   // encode the installed samples once
+    const size_t bytes = sizeof(uint16_t) * (size_t)m->kin * (size_t)c->N_max;
+    int rc = c->enc.bytes >= bytes ? SAA_OK : c->enc.alloc(bytes);
     if (rc) return rc;
-    saa_launch::mlp_encode((const double*)c->xi.p, c->K1 * c->K1, (const int*)c->order.p, d.r_m, c->N, c->enc.p,
-                           c->st);
+    saa_launch::mlp_encode((const double*)c->xi.p, (int)c->n_kl, (const int*)c->order.p, d.r_m, m->kin, c->N,
+                           c->enc.p, c->st);
     if ((rc = check_hip(hipGetLastError()))) return rc;
-    c->enc_rm = d.r_m;
+    c->enc_rm = enc_key(d.r_m, m->kin);
   }
   const int rc = saa_launch::mlp_eval(v, prec == SAA_FP32 ? 0 : prec == SAA_BF16 ? 1 : 2, (const double*)c->xi.p,
-                                      c->K1 * c->K1,
-                                      (const int*)c->order.p, c->enc.p, c->N, q, g, 0, c->st);
+                                      (int)c->n_kl, (const int*)c->order.p, c->enc.p, c->N, q, g, 0, c->st);
   if (rc) return SAA_E_DEVICE;
   return check_hip(hipGetLastError());
 }

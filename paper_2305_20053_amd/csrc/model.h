@@ -53,5 +53,8 @@ int pack(mrdino_model* m);
 MlpDev view(const mrdino_model* m);
 }  // namespace saa_model
 
+// Key of the BF16 encoding a context holds: r_m leading coordinates padded to kin.
+inline int enc_key(int r_m, int kin) { return r_m * 4096 + kin; }
+
 // Surrogate q and dq/dz for the installed samples (device outputs, ctx stream).
 int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, double* q, double* g);

@@ -769,9 +769,10 @@ __global__ void __launch_bounds__(HB) saa_k_hierarchy3(Pde3Geo g, const double* 
 // q = (u - ut)^T M (u - ut).  One block per sample; all samples share z.
 // ---------------------------------------------------------------------------
 template <typename TW, typename TS, int BSZ>
-__global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, const double* k64_all, TW* u_all,
-                                                   TW* f_all, Mg3Bufs<TS> all, SolveParams sp, double* q_out,
-                                                   int* newton_out, int* lin_out, int* flag_out, int64_t N) {
+__global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, int64_t z_stride,
+                                                   const double* k64_all, TW* u_all, TW* f_all, Mg3Bufs<TS> all,
+                                                   SolveParams sp, double* q_out, int* newton_out, int* lin_out,
+                                                   int* flag_out, int64_t N) {
   __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
   __shared__ double zs[SAA_MAX_DZ];
   __shared__ double Gs[4 * 97];
@@ -782,7 +783,7 @@ __global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, 
   TW* u = u_all + s * g.nodes;
   TW* f = f_all + s * g.nodes;
   Mg3Bufs<TS> m = sample_bufs3(all, g, s);
-  if (threadIdx.x < g.dz) zs[threadIdx.x] = Z[threadIdx.x];
+  if (threadIdx.x < g.dz) zs[threadIdx.x] = Z[s * z_stride + threadIdx.x];   // z_stride 0: one shared control
   for (int t = threadIdx.x; t < ns * np; t += BSZ) Gs[t] = g.G[t];
   __syncthreads();
   // f = F z: lumped separable sources; u = 0
@@ -927,6 +928,100 @@ __global__ void __launch_bounds__(BSZ) saa_k_adjoint3(Pde3Geo g, const double* k
   }
 }
 
+// ---------------------------------------------------------------------------
+// Control Jacobians (training data, Sec. 3.4 eq. (projected_sensitivity)):
+// for samples s0 .. s0 + gridDim.x and controls k0 .. k0 + nk, solve
+// A(u) x = F e_k (the lumped k-th source, separable) by defect-corrected
+// MG-PCG reusing the sample's hierarchy, and write x at the interior nodes
+// (interior order, x fastest) to out[((s - s0) nk + k - k0) ld + .] in FP64.
+// ---------------------------------------------------------------------------
+template <typename TW, typename TS, int BSZ>
+__global__ void __launch_bounds__(BSZ) saa_k_linearized3(Pde3Geo g, const double* k64_all, const TW* u_all,
+                                                        TW* b_all, TW* x_all, Mg3Bufs<TS> all, SolveParams sp,
+                                                        int64_t s0, int k0, int nk, double* out, int64_t ld,
+                                                        int* lin_out, int* flag_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
+  __shared__ double Gs[4 * 97];
+  const int64_t s = s0 + blockIdx.x;
+  if (s >= N) return;
+  const int n = g.n[0], np = n + 1, ns = g.s, m1 = n - 1;
+  const double* K = k64_all + s * g.nodes;
+  const TW* u = u_all + s * g.nodes;
+  TW* b = b_all + s * g.nodes;
+  TW* x = x_all + s * g.nodes;
+  Mg3Bufs<TS> m = sample_bufs3(all, g, s);
+  for (int t = threadIdx.x; t < ns * np; t += BSZ) Gs[t] = g.G[t];
+  __syncthreads();
+  build_diagonals3<TW, TS>(g, m, u);
+  int lin = 0;
+  bool ok = true;
+  for (int kk = k0; kk < k0 + nk; ++kk) {
+    const int a = kk % ns, bb = (kk / ns) % ns, c = kk / (ns * ns);
+    for_nodes3(n, [&](int p, int i, int j, int k) {
+      const double v = inner3(i, j, k, n) ? g.src_c * Gs[a * np + i] * Gs[bb * np + j] * Gs[c * np + k] : 0.0;
+      b[p] = (TW)v;
+    });
+    __syncthreads();
+    lin += dc_solve3<TW, TS>(g, m, sp, K, u, b, x, red, &ok);
+    double* o = out + ((s - s0) * nk + (kk - k0)) * ld;
+    for_nodes3(n, [&](int p, int i, int j, int k) {
+      if (inner3(i, j, k, n)) o[(i - 1) + (int64_t)m1 * ((j - 1) + (int64_t)m1 * (k - 1))] = (double)x[p];
+    });
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    lin_out[s] = lin;
+    if (!ok) flag_out[s] |= SAA_FLAG_DC;
+  }
+}
+
+// Interior values of node vectors: out[s][(i-1) + m (j-1) + m^2 (k-1)] =
+// u[s][node (i, j, k)], m = n - 1, in FP64.
+template <typename TW>
+__global__ void saa_k_interior3(const TW* u_all, double* out, int n, int64_t nodes, int64_t N) {
+  const int m = n - 1;
+  const int64_t du = (int64_t)m * m * m;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * du) return;
+  const int64_t s = t / du;
+  const int64_t p = t - s * du;
+  const int i = (int)(p % m) + 1, j = (int)((p / m) % m) + 1, k = (int)(p / ((int64_t)m * m)) + 1;
+  out[t] = (double)u_all[s * nodes + i + (int64_t)(n + 1) * (j + (int64_t)(n + 1) * k)];
+}
+
+// out[s][p] = (M_II (v_s - vbar))_p on the (n-1)^3 interior grid (interior
+// order), consistent Q1 mass: the tensor product of the 1D (h/6) [1 4 1]
+// (boundary values zero).  vbar may be null.
+__global__ void saa_k_mass_rows3(const double* V, int64_t ldv, const double* vbar, double* out, int64_t ldo, int n,
+                                 int64_t rows) {
+  const int m = n - 1;
+  const int64_t du = (int64_t)m * m * m;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * du) return;
+  const int64_t s = t / du;
+  const int64_t p = t - s * du;
+  const int i = (int)(p % m), j = (int)((p / m) % m), k = (int)(p / ((int64_t)m * m));
+  const double* v = V + s * ldv;
+  const double h = 1.0 / n, w1[3] = {1.0, 4.0, 1.0};
+  double acc = 0.0;
+  for (int dk = -1; dk <= 1; ++dk) {
+    const int kk = k + dk;
+    if (kk < 0 || kk >= m) continue;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= m) continue;
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= m) continue;
+        const int64_t q = ii + (int64_t)m * (jj + (int64_t)m * kk);
+        acc += w1[di + 1] * w1[dj + 1] * w1[dk + 1] * (vbar ? v[q] - vbar[q] : v[q]);
+      }
+    }
+  }
+  const double c = h / 6.0;
+  out[s * ldo + p] = c * c * c * acc;
+}
+
 namespace saa_launch {
 
 void field3(const double* xi, const double* S, const double* amp, double* em, int K1, int n, int64_t N,
@@ -944,14 +1039,45 @@ template void hierarchy3<double>(const Pde3Geo&, const double*, double*, const M
                                  hipStream_t);
 
 template <typename TW, typename TS>
-void state3(const Pde3Geo& g, const double* Z, const double* k64, TW* u, TW* f, const Mg3Bufs<TS>& b,
-            const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N, int bs,
-            hipStream_t st) {
+void state3(const Pde3Geo& g, const double* Z, int64_t z_stride, const double* k64, TW* u, TW* f,
+            const Mg3Bufs<TS>& b, const SolveParams& sp, double* q, int* newton, int* lin, int* flag, int64_t N,
+            int bs, hipStream_t st) {
   switch (bs) {
-    case 256: saa_k_state3<TW, TS, 256><<<(unsigned)N, 256, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N); break;
-    case 1024: saa_k_state3<TW, TS, 1024><<<(unsigned)N, 1024, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N); break;
-    default: saa_k_state3<TW, TS, 512><<<(unsigned)N, 512, 0, st>>>(g, Z, k64, u, f, b, sp, q, newton, lin, flag, N);
+    case 256:
+      saa_k_state3<TW, TS, 256><<<(unsigned)N, 256, 0, st>>>(g, Z, z_stride, k64, u, f, b, sp, q, newton, lin, flag,
+                                                             N);
+      break;
+    case 1024:
+      saa_k_state3<TW, TS, 1024><<<(unsigned)N, 1024, 0, st>>>(g, Z, z_stride, k64, u, f, b, sp, q, newton, lin,
+                                                               flag, N);
+      break;
+    default:
+      saa_k_state3<TW, TS, 512><<<(unsigned)N, 512, 0, st>>>(g, Z, z_stride, k64, u, f, b, sp, q, newton, lin, flag,
+                                                             N);
   }
+}
+
+// Control Jacobians of samples [s0, s0 + ns) (512-thread workgroups).
+template <typename TW, typename TS>
+void linearized3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* x, const Mg3Bufs<TS>& b,
+                 const SolveParams& sp, int64_t s0, int64_t ns, int k0, int nk, double* out, int64_t ld, int* lin,
+                 int* flag, int64_t N, hipStream_t st) {
+  saa_k_linearized3<TW, TS, 512><<<(unsigned)ns, 512, 0, st>>>(g, k64, u, bvec, x, b, sp, s0, k0, nk, out, ld, lin,
+                                                               flag, N);
+}
+
+template <typename TW>
+void interior_copy3(const TW* u, double* out, int n, int64_t nodes, int64_t N, hipStream_t st) {
+  const int64_t du = (int64_t)(n - 1) * (n - 1) * (n - 1);
+  saa_k_interior3<TW><<<(unsigned)((N * du + 255) / 256), 256, 0, st>>>(u, out, n, nodes, N);
+}
+template void interior_copy3<double>(const double*, double*, int, int64_t, int64_t, hipStream_t);
+template void interior_copy3<float>(const float*, double*, int, int64_t, int64_t, hipStream_t);
+
+void mass_rows3(const double* V, int64_t ldv, const double* vbar, double* out, int64_t ldo, int n, int64_t rows,
+                hipStream_t st) {
+  const int64_t du = (int64_t)(n - 1) * (n - 1) * (n - 1);
+  saa_k_mass_rows3<<<(unsigned)((rows * du + 255) / 256), 256, 0, st>>>(V, ldv, vbar, out, ldo, n, rows);
 }
 
 template <typename TW, typename TS>
@@ -974,8 +1100,12 @@ void adjoint3(const Pde3Geo& g, const double* k64, const TW* u, TW* bvec, TW* la
 }
 
 #define SAA_INST3(TW, TS)                                                                                    \
-  template void state3<TW, TS>(const Pde3Geo&, const double*, const double*, TW*, TW*, const Mg3Bufs<TS>&,   \
-                               const SolveParams&, double*, int*, int*, int*, int64_t, int, hipStream_t);      \
+  template void state3<TW, TS>(const Pde3Geo&, const double*, int64_t, const double*, TW*, TW*,              \
+                               const Mg3Bufs<TS>&, const SolveParams&, double*, int*, int*, int*, int64_t, int,\
+                               hipStream_t);                                                                  \
+  template void linearized3<TW, TS>(const Pde3Geo&, const double*, const TW*, TW*, TW*, const Mg3Bufs<TS>&,   \
+                                    const SolveParams&, int64_t, int64_t, int, int, double*, int64_t, int*,   \
+                                    int*, int64_t, hipStream_t);                                              \
   template void adjoint3<TW, TS>(const Pde3Geo&, const double*, const TW*, TW*, TW*, const Mg3Bufs<TS>&,       \
                                  const SolveParams&, const double*, const double*, int, double, double*, int*, \
                                  int*, int*, int64_t, int, hipStream_t);

@@ -29,6 +29,8 @@ rocblas_handle blas_create();
 void blas_destroy(rocblas_handle h);
 void mass_rows(const double* U, int64_t ldu, const double* ubar, double* out, int64_t ldo, int n, int64_t rows,
                hipStream_t st);
+void mass_rows3(const double* V, int64_t ldv, const double* vbar, double* out, int64_t ldo, int n, int64_t rows,
+                hipStream_t st);
 void colmean(const double* X, int64_t rows, int cols, int64_t ldx, double* out, hipStream_t st);
 void train_inputs(const double* xi, int nkl, const int* order, int r_m, const double* Z, int d_z, int64_t N, float* X,
                   hipStream_t st);
@@ -54,7 +56,7 @@ int sumsq(const float* x, int64_t n, double* part, hipStream_t st);
 using namespace saa_rt;
 
 struct mrdino_data {
-  int n = 0, r_m = 0, d_z = 0, r_u = 0, n_pod = 0;
+  int dim = 2, n = 0, r_m = 0, d_z = 0, r_u = 0, n_pod = 0;
   int64_t N = 0, d_u = 0;
   DevBuf X, Y, JY;          // FP32 training arrays: N x (r_m + d_z), N x r_u, (N d_z) x r_u
   DevBuf PhiT, ubar;        // FP64 r_u x d_U (M-orthonormal rows), d_U
@@ -300,13 +302,21 @@ int saa_model_set_train_state(mrdino_model* m, const TrainCheckpoint& ck) {
   return SAA_OK;
 }
 
+// Consistent mass on interior rows (P1 on the square, Q1 on the cube):
+// out[s] = M_II (U[s] - ubar), rows of the interior grid.
+static void mass_rows_dim(int dim, const double* U, int64_t ldu, const double* ubar, double* out, int64_t ldo, int n,
+                          int64_t rows, hipStream_t st) {
+  if (dim == 3) saa_launch::mass_rows3(U, ldu, ubar, out, ldo, n, rows, st);
+  else saa_launch::mass_rows(U, ldu, ubar, out, ldo, n, rows, st);
+}
+
 // Reduced QoI terms of the tracking functional for a target with interior
 // mass vector mt (node layout) and ut^T M ut = ctt (Sec. 3.3):
 //   c = Phi^T (M ubar - (M ut)_I),  c0 = ubar^T M ubar - 2 ubar . (M ut)_I + ctt - |c|^2,
 // so that |u - ut|_M^2 = |phi + c|^2 + c0 for u = ubar + Phi phi (Phi M-orthonormal).
 static int qoi_terms(const mrdino_data* D, const std::vector<double>& mt, double ctt, std::vector<double>& c_out,
                      double& c0_out) {
-  const int64_t du = (int64_t)(D->n - 1) * (D->n - 1);
+  const int64_t du = D->d_u;
   const int r_u = D->r_u;
   hipStream_t st = D->st;
   saa_rt::DevBuf Mub, vdev, cdev;
@@ -314,7 +324,7 @@ static int qoi_terms(const mrdino_data* D, const std::vector<double>& mt, double
   if ((rc = Mub.alloc(sizeof(double) * du)) || (rc = vdev.alloc(sizeof(double) * du)) ||
       (rc = cdev.alloc(sizeof(double) * r_u)))
     return rc;
-  saa_launch::mass_rows((double*)D->ubar.p, du, nullptr, (double*)Mub.p, du, D->n, 1, st);
+  mass_rows_dim(D->dim, (double*)D->ubar.p, du, nullptr, (double*)Mub.p, du, D->n, 1, st);
   std::vector<double> ub(du), mub(du);
   if ((rc = check_hip(hipMemcpyAsync(ub.data(), D->ubar.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
       (rc = check_hip(hipMemcpyAsync(mub.data(), Mub.p, sizeof(double) * du, hipMemcpyDeviceToHost, st))) ||
@@ -325,8 +335,9 @@ static int qoi_terms(const mrdino_data* D, const std::vector<double>& mt, double
   std::vector<double> v(du);
   double quad = 0.0, cross = 0.0;
   for (int64_t p = 0; p < du; ++p) {
-    const int64_t i = p % (nn - 1) + 1, j = p / (nn - 1) + 1;
-    const double m = mt[(size_t)(j * (nn + 1) + i)];
+    const int64_t i = p % (nn - 1) + 1, j = (p / (nn - 1)) % (nn - 1) + 1, k = p / ((int64_t)(nn - 1) * (nn - 1)) + 1;
+    const int64_t node = D->dim == 3 ? i + (nn + 1) * (j + (int64_t)(nn + 1) * k) : j * (nn + 1) + i;
+    const double m = mt[(size_t)node];
     v[p] = mub[p] - m;
     quad += ub[p] * mub[p];
     cross += ub[p] * m;
@@ -354,15 +365,18 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   const int64_t N = c->N, du = c->d_u;
   const int dz = c->dz;
   if (basis) {
-    if (basis->d_u != du || basis->r_u != r_u || basis->d_z != dz || basis->n != c->prob.n) return SAA_E_INVALID;
+    if (basis->d_u != du || basis->r_u != r_u || basis->d_z != dz || basis->n != c->prob.n ||
+        basis->dim != (c->d3 ? 3 : 2))
+      return SAA_E_INVALID;
     n_pod = basis->n_pod;
-    if (N < 1 || r_m < 1 || r_m > c->K1 * c->K1) return SAA_E_INVALID;
-  } else if (N < 2 || r_m < 1 || r_m > c->K1 * c->K1 || r_u < 1 || n_pod < r_u || n_pod > N || n_pod > 8192) {
+    if (N < 1 || r_m < 1 || r_m > c->n_kl) return SAA_E_INVALID;
+  } else if (N < 2 || r_m < 1 || r_m > c->n_kl || r_u < 1 || n_pod < r_u || n_pod > N || n_pod > 8192) {
     return SAA_E_INVALID;
   }
   hipStream_t st = c->st;
   mrdino_data* D = new (std::nothrow) mrdino_data();
   if (!D) return SAA_E_OOM;
+  D->dim = c->d3 ? 3 : 2;
   D->n = c->prob.n;
   D->r_m = r_m;
   D->d_z = dz;
@@ -377,13 +391,16 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   };
   if (!(D->blas = saa_launch::blas_create())) return fail(SAA_E_DEVICE);
   DevBuf U, dUdz, Dm, MD, G, Vs, MPhiT, Yd, JYd;
-  // control Jacobians: d_Z forward solves, or r_u adjoint solves (Sec. 3.4)
-  const bool adj = opt->jac_mode == SAA_JAC_ADJOINT || (opt->jac_mode == SAA_JAC_AUTO && dz >= r_u);
+  // control Jacobians: d_Z forward solves, or r_u adjoint solves (Sec. 3.4);
+  // on the cube only forward solves, projected chunk by chunk (a full
+  // N x d_Z x d_U array would not fit)
+  if (c->d3 && opt->jac_mode == SAA_JAC_ADJOINT) return fail(SAA_E_INVALID);
+  const bool adj = !c->d3 && (opt->jac_mode == SAA_JAC_ADJOINT || (opt->jac_mode == SAA_JAC_AUTO && dz >= r_u));
   int rc = U.alloc(sizeof(double) * N * du);
-  if (!rc && !adj) rc = dUdz.alloc(sizeof(double) * N * dz * du);
+  if (!rc && !adj && !c->d3) rc = dUdz.alloc(sizeof(double) * N * dz * du);
   if (rc) return fail(rc);
-  // 1. states (and forward-mode control Jacobians) of the training samples
-  rc = saa_solve_states(c, Z_dev, opt, (double*)U.p, nullptr, adj ? nullptr : (double*)dUdz.p, rep);
+  // 1. states (and, on the square, forward-mode control Jacobians) of the training samples
+  rc = saa_solve_states(c, Z_dev, opt, (double*)U.p, nullptr, (adj || c->d3) ? nullptr : (double*)dUdz.p, rep);
   if (rc) return fail(rc);
   if (basis) {  // held-out data: reuse the training basis and QoI terms
     if ((rc = D->ubar.alloc(sizeof(double) * du)) || (rc = D->PhiT.alloc(sizeof(double) * r_u * du)) ||
@@ -394,7 +411,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
                                        st))))
       return fail(rc);
     D->lam = basis->lam;
-    saa_launch::mass_rows((double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
+    mass_rows_dim(D->dim, (double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
   } else {
   // 2. weighted POD from the first n_pod states (Sec. 3.3; the paper uses 512)
   if ((rc = D->ubar.alloc(sizeof(double) * du)) || (rc = Dm.alloc(sizeof(double) * n_pod * du)) ||
@@ -402,7 +419,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     return fail(rc);
   saa_launch::colmean((double*)U.p, n_pod, (int)du, du, (double*)D->ubar.p, st);
   saa_launch::center_rows((double*)U.p, (double*)D->ubar.p, (double*)Dm.p, du, n_pod, st);
-  saa_launch::mass_rows((double*)Dm.p, du, nullptr, (double*)MD.p, du, D->n, n_pod, st);
+  mass_rows_dim(D->dim, (double*)Dm.p, du, nullptr, (double*)MD.p, du, D->n, n_pod, st);
   if ((rc = saa_launch::dgemm(D->blas, false, true, n_pod, n_pod, (int)du, 1.0, (double*)Dm.p, (int)du,
                               (double*)MD.p, (int)du, 0.0, (double*)G.p, n_pod, st)))
     return fail(rc);
@@ -435,7 +452,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   if ((rc = saa_launch::dgemm(D->blas, true, false, r_u, (int)du, n_pod, 1.0, (double*)Vs.p, r_u, (double*)Dm.p,
                               (int)du, 0.0, (double*)D->PhiT.p, (int)du, st)))
     return fail(rc);
-  saa_launch::mass_rows((double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
+  mass_rows_dim(D->dim, (double*)D->PhiT.p, du, nullptr, (double*)MPhiT.p, du, D->n, r_u, st);
   Dm.release();
   MD.release();
   }
@@ -447,6 +464,17 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     return fail(rc);
   if (adj) {   // J_r = (A^{-1} M Phi)^T F, from the states still held by the context
     if ((rc = saa_rt::adjoint_jacobians(c, opt, (const double*)MPhiT.p, r_u, (double*)JYd.p))) return fail(rc);
+  } else if (c->d3) {   // du/dz of a chunk of samples, then J_r = (M Phi)^T du/dz for the chunk
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)2 << 30) / (8 * dz * du)));
+    if ((rc = dUdz.alloc(sizeof(double) * chunk * dz * du))) return fail(rc);
+    for (int64_t s0 = 0; s0 < N && !rc; s0 += chunk) {
+      const int64_t ns = std::min<int64_t>(chunk, N - s0);
+      rc = saa_rt::jacobians3(c, opt, s0, ns, (double*)dUdz.p, du);
+      if (!rc)
+        rc = saa_launch::dgemm(D->blas, false, true, (int)(ns * dz), r_u, (int)du, 1.0, (double*)dUdz.p, (int)du,
+                               (double*)MPhiT.p, (int)du, 0.0, (double*)JYd.p + s0 * dz * r_u, r_u, st);
+    }
+    if (rc) return fail(rc);
   } else {
     if ((rc = saa_launch::dgemm(D->blas, false, true, (int)(N * dz), r_u, (int)du, 1.0, (double*)dUdz.p, (int)du,
                                 (double*)MPhiT.p, (int)du, 0.0, (double*)JYd.p, r_u, st)))
@@ -457,7 +485,7 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
     return fail(rc);
   saa_launch::d2f((double*)Yd.p, (float*)D->Y.p, N * r_u, st);
   saa_launch::d2f((double*)JYd.p, (float*)D->JY.p, N * dz * r_u, st);
-  saa_launch::train_inputs((const double*)c->xi.p, c->K1 * c->K1, (const int*)c->order.p, r_m, Z_dev, dz, N,
+  saa_launch::train_inputs((const double*)c->xi.p, (int)c->n_kl, (const int*)c->order.p, r_m, Z_dev, dz, N,
                            (float*)D->X.p, st);
   // 4. reduced QoI terms c, c0 for the context's target (Sec. 3.3)
   if ((rc = qoi_terms(D, c->mt_host, c->ctt, D->c, D->c0))) return fail(rc);
@@ -477,7 +505,8 @@ int mrdino_data_qoi(const mrdino_data* D, int target, double u_target, double* c
   if (target != SAA_TARGET_CONST && target != SAA_TARGET_SIN && target != SAA_TARGET_QUAD) return SAA_E_INVALID;
   std::vector<double> mt, cv;
   double ctt = 0.0, c0v = 0.0;
-  saa_rt::target_mass(D->n, target, u_target, mt, ctt);
+  if (D->dim == 3) saa_rt::target_mass3(D->n, target, u_target, mt, ctt);
+  else saa_rt::target_mass(D->n, target, u_target, mt, ctt);
   const int rc = qoi_terms(D, mt, ctt, cv, c0v);
   if (rc) return rc;
   for (int k = 0; k < D->r_u; ++k) c[k] = cv[k];
@@ -541,7 +570,7 @@ int mrdino_eval(mrdino_model* m, saa_ctx* c, const double* z, int want, int prec
       ((want & MRDINO_WANT_PHI) && !phi_dev) || ((want & MRDINO_WANT_DPHIDZ) && !dphidz_dev))
     return SAA_E_INVALID;
   const mrdino_dims& d = m->dims;
-  if (d.d_z != c->dz || d.r_m > c->K1 * c->K1) return SAA_E_MODEL;
+  if (d.d_z != c->dz || d.r_m > c->n_kl) return SAA_E_MODEL;
   for (int k = 0; k < d.d_z; ++k)
     if (!std::isfinite(z[k])) return SAA_E_INVALID;
   int rc = SAA_OK;
@@ -566,7 +595,7 @@ int mrdino_eval(mrdino_model* m, saa_ctx* c, const double* z, int want, int prec
     if ((rc = check_hip(hipMemcpyAsync(Zb.p, zrep.data(), sizeof(double) * zrep.size(), hipMemcpyHostToDevice,
                                        m->st))))
       return rc;
-    const int nkl = c->K1 * c->K1;
+    const int nkl = (int)c->n_kl;
     for (int64_t b0 = 0; b0 < c->N && !rc; b0 += B) {
       const int nb = (int)std::min<int64_t>(B, c->N - b0);
       saa_launch::train_inputs((const double*)c->xi.p + b0 * nkl, nkl, (const int*)c->order.p, d.r_m,

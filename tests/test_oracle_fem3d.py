@@ -203,3 +203,25 @@ def test_cg_stand_in_matches_lu():
     b = fem3d.solve_sample(ops, xi, z, linear="cg")
     assert abs(a["q"] - b["q"]) <= 1e-13 * abs(a["q"])
     assert np.linalg.norm(a["g"] - b["g"]) <= 1e-11 * np.linalg.norm(a["g"])
+
+
+def test_control_jacobian_matches_nonlinear_differences():
+    """du/dz from the d_Z linearised solves (Sec. 3.4) against central
+    differences of the nonlinear state in z (second-order differences with
+    h = 1e-5 leave an error of order h^2 u''' ~ 1e-10), and the chain rule
+    (dq/du)^T du/dz against the adjoint gradient."""
+    prob = fem3d.Problem3D(n=6, n_src_per_dim=4, kl_per_dim=3, kl_amp=20.0, target=fem3d.TARGET_SIN)
+    ops = fem3d.operators(prob)
+    xi = si.kl_coefficients(83, 1, 3, dim=3)[0]
+    z = si.control(84, prob.d_z, lo=-2.0, hi=4.0)
+    s = fem3d.solve_sample(ops, xi, z)
+    J = fem3d.control_jacobian(ops, s)
+    assert J.shape == (len(ops.interior), prob.d_z)
+    h = 1e-5
+    for k in (0, 21, 63):
+        e = np.zeros(prob.d_z)
+        e[k] = h
+        up = fem3d.solve_sample(ops, xi, z + e, want_grad=False)["u"]
+        um = fem3d.solve_sample(ops, xi, z - e, want_grad=False)["u"]
+        np.testing.assert_allclose(J[:, k], (up - um) / (2 * h), rtol=1e-6, atol=1e-7 * np.abs(J[:, k]).max())
+    np.testing.assert_allclose(fem3d.qoi_gradient(ops, s["u"]) @ J, s["g"], rtol=1e-11)
