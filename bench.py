@@ -152,8 +152,7 @@ def train_surrogate(saa, si, epochs, lo=0.0, hi=1.0, n_pod=2048):
     vdata = saa.TrainData(vctx, torch.from_numpy(si.controls(si.SEED_Z_VALID, 256, lo=lo, hi=hi)).cuda(),
                           r_m=100, r_u=200, basis=data)
     model = saa.Model(100, 25, 200, 256, 4)
-    layers = si.glorot_mlp(2315, model.widths())
-    model.set_params(np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers]))
+    model.set_params(saa.init_params(si.glorot_mlp(2315, model.widths()), data.output_scale()))
     c, c0, _ = data.info()
     model.set_qoi(c, c0)
     t0 = time.perf_counter()
@@ -166,6 +165,7 @@ def train_surrogate(saa, si, epochs, lo=0.0, hi=1.0, n_pod=2048):
     qoi = {t: data.qoi(t) for t in (saa.TARGET_CONST, saa.TARGET_SIN, saa.TARGET_QUAD)}   # one network, several objectives
     info = {"train_samples": 2048, "z_box": [lo, hi], "n_pod": n_pod, "r_m": 100, "r_u": 200, "epochs": epochs,
             "batch": 256, "steps": epochs * (2048 // 256), "precision": "bf16 products, fp32 accumulation and master",
+            "output_scale": data.output_scale(),
             "data_s": t_data, "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
             "train_rel_err_state": es, "train_rel_err_jacobian": ej,
             "heldout_rel_err_state": vs, "heldout_rel_err_jacobian": vj}
@@ -327,6 +327,98 @@ def bench_mrdino(saa, si, steps, warmup, zs, pde_value, epochs, ouu=True, ceil=N
         out["ouu"]["training"] = tinfo_box
         model_box.close()
         out["jacobian_modes"] = bench_jacobian_modes(saa, si)
+    model.close()
+    ctx.close()
+    return out
+
+
+MRDINO3_FLOP_PER_SAMPLE = (2 * (264 * 512 + 3 * 512 ** 2 + 512 * 400) +
+                           2 * (400 * 512 + 3 * 512 ** 2 + 512 * 64))
+
+
+def bench_mrdino3d(saa, si, steps, warmup, pde3_value, epochs=1600):
+    """The 3D surrogate (r_m = 200, r_u = 400, 264 -> 512^4 -> 400, d_Z =
+    64) at N = 16384 samples of the 48^3 problem: trained on 1024 GPU
+    PDE-form samples (z ~ U[0,1]^64, FP32 solves for the data, POD of all
+    1024 states, batch 128, Adam 1e-3 -> 2.5e-4, BF16 products), timed in BF16
+    and FP32, judged against the 3D PDE form on 256 held-out samples; the
+    ratio to the 3D PDE form is quoted only when the estimate is within 1e-2."""
+    import numpy as np
+    import torch
+    prob = saa.problem_3d()
+    n_train = 1024
+    t0 = time.perf_counter()
+    tctx = saa.Context(prob, n_train)
+    tctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_TRAIN3D, n_train, prob.kl_per_dim, dim=3)).cuda())
+    Zt = torch.from_numpy(si.controls(si.SEED_Z_TRAIN3D, n_train, prob.d_z)).cuda()
+    data = saa.TrainData(tctx, Zt, r_m=200, r_u=400, n_pod=n_train, opt=saa.options(prec=saa.FP32))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    model = saa.Model(200, prob.d_z, 400, 512, 4)
+    model.set_params(saa.init_params(si.glorot_mlp(2316, model.widths()), data.output_scale()))
+    t0 = time.perf_counter()
+    hist, _ = saa.train(model, data, saa.train_cfg(batch=128, epochs=epochs, lr_drop_epoch=epochs // 2, seed=8,
+                                                   prec=saa.BF16))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    es, ej = saa.data_errors(model, data)
+    data.close()
+    tctx.close()
+    N = 16384
+    ctx = saa.Context(prob, N)
+    ctx.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_LARGE3D, N, prob.kl_per_dim, dim=3)).cuda())
+    zs = [si.control(s, prob.d_z) for s in si.SEED_Z_EVAL]
+    out = {"N": N, "training": {"train_samples": n_train, "data_s": t_data, "train_s": t_train, "epochs": epochs,
+                                "batch": 128, "steps": epochs * (n_train // 128), "loss_first": float(hist[0]),
+                                "loss_last": float(hist[-1]), "train_rel_err_state": es,
+                                "train_rel_err_jacobian": ej}}
+    for name, prec in (("bf16", saa.BF16), ("fp32", saa.FP32)):
+        opt = saa.options(prec=prec)
+        nsteps = steps if prec != saa.FP32 else max(2, steps // 4)
+        for k in range(warmup):
+            ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model, opt=opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nsteps):
+            ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model, opt=opt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        reps = [ctx.objective_grad(zs[k % len(zs)], form=saa.FORM_MRDINO, model=model,
+                                   opt=saa.options(prec=prec, timing=1))[2] for k in range(min(nsteps, 5))]
+        ms_k = float(np.mean([r["ms_state"] for r in reps]))
+        flops = MRDINO3_FLOP_PER_SAMPLE * N
+        peak = MFMA_BF16_PEAK_TFLOPS if prec == saa.BF16 else VEC_FP32_PEAK_TFLOPS
+        ach = flops / (ms_k * 1e-3) / 1e12
+        out[name] = {"value": N * nsteps / wall, "ms_per_step": 1e3 * wall / nsteps, "kernel_ms": ms_k,
+                     "reduce_ms": float(np.mean([r["ms_reduce"] for r in reps])),
+                     "roofline": {"bound": "mfma" if prec == saa.BF16 else "alu", "achieved": ach, "peak": peak,
+                                  "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                                  "kernel": "saa_k_mlp_mfma<512,bf16>" if prec == saa.BF16 else "saa_k_mlp_fp32<512>",
+                                  "alg_flop_per_launch": flops}}
+    tol = 1e-2
+    hold = saa.Context(prob, 256)
+    hold.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_HELDOUT3D, 256, prob.kl_per_dim, dim=3)).cuda())
+    saa.attach_holdout(ctx, hold)
+    errs = [ctx.objective_grad(z, form=saa.FORM_MRDINO, model=model,
+                               opt=saa.options(prec=saa.BF16, fallback_tol=1e30))[2]["err_estimate"] for z in zs]
+    out["bf16"]["heldout"] = {"err_estimate": errs, "max": max(errs), "tol": tol, "samples": 256,
+                              "would_fall_back": int(sum(e > tol for e in errs))}
+    out["stated_error"] = {"tol": tol, "bf16_max_err_estimate": max(errs), "met": bool(max(errs) <= tol)}
+    if max(errs) <= tol:
+        out["stated_error"]["ratio_bf16_over_pde3d"] = out["bf16"]["value"] / pde3_value
+    else:   # what a caller gets under the rule: the 3D PDE form on the same 16384 samples
+        opt = saa.options(prec=saa.BF16, fallback_tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.objective_grad(zs[0], form=saa.FORM_MRDINO, model=model, opt=opt)[2]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["stated_error"]["fallback_value"] = N / wall
+        out["stated_error"]["fallback_used"] = r["fallback_used"]
+        out["stated_error"]["ratio_with_fallback_over_pde3d"] = (N / wall) / pde3_value
+    saa.attach_holdout(ctx, None)
+    out["ratio_bf16_over_pde3d_unqualified"] = out["bf16"]["value"] / pde3_value
+    hold.close()
     model.close()
     ctx.close()
     return out
@@ -648,6 +740,9 @@ def main():
         r3["frac_vs_copy"] = r3["achieved"] / ceil["copy_GBps"]
         r3["frac_vs_triad"] = r3["achieved"] / ceil["triad_GBps"]
         out["pde3d"]["companions_2d_N256"] = bench_companions(saa, si, args.steps, args.warmup)
+        if not args.no_mrdino and args.train_epochs > 0:
+            out["pde3d"]["mrdino3d"] = bench_mrdino3d(saa, si, args.steps, args.warmup, out["pde3d"]["value"],
+                                                      args.train_epochs)
     if not args.no_mrdino:
         out["mrdino"] = bench_mrdino(saa, si, args.steps, args.warmup, zs, value, args.train_epochs,
                                      not args.no_ouu, ceil)

@@ -444,8 +444,14 @@ typedef struct mrdino_train_cfg {
  * which drive lr_drop_epoch, and the minibatch stream) lives in the model:
  * cfg.resume = 1 continues it, so k epochs then m more give bitwise the same
  * parameters as k + m epochs in one call.  On return the device operands are
- * repacked and the model's reduced-QoI terms are set from the data.
- * epoch_loss (host, epochs, may be NULL) receives the mean loss of each epoch;
+ * repacked and the model's reduced-QoI terms are set from the data.  The
+ * output layer is trained in scaled units, phi = sigma phi', against the
+ * targets y / sigma and J / sigma (the DINO loss divided by sigma^2: the same
+ * minimiser), sigma = the RMS of the data's reduced states rounded to a power
+ * of two, so that the conversion of the stored parameters (always in the
+ * data's units) is exact; a fresh output layer scaled by sigma starts at the
+ * scale of the targets.  epoch_loss (host, epochs, may be NULL) receives the
+ * mean loss of each epoch in the data's units;
  * seconds (may be NULL) the device time of the loop.  Invalid settings return
  * SAA_E_INVALID before any device work; a failed launch SAA_E_DEVICE. */
 int mrdino_train(mrdino_model* model, mrdino_data* data, const mrdino_train_cfg* cfg, double* epoch_loss,

@@ -550,6 +550,17 @@ def sym_eig_gpu(A):
     return w, V, sw.value
 
 
+def init_params(layers, out_scale=1.0):
+    """Packed FP32 parameters of a list of (W, b) layers with the output
+    layer multiplied by out_scale (e.g. TrainData.output_scale())."""
+    import numpy as np
+    parts = []
+    for k, (W, b) in enumerate(layers):
+        f = out_scale if k == len(layers) - 1 else 1.0
+        parts.append(np.concatenate([np.ravel(W) * f, np.asarray(b) * f]))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def train_cfg(batch=256, epochs=1600, lr_drop_epoch=800, lr=1e-3, lr_late=2.5e-4, dino=1, seed=2305,
               beta1=0.9, beta2=0.999, adam_eps=1e-8, prec=None, resume=0) -> CTrainCfg:
     """Adam schedule of Sec. 4.2.1 (lr 1e-3, 2.5e-4 after 800 of 1600 epochs);
@@ -612,6 +623,16 @@ class TrainData:
         c0 = ctypes.c_double()
         _check(self._lib.mrdino_data_qoi(self._h, target, u_target, c.ctypes.data, ctypes.byref(c0)))
         return c, c0.value
+
+    def output_scale(self):
+        """The output scale sigma of training on this data: the RMS of the
+        reduced states rounded to a power of two (mrdino_train trains the
+        output layer as phi = sigma phi').  A fresh network whose output
+        layer is multiplied by sigma starts at the scale of the targets."""
+        import numpy as np
+        y = self.get("Y").astype(np.float64)
+        rms = float(np.sqrt(np.mean(y * y)))
+        return float(2.0 ** round(np.log2(rms))) if rms > 0 and np.isfinite(rms) else 1.0
 
     def get(self, which: str):
         """'X', 'Y', 'J' (float32) or 'PhiT', 'ubar' (float64) as numpy arrays."""

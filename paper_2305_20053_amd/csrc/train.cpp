@@ -39,7 +39,9 @@ void bias_gelu(float* A, const float* bias, float* H, int64_t rows, int cols, in
 void tangent0(const float* W0, int ldw, int r_m, int d_z, const float* A, int B, int W, float* JA, float* JH,
               hipStream_t st);
 void tangent_scale(const float* JA, const float* A, int B, int d_z, int W, float* JH, hipStream_t st);
-int residual(const float* P, const float* Y, int64_t n, float scale, float* G, double* part, hipStream_t st);
+int residual(const float* P, const float* Y, int64_t n, float scale, float y_scale, float* G, double* part,
+             hipStream_t st);
+void scale(float* x, int64_t n, float f, hipStream_t st);
 void layer_back(float* gH, float* gJH, const float* A, const float* JA, int B, int d_z, int W, int dino,
                 hipStream_t st);
 void colsum(const float* X, int64_t rows, int cols, float* out, int accumulate, hipStream_t st);
@@ -65,6 +67,7 @@ struct mrdino_data {
   double c0 = 0.0;
   hipStream_t st = nullptr;
   rocblas_handle blas = nullptr;   // FP64 POD products (library GEMM), owned
+  double y_scale = 0.0;            // training output scale (0: not yet computed)
   ~mrdino_data() { saa_launch::blas_destroy(blas); }
 };
 
@@ -187,7 +190,7 @@ int forward(mrdino_model* mdl, TrainWs& w, int B, int dino, bool bf) {
 
 // Loss (ws.loss[0] = state part, [1] = Jacobian part, unnormalised sums) and,
 // with want_grad, the gradient of L = (1/B) sum (|e|^2 + |E_J|_F^2) into ws.grad.
-int loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad, bool bf) {
+int loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad, bool bf, float y_scale = 1.0f) {
   const mrdino_dims& d = mdl->dims;
   const int W = d.width, in = d.r_m + d.d_z, dz = d.d_z;
   const float* P = (const float*)mdl->master.p;
@@ -196,10 +199,11 @@ int loss_grad(mrdino_model* mdl, TrainWs& w, int B, int dino, bool want_grad, bo
   int rc = forward(mdl, w, B, dino, bf);
   if (rc) return rc;
   const float sc = 2.0f / (float)B;
-  int nb = saa_launch::residual(F(w.P), F(w.Yb), (int64_t)B * d.r_u, sc, F(w.gP), (double*)w.parts.p, st);
+  int nb = saa_launch::residual(F(w.P), F(w.Yb), (int64_t)B * d.r_u, sc, y_scale, F(w.gP), (double*)w.parts.p, st);
   saa_launch::sum_parts((double*)w.parts.p, nb, loss + 0, 0, st);
   if (dino) {
-    nb = saa_launch::residual(F(w.JP), F(w.JYb), (int64_t)B * dz * d.r_u, sc, F(w.gJP), (double*)w.parts.p, st);
+    nb = saa_launch::residual(F(w.JP), F(w.JYb), (int64_t)B * dz * d.r_u, sc, y_scale, F(w.gJP),
+                              (double*)w.parts.p, st);
     saa_launch::sum_parts((double*)w.parts.p, nb, loss + 1, 0, st);
   } else {
     saa_launch::sum_parts((double*)w.parts.p, 0, loss + 1, 0, st);   // zero
@@ -243,6 +247,29 @@ void load_batch(mrdino_model* mdl, mrdino_data* D, TrainWs& w, const int* idx_de
   saa_launch::gather_rows(F(D->X), d.r_m + d.d_z, idx_dev, B, F(w.Xb), mdl->st);
   saa_launch::gather_rows(F(D->Y), d.r_u, idx_dev, B, F(w.Yb), mdl->st);
   saa_launch::gather_rows(F(D->JY), (int64_t)d.d_z * d.r_u, idx_dev, B, F(w.JYb), mdl->st);
+}
+
+// 2^round(log2(rms)) of the reduced training states (1 if they vanish).
+int output_scale(mrdino_data* D, hipStream_t st, double* sigma) {
+  if (D->y_scale > 0.0) {
+    *sigma = D->y_scale;
+    return SAA_OK;
+  }
+  const int64_t n = D->N * D->r_u;
+  DevBuf parts, acc;
+  int rc = parts.alloc(sizeof(double) * ((n + 1023) / 1024 + 1));
+  if (!rc) rc = acc.alloc(sizeof(double));
+  if (rc) return rc;
+  const int nb = saa_launch::sumsq((const float*)D->Y.p, n, (double*)parts.p, st);
+  saa_launch::sum_parts((double*)parts.p, nb, (double*)acc.p, 0, st);
+  double ss = 0.0;
+  if ((rc = check_hip(hipMemcpyAsync(&ss, acc.p, sizeof(double), hipMemcpyDeviceToHost, st))) ||
+      (rc = check_hip(hipStreamSynchronize(st))))
+    return rc;
+  const double rms = std::sqrt(ss / (double)n);
+  D->y_scale = (rms > 0.0 && std::isfinite(rms)) ? std::ldexp(1.0, (int)std::lround(std::log2(rms))) : 1.0;
+  *sigma = D->y_scale;
+  return SAA_OK;
 }
 
 bool compatible(const mrdino_model* m, const mrdino_data* D) {
@@ -636,8 +663,22 @@ int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, d
     ts->rng = cfg->seed;
     ts->started = true;
   }
+  // Output scale: the reduced states of this workload vary by a few 1e-3
+  // while a fresh network outputs O(1); the output layer is trained as
+  // phi = sigma phi' with targets y / sigma, J / sigma (the DINO loss divided
+  // by sigma^2), sigma the RMS of the reduced states rounded to a power of
+  // two, so the conversions of the stored parameters are exact.
+  double sigma = 1.0;
+  if ((rc = output_scale(D, st, &sigma))) return rc;
+  const float inv_sigma = (float)(1.0 / sigma);
+  float* out_layer = (float*)m->master.p + m->off_w[m->dims.depth];
+  const int64_t n_out = m->off_b[m->dims.depth] + m->dims.r_u - m->off_w[m->dims.depth];
+  saa_launch::scale(out_layer, n_out, inv_sigma, st);
   DevBuf perm_dev;
-  if ((rc = perm_dev.alloc(sizeof(int) * D->N))) return rc;
+  if ((rc = perm_dev.alloc(sizeof(int) * D->N))) {
+    saa_launch::scale(out_layer, n_out, (float)sigma, st);
+    return rc;
+  }
   std::vector<int> perm(D->N);
   const int steps = (int)(D->N / B);
   double* loss = (double*)w.loss.p;
@@ -659,7 +700,7 @@ int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, d
         (float)((cfg->lr_drop_epoch > 0 && ts->epoch >= cfg->lr_drop_epoch) ? cfg->lr_late : cfg->lr);
     for (int s = 0; s < steps; ++s) {
       load_batch(m, D, w, (const int*)perm_dev.p + (int64_t)s * B, B);
-      if ((rc = loss_grad(m, w, B, cfg->dino, true, bf))) break;
+      if ((rc = loss_grad(m, w, B, cfg->dino, true, bf, inv_sigma))) break;
       saa_launch::sum_parts(loss, 2, loss + 2, 1, st);
       ++ts->step;
       const float c1 = 1.0f - std::pow((float)cfg->beta1, (float)ts->step);
@@ -674,10 +715,11 @@ int mrdino_train(mrdino_model* m, mrdino_data* D, const mrdino_train_cfg* cfg, d
       if ((rc = check_hip(hipMemcpyAsync(&tot, loss + 2, sizeof(double), hipMemcpyDeviceToHost, st))) ||
           (rc = check_hip(hipStreamSynchronize(st))))
         break;
-      epoch_loss[ep] = tot / ((double)steps * B);
+      epoch_loss[ep] = sigma * sigma * tot / ((double)steps * B);   // in the data's units
     }
   }
   (void)hipEventRecord(e1, st);
+  saa_launch::scale(out_layer, n_out, (float)sigma, st);   // back to the data's units
   if (!rc) rc = saa_model::pack(m);
   if (!rc) rc = check_hip(hipStreamSynchronize(st));
   float ms = 0.0f;

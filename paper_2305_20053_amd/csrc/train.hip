@@ -104,14 +104,16 @@ __global__ void saa_k_tangent_scale(const float* JA, const float* A, int B, int 
   JH[t] = dgelu_f(A[b * W + f]) * JA[t];
 }
 
-// Residuals and loss: E = Phi + bias - Y (scaled by 2/B into G), partial sums
-// of |E|^2 per block into part[blockIdx.x].
-__global__ void saa_k_residual(const float* P, const float* Y, int64_t n, float scale, float* G, double* part) {
+// Residuals and loss: E = Phi - y_scale Y (scaled by 2/B into G), partial
+// sums of |E|^2 per block into part[blockIdx.x].  y_scale is 1, or the
+// inverse power-of-two output scale of training (exact).
+__global__ void saa_k_residual(const float* P, const float* Y, int64_t n, float scale, float y_scale, float* G,
+                               double* part) {
   __shared__ double red[16];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double e2 = 0.0;
   if (t < n) {
-    const float e = P[t] - Y[t];
+    const float e = P[t] - y_scale * Y[t];
     G[t] = scale * e;
     e2 = (double)e * (double)e;
   }
@@ -213,6 +215,12 @@ __global__ void saa_k_sumsq(const float* x, int64_t n, double* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// x[i] *= f for i < n (f a power of two: exact).
+__global__ void saa_k_scale(float* x, int64_t n, float f) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] *= f;
+}
+
 // Convert float64 -> float32.
 __global__ void saa_k_d2f(const double* x, float* y, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -276,9 +284,10 @@ void tangent0(const float* W0, int ldw, int r_m, int d_z, const float* A, int B,
 void tangent_scale(const float* JA, const float* A, int B, int d_z, int W, float* JH, hipStream_t st) {
   saa_k_tangent_scale<<<nb((int64_t)B * d_z * W), 256, 0, st>>>(JA, A, B, d_z, W, JH);
 }
-int residual(const float* P, const float* Y, int64_t n, float scale, float* G, double* part, hipStream_t st) {
+int residual(const float* P, const float* Y, int64_t n, float scale, float y_scale, float* G, double* part,
+             hipStream_t st) {
   const unsigned blocks = nb(n, 1024);
-  saa_k_residual<<<blocks, 1024, 0, st>>>(P, Y, n, scale, G, part);
+  saa_k_residual<<<blocks, 1024, 0, st>>>(P, Y, n, scale, y_scale, G, part);
   return (int)blocks;
 }
 void layer_back(float* gH, float* gJH, const float* A, const float* JA, int B, int d_z, int W, int dino,
@@ -299,6 +308,9 @@ void sum_parts(const double* part, int n, double* out, int accumulate, hipStream
   saa_k_sum_parts<<<1, 1024, 0, st>>>(part, n, out, accumulate);
 }
 void d2f(const double* x, float* y, int64_t n, hipStream_t st) { saa_k_d2f<<<nb(n), 256, 0, st>>>(x, y, n); }
+void scale(float* x, int64_t n, float f, hipStream_t st) {
+  if (n > 0) saa_k_scale<<<nb(n), 256, 0, st>>>(x, n, f);
+}
 void center_rows(const double* U, const double* ubar, double* out, int64_t cols, int64_t rows, hipStream_t st) {
   saa_k_center_rows<<<nb(rows * cols), 256, 0, st>>>(U, ubar, out, cols, rows);
 }

@@ -34,6 +34,10 @@ SEED_XI_HELDOUT = 2312   # held-out PDE samples for the surrogate error estimate
 SEED_Z_EVAL = (101, 102, 103, 104, 105)
 SEED_XI_3D = 2313        # 3D problem on 48^3, N = 256
 SEED_Z_3D = 2314         # its control (64 sources)
+SEED_XI_TRAIN3D = 2321   # 3D surrogate: training fields, N = 1024
+SEED_Z_TRAIN3D = 2322    # its training controls
+SEED_XI_HELDOUT3D = 2323 # held-out 3D PDE samples for the error estimate
+SEED_XI_LARGE3D = 2324   # 3D surrogate SAA, N = 16384
 
 
 def kl_coefficients(seed: int, n_samples: int, kl_per_dim: int, dim: int = 2) -> np.ndarray:

@@ -27,7 +27,7 @@ def trained(gpu_lib):
     Zv = torch.from_numpy(si.controls(si.SEED_Z_VALID, N_VAL)).cuda()
     vdata = saa.TrainData(vctx, Zv, r_m=R_M, r_u=R_U, basis=data)
     widths = [R_M + ctx.d_z, 256, 256, 256, 256, R_U]
-    init = training.flatten(si.glorot_mlp(2315, widths))
+    init = saa.init_params(si.glorot_mlp(2315, widths), data.output_scale())
     out = {}
     for name, dino in (("dino", 1), ("no", 0)):
         model = saa.Model(R_M, ctx.d_z, R_U, 256, 4)
