@@ -523,6 +523,34 @@ def bench_companions(saa, si, steps, warmup):
     sep = sum(v["ms_per_step"] for v in out.values())
     out["one_launch"] = {"samples_per_s": 768 * steps / wall, "ms_per_step": 1e3 * wall / steps,
                          "separate_ms_per_step_sum": sep}
+    # the 3D workload (48^3, N = 256) and the three 2D instances: one state
+    # launch and one adjoint launch for all 1024 samples
+    p3 = saa.problem_3d()
+    c3 = saa.Context(p3, 256)
+    c3.set_samples(torch.from_numpy(si.kl_coefficients(si.SEED_XI_3D, 256, p3.kl_per_dim, dim=3)).cuda())
+    z3 = si.control(si.SEED_Z_3D, p3.d_z)
+    for k in range(warmup):
+        c3.objective_grad(z3, opt=opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        c3.objective_grad(z3, opt=opt)
+    torch.cuda.synchronize()
+    ms3 = 1e3 * (time.perf_counter() - t0) / steps
+    allc = [c3] + ctxs
+    for k in range(warmup):
+        saa.objective_grad_multi(allc, [z3] + [zs[k % len(zs)]] * 3, opt=opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        saa.objective_grad_multi(allc, [z3] + [zs[k % len(zs)]] * 3, opt=opt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["with_3d_one_launch"] = {"samples_per_s": 1024 * steps / wall, "ms_per_step": 1e3 * wall / steps,
+                                 "separate_ms_per_step_sum": ms3 + sep, "ms_3d_alone": ms3,
+                                 "threads_per_sample_3d_alone": c3.launch3(saa.FP32_DC64)[0],
+                                 "threads_per_sample_mixed": 1024}
+    c3.close()
     for c in ctxs:
         c.close()
     return out

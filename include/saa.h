@@ -564,6 +564,23 @@ int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z
 int saa_risk_reduce_noalloc(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
                             const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream);
 
+/* Autotuning cache.  Launch shapes are chosen by timing the candidates at the
+ * first use for a given size and recorded per device (architecture and
+ * compute-unit count) in a text file of "key value" lines that later
+ * processes reuse: $SAA_TUNE_CACHE ("off" keeps choices in memory only), else
+ * $HOME/.cache/saa_tune.txt.  Keys (the device tag is added internally):
+ *   mlp/w<width>/p<1 BF16 | 2 FP8>/N<N rounded up to a power of two>:
+ *     tile shape of the fused surrogate kernel, 0..2 at width 256 (8 waves x
+ *     64 samples, 8 x 32, 4 x 64), 0..1 at width 512 (8 x 32, 16 x 32); every
+ *     shape gives bitwise the same results;
+ *   state3/p<prec>/n<n>/N<N>, adjoint3/p<prec>/n<n>/N<N>: threads per sample
+ *     of the 3D kernels (256, 512, 1024).
+ * saa_tune_get returns SAA_E_INVALID when the key has no recorded choice;
+ * saa_tune_set records one (it takes effect for contexts without an installed
+ * choice; see saa_ctx_launch3).  Keys may not contain spaces. */
+int saa_tune_get(const char* key, int* value);
+int saa_tune_set(const char* key, int value);
+
 /* Per-sample status of the last saa_objective_grad, saa_per_sample or
  * saa_solve_states call on this context.  Host arrays of N entries each (any
  * may be NULL): flags (bit 1: Newton not converged, 2: an inner PCG hit

@@ -488,6 +488,8 @@ _SIGS.update({
     "saa_sym_eig": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
     "saa_sym_eig_gpu": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "saa_attach_holdout": (ctypes.c_int, [_P, _P]),
+    "saa_tune_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
+    "saa_tune_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),
     "saa_risk_reduce": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(COptions), _P, _P,
                                        _P]),
     "saa_risk_reduce_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(COptions),
@@ -514,6 +516,18 @@ def risk_reduce(q, g, z, opt=None, noalloc=False):
               _P(torch.cuda.current_stream().cuda_stream)))
     o = out.cpu().numpy()
     return float(o[0]), float(o[1]), o[2:].copy(), float(t.item())
+
+
+def tune_get(key: str):
+    """The autotuner's recorded choice for `key` on this device, or None."""
+    v = ctypes.c_int()
+    st = _load().saa_tune_get(key.encode(), ctypes.byref(v))
+    return v.value if st == SAA_OK else None
+
+
+def tune_set(key: str, value: int):
+    """Record a launch-shape choice (see include/saa.h for the keys)."""
+    _check(_load().saa_tune_set(key.encode(), int(value)))
 
 
 def attach_holdout(ctx: Context, holdout):

@@ -9,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsaa.so")
-SOURCES = ["api.cpp", "model.cpp", "train.cpp", "linalg.cpp", "ouu.cpp", "pde.hip", "pde3.hip", "cvar.hip", "mlp.hip", "train.hip",
-           "eig.hip", "gemm.hip"]
+SOURCES = ["api.cpp", "model.cpp", "train.cpp", "linalg.cpp", "ouu.cpp", "pde_all.hip", "cvar.hip", "mlp.hip", "train.hip",
+           "eig.hip", "gemm.hip", "tune.cpp"]
 ARCH = os.environ.get("SAA_OFFLOAD_ARCH", "gfx950")
 
 

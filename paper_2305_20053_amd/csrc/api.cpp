@@ -10,9 +10,11 @@
 #include <algorithm>
 #include <array>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/saa.h"
+#include "tune.h"
 #include "pde.h"
 #include "pde3.h"
 #include "runtime.h"
@@ -62,6 +64,12 @@ void adjoint_multi(const AdjointJob<TW, TS>* jobs, int count, int64_t blocks, si
                    int act, double act_w, hipStream_t st);
 template <typename TS>
 size_t coarse_lds(const PdeGeo& g);
+template <typename TW, typename TS>
+void state_mixed(const State3Job<TW, TS>* j3, int n3, const StateJob<TW, TS>* j2, int n2, int64_t blocks,
+                 size_t lds, const SolveParams& sp, hipStream_t st);
+template <typename TW, typename TS>
+void adjoint_mixed(const Adjoint3Job<TW, TS>* j3, int n3, const AdjointJob<TW, TS>* j2, int n2, int64_t blocks,
+                   size_t lds, const SolveParams& sp, int act, double act_w, hipStream_t st);
 template <typename TS>
 void hierarchy3(const Pde3Geo& g, const double* em, double* k64, const Mg3Bufs<TS>& b, int64_t N, hipStream_t st);
 template <typename TW, typename TS>
@@ -308,7 +316,14 @@ int validate_options(const saa_options* o) {
 // recomputed from the inputs); the chosen size then runs once more so that
 // the outputs come from it.
 template <typename F>
-int launch3(saa_ctx* c, int& choice, F&& launch) {
+int launch3(saa_ctx* c, int& choice, const char* kind, int prec, F&& launch) {
+  // a recorded choice of an earlier process for this size (persisted tuning cache)
+  const std::string key = std::string(kind) + "/p" + std::to_string(prec) + "/n" + std::to_string(c->prob.n) +
+                          "/N" + std::to_string(c->N);
+  if (!choice) {
+    const int v = saa_tune::lookup(key);
+    if (v == 256 || v == 512 || v == 1024) choice = v;
+  }
   if (choice) {
     launch(choice);
     return check_hip(hipGetLastError());
@@ -336,6 +351,7 @@ int launch3(saa_ctx* c, int& choice, F&& launch) {
   if (e1) (void)hipEventDestroy(e1);
   if (rc) return rc;
   choice = pick;
+  saa_tune::store(key, pick);
   if (pick != cand[2]) launch(pick);
   return check_hip(hipGetLastError());
 }
@@ -350,7 +366,7 @@ int run_state3(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const So
     case SAA_FP64:
       if (!c->mg3_64.built && (rc = build_mg3(c, c->mg3_64))) return rc;
       if (!K() || !c->mg3_64.E.p) return SAA_E_INVALID;
-      return launch3(c, bs, [&](int b) {
+      return launch3(c, bs, "state3", prec, [&](int b) {
         saa_launch::state3<double, double>(c->geo3, Z, z_stride, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_64.view(), sp,
                                            (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
                                            b, c->st);
@@ -358,7 +374,7 @@ int run_state3(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const So
     case SAA_FP32_DC64:
       if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
       if (!K() || !c->mg3_32.E.p) return SAA_E_INVALID;
-      return launch3(c, bs, [&](int b) {
+      return launch3(c, bs, "state3", prec, [&](int b) {
         saa_launch::state3<double, float>(c->geo3, Z, z_stride, K(), (double*)c->u.p, (double*)c->f.p, c->mg3_32.view(), sp,
                                           (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
                                           b, c->st);
@@ -366,7 +382,7 @@ int run_state3(saa_ctx* c, int prec, const double* Z, int64_t z_stride, const So
     case SAA_FP32:
       if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) return rc;
       if (!K() || !c->mg3_32.E.p) return SAA_E_INVALID;
-      return launch3(c, bs, [&](int b) {
+      return launch3(c, bs, "state3", prec, [&](int b) {
         saa_launch::state3<float, float>(c->geo3, Z, z_stride, K(), (float*)c->u.p, (float*)c->f.p, c->mg3_32.view(), sp,
                                          (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p, c->N,
                                          b, c->st);
@@ -416,19 +432,19 @@ int run_adjoint3(saa_ctx* c, int prec, const SolveParams& sp, int act, double ac
   const double* K = (const double*)c->k64.p;
   switch (prec) {
     case SAA_FP64:
-      return launch3(c, bs, [&](int b) {
+      return launch3(c, bs, "adjoint3", prec, [&](int b) {
         saa_launch::adjoint3<double, double>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
                                              c->mg3_64.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
                                              (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, b, c->st);
       });
     case SAA_FP32_DC64:
-      return launch3(c, bs, [&](int b) {
+      return launch3(c, bs, "adjoint3", prec, [&](int b) {
         saa_launch::adjoint3<double, float>(c->geo3, K, (double*)c->u.p, (double*)c->f.p, (double*)c->lam.p,
                                             c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
                                             (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, b, c->st);
       });
     case SAA_FP32:
-      return launch3(c, bs, [&](int b) {
+      return launch3(c, bs, "adjoint3", prec, [&](int b) {
         saa_launch::adjoint3<float, float>(c->geo3, K, (float*)c->u.p, (float*)c->f.p, (float*)c->lam.p,
                                            c->mg3_32.view(), sp, (double*)c->q.p, c->tstar(), act, act_w, gout,
                                            (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, b, c->st);
@@ -652,43 +668,74 @@ namespace {
 // Device work of a multi-problem evaluation in precision (TW, TS): the job
 // tables go to ctx[0]'s job buffer (state jobs first, adjoint jobs after).
 template <typename TW, typename TS>
-int multi_work(int count, saa_ctx* const* ctx, const saa_options* opt, MgStore<TS> saa_ctx::*store) {
+int multi_work(int count, saa_ctx* const* ctx, const saa_options* opt, MgStore<TS> saa_ctx::*store,
+               Mg3Store<TS> saa_ctx::*store3) {
   saa_ctx* c0 = ctx[0];
   hipStream_t st = c0->st;
   const SolveParams sp = solve_params(opt, sizeof(TW) == 4);
   StateJob<TW, TS> sj[SAA_MAX_JOBS];
   AdjointJob<TW, TS> aj[SAA_MAX_JOBS];
+  State3Job<TW, TS> sj3[SAA_MAX_JOBS];
+  Adjoint3Job<TW, TS> aj3[SAA_MAX_JOBS];
+  int n2 = 0, n3 = 0;
   int64_t blocks = 0;
   size_t lds = 0;
   bool all_lds = true;
-  for (int k = 0; k < count; ++k) {
-    saa_ctx* c = ctx[k];
-    MgStore<TS>& m = c->*store;
-    const size_t l = saa_launch::coarse_lds<TS>(c->geo);
-    if (!l) all_lds = false;
-    lds = std::max(lds, l);
-    sj[k] = StateJob<TW, TS>{c->geo, (const double*)c->FT.p, (const double*)c->zdev.p, (const double*)c->em.p,
-                              (TW*)c->u.p, (TW*)c->f.p, m.view(), (double*)c->q.p, (int*)c->newton.p,
-                              (int*)c->lin.p, (int*)c->flag.p, c->N, blocks};
-    aj[k] = AdjointJob<TW, TS>{c->geo, (const double*)c->FT.p, (const double*)c->em.p, (const TW*)c->u.p,
-                                (TW*)c->f.p, (TW*)c->lam.p, m.view(), (const double*)c->q.p, c->tstar(),
-                                (double*)c->g.p, (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, blocks};
-    blocks += c->N;
-  }
-  if (!all_lds) lds = 0;
+  // 3D jobs take the first workgroups (the long solves start first), 2D after
+  for (int pass = 0; pass < 2; ++pass)
+    for (int k = 0; k < count; ++k) {
+      saa_ctx* c = ctx[k];
+      if (c->d3 != (pass == 0)) continue;
+      if (c->d3) {
+        Mg3Store<TS>& m = c->*store3;
+        sj3[n3] = State3Job<TW, TS>{c->geo3, (const double*)c->zdev.p, (const double*)c->k64.p, (TW*)c->u.p,
+                                    (TW*)c->f.p, m.view(), (double*)c->q.p, (int*)c->newton.p, (int*)c->lin.p,
+                                    (int*)c->flag.p, c->N, blocks};
+        aj3[n3] = Adjoint3Job<TW, TS>{c->geo3, (const double*)c->k64.p, (const TW*)c->u.p, (TW*)c->f.p,
+                                      (TW*)c->lam.p, m.view(), (const double*)c->q.p, c->tstar(), (double*)c->g.p,
+                                      (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N, blocks};
+        ++n3;
+      } else {
+        MgStore<TS>& m = c->*store;
+        const size_t l = saa_launch::coarse_lds<TS>(c->geo);
+        if (!l) all_lds = false;
+        lds = std::max(lds, l);
+        sj[n2] = StateJob<TW, TS>{c->geo, (const double*)c->FT.p, (const double*)c->zdev.p, (const double*)c->em.p,
+                                  (TW*)c->u.p, (TW*)c->f.p, m.view(), (double*)c->q.p, (int*)c->newton.p,
+                                  (int*)c->lin.p, (int*)c->flag.p, c->N, blocks};
+        aj[n2] = AdjointJob<TW, TS>{c->geo, (const double*)c->FT.p, (const double*)c->em.p, (const TW*)c->u.p,
+                                    (TW*)c->f.p, (TW*)c->lam.p, m.view(), (const double*)c->q.p, c->tstar(),
+                                    (double*)c->g.p, (int*)c->lin_adj.p, (int*)c->flag.p, (int*)c->did.p, c->N,
+                                    blocks};
+        ++n2;
+      }
+      blocks += c->N;
+    }
+  if (!all_lds || n2 == 0) lds = 0;
   const size_t sb = sizeof(sj[0]) * SAA_MAX_JOBS, ab = sizeof(aj[0]) * SAA_MAX_JOBS;
+  const size_t sb3 = sizeof(sj3[0]) * SAA_MAX_JOBS, ab3 = sizeof(aj3[0]) * SAA_MAX_JOBS;
+  char* base = nullptr;
   int rc;
-  if (c0->jobs.bytes < sb + ab && (rc = c0->jobs.alloc(sb + ab))) return rc;
-  if ((rc = check_hip(hipMemcpyAsync(c0->jobs.p, sj, sizeof(sj[0]) * count, hipMemcpyHostToDevice, st))) ||
-      (rc = check_hip(hipMemcpyAsync((char*)c0->jobs.p + sb, aj, sizeof(aj[0]) * count, hipMemcpyHostToDevice, st))))
+  if (c0->jobs.bytes < sb + ab + sb3 + ab3 && (rc = c0->jobs.alloc(sb + ab + sb3 + ab3))) return rc;
+  base = (char*)c0->jobs.p;
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    return bytes ? check_hip(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st)) : SAA_OK;
+  };
+  if ((rc = put(0, sj, sizeof(sj[0]) * n2)) || (rc = put(sb, aj, sizeof(aj[0]) * n2)) ||
+      (rc = put(sb + ab, sj3, sizeof(sj3[0]) * n3)) || (rc = put(sb + ab + sb3, aj3, sizeof(aj3[0]) * n3)))
     return rc;
-  saa_launch::state_multi<TW, TS>((const StateJob<TW, TS>*)c0->jobs.p, count, blocks, lds, sp, st);
+  const auto* dsj = (const StateJob<TW, TS>*)base;
+  const auto* daj = (const AdjointJob<TW, TS>*)(base + sb);
+  const auto* dsj3 = (const State3Job<TW, TS>*)(base + sb + ab);
+  const auto* daj3 = (const Adjoint3Job<TW, TS>*)(base + sb + ab + sb3);
+  if (n3) saa_launch::state_mixed<TW, TS>(dsj3, n3, dsj, n2, blocks, lds, sp, st);
+  else saa_launch::state_multi<TW, TS>(dsj, n2, blocks, lds, sp, st);
   if ((rc = check_hip(hipGetLastError()))) return rc;
   for (int k = 0; k < count; ++k)
     reduce(ctx[k], (double*)ctx[k]->q.p, (double*)ctx[k]->g.p, opt, 1, nullptr, nullptr, nullptr, nullptr, nullptr,
            nullptr);
-  saa_launch::adjoint_multi<TW, TS>((const AdjointJob<TW, TS>*)((char*)c0->jobs.p + sb), count, blocks, lds, sp,
-                                    adjoint_act(opt), adjoint_act_w(opt), st);
+  if (n3) saa_launch::adjoint_mixed<TW, TS>(daj3, n3, daj, n2, blocks, lds, sp, adjoint_act(opt), adjoint_act_w(opt), st);
+  else saa_launch::adjoint_multi<TW, TS>(daj, n2, blocks, lds, sp, adjoint_act(opt), adjoint_act_w(opt), st);
   if ((rc = check_hip(hipGetLastError()))) return rc;
   for (int k = 0; k < count; ++k) {
     saa_ctx* c = ctx[k];
@@ -1294,7 +1341,7 @@ int saa_objective_grad_multi(int count, saa_ctx* const* ctx, const double* const
   if (opt->timing) return SAA_E_INVALID;
   int64_t total = 0;
   for (int k = 0; k < count; ++k) {
-    if (!ctx[k] || !z[k] || !grad_z[k] || ctx[k]->d3 || ctx[k]->N < 1 || ctx[k]->st != ctx[0]->st) return SAA_E_INVALID;
+    if (!ctx[k] || !z[k] || !grad_z[k] || ctx[k]->N < 1 || ctx[k]->st != ctx[0]->st) return SAA_E_INVALID;
     for (int j = 0; j < k; ++j)
       if (ctx[j] == ctx[k]) return SAA_E_INVALID;
     for (int i = 0; i < ctx[k]->dz; ++i)
@@ -1310,7 +1357,13 @@ int saa_objective_grad_multi(int count, saa_ctx* const* ctx, const double* const
       if ((rc = c->u.alloc_zero(tw, c->st)) || (rc = c->f.alloc_zero(tw, c->st)) || (rc = c->lam.alloc_zero(tw, c->st)))
         return rc;
     }
-    if (opt->prec == SAA_FP64) {
+    if (c->d3) {
+      if (opt->prec == SAA_FP64) {
+        if (!c->mg3_64.built && (rc = build_mg3(c, c->mg3_64))) return rc;
+      } else if (!c->mg3_32.built && (rc = build_mg3(c, c->mg3_32))) {
+        return rc;
+      }
+    } else if (opt->prec == SAA_FP64) {
       if (!c->mg64.built && (rc = build_mg(c, c->mg64))) return rc;
     } else if (!c->mg32.built && (rc = build_mg(c, c->mg32))) {
       return rc;
@@ -1319,9 +1372,9 @@ int saa_objective_grad_multi(int count, saa_ctx* const* ctx, const double* const
       return rc;
   }
   switch (opt->prec) {
-    case SAA_FP64: rc = multi_work<double, double>(count, ctx, opt, &saa_ctx::mg64); break;
-    case SAA_FP32_DC64: rc = multi_work<double, float>(count, ctx, opt, &saa_ctx::mg32); break;
-    default: rc = multi_work<float, float>(count, ctx, opt, &saa_ctx::mg32); break;
+    case SAA_FP64: rc = multi_work<double, double>(count, ctx, opt, &saa_ctx::mg64, &saa_ctx::mg3_64); break;
+    case SAA_FP32_DC64: rc = multi_work<double, float>(count, ctx, opt, &saa_ctx::mg32, &saa_ctx::mg3_32); break;
+    default: rc = multi_work<float, float>(count, ctx, opt, &saa_ctx::mg32, &saa_ctx::mg3_32); break;
   }
   if (rc) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1334,6 +1387,20 @@ int saa_objective_grad_multi(int count, saa_ctx* const* ctx, const double* const
     if (r) worst = r;
   }
   return worst;
+}
+
+int saa_tune_get(const char* key, int* value) {
+  if (!key || !value || !*key) return SAA_E_INVALID;
+  const int v = saa_tune::lookup(key);
+  if (v < 0) return SAA_E_INVALID;
+  *value = v;
+  return SAA_OK;
+}
+
+int saa_tune_set(const char* key, int value) {
+  if (!key || !*key || value < 0 || std::strchr(key, ' ') || std::strchr(key, '\n')) return SAA_E_INVALID;
+  saa_tune::store(key, value);
+  return SAA_OK;
 }
 
 int saa_ctx_launch3(saa_ctx* c, int prec, int* bs_state, int* bs_adjoint, int set) {

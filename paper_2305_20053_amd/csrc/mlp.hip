@@ -25,8 +25,11 @@
 // L2, where the whole set (1.1 MB in BF16) stays resident.
 #include <hip/hip_fp16.h>
 
+#include <string>
+
 #include "common.h"
 #include "mlp.h"
+#include "tune.h"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   constexpr int SMAX = OP::scaled ? WAVES * SB * 16 * 4 : 0;
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, c16 = ln & 15;
   _Float16* myg = (_Float16*)((char*)lds + SB * KS * FB + SMAX) + (size_t)wv * DEPTH * MW * SB * 256;
-  float* qs = (float*)lds;                                       // [WAVES][SB][16] (reuses act)
+  float* qs = (float*)lds;                                       // [MT][SB][16] (reuses act)
   const int64_t base = (int64_t)blockIdx.x * (16 * SB);
   f32x4 acc[MW][SB];
   float ax[SB];                          // scale of the current B operands, per sample block (FP8)
@@ -387,9 +390,10 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
   {
     product(operand(net.wp[DEPTH]), MT, KS, false);
-    float qp[SB];                          // this wave's part of |phi + c|^2
-#pragma unroll
-    for (int sb = 0; sb < SB; ++sb) qp[sb] = 0.0f;
+    // |phi + c|^2 as per-tile partial sums (16 features: a lane's 4 rows,
+    // then across the 4 row groups), added in tile order by one wave, so the
+    // result does not depend on how the tiles are split over the waves
+    float qp[MW][SB];
 #pragma unroll
     for (int j = 0; j < MW; ++j) {
       // rows past r_u have zero weights and zero bias + c, so v = 0 there
@@ -398,29 +402,29 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
         const float cs = unscale(DEPTH, sb);
+        qp[j][sb] = 0.0f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float v = OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r];
-          qp[sb] += v * v;
+          qp[j][sb] += v * v;
           acc[j][sb][r] = 2.0f * v;
         }
+        qp[j][sb] += __shfl_xor(qp[j][sb], 16, 64);
+        qp[j][sb] += __shfl_xor(qp[j][sb], 32, 64);
       }
     }
-#pragma unroll
-    for (int sb = 0; sb < SB; ++sb) {
-      qp[sb] += __shfl_xor(qp[sb], 16, 64);
-      qp[sb] += __shfl_xor(qp[sb], 32, 64);
-    }
-    __syncthreads();   // every wave finished reading act: reuse it for the partial sums
+    __syncthreads();   // every wave finished reading act: reuse it for the partial sums [MT][SB][16]
     if (g == 0)
 #pragma unroll
-      for (int sb = 0; sb < SB; ++sb) qs[(wv * SB + sb) * 16 + c16] = qp[sb];
+      for (int j = 0; j < MW; ++j)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) qs[((MW * wv + j) * SB + sb) * 16 + c16] = qp[j][sb];
     __syncthreads();
     if (wv == 0 && ln < 16 * SB) {
       const int sb = ln >> 4;
       const int64_t smp = base + ln;
       float qsum = 0.0f;
-      for (int w = 0; w < WAVES; ++w) qsum += qs[(w * SB + sb) * 16 + c16];
+      for (int t = 0; t < MT; ++t) qsum += qs[(t * SB + sb) * 16 + c16];
       if (smp < N) q_out[smp] = (double)qsum + net.c0;
     }
     publish();
@@ -643,19 +647,59 @@ void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, 
 // width 512 (r_m <= 256, d_z <= 64, 32 samples per workgroup: the fp16
 // GELU' of 4 layers x 512 features x 32 samples fills 128 KB of LDS), depth
 // 4, r_u <= width.  prec: 0 FP32 reference kernel, 1 BF16, 2 FP8.
-struct MlpShape256 {
-  static constexpr int W = 256, KIN = 128, NZT = 2, SB = 4;
-};
-struct MlpShape512 {
-  static constexpr int W = 512, KIN = 256, NZT = 4, SB = 2;
+// Tile shapes of the fused kernel (the autotuner's candidates): waves per
+// workgroup x samples per workgroup.  Every shape computes each output of
+// each product with the same k order, so all give bitwise the same results.
+template <int W_, int KIN_, int NZT_, int WAVES_, int SB_>
+struct MlpShape {
+  static constexpr int W = W_, KIN = KIN_, NZT = NZT_, WAVES = WAVES_, SB = SB_;
 };
 int mlp_kin(int width) { return width == 512 ? 256 : 128; }
 int mlp_nzt(int width) { return width == 512 ? 4 : 2; }
+int mlp_variants(int width) { return width == 512 ? 2 : 3; }
 bool mlp_shape_ok(int width, int depth, int r_m, int d_z, int r_u) {
   if (depth != 4 || r_m < 1 || d_z < 1 || r_u < 1 || r_u > width) return false;
   if (width == 256) return r_m <= 128 && d_z <= 32;
   if (width == 512) return r_m <= 256 && d_z <= 64;
   return false;
+}
+
+template <class OP, class SH>
+static int mlp_launch(const MlpDev& net, const void* xenc, int64_t N, double* q, double* g, hipStream_t st) {
+  const void* fn = (const void*)saa_k_mlp_mfma<SH::W, SH::KIN, 4, SH::NZT, SH::WAVES, SH::SB, OP>;
+  const size_t gelu_lds = (size_t)4 * SH::W * 2 * 16 * SH::SB;   // DEPTH x width x fp16 x samples
+  const size_t lds =
+      (size_t)SH::SB * (SH::W / 32) * OP::FB + (OP::scaled ? SH::WAVES * SH::SB * 16 * 4 : 0) + gelu_lds;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -2;
+    attr_set = true;
+  }
+  const unsigned grid = (unsigned)((N + 16 * SH::SB - 1) / (16 * SH::SB));
+  saa_k_mlp_mfma<SH::W, SH::KIN, 4, SH::NZT, SH::WAVES, SH::SB, OP>
+      <<<grid, SH::WAVES * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
+  return 0;
+}
+
+// Variant v of the width's candidates: width 256: (8 waves, 64 samples),
+// (8, 32), (4, 64); width 512: (8 waves, 32 samples), (16, 32).
+template <class OP>
+static int mlp_variant(int v, const MlpDev& net, const void* xenc, int64_t N, double* q, double* g, hipStream_t st) {
+  if (net.width == 256) {
+    if (v == 1) return mlp_launch<OP, MlpShape<256, 128, 2, 8, 2>>(net, xenc, N, q, g, st);
+    if (v == 2) return mlp_launch<OP, MlpShape<256, 128, 2, 4, 4>>(net, xenc, N, q, g, st);
+    return mlp_launch<OP, MlpShape<256, 128, 2, 8, 4>>(net, xenc, N, q, g, st);
+  }
+  if (v == 1) return mlp_launch<OP, MlpShape<512, 256, 4, 16, 2>>(net, xenc, N, q, g, st);
+  return mlp_launch<OP, MlpShape<512, 256, 4, 8, 2>>(net, xenc, N, q, g, st);
+}
+
+// The autotuner's key of a launch: width, precision and N rounded up to a
+// power of two.
+std::string mlp_tune_key(int width, int prec, int64_t N) {
+  int64_t b = 1;
+  while (b < N) b <<= 1;
+  return "mlp/w" + std::to_string(width) + "/p" + std::to_string(prec) + "/N" + std::to_string(b);
 }
 
 int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* order, const void* xenc,
@@ -664,34 +708,47 @@ int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* 
   (void)n_cu;
   const int W = net.width;
   if (prec == 1 || prec == 2) {
-    constexpr int SW = 8;   // waves per workgroup: two per SIMD
     const int kin = mlp_kin(W), nzt = mlp_nzt(W);
     // wp[0], wp[1..4] and wt[4..1], w0z (the stream of the model's packing)
     const int64_t frags =
         (int64_t)(W / 16) * (kin / 32) + 8 * (int64_t)(W / 16) * (W / 32) + (int64_t)nzt * (W / 32);
     if (net.kin != kin || net.ws_frags != frags) return -1;
     if (prec == 2 && (!net.ws8 || !net.wsc_inv)) return -1;
-    auto run = [&](auto op, auto shape, const void* fn) -> int {
-      typedef decltype(op) OP;
-      typedef decltype(shape) SH;
-      const size_t gelu_lds = (size_t)4 * SH::W * 2 * 16 * SH::SB;   // DEPTH x width x fp16 x samples
-      const size_t lds = (size_t)SH::SB * (SH::W / 32) * OP::FB + (OP::scaled ? SW * SH::SB * 16 * 4 : 0) + gelu_lds;
-      static bool attr_set = false;
-      if (!attr_set) {
-        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -2;
-        attr_set = true;
-      }
-      const unsigned grid = (unsigned)((N + 16 * SH::SB - 1) / (16 * SH::SB));
-      saa_k_mlp_mfma<SH::W, SH::KIN, 4, SH::NZT, SW, SH::SB, OP>
-          <<<grid, SW * 64, lds, st>>>(net, (const __bf16*)xenc, N, q, g);
-      return 0;
+    auto run = [&](int v) {
+      return prec == 1 ? mlp_variant<OpBF16>(v, net, xenc, N, q, g, st)
+                       : mlp_variant<OpFP8>(v, net, xenc, N, q, g, st);
     };
-    if (W == 256) {
-      if (prec == 1) return run(OpBF16{}, MlpShape256{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, 4, OpBF16>);
-      return run(OpFP8{}, MlpShape256{}, (const void*)saa_k_mlp_mfma<256, 128, 4, 2, SW, 4, OpFP8>);
+    const std::string key = mlp_tune_key(W, prec, N);
+    int v = saa_tune::lookup(key);
+    if (v < 0 || v >= mlp_variants(W)) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return run(0);   // no timing under capture: the default shape
+      }
+      // time every candidate once (the launches are idempotent: q and g are
+      // rewritten), keep the fastest, and run it last so its outputs stay
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -2;
+      float best = INFINITY;
+      int pick = 0;
+      for (int c = 0; c < mlp_variants(W); ++c) {
+        int rc = run(c);   // warm (LDS attribute, code object)
+        if (!rc && hipEventRecord(e0, st) == hipSuccess) rc = run(c);
+        float ms = INFINITY;
+        if (!rc && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+          (void)hipEventElapsedTime(&ms, e0, e1);
+        if (!rc && ms < best) {
+          best = ms;
+          pick = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      saa_tune::store(key, pick);
+      v = pick;
     }
-    if (prec == 1) return run(OpBF16{}, MlpShape512{}, (const void*)saa_k_mlp_mfma<512, 256, 4, 4, SW, 2, OpBF16>);
-    return run(OpFP8{}, MlpShape512{}, (const void*)saa_k_mlp_mfma<512, 256, 4, 4, SW, 2, OpFP8>);
+    return run(v);
   }
   const int64_t blocks = (N + 7) / 8;
   if (W == 256) saa_k_mlp_fp32<256, 4><<<(unsigned)blocks, 256, 0, st>>>(net, xi, nkl, order, N, q, g);

@@ -41,3 +41,39 @@ struct Mg3Bufs {
   TS* cp;  // CG direction
   TS* cq;  // A p
 };
+
+// One 3D problem of a mixed-dimension launch (state and adjoint): sample s of
+// the job runs in workgroup first + s.
+template <typename TW, typename TS>
+struct State3Job {
+  Pde3Geo g;
+  const double* Z;    // the problem's control (shared by its samples)
+  const double* k64;  // fine element kappas (FP64), per sample
+  TW* u;
+  TW* f;
+  Mg3Bufs<TS> b;
+  double* q;
+  int* newton;
+  int* lin;
+  int* flag;
+  int64_t N;
+  int64_t first;
+};
+
+template <typename TW, typename TS>
+struct Adjoint3Job {
+  Pde3Geo g;
+  const double* k64;
+  const TW* u;
+  TW* bvec;
+  TW* lam;
+  Mg3Bufs<TS> b;
+  const double* q;
+  const double* tstar;
+  double* gout;
+  int* lin;
+  int* flag;
+  int* did;
+  int64_t N;
+  int64_t first;
+};

@@ -768,16 +768,13 @@ __global__ void __launch_bounds__(HB) saa_k_hierarchy3(Pde3Geo g, const double* 
 // State solve: Newton (precision TW) with inner MG-PCG (precision TS), then
 // q = (u - ut)^T M (u - ut).  One block per sample; all samples share z.
 // ---------------------------------------------------------------------------
+// One sample's 3D state solve (shared by the single-problem kernel and the
+// mixed-dimension launch); red, zs and Gs are LDS scratch of the caller.
 template <typename TW, typename TS, int BSZ>
-__global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, int64_t z_stride,
-                                                   const double* k64_all, TW* u_all, TW* f_all, Mg3Bufs<TS> all,
-                                                   SolveParams sp, double* q_out, int* newton_out, int* lin_out,
-                                                   int* flag_out, int64_t N) {
-  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
-  __shared__ double zs[SAA_MAX_DZ];
-  __shared__ double Gs[4 * 97];
-  const int64_t s = blockIdx.x;
-  if (s >= N) return;
+__device__ __forceinline__ void state3_sample(const Pde3Geo& g, const double* Z, int64_t z_stride,
+                                              const double* k64_all, TW* u_all, TW* f_all, const Mg3Bufs<TS>& all,
+                                              const SolveParams& sp, double* q_out, int* newton_out, int* lin_out,
+                                              int* flag_out, int64_t s, double* red, double* zs, double* Gs) {
   const int n = g.n[0], np = n + 1, np2 = np * np, ns = g.s;
   const double* K = k64_all + s * g.nodes;
   TW* u = u_all + s * g.nodes;
@@ -856,21 +853,34 @@ __global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, 
   }
 }
 
+template <typename TW, typename TS, int BSZ>
+__global__ void __launch_bounds__(BSZ) saa_k_state3(Pde3Geo g, const double* Z, int64_t z_stride,
+                                                   const double* k64_all, TW* u_all, TW* f_all, Mg3Bufs<TS> all,
+                                                   SolveParams sp, double* q_out, int* newton_out, int* lin_out,
+                                                   int* flag_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
+  __shared__ double zs[SAA_MAX_DZ];
+  __shared__ double Gs[4 * 97];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  state3_sample<TW, TS, BSZ>(g, Z, z_stride, k64_all, u_all, f_all, all, sp, q_out, newton_out, lin_out, flag_out, s,
+                             red, zs, Gs);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint: A(u) lambda = 2 (M (u - ut))_I, g = F^T lambda (Sec. 2.3) for the
 // samples whose risk weight can be non-zero (the activity rules of the 2D
 // kernel: act 0 CVaR tail q > t, 1 all, 2 0 < q - t < act_w, 3 buffered
 // exceedance); the others get a zero g row.
 // ---------------------------------------------------------------------------
+// One sample's 3D adjoint (shared by the single-problem kernel and the
+// mixed-dimension launch); red and Gs are LDS scratch of the caller.
 template <typename TW, typename TS, int BSZ>
-__global__ void __launch_bounds__(BSZ) saa_k_adjoint3(Pde3Geo g, const double* k64_all, const TW* u_all, TW* b_all,
-                                                     TW* lam_all, Mg3Bufs<TS> all, SolveParams sp, const double* q,
-                                                     const double* tstar, int act, double act_w, double* g_out,
-                                                     int* lin_out, int* flag_out, int* did_out, int64_t N) {
-  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
-  __shared__ double Gs[4 * 97];
-  const int64_t s = blockIdx.x;
-  if (s >= N) return;
+__device__ __forceinline__ void adjoint3_sample(const Pde3Geo& g, const double* k64_all, const TW* u_all, TW* b_all,
+                                                TW* lam_all, const Mg3Bufs<TS>& all, const SolveParams& sp,
+                                                const double* q, const double* tstar, int act, double act_w,
+                                                double* g_out, int* lin_out, int* flag_out, int* did_out, int64_t s,
+                                                double* red, double* Gs) {
   const int n = g.n[0], np = n + 1, np2 = np * np, ns = g.s;
   const double xq = q[s] - tstar[0];
   const bool active = act == 1 || (act == 3 ? (tstar[0] > 0.0 && tstar[0] < INFINITY &&
@@ -926,6 +936,19 @@ __global__ void __launch_bounds__(BSZ) saa_k_adjoint3(Pde3Geo g, const double* k
     did_out[s] = 1;
     if (!ok) flag_out[s] |= SAA_FLAG_DC;
   }
+}
+
+template <typename TW, typename TS, int BSZ>
+__global__ void __launch_bounds__(BSZ) saa_k_adjoint3(Pde3Geo g, const double* k64_all, const TW* u_all, TW* b_all,
+                                                     TW* lam_all, Mg3Bufs<TS> all, SolveParams sp, const double* q,
+                                                     const double* tstar, int act, double act_w, double* g_out,
+                                                     int* lin_out, int* flag_out, int* did_out, int64_t N) {
+  __shared__ double red[SAA_MAX_DZ * (BSZ / SAA_WAVE)];
+  __shared__ double Gs[4 * 97];
+  const int64_t s = blockIdx.x;
+  if (s >= N) return;
+  adjoint3_sample<TW, TS, BSZ>(g, k64_all, u_all, b_all, lam_all, all, sp, q, tstar, act, act_w, g_out, lin_out,
+                               flag_out, did_out, s, red, Gs);
 }
 
 // ---------------------------------------------------------------------------

@@ -186,10 +186,19 @@ def test_full_size_precisions_and_taylor(full3):
     assert errs[1] <= 0.35 * errs[0] or errs[1] <= 1e-10 * abs(g64 @ d)
 
 
-def test_3d_rejects_surrogate_and_training_calls(small3):
+def test_3d_training_calls_validate(small3):
+    """3D contexts build training data with forward control Jacobians only
+    (the adjoint mode is refused), and a surrogate must match the context's
+    d_Z and KL size."""
     prob, xi, z, ref, ctx = small3
+    Z = torch.zeros((len(xi), prob.d_z), dtype=torch.float64, device="cuda")
     with pytest.raises(saa.SaaError):
-        ctx.solve_states(torch.zeros((len(xi), prob.d_z), dtype=torch.float64, device="cuda"))
+        saa.TrainData(ctx, Z, r_m=4, r_u=2, n_pod=len(xi), opt=saa.options(jac_mode=saa.JAC_ADJOINT))
+    bad = saa.Model(4, prob.d_z + 1 if prob.d_z < 64 else 1, 8, 512, 4)
+    with pytest.raises(saa.SaaError) as e:
+        ctx.objective_grad(z, form=saa.FORM_MRDINO, model=bad, opt=saa.options(prec=saa.BF16))
+    assert e.value.status == saa.SAA_E_MODEL
+    bad.close()
 
 
 @pytest.mark.parametrize("kind", [saa.RISK_MEAN, saa.RISK_MEAN_VAR, saa.RISK_POF, saa.RISK_BPOE])
@@ -300,3 +309,39 @@ def test_largest_3d_grid_converges_at_second_order(gpu_lib):
     print(f"ratios n=12,24,48: {r1}  n=24,48,96: {r2}", flush=True)
     assert np.all((r2 >= 0.23) & (r2 <= 0.28)), r2
     assert np.all(np.abs(r2 - 0.25) <= 0.5 * np.abs(r1 - 0.25) + 2e-3), (r1, r2)
+
+
+def test_mixed_dimension_launch_matches_separate_calls(gpu_lib):
+    """A 3D problem and two 2D problems in one state launch and one adjoint
+    launch (the 3D workload with its 2D companions, here at small sizes):
+    J, grad and solver counts of each equal separate evaluations bit for bit
+    (the 3D context's separate call pinned to the mixed launch's 1024
+    threads per sample), in FP64, FP32-DC64 and FP32; the 3D member also
+    against the oracle."""
+    p3 = problem3(8, s=2, K1=3, kl_amp=20.0, target=saa.TARGET_SIN)
+    xi3 = si.kl_coefficients(2461, 7, 3, dim=3)
+    c3 = saa.Context(p3, 7)
+    c3.set_samples(torch.from_numpy(xi3).cuda())
+    ctxs, zs = [c3], [si.control(2462, p3.d_z)]
+    for k, (n, N) in enumerate(((16, 5), (24, 9))):
+        prob = saa.Problem(n=n, kl_per_dim=8, target=saa.TARGET_SIN)
+        c = saa.Context(prob, N)
+        c.set_samples(torch.from_numpy(si.kl_coefficients(2463 + k, N, prob.kl_per_dim)).cuda())
+        ctxs.append(c)
+        zs.append(si.control(2465 + k))
+    print("case mixed 3D + 2D launch", flush=True)
+    for prec in (saa.FP64, saa.FP32_DC64, saa.FP32):
+        c3.launch3(prec, state=1024, adjoint=1024)
+        opt = saa.options(prec=prec)
+        multi = saa.objective_grad_multi(ctxs, zs, opt=opt)
+        for c, z, (J, g, rep) in zip(ctxs, zs, multi):
+            J1, g1, rep1 = c.objective_grad(z, opt=opt)
+            assert J == J1 and np.array_equal(g, g1), (prec, J, J1)
+            assert rep["newton_total"] == rep1["newton_total"] and rep["lin_total"] == rep1["lin_total"]
+            assert rep["n_adjoints"] == rep1["n_adjoints"] and rep["t_star"] == rep1["t_star"]
+        if prec == saa.FP64:
+            ref = osaa.objective_grad(_oprob(p3), xi3, zs[0])
+            J, g, _ = multi[0]
+            assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) and _rel(g, ref["grad"]) <= 1e-9
+    for c in ctxs:
+        c.close()
