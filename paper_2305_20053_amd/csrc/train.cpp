@@ -492,7 +492,9 @@ int mrdino_data_create(saa_ctx* c, const double* Z_dev, int r_m, int r_u, int n_
   if (adj) {   // J_r = (A^{-1} M Phi)^T F, from the states still held by the context
     if ((rc = saa_rt::adjoint_jacobians(c, opt, (const double*)MPhiT.p, r_u, (double*)JYd.p))) return fail(rc);
   } else if (c->d3) {   // du/dz of a chunk of samples, then J_r = (M Phi)^T du/dz for the chunk
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)2 << 30) / (8 * dz * du)));
+    // one workgroup per sample: chunks of at least a CU round (256 samples)
+    // keep every CU busy; 16 GiB of du/dz per chunk (about 320 samples at 48^3)
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, ((int64_t)16 << 30) / (8 * dz * du)));
     if ((rc = dUdz.alloc(sizeof(double) * chunk * dz * du))) return fail(rc);
     for (int64_t s0 = 0; s0 < N && !rc; s0 += chunk) {
       const int64_t ns = std::min<int64_t>(chunk, N - s0);
