@@ -202,16 +202,15 @@ __global__ void saa_k_add_pad(float* dst, const float* a, const float* b, int n,
 }
 
 // b0eff[f] = b_0[f] + sum_k W_0[f][r_m + k] z_k  (the control enters only
-// through the first layer and is shared by all samples).
-__global__ void saa_k_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m,
-                            int d_z) {
+// through the first layer and is shared by all samples).  W0zT is the packed
+// transposed copy of those columns (d_z x width), so consecutive threads
+// read consecutive features.
+__global__ void saa_k_b0eff(float* b0eff, const float* W0zT, const float* b0, const double* z, int width, int d_z) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= width) return;
-  const float* w = W0 + (int64_t)f * (r_m + d_z) + r_m;
   float acc = b0[f];
-#pragma unroll
-  for (int k = 0; k < 64; ++k)   // d_z <= 64: every load issued at once
-    if (k < d_z) acc += w[k] * (float)z[k];
+#pragma unroll 8
+  for (int k = 0; k < d_z; ++k) acc += W0zT[(int64_t)k * width + f] * (float)z[k];
   b0eff[f] = acc;
 }
 
@@ -637,9 +636,9 @@ void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int kin, i
 void mlp_add_pad(float* dst, const float* a, const float* b, int n, int w, hipStream_t st) {
   saa_k_add_pad<<<nblk(w, 256), 256, 0, st>>>(dst, a, b, n, w);
 }
-void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
+void mlp_b0eff(float* b0eff, const float* W0zT, const float* b0, const double* z, int width, int d_z,
                hipStream_t st) {
-  saa_k_b0eff<<<nblk(width, 256), 256, 0, st>>>(b0eff, W0, b0, z, width, r_m, d_z);
+  saa_k_b0eff<<<nblk(width, 64), 64, 0, st>>>(b0eff, W0zT, b0, z, width, d_z);
 }
 
 // Network shapes of the fused kernel (and of the FP32 reference kernel):

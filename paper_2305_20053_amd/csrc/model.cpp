@@ -18,7 +18,7 @@ void mlp_pack_bwd(void* dst, const float* src, int rows, int cols, int src_rows,
                   int col0, hipStream_t st);
 void mlp_transpose(float* dst, const float* src, int rows, int cols, int src_ld, hipStream_t st);
 void mlp_pad(float* dst, const float* src, int n_src, int n_dst, hipStream_t st);
-void mlp_b0eff(float* b0eff, const float* W0, const float* b0, const double* z, int width, int r_m, int d_z,
+void mlp_b0eff(float* b0eff, const float* W0zT, const float* b0, const double* z, int width, int d_z,
                hipStream_t st);
 int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* order, const void* xenc,
              int64_t N, double* q, double* g, int n_cu, hipStream_t st);
@@ -95,6 +95,7 @@ int pack(mrdino_model* m) {
     if (L == 0) {
       saa_launch::mlp_pack_fwd(wsb + 1024 * m->f_wp[0], w, W, m->kin, W, d.r_m, in, 1, st);
       saa_launch::mlp_transpose((float*)m->wtn[0].p, w, W, d.r_m, in, st);   // r_m x W
+      saa_launch::mlp_transpose((float*)m->w0zT.p, w + d.r_m, W, d.d_z, in, st);   // d_z x W (control columns)
     } else {
       saa_launch::mlp_pack_fwd(wsb + 1024 * m->f_wp[L], w, W, W, rows, W, W, 0, st);
       saa_launch::mlp_pack_bwd(wsb + 1024 * m->f_wt[L], w, W, W, rows, W, W, 0, st);
@@ -177,6 +178,7 @@ int mrdino_create(const mrdino_dims* d, void* hip_stream, mrdino_model** out) {
     if (!rc) rc = m->wtn[L].alloc_zero(sizeof(float) * (size_t)W * (L == 0 ? d->r_m : W), m->st);
   }
   if (!rc) rc = m->b0eff.alloc_zero(sizeof(float) * W, m->st);
+  if (!rc) rc = m->w0zT.alloc_zero(sizeof(float) * (size_t)d->d_z * W, m->st);
   if (!rc) rc = m->c.alloc_zero(sizeof(float) * W, m->st);
   if (!rc) rc = m->bc.alloc_zero(sizeof(float) * W, m->st);
   if (!rc) rc = m->zdev.alloc_zero(sizeof(double) * 64, m->st);
@@ -374,8 +376,8 @@ int saa_model_eval(mrdino_model* m, saa_ctx* c, const double* z_dev, int prec, d
   const mrdino_dims& d = m->dims;
   if (d.d_z != c->dz || d.r_m > c->n_kl) return SAA_E_MODEL;
   if (prec != SAA_FP32 && prec != SAA_BF16 && prec != SAA_FP8) return SAA_E_INVALID;
-  saa_launch::mlp_b0eff((float*)m->b0eff.p, (const float*)m->master.p + m->off_w[0],
-                        (const float*)m->master.p + m->off_b[0], z_dev, d.width, d.r_m, d.d_z, c->st);
+  saa_launch::mlp_b0eff((float*)m->b0eff.p, (const float*)m->w0zT.p, (const float*)m->master.p + m->off_b[0], z_dev,
+                        d.width, d.d_z, c->st);
   const MlpDev v = view(m);
   if (prec != SAA_FP32 && c->enc_rm != enc_key(d.r_m, m->kin)) {   // encode the installed samples once
     const size_t bytes = sizeof(uint16_t) * (size_t)m->kin * (size_t)c->N_max;

@@ -22,6 +22,7 @@ struct mrdino_model {
   saa_rt::DevBuf bias[MLP_MAX_DEPTH + 1];   // FP32 biases padded to width
   saa_rt::DevBuf wtn[MLP_MAX_DEPTH + 1];    // FP32 transposed weights (reference kernel)
   saa_rt::DevBuf b0eff, c, zdev;
+  saa_rt::DevBuf w0zT;                      // control columns of W_0, transposed (d_z x width), FP32
   saa_rt::DevBuf bc;                        // output bias + c (padded), for the BF16 kernel
   double c0 = 0.0;
   std::vector<double> c_host;               // c as given to mrdino_set_qoi (zeros until set)
