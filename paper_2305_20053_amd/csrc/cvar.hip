@@ -37,7 +37,9 @@
 // derivative enters) are per-workgroup partial sums over contiguous chunks,
 // reduced in chunk order by one workgroup.  Every sum has a fixed order, so
 // results are bitwise reproducible.
+#include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <mutex>
 
 #include "../../include/saa.h"
@@ -58,14 +60,15 @@ constexpr int TILE = 4 * RBS;     // samples per compaction tile
 constexpr int PSTRIDE = 2 + SAA_MAX_DZ;
 constexpr int WAVE_NEWTON = 256;  // active sets up to this size are solved by one wave
 constexpr int RPASSES = 4;        // refinement passes when the active set overflows
-constexpr double FIX_SCALE = 274877906944.0;   // 2^38: fixed-point scale of the refinement sums
+constexpr int RFB = 1024;         // threads of the refinement passes (16 waves share a chunk)
+constexpr int SLOTS = 8;          // copies of each atomic counter (workgroup b adds to copy b % SLOTS)
 
 // Workspace of one reduction: per-workgroup min / max and partial sums, the
 // active-set segments, the refinement sums, the probe histograms and the
-// active-set counters (about 4.3 MB, independent of N).
+// active-set counters (about 4.4 MB, independent of N).
 constexpr size_t kCvarWorkBytes =
     sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
-    sizeof(unsigned long long) * RPASSES * NP + sizeof(int) * ((size_t)PASSES * 2 * NB + 2 * GMAX + 2);
+    sizeof(unsigned long long) * RPASSES * SLOTS * NP + sizeof(int) * ((size_t)PASSES * SLOTS * 2 * NB + 2 * GMAX + SLOTS);
 constexpr int kMaxDevices = 64;
 static_assert(NP == SAA_WAVE, "one probe per lane");
 static_assert(GMAX % SAA_WAVE == 0, "partial rows per lane in the final reduction");
@@ -74,13 +77,16 @@ static_assert(SAA_MAX_DZ <= SAA_WAVE, "one gradient component per lane");
 // Device workspace, carved from one allocation of cvar_work_bytes().
 struct CvarWork {
   double* mm;     // [GMAX][2] partial min / max of q
-  double* part;   // [GMAX][PSTRIDE] partial sums of the value / gradient
+  double* part;   // [PSTRIDE][GMAX] partial sums of the value / gradient (column c of workgroup b at c GMAX + b)
   double* aval;   // [GMAX][SEG] active q values per workgroup, in index order
-  int* hist;      // [PASSES][2][NB] probe histograms
+  // The counters that every workgroup adds to are kept in SLOTS copies, so
+  // that fewer atomics meet on one address; readers add the copies up.
+  int* hist;      // [PASSES][SLOTS][2][NB] probe histograms
   int* nact;      // [GMAX] active samples per workgroup
   int* nabove;    // [GMAX] samples at or above hi + eps per workgroup
-  int* act_total; // [1] active samples over all workgroups
-  unsigned long long* fix;   // [RPASSES][NP] Phi at the refinement probes, fixed point 2^38
+  int* act_total; // [SLOTS] active samples over all workgroups
+  unsigned long long* fix;   // [RPASSES][SLOTS][NP] Phi at the refinement probes, fixed point
+  double fscale;  // the fixed-point scale: 2^38, lowered for N >= 2^24 so N fscale < 2^62
 };
 
 // s_eps and its derivatives; ie = 1 / e (one division per kernel, not per sample)
@@ -100,6 +106,74 @@ __device__ __forceinline__ double sp_d2(double x, double e, double ie) {
   if (x <= 0.0 || x >= e) return 0.0;
   const double r = x * ie;
   return 6.0 * r * (1.0 - r) * ie;         // 6x/e^2 - 6x^2/e^3
+}
+
+// Wave-wide max / min / integer sums and suffix sums from DPP row moves and
+// lane reads.  They run at the head of every pass, on the serial path of the
+// reduction, where shuffles routed through the LDS unit cost several times
+// more.  Max, min and integer sums are exact, so the results do not depend on
+// the combining order.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);   // lanes without a source read 0
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  return __hiloint2double(dpp_mov<CTRL>(__double2hiint(v)), dpp_mov<CTRL>(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+constexpr int DPP_XOR1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+constexpr int DPP_SHR = 0x110;        // + n: row_shr:n
+
+template <bool MAX>
+__device__ __forceinline__ double wave_ext(double v) {
+  auto op = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+  v = op(v, dpp_mov<DPP_XOR1>(v));          // quads
+  v = op(v, dpp_mov<DPP_XOR2>(v));
+  v = op(v, dpp_mov<DPP_HALF_MIRROR>(v));   // rows of 8, then 16
+  v = op(v, dpp_mov<DPP_MIRROR>(v));
+  return op(op(lane_read(v, 0), lane_read(v, 16)), op(lane_read(v, 32), lane_read(v, 48)));
+}
+__device__ __forceinline__ double fast_max(double v) { return wave_ext<true>(v); }
+// Sum over the lanes in one fixed tree order (quads, half rows, rows, then
+// ((row 0 + row 1) + (row 2 + row 3))); every lane gets the same value.
+__device__ __forceinline__ double fast_sum(double v) {
+  v += dpp_mov<DPP_XOR1>(v);
+  v += dpp_mov<DPP_XOR2>(v);
+  v += dpp_mov<DPP_HALF_MIRROR>(v);
+  v += dpp_mov<DPP_MIRROR>(v);
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+__device__ __forceinline__ double fast_min(double v) { return wave_ext<false>(v); }
+
+// Inclusive prefix sum over the lanes; *total gets the sum of all 64.
+__device__ __forceinline__ int wave_prefix(int v, int* total) {
+  v += dpp_mov<DPP_SHR + 1>(v);   // inclusive scans of each row of 16
+  v += dpp_mov<DPP_SHR + 2>(v);
+  v += dpp_mov<DPP_SHR + 4>(v);
+  v += dpp_mov<DPP_SHR + 8>(v);
+  const int t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31);
+  const int t2 = __builtin_amdgcn_readlane(v, 47), t3 = __builtin_amdgcn_readlane(v, 63);
+  const int row = (threadIdx.x & (SAA_WAVE - 1)) >> 4;
+  *total = t0 + t1 + t2 + t3;
+  return v + (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
+}
+__device__ __forceinline__ int fast_sum(int v) {
+  int t;
+  (void)wave_prefix(v, &t);
+  return t;
+}
+// sum_{k >= lane} v_k
+__device__ __forceinline__ int wave_suffix(int v) {
+  int t;
+  const int p = wave_prefix(v, &t);
+  return t - p + v;
 }
 
 // Probe j of a pass over [lo, hi]; non-decreasing in j for any rounding.
@@ -132,8 +206,15 @@ __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double ep
   int hc1[PASSES], hc2[PASSES];
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
-    hc1[p] = p < passes ? w.hist[p * 2 * NB + lane + 1] : 0;
-    hc2[p] = p < passes ? w.hist[p * 2 * NB + NB + lane + 1] : 0;
+    hc1[p] = 0;
+    hc2[p] = 0;
+    if (p < passes) {
+#pragma unroll
+      for (int k = 0; k < SLOTS; ++k) {
+        hc1[p] += w.hist[(p * SLOTS + k) * 2 * NB + lane + 1];
+        hc2[p] += w.hist[(p * SLOTS + k) * 2 * NB + NB + lane + 1];
+      }
+    }
   }
 #pragma unroll
   for (int k = 0; k < GMAX / SAA_WAVE; ++k) {
@@ -144,8 +225,8 @@ __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double ep
     }
   }
   Bracket br;
-  br.lo = wave_min(mn) - eps;
-  br.hi = wave_max(mx);
+  br.lo = fast_min(mn) - eps;
+  br.hi = fast_max(mx);
   br.live = target < N;
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
@@ -153,20 +234,11 @@ __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double ep
     br.live = br.live && (br.hi - br.lo > 4.0 * eps);
     if (!br.live) break;
     // suffix sums over the bins above probe `lane`: #{q > probe}, #{q > probe + eps}
-    int c1 = hc1[p], c2 = hc2[p];
-#pragma unroll
-    for (int off = 1; off < SAA_WAVE; off <<= 1) {
-      const int y1 = __shfl_down(c1, off, SAA_WAVE);
-      const int y2 = __shfl_down(c2, off, SAA_WAVE);
-      if (lane + off < SAA_WAVE) {
-        c1 += y1;
-        c2 += y2;
-      }
-    }
+    const int c1 = wave_suffix(hc1[p]), c2 = wave_suffix(hc2[p]);
     const double step = (br.hi - br.lo) / (NP + 1);
     const double pj = probe(br.lo, step, lane);
-    const double nlo = wave_max((double)c2 > target ? pj : br.lo);
-    const double nhi = wave_min((double)c1 <= target ? pj : br.hi);
+    const double nlo = fast_max((double)c2 > target ? pj : br.lo);
+    const double nhi = fast_min((double)c1 <= target ? pj : br.hi);
     if (!(nhi - nlo < br.hi - br.lo)) {
       br.live = false;
       break;
@@ -175,6 +247,14 @@ __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double ep
     br.hi = nhi;
   }
   return br;
+}
+
+// Active samples over all workgroups (above CAP: overflow).
+__device__ __forceinline__ int active_total(const CvarWork& w) {
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < SLOTS; ++k) t += w.act_total[k];
+  return t;
 }
 
 __device__ __forceinline__ void chunk_of(int64_t N, int G, int64_t& i0, int64_t& i1) {
@@ -243,7 +323,8 @@ __device__ int block_scan(int v, int* excl, int* sh) {
 
 }  // namespace
 
-// 1. partial min / max per workgroup; workgroup 0 clears the histograms.
+// 1. partial min / max per workgroup; the workgroups together clear the
+// counters of the later passes.
 __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_t N, CvarWork w, int G) {
   __shared__ double red[RBS / SAA_WAVE];
   int64_t i0, i1;
@@ -259,11 +340,10 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_
     w.mm[2 * blockIdx.x] = mn;
     w.mm[2 * blockIdx.x + 1] = mx;
   }
-  if (blockIdx.x == 0) {
-    for (int k = threadIdx.x; k < PASSES * 2 * NB; k += RBS) w.hist[k] = 0;
-    for (int k = threadIdx.x; k < RPASSES * NP; k += RBS) w.fix[k] = 0;
-    if (threadIdx.x == 0) w.act_total[0] = 0;
-  }
+  const int gt = blockIdx.x * RBS + threadIdx.x, gs = G * RBS;
+  for (int k = gt; k < PASSES * SLOTS * 2 * NB; k += gs) w.hist[k] = 0;
+  for (int k = gt; k < RPASSES * SLOTS * NP; k += gs) w.fix[k] = 0;
+  for (int k = gt; k < SLOTS; k += gs) w.act_total[k] = 0;
 }
 
 // 2. bracketing pass p: probe histograms of this workgroup's chunk.
@@ -292,7 +372,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_probe(const double* q, int64_t
     else atomicAdd(&hl[NB + b2], 1);
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) edge[k] = wave_sum(edge[k]);
+  for (int k = 0; k < 4; ++k) edge[k] = fast_sum(edge[k]);
   if ((threadIdx.x & (SAA_WAVE - 1)) == 0) {
     atomicAdd(&hl[0], edge[0]);
     atomicAdd(&hl[NP], edge[1]);
@@ -301,7 +381,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_probe(const double* q, int64_t
   }
   __syncthreads();
   for (int k = threadIdx.x; k < 2 * NB; k += RBS)
-    if (hl[k]) atomicAdd(&w.hist[p * 2 * NB + k], hl[k]);
+    if (hl[k]) atomicAdd(&w.hist[(p * SLOTS + blockIdx.x % SLOTS) * 2 * NB + k], hl[k]);
 }
 
 // 3. gather this workgroup's active samples (lo < q < hi + eps) in index
@@ -340,7 +420,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_compact(const double* q, int64
     }
     base += tot;
   }
-  above = wave_sum(above);
+  above = fast_sum(above);
   if ((threadIdx.x & (SAA_WAVE - 1)) == 0) sh[threadIdx.x / SAA_WAVE] = above;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -349,13 +429,13 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_compact(const double* q, int64
     w.nact[blockIdx.x] = base;
     w.nabove[blockIdx.x] = a;
     // a segment overflow counts as an overflow of the whole active set
-    if (base > 0) atomicAdd(w.act_total, base > SEG ? base + CAP + 1 : base);
+    if (base > 0) atomicAdd(&w.act_total[blockIdx.x % SLOTS], base > SEG ? base + CAP + 1 : base);
   }
 }
 
 // Bracket after the count passes and `passes` refinement passes.  Pass r
 // evaluated Phi exactly at the 64 points lo + j (hi - lo) / 63 (sums over all
-// workgroups in 2^-38 fixed point, so their order does not matter); the new
+// workgroups in fixed point, so their order does not matter); the new
 // bracket is the pair of neighbouring points where Phi crosses the target.
 // plo, phi hold Phi at the ends once a refinement pass has run (else -1).
 // Every wave gets the same result.
@@ -366,17 +446,22 @@ __device__ Bracket bracket_refined(const CvarWork& w, int G, int passes, double 
   plo = phi = -1.0;
   unsigned long long f[RPASSES];
 #pragma unroll
-  for (int r = 0; r < RPASSES; ++r) f[r] = r < passes ? w.fix[r * NP + lane] : 0ull;
+  for (int r = 0; r < RPASSES; ++r) {
+    f[r] = 0ull;
+    if (r < passes)
+#pragma unroll
+      for (int k = 0; k < SLOTS; ++k) f[r] += w.fix[(r * SLOTS + k) * NP + lane];
+  }
 #pragma unroll
   for (int r = 0; r < RPASSES; ++r) {
     if (r >= passes || !(br.hi - br.lo > 8.0 * DBL_EPSILON * fmax(fabs(br.lo), fabs(br.hi)))) break;
     const double step = (br.hi - br.lo) / (NP - 1);
-    const double pv = (double)f[r] * (1.0 / FIX_SCALE);
-    const int jl = (int)wave_max((double)((lane < NP - 1 && pv > target) ? lane : 0));
+    const double pv = (double)f[r] / w.fscale;
+    const int jl = (int)fast_max((double)((lane < NP - 1 && pv > target) ? lane : 0));
     const double tl = br.lo + (double)jl * step;
     const double th = jl + 1 == NP - 1 ? br.hi : br.lo + (double)(jl + 1) * step;
-    plo = __shfl(pv, jl, SAA_WAVE);
-    phi = __shfl(pv, jl + 1, SAA_WAVE);
+    plo = lane_read(pv, jl);
+    phi = lane_read(pv, jl + 1);
     br.lo = tl;
     br.hi = th;
   }
@@ -385,12 +470,14 @@ __device__ Bracket bracket_refined(const CvarWork& w, int G, int passes, double 
 
 // 3b. refinement pass r (only when the active set overflowed its capacity):
 // Phi at 64 points of the current bracket, lane j evaluating point j over the
-// window samples of this workgroup's chunk.
-__global__ void __launch_bounds__(RBS) saa_k_cvar_refine(const double* q, int64_t N, CvarWork w, int G, int r,
+// window samples of this workgroup's chunk.  Wave k of the 16 takes the
+// tile's samples k, k + 16, ..., four at a time (independent chains).
+__global__ void __launch_bounds__(RFB) saa_k_cvar_refine(const double* q, int64_t N, CvarWork w, int G, int r,
                                                          double eps, double target) {
-  __shared__ double part[RBS / SAA_WAVE][NP];
+  constexpr int NWV = RFB / SAA_WAVE;
+  __shared__ double part[NWV][NP];
   __shared__ double qt[TILE];
-  if (!(target < (double)N) || w.act_total[0] <= CAP) return;
+  if (!(target < (double)N) || active_total(w) <= CAP) return;
   double plo, phi;
   const Bracket br = bracket_refined(w, G, r, eps, target, (double)N, plo, phi);
   if (!(br.hi - br.lo > 8.0 * DBL_EPSILON * fmax(fabs(br.lo), fabs(br.hi)))) return;
@@ -398,28 +485,32 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_refine(const double* q, int64_
   const double ie = 1.0 / eps;
   const double step = (br.hi - br.lo) / (NP - 1);
   const double tj = lane == NP - 1 ? br.hi : br.lo + (double)lane * step;
-  const double top = br.hi + eps;
+  const double top = br.hi + eps, lo = br.lo;
+  auto term = [&](double x) { return x >= top ? 1.0 : (x > lo ? sp_d1(x - tj, eps, ie) : 0.0); };
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
-  double acc = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t t0 = i0; t0 < i1; t0 += TILE) {
     const int nt = (int)(i1 - t0 < TILE ? i1 - t0 : TILE);
-    for (int i = threadIdx.x; i < nt; i += RBS) qt[i] = q[t0 + i];
+    for (int i = threadIdx.x; i < nt; i += RFB) qt[i] = q[t0 + i];
     __syncthreads();
-    // wave wid takes every 4th sample of the tile; all lanes see the same sample
-    for (int i = wid; i < nt; i += RBS / SAA_WAVE) {
-      const double x = qt[i];
-      if (x >= top) acc += 1.0;
-      else if (x > br.lo) acc += sp_d1(x - tj, eps, ie);
+    int i = wid;
+    for (; i + 3 * NWV < nt; i += 4 * NWV) {
+      const double x0 = qt[i], x1 = qt[i + NWV], x2 = qt[i + 2 * NWV], x3 = qt[i + 3 * NWV];
+      acc[0] += term(x0);
+      acc[1] += term(x1);
+      acc[2] += term(x2);
+      acc[3] += term(x3);
     }
+    for (; i < nt; i += NWV) acc[0] += term(qt[i]);
     __syncthreads();
   }
-  part[wid][lane] = acc;
+  part[wid][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (wid == 0) {
     double v = 0.0;
-    for (int k = 0; k < RBS / SAA_WAVE; ++k) v += part[k][lane];
-    if (v > 0.0) atomicAdd(&w.fix[r * NP + lane], (unsigned long long)llrint(v * FIX_SCALE));
+    for (int k = 0; k < NWV; ++k) v += part[k][lane];
+    if (v > 0.0) atomicAdd(&w.fix[(r * SLOTS + blockIdx.x % SLOTS) * NP + lane], (unsigned long long)llrint(v * w.fscale));
   }
 }
 
@@ -435,7 +526,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
     if (threadIdx.x == 0) tstar[0] = t_in;
     return;
   }
-  const int total = w.act_total[0];
+  const int total = active_total(w);
   const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N);
   if (!(target < (double)N)) {   // beta = 0: every t <= min q - eps is a minimiser
     if (threadIdx.x == 0) tstar[0] = br.lo;
@@ -602,15 +693,15 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
   block_sum<2>(v, red);
   gw[wid][lane] = acc;
   __syncthreads();
-  double* pp = w.part + (size_t)blockIdx.x * PSTRIDE;
+  double* pp = w.part + blockIdx.x;   // column c of this workgroup's row at pp[c GMAX]
   if (threadIdx.x == 0) {
     pp[0] = v[0];
-    pp[1] = v[1];
+    pp[GMAX] = v[1];
   }
   if (threadIdx.x < dz) {
     double a = 0.0;
     for (int k = 0; k < RBS / SAA_WAVE; ++k) a += gw[k][threadIdx.x];
-    pp[2 + threadIdx.x] = a;
+    pp[(size_t)(2 + threadIdx.x) * GMAX] = a;
   }
 }
 
@@ -666,7 +757,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
 #pragma unroll
     for (int cc = 0; cc < CPW; ++cc) {
       const int c = wid + NW * cc < PSTRIDE ? wid + NW * cc : PSTRIDE - 1;
-      x[cc][r] = w.part[(size_t)b * PSTRIDE + c];
+      x[cc][r] = w.part[(size_t)c * GMAX + b];
     }
   }
 #pragma unroll
@@ -674,7 +765,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
     double a = 0.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) a += lane + SAA_WAVE * r < G ? x[cc][r] : 0.0;
-    a = wave_sum(a);
+    a = fast_sum(a);
     const int c = wid + NW * cc;
     if (lane == 0 && c < ncol) col[0][c] = a;
   }
@@ -683,7 +774,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
   double zz = 0.0;
   if (k < SAA_WAVE) {   // |z|^2 by the whole of wave 0, one load per lane
     const double zl = k < dz ? z[k] : 0.0;
-    zz = wave_sum(zl * zl);
+    zz = fast_sum(zl * zl);
   }
   if (k >= ncol) return;
   const double acc = col[0][k];
@@ -810,14 +901,15 @@ static CvarWork carve(void* work) {
   w.aval = (double*)p;
   p += sizeof(double) * (size_t)GMAX * SEG;
   w.fix = (unsigned long long*)p;
-  p += sizeof(unsigned long long) * RPASSES * NP;
+  p += sizeof(unsigned long long) * RPASSES * SLOTS * NP;
   w.hist = (int*)p;
-  p += sizeof(int) * PASSES * 2 * NB;
+  p += sizeof(int) * PASSES * SLOTS * 2 * NB;
   w.nact = (int*)p;
   p += sizeof(int) * GMAX;
   w.nabove = (int*)p;
   p += sizeof(int) * GMAX;
   w.act_total = (int*)p;
+  w.fscale = 1.0;
   return w;
 }
 
@@ -830,7 +922,8 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
           const double* z, int t_mode, double t_in, int phase, double* tstar, double* out, const int* newton,
           const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats, void* work,
           hipStream_t st) {
-  const CvarWork w = carve(work);
+  CvarWork w = carve(work);
+  w.fscale = std::ldexp(1.0, std::min(38, 61 - std::ilogb((double)N)));   // N < 2^(ilogb N + 1)
   const int G = groups(N);
   const double target = (double)N * (1.0 - beta);
   if (phase & 1) {
@@ -838,7 +931,7 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
       saa_k_cvar_minmax<<<G, RBS, 0, st>>>(q, N, w, G);
       for (int ps = 0; ps < PASSES; ++ps) saa_k_cvar_probe<<<G, RBS, 0, st>>>(q, N, w, G, ps, eps, target);
       saa_k_cvar_compact<<<G, RBS, 0, st>>>(q, N, w, G, eps, target);
-      for (int r = 0; r < RPASSES; ++r) saa_k_cvar_refine<<<G, RBS, 0, st>>>(q, N, w, G, r, eps, target);
+      for (int r = 0; r < RPASSES; ++r) saa_k_cvar_refine<<<G, RFB, 0, st>>>(q, N, w, G, r, eps, target);
     }
     saa_k_cvar_solve<<<1, SBS, 0, st>>>(q, N, w, G, eps, target, t_mode, t_in, tstar);
   }
