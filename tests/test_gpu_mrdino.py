@@ -55,7 +55,14 @@ def test_params_roundtrip(setup):
     assert np.array_equal(model.get_params(), p)
 
 
-@pytest.mark.parametrize("prec,tol_q,tol_g", [(saa.FP32, 1e-5, 1e-4), (saa.BF16, 2e-2, 2e-1), (saa.FP8, 5e-2, 6e-1)])
+# BF16: each product's operands are rounded to BF16 (unit roundoff u = 2^-9);
+# q passes through five chained products (about 2u sqrt(5) = 9e-3 at worst,
+# 2e-3 allows the measured 8.5e-4 with the typical sqrt growth), dq/dz through
+# about ten more of the reverse pass (2u sqrt(10) = 1.2e-2: 4e-2 allows 20u
+# for the worst sample, 1e-2 for the median).  FP8 (E4M3, u = 2^-4 before the
+# per-sample scaling) has no accuracy target: its bounds only guard against
+# a broken path.
+@pytest.mark.parametrize("prec,tol_q,tol_g", [(saa.FP32, 1e-5, 1e-4), (saa.BF16, 2e-3, 4e-2), (saa.FP8, 5e-2, 6e-1)])
 def test_per_sample(setup, prec, tol_q, tol_g):
     prob, xi, z, model, ctx, q_ref, g_ref = setup
     print(f"case mrdino per_sample prec={prec}", flush=True)

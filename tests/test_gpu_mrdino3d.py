@@ -48,7 +48,9 @@ def setup3(gpu_lib):
     model.close()
 
 
-@pytest.mark.parametrize("prec,tol_q,tol_g", [(saa.FP32, 1e-5, 1e-4), (saa.BF16, 2e-2, 2e-1), (saa.FP8, 8e-2, 1.0)])
+# Bounds derived as for the 2D surrogate (BF16 unit roundoff 2^-9 through the
+# forward and reverse chains of products); FP8 has no accuracy target.
+@pytest.mark.parametrize("prec,tol_q,tol_g", [(saa.FP32, 1e-5, 1e-4), (saa.BF16, 2e-3, 4e-2), (saa.FP8, 5e-2, 6e-1)])
 def test_per_sample_3d(setup3, prec, tol_q, tol_g):
     prob, xi, z, model, ctx, q_ref, g_ref, widths = setup3
     print(f"case mrdino3d per_sample prec={prec}", flush=True)
