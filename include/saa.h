@@ -560,7 +560,7 @@ int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z
  * serialised by the caller.  Sizes beyond N = SAA_REDUCE_MAX_N or d_Z = 64
  * return SAA_E_INVALID before any device work; SAA_E_DEVICE if the
  * workspace's device address cannot be obtained or a launch fails. */
-#define SAA_REDUCE_SCRATCH_BYTES 4364512
+#define SAA_REDUCE_SCRATCH_BYTES 4380704
 int saa_risk_reduce_noalloc(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
                             const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream);
 

@@ -15,18 +15,24 @@
 //         #{q > t + eps} <= Phi(t) <= #{q > t};
 //     a probe t with #{q > t + eps} > target is a valid lo, one with
 //     #{q > t} <= target a valid hi.  Each pass histograms every q against
-//     NP equispaced probes (exact binary search over the probe values) and
-//     the bracket shrinks about NP/2-fold, until it is a few eps wide;
+//     PP = 256 equispaced probes (exact binary search over the probe values)
+//     and the bracket shrinks about 128-fold, until it is a few eps wide;
 //  3. compact (G workgroups): samples in (lo, hi + eps) are the only ones
 //     whose s_eps' varies inside the bracket; each workgroup gathers its
 //     "active" samples in index order and counts those at or above hi + eps
 //     (their s_eps' is 1 throughout the bracket);
+//  3b. only if the active set overflows its capacity (q within a few eps of
+//     each other, as trained surrogates give): RPASSES refinement passes
+//     (G workgroups) evaluate Phi exactly at 64 points of the bracket and
+//     keep the crossing pair;
 //  4. solve (1 workgroup): the active samples are concatenated in workgroup
 //     order in LDS and a safeguarded Newton iteration on
 //         Phi(t) = #{q >= hi + eps} + sum_active s_eps'(q_a - t)
 //     runs inside the bracket (bisection when a step leaves it or stalls),
-//     followed by one polish step.  If the active set overflows its capacity
-//     the same iteration runs over all N samples.
+//     followed by one polish step; after an overflow, the root of the cubic
+//     through Phi at four points of the last refinement pass around the
+//     crossing.  With the value and gradient sums in the same call, the
+//     partial-sum pass does this step itself (no separate launch).
 // Every wave recomputes the bracket from the previous launches' results with
 // the same arithmetic, so all of them agree on it without a grid barrier.
 // For beta = 0 (target = N) every t <= min(q) - eps is a minimiser with the
@@ -50,16 +56,17 @@ namespace {
 
 constexpr int RBS = 256;          // threads of the multi-workgroup passes
 constexpr int SBS = 1024;         // threads of the single-workgroup kernels
-constexpr int NP = 64;            // probes per bracketing pass (one per lane)
-constexpr int NB = NP + 1;        // histogram bins: number of probes below q
-constexpr int PASSES = 3;         // bracketing passes (shrink ~32x each)
+constexpr int NP = 64;            // points per refinement pass (one per lane)
+constexpr int PP = 256;           // probes per bracketing pass (four per lane)
+constexpr int PPL = PP / 64;      // probes of one lane: 4 lane .. 4 lane + 3
+constexpr int PASSES = 2;         // bracketing passes (shrink ~128x each)
 constexpr int CAP = 8192;         // active-set capacity (doubles in LDS)
 constexpr int SEG = 2048;         // active-set capacity per workgroup
 constexpr int GMAX = 256;         // workgroups of the multi-workgroup passes
 constexpr int TILE = 4 * RBS;     // samples per compaction tile
 constexpr int PSTRIDE = 2 + SAA_MAX_DZ;
 constexpr int WAVE_NEWTON = 256;  // active sets up to this size are solved by one wave
-constexpr int RPASSES = 4;        // refinement passes when the active set overflows
+constexpr int RPASSES = 3;        // refinement passes when the active set overflows
 constexpr int RFB = 1024;         // threads of the refinement passes (16 waves share a chunk)
 constexpr int SLOTS = 8;          // copies of each atomic counter (workgroup b adds to copy b % SLOTS)
 
@@ -68,9 +75,9 @@ constexpr int SLOTS = 8;          // copies of each atomic counter (workgroup b 
 // active-set counters (about 4.4 MB, independent of N).
 constexpr size_t kCvarWorkBytes =
     sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
-    sizeof(unsigned long long) * RPASSES * SLOTS * NP + sizeof(int) * ((size_t)PASSES * SLOTS * 2 * NB + 2 * GMAX + SLOTS);
+    sizeof(unsigned long long) * RPASSES * SLOTS * NP + sizeof(int) * ((size_t)PASSES * SLOTS * 2 * PP + 2 * GMAX + SLOTS);
 constexpr int kMaxDevices = 64;
-static_assert(NP == SAA_WAVE, "one probe per lane");
+static_assert(NP == SAA_WAVE && PPL * SAA_WAVE == PP && PPL == 4, "refinement point per lane, four probes per lane");
 static_assert(GMAX % SAA_WAVE == 0, "partial rows per lane in the final reduction");
 static_assert(SAA_MAX_DZ <= SAA_WAVE, "one gradient component per lane");
 
@@ -81,11 +88,12 @@ struct CvarWork {
   double* aval;   // [GMAX][SEG] active q values per workgroup, in index order
   // The counters that every workgroup adds to are kept in SLOTS copies, so
   // that fewer atomics meet on one address; readers add the copies up.
-  int* hist;      // [PASSES][SLOTS][2][NB] probe histograms
+  int* hist;      // [PASSES][SLOTS][2][PP] probe histograms: entry j counts q with j + 1 probes below (no
+                  // entry for 0: the counts only enter through #{q > probe j})
   int* nact;      // [GMAX] active samples per workgroup
   int* nabove;    // [GMAX] samples at or above hi + eps per workgroup
   int* act_total; // [SLOTS] active samples over all workgroups
-  unsigned long long* fix;   // [RPASSES][SLOTS][NP] Phi at the refinement probes, fixed point
+  unsigned long long* fix;   // [RPASSES][SLOTS][NP] Phi at the refinement points, fixed point
   double fscale;  // the fixed-point scale: 2^38, lowered for N >= 2^24 so N fscale < 2^62
 };
 
@@ -179,9 +187,9 @@ __device__ __forceinline__ int wave_suffix(int v) {
 // Probe j of a pass over [lo, hi]; non-decreasing in j for any rounding.
 __device__ __forceinline__ double probe(double lo, double step, int j) { return lo + (double)(j + 1) * step; }
 
-// #{j < NP : probe(j) + shift < x}, exact (binary search over monotone probes).
+// #{j < PP : probe(j) + shift < x}, exact (binary search over monotone probes).
 __device__ __forceinline__ int probes_below(double x, double lo, double step, double shift) {
-  int a = 0, b = NP;
+  int a = 0, b = PP;
   while (a < b) {
     const int m = (a + b) >> 1;
     if (probe(lo, step, m) + shift < x) a = m + 1;
@@ -196,23 +204,32 @@ struct Bracket {
 };
 
 // Bracket after `passes` bracketing passes, recomputed from the workspace by
-// each wave on its own (lane j evaluates probe j); every wave of every
-// workgroup gets the same result.  No LDS, no barrier.
+// each wave on its own (lane l evaluates probes 4 l .. 4 l + 3); every wave of
+// every workgroup gets the same result.  No LDS, no barrier.
 __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double eps, double target, double N) {
   const int lane = threadIdx.x & (SAA_WAVE - 1);
   // every load is issued up front (none depends on the bracket): one memory
-  // round trip instead of one per pass
+  // round trip instead of one per pass; entries 4 l .. 4 l + 3 of a row are
+  // one 16-byte load
   double mn = INFINITY, mx = -INFINITY;
-  int hc1[PASSES], hc2[PASSES];
+  int4 hc1[PASSES], hc2[PASSES];
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
-    hc1[p] = 0;
-    hc2[p] = 0;
+    hc1[p] = make_int4(0, 0, 0, 0);
+    hc2[p] = make_int4(0, 0, 0, 0);
     if (p < passes) {
 #pragma unroll
       for (int k = 0; k < SLOTS; ++k) {
-        hc1[p] += w.hist[(p * SLOTS + k) * 2 * NB + lane + 1];
-        hc2[p] += w.hist[(p * SLOTS + k) * 2 * NB + NB + lane + 1];
+        const int4 a = *(const int4*)(w.hist + (size_t)(p * SLOTS + k) * 2 * PP + PPL * lane);
+        const int4 b = *(const int4*)(w.hist + (size_t)(p * SLOTS + k) * 2 * PP + PP + PPL * lane);
+        hc1[p].x += a.x;
+        hc1[p].y += a.y;
+        hc1[p].z += a.z;
+        hc1[p].w += a.w;
+        hc2[p].x += b.x;
+        hc2[p].y += b.y;
+        hc2[p].z += b.z;
+        hc2[p].w += b.w;
       }
     }
   }
@@ -233,12 +250,22 @@ __device__ Bracket bracket_after(const CvarWork& w, int G, int passes, double ep
     if (p >= passes) break;
     br.live = br.live && (br.hi - br.lo > 4.0 * eps);
     if (!br.live) break;
-    // suffix sums over the bins above probe `lane`: #{q > probe}, #{q > probe + eps}
-    const int c1 = wave_suffix(hc1[p]), c2 = wave_suffix(hc2[p]);
-    const double step = (br.hi - br.lo) / (NP + 1);
-    const double pj = probe(br.lo, step, lane);
-    const double nlo = fast_max((double)c2 > target ? pj : br.lo);
-    const double nhi = fast_min((double)c1 <= target ? pj : br.hi);
+    // #{q > probe j} = sum of the entries j .. PP - 1 (and the same with
+    // probe j + eps): suffix sums over the lanes' totals, then within a lane
+    const int4 e1 = hc1[p], e2 = hc2[p];
+    const int s1 = wave_suffix(e1.x + e1.y + e1.z + e1.w), s2 = wave_suffix(e2.x + e2.y + e2.z + e2.w);
+    const int c1[PPL] = {s1, s1 - e1.x, s1 - e1.x - e1.y, s1 - e1.x - e1.y - e1.z};
+    const int c2[PPL] = {s2, s2 - e2.x, s2 - e2.x - e2.y, s2 - e2.x - e2.y - e2.z};
+    const double step = (br.hi - br.lo) / (PP + 1);
+    double lo_c = br.lo, hi_c = br.hi;
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const double pj = probe(br.lo, step, PPL * lane + i);
+      if ((double)c2[i] > target) lo_c = fmax(lo_c, pj);
+      if ((double)c1[i] <= target) hi_c = fmin(hi_c, pj);
+    }
+    const double nlo = fast_max(lo_c);
+    const double nhi = fast_min(hi_c);
     if (!(nhi - nlo < br.hi - br.lo)) {
       br.live = false;
       break;
@@ -255,6 +282,35 @@ __device__ __forceinline__ int active_total(const CvarWork& w) {
 #pragma unroll
   for (int k = 0; k < SLOTS; ++k) t += w.act_total[k];
   return t;
+}
+
+// The bracket (and the overflow flag) computed by wave 0 of the workgroup
+// and passed to the others through LDS (sb: 4 doubles), so that the
+// workgroup reads the shared counters once rather than once per wave.  All
+// threads must call.
+struct Shared {
+  Bracket br;
+  bool overflow;
+};
+__device__ Shared shared_bracket(const CvarWork& w, int G, int passes, double eps, double target, double N,
+                                 double* sb) {
+  if (threadIdx.x < SAA_WAVE) {
+    const Bracket br = bracket_after(w, G, passes, eps, target, N);
+    const bool ov = active_total(w) > CAP;
+    if (threadIdx.x == 0) {
+      sb[0] = br.lo;
+      sb[1] = br.hi;
+      sb[2] = br.live ? 1.0 : 0.0;
+      sb[3] = ov ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  Shared r;
+  r.br.lo = sb[0];
+  r.br.hi = sb[1];
+  r.br.live = sb[2] != 0.0;
+  r.overflow = sb[3] != 0.0;
+  return r;
 }
 
 __device__ __forceinline__ void chunk_of(int64_t N, int G, int64_t& i0, int64_t& i1) {
@@ -341,7 +397,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_
     w.mm[2 * blockIdx.x + 1] = mx;
   }
   const int gt = blockIdx.x * RBS + threadIdx.x, gs = G * RBS;
-  for (int k = gt; k < PASSES * SLOTS * 2 * NB; k += gs) w.hist[k] = 0;
+  for (int k = gt; k < PASSES * SLOTS * 2 * PP; k += gs) w.hist[k] = 0;
   for (int k = gt; k < RPASSES * SLOTS * NP; k += gs) w.fix[k] = 0;
   for (int k = gt; k < SLOTS; k += gs) w.act_total[k] = 0;
 }
@@ -349,39 +405,37 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_minmax(const double* q, int64_
 // 2. bracketing pass p: probe histograms of this workgroup's chunk.
 __global__ void __launch_bounds__(RBS) saa_k_cvar_probe(const double* q, int64_t N, CvarWork w, int G, int p,
                                                         double eps, double target) {
-  __shared__ int hl[2 * NB];
-  const Bracket br = bracket_after(w, G, p, eps, target, (double)N);
+  __shared__ int hl[2 * PP];
+  __shared__ double sb[4];
+  const Bracket br = shared_bracket(w, G, p, eps, target, (double)N, sb).br;
   if (!(br.live && br.hi - br.lo > 4.0 * eps)) return;
-  for (int k = threadIdx.x; k < 2 * NB; k += RBS) hl[k] = 0;
+  for (int k = threadIdx.x; k < 2 * PP; k += RBS) hl[k] = 0;
   __syncthreads();
-  const double step = (br.hi - br.lo) / (NP + 1);
+  const double step = (br.hi - br.lo) / (PP + 1);
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
-  // most samples fall outside the bracket (bins 0 and NP): count those in
-  // registers, so the LDS atomics only see the few in between
-  int edge[4] = {0, 0, 0, 0};
+  // samples below every probe are not counted; those above every probe
+  // (entry PP - 1) are counted in registers, so the LDS atomics only see
+  // the samples in between
+  int edge[2] = {0, 0};
   for (int64_t i = i0 + threadIdx.x; i < i1; i += RBS) {
     const double qi = q[i];
     const int b1 = probes_below(qi, br.lo, step, 0.0);
     const int b2 = probes_below(qi, br.lo, step, eps);
-    if (b1 == 0) ++edge[0];
-    else if (b1 == NP) ++edge[1];
-    else atomicAdd(&hl[b1], 1);
-    if (b2 == 0) ++edge[2];
-    else if (b2 == NP) ++edge[3];
-    else atomicAdd(&hl[NB + b2], 1);
+    if (b1 == PP) ++edge[0];
+    else if (b1 > 0) atomicAdd(&hl[b1 - 1], 1);
+    if (b2 == PP) ++edge[1];
+    else if (b2 > 0) atomicAdd(&hl[PP + b2 - 1], 1);
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) edge[k] = fast_sum(edge[k]);
+  edge[0] = fast_sum(edge[0]);
+  edge[1] = fast_sum(edge[1]);
   if ((threadIdx.x & (SAA_WAVE - 1)) == 0) {
-    atomicAdd(&hl[0], edge[0]);
-    atomicAdd(&hl[NP], edge[1]);
-    atomicAdd(&hl[NB], edge[2]);
-    atomicAdd(&hl[NB + NP], edge[3]);
+    atomicAdd(&hl[PP - 1], edge[0]);
+    atomicAdd(&hl[2 * PP - 1], edge[1]);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < 2 * NB; k += RBS)
-    if (hl[k]) atomicAdd(&w.hist[(p * SLOTS + blockIdx.x % SLOTS) * 2 * NB + k], hl[k]);
+  for (int k = threadIdx.x; k < 2 * PP; k += RBS)
+    if (hl[k]) atomicAdd(&w.hist[(size_t)(p * SLOTS + blockIdx.x % SLOTS) * 2 * PP + k], hl[k]);
 }
 
 // 3. gather this workgroup's active samples (lo < q < hi + eps) in index
@@ -389,7 +443,8 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_probe(const double* q, int64_t
 __global__ void __launch_bounds__(RBS) saa_k_cvar_compact(const double* q, int64_t N, CvarWork w, int G,
                                                           double eps, double target) {
   __shared__ int sh[RBS / SAA_WAVE];
-  const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N);
+  __shared__ double sb[4];
+  const Bracket br = shared_bracket(w, G, PASSES, eps, target, (double)N, sb).br;
   if (!(target < (double)N)) return;
   const double top = br.hi + eps;
   int64_t i0, i1;
@@ -437,13 +492,22 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_compact(const double* q, int64
 // evaluated Phi exactly at the 64 points lo + j (hi - lo) / 63 (sums over all
 // workgroups in fixed point, so their order does not matter); the new
 // bracket is the pair of neighbouring points where Phi crosses the target.
-// plo, phi hold Phi at the ends once a refinement pass has run (else -1).
-// Every wave gets the same result.
-__device__ Bracket bracket_refined(const CvarWork& w, int G, int passes, double eps, double target, double N,
-                                   double& plo, double& phi) {
+// Once a refinement pass has run, pv[0..3] hold Phi at the four points
+// j0 .. j0 + 3 of the last pass around the crossing pair (jl, jl + 1) and
+// *lo4 = point j0, *h = the point spacing (pv[0] = -1 otherwise).  Every wave
+// gets the same result.
+struct Refined {
+  Bracket br;
+  double pv[4], lo4, h;
+  int k;   // the crossing pair is points k, k + 1 of the four
+};
+__device__ Refined bracket_refined(const CvarWork& w, int G, int passes, double eps, double target, double N) {
   const int lane = threadIdx.x & (SAA_WAVE - 1);
-  Bracket br = bracket_after(w, G, PASSES, eps, target, N);
-  plo = phi = -1.0;
+  Refined R;
+  R.br = bracket_after(w, G, PASSES, eps, target, N);
+  R.pv[0] = -1.0;
+  R.lo4 = R.h = 0.0;
+  R.k = 0;
   unsigned long long f[RPASSES];
 #pragma unroll
   for (int r = 0; r < RPASSES; ++r) {
@@ -454,18 +518,50 @@ __device__ Bracket bracket_refined(const CvarWork& w, int G, int passes, double 
   }
 #pragma unroll
   for (int r = 0; r < RPASSES; ++r) {
+    Bracket& br = R.br;
     if (r >= passes || !(br.hi - br.lo > 8.0 * DBL_EPSILON * fmax(fabs(br.lo), fabs(br.hi)))) break;
     const double step = (br.hi - br.lo) / (NP - 1);
     const double pv = (double)f[r] / w.fscale;
     const int jl = (int)fast_max((double)((lane < NP - 1 && pv > target) ? lane : 0));
+    const int j0 = jl < 1 ? 0 : (jl > NP - 3 ? NP - 4 : jl - 1);   // four points inside 0 .. 63
+#pragma unroll
+    for (int i = 0; i < 4; ++i) R.pv[i] = lane_read(pv, j0 + i);
+    R.k = jl - j0;
+    R.lo4 = br.lo + (double)j0 * step;
+    R.h = step;
     const double tl = br.lo + (double)jl * step;
     const double th = jl + 1 == NP - 1 ? br.hi : br.lo + (double)(jl + 1) * step;
-    plo = lane_read(pv, jl);
-    phi = lane_read(pv, jl + 1);
     br.lo = tl;
     br.hi = th;
   }
-  return br;
+  return R;
+}
+
+// Root in [lo, hi] of the cubic through Phi at four equispaced points
+// (pv[i] at lo4 + i h; the crossing pair is points k, k + 1, with lo, hi
+// their abscissae): Newton from the secant point, kept inside [lo, hi].
+// After three refinement passes h is about 4 eps / 63^3, and the cubic's
+// error there is far below the rounding of t.
+__device__ double cubic_root(const Refined& R, double target) {
+  const double* p = R.pv;
+  // Newton form on nodes 0, 1, 2, 3 (unit spacing)
+  const double d1 = p[1] - p[0], d2 = (p[2] - 2.0 * p[1] + p[0]) * 0.5,
+               d3 = (p[3] - 3.0 * p[2] + 3.0 * p[1] - p[0]) / 6.0;
+  auto P = [&](double x) { return p[0] + x * (d1 + (x - 1.0) * (d2 + (x - 2.0) * d3)); };
+  auto dP = [&](double x) {
+    return d1 + d2 * (2.0 * x - 1.0) + d3 * (3.0 * x * x - 6.0 * x + 2.0);
+  };
+  const double a = (double)R.k, b = a + 1.0;
+  const double pa = p[R.k], pb = p[R.k + 1];
+  double x = pa > pb ? a + (pa - target) / (pa - pb) : a + 0.5;
+  x = fmin(fmax(x, a), b);
+  for (int it = 0; it < 4; ++it) {
+    const double dp = dP(x);
+    if (!(dp < 0.0)) break;
+    x = fmin(fmax(x - (P(x) - target) / dp, a), b);
+  }
+  const double t = R.lo4 + x * R.h;
+  return fmin(fmax(t, R.br.lo), R.br.hi);
 }
 
 // 3b. refinement pass r (only when the active set overflowed its capacity):
@@ -477,9 +573,22 @@ __global__ void __launch_bounds__(RFB) saa_k_cvar_refine(const double* q, int64_
   constexpr int NWV = RFB / SAA_WAVE;
   __shared__ double part[NWV][NP];
   __shared__ double qt[TILE];
-  if (!(target < (double)N) || active_total(w) <= CAP) return;
-  double plo, phi;
-  const Bracket br = bracket_refined(w, G, r, eps, target, (double)N, plo, phi);
+  __shared__ double sb[4];
+  if (!(target < (double)N)) return;
+  if (threadIdx.x < SAA_WAVE) {   // wave 0 finds the bracket; the others take it from LDS
+    const bool ov = active_total(w) > CAP;
+    const Refined R = bracket_refined(w, G, r, eps, target, (double)N);
+    if (threadIdx.x == 0) {
+      sb[0] = R.br.lo;
+      sb[1] = R.br.hi;
+      sb[2] = ov ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  Bracket br;
+  br.lo = sb[0];
+  br.hi = sb[1];
+  if (sb[2] == 0.0) return;   // no overflow: no refinement
   if (!(br.hi - br.lo > 8.0 * DBL_EPSILON * fmax(fabs(br.lo), fabs(br.hi)))) return;
   const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
   const double ie = 1.0 / eps;
@@ -510,42 +619,35 @@ __global__ void __launch_bounds__(RFB) saa_k_cvar_refine(const double* q, int64_
   if (wid == 0) {
     double v = 0.0;
     for (int k = 0; k < NWV; ++k) v += part[k][lane];
-    if (v > 0.0) atomicAdd(&w.fix[(r * SLOTS + blockIdx.x % SLOTS) * NP + lane], (unsigned long long)llrint(v * w.fscale));
+    if (v > 0.0)
+      atomicAdd(&w.fix[(r * SLOTS + blockIdx.x % SLOTS) * NP + lane], (unsigned long long)llrint(v * w.fscale));
   }
 }
 
-// 4. t* (or t_in when t_mode = 1) -> tstar[0].
-__global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t N, CvarWork w, int G, double eps,
-                                                        double target, int t_mode, double t_in, double* tstar) {
-  __shared__ double red[2 * (SBS / SAA_WAVE)];
-  __shared__ int off[GMAX + 1];
-  __shared__ int sh[SBS / SAA_WAVE];
-  __shared__ double s[CAP];
+// 4. t* (or t_in when t_mode = 1), by one workgroup of RBS threads; every
+// thread returns the same value.  LDS: s holds CAP doubles, off GMAX + 1
+// ints, sh RBS / 64 ints, red 2 RBS / 64 doubles.
+__device__ double cvar_tstar(const CvarWork& w, int64_t N, int G, double eps, double target, int t_mode,
+                             double t_in, double* s, int* off, int* sh, double* red, double* sb) {
+  const int lane = threadIdx.x & (SAA_WAVE - 1);
   const double ie = 1.0 / eps;
-  if (t_mode == 1) {
-    if (threadIdx.x == 0) tstar[0] = t_in;
-    return;
-  }
-  const int total = active_total(w);
-  const Bracket br = bracket_after(w, G, PASSES, eps, target, (double)N);
-  if (!(target < (double)N)) {   // beta = 0: every t <= min q - eps is a minimiser
-    if (threadIdx.x == 0) tstar[0] = br.lo;
-    return;
-  }
-  if (total > CAP) {
-    // overflow (a segment overflow also pushes act_total above CAP): the
-    // refinement passes narrowed the bracket to (hi - lo) ~ 4 eps / 63^4; a
-    // secant step between its ends (where Phi is known) finishes t*
-    if (threadIdx.x >= SAA_WAVE) return;
-    double plo, phi;
-    const Bracket rb = bracket_refined(w, G, RPASSES, eps, target, (double)N, plo, phi);
-    double t = 0.5 * (rb.lo + rb.hi);
-    if (plo >= 0.0 && phi >= 0.0 && plo > phi) {
-      const double tn = rb.lo + (plo - target) / (plo - phi) * (rb.hi - rb.lo);
-      if (tn >= rb.lo && tn <= rb.hi) t = tn;
+  if (t_mode == 1) return t_in;
+  const Shared S = shared_bracket(w, G, PASSES, eps, target, (double)N, sb);
+  const Bracket br = S.br;
+  if (!(target < (double)N)) return br.lo;   // beta = 0: every t <= min q - eps is a minimiser
+  if (S.overflow) {
+    // overflow (a segment overflow also pushes the total above CAP): the
+    // refinement passes narrowed the bracket to (hi - lo) ~ 4 eps / 63^3;
+    // the cubic through Phi at four points of the last pass finishes t*
+    // (wave 0 computes it, the others take it from LDS)
+    if (threadIdx.x < SAA_WAVE) {
+      const Refined R = bracket_refined(w, G, RPASSES, eps, target, (double)N);
+      double t = 0.5 * (R.br.lo + R.br.hi);
+      if (R.pv[0] >= 0.0) t = cubic_root(R, target);
+      if (threadIdx.x == 0) sb[0] = t;
     }
-    if (threadIdx.x == 0) tstar[0] = t;
-    return;
+    __syncthreads();
+    return sb[0];
   }
   // concatenate the per-workgroup active sets in workgroup order
   const int cb = threadIdx.x < G ? w.nact[threadIdx.x] : 0;
@@ -557,13 +659,13 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
   if (threadIdx.x < G && cb > SEG) fits = false;
   int ex2;
   const double above = (double)block_scan(ab, &ex2, sh);
-  // act_total <= CAP here, so no segment overflowed and n <= CAP
+  // the total is <= CAP here, so no segment overflowed and n <= CAP
   fits = __syncthreads_and(fits) && n <= CAP;
   if (threadIdx.x == 0) off[G] = n;
   __syncthreads();
   double t = 0.5 * (br.lo + br.hi);   // (fits always holds here)
   if (fits) {
-    for (int r = threadIdx.x; r < n; r += SBS) {
+    for (int r = threadIdx.x; r < n; r += RBS) {
       int a = 0, b = G;   // last workgroup with off <= r
       while (b - a > 1) {
         const int m = (a + b) >> 1;
@@ -573,11 +675,10 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
       s[r] = w.aval[(size_t)a * SEG + (r - off[a])];
     }
     __syncthreads();
-    if (n <= WAVE_NEWTON) {   // one wave, no barriers
-      if (threadIdx.x >= SAA_WAVE) return;
+    if (n <= WAVE_NEWTON) {   // every wave on its own, no barriers
       t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
         double a0 = 0.0, a1 = 0.0;
-        for (int i = threadIdx.x; i < n; i += SAA_WAVE) {
+        for (int i = lane; i < n; i += SAA_WAVE) {
           a0 += sp_d1(s[i] - tc, eps, ie);
           a1 += sp_d2(s[i] - tc, eps, ie);
         }
@@ -587,7 +688,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
     } else {
       t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
         double a[2] = {0.0, 0.0};
-        for (int i = threadIdx.x; i < n; i += SBS) {
+        for (int i = threadIdx.x; i < n; i += RBS) {
           a[0] += sp_d1(s[i] - tc, eps, ie);
           a[1] += sp_d2(s[i] - tc, eps, ie);
         }
@@ -597,6 +698,18 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_solve(const double* q, int64_t
       });
     }
   }
+  return t;
+}
+
+// t* -> tstar[0] (used when the adjoints need t* before the partial sums).
+__global__ void __launch_bounds__(RBS) saa_k_cvar_solve(int64_t N, CvarWork w, int G, double eps, double target,
+                                                        int t_mode, double t_in, double* tstar) {
+  __shared__ double red[2 * (RBS / SAA_WAVE)];
+  __shared__ int off[GMAX + 1];
+  __shared__ int sh[RBS / SAA_WAVE];
+  __shared__ double s[CAP];
+  __shared__ double sb[4];
+  const double t = cvar_tstar(w, N, G, eps, target, t_mode, t_in, s, off, sh, red, sb);
   if (threadIdx.x == 0) tstar[0] = t;
 }
 
@@ -644,22 +757,43 @@ __device__ __forceinline__ void risk_terms(double qi, double t, double eps, doub
 // 5. per-workgroup partial sums: sum v, sum d, sum d dq/dz (see risk_terms).
 // The weighted samples of each tile are listed in LDS; wave k of the block
 // then takes every (RBS/64)-th of them with lane c accumulating component c.
-template <int KIND>
+// SOLVE (CVaR, t and the sums in one call): every workgroup first finds t*
+// itself (the same arithmetic as saa_k_cvar_solve, so the same value), and
+// workgroup 0 stores it; otherwise t is read from tstar[0].
+template <int KIND, bool SOLVE>
 __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const double* g, int64_t N, int dz,
                                                        CvarWork w, int G, double eps, double kappa, double tau,
-                                                       const double* tstar) {
+                                                       double* tstar, double target, int t_mode, double t_in) {
   __shared__ double red[2 * (RBS / SAA_WAVE)];
   __shared__ int sh[RBS / SAA_WAVE];
   __shared__ int li[TILE];
   __shared__ double lw[TILE];
   __shared__ double gw[RBS / SAA_WAVE][SAA_WAVE];
+  __shared__ double st[SOLVE ? CAP : 1];
+  __shared__ int soff[SOLVE ? GMAX + 1 : 1];
+  __shared__ double sb[4];
   const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
-  const double t = tstar[0];
-  const double ie = 1.0 / eps;
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
+  // the first tile's q is loaded before t is known (its latency overlaps the
+  // t* computation)
+  double qv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = i0 + 4 * threadIdx.x + r;
+    qv[r] = i < i1 ? q[i] : 0.0;
+  }
+  double t;
+  if constexpr (SOLVE) {
+    t = cvar_tstar(w, N, G, eps, target, t_mode, t_in, st, soff, sh, red, sb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) tstar[0] = t;
+    __syncthreads();   // sh and red are reused below
+  } else {
+    t = tstar[0];
+  }
+  const double ie = 1.0 / eps;
   double v[2] = {0.0, 0.0};
-  double acc = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t t0 = i0; t0 < i1; t0 += TILE) {
     double d[4];
     int n = 0;
@@ -669,7 +803,7 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
       d[r] = 0.0;
       if (i < i1) {
         double vi;
-        risk_terms<KIND>(q[i], t, eps, ie, kappa, tau, vi, d[r]);
+        risk_terms<KIND>(t0 == i0 ? qv[r] : q[i], t, eps, ie, kappa, tau, vi, d[r]);
         v[0] += vi;
         v[1] += d[r];
       }
@@ -686,12 +820,25 @@ __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const do
       }
     }
     __syncthreads();
-    if (lane < dz)
-      for (int r = wid; r < tot; r += RBS / SAA_WAVE) acc += lw[r] * g[(t0 + li[r]) * dz + lane];
+    // wave k takes the weighted samples k, k + 4, ... in turn into four
+    // accumulators (four independent load chains; a fixed order)
+    constexpr int NW = RBS / SAA_WAVE;
+    if (lane < dz) {
+      int r = wid;
+      for (; r + 3 * NW < tot; r += 4 * NW) {
+        const double g0 = g[(t0 + li[r]) * dz + lane], g1 = g[(t0 + li[r + NW]) * dz + lane];
+        const double g2 = g[(t0 + li[r + 2 * NW]) * dz + lane], g3 = g[(t0 + li[r + 3 * NW]) * dz + lane];
+        acc[0] += lw[r] * g0;
+        acc[1] += lw[r + NW] * g1;
+        acc[2] += lw[r + 2 * NW] * g2;
+        acc[3] += lw[r + 3 * NW] * g3;
+      }
+      for (; r < tot; r += NW) acc[0] += lw[r] * g[(t0 + li[r]) * dz + lane];
+    }
     __syncthreads();
   }
   block_sum<2>(v, red);
-  gw[wid][lane] = acc;
+  gw[wid][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   double* pp = w.part + blockIdx.x;   // column c of this workgroup's row at pp[c GMAX]
   if (threadIdx.x == 0) {
@@ -903,7 +1050,7 @@ static CvarWork carve(void* work) {
   w.fix = (unsigned long long*)p;
   p += sizeof(unsigned long long) * RPASSES * SLOTS * NP;
   w.hist = (int*)p;
-  p += sizeof(int) * PASSES * SLOTS * 2 * NB;
+  p += sizeof(int) * PASSES * SLOTS * 2 * PP;
   w.nact = (int*)p;
   p += sizeof(int) * GMAX;
   w.nabove = (int*)p;
@@ -933,9 +1080,15 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
       saa_k_cvar_compact<<<G, RBS, 0, st>>>(q, N, w, G, eps, target);
       for (int r = 0; r < RPASSES; ++r) saa_k_cvar_refine<<<G, RFB, 0, st>>>(q, N, w, G, r, eps, target);
     }
-    saa_k_cvar_solve<<<1, SBS, 0, st>>>(q, N, w, G, eps, target, t_mode, t_in, tstar);
+    // with the sums in the same call, the partial-sum pass finds t* itself
+    if (!(phase & 2)) saa_k_cvar_solve<<<1, RBS, 0, st>>>(N, w, G, eps, target, t_mode, t_in, tstar);
   }
-  if (phase & 2) saa_k_cvar_part<SAA_RISK_CVAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar);
+  if ((phase & 3) == 3)
+    saa_k_cvar_part<SAA_RISK_CVAR, true><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar, target, t_mode,
+                                                           t_in);
+  else if (phase & 2)
+    saa_k_cvar_part<SAA_RISK_CVAR, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar, target, 0,
+                                                            0.0);
   if ((phase & 2) || stats)
     saa_k_cvar_final<<<1, SBS, 0, st>>>(N, dz, w, G, target, SAA_RISK_CVAR, alpha, z, tstar, (phase & 2) ? 1 : 0,
                                         out, newton, lin, flag, lin_adj, did, (CvarStats*)stats);
@@ -961,16 +1114,20 @@ void risk(const double* q, const double* g, int64_t N, int dz, int kind, double 
   if (phase & 2) {
     switch (kind) {
       case SAA_RISK_MEAN:
-        saa_k_cvar_part<SAA_RISK_MEAN><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
+        saa_k_cvar_part<SAA_RISK_MEAN, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
+                                                            0.0);
         break;
       case SAA_RISK_MEAN_VAR:
-        saa_k_cvar_part<SAA_RISK_MEAN_VAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
+        saa_k_cvar_part<SAA_RISK_MEAN_VAR, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
+                                                            0.0);
         break;
       case SAA_RISK_POF:
-        saa_k_cvar_part<SAA_RISK_POF><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
+        saa_k_cvar_part<SAA_RISK_POF, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
+                                                            0.0);
         break;
       default:
-        saa_k_cvar_part<SAA_RISK_BPOE><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
+        saa_k_cvar_part<SAA_RISK_BPOE, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
+                                                            0.0);
     }
   }
   if ((phase & 2) || stats)
