@@ -227,7 +227,13 @@ int saa_options_default(saa_options* opt);
  * saa_set_samples; SAA_E_OOM when an allocation fails, SAA_E_INVALID for a
  * problem outside the ranges above or N_max outside 1 .. 4194303 in 2D (one
  * 1024-thread workgroup per sample must fit a grid of 2^32 - 1 work-items;
- * the 3D bound is stated above), checked before any device work. */
+ * the 3D bound is stated above), checked before any device work.
+ * Debugging aid: with the environment variable SAA_POISON_WORKSPACE set (and
+ * not "0") when the context is created, every saa_objective_grad and
+ * saa_per_sample call first fills the context's per-call buffers (q, dq/dz,
+ * results, reduction workspace, state, right-hand side, adjoint and
+ * per-sample counters) with NaN bytes; results must not change.  It adds
+ * one fill per buffer per call and is off by default. */
 int saa_ctx_create(const saa_problem* prob, int64_t N_max, void* hip_stream, saa_ctx** out);
 
 /* Free a context and everything it owns (NULL is ignored). */

@@ -5,6 +5,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <algorithm>
@@ -247,6 +248,28 @@ SolveParams solve_params(const saa_options* o, bool fp32_state) {
   sp.max_dc = o->max_dc > 0 ? o->max_dc : 10;
   sp.nu = 1;
   return sp;
+}
+
+// SAA_POISON_WORKSPACE set (and not "0") when the context is created: every
+// objective / per-sample call first fills the library-owned buffers that the
+// call writes before it reads them (q, g, the results block, the reduction
+// workspace, the state, right-hand side and adjoint vectors, the per-sample
+// counters) with all-ones bytes, a NaN in FP32 and FP64.  A kernel that read
+// any of them before writing it would turn the results into NaN.  (The
+// multigrid and CG scratch arrays are not filled: their boundary entries are
+// zero from allocation on and are never written, by design.)
+bool poison_requested() {
+  const char* e = std::getenv("SAA_POISON_WORKSPACE");
+  return e && *e && std::strcmp(e, "0") != 0;
+}
+
+int poison_workspaces(saa_ctx* c) {
+  if (!c->poison) return SAA_OK;
+  saa_rt::DevBuf* bufs[] = {&c->q, &c->g, &c->res, &c->cwork, &c->u, &c->f, &c->lam,
+                            &c->newton, &c->lin, &c->lin_adj, &c->flag, &c->did};
+  for (saa_rt::DevBuf* b : bufs)
+    if (b->p && b->bytes && hipMemsetAsync(b->p, 0xFF, b->bytes, c->st) != hipSuccess) return SAA_E_DEVICE;
+  return SAA_OK;
 }
 
 // The risk reduction of `opt` over (q, g): CVaR (t* search, eq. (CVaR_saa_ouu))
@@ -568,6 +591,7 @@ int ctx_create3(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ctx**
   if (N_max < 1 || N_max > max_samples3d(p->n)) return SAA_E_INVALID;
 
   saa_ctx* c = new (std::nothrow) saa_ctx();
+  if (c) c->poison = poison_requested();
   if (!c) return SAA_E_OOM;
   c->prob = *p;
   c->N_max = N_max;
@@ -851,6 +875,7 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   if (N_max < 1 || N_max > kMaxSamples2D) return SAA_E_INVALID;
 
   saa_ctx* c = new (std::nothrow) saa_ctx();
+  if (c) c->poison = poison_requested();
   if (!c) return SAA_E_OOM;
   c->prob = *p;
   c->N_max = N_max;
@@ -1046,6 +1071,7 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
   const auto t0 = std::chrono::steady_clock::now();
   if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
     return rc;
+  if ((rc = poison_workspaces(c))) return rc;
   PhaseTimer& tm = c->timer;
   tm.on = opt->timing != 0;
   tm.mark(c->st, 0);
@@ -1183,6 +1209,7 @@ int saa_per_sample(saa_ctx* c, const double* z, int form, const void* model, con
   const auto t0 = std::chrono::steady_clock::now();
   if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
     return rc;
+  if ((rc = poison_workspaces(c))) return rc;
   if (form == SAA_FORM_PDE) {
     const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
     if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;

@@ -183,6 +183,7 @@ struct saa_ctx {
   saa_rt::DevBuf order;       // KL modes by increasing |k|^2 (ties lexicographic), K1^dim entries
   saa_rt::PhaseTimer timer;
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)
+  bool poison = false;         // fill the per-call workspaces with NaN before each call (SAA_POISON_WORKSPACE)
   SurrogateGraph sg;
   double* out() { return (double*)res.p; }
   double* tstar() { return (double*)res.p + RES_T; }
