@@ -51,8 +51,10 @@ void tridiagonalize(int n, double* A, double* d, double* e) {
     for (int j = 0; j < k; ++j) a(k, j) = v[j];   // keep u for the accumulation
     d[k] = h;
   }
-  e[1] = (n > 1) ? a(1, 0) : 0.0;
-  if (n > 1) d[1] = 0.0;
+  if (n > 1) {   // (for n = 1 there is no entry (1, 0): d and e hold one element)
+    e[1] = a(1, 0);
+    d[1] = 0.0;
+  }
   d[0] = 0.0;
   e[0] = 0.0;
   // accumulate Q = H_{n-1} ... H_2 applied to the identity, innermost first
