@@ -278,12 +278,12 @@ int poison_workspaces(saa_ctx* c) {
 void reduce(saa_ctx* c, const double* q, const double* g, const saa_options* opt, int phase, const int* newton,
             const int* lin, const int* flag, const int* lin_adj, const int* did, void* stats) {
   if (opt->risk == SAA_RISK_CVAR)
-    saa_launch::cvar(q, g, c->N, c->dz, opt->beta, opt->eps, opt->alpha, (double*)c->zdev.p, opt->t_mode,
+    saa_launch::cvar(q, g, c->N, c->dz, opt->beta, opt->eps, opt->alpha, c->zd(), opt->t_mode,
                      opt->t_in, phase, c->tstar(), c->out(), newton, lin, flag, lin_adj, did, stats, c->cwork.p,
                      c->st);
   else
     saa_launch::risk(q, g, c->N, c->dz, opt->risk, opt->eps, opt->risk_kappa, opt->risk_tau, opt->alpha,
-                     (double*)c->zdev.p, phase, c->tstar(), c->out(), newton, lin, flag, lin_adj, did, stats,
+                     c->zd(), phase, c->tstar(), c->out(), newton, lin, flag, lin_adj, did, stats,
                      c->cwork.p, c->st);
 }
 
@@ -1021,16 +1021,17 @@ int saa_set_samples(saa_ctx* c, int64_t N, const double* xi_dev) {
 // Device work of one MR-DINO evaluation on c->st: control bias, fused network
 // kernel (q and dq/dz of every sample), CVaR reduction.
 static int surrogate_work(saa_ctx* c, mrdino_model* m, const saa_options* opt) {
-  int rc = saa_model_eval(m, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p, (double*)c->g.p);
+  int rc = saa_model_eval(m, c, c->zd(), opt->prec, (double*)c->q.p, (double*)c->g.p);
   if (rc) return rc;
   reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 3, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats());
   return check_hip(hipGetLastError());
 }
 
-// Capture surrogate_work into c->sg (kernel nodes only: z is uploaded and the
-// results are copied outside the graph).  The capture runs on a stream of the
-// context, since the caller's may be the legacy stream; a failure leaves the
-// context evaluating eagerly.
+// Capture surrogate_work into c->sg (kernel nodes only).  The captured kernels
+// read z from the pinned host buffer hz and write the result block straight
+// into the pinned host buffer hres, so a replay needs no copy before or after
+// it.  The capture runs on a stream of the context, since the caller's may be
+// the legacy stream; a failure leaves the context evaluating eagerly.
 static int capture_surrogate(saa_ctx* c, mrdino_model* m, const saa_options* opt,
                              const SurrogateGraph::Key& key) {
   SurrogateGraph& sg = c->sg;
@@ -1041,8 +1042,14 @@ static int capture_surrogate(saa_ctx* c, mrdino_model* m, const saa_options* opt
     (void)hipGetLastError();
     return SAA_OK;
   }
+  if (!c->hz.p && c->hz.alloc(sizeof(double) * SAA_MAX_DZ)) {
+    sg.disabled = true;
+    return SAA_OK;
+  }
   hipStream_t user = c->st;
   c->st = sg.cap;
+  c->z_over = (const double*)c->hz.p;
+  c->res_over = c->hres.p;
   hipGraph_t graph = nullptr;
   int rc = SAA_OK;
   hipError_t e = hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal);
@@ -1051,6 +1058,8 @@ static int capture_surrogate(saa_ctx* c, mrdino_model* m, const saa_options* opt
     e = hipStreamEndCapture(sg.cap, &graph);
   }
   c->st = user;
+  c->z_over = nullptr;
+  c->res_over = nullptr;
   if (e == hipSuccess && graph && !rc) e = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc || e != hipSuccess || !sg.exec) {
@@ -1069,13 +1078,35 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
   int rc = validate_call(c, z, form, model, opt);
   if (rc) return rc;
   const auto t0 = std::chrono::steady_clock::now();
-  if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice, c->st))))
-    return rc;
-  if ((rc = poison_workspaces(c))) return rc;
   PhaseTimer& tm = c->timer;
   tm.on = opt->timing != 0;
+  // surrogate: q and dq/dz of every sample in one fused launch, then the
+  // reduction.  The second evaluation with the same arguments captures this
+  // device work in a hipGraph; later ones replay it (untimed calls only),
+  // with z and the results in pinned host memory.
+  mrdino_model* m = (mrdino_model*)model;
+  SurrogateGraph& sg = c->sg;
+  SurrogateGraph::Key key{};
+  bool replay = false;
+  if (form == SAA_FORM_MRDINO) {
+    key = SurrogateGraph::Key{m->serial, m->version, opt->prec,  opt->t_mode,     opt->beta,
+                              opt->eps,   opt->alpha,  opt->t_in, c->N,            opt->risk,
+                              opt->risk_kappa, opt->risk_tau};
+    const bool enc_ready = opt->prec == SAA_FP32 || c->enc_rm == enc_key(m->dims.r_m, m->kin);
+    if (!tm.on && !sg.disabled && !(sg.exec && sg.key == key) && sg.seen == key && enc_ready &&
+        (rc = capture_surrogate(c, m, opt, key)))
+      return rc;
+    replay = !tm.on && sg.exec && sg.key == key;
+  }
+  if (replay) {
+    std::memcpy(c->hz.p, z, sizeof(double) * c->dz);
+    if (c->poison) std::memset(c->hres.p, 0xFF, RES_BYTES);
+  } else if ((rc = check_hip(hipMemcpyAsync(c->zdev.p, z, sizeof(double) * c->dz, hipMemcpyHostToDevice,
+                                            c->st)))) {
+    return rc;
+  }
+  if ((rc = poison_workspaces(c))) return rc;
   tm.mark(c->st, 0);
-  int graph_used = 0;
   if (form == SAA_FORM_PDE) {
     const SolveParams sp = solve_params(opt, opt->prec == SAA_FP32);
     if ((rc = run_state(c, opt->prec, (const double*)c->zdev.p, 0, sp))) return rc;
@@ -1086,41 +1117,27 @@ static int objective_grad_impl(saa_ctx* c, const double* z, int form, const void
     tm.mark(c->st, 3);
     reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 2, (int*)c->newton.p, (int*)c->lin.p, (int*)c->flag.p,
            (int*)c->lin_adj.p, (int*)c->did.p, c->stats());
+  } else if (replay) {
+    if ((rc = check_hip(hipGraphLaunch(sg.exec, c->st)))) return rc;
   } else {
-    // surrogate: q and dq/dz of every sample in one fused launch, then the
-    // reduction.  The second evaluation with the same arguments captures this
-    // device work in a hipGraph; later ones replay it (untimed calls only).
-    mrdino_model* m = (mrdino_model*)model;
-    SurrogateGraph& sg = c->sg;
-    const SurrogateGraph::Key key{m->serial, m->version, opt->prec,  opt->t_mode,     opt->beta,
-                                  opt->eps,   opt->alpha,  opt->t_in, c->N,            opt->risk,
-                                  opt->risk_kappa, opt->risk_tau};
-    const bool enc_ready = opt->prec == SAA_FP32 || c->enc_rm == enc_key(m->dims.r_m, m->kin);
-    if (!tm.on && !sg.disabled && !(sg.exec && sg.key == key) && sg.seen == key && enc_ready &&
-        (rc = capture_surrogate(c, m, opt, key)))
+    if ((rc = saa_model_eval(m, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p, (double*)c->g.p)))
       return rc;
-    if (!tm.on && sg.exec && sg.key == key) {
-      if ((rc = check_hip(hipGraphLaunch(sg.exec, c->st)))) return rc;
-      graph_used = 1;
-    } else {
-      if ((rc = saa_model_eval(m, c, (const double*)c->zdev.p, opt->prec, (double*)c->q.p, (double*)c->g.p)))
-        return rc;
-      tm.mark(c->st, 1);
-      tm.mark(c->st, 2);
-      tm.mark(c->st, 3);
-      reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 3, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats());
-      sg.seen = key;
-    }
+    tm.mark(c->st, 1);
+    tm.mark(c->st, 2);
+    tm.mark(c->st, 3);
+    reduce(c, (double*)c->q.p, (double*)c->g.p, opt, 3, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats());
+    sg.seen = key;
   }
   tm.mark(c->st, 4);
   if ((rc = check_hip(hipGetLastError()))) return rc;
-  if ((rc = fetch_results(c))) return rc;
+  // a replay has written the results to pinned host memory already
+  if ((rc = replay ? check_hip(hipStreamSynchronize(c->st)) : fetch_results(c))) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   const double* host = (const double*)c->hres.p;
   *J = host[0];
   for (int k = 0; k < c->dz; ++k) grad_z[k] = host[2 + k];
   rc = fill_report(c, rep, secs, &tm);
-  if (rep) rep->graph = graph_used;
+  if (rep) rep->graph = replay ? 1 : 0;
   return rc;
 }
 

@@ -185,7 +185,16 @@ struct saa_ctx {
   saa_ctx* holdout = nullptr;  // held-out samples for the surrogate error estimate (not owned)
   bool poison = false;         // fill the per-call workspaces with NaN before each call (SAA_POISON_WORKSPACE)
   SurrogateGraph sg;
-  double* out() { return (double*)res.p; }
-  double* tstar() { return (double*)res.p + RES_T; }
-  void* stats() { return (char*)res.p + RES_STATS; }
+  // The replayed surrogate graph reads z from, and writes its result block
+  // to, pinned host memory (hz, hres): no copies around the replay.  While it
+  // is captured these point there; otherwise they are null and the device
+  // buffers zdev, res are used.
+  saa_rt::HostBuf hz;         // pinned host copy of z for the graph (SAA_MAX_DZ doubles)
+  const double* z_over = nullptr;
+  void* res_over = nullptr;
+  const double* zd() const { return z_over ? z_over : (const double*)zdev.p; }
+  char* resb() { return (char*)(res_over ? res_over : res.p); }
+  double* out() { return (double*)resb(); }
+  double* tstar() { return (double*)resb() + RES_T; }
+  void* stats() { return resb() + RES_STATS; }
 };

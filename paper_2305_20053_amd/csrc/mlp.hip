@@ -205,12 +205,18 @@ __global__ void saa_k_add_pad(float* dst, const float* a, const float* b, int n,
 // through the first layer and is shared by all samples).  W0zT is the packed
 // transposed copy of those columns (d_z x width), so consecutive threads
 // read consecutive features.
-__global__ void saa_k_b0eff(float* b0eff, const float* W0zT, const float* b0, const double* z, int width, int d_z) {
+// z may live in pinned host memory (a replayed graph): the workgroup reads it
+// once into LDS.
+__global__ void __launch_bounds__(64) saa_k_b0eff(float* b0eff, const float* W0zT, const float* b0, const double* z,
+                                                 int width, int d_z) {
+  __shared__ float zs[64];
+  if (threadIdx.x < d_z) zs[threadIdx.x] = (float)z[threadIdx.x];
+  __syncthreads();
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= width) return;
   float acc = b0[f];
 #pragma unroll 8
-  for (int k = 0; k < d_z; ++k) acc += W0zT[(int64_t)k * width + f] * (float)z[k];
+  for (int k = 0; k < d_z; ++k) acc += W0zT[(int64_t)k * width + f] * zs[k];
   b0eff[f] = acc;
 }
 
