@@ -862,6 +862,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
   constexpr int NW = SBS / SAA_WAVE;
   __shared__ double red[5 * NW];
   __shared__ double col[NW][PSTRIDE];
+  __shared__ double zsh[SAA_WAVE];
   if (stats && !newton && !lin && !flag && !lin_adj && !did) {   // no per-sample solver (surrogate)
     if (threadIdx.x == 0) *stats = CvarStats{};
   } else if (stats) {
@@ -916,13 +917,14 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
     const int c = wid + NW * cc;
     if (lane == 0 && c < ncol) col[0][c] = a;
   }
-  __syncthreads();
   const int k = threadIdx.x;
   double zz = 0.0;
-  if (k < SAA_WAVE) {   // |z|^2 by the whole of wave 0, one load per lane
+  if (k < SAA_WAVE) {   // |z|^2 by the whole of wave 0, one load per lane (z may be in host memory)
     const double zl = k < dz ? z[k] : 0.0;
+    zsh[k] = zl;
     zz = fast_sum(zl * zl);
   }
+  __syncthreads();
   if (k >= ncol) return;
   const double acc = col[0][k];
   const double scale = 1.0 / target;   // 1 / (N (1 - beta)) for CVaR, else 1 / N
@@ -932,7 +934,7 @@ __global__ void __launch_bounds__(SBS) saa_k_cvar_final(int64_t N, int dz, CvarW
   } else if (k == 1) {
     out[1] = cv ? 1.0 - scale * acc : 0.0;
   } else {
-    out[k] = scale * acc + alpha * z[k - 2];
+    out[k] = scale * acc + alpha * zsh[k - 2];
   }
 }
 
