@@ -546,7 +546,7 @@ int saa_ouu_solve(saa_ctx* ctx, int form, const void* model, const saa_options* 
  * = t* (CVaR), the mean of q (mean + kappa Var), tau (probability of
  * failure), a* (buffered probability of exceedance) or 0 (mean).  Work is
  * enqueued on `hip_stream` (a hipStream_t, NULL = default); the library
- * allocates a workspace of about 4.4 MB for the call and synchronises the
+ * allocates a workspace of about 2.3 MB for the call and synchronises the
  * stream before releasing it.  SAA_E_INVALID (before any device work) for
  * null pointers, N outside 1 .. SAA_REDUCE_MAX_N, d_Z outside 1 ..
  * SAA_MAX_DZ (64) or invalid options; SAA_E_OOM, SAA_E_DEVICE on failure.
@@ -557,7 +557,7 @@ int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z
 /* saa_risk_reduce for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments, kernels and results, but the workspace is a static
- * device array of SAA_REDUCE_SCRATCH_BYTES (about 4.4 MB) that each GPU the
+ * device array of SAA_REDUCE_SCRATCH_BYTES (about 2.3 MB) that each GPU the
  * library runs on holds until the process ends.  Nothing is allocated or
  * freed and the stream is not synchronised: results are ready when the work
  * enqueued on `hip_stream` completes.  Every call on one GPU shares that
@@ -566,7 +566,7 @@ int saa_risk_reduce(const double* q_dev, const double* g_dev, int64_t N, int d_z
  * serialised by the caller.  Sizes beyond N = SAA_REDUCE_MAX_N or d_Z = 64
  * return SAA_E_INVALID before any device work; SAA_E_DEVICE if the
  * workspace's device address cannot be obtained or a launch fails. */
-#define SAA_REDUCE_SCRATCH_BYTES 4380704
+#define SAA_REDUCE_SCRATCH_BYTES 2283552
 int saa_risk_reduce_noalloc(const double* q_dev, const double* g_dev, int64_t N, int d_z, const double* z_dev,
                             const saa_options* opt, double* out_dev, double* t_dev, void* hip_stream);
 

@@ -31,8 +31,7 @@
 //     runs inside the bracket (bisection when a step leaves it or stalls),
 //     followed by one polish step; after an overflow, the root of the cubic
 //     through Phi at four points of the last refinement pass around the
-//     crossing.  With the value and gradient sums in the same call, the
-//     partial-sum pass does this step itself (no separate launch).
+//     crossing.
 // Every wave recomputes the bracket from the previous launches' results with
 // the same arithmetic, so all of them agree on it without a grid barrier.
 // For beta = 0 (target = N) every t <= min(q) - eps is a minimiser with the
@@ -60,8 +59,8 @@ constexpr int NP = 64;            // points per refinement pass (one per lane)
 constexpr int PP = 256;           // probes per bracketing pass (four per lane)
 constexpr int PPL = PP / 64;      // probes of one lane: 4 lane .. 4 lane + 3
 constexpr int PASSES = 2;         // bracketing passes (shrink ~128x each)
-constexpr int CAP = 8192;         // active-set capacity (doubles in LDS)
-constexpr int SEG = 2048;         // active-set capacity per workgroup
+constexpr int CAP = 1024;         // active-set capacity (doubles in LDS); larger sets take the refinement passes
+constexpr int SEG = 1024;         // active-set capacity per workgroup
 constexpr int GMAX = 256;         // workgroups of the multi-workgroup passes
 constexpr int TILE = 4 * RBS;     // samples per compaction tile
 constexpr int PSTRIDE = 2 + SAA_MAX_DZ;
@@ -72,7 +71,7 @@ constexpr int SLOTS = 8;          // copies of each atomic counter (workgroup b 
 
 // Workspace of one reduction: per-workgroup min / max and partial sums, the
 // active-set segments, the refinement sums, the probe histograms and the
-// active-set counters (about 4.4 MB, independent of N).
+// active-set counters (about 2.3 MB, independent of N).
 constexpr size_t kCvarWorkBytes =
     sizeof(double) * ((size_t)2 * GMAX + (size_t)GMAX * PSTRIDE + (size_t)GMAX * SEG) +
     sizeof(unsigned long long) * RPASSES * SLOTS * NP + sizeof(int) * ((size_t)PASSES * SLOTS * 2 * PP + 2 * GMAX + SLOTS);
@@ -624,9 +623,10 @@ __global__ void __launch_bounds__(RFB) saa_k_cvar_refine(const double* q, int64_
   }
 }
 
-// 4. t* (or t_in when t_mode = 1), by one workgroup of RBS threads; every
+// 4. t* (or t_in when t_mode = 1), by one workgroup of BSZ threads; every
 // thread returns the same value.  LDS: s holds CAP doubles, off GMAX + 1
-// ints, sh RBS / 64 ints, red 2 RBS / 64 doubles.
+// ints, sh BSZ / 64 ints, red 2 BSZ / 64 doubles.
+template <int BSZ>
 __device__ double cvar_tstar(const CvarWork& w, int64_t N, int G, double eps, double target, int t_mode,
                              double t_in, double* s, int* off, int* sh, double* red, double* sb) {
   const int lane = threadIdx.x & (SAA_WAVE - 1);
@@ -665,7 +665,7 @@ __device__ double cvar_tstar(const CvarWork& w, int64_t N, int G, double eps, do
   __syncthreads();
   double t = 0.5 * (br.lo + br.hi);   // (fits always holds here)
   if (fits) {
-    for (int r = threadIdx.x; r < n; r += RBS) {
+    for (int r = threadIdx.x; r < n; r += BSZ) {
       int a = 0, b = G;   // last workgroup with off <= r
       while (b - a > 1) {
         const int m = (a + b) >> 1;
@@ -682,34 +682,48 @@ __device__ double cvar_tstar(const CvarWork& w, int64_t N, int G, double eps, do
           a0 += sp_d1(s[i] - tc, eps, ie);
           a1 += sp_d2(s[i] - tc, eps, ie);
         }
-        v[0] = above + wave_sum(a0);
-        v[1] = wave_sum(a1);
+        v[0] = above + fast_sum(a0);
+        v[1] = fast_sum(a1);
       });
     } else {
       t = newton_in_bracket(br.lo, br.hi, target, [&](double tc, double* v) {
         double a[2] = {0.0, 0.0};
-        for (int i = threadIdx.x; i < n; i += RBS) {
+        for (int i = threadIdx.x; i < n; i += BSZ) {
           a[0] += sp_d1(s[i] - tc, eps, ie);
           a[1] += sp_d2(s[i] - tc, eps, ie);
         }
-        block_sum<2>(a, red);
-        v[0] = above + a[0];
-        v[1] = a[1];
+        // block sums: DPP within each wave, then the waves in order
+        constexpr int NW = BSZ / SAA_WAVE;
+        a[0] = fast_sum(a[0]);
+        a[1] = fast_sum(a[1]);
+        if (lane == 0) {
+          red[threadIdx.x / SAA_WAVE] = a[0];
+          red[NW + threadIdx.x / SAA_WAVE] = a[1];
+        }
+        __syncthreads();
+        double s0 = 0.0, s1 = 0.0;
+        for (int k = 0; k < NW; ++k) {
+          s0 += red[k];
+          s1 += red[NW + k];
+        }
+        __syncthreads();
+        v[0] = above + s0;
+        v[1] = s1;
       });
     }
   }
   return t;
 }
 
-// t* -> tstar[0] (used when the adjoints need t* before the partial sums).
-__global__ void __launch_bounds__(RBS) saa_k_cvar_solve(int64_t N, CvarWork w, int G, double eps, double target,
+// t* -> tstar[0].
+__global__ void __launch_bounds__(SBS) saa_k_cvar_solve(int64_t N, CvarWork w, int G, double eps, double target,
                                                         int t_mode, double t_in, double* tstar) {
-  __shared__ double red[2 * (RBS / SAA_WAVE)];
+  __shared__ double red[2 * (SBS / SAA_WAVE)];
   __shared__ int off[GMAX + 1];
-  __shared__ int sh[RBS / SAA_WAVE];
+  __shared__ int sh[SBS / SAA_WAVE];
   __shared__ double s[CAP];
   __shared__ double sb[4];
-  const double t = cvar_tstar(w, N, G, eps, target, t_mode, t_in, s, off, sh, red, sb);
+  const double t = cvar_tstar<SBS>(w, N, G, eps, target, t_mode, t_in, s, off, sh, red, sb);
   if (threadIdx.x == 0) tstar[0] = t;
 }
 
@@ -757,40 +771,26 @@ __device__ __forceinline__ void risk_terms(double qi, double t, double eps, doub
 // 5. per-workgroup partial sums: sum v, sum d, sum d dq/dz (see risk_terms).
 // The weighted samples of each tile are listed in LDS; wave k of the block
 // then takes every (RBS/64)-th of them with lane c accumulating component c.
-// SOLVE (CVaR, t and the sums in one call): every workgroup first finds t*
-// itself (the same arithmetic as saa_k_cvar_solve, so the same value), and
-// workgroup 0 stores it; otherwise t is read from tstar[0].
-template <int KIND, bool SOLVE>
+template <int KIND>
 __global__ void __launch_bounds__(RBS) saa_k_cvar_part(const double* q, const double* g, int64_t N, int dz,
                                                        CvarWork w, int G, double eps, double kappa, double tau,
-                                                       double* tstar, double target, int t_mode, double t_in) {
+                                                       const double* tstar) {
   __shared__ double red[2 * (RBS / SAA_WAVE)];
   __shared__ int sh[RBS / SAA_WAVE];
   __shared__ int li[TILE];
   __shared__ double lw[TILE];
   __shared__ double gw[RBS / SAA_WAVE][SAA_WAVE];
-  __shared__ double st[SOLVE ? CAP : 1];
-  __shared__ int soff[SOLVE ? GMAX + 1 : 1];
-  __shared__ double sb[4];
   const int lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
   int64_t i0, i1;
   chunk_of(N, G, i0, i1);
-  // the first tile's q is loaded before t is known (its latency overlaps the
-  // t* computation)
+  // the first tile's q is loaded before t (its latency overlaps that of t)
   double qv[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t i = i0 + 4 * threadIdx.x + r;
     qv[r] = i < i1 ? q[i] : 0.0;
   }
-  double t;
-  if constexpr (SOLVE) {
-    t = cvar_tstar(w, N, G, eps, target, t_mode, t_in, st, soff, sh, red, sb);
-    if (blockIdx.x == 0 && threadIdx.x == 0) tstar[0] = t;
-    __syncthreads();   // sh and red are reused below
-  } else {
-    t = tstar[0];
-  }
+  const double t = tstar[0];
   const double ie = 1.0 / eps;
   double v[2] = {0.0, 0.0};
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1082,15 +1082,9 @@ void cvar(const double* q, const double* g, int64_t N, int dz, double beta, doub
       saa_k_cvar_compact<<<G, RBS, 0, st>>>(q, N, w, G, eps, target);
       for (int r = 0; r < RPASSES; ++r) saa_k_cvar_refine<<<G, RFB, 0, st>>>(q, N, w, G, r, eps, target);
     }
-    // with the sums in the same call, the partial-sum pass finds t* itself
-    if (!(phase & 2)) saa_k_cvar_solve<<<1, RBS, 0, st>>>(N, w, G, eps, target, t_mode, t_in, tstar);
+    saa_k_cvar_solve<<<1, SBS, 0, st>>>(N, w, G, eps, target, t_mode, t_in, tstar);
   }
-  if ((phase & 3) == 3)
-    saa_k_cvar_part<SAA_RISK_CVAR, true><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar, target, t_mode,
-                                                           t_in);
-  else if (phase & 2)
-    saa_k_cvar_part<SAA_RISK_CVAR, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar, target, 0,
-                                                            0.0);
+  if (phase & 2) saa_k_cvar_part<SAA_RISK_CVAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, 0.0, 0.0, tstar);
   if ((phase & 2) || stats)
     saa_k_cvar_final<<<1, SBS, 0, st>>>(N, dz, w, G, target, SAA_RISK_CVAR, alpha, z, tstar, (phase & 2) ? 1 : 0,
                                         out, newton, lin, flag, lin_adj, did, (CvarStats*)stats);
@@ -1116,20 +1110,16 @@ void risk(const double* q, const double* g, int64_t N, int dz, int kind, double 
   if (phase & 2) {
     switch (kind) {
       case SAA_RISK_MEAN:
-        saa_k_cvar_part<SAA_RISK_MEAN, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
-                                                            0.0);
+        saa_k_cvar_part<SAA_RISK_MEAN><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
         break;
       case SAA_RISK_MEAN_VAR:
-        saa_k_cvar_part<SAA_RISK_MEAN_VAR, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
-                                                            0.0);
+        saa_k_cvar_part<SAA_RISK_MEAN_VAR><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
         break;
       case SAA_RISK_POF:
-        saa_k_cvar_part<SAA_RISK_POF, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
-                                                            0.0);
+        saa_k_cvar_part<SAA_RISK_POF><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
         break;
       default:
-        saa_k_cvar_part<SAA_RISK_BPOE, false><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar, 0.0, 0,
-                                                            0.0);
+        saa_k_cvar_part<SAA_RISK_BPOE><<<G, RBS, 0, st>>>(q, g, N, dz, w, G, eps, kappa, tau, tstar);
     }
   }
   if ((phase & 2) || stats)
