@@ -18,7 +18,7 @@ struct MlpDev {
   // order), stored back to back in the order the kernel reads them:
   // wp[0..depth], wt[depth..1], w0z.
   const void* ws;                        // the whole weight stream (BF16)
-  const void* ws8;                       // the same in FP8 (E4M3), 512 B per fragment
+  const void* ws8;                       // the same in FP8 (E4M3), 16 x 128 fragments of 2 KB
   const float* wsc_inv;                  // FP8: 1 / scale of each operand, stream order
   int64_t ws_frags;                      // its length in 1 KB fragments
   const void* wp[MLP_MAX_DEPTH + 1];     // forward: rows = outputs, cols = inputs

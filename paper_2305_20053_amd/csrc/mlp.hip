@@ -7,7 +7,8 @@
 //   dq/dz by reverse mode: delta = 2 (phi + c), back through the layers with
 //   GELU'(a_L), and finally the control columns of W_0.
 //
-// MFMA kernel (v_mfma_f32_16x16x32_bf16, or _fp8_fp8; FP32 accumulation).
+// MFMA kernel (v_mfma_f32_16x16x32_bf16, or v_mfma_scale_f32_16x16x128_f8f6f4
+// on E4M3 operands; FP32 accumulation).
 // Products are formed transposed, C = W_L * H^T: output features run along
 // the MFMA M dimension and samples along N, so one lane holds, for its sample,
 // 4 consecutive features of every 16-feature tile.  That accumulator layout is
@@ -34,6 +35,8 @@
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef long i64x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -77,13 +80,18 @@ __device__ __forceinline__ float dgelu_f(float a) {
   return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * 0.39894228040143268f * __expf(-0.5f * a * a);
 }
 
-// Operand formats of the fused kernel.  Both use a 16 x 16 x 32 MFMA with the
-// same lane layout (lane 16 g + c: row / column c, k = 8 g .. 8 g + 8):
-//  OpBF16: BF16 values, 1 KB per 16 x 32 fragment;
-//  OpFP8:  FP8 (E4M3) values, 512 B per fragment.  Weights carry a power-of-two
-//          scale per operand, activations one per sample (from the largest
-//          magnitude of the sample's 256 features), both undone in FP32 after
-//          the product, so only the 3-bit mantissa rounding remains.
+// Operand formats of the fused kernel.  Outputs are exchanged through LDS
+// as 16 x 32 blocks (lane 16 g + c: row / column c, k = 8 g .. 8 g + 8):
+//  OpBF16: BF16 values, 1 KB per block, one v_mfma_f32_16x16x32_bf16 per
+//          block;
+//  OpFP8:  FP8 (E4M3) values, 512 B per block; one
+//          v_mfma_scale_f32_16x16x128_f8f6f4 takes four consecutive blocks
+//          (a lane's 32 bytes are its 8 bytes of each, in order; the weight
+//          copy stores them contiguously, 2 KB per 16 x 128 fragment).
+//          Weights carry a power-of-two scale per operand, activations one
+//          per sample (from the largest magnitude of the sample's features);
+//          the MFMA undoes both through its E8M0 operand scales, so only the
+//          3-bit mantissa rounding remains.
 struct OpBF16 {
   typedef bf16x8 vec;
   static constexpr int FB = 1024;
@@ -100,8 +108,9 @@ struct OpFP8 {
   typedef long vec;
   static constexpr int FB = 512;
   static constexpr bool scaled = true;
-  __device__ static f32x4 mma(vec a, vec b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  // sa, sb: E8M0 scale (2^(s - 127)) of the lane's A row / B column
+  __device__ static f32x4 mma4(i32x8 a, i32x8 b, f32x4 c, int sa, int sb) {
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
   }
   __device__ static vec pack(const float (&v)[8], float s) {
     int lo = 0, hi = 0;
@@ -113,15 +122,16 @@ struct OpFP8 {
   }
 };
 
-// Power of two s with m s in [128, 256) (1 for m = 0): the FP8 operand scale
-// of values of largest magnitude m (E4M3 holds magnitudes up to 448).
-__device__ __forceinline__ float pow2_scale(float m, float top) {
-  if (!(m > 0.0f) || !(m < INFINITY)) return 1.0f;
+// Exponent e of the power of two s = 2^e with m s in [top / 2, top) (0 for
+// m = 0), clamped to [-60, 60]: the FP8 operand scale of values of largest
+// magnitude m (E4M3 holds magnitudes up to 448).
+__device__ __forceinline__ int pow2_exp(float m, float top) {
+  if (!(m > 0.0f) || !(m < INFINITY)) return 0;
   int e;
   (void)frexpf(top / m, &e);
-  e = e - 1 < -60 ? -60 : (e - 1 > 60 ? 60 : e - 1);
-  return ldexpf(1.0f, e);
+  return e - 1 < -60 ? -60 : (e - 1 > 60 ? 60 : e - 1);
 }
+__device__ __forceinline__ float pow2_scale(float m, float top) { return ldexpf(1.0f, pow2_exp(m, top)); }
 
 }  // namespace
 
@@ -232,7 +242,10 @@ __global__ void __launch_bounds__(64) saa_k_b0eff(float* b0eff, const float* W0z
 // needs it in the reverse pass.  Two waves per SIMD let one wave's GELU
 // epilogue overlap the other's MFMAs.
 // FP8: the activations of a sample share one power-of-two scale; each wave
-// posts its per-sample maximum in LDS before the publishing barrier.
+// posts its per-sample maximum in LDS before the publishing barrier.  A
+// product takes four 16 x 32 blocks per MFMA (16 x 16 x 128), the A operand
+// from the 2 KB fragments of the FP8 stream, the B operand gathered from the
+// four blocks in LDS; the scales travel as the MFMA's E8M0 operand scales.
 // ---------------------------------------------------------------------------
 template <int W, int KIN, int DEPTH, int NZT, int WAVES, int SB, class OP>
 __global__ void __launch_bounds__(WAVES * 64, 1)
@@ -253,9 +266,9 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   float* qs = (float*)lds;                                       // [MT][SB][16] (reuses act)
   const int64_t base = (int64_t)blockIdx.x * (16 * SB);
   f32x4 acc[MW][SB];
-  float ax[SB];                          // scale of the current B operands, per sample block (FP8)
+  int axe[SB];                           // FP8: exponent of the current B operands' scale, per sample block
 #pragma unroll
-  for (int sb = 0; sb < SB; ++sb) ax[sb] = 1.0f;
+  for (int sb = 0; sb < SB; ++sb) axe[sb] = 0;
   // operand k of the stream in this format (the FP8 copy has 512-byte fragments)
   auto operand = [&](const void* bf16_op) -> const char* {
     if constexpr (OP::scaled)
@@ -264,48 +277,92 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       return (const char*)bf16_op;
   };
 
+  // E8M0 scales that undo the FP8 scalings: operand `op` of the weight
+  // stream (A), and the activations of sample block sb (B)
+  auto a_scale = [&](int op) -> int {
+    int e;
+    (void)frexpf(net.wsc_inv[op], &e);   // wsc_inv = 2^(e - 1)
+    return 126 + e;
+  };
+  auto b_scale = [&](int sb) -> int { return 127 - axe[sb]; };
+  // B operand of the 16 x 16 x 128 MFMA: this lane's bytes of blocks 4 k4 .. 4 k4 + 3
+  auto b_quad = [&](int sb, int k4) -> i32x8 {
+    const long* a8 = (const long*)act + (sb * KS + 4 * k4) * 64 + ln;
+    const i64x4 v = {a8[0], a8[64], a8[128], a8[192]};
+    return __builtin_bit_cast(i32x8, v);
+  };
+
   // acc += A(MW wv + j, ks) B(sb, ks); A fragment (ks, mt) of an operand with
   // mtx row tiles at A + (ks mtx + mt) FB bytes; B from act, or (BF16) from
-  // the encoded input for layer 0
-  auto product = [&](const char* A, int mtx, int nks, bool from_input) {
+  // the encoded input for layer 0.  FP8: 16 x 128 fragments (k4, mt) at
+  // A + (k4 mtx + mt) 4 FB bytes; `op` is the operand's index in the stream.
+  auto product = [&](const char* A, int mtx, int nks, bool from_input, int op) {
 #pragma unroll
     for (int j = 0; j < MW; ++j)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc[j][sb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const char* Aw = A + (size_t)(MW * wv) * FB + ln * (FB / 64);
-    vec a[3][MW];
+    if constexpr (OP::scaled) {
+      constexpr int KS4 = KS / 4;
+      const int nk4 = nks / 4;
+      const int sa = a_scale(op);
+      int sbv[SB];
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+      for (int sb = 0; sb < SB; ++sb) sbv[sb] = b_scale(sb);
+      const char* Aw = A + (size_t)(MW * wv) * (4 * FB) + ln * 32;
+      i32x8 a[2][MW];
 #pragma unroll
-      for (int j = 0; j < MW; ++j)
-        if (p < nks) a[p][j] = *(const vec*)(Aw + (size_t)(p * mtx + j) * FB);
+      for (int j = 0; j < MW; ++j) a[0][j] = *(const i32x8*)(Aw + (size_t)j * (4 * FB));
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      if (ks < nks) {
-        if (ks + 2 < nks) {
+      for (int k4 = 0; k4 < KS4; ++k4) {
+        if (k4 < nk4) {
+          if (k4 + 1 < nk4) {
 #pragma unroll
-          for (int j = 0; j < MW; ++j) a[(ks + 2) % 3][j] = *(const vec*)(Aw + (size_t)((ks + 2) * mtx + j) * FB);
-        }
-        vec b[SB];
-#pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
-          if (!OP::scaled && from_input) {
-            const int64_t smp = base + 16 * sb + c16;
-            b[sb] = vec{};
-            if (smp < N) b[sb] = *(const vec*)(xenc + smp * KIN + 32 * ks + 8 * g);
-          } else {
-            b[sb] = act[(sb * KS + ks) * 64 + ln];
+            for (int j = 0; j < MW; ++j)
+              a[(k4 + 1) & 1][j] = *(const i32x8*)(Aw + (size_t)((k4 + 1) * mtx + j) * (4 * FB));
           }
+          i32x8 b[SB];
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) b[sb] = b_quad(sb, k4);
+#pragma unroll
+          for (int j = 0; j < MW; ++j)
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) acc[j][sb] = OP::mma4(a[k4 & 1][j], b[sb], acc[j][sb], sa, sbv[sb]);
         }
+      }
+    } else {
+      const char* Aw = A + (size_t)(MW * wv) * FB + ln * (FB / 64);
+      vec a[3][MW];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int j = 0; j < MW; ++j)
+          if (p < nks) a[p][j] = *(const vec*)(Aw + (size_t)(p * mtx + j) * FB);
 #pragma unroll
-          for (int sb = 0; sb < SB; ++sb) acc[j][sb] = OP::mma(a[ks % 3][j], b[sb], acc[j][sb]);
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks < nks) {
+          if (ks + 2 < nks) {
+#pragma unroll
+            for (int j = 0; j < MW; ++j) a[(ks + 2) % 3][j] = *(const vec*)(Aw + (size_t)((ks + 2) * mtx + j) * FB);
+          }
+          vec b[SB];
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) {
+            if (!OP::scaled && from_input) {
+              const int64_t smp = base + 16 * sb + c16;
+              b[sb] = vec{};
+              if (smp < N) b[sb] = *(const vec*)(xenc + smp * KIN + 32 * ks + 8 * g);
+            } else {
+              b[sb] = act[(sb * KS + ks) * 64 + ln];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < MW; ++j)
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) acc[j][sb] = OP::mma(a[ks % 3][j], b[sb], acc[j][sb]);
+        }
       }
     }
   };
-  // 1 / (weight scale x activation scale) of product `op` for sample block sb
-  auto unscale = [&](int op, int sb) -> float { return OP::scaled ? net.wsc_inv[op] / ax[sb] : 1.0f; };
   // publish this wave's outputs (acc holds them) as B fragments of k-steps KW wv ..
   auto publish = [&]() {
     if constexpr (OP::scaled) {   // per-sample maxima of this wave's features
@@ -327,7 +384,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       for (int sb = 0; sb < SB; ++sb) {
         float m = 0.0f;
         for (int w = 0; w < WAVES; ++w) m = fmaxf(m, smax[(w * SB + sb) * 16 + c16]);
-        ax[sb] = pow2_scale(m, 256.0f);
+        axe[sb] = pow2_exp(m, 256.0f);
       }
     }
 #pragma unroll
@@ -337,7 +394,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
         const float e[8] = {acc[2 * jp][sb][0],     acc[2 * jp][sb][1],     acc[2 * jp][sb][2],
                             acc[2 * jp][sb][3],     acc[2 * jp + 1][sb][0], acc[2 * jp + 1][sb][1],
                             acc[2 * jp + 1][sb][2], acc[2 * jp + 1][sb][3]};
-        act[(sb * KS + KW * wv + jp) * 64 + ln] = OP::pack(e, ax[sb]);
+        act[(sb * KS + KW * wv + jp) * 64 + ln] = OP::pack(e, ldexpf(1.0f, axe[sb]));
       }
     __syncthreads();
   };
@@ -368,18 +425,17 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
   for (int L = 0; L < DEPTH; ++L) {
     const float* bl = (L == 0) ? net.b0eff : net.bias[L];
-    product(operand(net.wp[L]), MT, L == 0 ? KS1 : KS, L == 0);
+    product(operand(net.wp[L]), MT, L == 0 ? KS1 : KS, L == 0, L);
 #pragma unroll
     for (int j = 0; j < MW; ++j) {
       const float4 b4 = *(const float4*)(bl + 16 * (MW * wv + j) + 4 * g);
       const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
-        const float cs = unscale(L, sb);
         f16x4 d4;
         float av[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) av[r] = OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r];
+        for (int r = 0; r < 4; ++r) av[r] = acc[j][sb][r] + bb[r];
         float hv[4];
         _Float16 dv[4];
         gelu_pair2(av[0], av[1], hv[0], hv[1], dv[0], dv[1]);
@@ -394,7 +450,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   }
   // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
   {
-    product(operand(net.wp[DEPTH]), MT, KS, false);
+    product(operand(net.wp[DEPTH]), MT, KS, false, DEPTH);
     // |phi + c|^2 as per-tile partial sums (16 features: a lane's 4 rows,
     // then across the 4 row groups), added in tile order by one wave, so the
     // result does not depend on how the tiles are split over the waves
@@ -406,11 +462,10 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
-        const float cs = unscale(DEPTH, sb);
         qp[j][sb] = 0.0f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float v = OP::scaled ? fmaf(acc[j][sb][r], cs, bb[r]) : acc[j][sb][r] + bb[r];
+          const float v = acc[j][sb][r] + bb[r];
           qp[j][sb] += v * v;
           acc[j][sb][r] = 2.0f * v;
         }
@@ -437,15 +492,14 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   // reverse pass: delta h_{L-1} = W_L^T delta a_L; delta a_{L-1} = GELU'(a_{L-1}) delta h_{L-1}
 #pragma unroll
   for (int L = DEPTH; L >= 1; --L) {
-    product(operand(net.wt[L]), MT, KS, false);
+    product(operand(net.wt[L]), MT, KS, false, DEPTH + 1 + (DEPTH - L));
 #pragma unroll
     for (int j = 0; j < MW; ++j)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
-        const float cs = unscale(DEPTH + 1 + (DEPTH - L), sb);
         const f16x4 d4 = *(const f16x4*)(myg + ((((L - 1) * MW + j) * SB + sb) * 64 + ln) * 4);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[j][sb][r] = (OP::scaled ? acc[j][sb][r] * cs : acc[j][sb][r]) * (float)d4[r];
+        for (int r = 0; r < 4; ++r) acc[j][sb][r] *= (float)d4[r];
       }
     publish();
   }
@@ -454,34 +508,46 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     f32x4 az[SB];
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) az[sb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const char* Aw = operand(net.w0z) + (size_t)wv * FB + ln * (FB / 64);
+    if constexpr (OP::scaled) {
+      const char* Aw = operand(net.w0z) + (size_t)wv * (4 * FB) + ln * 32;
+      const int sa = a_scale(2 * DEPTH + 1);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const vec a = *(const vec*)(Aw + (size_t)(ks * NZT) * FB);
+      for (int k4 = 0; k4 < KS / 4; ++k4) {
+        const i32x8 a = *(const i32x8*)(Aw + (size_t)(k4 * NZT) * (4 * FB));
 #pragma unroll
-      for (int sb = 0; sb < SB; ++sb) az[sb] = OP::mma(a, act[(sb * KS + ks) * 64 + ln], az[sb]);
+        for (int sb = 0; sb < SB; ++sb) az[sb] = OP::mma4(a, b_quad(sb, k4), az[sb], sa, b_scale(sb));
+      }
+    } else {
+      const char* Aw = operand(net.w0z) + (size_t)wv * FB + ln * (FB / 64);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const vec a = *(const vec*)(Aw + (size_t)(ks * NZT) * FB);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) az[sb] = OP::mma(a, act[(sb * KS + ks) * 64 + ln], az[sb]);
+      }
     }
     const int d_z = net.d_z;
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
-      const float cs = unscale(2 * DEPTH + 1, sb);
       const int64_t smp = base + 16 * sb + c16;
       if (smp < N)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int zi = 16 * wv + 4 * g + r;
-          if (zi < d_z) g_out[smp * d_z + zi] = (double)(OP::scaled ? az[sb][r] * cs : az[sb][r]);
+          if (zi < d_z) g_out[smp * d_z + zi] = (double)az[sb][r];
         }
     }
   }
 }
 
 // FP8 copy of the BF16 weights: every operand scaled by its own power of
-// two (largest magnitude -> [112, 224)).  Operand k spans fragments
-// [off[k], off[k + 1]); one workgroup per operand finds its scale.
+// two (largest magnitude -> [112, 224)).  Operand k spans 16 x 32 blocks
+// [off[k], off[k + 1]) of the BF16 stream, with mtx[k] row tiles; one
+// workgroup per operand finds its scale.
 struct OpRanges {
   int n;
   int64_t off[2 * MLP_MAX_DEPTH + 3];
+  int mtx[2 * MLP_MAX_DEPTH + 2];
 };
 
 __global__ void __launch_bounds__(256) saa_k_op_scale(const __bf16* ws, OpRanges ops, float* wsc_inv) {
@@ -499,16 +565,25 @@ __global__ void __launch_bounds__(256) saa_k_op_scale(const __bf16* ws, OpRanges
   }
 }
 
+// The FP8 stream holds each operand in 16 x 128 fragments (k4, mt) of 2 KB
+// at (k4 mtx + mt) 2 KB from the operand's start (the same start as in
+// 512-byte blocks): lane l's 32 bytes are its 8 values of the 16 x 32 blocks
+// (4 k4 + t, mt), t = 0..3, in order.  Four bytes per thread.
 __global__ void saa_k_pack_fp8(const __bf16* ws, OpRanges ops, const float* wsc_inv, int64_t n, uint8_t* dst) {
   const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (t >= n) return;
   const int64_t f = t / 512;
   int k = 0;
   while (k + 1 < ops.n && ops.off[k + 1] <= f) ++k;
+  const int64_t rel = t - ops.off[k] * 512;
+  const int64_t F = rel / 2048;
+  const int within = (int)(rel % 2048), lane = within / 32, byte = within % 32;
+  const int64_t k4 = F / ops.mtx[k], mt = F % ops.mtx[k];
+  const int64_t src = (ops.off[k] + (4 * k4 + byte / 8) * ops.mtx[k] + mt) * 512 + lane * 8 + byte % 8;
   const float sc = 1.0f / wsc_inv[k];
   int v = 0;
-  v = __builtin_amdgcn_cvt_pk_fp8_f32((float)ws[t] * sc, (float)ws[t + 1] * sc, v, false);
-  v = __builtin_amdgcn_cvt_pk_fp8_f32((float)ws[t + 2] * sc, (float)ws[t + 3] * sc, v, true);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32((float)ws[src] * sc, (float)ws[src + 1] * sc, v, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32((float)ws[src + 2] * sc, (float)ws[src + 3] * sc, v, true);
   *(int*)(dst + t) = v;
 }
 
@@ -761,12 +836,15 @@ int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* 
   return 0;
 }
 
-// FP8 weight stream and per-operand scales from the BF16 stream.
-void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, float* wsc_inv, void* ws8, int64_t n_frags,
-                  hipStream_t st) {
+// FP8 weight stream and per-operand scales from the BF16 stream (operands
+// in stream order wp[0..depth], wt[depth..1], w0z: width / 16 row tiles,
+// the last one mlp_nzt(width)).
+void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, int width, float* wsc_inv, void* ws8,
+                  int64_t n_frags, hipStream_t st) {
   OpRanges r{};
   r.n = n_ops;
   for (int k = 0; k <= n_ops; ++k) r.off[k] = op_off[k];
+  for (int k = 0; k < n_ops; ++k) r.mtx[k] = k + 1 < n_ops ? width / 16 : mlp_nzt(width);
   saa_k_op_scale<<<n_ops, 256, 0, st>>>((const __bf16*)ws, r, wsc_inv);
   const int64_t n = n_frags * 512;
   saa_k_pack_fp8<<<nblk(n / 4, 256), 256, 0, st>>>((const __bf16*)ws, r, wsc_inv, n, (uint8_t*)ws8);

@@ -22,7 +22,8 @@ void mlp_b0eff(float* b0eff, const float* W0zT, const float* b0, const double* z
                hipStream_t st);
 int mlp_eval(const MlpDev& net, int prec, const double* xi, int nkl, const int* order, const void* xenc,
              int64_t N, double* q, double* g, int n_cu, hipStream_t st);
-void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, float* wsc_inv, void* ws8, int64_t n_frags,
+void mlp_pack_fp8(const void* ws, const int64_t* op_off, int n_ops, int width, float* wsc_inv, void* ws8,
+                  int64_t n_frags,
                   hipStream_t st);
 void mlp_encode(const double* xi, int nkl, const int* order, int r_m, int kin, int64_t N, void* X, hipStream_t st);
 int mlp_kin(int width);
@@ -113,7 +114,7 @@ int pack(mrdino_model* m) {
   for (int L = d.depth; L >= 1; --L) off[n++] = m->f_wt[L];
   off[n++] = m->f_w0z;
   off[n] = m->ws_frags;
-  saa_launch::mlp_pack_fp8(m->ws.p, off, n, (float*)m->wsc.p, m->ws8.p, m->ws_frags, st);
+  saa_launch::mlp_pack_fp8(m->ws.p, off, n, W, (float*)m->wsc.p, m->ws8.p, m->ws_frags, st);
   return check_hip(hipGetLastError());
 }
 
