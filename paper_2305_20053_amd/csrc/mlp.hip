@@ -27,6 +27,7 @@
 #include <hip/hip_fp16.h>
 
 #include <string>
+#include <type_traits>
 
 #include "common.h"
 #include "mlp.h"
@@ -132,6 +133,15 @@ __device__ __forceinline__ int pow2_exp(float m, float top) {
   return e - 1 < -60 ? -60 : (e - 1 > 60 ? 60 : e - 1);
 }
 __device__ __forceinline__ float pow2_scale(float m, float top) { return ldexpf(1.0f, pow2_exp(m, top)); }
+// The same for top = 256 without a division: m = f 2^em with f in [0.5, 1)
+// gives m 2^(8 - em) in [128, 256).
+__device__ __forceinline__ int pow2_exp256(float m) {
+  if (!(m > 0.0f) || !(m < INFINITY)) return 0;
+  int em;
+  (void)frexpf(m, &em);
+  const int e = 8 - em;
+  return e < -60 ? -60 : (e > 60 ? 60 : e);
+}
 
 }  // namespace
 
@@ -292,16 +302,73 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     return __builtin_bit_cast(i32x8, v);
   };
 
+  // Whole-product prefetch (when a product's A fragments fit in 64 VGPRs and
+  // a wave may hold 256):
+  // the fragments of the next product are loaded while the current one
+  // finishes, so their L2 latency hides behind the epilogue and the barriers.
+  constexpr int KX = OP::scaled ? KS / 4 : KS;             // MFMA k-steps of a full product
+  constexpr int FX = OP::scaled ? 4 * FB : FB;             // bytes per MFMA A fragment
+  typedef typename std::conditional<OP::scaled, i32x8, vec>::type avec;
+  constexpr bool WHOLE = KX * MW * (int)sizeof(avec) <= 64 * 4 && WAVES <= 8;
+  avec ab[WHOLE ? KX : 1][MW];
+  auto load_all = [&](const char* A, int mtx, int nks) {
+    if constexpr (WHOLE) {
+      const char* Aw = A + (size_t)(MW * wv) * FX + ln * (FX / 64);
+      const int nkx = OP::scaled ? nks / 4 : nks;
+#pragma unroll
+      for (int kx = 0; kx < KX; ++kx)
+        if (kx < nkx)
+#pragma unroll
+          for (int j = 0; j < MW; ++j) ab[kx][j] = *(const avec*)(Aw + (size_t)(kx * mtx + j) * FX);
+    }
+  };
+
   // acc += A(MW wv + j, ks) B(sb, ks); A fragment (ks, mt) of an operand with
   // mtx row tiles at A + (ks mtx + mt) FB bytes; B from act, or (BF16) from
   // the encoded input for layer 0.  FP8: 16 x 128 fragments (k4, mt) at
   // A + (k4 mtx + mt) 4 FB bytes; `op` is the operand's index in the stream.
+  // WHOLE: the A fragments are already in ab (load_all).
   auto product = [&](const char* A, int mtx, int nks, bool from_input, int op) {
 #pragma unroll
     for (int j = 0; j < MW; ++j)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) acc[j][sb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if constexpr (OP::scaled) {
+    if constexpr (WHOLE) {
+      int sa = 0, sbv[SB];
+      if constexpr (OP::scaled) {
+        sa = a_scale(op);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) sbv[sb] = b_scale(sb);
+      }
+      const int nkx = OP::scaled ? nks / 4 : nks;
+#pragma unroll
+      for (int kx = 0; kx < KX; ++kx) {
+        if (kx < nkx) {
+          avec b[SB];
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) {
+            if constexpr (OP::scaled) {
+              b[sb] = b_quad(sb, kx);
+            } else if (from_input) {
+              const int64_t smp = base + 16 * sb + c16;
+              b[sb] = vec{};
+              if (smp < N) b[sb] = *(const vec*)(xenc + smp * KIN + 32 * kx + 8 * g);
+            } else {
+              b[sb] = act[(sb * KS + kx) * 64 + ln];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < MW; ++j)
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) {
+              if constexpr (OP::scaled)
+                acc[j][sb] = OP::mma4(ab[kx][j], b[sb], acc[j][sb], sa, sbv[sb]);
+              else
+                acc[j][sb] = OP::mma(ab[kx][j], b[sb], acc[j][sb]);
+            }
+        }
+      }
+    } else if constexpr (OP::scaled) {
       constexpr int KS4 = KS / 4;
       const int nk4 = nks / 4;
       const int sa = a_scale(op);
@@ -384,7 +451,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
       for (int sb = 0; sb < SB; ++sb) {
         float m = 0.0f;
         for (int w = 0; w < WAVES; ++w) m = fmaxf(m, smax[(w * SB + sb) * 16 + c16]);
-        axe[sb] = pow2_exp(m, 256.0f);
+        axe[sb] = pow2_exp256(m);
       }
     }
 #pragma unroll
@@ -399,6 +466,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
     __syncthreads();
   };
 
+  load_all(operand(net.wp[0]), MT, KS1);
   if constexpr (OP::scaled) {   // FP8: scale and publish the encoded input like a layer output
 #pragma unroll
     for (int j = 0; j < MW; ++j)
@@ -425,10 +493,14 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
   for (int L = 0; L < DEPTH; ++L) {
     const float* bl = (L == 0) ? net.b0eff : net.bias[L];
+    float4 bias4[MW];   // loaded before the next product's fragments, so waiting for them does not wait for those
+#pragma unroll
+    for (int j = 0; j < MW; ++j) bias4[j] = *(const float4*)(bl + 16 * (MW * wv + j) + 4 * g);
     product(operand(net.wp[L]), MT, L == 0 ? KS1 : KS, L == 0, L);
+    load_all(operand(net.wp[L + 1]), MT, KS);
 #pragma unroll
     for (int j = 0; j < MW; ++j) {
-      const float4 b4 = *(const float4*)(bl + 16 * (MW * wv + j) + 4 * g);
+      const float4 b4 = bias4[j];
       const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
@@ -450,7 +522,11 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
   }
   // output layer phi = W h + b (rows padded to W), reduced QoI and its gradient
   {
+    float4 bias4[MW];
+#pragma unroll
+    for (int j = 0; j < MW; ++j) bias4[j] = *(const float4*)(net.bc + 16 * (MW * wv + j) + 4 * g);
     product(operand(net.wp[DEPTH]), MT, KS, false, DEPTH);
+    load_all(operand(net.wt[DEPTH]), MT, KS);
     // |phi + c|^2 as per-tile partial sums (16 features: a lane's 4 rows,
     // then across the 4 row groups), added in tile order by one wave, so the
     // result does not depend on how the tiles are split over the waves
@@ -458,7 +534,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
     for (int j = 0; j < MW; ++j) {
       // rows past r_u have zero weights and zero bias + c, so v = 0 there
-      const float4 b4 = *(const float4*)(net.bc + 16 * (MW * wv + j) + 4 * g);
+      const float4 b4 = bias4[j];
       const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
@@ -493,6 +569,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1)
 #pragma unroll
   for (int L = DEPTH; L >= 1; --L) {
     product(operand(net.wt[L]), MT, KS, false, DEPTH + 1 + (DEPTH - L));
+    if (L > 1) load_all(operand(net.wt[L - 1]), MT, KS);
 #pragma unroll
     for (int j = 0; j < MW; ++j)
 #pragma unroll
