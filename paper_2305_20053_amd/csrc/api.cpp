@@ -911,6 +911,7 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
   int rc = SAA_OK;
   const size_t tw = (size_t)N_max * c->nodes * sizeof(double);
   if (!rc) rc = c->FT.alloc((size_t)c->dz * c->nodes * sizeof(double));
+  if (!rc) rc = c->src1.alloc((size_t)p->n_src_per_dim * (p->n + 1) * sizeof(double));
   if (!rc) rc = c->S.alloc((size_t)c->K1 * (p->n + 1) * sizeof(double));
   if (!rc) rc = c->amp.alloc((size_t)c->K1 * c->K1 * sizeof(double));
   if (!rc) rc = c->em.alloc(tw);
@@ -961,6 +962,21 @@ int saa_ctx_create(const saa_problem* p, int64_t N_max, void* hip_stream, saa_ct
     rc = check_hip(hipMemcpyAsync(c->amp.p, a, sizeof(double) * c->K1 * c->K1, hipMemcpyHostToDevice, c->st));
     if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
     delete[] a;
+  }
+  if (!rc) {  // 1D factors of the separable source matrix (Sec. 4.1's Gaussian sources on an s x s grid)
+    const int s = p->n_src_per_dim, np = p->n + 1;
+    const double h = 1.0 / p->n;
+    std::vector<double> G((size_t)s * np);
+    for (int a = 0; a < s; ++a)
+      for (int i = 0; i < np; ++i) {
+        const double d = i * h - (a + 1.0) / (s + 1.0);
+        G[(size_t)a * np + i] = std::exp(-d * d / (2.0 * p->src_sigma * p->src_sigma));
+      }
+    g.src1 = (const double*)c->src1.p;
+    g.src_s = s;
+    g.src_c = h * h / (p->src_sigma * std::sqrt(2.0 * M_PI));
+    rc = check_hip(hipMemcpyAsync(c->src1.p, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, c->st));
+    if (!rc) rc = check_hip(hipStreamSynchronize(c->st));
   }
   if (!rc) {
     saa_launch::sine_table((double*)c->S.p, c->K1, p->n, c->st);

@@ -163,6 +163,7 @@ struct saa_ctx {
   int64_t n_kl = 0;                   // K1^dim KL coefficients per sample
   int64_t nodes = 0, d_u = 0;
   saa_rt::DevBuf FT, S, amp, em, xi, kap;
+  saa_rt::DevBuf src1;   // 2D: the 1D Gaussian factors of the separable source matrix
   saa_rt::DevBuf mt;                  // (M u_target) at interior nodes (node layout), FP64
   std::vector<double> mt_host;        // the same on the host
   double ctt = 0.0;                   // u_target^T M u_target

@@ -21,6 +21,12 @@ struct PdeGeo {
   double r;                     // reaction coefficient
   const double* mt;             // (M u_target) at interior nodes, 0 on the boundary (node layout)
   double ctt;                   // u_target^T M u_target over all nodes
+  // The lumped source matrix is separable: F[p][s b + a] = src_c G[a][i] G[b][j]
+  // at interior node p = (i, j), with G[a][i] = exp(-(i h - (a + 1) / (s + 1))^2
+  // / (2 sigma^2)) stored in src1 (s x (n_0 + 1)) and src_c = h^2 / (sigma sqrt(2 pi)).
+  const double* src1;
+  int src_s;
+  double src_c;
 };
 
 // Per-sample multigrid / CG workspaces in the solver precision TS.

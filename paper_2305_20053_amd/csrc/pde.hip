@@ -665,10 +665,18 @@ __device__ __forceinline__ void state_sample(const PdeGeo& g, const double* FT, 
   const double c = g.r * g.h2;
   // Initialising passes write every node (boundary zeros included): the TW
   // buffers are shared by the FP32 and FP64 state precisions.
+  // f = F z from the separable factors: f_p = c sum_b G[b][j] sum_a z_{s b + a} G[a][i]
+  const int ns = g.src_s;
   for_nodes(n, [&](int p, int i, int j) {
     double acc = 0.0;
-    if (interior(i, j, n))
-      for (int k = 0; k < g.dz; ++k) acc += FT[(int64_t)k * g.nodes + p] * zs[k];
+    if (interior(i, j, n)) {
+      for (int b = 0; b < ns; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < ns; ++a) t += zs[ns * b + a] * g.src1[a * np + i];
+        acc += g.src1[b * np + j] * t;
+      }
+      acc *= g.src_c;
+    }
     f[p] = (TW)acc;
     u[p] = (TW)0;
   });
@@ -815,22 +823,42 @@ __device__ __forceinline__ void adjoint_sample(const PdeGeo& g, const double* FT
   bool ok = true;
   int passes = 0;
   const int lin = dc_solve<TW, TS>(g, m, sp, em, u, b, lam, red, &ok, &passes);
-  // g = F^T lambda, eight controls per pass over the grid (register-resident sums)
-  for (int k0 = 0; k0 < g.dz; k0 += 8) {
-    double v[8];
+  // g = F^T lambda from the separable factors: g_{s b + a} = c sum_j G[b][j] r_a(j)
+  // with the row sums r_a(j) = sum_i G[a][i] lambda_ij.  Each wave takes whole
+  // interior rows (lanes split the row, a butterfly sum gives every lane the
+  // s row sums); lane s b + a accumulates its control; the waves' partials are
+  // added in wave order.
+  {
+    const int ns = g.src_s, lane = threadIdx.x & (SAA_WAVE - 1), wid = threadIdx.x / SAA_WAVE;
+    const int nw = blockDim.x / SAA_WAVE;
+    const int la = lane % ns, lb = lane / ns;   // this lane's control (a, b) when lane < s^2
+    double acc = 0.0;
+    for (int j = 1 + wid; j < n; j += nw) {
+      double r[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = 0.0;
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        const double l = (double)lam[p];
+      for (int a = 0; a < 8; ++a) r[a] = 0.0;
+      for (int i = 1 + lane; i < n; i += SAA_WAVE) {
+        const double l = (double)lam[j * np + i];
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if (k0 + t < g.dz) v[t] += FT[(int64_t)(k0 + t) * g.nodes + p] * l;
+        for (int a = 0; a < 8; ++a)
+          if (a < ns) r[a] += g.src1[a * np + i] * l;
       }
-    });
-    block_sum<8>(v, red);
-    if (threadIdx.x == 0) {
-      for (int t = 0; t < 8 && k0 + t < g.dz; ++t) g_out[s * g.dz + k0 + t] = v[t];
+      double ra = 0.0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (a < ns) {
+          const double t = wave_sum(r[a]);
+          if (a == la) ra = t;
+        }
+      }
+      if (lane < g.dz) acc += g.src1[lb * np + j] * ra;
+    }
+    red[wid * SAA_WAVE + lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < g.dz) {
+      double v = 0.0;
+      for (int w = 0; w < nw; ++w) v += red[w * SAA_WAVE + threadIdx.x];
+      g_out[s * g.dz + threadIdx.x] = g.src_c * v;
     }
   }
   if (threadIdx.x == 0) {
