@@ -3,6 +3,7 @@
 Tolerances (relative, 2-norm): FP64 and FP32-in-FP64-defect-correction paths
 1e-9 on J and grad J; pure FP32 1e-4.  t* to 1e-14 relative.
 """
+import dataclasses
 import json
 import os
 
@@ -83,6 +84,29 @@ def test_other_targets_per_sample(gpu_lib, target):
     assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= 1e-12
     for i in range(len(q)):
         assert _rel(g[i], ref["g"][i]) <= TOL[saa.FP64], i
+    ctx.close()
+
+
+@pytest.mark.parametrize("s", [1, 3, 8])
+@pytest.mark.parametrize("prec", [saa.FP64, saa.FP32_DC64])
+def test_source_grid_sizes_per_sample(gpu_lib, s, prec):
+    """The separable source (Sec. 4.1's Gaussian sources on an s x s grid,
+    f = F z and g = F^T lambda formed from 1D factors) for d_Z = 1, 9 and 64
+    (every lane of a wave holds a control) on the n = 32 grid: q_i and
+    dq_i/dz of 16 samples against the oracle's dense source matrix."""
+    prob = dataclasses.replace(saa.problem_small(), n_src_per_dim=s)
+    print(f"case sources s={s} prec={prec} per_sample", flush=True)
+    xi = si.kl_coefficients(si.SEED_XI_SMALL, 16, prob.kl_per_dim)
+    z = si.control(si.SEED_Z_SMALL, s * s)
+    ref = osaa.objective_grad(_oprob(prob), xi, z)
+    ctx = saa.Context(prob, 16)
+    ctx.set_samples(torch.from_numpy(xi).cuda())
+    q, g, _ = ctx.per_sample(z, opt=saa.options(prec=prec))
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    assert g.shape == (16, s * s)
+    assert np.max(np.abs(q - ref["q"]) / np.abs(ref["q"])) <= 1e-12
+    for i in range(len(q)):
+        assert _rel(g[i], ref["g"][i]) <= TOL[prec], i
     ctx.close()
 
 
