@@ -346,14 +346,23 @@ __device__ void vcycle_from(const PdeGeo& g, const MgBufs<TS>& m, int l0) {
 template <typename TW, typename TS>
 __device__ void build_diagonals(const PdeGeo& g, const MgBufs<TS>& m, const TW* u) {
   const double c = 3.0 * g.r * g.h2;
-  for_nodes(g.n[0], [&](int p, int i, int j) {
-    if (interior(i, j, g.n[0])) {
-      const double uu = (double)u[p];
-      const TS d = (TS)(c * uu * uu);
-      m.T[p] = d;
-      m.D[p] = m.KD[p] + d;
-    }
-  });
+  struct TD {
+    TS t, d;
+  };
+  for_nodes_split(
+      g.n[0],
+      [&](int p, int i, int j) -> TD {
+        if (!interior(i, j, g.n[0])) return TD{(TS)0, (TS)0};
+        const double uu = (double)u[p];
+        const TS d = (TS)(c * uu * uu);
+        return TD{d, m.KD[p] + d};
+      },
+      [&](int p, int i, int j, const TD& r) {
+        if (interior(i, j, g.n[0])) {
+          m.T[p] = r.t;
+          m.D[p] = r.d;
+        }
+      });
   __syncthreads();
   for (int l = 0; l < g.L - 1; ++l) {
     TS* tc = at_level(m.T, m.lT, g, l + 1);
@@ -540,15 +549,23 @@ __device__ int dc_solve(const PdeGeo& g, const MgBufs<TS>& m, const SolveParams&
     bool cg_ok = true;
     lin += pcg(g, m, ctl.eta, sp.max_lin, sp.nu, red, &cg_ok);
     double v[2] = {0.0, 0.0};
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        const TW d = (TW)m.cx[p];
-        const TW xn = x[p] + d;
-        x[p] = xn;
-        v[0] += (double)d * (double)d;
-        v[1] += (double)xn * (double)xn;
-      }
-    });
+    struct DX {
+      TW d, xn;
+    };
+    for_nodes_split(
+        n,
+        [&](int p, int i, int j) -> DX {
+          if (!interior(i, j, n)) return DX{(TW)0, (TW)0};
+          const TW d = (TW)m.cx[p];
+          return DX{d, x[p] + d};
+        },
+        [&](int p, int i, int j, const DX& r) {
+          if (interior(i, j, n)) {
+            x[p] = r.xn;
+            v[0] += (double)r.d * (double)r.d;
+            v[1] += (double)r.xn * (double)r.xn;
+          }
+        });
     block_sum<2>(v, red);
     if (!(v[0] == v[0]) || !(v[1] == v[1])) {
       *ok = false;
@@ -556,13 +573,17 @@ __device__ int dc_solve(const PdeGeo& g, const MgBufs<TS>& m, const SolveParams&
     }
     if (outer_converged(ctl, v[0], v[1], sp.adj_tol, sp.lin_rtol)) break;
     // new defect b - A x in precision TW
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        const TW uu = u[p];
-        const TW ax = stiff_apply_em<TW>(em, x, p, np) + (TW)c * uu * uu * x[p];
-        m.cr[p] = (TS)(b[p] - ax);
-      }
-    });
+    for_nodes_split(
+        n,
+        [&](int p, int i, int j) -> TW {
+          if (!interior(i, j, n)) return (TW)0;
+          const TW uu = u[p];
+          const TW ax = stiff_apply_em<TW>(em, x, p, np) + (TW)c * uu * uu * x[p];
+          return b[p] - ax;
+        },
+        [&](int p, int i, int j, TW r) {
+          if (interior(i, j, n)) m.cr[p] = (TS)r;
+        });
     __syncthreads();
   }
   if (pass == sp.max_dc) *ok = false;
@@ -750,28 +771,39 @@ __device__ __forceinline__ void state_sample(const PdeGeo& g, const double* FT, 
   ctl.eta = sp.lin_rtol;
   for (it = 0; it < sp.max_newton; ++it) {
     // residual R = K u + r h^2 u^3 - f; CG right-hand side -R
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        const TW uu = u[p];
-        const TW R = stiff_apply_em<TW>(em, u, p, np) + (TW)c * uu * uu * uu - f[p];
-        m.cr[p] = (TS)(-R);
-      }
-    });
+    for_nodes_split(
+        n,
+        [&](int p, int i, int j) -> TW {
+          if (!interior(i, j, n)) return (TW)0;
+          const TW uu = u[p];
+          return stiff_apply_em<TW>(em, u, p, np) + (TW)c * uu * uu * uu - f[p];
+        },
+        [&](int p, int i, int j, TW R) {
+          if (interior(i, j, n)) m.cr[p] = (TS)(-R);
+        });
     __syncthreads();
     build_diagonals<TW, TS>(g, m, u);
     bool ok = true;
     lin += pcg(g, m, ctl.eta, sp.max_lin, sp.nu, red, &ok);
     if (!ok) flags |= SAA_FLAG_CG;
     double v[2] = {0.0, 0.0};
-    for_nodes(n, [&](int p, int i, int j) {
-      if (interior(i, j, n)) {
-        const TW d = (TW)m.cx[p];
-        const TW un = u[p] + d;
-        u[p] = un;
-        v[0] += (double)d * (double)d;
-        v[1] += (double)un * (double)un;
-      }
-    });
+    struct DU {
+      TW d, un;
+    };
+    for_nodes_split(
+        n,
+        [&](int p, int i, int j) -> DU {
+          if (!interior(i, j, n)) return DU{(TW)0, (TW)0};
+          const TW d = (TW)m.cx[p];
+          return DU{d, u[p] + d};
+        },
+        [&](int p, int i, int j, const DU& r) {
+          if (interior(i, j, n)) {
+            u[p] = r.un;
+            v[0] += (double)r.d * (double)r.d;
+            v[1] += (double)r.un * (double)r.un;
+          }
+        });
     block_sum<2>(v, red);
     if (!(v[0] == v[0]) || !(v[1] == v[1])) {
       flags |= SAA_FLAG_NAN;
