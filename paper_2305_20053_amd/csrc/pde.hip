@@ -126,9 +126,9 @@ __device__ __forceinline__ Level<TS> level(const PdeGeo& g, const MgBufs<TS>& m,
 // values, `store` writes them.  The passes whose computed nodes read no value
 // that the pass stores (red-black half sweeps, residuals, the CG vector
 // passes) are written this way; it gives the compiler independent loads and
-// stores to schedule (the FP32 state kernel at n = 128 runs 3 % faster than
-// with one load-compute-store body; visiting two or four nodes of a thread
-// per group was slower for the adjoint).
+// stores to schedule (the FP32 state kernel at n = 128 runs 5 % faster than
+// with one load-compute-store body; visiting two nodes of a thread per group
+// before storing was much slower).
 template <typename C, typename S>
 __device__ __forceinline__ void for_nodes_split(int n, C&& compute, S&& store) {
   for_nodes(n, [&](int p, int i, int j) { store(p, i, j, compute(p, i, j)); });
